@@ -1,0 +1,83 @@
+"""Black-box operators ``x -> A x`` and ``x -> A^* x`` on N x c blocks
+(Sec. 1: the method touches A only through such products).
+
+* ``DenseOp``  -- an explicit matrix.
+* ``KernelOp`` -- a kernel matrix ``A(i,j) = K(x_i, x_j)`` on 2-D points,
+  evaluated tile by tile (never stored whole):
+  ``"log"``: ``log|x_i - x_j|`` off the diagonal, 1 on it;
+  ``"near"``: ``1 / (|x_i - x_j| + delta)`` everywhere (delta = 1e-3 default).
+* ``HBSOp``    -- a matrix given in HBS form, applied in O(N k) (Fig. 7 + D).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+class DenseOp:
+    def __init__(self, A: np.ndarray):
+        self.A = np.asarray(A, dtype=np.float64)
+        self.n = self.A.shape[0]
+
+    def apply(self, X):
+        return self.A @ X
+
+    def apply_adjoint(self, X):
+        return self.A.T @ X
+
+    def entries(self, rows, cols):
+        return self.A[np.ix_(rows, cols)]
+
+
+class KernelOp:
+    def __init__(self, points: np.ndarray, kind: str = "near", delta: float = 1e-3,
+                 tile: int = 512):
+        self.p = np.asarray(points, dtype=np.float64)
+        self.n = self.p.shape[0]
+        if kind not in ("log", "near"):
+            raise ValueError(kind)
+        self.kind = kind
+        self.delta = delta
+        self.tile = tile
+
+    def entries(self, rows, cols):
+        rows = np.asarray(rows)
+        cols = np.asarray(cols)
+        dx = self.p[rows, 0][:, None] - self.p[cols, 0][None, :]
+        dy = self.p[rows, 1][:, None] - self.p[cols, 1][None, :]
+        d = np.sqrt(dx * dx + dy * dy)
+        if self.kind == "near":
+            return 1.0 / (d + self.delta)
+        same = rows[:, None] == cols[None, :]
+        with np.errstate(divide="ignore"):
+            v = np.log(np.where(same, 1.0, d))
+        return np.where(same, 1.0, v)
+
+    def apply(self, X):
+        X = np.asarray(X, dtype=np.float64)
+        vec = X.ndim == 1
+        if vec:
+            X = X[:, None]
+        Y = np.zeros((self.n, X.shape[1]))
+        cols = np.arange(self.n)
+        for i0 in range(0, self.n, self.tile):
+            rows = np.arange(i0, min(i0 + self.tile, self.n))
+            Y[rows] = self.entries(rows, cols) @ X
+        return Y[:, 0] if vec else Y
+
+    apply_adjoint = apply          # both kernels are symmetric
+
+    def dense(self):
+        idx = np.arange(self.n)
+        return self.entries(idx, idx)
+
+
+class HBSOp:
+    def __init__(self, h):
+        self.h = h
+        self.n = h.tree.n
+
+    def apply(self, X):
+        return self.h.apply(X)
+
+    def apply_adjoint(self, X):
+        return self.h.apply_adjoint(X)

@@ -1,0 +1,204 @@
+"""Pins of the oracle's HBS path (Fig. 4, Fig. 5, Fig. 7) against what the
+paper and the mathematics fix:
+
+* exact recovery of operators with off-diagonal rank exactly k (range
+  finder with s_{k+1} = 0, Sec. 2.5; peeling identity eq. gretchen), with
+  revealed ranks exactly k;
+* Fig. 7 + D equals a dense assembly written from the format's definition
+  (eq. babytelescope), and the adjoint passes the dot-product test;
+* the peeled sample equals the sibling block times the Gaussian (eq. gretchen);
+* telescoping of the spanning matrices, orthonormality, the HBS-ID identity,
+  nested skeletons, and ``B^skel = A(skel_in, skel_out)`` (eq. ben1);
+* the literal sample count of Fig. 4 (4 r L + n_max columns);
+* brute-force neutered-block optimality on tiny N (Eckart-Young + eq. err_prob);
+* the paper's printed B pairing (Fig. 3/4) and downward order (Fig. 7) fail.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import grad, hbs, metrics, operators
+from oracle.tree import Tree
+
+
+def _dense_from_gen(g):
+    import torch
+    tree = Tree(g["n"], g["leaf"])
+    T = {k: torch.tensor(g[k]) for k in ("U", "V", "Ut", "Vt", "B", "D")}
+    return grad.dense_from_generators(tree, **T).numpy()
+
+
+@pytest.fixture(scope="module")
+def syn():
+    g = W.synthetic_hbs(1024, 64, 10, seed=1)
+    return g, _dense_from_gen(g)
+
+
+def test_apply_equals_dense_definition(syn):
+    g, A = syn
+    h = hbs.from_generators(g)
+    x = W.gaussian((1024, 3), seed=5)
+    assert np.linalg.norm(h.apply(x) - A @ x) < 1e-13 * np.linalg.norm(A @ x)
+    assert np.linalg.norm(h.apply_adjoint(x) - A.T @ x) < 1e-13 * np.linalg.norm(A.T @ x)
+    yv = W.gaussian(1024, seed=6)
+    lhs = yv @ h.apply(x[:, 0])
+    rhs = h.apply_adjoint(yv) @ x[:, 0]
+    assert abs(lhs - rhs) < 1e-13 * abs(lhs)
+
+
+def test_printed_downward_order_fails(syn):
+    g, A = syn
+    h = hbs.from_generators(g)
+    x = W.gaussian((1024, 2), seed=5)
+    y = hbs.apply_partial(h.tree, h.tree.L, h.U, h.V, h.Ut, h.Vt, h.B, x,
+                          downward="as-printed")
+    for t in h.tree.leaves():
+        y[h.tree.I(t)] += h.D[t] @ x[h.tree.I(t)]
+    assert np.linalg.norm(y - A @ x) > 1e-3 * np.linalg.norm(A @ x)
+
+
+@pytest.mark.parametrize("to_id", [False, True])
+def test_exact_recovery_synthetic_hbs(syn, to_id):
+    g, A = syn
+    h, st, ex = hbs.compress(operators.DenseOp(A), 1024, 64, r=20, seed=11, rank=10,
+                             to_id=to_id)
+    assert metrics.rel_fro(h.dense(), A) < 1e-12
+    if to_id:
+        assert all(h.rank_u(t) == 10 and h.rank_v(t) == 10 for t in range(2, 2 ** (h.tree.L + 1)))
+
+
+def test_exact_recovery_tolerance_mode_reveals_rank(syn):
+    g, A = syn
+    h, st, ex = hbs.compress(operators.DenseOp(A), 1024, 64, r=20, seed=12, tol=1e-11)
+    assert metrics.rel_fro(h.dense(), A) < 1e-12
+    ranks = {h.rank_u(t) for t in range(2, 2 ** (h.tree.L + 1))}
+    assert ranks == {10}
+
+
+def test_printed_b_pairing_fails(syn):
+    g, A = syn
+    h, _, ex = hbs.compress(operators.DenseOp(A), 1024, 64, r=20, seed=11, rank=10,
+                            to_id=False, b_pairing="as-printed")
+    assert metrics.rel_fro(h.dense(), A) > 1e-3
+
+
+def test_sample_count_fig4(syn):
+    g, A = syn
+    n, leaf, r = 1024, 64, 20
+    h, st, _ = hbs.compress(operators.DenseOp(A), n, leaf, r=r, seed=1, rank=10)
+    L = h.tree.L
+    assert st.columns == 4 * r * L + h.tree.nmax()
+    assert st.calls == 4 * L + 1
+
+
+def test_peeling_identity_eq_gretchen(syn):
+    g, A = syn
+    tr = {}
+    hbs.compress(operators.DenseOp(A), 1024, 64, r=20, seed=3, rank=10, trace=tr)
+    tree = Tree(1024, 64)
+    for lev in range(tree.L):
+        G, Y1, Y2 = tr["G"][lev], tr["Y1"][lev], tr["Y2"][lev]
+        for t in tree.level_nodes(lev):
+            a, b = tree.children(t)
+            ref1 = A[tree.I(a), tree.I(b)] @ G[tree.I(b)]
+            ref2 = A[tree.I(b), tree.I(a)] @ G[tree.I(a)]
+            assert np.linalg.norm(Y1[tree.I(a)] - ref1) < 1e-12 * np.linalg.norm(ref1)
+            assert np.linalg.norm(Y2[tree.I(b)] - ref2) < 1e-12 * np.linalg.norm(ref2)
+
+
+def test_orthonormality_and_telescoping(syn):
+    g, A = syn
+    tr = {}
+    h, _, ex = hbs.compress(operators.DenseOp(A), 1024, 64, r=20, seed=4, rank=10, trace=tr)
+    tree = h.tree
+    y = ex["y"]
+    o = ex["ortho"]
+    for lev in range(1, tree.L):
+        Ul_parent, Ul_child = tr["Ulong"][lev - 1], tr["Ulong"][lev]
+        for t in tree.level_nodes(lev):
+            a, b = tree.children(t)
+            Q = Ul_parent[t]
+            assert np.linalg.norm(Q.T @ Q - np.eye(Q.shape[1])) < 1e-13
+            tele = np.vstack([Ul_child[a] @ o.Ut[t][:Ul_child[a].shape[1]],
+                              Ul_child[b] @ o.Ut[t][Ul_child[a].shape[1]:]])
+            # The spanning matrix Y_t = Ulong_t diag(y_t) telescopes.
+            err = np.linalg.norm((Q - tele) * y[t][None, :])
+            assert err < 1e-12 * np.linalg.norm(y[t])
+
+
+def test_hbs_id_structure_and_submatrix_property(syn):
+    g, A = syn
+    h, _, _ = hbs.compress(operators.DenseOp(A), 1024, 64, r=20, seed=5, rank=10)
+    tree = h.tree
+    for t in tree.leaves():
+        J = h.skel_in[t] - tree.lo[t]
+        assert np.allclose(h.U[t][J], np.eye(len(J)))
+    for lev in range(1, tree.L):
+        for t in tree.level_nodes(lev):
+            a, b = tree.children(t)
+            assert set(h.skel_in[t]) <= set(h.skel_in[a]) | set(h.skel_in[b])
+            assert set(h.skel_out[t]) <= set(h.skel_out[a]) | set(h.skel_out[b])
+    for v in range(2, 2 ** (tree.L + 1)):
+        s = v ^ 1
+        ref = A[np.ix_(h.skel_in[s], h.skel_out[v])]
+        assert np.linalg.norm(h.B[(s, v)] - ref) < 1e-12 * np.linalg.norm(ref)
+
+
+@pytest.fixture(scope="module")
+def logker():
+    P = W.ellipse_points(512)
+    K = operators.KernelOp(P, "log")
+    return K, K.dense()
+
+
+def test_kernel_tolerance_mode_error_and_E(logker):
+    K, A = logker
+    h, _, ex = hbs.compress(K, 512, 32, r=50, seed=7, tol=1e-10)
+    assert metrics.rel_fro(ex["ortho"].dense(), A) < 1e-12
+    assert metrics.rel_fro(h.dense(), A) < 1e-8
+    E = metrics.estimate_E(K.apply, h.apply, 512)
+    assert E < 1e-8
+
+
+def test_kernel_submatrix_property_to_tolerance(logker):
+    K, A = logker
+    h, _, _ = hbs.compress(K, 512, 32, r=50, seed=8, tol=1e-10)
+    for v in range(2, 2 ** (h.tree.L + 1)):
+        s = v ^ 1
+        ref = A[np.ix_(h.skel_in[s], h.skel_out[v])]
+        assert np.linalg.norm(h.B[(s, v)] - ref) < 1e-7 * np.linalg.norm(A)
+
+
+def test_neutered_block_error_bruteforce(logker):
+    """Fixed rank k: on every neutered row block A(I_t, I_t^c) the HBS error
+    is within the randomized bound (eq. err_prob, with a factor L for
+    aggregation over levels) of the best rank-k error (Eckart-Young).  A
+    node's neutered block contains its ancestors' far field, so the bound
+    takes the largest s_{k+1} over the node and its ancestors."""
+    K, A = logker
+    k, p = 16, 10
+    h, _, ex = hbs.compress(K, 512, 32, r=k + p, seed=9, rank=k)
+    Ah = h.dense()
+    tree = h.tree
+    sk1 = {}
+    for lev in range(1, tree.L + 1):
+        for t in tree.level_nodes(lev):
+            I = np.arange(tree.lo[t], tree.hi[t])
+            Ic = np.setdiff1d(np.arange(512), I)
+            s = np.linalg.svd(A[np.ix_(I, Ic)], compute_uv=False)
+            sk1[t] = max(s[k], sk1.get(t // 2, 0.0))
+            err = np.linalg.norm(A[np.ix_(I, Ic)] - Ah[np.ix_(I, Ic)], 2)
+            bound = (1 + 11 * np.sqrt(k + p) * np.sqrt(min(len(I), len(Ic)))) * sk1[t]
+            assert err <= tree.L * bound
+            assert err >= 0.99 * s[k]          # never better than optimal
+
+
+def test_storage_linear_in_n():
+    """HBS memory per index stays flat as N doubles (Sec. 4.4, Sec. 5)."""
+    per = []
+    for n in (512, 1024, 2048):
+        g = W.synthetic_hbs(n, 64, 8, seed=2)
+        A = _dense_from_gen(g)
+        h, _, _ = hbs.compress(operators.DenseOp(A), n, 64, r=16, seed=1, rank=8)
+        per.append(h.storage_reals() / n)
+    assert max(per) / min(per) < 1.15
