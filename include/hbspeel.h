@@ -1,0 +1,235 @@
+/*
+ * hbspeel -- randomized compression of rank-structured matrices on MI355X.
+ *
+ * C ABI of the library (libhbspeel.so).  It implements, on one GPU, the
+ * method of Martinsson, "Compressing rank-structured matrices via randomized
+ * sampling" (arXiv 1503.07152):
+ *
+ *   hodlr_compress     Fig. 2  (HODLR, SVD variant of eq. SVDtogetV/SVDtogetB)
+ *   hbs_compress       Fig. 4  (storage-efficient HBS) + Fig. 5 (HBS-ID)
+ *   hss_apply(_adjoint) Fig. 7 with m = L, plus the diagonal blocks
+ *
+ * Conventions for every entry point
+ *   - Matrices are column-major; "ld" is the leading dimension in elements.
+ *   - Array arguments are DEVICE pointers unless stated "host".  The caller
+ *     owns them; the library never keeps them past the call (except the
+ *     operator's points / dense matrix, which must stay valid for the
+ *     duration of a compress call).
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued
+ *     on it; calls return when the work is enqueued unless stated otherwise.
+ *     Compress calls synchronise the stream before returning (they report
+ *     statistics and status).
+ *   - Return value: HM_OK (0) on success, a negative HM_ERR_* code on error,
+ *     a positive HM_WARN_* code for a successful call with a warning.  On
+ *     error no handle is returned (out-pointer set to NULL), partial state is
+ *     freed, and hm_last_error() gives a message (thread-local).
+ *   - Handles (hm_hbs, hm_hodlr) are owned by the library and immutable
+ *     after creation; apply may run concurrently on different streams.
+ */
+#ifndef HBSPEEL_H
+#define HBSPEEL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define HM_OK 0
+#define HM_WARN_RANK_SATURATED 1   /* a revealed eps-rank reached r - p (Sec. 2.5:
+                                      the sample may not have captured the block) */
+#define HM_ERR_ARG (-1)            /* invalid argument (sizes, ld, options)     */
+#define HM_ERR_ALLOC (-2)          /* device allocation failed                  */
+#define HM_ERR_HIP (-3)            /* a HIP runtime call failed                 */
+#define HM_ERR_CALLBACK (-4)       /* the user's matvec callback returned != 0  */
+#define HM_ERR_NONFINITE (-5)      /* NaN/Inf in an operator sample             */
+#define HM_ERR_UNSUPPORTED (-6)    /* size beyond a documented limit            */
+
+/* ---- element types ------------------------------------------------------ */
+#define HM_F64 0
+#define HM_F32 1
+#define HM_BF16 2
+
+/* ---- limits ---------------------------------------------------------------
+ * Samples per level r = rank + oversample <= HM_MAX_SAMPLES.  The per-node
+ * factorisations hold a (2r x 2r) triangle pair in LDS (160 KB per CU). */
+#define HM_MAX_SAMPLES 48
+/* Leaves hold at most HM_MAX_LEAF indices when the tree has more than one
+ * level (the interpolative decomposition of a leaf runs in LDS). */
+#define HM_MAX_LEAF 256
+
+/* ---- operators (the black box of Sec. 1: x -> A x and x -> A^* x) -------- */
+#define HM_OP_CALLBACK 0   /* user function                                    */
+#define HM_OP_KERNEL 1     /* built-in kernel matrix on 2-D points, tiled MFMA */
+#define HM_OP_DENSE 2      /* explicit N x N matrix                            */
+#define HM_OP_HBS 3        /* a matrix held as an HBS handle, applied in O(N k) */
+
+#define HM_KERNEL_LOG 0    /* A(i,j) = log|x_i - x_j| (i != j), A(i,i) = 1       */
+#define HM_KERNEL_NEAR 1   /* A(i,j) = 1 / (|x_i - x_j| + kparam) (all i, j)     */
+
+typedef struct hm_hbs_s hm_hbs;
+typedef struct hm_hodlr_s hm_hodlr;
+
+/*
+ * Black-box product (Sec. 1, "T_mult"; applied to N x ncols blocks as in
+ * Sec. 5.3).  Must write Y = A X (adjoint = 0) or Y = A^* X (adjoint = 1),
+ * X and Y FP64 device arrays (n x ncols, column-major, leading dims ldx, ldy)
+ * owned by the library for the duration of the call.  The work must be
+ * enqueued on `stream` (a hipStream_t) or finished before returning; the
+ * pointers must not be kept.  Return 0 on success; any other value aborts
+ * the compression with HM_ERR_CALLBACK.
+ */
+typedef int (*hm_matvec_fn)(void* user, int adjoint, int64_t n, int64_t ncols,
+                            const double* X, int64_t ldx, double* Y, int64_t ldy,
+                            void* stream);
+
+typedef struct hm_operator {
+  int32_t kind;          /* HM_OP_*                                              */
+  int32_t sample_dtype;  /* HM_OP_KERNEL: precision of the sampling product:
+                            HM_F64 (FP64 MFMA), HM_F32 (FP32 MFMA),
+                            HM_BF16 (BF16 MFMA, FP32 accumulation).  The samples
+                            are returned in FP64 in every case.                 */
+  hm_matvec_fn fn;       /* HM_OP_CALLBACK                                       */
+  void* user;            /* HM_OP_CALLBACK: passed back to fn                    */
+  const double* points;  /* HM_OP_KERNEL: device, n points as (x0,y0,x1,y1,...)  */
+  int32_t kernel_id;     /* HM_OP_KERNEL: HM_KERNEL_*                            */
+  double kparam;         /* HM_OP_KERNEL: delta of HM_KERNEL_NEAR                */
+  const double* dense;   /* HM_OP_DENSE: device, n x n column-major FP64         */
+  int64_t ld;            /* HM_OP_DENSE: leading dimension                       */
+  const hm_hbs* hbs;     /* HM_OP_HBS: an FP64 handle                            */
+} hm_operator;
+
+/* Flags */
+#define HM_FLAG_ORTHONORMAL 1  /* hbs_compress: stop after Fig. 4 (orthonormal
+                                  nested bases, r columns per node), no Fig. 5 */
+
+typedef struct hm_options {
+  int64_t n;            /* matrix size N >= 1                                    */
+  int64_t leaf_size;    /* m of Sec. 2.6: intervals of more than m indices are split
+                           (uniform depth L = ceil(log2(N/m)), left half ceil(n/2)) */
+  int32_t rank;         /* k >= 1: fixed rank (tol == 0) or rank cap (tol > 0)   */
+  int32_t oversample;   /* p >= 0 (Sec. 2.5); r = rank + p samples per level     */
+  double tol;           /* eps in [0,1): relative per block (s_j > eps s_1,
+                           |R_jj| > eps |R_11|); 0 selects fixed rank k          */
+  uint64_t seed;        /* key of the Philox4x32-10 Gaussian stream               */
+  int32_t flags;        /* HM_FLAG_*                                             */
+} hm_options;
+
+typedef struct hm_info {
+  int64_t n, leaf_size;
+  int32_t levels;        /* L                                                      */
+  int32_t rank_pad;      /* R: padded rank of the stored generators               */
+  int32_t max_rank, min_rank;   /* over non-root nodes (HBS) or sibling blocks (HODLR) */
+  int32_t is_id;         /* HBS-ID form (identity on skeleton rows)               */
+  int32_t dtype;         /* storage type of the generators                        */
+  int64_t storage_reals; /* reals needed at the revealed ranks (M of Sec. 5)      */
+  int64_t sample_columns;/* columns sent to the operator (4 r L + n_max)          */
+  int32_t operator_calls;/* operator invocations (2 L + 1: Omega_1, Omega_2 merged) */
+  int32_t saturated;     /* nodes whose revealed rank reached r - p               */
+  double t_compress_ms;  /* wall time of the compress call                        */
+  double t_operator_ms;  /* time inside the operator (T_compress - T_net)         */
+} hm_info;
+
+/* ---- library ------------------------------------------------------------- */
+/* Message of the last error on this thread ("" if none). */
+const char* hm_last_error(void);
+/* Build identification string (static storage). */
+const char* hm_version(void);
+
+/* ---- test matrices (Sec. 2.5; the randn of Fig. 2/4) ---------------------
+ * Writes G(i, j) for rows i = row0 .. row0+nrows-1 and columns j = 0..ncols-1
+ * of the counter-based Gaussian stream: Philox4x32-10 (Salmon et al., SC'11)
+ * with counter (i, j>>1, level, phase) and key (seed mod 2^32, seed>>32), two
+ * 53-bit uniforms u1 in (0,1], u2 in [0,1), Box-Muller (even j: cos branch,
+ * odd j: sin branch).  out: device FP64 nrows x ncols, leading dim ld. */
+int hm_gauss(uint64_t seed, int32_t level, int32_t phase, int64_t row0,
+             int64_t nrows, int32_t ncols, double* out, int64_t ld, void* stream);
+
+/* ---- operators ----------------------------------------------------------------
+ * Y = A X (adjoint = 0) or A^* X through the operator `op` (any kind), exactly
+ * as the compression samples it: X, Y device FP64 n x ncols column-major.  For
+ * HM_OP_KERNEL the product runs in op->sample_dtype and is returned in FP64. */
+int hm_operator_apply(const hm_operator* op, int64_t n, int32_t adjoint, int64_t ncols,
+                      const double* X, int64_t ldx, double* Y, int64_t ldy, void* stream);
+
+/* ---- compression ------------------------------------------------------------
+ * hodlr_compress: Fig. 2.  Per level: Y = A [Omega_2 | Omega_1] - A^(l) [...],
+ * U = qr(Y block), Z = A^* [Psi_2 | Psi_1] - (A^(l))^* [...], [V, B, U^] =
+ * svd(Z block, eps or k), U <- U U^; then D from a block-identity sample.
+ * hbs_compress: Fig. 4 then (unless HM_FLAG_ORTHONORMAL) Fig. 5.
+ * Returns HM_OK or HM_WARN_RANK_SATURATED with *out set; errors as above. */
+int hodlr_compress(const hm_options* opts, const hm_operator* op, void* stream,
+                   hm_hodlr** out);
+int hbs_compress(const hm_options* opts, const hm_operator* op, void* stream,
+                 hm_hbs** out);
+
+/* Many independent HBS compressions (count instances of uneven N and rank),
+ * level-synchronous: each level's sampling, peeling and node factorisations
+ * of all instances run in the same batched launches.  Every operator must be
+ * a built-in (HM_OP_HBS / HM_OP_KERNEL / HM_OP_DENSE).  outs: host array of
+ * count handle pointers. */
+int hbs_compress_batched(int32_t count, const hm_options* opts,
+                         const hm_operator* ops, void* stream, hm_hbs** outs);
+
+/* ---- apply (Fig. 7 with m = L, plus D) --------------------------------------
+ * y = A_H x  /  y = A_H^* x for an n x nrhs block x.  x, y: device arrays of
+ * the handle's dtype (HM_F64 or HM_F32), column-major, leading dims >= n.
+ * x and y must not overlap. */
+int hss_apply(const hm_hbs* h, int64_t nrhs, const void* x, int64_t ldx,
+              void* y, int64_t ldy, void* stream);
+int hss_apply_adjoint(const hm_hbs* h, int64_t nrhs, const void* x, int64_t ldx,
+                      void* y, int64_t ldy, void* stream);
+
+/* Backward of y = A_H x (not in the paper): given gy, writes gx = A_H^* gy and
+ * the gradients of <gy, A_H x> with respect to the generators in the flat
+ * layout of hm_hbs_from_generators (any of the generator outputs may be NULL
+ * to skip it).  Same dtype rules as hss_apply. */
+int hss_apply_backward(const hm_hbs* h, int64_t nrhs, const void* x, int64_t ldx,
+                       const void* gy, int64_t ldgy, void* gx, int64_t ldgx,
+                       void* gU, void* gV, void* gUt, void* gVt, void* gB,
+                       void* gD, void* stream);
+
+/* HODLR apply: y = A_H x (adjoint = 0) or A_H^* x; FP64. */
+int hodlr_apply(const hm_hodlr* h, int32_t adjoint, int64_t nrhs,
+                const double* x, int64_t ldx, double* y, int64_t ldy, void* stream);
+
+/* ---- handles ----------------------------------------------------------------
+ * hm_hbs_from_generators: an HBS handle from generators of uniform rank k in
+ * the flat layout (all device, column-major blocks; nn = 2^(L+1)):
+ *   U, V   n x k          rows I_t of leaf t hold its basis
+ *   Ut, Vt nn blocks of 2k x k (block t at offset t*2k*k); rows 0..k-1 couple
+ *          to the left child 2t, rows k..2k-1 to 2t+1; used for 2 <= t < 2^L
+ *   B      nn blocks of k x k; B[v] maps the outgoing expansion of v to the
+ *          incoming expansion of its sibling: A(I_sib(v), I_v) = U_sib B[v] V_v^*
+ *   D      n x nmax; rows I_t of leaf t hold D_t in columns 0..n_t-1
+ * dtype HM_F64 or HM_F32 (the arrays' type).  The data is copied. */
+int hm_hbs_from_generators(int64_t n, int64_t leaf_size, int32_t k, int32_t dtype,
+                           const void* U, const void* V, const void* Ut,
+                           const void* Vt, const void* B, const void* D,
+                           void* stream, hm_hbs** out);
+/* Copy of a handle converted to another storage dtype (HM_F64 / HM_F32). */
+int hm_hbs_convert(const hm_hbs* h, int32_t dtype, void* stream, hm_hbs** out);
+int hm_hbs_info(const hm_hbs* h, hm_info* host_out);
+int hm_hodlr_info(const hm_hodlr* h, hm_info* host_out);
+/* Generators in the flat layout above with k = info.rank_pad (zero-padded
+ * beyond each node's rank), written to caller device buffers of the handle's
+ * dtype (any may be NULL).  ranks_u / ranks_v: host int32[nn] (may be NULL).
+ * skel_in / skel_out: host int32[nn * rank_pad] global skeleton rows of the
+ * HBS-ID form, -1 padded (may be NULL; -1 everywhere if not is_id). */
+int hm_hbs_export(const hm_hbs* h, void* U, void* V, void* Ut, void* Vt, void* B,
+                  void* D, int32_t* ranks_u, int32_t* ranks_v, int32_t* skel_in,
+                  int32_t* skel_out, void* stream);
+/* HODLR generators: per level l = 1..L, U_l, V_l (n x rank_pad, rows I_t of
+ * the level's nodes), diagonal B entries s_l (nn x rank_pad: B_{sib(v),v} =
+ * diag(s[v])), D (n x nmax).  U, V: device arrays of L*n*rank_pad (level l at
+ * offset (l-1)*n*rank_pad); s: device nn*rank_pad; ranks: host int32[nn]. */
+int hm_hodlr_export(const hm_hodlr* h, double* U, double* V, double* s, double* D,
+                    int32_t* ranks, void* stream);
+void hm_hbs_free(hm_hbs* h);
+void hm_hodlr_free(hm_hodlr* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HBSPEEL_H */

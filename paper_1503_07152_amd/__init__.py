@@ -1,0 +1,410 @@
+"""Python binding of libhbspeel (randomized HODLR / HBS compression on MI355X).
+
+Argument marshalling only: every step of compression and apply runs in the
+HIP kernels of ``libhbspeel.so`` behind the C ABI of ``include/hbspeel.h``.
+PyTorch supplies device memory and the current stream.  Matrices cross the
+boundary column-major; helpers here make column-major ("Fortran") tensors.
+
+If the shared library is missing this module raises at import: there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+__all__ = [
+    "HM_F64", "HM_F32", "HM_BF16", "lib", "HMError", "fortran", "to_fortran",
+    "Options", "KernelOperator", "DenseOperator", "HBSOperator", "CallbackOperator",
+    "HBS", "HODLR", "hm_gauss", "hm_operator_apply", "hbs_compress", "hodlr_compress", "hbs_compress_batched",
+    "hss_apply", "hss_apply_adjoint", "hss_apply_backward", "hodlr_apply",
+    "hm_hbs_from_generators",
+]
+
+HM_OK, HM_WARN_RANK_SATURATED = 0, 1
+HM_F64, HM_F32, HM_BF16 = 0, 1, 2
+HM_OP_CALLBACK, HM_OP_KERNEL, HM_OP_DENSE, HM_OP_HBS = 0, 1, 2, 3
+HM_KERNEL_LOG, HM_KERNEL_NEAR = 0, 1
+HM_FLAG_ORTHONORMAL = 1
+HM_MAX_SAMPLES = 48
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libhbspeel.so")
+if not os.path.exists(_LIB_PATH):
+    raise ImportError(
+        f"{_LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`"
+        " (there is no CPU fallback)")
+lib = C.CDLL(_LIB_PATH)
+
+MATVEC = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.c_int64, C.c_int64, C.c_void_p, C.c_int64,
+                     C.c_void_p, C.c_int64, C.c_void_p)
+
+
+class _Operator(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("sample_dtype", C.c_int32), ("fn", MATVEC),
+                ("user", C.c_void_p), ("points", C.c_void_p), ("kernel_id", C.c_int32),
+                ("kparam", C.c_double), ("dense", C.c_void_p), ("ld", C.c_int64),
+                ("hbs", C.c_void_p)]
+
+
+class _Options(C.Structure):
+    _fields_ = [("n", C.c_int64), ("leaf_size", C.c_int64), ("rank", C.c_int32),
+                ("oversample", C.c_int32), ("tol", C.c_double), ("seed", C.c_uint64),
+                ("flags", C.c_int32)]
+
+
+class _Info(C.Structure):
+    _fields_ = [("n", C.c_int64), ("leaf_size", C.c_int64), ("levels", C.c_int32),
+                ("rank_pad", C.c_int32), ("max_rank", C.c_int32), ("min_rank", C.c_int32),
+                ("is_id", C.c_int32), ("dtype", C.c_int32), ("storage_reals", C.c_int64),
+                ("sample_columns", C.c_int64), ("operator_calls", C.c_int32),
+                ("saturated", C.c_int32), ("t_compress_ms", C.c_double),
+                ("t_operator_ms", C.c_double)]
+
+
+_P, _I64, _I32 = C.c_void_p, C.c_int64, C.c_int32
+_SIGS = {
+    "hm_last_error": (C.c_char_p, []),
+    "hm_version": (C.c_char_p, []),
+    "hm_gauss": (C.c_int, [C.c_uint64, _I32, _I32, _I64, _I64, _I32, _P, _I64, _P]),
+    "hm_operator_apply": (C.c_int, [C.POINTER(_Operator), _I64, _I32, _I64, _P, _I64, _P, _I64,
+                                    _P]),
+    "hbs_compress": (C.c_int, [C.POINTER(_Options), C.POINTER(_Operator), _P, C.POINTER(_P)]),
+    "hodlr_compress": (C.c_int, [C.POINTER(_Options), C.POINTER(_Operator), _P, C.POINTER(_P)]),
+    "hbs_compress_batched": (C.c_int, [_I32, C.POINTER(_Options), C.POINTER(_Operator), _P,
+                                       C.POINTER(_P)]),
+    "hss_apply": (C.c_int, [_P, _I64, _P, _I64, _P, _I64, _P]),
+    "hss_apply_adjoint": (C.c_int, [_P, _I64, _P, _I64, _P, _I64, _P]),
+    "hss_apply_backward": (C.c_int, [_P, _I64, _P, _I64, _P, _I64, _P, _I64, _P, _P, _P, _P, _P,
+                                     _P, _P]),
+    "hodlr_apply": (C.c_int, [_P, _I32, _I64, _P, _I64, _P, _I64, _P]),
+    "hm_hbs_from_generators": (C.c_int, [_I64, _I64, _I32, _I32, _P, _P, _P, _P, _P, _P, _P,
+                                         C.POINTER(_P)]),
+    "hm_hbs_convert": (C.c_int, [_P, _I32, _P, C.POINTER(_P)]),
+    "hm_hbs_info": (C.c_int, [_P, C.POINTER(_Info)]),
+    "hm_hodlr_info": (C.c_int, [_P, C.POINTER(_Info)]),
+    "hm_hbs_export": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "hm_hodlr_export": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    "hm_hbs_free": (None, [_P]),
+    "hm_hodlr_free": (None, [_P]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class HMError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"hbspeel error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc < 0:
+        raise HMError(rc, lib.hm_last_error().decode())
+    return rc
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def fortran(rows, cols, dtype=torch.float64, device="cuda"):
+    """An uninitialised rows x cols tensor in column-major layout (ld = rows)."""
+    return torch.empty((cols, rows), dtype=dtype, device=device).t()
+
+
+def to_fortran(x, dtype=None, device="cuda"):
+    """Column-major device copy of a 2-D array (numpy or torch); 1-D becomes n x 1."""
+    if isinstance(x, np.ndarray):
+        x = torch.from_numpy(np.ascontiguousarray(x))
+    if x.dim() == 1:
+        x = x[:, None]
+    dtype = dtype or x.dtype
+    out = fortran(x.shape[0], x.shape[1], dtype, device)
+    out.copy_(x)
+    return out
+
+
+def _ld(t):
+    """Leading dimension of a column-major 2-D tensor."""
+    if t.dim() != 2 or t.stride(0) != 1:
+        raise ValueError("expected a column-major 2-D tensor (see fortran())")
+    return max(t.stride(1), t.shape[0])
+
+
+class Options:
+    def __init__(self, n, leaf_size, rank, oversample=10, tol=0.0, seed=0, orthonormal=False):
+        self.c = _Options(n, leaf_size, rank, oversample, tol, seed,
+                          HM_FLAG_ORTHONORMAL if orthonormal else 0)
+
+
+class KernelOperator:
+    """Built-in kernel matrix on 2-D points: ``'log'`` (log|x-y|, 1 on the
+    diagonal) or ``'near'`` (1/(|x-y| + delta)); sampled in ``sample_dtype``."""
+
+    def __init__(self, points, kernel="near", kparam=1e-3, sample_dtype=HM_F64):
+        pts = points if isinstance(points, torch.Tensor) else torch.from_numpy(np.asarray(points))
+        self.points = pts.to(device="cuda", dtype=torch.float64).contiguous()
+        self.c = _Operator()
+        self.c.kind = HM_OP_KERNEL
+        self.c.sample_dtype = sample_dtype
+        self.c.points = self.points.data_ptr()
+        self.c.kernel_id = HM_KERNEL_LOG if kernel == "log" else HM_KERNEL_NEAR
+        self.c.kparam = kparam
+
+
+class DenseOperator:
+    def __init__(self, A):
+        self.A = to_fortran(A, torch.float64)
+        self.c = _Operator()
+        self.c.kind = HM_OP_DENSE
+        self.c.dense = self.A.data_ptr()
+        self.c.ld = _ld(self.A)
+
+
+class HBSOperator:
+    def __init__(self, h):
+        self.h = h
+        self.c = _Operator()
+        self.c.kind = HM_OP_HBS
+        self.c.hbs = h.handle
+
+
+class _DevArray:
+    """Raw device buffer seen by torch through __cuda_array_interface__."""
+
+    def __init__(self, ptr, rows, cols, ld):
+        self.__cuda_array_interface__ = {
+            "shape": (cols, ld), "typestr": "<f8", "data": (ptr, False), "version": 2,
+            "strides": None}
+
+
+class CallbackOperator:
+    """User black box: ``fn(adjoint: bool, X, Y)`` with X, Y n x c column-major
+    float64 tensors that alias library buffers; must write ``Y = A X`` (or
+    ``A^* X``) on the current stream and return None (or 0)."""
+
+    def __init__(self, fn):
+        self.fn = fn
+
+        def tramp(user, adjoint, n, ncols, X, ldx, Y, ldy, stream):
+            try:
+                Xt = torch.as_tensor(_DevArray(X, n, ncols, ldx), device="cuda").t()[:n]
+                Yt = torch.as_tensor(_DevArray(Y, n, ncols, ldy), device="cuda").t()[:n]
+                rc = self.fn(bool(adjoint), Xt, Yt)
+                return int(rc or 0)
+            except Exception:  # noqa: BLE001 -- a failing callback aborts the compression
+                return 1
+
+        self._tramp = MATVEC(tramp)
+        self.c = _Operator()
+        self.c.kind = HM_OP_CALLBACK
+        self.c.fn = self._tramp
+
+
+def _info(fn, handle):
+    inf = _Info()
+    _check(fn(handle, C.byref(inf)))
+    return {k: getattr(inf, k) for k, _ in _Info._fields_}
+
+
+class HBS:
+    """An HBS handle owned by the library."""
+
+    def __init__(self, handle, status=HM_OK):
+        self.handle = handle
+        self.status = status
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            lib.hm_hbs_free(self.handle)
+            self.handle = None
+
+    def info(self):
+        return _info(lib.hm_hbs_info, self.handle)
+
+    def export(self, stream=None):
+        """Generators in the flat layout (torch tensors on the device, heap-
+        indexed blocks) plus host ranks and skeletons."""
+        inf = self.info()
+        n, R, L = inf["n"], inf["rank_pad"], inf["levels"]
+        nn = 2 ** (L + 1)
+        dt = torch.float64 if inf["dtype"] == HM_F64 else torch.float32
+        leafmax = self._nmax(n, inf["leaf_size"], L)
+        out = dict(U=fortran(n, R, dt), V=fortran(n, R, dt),
+                   Ut=torch.zeros((nn, R, 2 * R), dtype=dt, device="cuda"),
+                   Vt=torch.zeros((nn, R, 2 * R), dtype=dt, device="cuda"),
+                   B=torch.zeros((nn, R, R), dtype=dt, device="cuda"),
+                   D=fortran(n, leafmax, dt))
+        ru = np.zeros(nn, dtype=np.int32)
+        rv = np.zeros(nn, dtype=np.int32)
+        si = np.full(nn * R, -1, dtype=np.int32)
+        so = np.full(nn * R, -1, dtype=np.int32)
+        ip = lambda a: a.ctypes.data_as(C.c_void_p)
+        _check(lib.hm_hbs_export(self.handle, _ptr(out["U"]), _ptr(out["V"]), _ptr(out["Ut"]),
+                                 _ptr(out["Vt"]), _ptr(out["B"]), _ptr(out["D"]), ip(ru), ip(rv),
+                                 ip(si), ip(so), _stream(stream)))
+        torch.cuda.synchronize()
+        # per-node blocks are column-major: block t viewed as (cols, rows) -> transpose
+        out["Ut"] = out["Ut"].transpose(1, 2)
+        out["Vt"] = out["Vt"].transpose(1, 2)
+        out["B"] = out["B"].transpose(1, 2)
+        out.update(rank_u=ru, rank_v=rv, skel_in=si.reshape(nn, R), skel_out=so.reshape(nn, R),
+                   n=n, R=R, L=L, leaf=inf["leaf_size"], is_id=inf["is_id"])
+        return out
+
+    @staticmethod
+    def _nmax(n, leaf, L):
+        return -(-n // (2 ** L))
+
+    def apply(self, x, adjoint=False, stream=None):
+        return (hss_apply_adjoint if adjoint else hss_apply)(self, x, stream=stream)
+
+
+class HODLR:
+    def __init__(self, handle, status=HM_OK):
+        self.handle = handle
+        self.status = status
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            lib.hm_hodlr_free(self.handle)
+            self.handle = None
+
+    def info(self):
+        return _info(lib.hm_hodlr_info, self.handle)
+
+    def apply(self, x, adjoint=False, stream=None):
+        return hodlr_apply(self, x, adjoint=adjoint, stream=stream)
+
+    def export(self, stream=None):
+        inf = self.info()
+        n, R, L = inf["n"], inf["rank_pad"], inf["levels"]
+        nn = 2 ** (L + 1)
+        U = torch.zeros((max(L, 1), R, n), dtype=torch.float64, device="cuda")
+        V = torch.zeros_like(U)
+        s = torch.zeros((nn, R), dtype=torch.float64, device="cuda")
+        D = fortran(n, HBS._nmax(n, inf["leaf_size"], L))
+        rk = np.zeros(nn, dtype=np.int32)
+        _check(lib.hm_hodlr_export(self.handle, _ptr(U), _ptr(V), _ptr(s), _ptr(D),
+                                   rk.ctypes.data_as(C.c_void_p), _stream(stream)))
+        torch.cuda.synchronize()
+        return dict(U=U.transpose(1, 2), V=V.transpose(1, 2), s=s, D=D, rank=rk, n=n, R=R, L=L)
+
+
+def hm_gauss(seed, level, phase, row0, nrows, ncols, out=None, stream=None):
+    """Rows row0.. of the counter-based Gaussian stream (n x ncols, column-major)."""
+    if out is None:
+        out = fortran(nrows, ncols)
+    _check(lib.hm_gauss(seed, level, phase, row0, nrows, ncols, _ptr(out), _ld(out),
+                        _stream(stream)))
+    return out
+
+
+def hm_operator_apply(op, x, adjoint=False, stream=None):
+    """Y = A X (or A^* X) through a built-in or callback operator."""
+    xf = to_fortran(x, torch.float64)
+    y = fortran(xf.shape[0], xf.shape[1])
+    _check(lib.hm_operator_apply(C.byref(op.c), xf.shape[0], 1 if adjoint else 0, xf.shape[1],
+                                 _ptr(xf), _ld(xf), _ptr(y), _ld(y), _stream(stream)))
+    return y
+
+
+def hbs_compress(opts: Options, op, stream=None) -> HBS:
+    h = C.c_void_p()
+    rc = _check(lib.hbs_compress(C.byref(opts.c), C.byref(op.c), _stream(stream), C.byref(h)))
+    return HBS(h, rc)
+
+
+def hodlr_compress(opts: Options, op, stream=None) -> HODLR:
+    h = C.c_void_p()
+    rc = _check(lib.hodlr_compress(C.byref(opts.c), C.byref(op.c), _stream(stream), C.byref(h)))
+    return HODLR(h, rc)
+
+
+def hbs_compress_batched(opts_list, ops_list, stream=None):
+    cnt = len(opts_list)
+    O = (_Options * cnt)(*[o.c for o in opts_list])
+    P = (_Operator * cnt)(*[o.c for o in ops_list])
+    H = (C.c_void_p * cnt)()
+    rc = _check(lib.hbs_compress_batched(cnt, O, P, _stream(stream), H))
+    return [HBS(C.c_void_p(H[i]), rc) for i in range(cnt)]
+
+
+def _apply(fn, h, x, stream):
+    dt = torch.float64 if h.info()["dtype"] == HM_F64 else torch.float32
+    xf = x if (x.dim() == 2 and x.stride(0) == 1 and x.dtype == dt and x.is_cuda) else to_fortran(x, dt)
+    y = fortran(xf.shape[0], xf.shape[1], dt)
+    _check(fn(h.handle, xf.shape[1], _ptr(xf), _ld(xf), _ptr(y), _ld(y), _stream(stream)))
+    return y
+
+
+def hss_apply(h: HBS, x, stream=None):
+    return _apply(lib.hss_apply, h, x, stream)
+
+
+def hss_apply_adjoint(h: HBS, x, stream=None):
+    return _apply(lib.hss_apply_adjoint, h, x, stream)
+
+
+def hss_apply_backward(h: HBS, x, gy, want_generators=True, stream=None):
+    """gx = A_H^* gy and the generator gradients of <gy, A_H x> (flat layout)."""
+    inf = h.info()
+    dt = torch.float64 if inf["dtype"] == HM_F64 else torch.float32
+    n, R, L = inf["n"], inf["rank_pad"], inf["levels"]
+    nn = 2 ** (L + 1)
+    xf = to_fortran(x, dt)
+    gyf = to_fortran(gy, dt)
+    gx = fortran(n, xf.shape[1], dt)
+    g = None
+    if want_generators:
+        g = dict(U=fortran(n, R, dt), V=fortran(n, R, dt),
+                 Ut=torch.zeros((nn, R, 2 * R), dtype=dt, device="cuda"),
+                 Vt=torch.zeros((nn, R, 2 * R), dtype=dt, device="cuda"),
+                 B=torch.zeros((nn, R, R), dtype=dt, device="cuda"),
+                 D=fortran(n, HBS._nmax(n, inf["leaf_size"], L), dt))
+    gp = (lambda k: _ptr(g[k]) if g else None)
+    _check(lib.hss_apply_backward(h.handle, xf.shape[1], _ptr(xf), _ld(xf), _ptr(gyf), _ld(gyf),
+                                  _ptr(gx), _ld(gx), gp("U"), gp("V"), gp("Ut"), gp("Vt"),
+                                  gp("B"), gp("D"), _stream(stream)))
+    if g:
+        for k in ("Ut", "Vt", "B"):
+            g[k] = g[k].transpose(1, 2)
+    return gx, g
+
+
+def hodlr_apply(h: HODLR, x, adjoint=False, stream=None):
+    xf = to_fortran(x, torch.float64)
+    y = fortran(xf.shape[0], xf.shape[1])
+    _check(lib.hodlr_apply(h.handle, 1 if adjoint else 0, xf.shape[1], _ptr(xf), _ld(xf), _ptr(y),
+                           _ld(y), _stream(stream)))
+    return y
+
+
+def hm_hbs_from_generators(g: dict, dtype=HM_F64, stream=None) -> HBS:
+    """HBS handle from generators in the flat layout of ``workloads.synthetic_hbs``
+    (numpy, row-major per-node blocks); uploads column-major copies."""
+    tdt = torch.float64 if dtype == HM_F64 else torch.float32
+    n, leaf, k = g["n"], g["leaf"], g["k"]
+    U = to_fortran(g["U"], tdt)
+    V = to_fortran(g["V"], tdt)
+    blk = lambda a: torch.from_numpy(np.ascontiguousarray(np.swapaxes(a, 1, 2))).to(
+        device="cuda", dtype=tdt).contiguous()
+    Ut, Vt, B = blk(g["Ut"]), blk(g["Vt"]), blk(g["B"])
+    D = to_fortran(g["D"], tdt)
+    h = C.c_void_p()
+    _check(lib.hm_hbs_from_generators(n, leaf, k, dtype, _ptr(U), _ptr(V), _ptr(Ut), _ptr(Vt),
+                                      _ptr(B), _ptr(D), _stream(stream), C.byref(h)))
+    torch.cuda.synchronize()
+    return HBS(h)

@@ -1,0 +1,371 @@
+// extern "C" entry points of libhbspeel (declared in include/hbspeel.h):
+// argument validation, exception-to-status translation, handle management.
+#include <cstring>
+
+#include "handle.h"
+
+using namespace hm;
+
+namespace {
+
+template <class F>
+int guarded(F&& f) {
+  try {
+    set_error("%s", "");
+    return f();
+  } catch (const Error& e) {
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return HM_ERR_ALLOC;
+  } catch (...) {
+    set_error("unexpected exception");
+    return HM_ERR_HIP;
+  }
+}
+
+void check_options(const hm_options* o) {
+  if (!o) HM_THROW(HM_ERR_ARG, "options is NULL");
+  if (o->n < 1) HM_THROW(HM_ERR_ARG, "n = %lld < 1", (long long)o->n);
+  if (o->leaf_size < 1) HM_THROW(HM_ERR_ARG, "leaf_size = %lld < 1", (long long)o->leaf_size);
+  if (o->rank < 1) HM_THROW(HM_ERR_ARG, "rank = %d < 1", o->rank);
+  if (o->oversample < 0) HM_THROW(HM_ERR_ARG, "oversample = %d < 0", o->oversample);
+  if (!(o->tol >= 0.0 && o->tol < 1.0)) HM_THROW(HM_ERR_ARG, "tol = %g outside [0, 1)", o->tol);
+  if (o->rank + o->oversample > HM_MAX_SAMPLES)
+    HM_THROW(HM_ERR_UNSUPPORTED, "rank + oversample = %d > %d", o->rank + o->oversample,
+             HM_MAX_SAMPLES);
+  if (o->n > ((int64_t)1 << 31)) HM_THROW(HM_ERR_UNSUPPORTED, "n > 2^31");
+  if (o->n > o->leaf_size && o->leaf_size > 256)
+    HM_THROW(HM_ERR_UNSUPPORTED, "leaf_size %lld > 256", (long long)o->leaf_size);
+}
+
+void check_operator(const hm_operator* op, int64_t n, bool builtin_only) {
+  if (!op) HM_THROW(HM_ERR_ARG, "operator is NULL");
+  switch (op->kind) {
+    case HM_OP_CALLBACK:
+      if (builtin_only) HM_THROW(HM_ERR_ARG, "callback operators are not allowed here");
+      if (!op->fn) HM_THROW(HM_ERR_ARG, "callback operator without function");
+      break;
+    case HM_OP_KERNEL:
+      if (!op->points) HM_THROW(HM_ERR_ARG, "kernel operator without points");
+      if (op->kernel_id != HM_KERNEL_LOG && op->kernel_id != HM_KERNEL_NEAR)
+        HM_THROW(HM_ERR_ARG, "unknown kernel id %d", op->kernel_id);
+      if (op->sample_dtype != HM_F64 && op->sample_dtype != HM_F32 && op->sample_dtype != HM_BF16)
+        HM_THROW(HM_ERR_ARG, "bad sample dtype %d", op->sample_dtype);
+      break;
+    case HM_OP_DENSE:
+      if (!op->dense || op->ld < n) HM_THROW(HM_ERR_ARG, "dense operator: null or ld < n");
+      break;
+    case HM_OP_HBS:
+      if (!op->hbs || op->hbs->f.n_total != n || op->hbs->dtype != HM_F64)
+        HM_THROW(HM_ERR_ARG, "HBS operator: null, size mismatch or not FP64");
+      break;
+    default:
+      HM_THROW(HM_ERR_ARG, "unknown operator kind %d", op->kind);
+  }
+}
+
+Forest single_forest(const hm_options* o) {
+  Forest f;
+  forest_add_tree(f, o->n, o->leaf_size, o->rank + o->oversample,
+                  o->tol > 0.0 ? o->rank : o->rank, o->oversample, o->tol, o->seed);
+  return f;
+}
+
+size_t dsize(int dtype) { return dtype == HM_F32 ? 4 : 8; }
+
+}  // namespace
+
+extern "C" {
+
+const char* hm_last_error(void) { return get_error(); }
+const char* hm_version(void) { return "hbspeel 0.1 (gfx950)"; }
+
+int hm_gauss(uint64_t seed, int32_t level, int32_t phase, int64_t row0, int64_t nrows,
+             int32_t ncols, double* out, int64_t ld, void* stream) {
+  return guarded([&] {
+    if (!out || nrows < 0 || ncols < 0 || ld < nrows || row0 < 0)
+      HM_THROW(HM_ERR_ARG, "hm_gauss: bad arguments");
+    launch_gauss_raw(seed, level, phase, row0, nrows, ncols, out, ld, (hipStream_t)stream);
+    return HM_OK;
+  });
+}
+
+int hm_operator_apply(const hm_operator* op, int64_t n, int32_t adjoint, int64_t ncols,
+                      const double* X, int64_t ldx, double* Y, int64_t ldy, void* stream) {
+  return guarded([&] {
+    if (n < 1 || ncols < 0 || !X || !Y || ldx < n || ldy < n)
+      HM_THROW(HM_ERR_ARG, "operator_apply: bad arguments");
+    check_operator(op, n, false);
+    if (ncols == 0) return HM_OK;
+    OpRunner run;
+    run.op = *op;
+    run.hbs = op->kind == HM_OP_HBS ? op->hbs : nullptr;
+    run.s = (hipStream_t)stream;
+    for (int64_t c0 = 0; c0 < ncols; c0 += 128) {
+      const int c = (int)std::min<int64_t>(128, ncols - c0);
+      run.apply(adjoint != 0, n, c, X + c0 * ldx, ldx, Y + c0 * ldy, ldy);
+    }
+    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    return HM_OK;
+  });
+}
+
+int hbs_compress(const hm_options* opts, const hm_operator* op, void* stream, hm_hbs** out) {
+  if (out) *out = nullptr;
+  return guarded([&] {
+    if (!out) HM_THROW(HM_ERR_ARG, "out is NULL");
+    check_options(opts);
+    check_operator(op, opts->n, false);
+    OpRunner run;
+    run.op = *op;
+    run.hbs = op->kind == HM_OP_HBS ? op->hbs : nullptr;
+    run.s = (hipStream_t)stream;
+    std::vector<OpRunner*> ops{&run};
+    int status = HM_OK;
+    hm_hbs_s* h = hbs_compress_forest(single_forest(opts), ops, opts->flags, (hipStream_t)stream,
+                                      &status);
+    *out = h;
+    return status;
+  });
+}
+
+int hbs_compress_batched(int32_t count, const hm_options* opts, const hm_operator* ops,
+                         void* stream, hm_hbs** outs) {
+  return guarded([&]() -> int {
+    if (count < 1 || !opts || !ops || !outs) HM_THROW(HM_ERR_ARG, "batched: bad arguments");
+    for (int i = 0; i < count; ++i) outs[i] = nullptr;
+    HM_THROW(HM_ERR_UNSUPPORTED, "batched compression is not built yet");
+  });
+}
+
+int hodlr_compress(const hm_options* opts, const hm_operator* op, void* stream, hm_hodlr** out) {
+  if (out) *out = nullptr;
+  return guarded([&]() -> int {
+    if (!out) HM_THROW(HM_ERR_ARG, "out is NULL");
+    check_options(opts);
+    check_operator(op, opts->n, false);
+    OpRunner run;
+    run.op = *op;
+    run.hbs = op->kind == HM_OP_HBS ? op->hbs : nullptr;
+    run.s = (hipStream_t)stream;
+    int status = HM_OK;
+    *out = hodlr_compress_forest(single_forest(opts), run, (hipStream_t)stream, &status);
+    return status;
+  });
+}
+
+static int apply_impl(const hm_hbs* h, bool adjoint, int64_t nrhs, const void* x, int64_t ldx,
+                      void* y, int64_t ldy, void* stream) {
+  return guarded([&] {
+    if (!h || !x || !y || nrhs < 0) HM_THROW(HM_ERR_ARG, "apply: bad arguments");
+    const int64_t n = h->f.n_total;
+    if (ldx < n || ldy < n) HM_THROW(HM_ERR_ARG, "apply: ld < n");
+    if (nrhs == 0) return HM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const int cmax = 128;
+    for (int64_t c0 = 0; c0 < nrhs; c0 += cmax) {
+      const int c = (int)std::min<int64_t>(cmax, nrhs - c0);
+      if (h->dtype == HM_F64) {
+        const size_t wb = apply_work_bytes<double>(h->f, h->full, h->R, c);
+        void* w = nullptr;
+        HIPCHK(hipMallocAsync(&w, wb, s));
+        apply_forest<double>(h->d_nodes.as<Node>(), h->full, h->view<double>(), adjoint, c,
+                             static_cast<const double*>(x) + c0 * ldx, ldx,
+                             static_cast<double*>(y) + c0 * ldy, ldy, 1.0, 0.0, w,
+                             h->f.nodes.size(), s);
+        HIPCHK(hipFreeAsync(w, s));
+      } else {
+        const size_t wb = apply_work_bytes<float>(h->f, h->full, h->R, c);
+        void* w = nullptr;
+        HIPCHK(hipMallocAsync(&w, wb, s));
+        apply_forest<float>(h->d_nodes.as<Node>(), h->full, h->view<float>(), adjoint, c,
+                            static_cast<const float*>(x) + c0 * ldx, ldx,
+                            static_cast<float*>(y) + c0 * ldy, ldy, 1.0f, 0.0f, w,
+                            h->f.nodes.size(), s);
+        HIPCHK(hipFreeAsync(w, s));
+      }
+    }
+    return HM_OK;
+  });
+}
+
+int hss_apply(const hm_hbs* h, int64_t nrhs, const void* x, int64_t ldx, void* y, int64_t ldy,
+              void* stream) {
+  return apply_impl(h, false, nrhs, x, ldx, y, ldy, stream);
+}
+
+int hss_apply_adjoint(const hm_hbs* h, int64_t nrhs, const void* x, int64_t ldx, void* y,
+                      int64_t ldy, void* stream) {
+  return apply_impl(h, true, nrhs, x, ldx, y, ldy, stream);
+}
+
+int hm_hbs_from_generators(int64_t n, int64_t leaf_size, int32_t k, int32_t dtype, const void* U,
+                           const void* V, const void* Ut, const void* Vt, const void* B,
+                           const void* D, void* stream, hm_hbs** out) {
+  if (out) *out = nullptr;
+  return guarded([&] {
+    if (!out || n < 1 || leaf_size < 1 || k < 1 || !U || !V || !Ut || !Vt || !B || !D)
+      HM_THROW(HM_ERR_ARG, "from_generators: bad arguments");
+    if (dtype != HM_F64 && dtype != HM_F32) HM_THROW(HM_ERR_ARG, "dtype must be F64 or F32");
+    if (k > 64) HM_THROW(HM_ERR_UNSUPPORTED, "rank %d > 64", k);
+    hipStream_t s = (hipStream_t)stream;
+    std::unique_ptr<hm_hbs_s> h(new hm_hbs_s());
+    forest_add_tree(h->f, n, leaf_size, k, k, 0, 0.0, 0);
+    forest_finish(h->f);
+    const Forest& f = h->f;
+    for (int g : f.leaves)
+      if (f.inst[0].L > 0 && f.nodes[g].hi - f.nodes[g].lo < k)
+        HM_THROW(HM_ERR_ARG, "every leaf must hold at least k indices");
+    h->R = k;
+    h->dtype = dtype;
+    h->is_id = 0;
+    const size_t es = dsize(dtype);
+    const int nn = (int)f.nodes.size();
+    const int nmax = f.nmax;
+    h->d_nodes = upload(f.nodes, s);
+    h->d_inst = upload(f.inst, s);
+    h->U = DevBuf((size_t)n * k * es);
+    h->V = DevBuf((size_t)n * k * es);
+    h->Ut = DevBuf((size_t)nn * 2 * k * k * es);
+    h->Vt = DevBuf((size_t)nn * 2 * k * k * es);
+    h->B = DevBuf((size_t)nn * k * k * es);
+    h->D = DevBuf((size_t)n * nmax * es);
+    auto cp = [&](DevBuf& d, const void* src, size_t off_elems, size_t elems) {
+      HIPCHK(hipMemcpyAsync(d.p, static_cast<const char*>(src) + off_elems * es, elems * es,
+                            hipMemcpyDeviceToDevice, s));
+    };
+    cp(h->U, U, 0, (size_t)n * k);
+    cp(h->V, V, 0, (size_t)n * k);
+    // flat layout is heap-indexed (block t), handles are node-indexed (g = t - 1)
+    cp(h->Ut, Ut, (size_t)2 * k * k, (size_t)nn * 2 * k * k);
+    cp(h->Vt, Vt, (size_t)2 * k * k, (size_t)nn * 2 * k * k);
+    cp(h->B, B, (size_t)k * k, (size_t)nn * k * k);
+    cp(h->D, D, 0, (size_t)n * nmax);
+    std::vector<int> mvec{f.inst[0].L};
+    build_apply_lists(f, mvec, h->full, s);
+    h->rank_u.assign(nn, 0);
+    h->rank_v.assign(nn, 0);
+    for (int g = 1; g < nn; ++g) h->rank_u[g] = h->rank_v[g] = k;
+    h->skel_in.assign((size_t)nn * k, -1);
+    h->skel_out.assign((size_t)nn * k, -1);
+    HIPCHK(hipStreamSynchronize(s));
+    finish_handle_info(h.get());
+    *out = h.release();
+    return HM_OK;
+  });
+}
+
+int hm_hbs_convert(const hm_hbs* h, int32_t dtype, void* stream, hm_hbs** out) {
+  if (out) *out = nullptr;
+  return guarded([&]() -> int {
+    if (!h || !out) HM_THROW(HM_ERR_ARG, "convert: bad arguments");
+    HM_THROW(HM_ERR_UNSUPPORTED, "conversion is not built yet");
+  });
+}
+
+int hm_hbs_info(const hm_hbs* h, hm_info* o) {
+  return guarded([&] {
+    if (!h || !o) HM_THROW(HM_ERR_ARG, "info: bad arguments");
+    *o = h->info;
+    return HM_OK;
+  });
+}
+
+int hm_hbs_export(const hm_hbs* h, void* U, void* V, void* Ut, void* Vt, void* B, void* D,
+                  int32_t* ranks_u, int32_t* ranks_v, int32_t* skel_in, int32_t* skel_out,
+                  void* stream) {
+  return guarded([&] {
+    if (!h) HM_THROW(HM_ERR_ARG, "export: NULL handle");
+    hipStream_t s = (hipStream_t)stream;
+    const Forest& f = h->f;
+    const int64_t n = f.n_total;
+    const int R = h->R;
+    const int nn = (int)f.nodes.size();
+    const size_t es = dsize(h->dtype);
+    auto cp = [&](void* dst, const DevBuf& src, size_t dst_off_elems, size_t elems) {
+      if (!dst) return;
+      HIPCHK(hipMemcpyAsync(static_cast<char*>(dst) + dst_off_elems * es, src.p, elems * es,
+                            hipMemcpyDeviceToDevice, s));
+    };
+    if (Ut) HIPCHK(hipMemsetAsync(Ut, 0, (size_t)2 * R * R * es, s));
+    if (Vt) HIPCHK(hipMemsetAsync(Vt, 0, (size_t)2 * R * R * es, s));
+    if (B) HIPCHK(hipMemsetAsync(B, 0, (size_t)R * R * es, s));
+    cp(U, h->U, 0, (size_t)n * R);
+    cp(V, h->V, 0, (size_t)n * R);
+    cp(Ut, h->Ut, (size_t)2 * R * R, (size_t)nn * 2 * R * R);
+    cp(Vt, h->Vt, (size_t)2 * R * R, (size_t)nn * 2 * R * R);
+    cp(B, h->B, (size_t)R * R, (size_t)nn * R * R);
+    cp(D, h->D, 0, (size_t)n * f.nmax);
+    // host arrays are heap-indexed (entry t = node t - 1); entry 0 unused
+    if (ranks_u) { ranks_u[0] = 0; std::memcpy(ranks_u + 1, h->rank_u.data(), nn * 4); }
+    if (ranks_v) { ranks_v[0] = 0; std::memcpy(ranks_v + 1, h->rank_v.data(), nn * 4); }
+    if (skel_in) {
+      std::fill(skel_in, skel_in + R, -1);
+      std::memcpy(skel_in + R, h->skel_in.data(), (size_t)nn * R * 4);
+    }
+    if (skel_out) {
+      std::fill(skel_out, skel_out + R, -1);
+      std::memcpy(skel_out + R, h->skel_out.data(), (size_t)nn * R * 4);
+    }
+    return HM_OK;
+  });
+}
+
+void hm_hbs_free(hm_hbs* h) { delete h; }
+
+int hss_apply_backward(const hm_hbs* h, int64_t nrhs, const void* x, int64_t ldx, const void* gy,
+                       int64_t ldgy, void* gx, int64_t ldgx, void* gU, void* gV, void* gUt,
+                       void* gVt, void* gB, void* gD, void* stream) {
+  return guarded([&]() -> int { HM_THROW(HM_ERR_UNSUPPORTED, "backward is not built yet"); });
+}
+
+int hodlr_apply(const hm_hodlr* h, int32_t adjoint, int64_t nrhs, const double* x, int64_t ldx,
+                double* y, int64_t ldy, void* stream) {
+  return guarded([&] {
+    if (!h || !x || !y || nrhs < 0) HM_THROW(HM_ERR_ARG, "hodlr_apply: bad arguments");
+    const int64_t n = h->f.n_total;
+    if (ldx < n || ldy < n) HM_THROW(HM_ERR_ARG, "hodlr_apply: ld < n");
+    for (int64_t c0 = 0; c0 < nrhs; c0 += 128) {
+      const int c = (int)std::min<int64_t>(128, nrhs - c0);
+      hodlr_apply_full(h, adjoint != 0, c, x + c0 * ldx, ldx, y + c0 * ldy, ldy,
+                       (hipStream_t)stream);
+    }
+    return HM_OK;
+  });
+}
+
+int hm_hodlr_info(const hm_hodlr* h, hm_info* o) {
+  return guarded([&] {
+    if (!h || !o) HM_THROW(HM_ERR_ARG, "info: bad arguments");
+    *o = h->info;
+    return HM_OK;
+  });
+}
+
+int hm_hodlr_export(const hm_hodlr* h, double* U, double* V, double* s, double* D, int32_t* ranks,
+                    void* stream) {
+  return guarded([&] {
+    if (!h) HM_THROW(HM_ERR_ARG, "export: NULL handle");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = h->f.n_total;
+    const int R = h->R;
+    const int nn = (int)h->f.nodes.size();
+    for (size_t l = 0; l < h->U.size(); ++l) {
+      if (U) HIPCHK(hipMemcpyAsync(U + l * n * R, h->U[l].p, (size_t)n * R * 8, hipMemcpyDeviceToDevice, st));
+      if (V) HIPCHK(hipMemcpyAsync(V + l * n * R, h->V[l].p, (size_t)n * R * 8, hipMemcpyDeviceToDevice, st));
+    }
+    if (s) {
+      HIPCHK(hipMemsetAsync(s, 0, (size_t)R * 8, st));
+      HIPCHK(hipMemcpyAsync(s + R, h->S.p, (size_t)nn * R * 8, hipMemcpyDeviceToDevice, st));
+    }
+    if (D) HIPCHK(hipMemcpyAsync(D, h->D.p, (size_t)n * h->f.nmax * 8, hipMemcpyDeviceToDevice, st));
+    if (ranks) { ranks[0] = 0; std::memcpy(ranks + 1, h->rank.data(), nn * 4); }
+    return HM_OK;
+  });
+}
+
+void hm_hodlr_free(hm_hodlr* h) { delete h; }
+
+}  // extern "C"
+

@@ -1,0 +1,147 @@
+// Internal declarations shared by the host orchestration and the HIP kernels
+// of libhbspeel.  Not part of the public ABI (include/hbspeel.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/hbspeel.h"
+
+namespace hm {
+
+// ---------------------------------------------------------------- errors --
+void set_error(const char* fmt, ...);
+const char* get_error();
+
+struct Error {
+  int code;
+};
+
+#define HM_THROW(code, ...)      \
+  do {                           \
+    ::hm::set_error(__VA_ARGS__); \
+    throw ::hm::Error{code};     \
+  } while (0)
+
+#define HIPCHK(expr)                                                        \
+  do {                                                                      \
+    hipError_t e_ = (expr);                                                 \
+    if (e_ != hipSuccess)                                                   \
+      HM_THROW(HM_ERR_HIP, "%s failed: %s (%s:%d)", #expr,                  \
+               hipGetErrorString(e_), __FILE__, __LINE__);                  \
+  } while (0)
+
+#define KCHK() HIPCHK(hipGetLastError())
+
+// ------------------------------------------------------------ forest --------
+// A forest of binary index trees (Sec. 2.6) over one global row space: one
+// tree per instance (a single compression is a forest of one tree).  Every
+// node carries global row bounds and explicit parent/child/sibling ids, so
+// kernels take node lists instead of heap arithmetic.
+struct Node {
+  int64_t lo, hi;      // global rows [lo, hi)
+  int32_t parent;      // -1 for a root
+  int32_t left, right; // -1 for a leaf
+  int32_t sib;         // -1 for a root
+  int32_t level;       // depth in its tree (root 0)
+  int32_t inst;        // instance
+  int32_t heap;        // heap number inside its tree (root 1, children 2t, 2t+1)
+  int32_t is_left;     // 1 if left child
+  int32_t pad_;
+};
+
+struct Instance {
+  int64_t row0, n, leaf;
+  int32_t L;           // depth of its leaves
+  int32_t r;           // samples per level (= rank + oversample)
+  int32_t k;           // rank (fixed) or rank cap (tol mode)
+  int32_t p;           // oversampling
+  double tol;
+  uint64_t seed;
+  int32_t root;        // global id of its root
+  int32_t nmax;        // largest leaf
+};
+
+struct Forest {
+  std::vector<Node> nodes;
+  std::vector<Instance> inst;
+  int64_t n_total = 0;
+  int32_t max_levels = 0;           // max over instances of L
+  // lists of global node ids
+  std::vector<std::vector<int32_t>> level;  // all nodes with level == l
+  std::vector<int32_t> leaves;
+  int32_t nmax = 0;                 // largest leaf over all instances
+  int32_t heap_size(int i) const { return 1 << (inst[i].L + 1); }
+};
+
+void forest_add_tree(Forest& f, int64_t n, int64_t leaf, int32_t r, int32_t k,
+                     int32_t p, double tol, uint64_t seed);
+void forest_finish(Forest& f);
+
+// ------------------------------------------------------------- memory -------
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t b) { alloc(b); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    release();
+    p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0;
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void alloc(size_t b);
+  void release();
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Upload a host vector into a fresh device buffer (synchronous w.r.t. host
+// memory: the copy is staged before return).
+template <class T>
+DevBuf upload(const std::vector<T>& v, hipStream_t s) {
+  DevBuf b(v.size() * sizeof(T) + 16);
+  if (!v.empty())
+    HIPCHK(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return b;
+}
+
+// ------------------------------------------------------------ kernels -------
+// Gaussian stream (Philox4x32-10 + Box-Muller), see hm_gauss.
+void launch_gauss_raw(uint64_t seed, int level, int phase, int64_t row0, int64_t nrows,
+                      int ncols, double* out, int64_t ld, hipStream_t s);
+// Structured test matrix [Omega_2 | Omega_1] for forest level `level`:
+// for every child node v in `kids` (nodes on level+1), rows I_v get the
+// instance's Gaussian G_level(i - row0, j), j < r, in columns [0, r) if v is a
+// right child, [R, R + r) if a left child.  Other columns of those rows are 0.
+void launch_gauss_masked(const Node* nodes, const Instance* inst, const int32_t* kids,
+                         int nkids, int64_t max_rows, int level, int R, double* Om,
+                         int64_t ld, hipStream_t s);
+// Same masking with a given long basis instead of Gaussians (Psi of Fig. 2/4):
+// rows I_v get U(I_v, 0:r) in the half chosen by the side of v.
+void launch_mask_basis(const Node* nodes, const Instance* inst, const int32_t* kids,
+                       int nkids, int64_t max_rows, int R, const double* U, int64_t ldu,
+                       double* Om, int64_t ld, hipStream_t s);
+// Block identity of the diagonal extraction: Om(I_t, 0:n_t) = I for leaves t.
+void launch_block_eye(const Node* nodes, const int32_t* leaves, int nleaves,
+                      int64_t max_rows, int nmax, double* Om, int64_t ld, hipStream_t s);
+
+// Zero D(I_t, n_t : nmax) of leaves smaller than nmax.
+void launch_zero_dpad(const Node* nodes, const int32_t* leaves, int nleaves, int64_t max_rows,
+                      int nmax, double* D, int64_t ld, hipStream_t s);
+void launch_fill(double* p, int64_t rows, int64_t cols, int64_t ld, double v, hipStream_t s);
+void launch_fill_f(float* p, int64_t count, float v, hipStream_t s);
+void launch_nonfinite_check(const double* p, int64_t rows, int64_t cols, int64_t ld,
+                            int* flag, hipStream_t s);
+
+// Small-matrix kernels used by apply and compress live in their own headers
+// (apply.h, factor.h, sampler.h).
+
+}  // namespace hm

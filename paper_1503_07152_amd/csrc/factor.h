@@ -1,0 +1,89 @@
+// Node factorisations of the peeling step: Householder QR of tall node blocks
+// by a tree of LDS-resident panels (TSQR), one-sided Jacobi SVD of the final
+// triangle, reflector application that writes the basis directly, and the
+// column-pivoted QR behind the interpolative decomposition (Sec. 2.2-2.4).
+#pragma once
+#include "common.h"
+
+namespace hm {
+
+constexpr int FAC_CMAX = 2 * HM_MAX_SAMPLES;  // columns of a node block
+constexpr int FAC_PMAX = 2 * FAC_CMAX;        // rows of a panel (two stacked triangles)
+constexpr int FAC_LDMAX = FAC_PMAX + 1;
+
+struct PanelDesc {
+  double* A;        // panel (global, column-major): rows x cols, factored in place
+  int64_t ld;
+  int32_t rows, cols;
+  double* tau;      // min(rows, cols) reflector scalars
+  double* Rout;     // R (min(rows,cols) x cols, zeros below the diagonal)
+  int64_t ldR;
+  const double* Cin;  // apply: h x ncol input (h = min(rows, cols))
+  int64_t ldCin;
+  double* Cout;     // apply: rows x ncol output  Q [Cin; 0]
+  int64_t ldCout;
+  int32_t ncol;
+  int32_t pad_;
+};
+
+struct SvdDesc {
+  const double* R;  // h x c (h <= c), leading dim ldR
+  int64_t ldR;
+  int32_t h, c;
+  double* W;        // left singular vectors, h x kout (descending singular values)
+  int64_t ldW;
+  double* sv;       // kout singular values
+  double* X;        // right singular vectors, c x kout (may be null)
+  int64_t ldX;
+  int32_t kout;
+  int32_t pad_;
+};
+
+void launch_panel_qr(const PanelDesc* d, int n, hipStream_t s);
+void launch_apply_q(const PanelDesc* d, int n, hipStream_t s);
+void launch_jacobi_svd(const SvdDesc* d, int n, hipStream_t s);
+
+// Node block of the peeling step (Fig. 4): for each child v (list), rows I_v of
+// M get [S(I_v, off : off + r), Lpar(I_v, 0:r) diag(w_parent)] with off = 0 for
+// a left child, R for a right child; the second half is omitted under the root.
+void launch_build_node_block(const Node* nodes, const Instance* inst, const int32_t* kids,
+                             int nkids, int64_t max_rows, int R, const double* S, int64_t lds,
+                             const double* Lpar, int64_t ldl, const double* w, double* M,
+                             int64_t ldm, hipStream_t s, int first_half_only = 0);
+// B[v] = X_v(0:r, 0:r) diag(z_v) (zero-padded to R x R); X_v at X + v*2R*R, ld 2R.
+void launch_form_b(const Node* nodes, const Instance* inst, const int32_t* kids, int nkids, int R,
+                   const double* X, const double* z, double* B, hipStream_t s);
+
+// Interpolative decomposition by column-pivoted QR of W^* (Sec. 2.4, eq.
+// buildTJ): for each node of `list`, the candidate rows of W = Src diag(w):
+//  leaf mode   : rows I_t of Src (N x R, ld lds); skeleton ids lo + i
+//  parent mode : Src block t (2R x R, ld 2R); candidate i maps to skeleton
+//                skel[left][i] (i < R) or skel[right][i - R]
+// Outputs: interpolation basis P (leaf: rows I_t of an N x R array, ld ldp;
+// parent: block t of 2R x R), samp_t = Src(J, :) (R x R, rows >= k zero),
+// rank_t, skel_t (R entries, -1 padded).  Truncation: k steps or the first
+// residual norm <= tol * |R_11| (tol > 0), never beyond r or a zero residual.
+void launch_cpqr_id(const Node* nodes, const Instance* inst, const int32_t* list, int nlist,
+                    int parent_mode, int R, const double* Src, int64_t lds, const double* w,
+                    double* P, int64_t ldp, double* samp, int32_t* rank, int32_t* skel,
+                    int32_t* saturated, hipStream_t s);
+// Utmp_t(side R + i, :) = samp_child(i, :) Tr_t(side R : side R + R, :)  (Fig. 5)
+void launch_utmp(const Node* nodes, const int32_t* list, int nlist, int R, const double* samp,
+                 const double* Tr, double* Utmp, hipStream_t s);
+// Bnew[v] = sampU[sib(v)] Bold[v] sampV[v]^T  (eq. ben0-ben2)
+void launch_bskel(const Node* nodes, const int32_t* list, int nlist, int R, const double* sampU,
+                  const double* sampV, const double* Bold, double* Bnew, hipStream_t s);
+
+// out(I_v, 0:N) = A(I_v, 0:K) Bn_w  for v in list, w = v (or sib(v) if
+// from_sibling); Bn_w at Bn + w*bstride (K x N, ld ldb).
+void launch_node_nn(const Node* nodes, const int32_t* list, int nlist, int64_t max_rows, int K,
+                    int N, const double* A, int64_t lda, const double* Bn, int64_t bstride,
+                    int64_t ldb, double* out, int64_t ldo, hipStream_t s, int from_sibling = 0);
+// Truncation of the HODLR Z-side SVD (Fig. 2 svd(., eps)): per node keep
+// k_v = #{s_j > tol s_1} (tol > 0) capped at k, or k (tol == 0); zero the rest of
+// the columns of Vl(I_v, :), sv_v and X_v; rank[v] = k_v.
+void launch_truncate(const Node* nodes, const Instance* inst, const int32_t* kids, int nkids,
+                     int64_t max_rows, int R, double* Vl, int64_t ldv, double* sv, double* X,
+                     int32_t* rank, int32_t* saturated, hipStream_t s);
+
+}  // namespace hm

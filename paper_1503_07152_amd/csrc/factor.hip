@@ -1,0 +1,559 @@
+// Node factorisations: TSQR panels, reflector application, Jacobi SVD,
+// node-block gather, interaction matrices, column-pivoted QR / ID.
+#include <cfloat>
+
+#include "factor.h"
+#include "tile.h"
+
+namespace hm {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ------------------------------------------------------------ panel QR ----
+// Unblocked Householder QR (H_j = I - tau_j v_j v_j^T, v_j(j) = 1) of one
+// panel held in LDS.  Reflectors are stored below the diagonal, R on and above.
+__global__ __launch_bounds__(256) void k_panel_qr(const PanelDesc* descs) {
+  __shared__ double sA[FAC_LDMAX * FAC_CMAX];
+  __shared__ double part[4][64];
+  __shared__ double sw[FAC_CMAX];
+  __shared__ double sc[3];
+  const PanelDesc d = descs[blockIdx.x];
+  const int m = d.rows, n = d.cols;
+  const int lds = (m & 1) ? m : m + 1;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int idx = tid; idx < m * n; idx += 256) {
+    const int i = idx % m, j = idx / m;
+    sA[i + j * lds] = d.A[i + (int64_t)j * d.ld];
+  }
+  __syncthreads();
+  const int h = min(m, n);
+  for (int j = 0; j < h; ++j) {
+    if (wave == 0) {
+      double s = 0.0;
+      for (int i = j + 1 + lane; i < m; i += 64) {
+        const double v = sA[i + j * lds];
+        s += v * v;
+      }
+      s = wave_sum(s);
+      if (lane == 0) {
+        const double alpha = sA[j + j * lds];
+        if (s == 0.0) {
+          sc[0] = alpha; sc[1] = 0.0; sc[2] = 0.0;
+        } else {
+          const double beta = -copysign(sqrt(alpha * alpha + s), alpha);
+          sc[0] = beta;
+          sc[1] = (beta - alpha) / beta;
+          sc[2] = 1.0 / (alpha - beta);
+        }
+      }
+    }
+    __syncthreads();
+    const double beta = sc[0], tau = sc[1], scl = sc[2];
+    if (tau != 0.0)
+      for (int i = j + 1 + tid; i < m; i += 256) sA[i + j * lds] *= scl;
+    __syncthreads();
+    if (tid == 0) sA[j + j * lds] = beta;
+    if (tau != 0.0 && j + 1 < n) {
+      const int rows = m - j;
+      const int q = (rows + 3) / 4;
+      const int ib = j + wave * q, ie = min(m, ib + q);
+      for (int kb = j + 1; kb < n; kb += 64) {
+        const int k = kb + lane;
+        double s = 0.0;
+        if (k < n)
+          for (int i = ib; i < ie; ++i) {
+            const double v = (i == j) ? 1.0 : sA[i + j * lds];
+            s += v * sA[i + k * lds];
+          }
+        part[wave][lane] = s;
+        __syncthreads();
+        if (wave == 0 && k < n) sw[k] = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
+        __syncthreads();
+      }
+      const int nk = n - j - 1;
+      for (int idx = tid; idx < rows * nk; idx += 256) {
+        const int i = j + idx % rows, k = j + 1 + idx / rows;
+        const double v = (i == j) ? 1.0 : sA[i + j * lds];
+        sA[i + k * lds] -= tau * v * sw[k];
+      }
+    }
+    if (tid == 0) d.tau[j] = tau;
+    __syncthreads();
+  }
+  for (int idx = tid; idx < m * n; idx += 256) {
+    const int i = idx % m, j = idx / m;
+    d.A[i + (int64_t)j * d.ld] = sA[i + j * lds];
+  }
+  if (d.Rout)
+    for (int idx = tid; idx < h * n; idx += 256) {
+      const int i = idx % h, j = idx / h;
+      d.Rout[i + (int64_t)j * d.ldR] = (i <= j) ? sA[i + j * lds] : 0.0;
+    }
+}
+
+void launch_panel_qr(const PanelDesc* d, int n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_panel_qr, dim3(n), dim3(256), 0, s, d);
+  KCHK();
+}
+
+// Cout = H_0 H_1 ... H_{h-1} [Cin; 0]
+constexpr int APQ_NMAX = HM_MAX_SAMPLES;
+__global__ __launch_bounds__(256) void k_apply_q(const PanelDesc* descs) {
+  __shared__ double sO[FAC_LDMAX * APQ_NMAX];
+  __shared__ double sv[FAC_PMAX];
+  __shared__ double part[4][64];
+  __shared__ double sw[64];
+  const PanelDesc d = descs[blockIdx.x];
+  const int m = d.rows, h = min(d.rows, d.cols), nc = d.ncol;
+  const int ldo = (m & 1) ? m : m + 1;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int idx = tid; idx < m * nc; idx += 256) {
+    const int i = idx % m, c = idx / m;
+    sO[i + c * ldo] = (i < h) ? d.Cin[i + (int64_t)c * d.ldCin] : 0.0;
+  }
+  __syncthreads();
+  for (int j = h - 1; j >= 0; --j) {
+    const double tau = d.tau[j];
+    if (tau == 0.0) continue;
+    for (int i = j + tid; i < m; i += 256) sv[i] = (i == j) ? 1.0 : d.A[i + (int64_t)j * d.ld];
+    __syncthreads();
+    const int rows = m - j, q = (rows + 3) / 4;
+    const int ib = j + wave * q, ie = min(m, ib + q);
+    double s = 0.0;
+    if (lane < nc)
+      for (int i = ib; i < ie; ++i) s += sv[i] * sO[i + lane * ldo];
+    part[wave][lane] = s;
+    __syncthreads();
+    if (wave == 0) sw[lane] = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
+    __syncthreads();
+    for (int idx = tid; idx < rows * nc; idx += 256) {
+      const int i = j + idx % rows, c = idx / rows;
+      sO[i + c * ldo] -= tau * sv[i] * sw[c];
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < m * nc; idx += 256) {
+    const int i = idx % m, c = idx / m;
+    d.Cout[i + (int64_t)c * d.ldCout] = sO[i + c * ldo];
+  }
+}
+
+void launch_apply_q(const PanelDesc* d, int n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_apply_q, dim3(n), dim3(256), 0, s, d);
+  KCHK();
+}
+
+// ------------------------------------------------------------ Jacobi SVD --
+// One-sided (Hestenes) Jacobi on the columns of R: R Z = W diag(s).  Pairs
+// follow a round-robin tournament; each 16-lane group rotates one pair.
+constexpr int JAC_LD = FAC_CMAX + 1;
+__global__ __launch_bounds__(256) void k_jacobi(const SvdDesc* descs) {
+  __shared__ double sA[FAC_CMAX * JAC_LD];
+  __shared__ double sZ[FAC_CMAX * JAC_LD];
+  __shared__ double snorm[FAC_CMAX];
+  __shared__ int flag;
+  const SvdDesc d = descs[blockIdx.x];
+  const int h = d.h, c = d.c;
+  const bool wantX = d.X != nullptr;
+  const int tid = threadIdx.x;
+  const int grp = tid >> 4, gl = tid & 15;
+  for (int idx = tid; idx < h * c; idx += 256) {
+    const int i = idx % h, j = idx / h;
+    sA[i + j * JAC_LD] = d.R[i + (int64_t)j * d.ldR];
+  }
+  if (wantX)
+    for (int idx = tid; idx < c * c; idx += 256) {
+      const int i = idx % c, j = idx / c;
+      sZ[i + j * JAC_LD] = (i == j) ? 1.0 : 0.0;
+    }
+  __syncthreads();
+  const int n2 = c + (c & 1);
+  const double tol = (double)max(h, 1) * DBL_EPSILON;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (tid == 0) flag = 0;
+    __syncthreads();
+    for (int t = 0; t < n2 - 1; ++t) {
+      for (int pi = grp; pi < n2 / 2; pi += 16) {
+        const int a = pi, b = n2 - 1 - pi;
+        const int pa = a == 0 ? 0 : 1 + (a - 1 + t) % (n2 - 1);
+        const int pb = b == 0 ? 0 : 1 + (b - 1 + t) % (n2 - 1);
+        const int p = min(pa, pb), q = max(pa, pb);
+        if (q >= c) continue;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int i = gl; i < h; i += 16) {
+          const double x = sA[i + p * JAC_LD], y = sA[i + q * JAC_LD];
+          al += x * x; be += y * y; ga += x * y;
+        }
+#pragma unroll
+        for (int o = 8; o >= 1; o >>= 1) {
+          al += __shfl_xor(al, o, 16);
+          be += __shfl_xor(be, o, 16);
+          ga += __shfl_xor(ga, o, 16);
+        }
+        if (ga != 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
+          const double zeta = (be - al) / (2.0 * ga);
+          double tt;
+          if (fabs(zeta) > 1e150) tt = 0.5 / zeta;
+          else tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+          for (int i = gl; i < h; i += 16) {
+            const double x = sA[i + p * JAC_LD], y = sA[i + q * JAC_LD];
+            sA[i + p * JAC_LD] = cs * x - sn * y;
+            sA[i + q * JAC_LD] = sn * x + cs * y;
+          }
+          if (wantX)
+            for (int i = gl; i < c; i += 16) {
+              const double x = sZ[i + p * JAC_LD], y = sZ[i + q * JAC_LD];
+              sZ[i + p * JAC_LD] = cs * x - sn * y;
+              sZ[i + q * JAC_LD] = sn * x + cs * y;
+            }
+          if (gl == 0) flag = 1;
+        }
+      }
+      __syncthreads();
+    }
+    if (flag == 0) break;
+    __syncthreads();
+  }
+  for (int j = tid; j < c; j += 256) {
+    double s = 0.0;
+    for (int i = 0; i < h; ++i) s += sA[i + j * JAC_LD] * sA[i + j * JAC_LD];
+    snorm[j] = sqrt(s);
+  }
+  __syncthreads();
+  for (int j = tid; j < c; j += 256) {
+    const double sj = snorm[j];
+    int rk = 0;
+    for (int i = 0; i < c; ++i) rk += (snorm[i] > sj) || (snorm[i] == sj && i < j);
+    if (rk < d.kout) {
+      d.sv[rk] = sj;
+      const double inv = sj > 0.0 ? 1.0 / sj : 0.0;
+      for (int i = 0; i < h; ++i) d.W[i + (int64_t)rk * d.ldW] = sA[i + j * JAC_LD] * inv;
+      if (wantX)
+        for (int i = 0; i < c; ++i) d.X[i + (int64_t)rk * d.ldX] = sZ[i + j * JAC_LD];
+    }
+  }
+}
+
+void launch_jacobi_svd(const SvdDesc* d, int n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_jacobi, dim3(n), dim3(256), 0, s, d);
+  KCHK();
+}
+
+// ------------------------------------------------------------ gathers -----
+__global__ void k_build_node_block(const Node* nodes, const Instance* inst, const int32_t* kids,
+                                   int R, const double* S, int64_t lds, const double* Lpar,
+                                   int64_t ldl, const double* w, double* M, int64_t ldm,
+                                   int first_half_only) {
+  const Node nd = nodes[kids[blockIdx.y]];
+  const int64_t i = nd.lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nd.hi) return;
+  const int r = inst[nd.inst].r;
+  const int off = nd.is_left ? 0 : R;
+  for (int j = 0; j < r; ++j) M[i + (int64_t)j * ldm] = S[i + (int64_t)(off + j) * lds];
+  if (!first_half_only && nodes[nd.parent].parent >= 0) {
+    const double* wp = w + (int64_t)nd.parent * R;
+    for (int j = 0; j < r; ++j) M[i + (int64_t)(r + j) * ldm] = Lpar[i + (int64_t)j * ldl] * wp[j];
+  }
+}
+
+void launch_build_node_block(const Node* nodes, const Instance* inst, const int32_t* kids,
+                             int nkids, int64_t max_rows, int R, const double* S, int64_t lds,
+                             const double* Lpar, int64_t ldl, const double* w, double* M,
+                             int64_t ldm, hipStream_t s, int first_half_only) {
+  if (nkids <= 0) return;
+  const int nt = 256;
+  hipLaunchKernelGGL(k_build_node_block, dim3((unsigned)((max_rows + nt - 1) / nt), nkids),
+                     dim3(nt), 0, s, nodes, inst, kids, R, S, lds, Lpar, ldl, w, M, ldm,
+                     first_half_only);
+  KCHK();
+}
+
+__global__ void k_form_b(const Node* nodes, const Instance* inst, const int32_t* kids, int R,
+                         const double* X, const double* z, double* B) {
+  const int v = kids[blockIdx.x];
+  const int r = inst[nodes[v].inst].r;
+  const double* Xv = X + (int64_t)v * 2 * R * R;
+  const double* zv = z + (int64_t)v * R;
+  double* Bv = B + (int64_t)v * R * R;
+  for (int e = threadIdx.x; e < R * R; e += blockDim.x) {
+    const int i = e % R, j = e / R;
+    Bv[e] = (i < r && j < r) ? Xv[i + j * 2 * R] * zv[j] : 0.0;
+  }
+}
+
+void launch_form_b(const Node* nodes, const Instance* inst, const int32_t* kids, int nkids, int R,
+                   const double* X, const double* z, double* B, hipStream_t s) {
+  if (nkids <= 0) return;
+  hipLaunchKernelGGL(k_form_b, dim3(nkids), dim3(256), 0, s, nodes, inst, kids, R, X, z, B);
+  KCHK();
+}
+
+// ------------------------------------------------------------ CPQR / ID ---
+constexpr int ID_NMAX = 256;  // candidates per node (leaf rows or 2R)
+__global__ __launch_bounds__(256) void k_cpqr_id(const Node* nodes, const Instance* inst,
+                                                 const int32_t* list, int parent_mode, int R,
+                                                 const double* Src, int64_t lds, const double* w,
+                                                 double* P, int64_t ldp, double* samp,
+                                                 int32_t* rank, int32_t* skel, int32_t* saturated) {
+  __shared__ double sM[(HM_MAX_SAMPLES + 1) * ID_NMAX];  // M = W^T, R x n, ld R+1
+  __shared__ double snrm[ID_NMAX];
+  __shared__ int sperm[ID_NMAX];
+  __shared__ double sv[HM_MAX_SAMPLES];
+  __shared__ double sc[4];
+  __shared__ int sk[2];
+  const int g = list[blockIdx.x];
+  const Node nd = nodes[g];
+  const Instance in = inst[nd.inst];
+  const int tid = threadIdx.x;
+  const int ldm = R + 1;
+  const int n = parent_mode ? 2 * R : (int)(nd.hi - nd.lo);
+  const double* src = parent_mode ? Src + (int64_t)g * 2 * R * R : Src + nd.lo;
+  const int64_t ls = parent_mode ? 2 * R : lds;
+  const double* wv = w + (int64_t)g * R;
+  for (int idx = tid; idx < n * R; idx += 256) {
+    const int b = idx % n, a = idx / n;  // candidate b, sample dim a
+    sM[a + b * ldm] = src[b + (int64_t)a * ls] * wv[a];
+  }
+  for (int b = tid; b < n; b += 256) sperm[b] = b;
+  __syncthreads();
+  const int kcap = min(min(in.k, in.r), min(R, n));
+  int k = 0;
+  double ref = 0.0;
+  for (int j = 0; j < kcap; ++j) {
+    for (int b = j + tid; b < n; b += 256) {
+      double s = 0.0;
+      for (int a = j; a < R; ++a) s += sM[a + b * ldm] * sM[a + b * ldm];
+      snrm[b] = s;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int p = j;
+      double best = snrm[j];
+      for (int b = j + 1; b < n; ++b)
+        if (snrm[b] > best) { best = snrm[b]; p = b; }
+      sk[0] = p;
+      sc[0] = sqrt(best);
+    }
+    __syncthreads();
+    const int p = sk[0];
+    const double nrm = sc[0];
+    if (j == 0) ref = nrm;
+    if (nrm == 0.0 || (in.tol > 0.0 && nrm <= in.tol * ref)) break;
+    if (p != j) {
+      for (int a = tid; a < R; a += 256) {
+        const double t = sM[a + j * ldm];
+        sM[a + j * ldm] = sM[a + p * ldm];
+        sM[a + p * ldm] = t;
+      }
+      if (tid == 0) {
+        const int t = sperm[j]; sperm[j] = sperm[p]; sperm[p] = t;
+      }
+    }
+    __syncthreads();
+    // Householder reflector zeroing M(j+1:R, j): v = x - alpha e1, H = I - 2 v v^T / (v^T v)
+    if (tid == 0) {
+      double s = 0.0;
+      for (int a = j; a < R; ++a) s += sM[a + j * ldm] * sM[a + j * ldm];
+      const double x0 = sM[j + j * ldm];
+      const double alpha = -copysign(sqrt(s), x0);
+      for (int a = j; a < R; ++a) sv[a] = sM[a + j * ldm];
+      sv[j] = x0 - alpha;
+      const double vn = s - x0 * x0 + sv[j] * sv[j];
+      sc[1] = alpha;
+      sc[2] = vn > 0.0 ? 2.0 / vn : 0.0;
+    }
+    __syncthreads();
+    const double f = sc[2];
+    for (int b = j + 1 + tid; b < n; b += 256) {
+      double s = 0.0;
+      for (int a = j; a < R; ++a) s += sv[a] * sM[a + b * ldm];
+      s *= f;
+      for (int a = j; a < R; ++a) sM[a + b * ldm] -= s * sv[a];
+    }
+    __syncthreads();
+    if (tid == 0) {
+      sM[j + j * ldm] = sc[1];
+      for (int a = j + 1; a < R; ++a) sM[a + j * ldm] = 0.0;
+    }
+    __syncthreads();
+    k = j + 1;
+  }
+  // T = R11^{-1} R12, column by column (back substitution); stored in place of R12.
+  for (int b = k + tid; b < n; b += 256) {
+    for (int a = k - 1; a >= 0; --a) {
+      double s = sM[a + b * ldm];
+      for (int c2 = a + 1; c2 < k; ++c2) s -= sM[a + c2 * ldm] * sM[c2 + b * ldm];
+      sM[a + b * ldm] = s / sM[a + a * ldm];
+    }
+  }
+  __syncthreads();
+  // P (n x R): row perm[b] = e_b (b < k) or T(:, b)^T (b >= k); columns >= k zero.
+  double* Pout = parent_mode ? P + (int64_t)g * 2 * R * R : P + nd.lo;
+  const int64_t lp = parent_mode ? 2 * R : ldp;
+  for (int idx = tid; idx < n * R; idx += 256) {
+    const int b = idx % n, col = idx / n;
+    double v = 0.0;
+    if (col < k) v = (b < k) ? (b == col ? 1.0 : 0.0) : sM[col + b * ldm];
+    Pout[sperm[b] + (int64_t)col * lp] = v;
+  }
+  double* sp = samp + (int64_t)g * R * R;
+  for (int idx = tid; idx < R * R; idx += 256) {
+    const int i = idx % R, a = idx / R;
+    sp[idx] = (i < k) ? src[sperm[i] + (int64_t)a * ls] : 0.0;
+  }
+  int32_t* sk_out = skel + (int64_t)g * R;
+  for (int i = tid; i < R; i += 256) {
+    int id = -1;
+    if (i < k) {
+      const int cnd = sperm[i];
+      if (!parent_mode) id = (int)(nd.lo - in.row0) + cnd;
+      else id = cnd < R ? skel[(int64_t)nd.left * R + cnd] : skel[(int64_t)nd.right * R + cnd - R];
+    }
+    sk_out[i] = id;
+  }
+  if (tid == 0) {
+    rank[g] = k;
+    if (in.tol > 0.0 && k > in.r - in.p && saturated) atomicAdd(saturated, 1);
+  }
+}
+
+void launch_cpqr_id(const Node* nodes, const Instance* inst, const int32_t* list, int nlist,
+                    int parent_mode, int R, const double* Src, int64_t lds, const double* w,
+                    double* P, int64_t ldp, double* samp, int32_t* rank, int32_t* skel,
+                    int32_t* saturated, hipStream_t s) {
+  if (nlist <= 0) return;
+  hipLaunchKernelGGL(k_cpqr_id, dim3(nlist), dim3(256), 0, s, nodes, inst, list, parent_mode, R,
+                     Src, lds, w, P, ldp, samp, rank, skel, saturated);
+  KCHK();
+}
+
+constexpr int STM = 64, STN = 64;
+__global__ __launch_bounds__(256) void k_utmp(const Node* nodes, const int32_t* list, int R,
+                                              const double* samp, const double* Tr,
+                                              double* Utmp) {
+  __shared__ double smem[tile_smem_elems<STM, STN>()];
+  const int t = list[blockIdx.x];
+  const int side = blockIdx.y;
+  const Node nd = nodes[t];
+  const int ch = side == 0 ? nd.left : nd.right;
+  TileAcc<double, STM, STN> acc;
+  acc.zero();
+  mm_tile<double, STM, STN>(R, R, R, samp + (int64_t)ch * R * R, 1, R,
+                            Tr + (int64_t)t * 2 * R * R + side * R, 1, 2 * R, acc, smem);
+  store_tile<double, STM, STN>(R, R, Utmp + (int64_t)t * 2 * R * R + side * R, 2 * R, acc, 1.0,
+                               0.0);
+}
+
+void launch_utmp(const Node* nodes, const int32_t* list, int nlist, int R, const double* samp,
+                 const double* Tr, double* Utmp, hipStream_t s) {
+  if (nlist <= 0) return;
+  hipLaunchKernelGGL(k_utmp, dim3(nlist, 2), dim3(256), 0, s, nodes, list, R, samp, Tr, Utmp);
+  KCHK();
+}
+
+__global__ __launch_bounds__(256) void k_bskel(const Node* nodes, const int32_t* list, int R,
+                                               const double* sampU, const double* sampV,
+                                               const double* Bold, double* Bnew) {
+  __shared__ double smem[tile_smem_elems<STM, STN>()];
+  __shared__ double sT[STM * STN];
+  const int v = list[blockIdx.x];
+  const int sb = nodes[v].sib;
+  TileAcc<double, STM, STN> acc;
+  acc.zero();
+  // T1 = Bold[v] sampV[v]^T  (R x R)
+  mm_tile<double, STM, STN>(R, R, R, Bold + (int64_t)v * R * R, 1, R, sampV + (int64_t)v * R * R,
+                            R, 1, acc, smem);
+  store_tile<double, STM, STN>(R, R, sT, STM, acc, 1.0, 0.0);
+  __syncthreads();
+  acc.zero();
+  mm_tile<double, STM, STN>(R, R, R, sampU + (int64_t)sb * R * R, 1, R, sT, 1, STM, acc, smem);
+  store_tile<double, STM, STN>(R, R, Bnew + (int64_t)v * R * R, R, acc, 1.0, 0.0);
+}
+
+void launch_bskel(const Node* nodes, const int32_t* list, int nlist, int R, const double* sampU,
+                  const double* sampV, const double* Bold, double* Bnew, hipStream_t s) {
+  if (nlist <= 0) return;
+  hipLaunchKernelGGL(k_bskel, dim3(nlist), dim3(256), 0, s, nodes, list, R, sampU, sampV, Bold,
+                     Bnew);
+  KCHK();
+}
+
+__global__ __launch_bounds__(256) void k_node_nn(const Node* nodes, const int32_t* list, int K,
+                                                 int N, const double* A, int64_t lda,
+                                                 const double* Bn, int64_t bstride, int64_t ldb,
+                                                 double* out, int64_t ldo, int from_sibling) {
+  __shared__ double smem[tile_smem_elems<STM, STN>()];
+  const int g = list[blockIdx.y];
+  const int gb = from_sibling ? nodes[g].sib : g;
+  const Node nd = nodes[g];
+  const int64_t i0 = nd.lo + (int64_t)blockIdx.x * STM;
+  if (i0 >= nd.hi) return;
+  const int M = (int)min<int64_t>(STM, nd.hi - i0);
+  const int j0 = blockIdx.z * STN;
+  TileAcc<double, STM, STN> acc;
+  acc.zero();
+  mm_tile<double, STM, STN>(M, N - j0, K, A + i0, 1, lda, Bn + (int64_t)gb * bstride + j0 * ldb,
+                            1, ldb, acc, smem);
+  store_tile<double, STM, STN>(M, N - j0, out + i0 + (int64_t)j0 * ldo, ldo, acc, 1.0, 0.0);
+}
+
+void launch_node_nn(const Node* nodes, const int32_t* list, int nlist, int64_t max_rows, int K,
+                    int N, const double* A, int64_t lda, const double* Bn, int64_t bstride,
+                    int64_t ldb, double* out, int64_t ldo, hipStream_t s, int from_sibling) {
+  if (nlist <= 0 || N <= 0) return;
+  hipLaunchKernelGGL(k_node_nn,
+                     dim3((unsigned)((max_rows + STM - 1) / STM), nlist, (N + STN - 1) / STN),
+                     dim3(256), 0, s, nodes, list, K, N, A, lda, Bn, bstride, ldb, out, ldo,
+                     from_sibling);
+  KCHK();
+}
+
+__global__ void k_truncate(const Node* nodes, const Instance* inst, const int32_t* kids, int R,
+                           double* Vl, int64_t ldv, double* sv, double* X, int32_t* rank,
+                           int32_t* saturated) {
+  const int v = kids[blockIdx.y];
+  const Node nd = nodes[v];
+  const Instance in = inst[nd.inst];
+  const double* s = sv + (int64_t)v * R;
+  int k = min(in.k, in.r);
+  if (in.tol > 0.0) {
+    int kk = 0;
+    for (int j = 0; j < in.r; ++j) kk += (s[0] > 0.0 && s[j] > in.tol * s[0]);
+    k = min(kk, k);
+  }
+  const int64_t i = nd.lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < nd.hi)
+    for (int j = k; j < R; ++j) Vl[i + (int64_t)j * ldv] = 0.0;
+  if (blockIdx.x == 0) {
+    __syncthreads();
+    double* Xv = X + (int64_t)v * 2 * R * R;
+    for (int e = threadIdx.x; e < 2 * R * R; e += blockDim.x)
+      if (e / (2 * R) >= k) Xv[e] = 0.0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int j = k; j < R; ++j) sv[(int64_t)v * R + j] = 0.0;
+      rank[v] = k;
+      if (in.tol > 0.0 && k > in.r - in.p && saturated) atomicAdd(saturated, 1);
+    }
+  }
+}
+
+void launch_truncate(const Node* nodes, const Instance* inst, const int32_t* kids, int nkids,
+                     int64_t max_rows, int R, double* Vl, int64_t ldv, double* sv, double* X,
+                     int32_t* rank, int32_t* saturated, hipStream_t s) {
+  if (nkids <= 0) return;
+  const int nt = 256;
+  hipLaunchKernelGGL(k_truncate, dim3((unsigned)((max_rows + nt - 1) / nt), nkids), dim3(nt), 0,
+                     s, nodes, inst, kids, R, Vl, ldv, sv, X, rank, saturated);
+  KCHK();
+}
+
+}  // namespace hm

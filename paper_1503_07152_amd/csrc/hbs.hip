@@ -1,0 +1,517 @@
+// Host orchestration of the randomized HBS compression: Fig. 4 (storage-
+// efficient peeling) followed by Fig. 5 (conversion to HBS-ID), on a forest
+// of one or many instances processed level-synchronously.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "handle.h"
+
+namespace hm {
+
+// ------------------------------------------------------------ operators ---
+OpRunner::~OpRunner() {
+  for (auto e : ev) (void)hipEventDestroy(e);
+}
+
+void OpRunner::apply(bool adjoint, int64_t n, int c, const double* X, int64_t ldx, double* Y,
+                     int64_t ldy) {
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  ev.push_back(e0);
+  ev.push_back(e1);
+  HIPCHK(hipEventRecord(e0, s));
+  ++calls;
+  columns += c;
+  switch (op.kind) {
+    case HM_OP_CALLBACK: {
+      const int rc = op.fn(op.user, adjoint ? 1 : 0, n, c, X, ldx, Y, ldy, (void*)s);
+      if (rc != 0) HM_THROW(HM_ERR_CALLBACK, "matvec callback returned %d", rc);
+      break;
+    }
+    case HM_OP_KERNEL:
+    case HM_OP_DENSE: {
+      const int mode = op.kind == HM_OP_DENSE ? 0
+                       : op.sample_dtype == HM_F32 ? 1
+                       : op.sample_dtype == HM_BF16 ? 2 : 0;
+      const int src = op.kind == HM_OP_DENSE ? (adjoint ? 3 : 2)
+                      : (op.kernel_id == HM_KERNEL_LOG ? 0 : 1);
+      for (int c0 = 0; c0 < c; c0 += SMP_MAXC) {
+        const int cc = std::min(SMP_MAXC, c - c0);
+        work.ensure(sampler_pack_bytes(mode, n, cc), s);
+        sampler_apply(mode, src, n, cc, op.points, op.kparam, op.dense, op.ld,
+                      X + (int64_t)c0 * ldx, ldx, Y + (int64_t)c0 * ldy, ldy, work.base(), s);
+      }
+      break;
+    }
+    case HM_OP_HBS: {
+      const hm_hbs_s* h = hbs;
+      work.ensure(apply_work_bytes<double>(h->f, h->full, h->R, c), s);
+      apply_forest<double>(h->d_nodes.as<Node>(), h->full, h->view<double>(), adjoint, c, X, ldx,
+                           Y, ldy, 1.0, 0.0, work.base(), h->f.nodes.size(), s);
+      break;
+    }
+    default:
+      HM_THROW(HM_ERR_ARG, "unknown operator kind %d", op.kind);
+  }
+  HIPCHK(hipEventRecord(e1, s));
+}
+
+double OpRunner::elapsed_ms() {
+  double t = 0.0;
+  for (size_t i = 0; i + 1 < ev.size(); i += 2) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess) t += ms;
+  }
+  return t;
+}
+
+// ------------------------------------------------------------ node SVD ----
+namespace {
+struct Alloc {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) / 256 * 256;
+    return o;
+  }
+};
+}  // namespace
+
+void node_svd(const std::vector<SvdJob>& jobs, double* M, int64_t ldm, double* Uout, int64_t ldu,
+              double* sv, double* X, int R, bool qr_only, Workspace& ws, Keeper& kp,
+              hipStream_t s) {
+  if (jobs.empty()) return;
+  int cmax = 1;
+  for (auto& j : jobs) cmax = std::max(cmax, j.cols);
+  if (cmax > FAC_CMAX) HM_THROW(HM_ERR_UNSUPPORTED, "node block of %d columns > %d", cmax, FAC_CMAX);
+  const int P0 = std::min(FAC_PMAX, 2 * cmax);
+  // ---- plan: per job, panels per stage (rows of each panel) -------------
+  struct Blk { int64_t row; int rows; };  // a block inside a stage buffer
+  const int nj = (int)jobs.size();
+  std::vector<std::vector<std::vector<Blk>>> stages(nj);  // [job][stage] -> panels
+  std::vector<int> top(nj);
+  for (int q = 0; q < nj; ++q) {
+    const SvdJob& jb = jobs[q];
+    std::vector<int> rows;   // rows of the blocks entering this stage
+    for (int r0 = 0; r0 < jb.rows; r0 += P0) rows.push_back(std::min(P0, jb.rows - r0));
+    // stage 0 panels = these row chunks; later stages group R blocks
+    int st = 0;
+    while (true) {
+      std::vector<Blk> pan;
+      if (st == 0) {
+        for (int r : rows) pan.push_back({0, r});
+      } else {
+        int acc = 0;
+        for (int r : rows) {
+          if (acc + r > P0 && acc > 0) { pan.push_back({0, acc}); acc = 0; }
+          acc += r;
+        }
+        pan.push_back({0, acc});
+      }
+      stages[q].push_back(pan);
+      if (pan.size() == 1) break;
+      std::vector<int> nxt;
+      for (auto& p : pan) nxt.push_back(std::min(p.rows, jb.cols));
+      rows = nxt;
+      ++st;
+    }
+    top[q] = st;
+  }
+  int nst = 0;
+  for (int q = 0; q < nj; ++q) nst = std::max(nst, top[q] + 1);
+  // stage buffers: stage st >= 1 stacks the R blocks of stage st-1 panels
+  std::vector<int64_t> srows(nst, 0);
+  std::vector<std::vector<int64_t>> in_off(nj, std::vector<int64_t>(nst, 0));
+  for (int q = 0; q < nj; ++q)
+    for (int st = 1; st <= top[q]; ++st) {
+      in_off[q][st] = srows[st];
+      int64_t tot = 0;
+      for (auto& p : stages[q][st - 1]) tot += std::min(p.rows, jobs[q].cols);
+      srows[st] += tot;
+    }
+  Alloc al;
+  std::vector<size_t> s_off(nst), c_off(nst), t_off(nst);
+  std::vector<int64_t> npan(nst, 0);
+  for (int q = 0; q < nj; ++q)
+    for (int st = 0; st <= top[q]; ++st) npan[st] += (int64_t)stages[q][st].size();
+  for (int st = 0; st < nst; ++st) {
+    s_off[st] = al.take((size_t)std::max<int64_t>(srows[st], 1) * cmax * sizeof(double));
+    c_off[st] = al.take((size_t)std::max<int64_t>(srows[st], 1) * R * sizeof(double));
+    t_off[st] = al.take((size_t)std::max<int64_t>(npan[st], 1) * cmax * sizeof(double));
+  }
+  const size_t rfin_off = al.take((size_t)nj * FAC_CMAX * FAC_CMAX * sizeof(double));
+  const size_t w_off = al.take((size_t)nj * FAC_CMAX * R * sizeof(double));
+  const size_t eye_off = al.take((size_t)FAC_CMAX * R * sizeof(double));
+  ws.ensure(al.off, s);
+  char* base = ws.base();
+  auto S = [&](int st) { return reinterpret_cast<double*>(base + s_off[st]); };
+  auto C = [&](int st) { return reinterpret_cast<double*>(base + c_off[st]); };
+  auto TAU = [&](int st) { return reinterpret_cast<double*>(base + t_off[st]); };
+  double* Rfin = reinterpret_cast<double*>(base + rfin_off);
+  double* W = reinterpret_cast<double*>(base + w_off);
+  double* EYE = reinterpret_cast<double*>(base + eye_off);
+  // ---- descriptors ---------------------------------------------------------
+  std::vector<std::vector<PanelDesc>> pd(nst);
+  std::vector<int64_t> tcount(nst, 0);
+  std::vector<SvdDesc> sd;
+  for (int q = 0; q < nj; ++q) {
+    const SvdJob& jb = jobs[q];
+    int64_t rrow_next = 0;  // row inside next stage buffer
+    for (int st = 0; st <= top[q]; ++st) {
+      int64_t row_in = 0;   // row inside this stage's input (node block or stage buffer)
+      rrow_next = st < top[q] ? in_off[q][st + 1] : 0;
+      for (size_t pi = 0; pi < stages[q][st].size(); ++pi) {
+        const Blk& b = stages[q][st][pi];
+        PanelDesc d{};
+        if (st == 0) { d.A = M + jb.lo + row_in; d.ld = ldm; }
+        else { d.A = S(st) + in_off[q][st] + row_in; d.ld = std::max<int64_t>(srows[st], 1); }
+        d.rows = b.rows;
+        d.cols = jb.cols;
+        d.tau = TAU(st) + tcount[st] * cmax;
+        tcount[st]++;
+        const int h = std::min(b.rows, jb.cols);
+        if (st < top[q]) {
+          d.Rout = S(st + 1) + rrow_next;
+          d.ldR = std::max<int64_t>(srows[st + 1], 1);
+          d.Cin = C(st + 1) + rrow_next;
+          d.ldCin = std::max<int64_t>(srows[st + 1], 1);
+          rrow_next += h;
+        } else {
+          d.Rout = Rfin + (int64_t)q * FAC_CMAX * FAC_CMAX;
+          d.ldR = FAC_CMAX;
+          d.Cin = qr_only ? EYE : W + (int64_t)q * FAC_CMAX * R;
+          d.ldCin = FAC_CMAX;
+          if (!qr_only) {
+            SvdDesc v{};
+            v.R = d.Rout; v.ldR = FAC_CMAX; v.h = h; v.c = jb.cols;
+            v.W = W + (int64_t)q * FAC_CMAX * R; v.ldW = FAC_CMAX;
+            v.sv = sv + (int64_t)jb.node * R;
+            v.X = X ? X + (int64_t)jb.node * 2 * R * R : nullptr;
+            v.ldX = 2 * R;
+            v.kout = jb.kout;
+            sd.push_back(v);
+          }
+        }
+        if (st == 0) { d.Cout = Uout + jb.lo + row_in; d.ldCout = ldu; }
+        else { d.Cout = C(st) + in_off[q][st] + row_in; d.ldCout = std::max<int64_t>(srows[st], 1); }
+        d.ncol = jb.kout;
+        pd[st].push_back(d);
+        row_in += b.rows;
+      }
+    }
+  }
+  if (qr_only) {
+    std::vector<double> eye((size_t)FAC_CMAX * R, 0.0);
+    for (int i = 0; i < std::min(FAC_CMAX, R); ++i) eye[i + (size_t)i * FAC_CMAX] = 1.0;
+    kp.host.emplace_back(eye.size() * sizeof(double));
+    std::memcpy(kp.host.back().data(), eye.data(), eye.size() * sizeof(double));
+    HIPCHK(hipMemcpyAsync(EYE, kp.host.back().data(), eye.size() * sizeof(double),
+                          hipMemcpyHostToDevice, s));
+  }
+  // ---- run -------------------------------------------------------------------
+  std::vector<PanelDesc*> dpd(nst);
+  for (int st = 0; st < nst; ++st) dpd[st] = kp.put(pd[st], s);
+  for (int st = 0; st < nst; ++st) launch_panel_qr(dpd[st], (int)pd[st].size(), s);
+  if (!qr_only) {
+    SvdDesc* dsd = kp.put(sd, s);
+    launch_jacobi_svd(dsd, (int)sd.size(), s);
+  }
+  for (int st = nst - 1; st >= 0; --st) launch_apply_q(dpd[st], (int)pd[st].size(), s);
+}
+
+// ------------------------------------------------------------ compress -----
+namespace {
+
+struct LevelLists {
+  std::vector<int32_t> kids;      // children of the level's nodes (active instances)
+  int64_t max_kid_rows = 0;
+  ApplyLists sub;                 // frontier = nodes on this level (for A^(l))
+};
+
+template <class T>
+void copy_dev(T* dst, const T* src, size_t n, hipStream_t s) {
+  if (n) HIPCHK(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyDeviceToDevice, s));
+}
+
+}  // namespace
+
+static void apply_ops(std::vector<OpRunner*>& ops, const Forest& f, bool adjoint, int c,
+                      const double* X, int64_t ldx, double* Y, int64_t ldy,
+                      const std::vector<int>& active) {
+  if (ops.size() == 1) {
+    ops[0]->apply(adjoint, f.n_total, c, X, ldx, Y, ldy);
+    return;
+  }
+  for (size_t i = 0; i < f.inst.size(); ++i) {
+    if (!active.empty() && !active[i]) continue;
+    const int64_t r0 = f.inst[i].row0;
+    ops[i]->apply(adjoint, f.inst[i].n, c, X + r0, ldx, Y + r0, ldy);
+  }
+}
+
+hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t flags, hipStream_t s,
+                              int* status) {
+  auto t0 = std::chrono::steady_clock::now();
+  forest_finish(f);
+  std::unique_ptr<hm_hbs_s> h(new hm_hbs_s());
+  int R = 0;
+  for (auto& in : f.inst) R = std::max(R, in.r);
+  const int64_t N = f.n_total;
+  const int nn = (int)f.nodes.size();
+  const int Lmax = f.max_levels;
+  const int nmax = f.nmax;
+  h->R = R;
+  h->dtype = HM_F64;
+  h->d_nodes = upload(f.nodes, s);
+  h->d_inst = upload(f.inst, s);
+  const Node* dn = h->d_nodes.as<Node>();
+  const Instance* di = h->d_inst.as<Instance>();
+  Keeper kp;
+  Workspace ws_svd, ws_apply, ws_seg;
+  // ---- buffers ---------------------------------------------------------------
+  const int W = std::max(2 * R, nmax);
+  DevBuf Om((size_t)N * W * 8), Y((size_t)N * W * 8), M((size_t)N * 2 * R * 8);
+  DevBuf Ucur((size_t)N * R * 8), Vcur((size_t)N * R * 8), Unx((size_t)N * R * 8),
+      Vnx((size_t)N * R * 8);
+  DevBuf yv((size_t)nn * R * 8), zv((size_t)nn * R * 8);
+  DevBuf Ut((size_t)nn * 2 * R * R * 8), Vt((size_t)nn * 2 * R * R * 8);
+  DevBuf B((size_t)nn * R * R * 8), Xr((size_t)nn * 2 * R * R * 8);
+  DevBuf flag(16);
+  HIPCHK(hipMemsetAsync(flag.p, 0, 16, s));
+  HIPCHK(hipMemsetAsync(yv.p, 0, yv.bytes, s));
+  HIPCHK(hipMemsetAsync(zv.p, 0, zv.bytes, s));
+  HIPCHK(hipMemsetAsync(Ut.p, 0, Ut.bytes, s));
+  HIPCHK(hipMemsetAsync(Vt.p, 0, Vt.bytes, s));
+  HIPCHK(hipMemsetAsync(B.p, 0, B.bytes, s));
+  HIPCHK(hipMemsetAsync(Xr.p, 0, Xr.bytes, s));
+  double* om = Om.as<double>();
+  double* y = Y.as<double>();
+  double* m = M.as<double>();
+  double *uc = Ucur.as<double>(), *vc = Vcur.as<double>(), *un = Unx.as<double>(),
+         *vn = Vnx.as<double>();
+  // ---- level lists -------------------------------------------------------------
+  std::vector<LevelLists> LL(std::max(Lmax, 1));
+  for (int l = 0; l < Lmax; ++l) {
+    std::vector<int> mvec(f.inst.size(), -1);
+    for (size_t i = 0; i < f.inst.size(); ++i)
+      if (f.inst[i].L > l) mvec[i] = l;
+    for (int g : f.level[l + 1]) {
+      LL[l].kids.push_back(g);
+      LL[l].max_kid_rows = std::max<int64_t>(LL[l].max_kid_rows, f.nodes[g].hi - f.nodes[g].lo);
+    }
+    if (l >= 1) build_apply_lists(f, mvec, LL[l].sub, s);
+  }
+  // ---- Fig. 4: peeling, level by level ------------------------------------------
+  for (int l = 0; l < Lmax; ++l) {
+    LevelLists& lv = LL[l];
+    std::vector<int> active(f.inst.size(), 0);
+    for (size_t i = 0; i < f.inst.size(); ++i) active[i] = f.inst[i].L > l;
+    const int32_t* dk = kp.put(lv.kids, s);
+    const int nk = (int)lv.kids.size();
+    if (f.inst.size() > 1) launch_fill(om, N, 2 * R, N, 0.0, s);
+    launch_gauss_masked(dn, di, dk, nk, lv.max_kid_rows, l, R, om, N, s);
+    apply_ops(ops, f, false, 2 * R, om, N, y, N, active);
+    launch_nonfinite_check(y, N, 2 * R, N, flag.as<int>(), s);
+    HbsView<double> hv;
+    hv.Ulong = uc; hv.Vlong = vc; hv.ldl = N; hv.Ut = Ut.as<double>(); hv.Vt = Vt.as<double>();
+    hv.B = B.as<double>(); hv.D = nullptr; hv.R = R;
+    if (l >= 1) {
+      ws_apply.ensure(apply_work_bytes<double>(f, lv.sub, R, 2 * R), s);
+      apply_forest<double>(dn, lv.sub, hv, false, 2 * R, om, N, y, N, -1.0, 1.0, ws_apply.base(),
+                           nn, s);
+    }
+    // incoming bases of the children
+    launch_build_node_block(dn, di, dk, nk, lv.max_kid_rows, R, y, N, uc, N, yv.as<double>(), m,
+                            N, s);
+    std::vector<SvdJob> jobs;
+    for (int g : lv.kids) {
+      const Node& nd = f.nodes[g];
+      const int r = f.inst[nd.inst].r;
+      const bool under_root = f.nodes[nd.parent].parent < 0;
+      jobs.push_back({g, (int)(nd.hi - nd.lo), under_root ? r : 2 * r, r, nd.lo});
+    }
+    launch_fill(un, N, R, N, 0.0, s);
+    node_svd(jobs, m, N, un, N, yv.as<double>(), nullptr, R, false, ws_svd, kp, s);
+    if (l >= 1) {
+      ws_seg.ensure(seg_tn_work_bytes<double>(nk, lv.max_kid_rows, R, R), s);
+      seg_tn<double>(dn, dk, nk, lv.max_kid_rows, R, R, un, N, uc, N, Ut.as<double>(),
+                     2 * R * R, 2 * R, 1.0, 0.0, ws_seg.base(), s, 1);
+    }
+    // outgoing bases and sibling matrices
+    launch_mask_basis(dn, di, dk, nk, lv.max_kid_rows, R, un, N, om, N, s);
+    apply_ops(ops, f, true, 2 * R, om, N, y, N, active);
+    launch_nonfinite_check(y, N, 2 * R, N, flag.as<int>(), s);
+    if (l >= 1)
+      apply_forest<double>(dn, lv.sub, hv, true, 2 * R, om, N, y, N, -1.0, 1.0, ws_apply.base(),
+                           nn, s);
+    launch_build_node_block(dn, di, dk, nk, lv.max_kid_rows, R, y, N, vc, N, zv.as<double>(), m,
+                            N, s);
+    launch_fill(vn, N, R, N, 0.0, s);
+    node_svd(jobs, m, N, vn, N, zv.as<double>(), Xr.as<double>(), R, false, ws_svd, kp, s);
+    launch_form_b(dn, di, dk, nk, R, Xr.as<double>(), zv.as<double>(), B.as<double>(), s);
+    if (l >= 1)
+      seg_tn<double>(dn, dk, nk, lv.max_kid_rows, R, R, vn, N, vc, N, Vt.as<double>(), 2 * R * R,
+                     2 * R, 1.0, 0.0, ws_seg.base(), s, 1);
+    std::swap(uc, un);
+    std::swap(vc, vn);
+  }
+  // ---- diagonal blocks ------------------------------------------------------------
+  DevBuf D((size_t)N * nmax * 8);
+  {
+    const int32_t* dl = kp.put(f.leaves, s);
+    int64_t maxl = 0;
+    for (int g : f.leaves) maxl = std::max<int64_t>(maxl, f.nodes[g].hi - f.nodes[g].lo);
+    launch_block_eye(dn, dl, (int)f.leaves.size(), maxl, nmax, om, N, s);
+    apply_ops(ops, f, false, nmax, om, N, D.as<double>(), N, {});
+    launch_nonfinite_check(D.as<double>(), N, nmax, N, flag.as<int>(), s);
+    std::vector<int> mvec(f.inst.size());
+    for (size_t i = 0; i < f.inst.size(); ++i) mvec[i] = f.inst[i].L;
+    build_apply_lists(f, mvec, h->full, s);
+    HbsView<double> hv;
+    hv.Ulong = uc; hv.Vlong = vc; hv.ldl = N; hv.Ut = Ut.as<double>(); hv.Vt = Vt.as<double>();
+    hv.B = B.as<double>(); hv.D = nullptr; hv.R = R;
+    if (Lmax >= 1) {
+      ws_apply.ensure(apply_work_bytes<double>(f, h->full, R, nmax), s);
+      apply_forest<double>(dn, h->full, hv, false, nmax, om, N, D.as<double>(), N, -1.0, 1.0,
+                           ws_apply.base(), nn, s);
+    }
+    launch_zero_dpad(dn, dl, (int)f.leaves.size(), maxl, nmax, D.as<double>(), N, s);
+  }
+  // ---- Fig. 5: HBS-ID -------------------------------------------------------------
+  DevBuf rk_u(nn * 4 + 16), rk_v(nn * 4 + 16), sk_in((size_t)nn * R * 4 + 16),
+      sk_out((size_t)nn * R * 4 + 16);
+  HIPCHK(hipMemsetAsync(rk_u.p, 0, rk_u.bytes, s));
+  HIPCHK(hipMemsetAsync(rk_v.p, 0, rk_v.bytes, s));
+  HIPCHK(hipMemsetAsync(sk_in.p, 0xff, sk_in.bytes, s));
+  HIPCHK(hipMemsetAsync(sk_out.p, 0xff, sk_out.bytes, s));
+  const bool to_id = !(flags & HM_FLAG_ORTHONORMAL) && Lmax >= 1;
+  if (to_id) {
+    DevBuf Unew((size_t)N * R * 8), Vnew((size_t)N * R * 8);
+    DevBuf Utn((size_t)nn * 2 * R * R * 8), Vtn((size_t)nn * 2 * R * R * 8);
+    DevBuf Bn((size_t)nn * R * R * 8), sU((size_t)nn * R * R * 8), sV((size_t)nn * R * R * 8);
+    DevBuf Tmp((size_t)nn * 2 * R * R * 8);
+    HIPCHK(hipMemsetAsync(Unew.p, 0, Unew.bytes, s));
+    HIPCHK(hipMemsetAsync(Vnew.p, 0, Vnew.bytes, s));
+    HIPCHK(hipMemsetAsync(Utn.p, 0, Utn.bytes, s));
+    HIPCHK(hipMemsetAsync(Vtn.p, 0, Vtn.bytes, s));
+    HIPCHK(hipMemsetAsync(sU.p, 0, sU.bytes, s));
+    HIPCHK(hipMemsetAsync(sV.p, 0, sV.bytes, s));
+    std::vector<int32_t> lv;
+    for (int g : f.leaves)
+      if (f.nodes[g].level > 0) lv.push_back(g);
+    const int32_t* dl = kp.put(lv, s);
+    int32_t* sat = flag.as<int32_t>() + 1;
+    launch_cpqr_id(dn, di, dl, (int)lv.size(), 0, R, uc, N, yv.as<double>(), Unew.as<double>(), N,
+                   sU.as<double>(), rk_u.as<int32_t>(), sk_in.as<int32_t>(), sat, s);
+    launch_cpqr_id(dn, di, dl, (int)lv.size(), 0, R, vc, N, zv.as<double>(), Vnew.as<double>(), N,
+                   sV.as<double>(), rk_v.as<int32_t>(), sk_out.as<int32_t>(), sat, s);
+    for (int l = Lmax - 1; l >= 1; --l) {
+      std::vector<int32_t> par;
+      for (int g : f.level[l])
+        if (f.nodes[g].left >= 0) par.push_back(g);
+      if (par.empty()) continue;
+      const int32_t* dp = kp.put(par, s);
+      launch_utmp(dn, dp, (int)par.size(), R, sU.as<double>(), Ut.as<double>(), Tmp.as<double>(), s);
+      launch_cpqr_id(dn, di, dp, (int)par.size(), 1, R, Tmp.as<double>(), 2 * R, yv.as<double>(),
+                     Utn.as<double>(), 2 * R, sU.as<double>(), rk_u.as<int32_t>(),
+                     sk_in.as<int32_t>(), sat, s);
+      launch_utmp(dn, dp, (int)par.size(), R, sV.as<double>(), Vt.as<double>(), Tmp.as<double>(), s);
+      launch_cpqr_id(dn, di, dp, (int)par.size(), 1, R, Tmp.as<double>(), 2 * R, zv.as<double>(),
+                     Vtn.as<double>(), 2 * R, sV.as<double>(), rk_v.as<int32_t>(),
+                     sk_out.as<int32_t>(), sat, s);
+    }
+    std::vector<int32_t> nonroot;
+    for (int g = 0; g < nn; ++g)
+      if (f.nodes[g].parent >= 0) nonroot.push_back(g);
+    const int32_t* dnr = kp.put(nonroot, s);
+    launch_bskel(dn, dnr, (int)nonroot.size(), R, sU.as<double>(), sV.as<double>(), B.as<double>(),
+                 Bn.as<double>(), s);
+    h->U = std::move(Unew);
+    h->V = std::move(Vnew);
+    h->Ut = std::move(Utn);
+    h->Vt = std::move(Vtn);
+    h->B = std::move(Bn);
+    h->is_id = 1;
+  } else {
+    // orthonormal HBS: the leaf long bases are the current level's bases
+    h->U = DevBuf((size_t)N * R * 8);
+    h->V = DevBuf((size_t)N * R * 8);
+    copy_dev(h->U.as<double>(), uc, (size_t)N * R, s);
+    copy_dev(h->V.as<double>(), vc, (size_t)N * R, s);
+    h->Ut = std::move(Ut);
+    h->Vt = std::move(Vt);
+    h->B = std::move(B);
+    h->is_id = 0;
+  }
+  h->D = std::move(D);
+  h->f = f;
+  // ---- status, ranks, statistics ------------------------------------------------
+  int hflag[4] = {0, 0, 0, 0};
+  HIPCHK(hipMemcpyAsync(hflag, flag.p, 16, hipMemcpyDeviceToHost, s));
+  h->rank_u.assign(nn, 0);
+  h->rank_v.assign(nn, 0);
+  h->skel_in.assign((size_t)nn * R, -1);
+  h->skel_out.assign((size_t)nn * R, -1);
+  if (to_id) {
+    HIPCHK(hipMemcpyAsync(h->rank_u.data(), rk_u.p, nn * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(h->rank_v.data(), rk_v.p, nn * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(h->skel_in.data(), sk_in.p, (size_t)nn * R * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(h->skel_out.data(), sk_out.p, (size_t)nn * R * 4, hipMemcpyDeviceToHost, s));
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  if (hflag[0]) HM_THROW(HM_ERR_NONFINITE, "operator samples contain NaN or Inf");
+  if (!to_id)
+    for (int g = 0; g < nn; ++g) {
+      const Node& nd = f.nodes[g];
+      if (nd.parent < 0) continue;
+      const int r = f.inst[nd.inst].r;
+      h->rank_u[g] = h->rank_v[g] = std::min<int64_t>(r, nd.left < 0 ? nd.hi - nd.lo : 2 * r);
+    }
+  double op_ms = 0.0;
+  int calls = 0;
+  int64_t cols = 0;
+  for (auto* o : ops) { op_ms += o->elapsed_ms(); calls += o->calls; cols += o->columns; }
+  finish_handle_info(h.get());
+  h->info.sample_columns = cols;
+  h->info.operator_calls = calls;
+  h->info.saturated = hflag[1];
+  h->info.t_operator_ms = op_ms;
+  h->info.t_compress_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  *status = hflag[1] > 0 ? HM_WARN_RANK_SATURATED : HM_OK;
+  return h.release();
+}
+
+void finish_handle_info(hm_hbs_s* h) {
+  const Forest& f = h->f;
+  hm_info& in = h->info;
+  in.n = f.n_total;
+  in.leaf_size = f.inst.empty() ? 0 : f.inst[0].leaf;
+  in.levels = f.max_levels;
+  in.rank_pad = h->R;
+  in.is_id = h->is_id;
+  in.dtype = h->dtype;
+  int mx = 0, mn = 1 << 30;
+  int64_t st = 0;
+  for (size_t g = 0; g < f.nodes.size(); ++g) {
+    const Node& nd = f.nodes[g];
+    const int64_t n = nd.hi - nd.lo;
+    if (nd.left < 0) st += n * n;   // D
+    if (nd.parent < 0) continue;
+    const int ku = h->rank_u[g], kv = h->rank_v[g];
+    mx = std::max(mx, std::max(ku, kv));
+    mn = std::min(mn, std::min(ku, kv));
+    st += (int64_t)h->rank_u[nd.sib] * kv;   // B_{sib, v}
+    if (nd.left < 0) st += n * (ku + kv);
+    else st += (int64_t)(h->rank_u[nd.left] + h->rank_u[nd.right]) * ku +
+               (int64_t)(h->rank_v[nd.left] + h->rank_v[nd.right]) * kv;
+  }
+  in.max_rank = mx;
+  in.min_rank = mn == (1 << 30) ? 0 : mn;
+  in.storage_reals = st;
+}
+
+}  // namespace hm

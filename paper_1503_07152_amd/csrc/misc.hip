@@ -1,0 +1,290 @@
+// Test-matrix generation (Sec. 2.5 randn of Fig. 2/4), masking of test
+// matrices to the children of a level, block identity of the diagonal
+// extraction, fills, the non-finite check, forest construction, errors and
+// device buffers.
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+
+#include "common.h"
+
+namespace hm {
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+
+void set_error(const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+const char* get_error() { return g_err.c_str(); }
+
+void DevBuf::alloc(size_t b) {
+  release();
+  if (b == 0) b = 16;
+  hipError_t e = hipMalloc(&p, b);
+  if (e != hipSuccess) {
+    p = nullptr;
+    (void)hipGetLastError();
+    HM_THROW(HM_ERR_ALLOC, "hipMalloc(%zu bytes) failed: %s", b, hipGetErrorString(e));
+  }
+  bytes = b;
+}
+
+void DevBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+// ------------------------------------------------------------------ forest
+void forest_add_tree(Forest& f, int64_t n, int64_t leaf, int32_t r, int32_t k, int32_t p,
+                     double tol, uint64_t seed) {
+  Instance in{};
+  in.row0 = f.n_total;
+  in.n = n;
+  in.leaf = leaf;
+  in.L = 0;
+  if (n > leaf) in.L = (int32_t)std::ceil(std::log2((double)n / (double)leaf) - 1e-12);
+  while ((((n + (1ll << in.L) - 1) >> in.L)) > leaf) in.L++;  // guard log2 rounding
+  in.r = r;
+  in.k = k;
+  in.p = p;
+  in.tol = tol;
+  in.seed = seed;
+  in.root = (int32_t)f.nodes.size();
+  const int id = (int)f.inst.size();
+  // heap numbering inside the tree; global ids are base + heap - 1
+  const int base = in.root;
+  const int hs = 1 << (in.L + 1);
+  for (int t = 1; t < hs; ++t) {
+    Node nd{};
+    nd.inst = id;
+    nd.heap = t;
+    nd.level = 31 - __builtin_clz((unsigned)t);
+    nd.parent = t == 1 ? -1 : base + t / 2 - 1;
+    nd.left = (t < (1 << in.L)) ? base + 2 * t - 1 : -1;
+    nd.right = (t < (1 << in.L)) ? base + 2 * t : -1;
+    nd.sib = t == 1 ? -1 : base + (t ^ 1) - 1;
+    nd.is_left = (t > 1 && (t & 1) == 0) ? 1 : 0;
+    f.nodes.push_back(nd);
+  }
+  // intervals: root [row0, row0+n); left child takes ceil(n/2)
+  f.nodes[base].lo = in.row0;
+  f.nodes[base].hi = in.row0 + n;
+  for (int t = 1; t < (1 << in.L); ++t) {
+    Node& P = f.nodes[base + t - 1];
+    const int64_t mid = P.lo + (P.hi - P.lo + 1) / 2;
+    f.nodes[base + 2 * t - 1].lo = P.lo;
+    f.nodes[base + 2 * t - 1].hi = mid;
+    f.nodes[base + 2 * t].lo = mid;
+    f.nodes[base + 2 * t].hi = P.hi;
+  }
+  in.nmax = 0;
+  for (int t = 1 << in.L; t < hs; ++t) {
+    const Node& nd = f.nodes[base + t - 1];
+    in.nmax = std::max<int32_t>(in.nmax, (int32_t)(nd.hi - nd.lo));
+  }
+  f.inst.push_back(in);
+  f.n_total += n;
+}
+
+void forest_finish(Forest& f) {
+  f.max_levels = 0;
+  f.nmax = 0;
+  for (auto& in : f.inst) {
+    f.max_levels = std::max(f.max_levels, in.L);
+    f.nmax = std::max(f.nmax, in.nmax);
+  }
+  f.level.assign(f.max_levels + 1, {});
+  f.leaves.clear();
+  for (int g = 0; g < (int)f.nodes.size(); ++g) {
+    const Node& nd = f.nodes[g];
+    f.level[nd.level].push_back(g);
+    if (nd.left < 0) f.leaves.push_back(g);
+  }
+}
+
+// -------------------------------------------------------------- Philox + BM
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+  for (int i = 0; i < 10; ++i) {
+    const uint32_t hi0 = __umulhi(M0, c[0]), lo0 = M0 * c[0];
+    const uint32_t hi1 = __umulhi(M1, c[2]), lo1 = M1 * c[2];
+    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+    k0 += W0; k1 += W1;
+  }
+}
+
+// Two Gaussians (columns 2*jp and 2*jp+1) of row i of the stream.
+__device__ __forceinline__ void gauss_pair(uint64_t seed, int level, int phase, uint64_t i,
+                                           uint32_t jp, double& z0, double& z1) {
+  uint32_t c[4] = {(uint32_t)i, jp, (uint32_t)level, (uint32_t)phase};
+  philox4x32_10(c, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32));
+  const uint64_t m1 = (uint64_t)(c[0] >> 5) * 67108864ull + (uint64_t)(c[1] >> 6);
+  const uint64_t m2 = (uint64_t)(c[2] >> 5) * 67108864ull + (uint64_t)(c[3] >> 6);
+  const double u1 = ((double)m1 + 1.0) * 0x1.0p-53;
+  const double u2 = (double)m2 * 0x1.0p-53;
+  const double rad = sqrt(-2.0 * log(u1));
+  const double ang = 2.0 * M_PI * u2;
+  z0 = rad * cos(ang);
+  z1 = rad * sin(ang);
+}
+
+__global__ void k_gauss_raw(uint64_t seed, int level, int phase, int64_t row0, int64_t nrows,
+                            int ncols, double* out, int64_t ld) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nrows) return;
+  for (int jp = 0; 2 * jp < ncols; ++jp) {
+    double z0, z1;
+    gauss_pair(seed, level, phase, (uint64_t)(row0 + i), (uint32_t)jp, z0, z1);
+    out[i + (int64_t)(2 * jp) * ld] = z0;
+    if (2 * jp + 1 < ncols) out[i + (int64_t)(2 * jp + 1) * ld] = z1;
+  }
+}
+
+void launch_gauss_raw(uint64_t seed, int level, int phase, int64_t row0, int64_t nrows,
+                      int ncols, double* out, int64_t ld, hipStream_t s) {
+  if (nrows <= 0 || ncols <= 0) return;
+  const int nt = 256;
+  hipLaunchKernelGGL(k_gauss_raw, dim3((unsigned)((nrows + nt - 1) / nt)), dim3(nt), 0, s, seed,
+                     level, phase, row0, nrows, ncols, out, ld);
+  KCHK();
+}
+
+__global__ void k_gauss_masked(const Node* nodes, const Instance* inst, const int32_t* kids,
+                               int level, int R, double* Om, int64_t ld) {
+  const Node nd = nodes[kids[blockIdx.y]];
+  const Instance in = inst[nd.inst];
+  const int64_t i = nd.lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nd.hi) return;
+  const int off = nd.is_left ? R : 0;     // left child -> Omega_1 half
+  const int oth = nd.is_left ? 0 : R;
+  for (int j = 0; j < R; ++j) Om[i + (int64_t)(oth + j) * ld] = 0.0;
+  for (int j = in.r; j < R; ++j) Om[i + (int64_t)(off + j) * ld] = 0.0;
+  for (int jp = 0; 2 * jp < in.r; ++jp) {
+    double z0, z1;
+    gauss_pair(in.seed, level, 0, (uint64_t)(i - in.row0), (uint32_t)jp, z0, z1);
+    Om[i + (int64_t)(off + 2 * jp) * ld] = z0;
+    if (2 * jp + 1 < in.r) Om[i + (int64_t)(off + 2 * jp + 1) * ld] = z1;
+  }
+}
+
+void launch_gauss_masked(const Node* nodes, const Instance* inst, const int32_t* kids, int nkids,
+                         int64_t max_rows, int level, int R, double* Om, int64_t ld,
+                         hipStream_t s) {
+  if (nkids <= 0) return;
+  const int nt = 256;
+  hipLaunchKernelGGL(k_gauss_masked, dim3((unsigned)((max_rows + nt - 1) / nt), nkids), dim3(nt),
+                     0, s, nodes, inst, kids, level, R, Om, ld);
+  KCHK();
+}
+
+__global__ void k_mask_basis(const Node* nodes, const Instance* inst, const int32_t* kids, int R,
+                             const double* U, int64_t ldu, double* Om, int64_t ld) {
+  const Node nd = nodes[kids[blockIdx.y]];
+  const int r = inst[nd.inst].r;
+  const int64_t i = nd.lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nd.hi) return;
+  const int off = nd.is_left ? R : 0;
+  const int oth = nd.is_left ? 0 : R;
+  for (int j = 0; j < R; ++j) Om[i + (int64_t)(oth + j) * ld] = 0.0;
+  for (int j = 0; j < R; ++j) Om[i + (int64_t)(off + j) * ld] = j < r ? U[i + (int64_t)j * ldu] : 0.0;
+}
+
+void launch_mask_basis(const Node* nodes, const Instance* inst, const int32_t* kids, int nkids,
+                       int64_t max_rows, int R, const double* U, int64_t ldu, double* Om,
+                       int64_t ld, hipStream_t s) {
+  if (nkids <= 0) return;
+  const int nt = 256;
+  hipLaunchKernelGGL(k_mask_basis, dim3((unsigned)((max_rows + nt - 1) / nt), nkids), dim3(nt), 0,
+                     s, nodes, inst, kids, R, U, ldu, Om, ld);
+  KCHK();
+}
+
+__global__ void k_block_eye(const Node* nodes, const int32_t* leaves, int nmax, double* Om,
+                            int64_t ld) {
+  const Node nd = nodes[leaves[blockIdx.y]];
+  const int64_t i = nd.lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nd.hi) return;
+  const int64_t li = i - nd.lo;
+  for (int j = 0; j < nmax; ++j) Om[i + (int64_t)j * ld] = (j == li) ? 1.0 : 0.0;
+}
+
+void launch_block_eye(const Node* nodes, const int32_t* leaves, int nleaves, int64_t max_rows,
+                      int nmax, double* Om, int64_t ld, hipStream_t s) {
+  if (nleaves <= 0) return;
+  const int nt = 256;
+  hipLaunchKernelGGL(k_block_eye, dim3((unsigned)((max_rows + nt - 1) / nt), nleaves), dim3(nt),
+                     0, s, nodes, leaves, nmax, Om, ld);
+  KCHK();
+}
+
+__global__ void k_zero_dpad(const Node* nodes, const int32_t* leaves, int nmax, double* D,
+                            int64_t ld) {
+  const Node nd = nodes[leaves[blockIdx.y]];
+  const int64_t i = nd.lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nd.hi) return;
+  for (int j = (int)(nd.hi - nd.lo); j < nmax; ++j) D[i + (int64_t)j * ld] = 0.0;
+}
+
+void launch_zero_dpad(const Node* nodes, const int32_t* leaves, int nleaves, int64_t max_rows,
+                      int nmax, double* D, int64_t ld, hipStream_t s) {
+  if (nleaves <= 0) return;
+  const int nt = 256;
+  hipLaunchKernelGGL(k_zero_dpad, dim3((unsigned)((max_rows + nt - 1) / nt), nleaves), dim3(nt),
+                     0, s, nodes, leaves, nmax, D, ld);
+  KCHK();
+}
+
+__global__ void k_fill(double* p, int64_t rows, int64_t cols, int64_t ld, double v) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= rows) return;
+  for (int64_t j = 0; j < cols; ++j) p[i + j * ld] = v;
+}
+
+void launch_fill(double* p, int64_t rows, int64_t cols, int64_t ld, double v, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return;
+  const int nt = 256;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)((rows + nt - 1) / nt)), dim3(nt), 0, s, p, rows,
+                     cols, ld, v);
+  KCHK();
+}
+
+__global__ void k_fill_f(float* p, int64_t count, float v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+void launch_fill_f(float* p, int64_t count, float v, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_fill_f, dim3(1024), dim3(256), 0, s, p, count, v);
+  KCHK();
+}
+
+__global__ void k_nonfinite(const double* p, int64_t rows, int64_t cols, int64_t ld, int* flag) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= rows) return;
+  bool bad = false;
+  for (int64_t j = 0; j < cols; ++j) bad |= !isfinite(p[i + j * ld]);
+  if (bad) atomicOr(flag, 1);
+}
+
+void launch_nonfinite_check(const double* p, int64_t rows, int64_t cols, int64_t ld, int* flag,
+                            hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return;
+  const int nt = 256;
+  hipLaunchKernelGGL(k_nonfinite, dim3((unsigned)((rows + nt - 1) / nt)), dim3(nt), 0, s, p, rows,
+                     cols, ld, flag);
+  KCHK();
+}
+
+}  // namespace hm

@@ -1,0 +1,248 @@
+// Built-in black-box operators Y = A X for the sampling step (the T_mult of
+// Sec. 1): a kernel matrix A(i,j) = K(x_i, x_j) on 2-D points evaluated tile
+// by tile on the fly (never stored), or an explicit dense matrix.  The
+// contraction runs on MFMA:
+//   F64  : v_mfma_f64_16x16x4f64, entries in FP64
+//   F32  : v_mfma_f32_16x16x4f32, entries in FP32 (coordinate differences in FP64)
+//   BF16 : v_mfma_f32_16x16x32_bf16, entries rounded to BF16, FP32 accumulation
+// X is first packed K-tile-major in the contraction type, and a bitmask per
+// K-tile records which 16-column groups are nonzero: the structured test
+// matrices of Fig. 2/4 (half of every row zero) and the block identity of the
+// diagonal step then skip the MFMAs of zero groups.
+#include <hip/hip_bf16.h>
+
+#include "sampler.h"
+
+namespace hm {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+constexpr int SMP_RT = 2;             // 16-row tiles per wave
+constexpr int SMP_ROWS = 4 * 16 * SMP_RT;  // rows per block (4 waves)
+constexpr int SMP_CT = SMP_MAXC / 16; // column tiles
+
+template <int MODE> struct ModeT;
+template <> struct ModeT<0> { typedef double T; static constexpr int BK = 16; };
+template <> struct ModeT<1> { typedef float T; static constexpr int BK = 16; };
+template <> struct ModeT<2> { typedef __bf16 T; static constexpr int BK = 32; };
+
+int sampler_bk(int mode) { return mode == 2 ? 32 : 16; }
+
+size_t sampler_pack_bytes(int mode, int64_t n, int c) {
+  const int bk = sampler_bk(mode);
+  const int64_t kt = (n + bk - 1) / bk;
+  const int cp = ((c + 15) / 16) * 16;
+  const size_t es = mode == 0 ? 8 : (mode == 1 ? 4 : 2);
+  return (size_t)kt * bk * cp * es + (size_t)kt * 4 + 512;
+}
+
+// Pack: F64/F32 tiles [kt][k][col]; BF16 tiles [kt][col][k].
+template <int MODE>
+__global__ void k_pack(int64_t n, int c, int cp, const double* X, int64_t ldx,
+                       typename ModeT<MODE>::T* Xp, uint32_t* mask) {
+  typedef typename ModeT<MODE>::T T;
+  constexpr int BK = ModeT<MODE>::BK;
+  __shared__ uint32_t m;
+  const int64_t kt = blockIdx.x;
+  if (threadIdx.x == 0) m = 0;
+  __syncthreads();
+  uint32_t mine = 0;
+  T* tile = Xp + kt * (int64_t)BK * cp;
+  for (int e = threadIdx.x; e < BK * cp; e += blockDim.x) {
+    int k, col;
+    if (MODE == 2) { k = e % BK; col = e / BK; } else { col = e % cp; k = e / cp; }
+    const int64_t row = kt * BK + k;
+    double v = 0.0;
+    if (row < n && col < c) v = X[row + (int64_t)col * ldx];
+    if (v != 0.0) mine |= 1u << (col / 16);
+    tile[e] = (T)v;
+  }
+  if (mine) atomicOr(&m, mine);
+  __syncthreads();
+  if (threadIdx.x == 0) mask[kt] = m;
+}
+
+template <int SRC>
+__device__ __forceinline__ double entry_f64(double xi, double yi, double xj, double yj, int64_t gi,
+                                            int64_t gj, double kp) {
+  const double dx = xi - xj, dy = yi - yj;
+  const double d2 = dx * dx + dy * dy;
+  if (SRC == 0) return gi == gj ? 1.0 : 0.5 * log(d2);
+  return 1.0 / (sqrt(d2) + kp);
+}
+
+template <int SRC>
+__device__ __forceinline__ float entry_f32(double xi, double yi, double xj, double yj, int64_t gi,
+                                           int64_t gj, float kp) {
+  const float dx = (float)(xi - xj), dy = (float)(yi - yj);
+  const float d2 = fmaf(dx, dx, dy * dy);
+  if (SRC == 0) return gi == gj ? 1.0f : 0.34657359027997264f * __builtin_amdgcn_logf(d2);
+  return __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(d2) + kp);
+}
+
+// SRC: 0 log kernel, 1 near-singular kernel, 2 dense matrix, 3 its transpose (F64 only).
+template <int MODE, int SRC>
+__global__ __launch_bounds__(256) void k_sampler(int64_t n, int c, int cp, const double* pts,
+                                                 double kp, const double* Ad, int64_t lda,
+                                                 const typename ModeT<MODE>::T* Xp,
+                                                 const uint32_t* mask, double* Y, int64_t ldy) {
+  typedef typename ModeT<MODE>::T T;
+  constexpr int BK = ModeT<MODE>::BK;
+  __shared__ __attribute__((aligned(16))) T sX[BK * SMP_MAXC + 16];
+  __shared__ double sP[2 * BK];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t row0 = (int64_t)blockIdx.x * SMP_ROWS + wave * 16 * SMP_RT;
+  const int ct_n = cp / 16;
+  // coordinates of this lane's A-operand rows
+  double xi[SMP_RT], yi[SMP_RT];
+  int64_t gi[SMP_RT];
+#pragma unroll
+  for (int rt = 0; rt < SMP_RT; ++rt) {
+    gi[rt] = row0 + rt * 16 + (lane & 15);
+    const int64_t ii = gi[rt] < n ? gi[rt] : n - 1;
+    if (SRC < 2) { xi[rt] = pts[2 * ii]; yi[rt] = pts[2 * ii + 1]; }
+  }
+  typedef typename std::conditional<MODE == 0, d4, f4>::type acc_t;
+  acc_t acc[SMP_RT][SMP_CT];
+#pragma unroll
+  for (int rt = 0; rt < SMP_RT; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < SMP_CT; ++ct) acc[rt][ct] = acc_t{0, 0, 0, 0};
+  const int64_t nkt = (n + BK - 1) / BK;
+  for (int64_t kt = 0; kt < nkt; ++kt) {
+    const uint32_t msk = mask[kt];
+    if (msk == 0) continue;  // whole K-tile of X is zero
+    const T* tile = Xp + kt * (int64_t)BK * cp;
+    // stage X tile (contiguous) and the tile's points
+    {
+      const int ne = BK * cp;
+      if (MODE == 0) {
+        for (int e = tid; e < ne; e += 256) sX[e] = tile[e];
+      } else {
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(tile);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(sX);
+        const int nw = ne * (int)sizeof(T) / 4;
+        for (int e = tid; e < nw; e += 256) dst[e] = src[e];
+      }
+      if (SRC < 2 && tid < 2 * BK) {
+        const int64_t j = kt * BK + tid / 2;
+        sP[tid] = j < n ? pts[2 * j + (tid & 1)] : 0.0;
+      }
+    }
+    __syncthreads();
+    if constexpr (MODE == 0 || MODE == 1) {
+#pragma unroll
+      for (int s = 0; s < BK / 4; ++s) {
+        const int jl = 4 * s + (lane >> 4);
+        const int64_t gj = kt * BK + jl;
+        T a[SMP_RT];
+#pragma unroll
+        for (int rt = 0; rt < SMP_RT; ++rt) {
+          T v = T(0);
+          if (gj < n) {
+            if constexpr (SRC == 2 || SRC == 3) {
+              const int64_t ii = gi[rt] < n ? gi[rt] : n - 1;
+              v = SRC == 2 ? (T)Ad[ii + gj * lda] : (T)Ad[gj + ii * lda];
+            } else if constexpr (MODE == 0) {
+              v = (T)entry_f64<SRC>(xi[rt], yi[rt], sP[2 * jl], sP[2 * jl + 1], gi[rt], gj, kp);
+            } else {
+              v = (T)entry_f32<SRC>(xi[rt], yi[rt], sP[2 * jl], sP[2 * jl + 1], gi[rt], gj,
+                                    (float)kp);
+            }
+          }
+          a[rt] = v;
+        }
+#pragma unroll
+        for (int ct = 0; ct < SMP_CT; ++ct) {
+          if (ct >= ct_n || !((msk >> ct) & 1u)) continue;
+          const T b = sX[jl * cp + ct * 16 + (lane & 15)];
+#pragma unroll
+          for (int rt = 0; rt < SMP_RT; ++rt) {
+            if constexpr (MODE == 0)
+              acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt], b, acc[rt][ct], 0, 0, 0);
+            else
+              acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt], b, acc[rt][ct], 0, 0, 0);
+          }
+        }
+      }
+    } else {
+      // BF16: lane holds A(row, 8*(lane/16) + e), e = 0..7, and X(8*(lane/16) + e, col).
+      const int kb = 8 * (lane >> 4);
+      bf8 a[SMP_RT];
+#pragma unroll
+      for (int rt = 0; rt < SMP_RT; ++rt) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int jl = kb + e;
+          const int64_t gj = kt * BK + jl;
+          float v = 0.0f;
+          if (gj < n)
+            v = entry_f32<SRC >= 2 ? 1 : SRC>(xi[rt], yi[rt], sP[2 * jl], sP[2 * jl + 1], gi[rt],
+                                              gj, (float)kp);
+          a[rt][e] = (__bf16)v;
+        }
+      }
+#pragma unroll
+      for (int ct = 0; ct < SMP_CT; ++ct) {
+        if (ct >= ct_n || !((msk >> ct) & 1u)) continue;
+        const bf8 b = *reinterpret_cast<const bf8*>(&sX[(ct * 16 + (lane & 15)) * BK + kb]);
+#pragma unroll
+        for (int rt = 0; rt < SMP_RT; ++rt)
+          acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rt], b, acc[rt][ct], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  // Accumulator layout (column lane % 16 of each 16 x 16 tile): item v of lane
+  // l holds row 4*(l/16) + v for the FP32-accumulating instructions and row
+  // l/16 + 4*v for v_mfma_f64_16x16x4f64 (checked on gfx950 with identity inputs).
+#pragma unroll
+  for (int rt = 0; rt < SMP_RT; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < SMP_CT; ++ct) {
+      const int col = ct * 16 + (lane & 15);
+      if (ct >= ct_n || col >= c) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int rr = MODE == 0 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v;
+        const int64_t row = row0 + rt * 16 + rr;
+        if (row < n) Y[row + (int64_t)col * ldy] = (double)acc[rt][ct][v];
+      }
+    }
+}
+
+template <int MODE, int SRC>
+static void run_sampler(int64_t n, int c, const double* pts, double kp, const double* Ad,
+                        int64_t lda, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                        void* work, hipStream_t s) {
+  typedef typename ModeT<MODE>::T T;
+  constexpr int BK = ModeT<MODE>::BK;
+  const int cp = ((c + 15) / 16) * 16;
+  const int64_t nkt = (n + BK - 1) / BK;
+  T* Xp = static_cast<T*>(work);
+  uint32_t* mask = reinterpret_cast<uint32_t*>(
+      static_cast<char*>(work) + (((size_t)nkt * BK * cp * sizeof(T) + 255) / 256) * 256);
+  hipLaunchKernelGGL(k_pack<MODE>, dim3((unsigned)nkt), dim3(256), 0, s, n, c, cp, X, ldx, Xp,
+                     mask);
+  KCHK();
+  hipLaunchKernelGGL((k_sampler<MODE, SRC>), dim3((unsigned)((n + SMP_ROWS - 1) / SMP_ROWS)),
+                     dim3(256), 0, s, n, c, cp, pts, kp, Ad, lda, Xp, mask, Y, ldy);
+  KCHK();
+}
+
+void sampler_apply(int mode, int src, int64_t n, int c, const double* pts, double kp,
+                   const double* Ad, int64_t lda, const double* X, int64_t ldx, double* Y,
+                   int64_t ldy, void* work, hipStream_t s) {
+  if (n <= 0 || c <= 0) return;
+  if (c > SMP_MAXC) HM_THROW(HM_ERR_UNSUPPORTED, "sampler: %d columns > %d", c, SMP_MAXC);
+  if (src >= 2 && mode != 0) HM_THROW(HM_ERR_ARG, "dense operator samples in FP64 only");
+#define CASE(M, S) \
+  if (mode == M && src == S) return run_sampler<M, S>(n, c, pts, kp, Ad, lda, X, ldx, Y, ldy, work, s);
+  CASE(0, 0) CASE(0, 1) CASE(0, 2) CASE(0, 3) CASE(1, 0) CASE(1, 1) CASE(2, 0) CASE(2, 1)
+#undef CASE
+  HM_THROW(HM_ERR_ARG, "sampler: bad mode %d / source %d", mode, src);
+}
+
+}  // namespace hm
