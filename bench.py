@@ -1,0 +1,240 @@
+"""Benchmark of the randomized HBS compression on one MI355X.
+
+Workload (the mixed-precision configuration): HBS compression of the kernel
+matrix A(i,j) = 1/(|x_i - x_j| + 1e-3) on N = 65536 points of a smooth
+random-Fourier closed curve (8 modes, amplitude 0.2, seed 3), leaf 128
+(L = 9 levels), rank k = 32, oversampling p = 16 (r = 48 samples per level),
+HBS-ID output.  The operator is sampled on BF16 MFMA with FP32 accumulation;
+node factorisations (Householder TSQR, Jacobi SVD, pivoted-QR ID) run in FP64.
+
+One step = one full ``hbs_compress`` call (test matrices, operator samples,
+telescoping subtraction, node factorisations, transfers, diagonal blocks,
+HBS-ID sweep) with the points already resident in HBM.
+
+Reported: ``value`` = GFLOP/s of the compression, counting the operator
+products as dense N x N x c products (2 N^2 per sampled column, the paper's
+T_mult cost) plus nothing else (the net factorisation work is ~1% and is not
+counted); compress seconds of the BF16, FP32 and FP64 forms; accuracy of each
+form on sampled rows against the exact matrix; the dominant kernel's
+roofline; the CPU oracle on a bounded sample of the same products.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N, LEAF, K, P, DELTA, SEED_PTS, SEED = 65536, 128, 32, 16, 1e-3, 3, 3
+
+# MI355X published peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_TF = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
+# Peak of plain vector ALU work: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# = 39.3e12 lane-operations/s (one instruction slot per lane per cycle,
+# non-packed; transcendentals take 4 slots).
+PEAK_ALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# instruction slots per kernel entry in the BF16/FP32 sampler: 2 FP64
+# subtractions + 2 FP64->FP32 conversions, mul, fma, sqrt (4), add, rcp (4),
+# BF16 conversion (1/2): 14.5 slots
+SLOTS_PER_ENTRY = 14.5
+
+
+def levels(n, leaf):
+    return 0 if n <= leaf else int(math.ceil(math.log2(n / leaf)))
+
+
+def sample_columns(n, leaf, r):
+    L = levels(n, leaf)
+    return 4 * r * L + -(-n // 2 ** L)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=N)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="only the timed BF16 steps (for profiling runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(multi-GPU sharding is design-only)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1503_07152_amd as hm
+    import workloads as W
+
+    n = args.n
+    r = K + P
+    torch.cuda.set_device(0)
+    pts = torch.from_numpy(W.fourier_curve_points(n, seed=SEED_PTS)).cuda()
+    op_bf16 = hm.KernelOperator(pts, "near", DELTA, hm.HM_BF16)
+    opts = hm.Options(n, LEAF, K, P, seed=SEED)
+    print(f"bench: HBS compress N={n} leaf={LEAF} k={K} p={P} BF16 sampling; "
+          f"warmup {args.warmup}, steps {args.steps}", flush=True)
+
+    for i in range(args.warmup):
+        h = hm.hbs_compress(opts, op_bf16)
+        print(f"warmup {i}: {h.info()['t_compress_ms']:.1f} ms", flush=True)
+        del h
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    h = None
+    for i in range(args.steps):
+        del h
+        h = hm.hbs_compress(opts, op_bf16)
+        infos.append(h.info())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    cols = sample_columns(n, LEAF, r)
+    assert infos[-1]["sample_columns"] == cols, (infos[-1]["sample_columns"], cols)
+    flops = 2.0 * n * n * cols
+    value = flops / (ms * 1e-3) / 1e9
+    print(f"timed: {ms:.1f} ms/step, {value:.0f} GFLOP/s; operator share "
+          f"{infos[-1]['t_operator_ms'] / infos[-1]['t_compress_ms']:.2f}", flush=True)
+
+    out = {
+        "metric": "HBS compress s + GFLOP/s at N=65536,k=32 vs FP64 GPU; rel error; bwd apply GB/s",
+        "value": round(value, 1), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic (random-Fourier curve points, seed 3; Philox test matrices, seed 3)",
+        "config": {"workload": f"HBS-ID compression N={n} leaf={LEAF} k={K} p={P}, "
+                               "kernel 1/(|x-y|+1e-3) on a random-Fourier curve, BF16 MFMA "
+                               "sampling, FP64 factorisations",
+                   "n": n, "leaf": LEAF, "rank": K, "oversample": P,
+                   "levels": levels(n, LEAF), "sample_columns": cols},
+        "compress_s_bf16": round(ms / 1e3, 4),
+        "t_net_s_bf16": round((infos[-1]["t_compress_ms"] - infos[-1]["t_operator_ms"]) / 1e3, 4),
+    }
+    if not args.no_extra:
+        out.update(extra_measurements(hm, W, torch, pts, n, h, ms))
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(W, n)
+    print(json.dumps(out), flush=True)
+
+
+def extra_measurements(hm, W, torch, pts, n, h_bf16, ms_bf16):
+    from oracle import operators as oops   # exact entries of A on sampled rows only
+    res = {}
+    # ---- other precisions, one compress each ---------------------------------
+    forms = {"bf16": h_bf16}
+    times = {"bf16": ms_bf16 / 1e3}
+    for name, dt in (("f32", hm.HM_F32), ("f64", hm.HM_F64)):
+        op = hm.KernelOperator(pts, "near", DELTA, dt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hh = hm.hbs_compress(hm.Options(n, LEAF, K, P, seed=SEED), op)
+        torch.cuda.synchronize()
+        times[name] = time.perf_counter() - t0
+        forms[name] = hh
+        print(f"{name} form: {times[name] * 1e3:.1f} ms", flush=True)
+    res["compress_s_f32"] = round(times["f32"], 4)
+    res["compress_s_f64"] = round(times["f64"], 4)
+    res["speedup_bf16_vs_f64_gpu"] = round(times["f64"] / times["bf16"], 2)
+    res["speedup_f32_vs_f64_gpu"] = round(times["f64"] / times["f32"], 2)
+    # ---- accuracy on sampled rows against the exact matrix --------------------
+    Kop = oops.KernelOp(pts.cpu().numpy(), "near", DELTA)
+    rows = np.random.default_rng(0).choice(n, 256, replace=False)
+    w = W.gaussian((n, 4), seed=21)
+    exact = Kop.entries(rows, np.arange(n)) @ w
+    for name, hh in forms.items():
+        y = hh.apply(torch.from_numpy(w)).cpu().numpy()[rows]
+        res[f"rel_err_{name}_vs_A_sampled_rows"] = float(np.linalg.norm(y - exact) /
+                                                          np.linalg.norm(exact))
+    yb = forms["bf16"].apply(torch.from_numpy(w)).cpu().numpy()
+    y64 = forms["f64"].apply(torch.from_numpy(w)).cpu().numpy()
+    y32 = forms["f32"].apply(torch.from_numpy(w)).cpu().numpy()
+    res["rel_err_bf16_vs_f64_gpu"] = float(np.linalg.norm(yb - y64) / np.linalg.norm(y64))
+    res["rel_err_f32_vs_f64_gpu"] = float(np.linalg.norm(y32 - y64) / np.linalg.norm(y64))
+    inf = forms["bf16"].info()
+    res["ranks"] = [inf["min_rank"], inf["max_rank"]]
+    res["storage_reals_per_dof"] = round(inf["storage_reals"] / n, 1)
+    # ---- dominant kernel: the BF16 sampler, timed live with HIP events --------
+    c = 2 * (K + P)
+    X = hm.fortran(n, c)
+    X.copy_(torch.from_numpy(W.gaussian((n, c), seed=5)))
+    half = n // 2
+    X[:half, :c // 2] = 0.0          # structured like [Omega_2 | Omega_1]
+    X[half:, c // 2:] = 0.0
+    s = torch.cuda.current_stream()
+    hm.hm_operator_apply(hm.KernelOperator(pts, "near", DELTA, hm.HM_BF16), X)
+    reps = 5
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    op = hm.KernelOperator(pts, "near", DELTA, hm.HM_BF16)
+    e0.record(s)
+    for _ in range(reps):
+        hm.hm_operator_apply(op, X, stream=s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    t_launch = e0.elapsed_time(e1) / reps * 1e-3
+    entries = float(n) * n
+    achieved = entries * SLOTS_PER_ENTRY / t_launch / 1e12
+    res["roofline"] = {"bound": "alu", "achieved": round(achieved, 2), "peak": round(PEAK_ALU_TOPS, 1),
+                       "unit": "Tslot/s", "frac": round(achieved / PEAK_ALU_TOPS, 3),
+                       "traffic": None,
+                       "kernel": "k_sampler<BF16, near> (+ k_pack)",
+                       "launch_ms": round(t_launch * 1e3, 3),
+                       "mfma_frac": round(2 * n * (n * c / 2) / t_launch / 1e12 /
+                                          PEAK_TF["bf16"], 4)}
+    # FP64 form of the same kernel, MFMA-bound
+    op64 = hm.KernelOperator(pts, "near", DELTA, hm.HM_F64)
+    hm.hm_operator_apply(op64, X, stream=s)
+    e0.record(s)
+    for _ in range(2):
+        hm.hm_operator_apply(op64, X, stream=s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    t64 = e0.elapsed_time(e1) / 2 * 1e-3
+    res["roofline_f64_sampler"] = {"bound": "mfma", "achieved": round(2 * n * (n * c / 2) / t64 / 1e12, 2),
+                                   "peak": PEAK_TF["f64"], "unit": "TFLOP/s",
+                                   "frac": round(2 * n * (n * c / 2) / t64 / 1e12 / PEAK_TF["f64"], 3),
+                                   "launch_ms": round(t64 * 1e3, 3),
+                                   "note": "flops of the nonzero half of the structured block"}
+    return res
+
+
+def cpu_baseline(W, n):
+    """The FP64 oracle's operator product (the dominant step of the
+    compression) on a bounded sample: 1024 of the N rows against all N columns
+    and 96 sampled columns; scaled to GFLOP/s with the same 2 N^2 per column
+    count as ``value``."""
+    from oracle import operators as oops
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:  # noqa: BLE001
+        threads = 1
+    pts = W.fourier_curve_points(n, seed=SEED_PTS)
+    Kop = oops.KernelOp(pts, "near", DELTA, tile=256)
+    X = W.gaussian((n, 96), seed=5)
+    rows = 1024
+    sub = oops.KernelOp(pts, "near", DELTA, tile=256)
+    t0 = time.perf_counter()
+    done = 0
+    for i0 in range(0, rows, 256):
+        idx = np.arange(i0, min(i0 + 256, rows))
+        _ = sub.entries(idx, np.arange(n)) @ X
+        done += len(idx)
+    dt = time.perf_counter() - t0
+    gflops = 2.0 * done * n * 96 / dt / 1e9
+    return {"value": round(gflops, 2), "unit": "GFLOP/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"oracle kernel-matrix product, {done} of {n} rows x {n} columns x 96 "
+                      f"columns ({dt:.1f} s); FP64 NumPy"}
+
+
+if __name__ == "__main__":
+    main()

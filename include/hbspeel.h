@@ -129,6 +129,8 @@ typedef struct hm_info {
   int32_t saturated;     /* nodes whose revealed rank reached r - p               */
   double t_compress_ms;  /* wall time of the compress call                        */
   double t_operator_ms;  /* time inside the operator (T_compress - T_net)         */
+  int32_t jacobi_sweeps; /* most one-sided Jacobi sweeps any node SVD needed       */
+  int32_t pad_;
 } hm_info;
 
 /* ---- library ------------------------------------------------------------- */

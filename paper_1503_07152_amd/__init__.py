@@ -62,7 +62,8 @@ class _Info(C.Structure):
                 ("is_id", C.c_int32), ("dtype", C.c_int32), ("storage_reals", C.c_int64),
                 ("sample_columns", C.c_int64), ("operator_calls", C.c_int32),
                 ("saturated", C.c_int32), ("t_compress_ms", C.c_double),
-                ("t_operator_ms", C.c_double)]
+                ("t_operator_ms", C.c_double), ("jacobi_sweeps", C.c_int32),
+                ("pad_", C.c_int32)]
 
 
 _P, _I64, _I32 = C.c_void_p, C.c_int64, C.c_int32

@@ -37,6 +37,7 @@ struct SvdDesc {
   int64_t ldX;
   int32_t kout;
   int32_t pad_;
+  int32_t* sweeps;  // optional: atomic max of the Jacobi sweeps used
 };
 
 void launch_panel_qr(const PanelDesc* d, int n, hipStream_t s);

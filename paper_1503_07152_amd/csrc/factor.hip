@@ -14,18 +14,24 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // ------------------------------------------------------------ panel QR ----
+// The node factorisations keep a whole panel in LDS (up to ~150 KB), so only
+// one workgroup fits on a CU; 1024 threads (4 waves per SIMD) hide the LDS
+// and FP64 latencies within that workgroup.
+constexpr int FT = 1024;
+constexpr int FW = FT / 64;
+
 // Unblocked Householder QR (H_j = I - tau_j v_j v_j^T, v_j(j) = 1) of one
 // panel held in LDS.  Reflectors are stored below the diagonal, R on and above.
-__global__ __launch_bounds__(256) void k_panel_qr(const PanelDesc* descs) {
+__global__ __launch_bounds__(FT) void k_panel_qr(const PanelDesc* descs) {
   __shared__ double sA[FAC_LDMAX * FAC_CMAX];
-  __shared__ double part[4][64];
+  __shared__ double part[FW][64];
   __shared__ double sw[FAC_CMAX];
   __shared__ double sc[3];
   const PanelDesc d = descs[blockIdx.x];
   const int m = d.rows, n = d.cols;
   const int lds = (m & 1) ? m : m + 1;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int idx = tid; idx < m * n; idx += 256) {
+  for (int idx = tid; idx < m * n; idx += FT) {
     const int i = idx % m, j = idx / m;
     sA[i + j * lds] = d.A[i + (int64_t)j * d.ld];
   }
@@ -54,12 +60,12 @@ __global__ __launch_bounds__(256) void k_panel_qr(const PanelDesc* descs) {
     __syncthreads();
     const double beta = sc[0], tau = sc[1], scl = sc[2];
     if (tau != 0.0)
-      for (int i = j + 1 + tid; i < m; i += 256) sA[i + j * lds] *= scl;
+      for (int i = j + 1 + tid; i < m; i += FT) sA[i + j * lds] *= scl;
     __syncthreads();
     if (tid == 0) sA[j + j * lds] = beta;
     if (tau != 0.0 && j + 1 < n) {
       const int rows = m - j;
-      const int q = (rows + 3) / 4;
+      const int q = (rows + FW - 1) / FW;
       const int ib = j + wave * q, ie = min(m, ib + q);
       for (int kb = j + 1; kb < n; kb += 64) {
         const int k = kb + lane;
@@ -71,11 +77,16 @@ __global__ __launch_bounds__(256) void k_panel_qr(const PanelDesc* descs) {
           }
         part[wave][lane] = s;
         __syncthreads();
-        if (wave == 0 && k < n) sw[k] = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
+        if (wave == 0 && k < n) {
+          double t = 0.0;
+#pragma unroll
+          for (int w = 0; w < FW; ++w) t += part[w][lane];
+          sw[k] = t;
+        }
         __syncthreads();
       }
       const int nk = n - j - 1;
-      for (int idx = tid; idx < rows * nk; idx += 256) {
+      for (int idx = tid; idx < rows * nk; idx += FT) {
         const int i = j + idx % rows, k = j + 1 + idx / rows;
         const double v = (i == j) ? 1.0 : sA[i + j * lds];
         sA[i + k * lds] -= tau * v * sw[k];
@@ -84,12 +95,12 @@ __global__ __launch_bounds__(256) void k_panel_qr(const PanelDesc* descs) {
     if (tid == 0) d.tau[j] = tau;
     __syncthreads();
   }
-  for (int idx = tid; idx < m * n; idx += 256) {
+  for (int idx = tid; idx < m * n; idx += FT) {
     const int i = idx % m, j = idx / m;
     d.A[i + (int64_t)j * d.ld] = sA[i + j * lds];
   }
   if (d.Rout)
-    for (int idx = tid; idx < h * n; idx += 256) {
+    for (int idx = tid; idx < h * n; idx += FT) {
       const int i = idx % h, j = idx / h;
       d.Rout[i + (int64_t)j * d.ldR] = (i <= j) ? sA[i + j * lds] : 0.0;
     }
@@ -97,22 +108,22 @@ __global__ __launch_bounds__(256) void k_panel_qr(const PanelDesc* descs) {
 
 void launch_panel_qr(const PanelDesc* d, int n, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_panel_qr, dim3(n), dim3(256), 0, s, d);
+  hipLaunchKernelGGL(k_panel_qr, dim3(n), dim3(FT), 0, s, d);
   KCHK();
 }
 
 // Cout = H_0 H_1 ... H_{h-1} [Cin; 0]
 constexpr int APQ_NMAX = HM_MAX_SAMPLES;
-__global__ __launch_bounds__(256) void k_apply_q(const PanelDesc* descs) {
+__global__ __launch_bounds__(FT) void k_apply_q(const PanelDesc* descs) {
   __shared__ double sO[FAC_LDMAX * APQ_NMAX];
   __shared__ double sv[FAC_PMAX];
-  __shared__ double part[4][64];
+  __shared__ double part[FW][64];
   __shared__ double sw[64];
   const PanelDesc d = descs[blockIdx.x];
   const int m = d.rows, h = min(d.rows, d.cols), nc = d.ncol;
   const int ldo = (m & 1) ? m : m + 1;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int idx = tid; idx < m * nc; idx += 256) {
+  for (int idx = tid; idx < m * nc; idx += FT) {
     const int i = idx % m, c = idx / m;
     sO[i + c * ldo] = (i < h) ? d.Cin[i + (int64_t)c * d.ldCin] : 0.0;
   }
@@ -120,24 +131,29 @@ __global__ __launch_bounds__(256) void k_apply_q(const PanelDesc* descs) {
   for (int j = h - 1; j >= 0; --j) {
     const double tau = d.tau[j];
     if (tau == 0.0) continue;
-    for (int i = j + tid; i < m; i += 256) sv[i] = (i == j) ? 1.0 : d.A[i + (int64_t)j * d.ld];
+    for (int i = j + tid; i < m; i += FT) sv[i] = (i == j) ? 1.0 : d.A[i + (int64_t)j * d.ld];
     __syncthreads();
-    const int rows = m - j, q = (rows + 3) / 4;
+    const int rows = m - j, q = (rows + FW - 1) / FW;
     const int ib = j + wave * q, ie = min(m, ib + q);
     double s = 0.0;
     if (lane < nc)
       for (int i = ib; i < ie; ++i) s += sv[i] * sO[i + lane * ldo];
     part[wave][lane] = s;
     __syncthreads();
-    if (wave == 0) sw[lane] = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
+    if (wave == 0) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < FW; ++w) t += part[w][lane];
+      sw[lane] = t;
+    }
     __syncthreads();
-    for (int idx = tid; idx < rows * nc; idx += 256) {
+    for (int idx = tid; idx < rows * nc; idx += FT) {
       const int i = j + idx % rows, c = idx / rows;
       sO[i + c * ldo] -= tau * sv[i] * sw[c];
     }
     __syncthreads();
   }
-  for (int idx = tid; idx < m * nc; idx += 256) {
+  for (int idx = tid; idx < m * nc; idx += FT) {
     const int i = idx % m, c = idx / m;
     d.Cout[i + (int64_t)c * d.ldCout] = sO[i + c * ldo];
   }
@@ -145,15 +161,17 @@ __global__ __launch_bounds__(256) void k_apply_q(const PanelDesc* descs) {
 
 void launch_apply_q(const PanelDesc* d, int n, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_apply_q, dim3(n), dim3(256), 0, s, d);
+  hipLaunchKernelGGL(k_apply_q, dim3(n), dim3(FT), 0, s, d);
   KCHK();
 }
 
 // ------------------------------------------------------------ Jacobi SVD --
 // One-sided (Hestenes) Jacobi on the columns of R: R Z = W diag(s).  Pairs
-// follow a round-robin tournament; each 16-lane group rotates one pair.
+// follow a round-robin tournament; each 16-lane group rotates one pair, so a
+// 1024-thread workgroup treats every pair of a round (c <= 96) at once.
 constexpr int JAC_LD = FAC_CMAX + 1;
-__global__ __launch_bounds__(256) void k_jacobi(const SvdDesc* descs) {
+constexpr int JAC_GROUPS = FT / 16;
+__global__ __launch_bounds__(FT) void k_jacobi(const SvdDesc* descs) {
   __shared__ double sA[FAC_CMAX * JAC_LD];
   __shared__ double sZ[FAC_CMAX * JAC_LD];
   __shared__ double snorm[FAC_CMAX];
@@ -163,23 +181,24 @@ __global__ __launch_bounds__(256) void k_jacobi(const SvdDesc* descs) {
   const bool wantX = d.X != nullptr;
   const int tid = threadIdx.x;
   const int grp = tid >> 4, gl = tid & 15;
-  for (int idx = tid; idx < h * c; idx += 256) {
+  for (int idx = tid; idx < h * c; idx += FT) {
     const int i = idx % h, j = idx / h;
     sA[i + j * JAC_LD] = d.R[i + (int64_t)j * d.ldR];
   }
   if (wantX)
-    for (int idx = tid; idx < c * c; idx += 256) {
+    for (int idx = tid; idx < c * c; idx += FT) {
       const int i = idx % c, j = idx / c;
       sZ[i + j * JAC_LD] = (i == j) ? 1.0 : 0.0;
     }
   __syncthreads();
   const int n2 = c + (c & 1);
   const double tol = (double)max(h, 1) * DBL_EPSILON;
-  for (int sweep = 0; sweep < 40; ++sweep) {
+  int sweep = 0;
+  for (; sweep < 40; ++sweep) {
     if (tid == 0) flag = 0;
     __syncthreads();
     for (int t = 0; t < n2 - 1; ++t) {
-      for (int pi = grp; pi < n2 / 2; pi += 16) {
+      for (int pi = grp; pi < n2 / 2; pi += JAC_GROUPS) {
         const int a = pi, b = n2 - 1 - pi;
         const int pa = a == 0 ? 0 : 1 + (a - 1 + t) % (n2 - 1);
         const int pb = b == 0 ? 0 : 1 + (b - 1 + t) % (n2 - 1);
@@ -221,29 +240,37 @@ __global__ __launch_bounds__(256) void k_jacobi(const SvdDesc* descs) {
     if (flag == 0) break;
     __syncthreads();
   }
-  for (int j = tid; j < c; j += 256) {
+  if (tid == 0 && d.sweeps) atomicMax(d.sweeps, sweep + 1);
+  for (int j = tid; j < c; j += FT) {
     double s = 0.0;
     for (int i = 0; i < h; ++i) s += sA[i + j * JAC_LD] * sA[i + j * JAC_LD];
     snorm[j] = sqrt(s);
   }
   __syncthreads();
-  for (int j = tid; j < c; j += 256) {
+  __shared__ int srank[FAC_CMAX];
+  for (int j = tid; j < c; j += FT) {
     const double sj = snorm[j];
     int rk = 0;
-    for (int i = 0; i < c; ++i) rk += (snorm[i] > sj) || (snorm[i] == sj && i < j);
-    if (rk < d.kout) {
-      d.sv[rk] = sj;
-      const double inv = sj > 0.0 ? 1.0 / sj : 0.0;
-      for (int i = 0; i < h; ++i) d.W[i + (int64_t)rk * d.ldW] = sA[i + j * JAC_LD] * inv;
-      if (wantX)
-        for (int i = 0; i < c; ++i) d.X[i + (int64_t)rk * d.ldX] = sZ[i + j * JAC_LD];
-    }
+    for (int i2 = 0; i2 < c; ++i2) rk += (snorm[i2] > sj) || (snorm[i2] == sj && i2 < j);
+    srank[j] = rk;
+  }
+  __syncthreads();
+  // column j goes to position srank[j] (descending norms, ties by index)
+  const int rows = max(h, c);
+  for (int e = tid; e < c * rows; e += FT) {
+    const int i = e % rows, j = e / rows;
+    const int rk = srank[j];
+    if (rk >= d.kout) continue;
+    const double sj = snorm[j];
+    if (i == 0) d.sv[rk] = sj;
+    if (i < h) d.W[i + (int64_t)rk * d.ldW] = sj > 0.0 ? sA[i + j * JAC_LD] / sj : 0.0;
+    if (wantX && i < c) d.X[i + (int64_t)rk * d.ldX] = sZ[i + j * JAC_LD];
   }
 }
 
 void launch_jacobi_svd(const SvdDesc* d, int n, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_jacobi, dim3(n), dim3(256), 0, s, d);
+  hipLaunchKernelGGL(k_jacobi, dim3(n), dim3(FT), 0, s, d);
   KCHK();
 }
 

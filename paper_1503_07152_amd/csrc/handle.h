@@ -108,7 +108,7 @@ struct SvdJob {
 };
 void node_svd(const std::vector<SvdJob>& jobs, double* M, int64_t ldm, double* Uout, int64_t ldu,
               double* sv, double* X, int R, bool qr_only, Workspace& ws, Keeper& kp,
-              hipStream_t s);
+              hipStream_t s, int32_t* sweeps = nullptr);
 
 hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t flags, hipStream_t s,
                               int* status);

@@ -82,7 +82,7 @@ struct Alloc {
 
 void node_svd(const std::vector<SvdJob>& jobs, double* M, int64_t ldm, double* Uout, int64_t ldu,
               double* sv, double* X, int R, bool qr_only, Workspace& ws, Keeper& kp,
-              hipStream_t s) {
+              hipStream_t s, int32_t* sweeps) {
   if (jobs.empty()) return;
   int cmax = 1;
   for (auto& j : jobs) cmax = std::max(cmax, j.cols);
@@ -192,6 +192,7 @@ void node_svd(const std::vector<SvdJob>& jobs, double* M, int64_t ldm, double* U
             v.X = X ? X + (int64_t)jb.node * 2 * R * R : nullptr;
             v.ldX = 2 * R;
             v.kout = jb.kout;
+            v.sweeps = sweeps;
             sd.push_back(v);
           }
         }
@@ -334,7 +335,8 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
       jobs.push_back({g, (int)(nd.hi - nd.lo), under_root ? r : 2 * r, r, nd.lo});
     }
     launch_fill(un, N, R, N, 0.0, s);
-    node_svd(jobs, m, N, un, N, yv.as<double>(), nullptr, R, false, ws_svd, kp, s);
+    node_svd(jobs, m, N, un, N, yv.as<double>(), nullptr, R, false, ws_svd, kp, s,
+             flag.as<int32_t>() + 2);
     if (l >= 1) {
       ws_seg.ensure(seg_tn_work_bytes<double>(nk, lv.max_kid_rows, R, R), s);
       seg_tn<double>(dn, dk, nk, lv.max_kid_rows, R, R, un, N, uc, N, Ut.as<double>(),
@@ -350,7 +352,8 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
     launch_build_node_block(dn, di, dk, nk, lv.max_kid_rows, R, y, N, vc, N, zv.as<double>(), m,
                             N, s);
     launch_fill(vn, N, R, N, 0.0, s);
-    node_svd(jobs, m, N, vn, N, zv.as<double>(), Xr.as<double>(), R, false, ws_svd, kp, s);
+    node_svd(jobs, m, N, vn, N, zv.as<double>(), Xr.as<double>(), R, false, ws_svd, kp, s,
+             flag.as<int32_t>() + 2);
     launch_form_b(dn, di, dk, nk, R, Xr.as<double>(), zv.as<double>(), B.as<double>(), s);
     if (l >= 1)
       seg_tn<double>(dn, dk, nk, lv.max_kid_rows, R, R, vn, N, vc, N, Vt.as<double>(), 2 * R * R,
@@ -478,6 +481,7 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
   h->info.sample_columns = cols;
   h->info.operator_calls = calls;
   h->info.saturated = hflag[1];
+  h->info.jacobi_sweeps = hflag[2];
   h->info.t_operator_ms = op_ms;
   h->info.t_compress_ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();

@@ -82,7 +82,24 @@ __device__ __forceinline__ float entry_f32(double xi, double yi, double xj, doub
   return __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(d2) + kp);
 }
 
+// FP32 entry from FP32 coordinates (BF16 form: the coordinate rounding,
+// ~6e-8 absolute, stays far below BF16 resolution of the entry).
+template <int SRC>
+__device__ __forceinline__ float entry_f32c(float xi, float yi, float xj, float yj, int64_t gi,
+                                            int64_t gj, float kp) {
+  const float dx = xi - xj, dy = yi - yj;
+  const float d2 = fmaf(dx, dx, dy * dy);
+  if (SRC == 0) return gi == gj ? 1.0f : 0.34657359027997264f * __builtin_amdgcn_logf(d2);
+  return __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(d2) + kp);
+}
+
+// K-tiles between flushes of the FP32 MFMA accumulators into FP64 (FP32 form)
+constexpr int SMP_FLUSH = 32;
+
 // SRC: 0 log kernel, 1 near-singular kernel, 2 dense matrix, 3 its transpose (F64 only).
+// One block = 4 waves x SMP_RT 16-row tiles; the whole X is streamed through
+// LDS in K-tiles, double-buffered, the next tile prefetched into registers
+// while the current one feeds the MFMAs.
 template <int MODE, int SRC>
 __global__ __launch_bounds__(256) void k_sampler(int64_t n, int c, int cp, const double* pts,
                                                  double kp, const double* Ad, int64_t lda,
@@ -90,109 +107,148 @@ __global__ __launch_bounds__(256) void k_sampler(int64_t n, int c, int cp, const
                                                  const uint32_t* mask, double* Y, int64_t ldy) {
   typedef typename ModeT<MODE>::T T;
   constexpr int BK = ModeT<MODE>::BK;
-  __shared__ __attribute__((aligned(16))) T sX[BK * SMP_MAXC + 16];
-  __shared__ double sP[2 * BK];
+  constexpr int TILE_BYTES = BK * SMP_MAXC * (int)sizeof(T);
+  constexpr int NV = (TILE_BYTES + 256 * 16 - 1) / (256 * 16);   // uint4 per thread
+  __shared__ __attribute__((aligned(16))) T sX[2][BK * SMP_MAXC + 16];
+  __shared__ double sP[2][2 * BK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t row0 = (int64_t)blockIdx.x * SMP_ROWS + wave * 16 * SMP_RT;
   const int ct_n = cp / 16;
-  // coordinates of this lane's A-operand rows
+  const int tile_u4 = BK * cp * (int)sizeof(T) / 16;
   double xi[SMP_RT], yi[SMP_RT];
+  float xif[SMP_RT], yif[SMP_RT];
   int64_t gi[SMP_RT];
 #pragma unroll
   for (int rt = 0; rt < SMP_RT; ++rt) {
     gi[rt] = row0 + rt * 16 + (lane & 15);
     const int64_t ii = gi[rt] < n ? gi[rt] : n - 1;
-    if (SRC < 2) { xi[rt] = pts[2 * ii]; yi[rt] = pts[2 * ii + 1]; }
+    if (SRC < 2) {
+      xi[rt] = pts[2 * ii]; yi[rt] = pts[2 * ii + 1];
+      xif[rt] = (float)xi[rt]; yif[rt] = (float)yi[rt];
+    }
   }
   typedef typename std::conditional<MODE == 0, d4, f4>::type acc_t;
   acc_t acc[SMP_RT][SMP_CT];
+  d4 acc64[MODE == 1 ? SMP_RT : 1][MODE == 1 ? SMP_CT : 1];
 #pragma unroll
   for (int rt = 0; rt < SMP_RT; ++rt)
 #pragma unroll
     for (int ct = 0; ct < SMP_CT; ++ct) acc[rt][ct] = acc_t{0, 0, 0, 0};
+  if constexpr (MODE == 1) {
+#pragma unroll
+    for (int rt = 0; rt < SMP_RT; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < SMP_CT; ++ct) acc64[rt][ct] = d4{0, 0, 0, 0};
+  }
   const int64_t nkt = (n + BK - 1) / BK;
-  for (int64_t kt = 0; kt < nkt; ++kt) {
-    const uint32_t msk = mask[kt];
-    if (msk == 0) continue;  // whole K-tile of X is zero
-    const T* tile = Xp + kt * (int64_t)BK * cp;
-    // stage X tile (contiguous) and the tile's points
-    {
-      const int ne = BK * cp;
-      if (MODE == 0) {
-        for (int e = tid; e < ne; e += 256) sX[e] = tile[e];
-      } else {
-        const uint32_t* src = reinterpret_cast<const uint32_t*>(tile);
-        uint32_t* dst = reinterpret_cast<uint32_t*>(sX);
-        const int nw = ne * (int)sizeof(T) / 4;
-        for (int e = tid; e < nw; e += 256) dst[e] = src[e];
-      }
-      if (SRC < 2 && tid < 2 * BK) {
-        const int64_t j = kt * BK + tid / 2;
-        sP[tid] = j < n ? pts[2 * j + (tid & 1)] : 0.0;
-      }
+  uint4 pre[NV];
+  double pp = 0.0;
+  auto fetch = [&](int64_t kt) {
+    const uint4* src = reinterpret_cast<const uint4*>(Xp + kt * (int64_t)BK * cp);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int e = tid + v * 256;
+      if (e < tile_u4) pre[v] = src[e];
     }
-    __syncthreads();
-    if constexpr (MODE == 0 || MODE == 1) {
+    if (SRC < 2 && tid < 2 * BK) {
+      const int64_t j = kt * BK + tid / 2;
+      pp = j < n ? pts[2 * j + (tid & 1)] : 0.0;
+    }
+  };
+  auto stash = [&](int buf) {
+    uint4* dst = reinterpret_cast<uint4*>(sX[buf]);
 #pragma unroll
-      for (int s = 0; s < BK / 4; ++s) {
-        const int jl = 4 * s + (lane >> 4);
-        const int64_t gj = kt * BK + jl;
-        T a[SMP_RT];
+    for (int v = 0; v < NV; ++v) {
+      const int e = tid + v * 256;
+      if (e < tile_u4) dst[e] = pre[v];
+    }
+    if (SRC < 2 && tid < 2 * BK) sP[buf][tid] = pp;
+  };
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int64_t kt = 0; kt < nkt; ++kt) {
+    const int buf = (int)(kt & 1);
+    if (kt + 1 < nkt) fetch(kt + 1);
+    const uint32_t msk = mask[kt];
+    const T* xs = sX[buf];
+    const double* ps = sP[buf];
+    if (msk != 0) {
+      if constexpr (MODE == 0 || MODE == 1) {
 #pragma unroll
-        for (int rt = 0; rt < SMP_RT; ++rt) {
-          T v = T(0);
-          if (gj < n) {
-            if constexpr (SRC == 2 || SRC == 3) {
-              const int64_t ii = gi[rt] < n ? gi[rt] : n - 1;
-              v = SRC == 2 ? (T)Ad[ii + gj * lda] : (T)Ad[gj + ii * lda];
-            } else if constexpr (MODE == 0) {
-              v = (T)entry_f64<SRC>(xi[rt], yi[rt], sP[2 * jl], sP[2 * jl + 1], gi[rt], gj, kp);
-            } else {
-              v = (T)entry_f32<SRC>(xi[rt], yi[rt], sP[2 * jl], sP[2 * jl + 1], gi[rt], gj,
-                                    (float)kp);
-            }
-          }
-          a[rt] = v;
-        }
-#pragma unroll
-        for (int ct = 0; ct < SMP_CT; ++ct) {
-          if (ct >= ct_n || !((msk >> ct) & 1u)) continue;
-          const T b = sX[jl * cp + ct * 16 + (lane & 15)];
+        for (int s = 0; s < BK / 4; ++s) {
+          const int jl = 4 * s + (lane >> 4);
+          const int64_t gj = kt * BK + jl;
+          T a[SMP_RT];
 #pragma unroll
           for (int rt = 0; rt < SMP_RT; ++rt) {
-            if constexpr (MODE == 0)
-              acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt], b, acc[rt][ct], 0, 0, 0);
-            else
-              acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt], b, acc[rt][ct], 0, 0, 0);
+            T v = T(0);
+            if (gj < n) {
+              if constexpr (SRC == 2 || SRC == 3) {
+                const int64_t ii = gi[rt] < n ? gi[rt] : n - 1;
+                v = SRC == 2 ? (T)Ad[ii + gj * lda] : (T)Ad[gj + ii * lda];
+              } else if constexpr (MODE == 0) {
+                v = (T)entry_f64<SRC>(xi[rt], yi[rt], ps[2 * jl], ps[2 * jl + 1], gi[rt], gj, kp);
+              } else {
+                v = (T)entry_f32<SRC>(xi[rt], yi[rt], ps[2 * jl], ps[2 * jl + 1], gi[rt], gj,
+                                      (float)kp);
+              }
+            }
+            a[rt] = v;
+          }
+#pragma unroll
+          for (int ct = 0; ct < SMP_CT; ++ct) {
+            if (ct >= ct_n || !((msk >> ct) & 1u)) continue;
+            const T b = xs[jl * cp + ct * 16 + (lane & 15)];
+#pragma unroll
+            for (int rt = 0; rt < SMP_RT; ++rt) {
+              if constexpr (MODE == 0)
+                acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt], b, acc[rt][ct], 0, 0, 0);
+              else
+                acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt], b, acc[rt][ct], 0, 0, 0);
+            }
           }
         }
-      }
-    } else {
-      // BF16: lane holds A(row, 8*(lane/16) + e), e = 0..7, and X(8*(lane/16) + e, col).
-      const int kb = 8 * (lane >> 4);
-      bf8 a[SMP_RT];
-#pragma unroll
-      for (int rt = 0; rt < SMP_RT; ++rt) {
+      } else {
+        // BF16: lane holds A(row, 8*(lane/16) + e), e = 0..7, and X(8*(lane/16) + e, col).
+        const int kb = 8 * (lane >> 4);
+        bf8 a[SMP_RT];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
           const int jl = kb + e;
           const int64_t gj = kt * BK + jl;
-          float v = 0.0f;
-          if (gj < n)
-            v = entry_f32<SRC >= 2 ? 1 : SRC>(xi[rt], yi[rt], sP[2 * jl], sP[2 * jl + 1], gi[rt],
-                                              gj, (float)kp);
-          a[rt][e] = (__bf16)v;
+          const float xj = (float)ps[2 * jl], yj = (float)ps[2 * jl + 1];
+#pragma unroll
+          for (int rt = 0; rt < SMP_RT; ++rt) {
+            float v = 0.0f;
+            if (gj < n)
+              v = entry_f32c<SRC >= 2 ? 1 : SRC>(xif[rt], yif[rt], xj, yj, gi[rt], gj, (float)kp);
+            a[rt][e] = (__bf16)v;
+          }
+        }
+#pragma unroll
+        for (int ct = 0; ct < SMP_CT; ++ct) {
+          if (ct >= ct_n || !((msk >> ct) & 1u)) continue;
+          const bf8 b = *reinterpret_cast<const bf8*>(&xs[(ct * 16 + (lane & 15)) * BK + kb]);
+#pragma unroll
+          for (int rt = 0; rt < SMP_RT; ++rt)
+            acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rt], b, acc[rt][ct], 0, 0, 0);
         }
       }
-#pragma unroll
-      for (int ct = 0; ct < SMP_CT; ++ct) {
-        if (ct >= ct_n || !((msk >> ct) & 1u)) continue;
-        const bf8 b = *reinterpret_cast<const bf8*>(&sX[(ct * 16 + (lane & 15)) * BK + kb]);
+    }
+    if constexpr (MODE == 1) {
+      if ((kt % SMP_FLUSH) == SMP_FLUSH - 1 || kt + 1 == nkt) {
 #pragma unroll
         for (int rt = 0; rt < SMP_RT; ++rt)
-          acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rt], b, acc[rt][ct], 0, 0, 0);
+#pragma unroll
+          for (int ct = 0; ct < SMP_CT; ++ct) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc64[rt][ct][v] += (double)acc[rt][ct][v];
+            acc[rt][ct] = acc_t{0, 0, 0, 0};
+          }
       }
     }
+    if (kt + 1 < nkt) stash(buf ^ 1);
     __syncthreads();
   }
   // Accumulator layout (column lane % 16 of each 16 x 16 tile): item v of lane
@@ -208,7 +264,10 @@ __global__ __launch_bounds__(256) void k_sampler(int64_t n, int c, int cp, const
       for (int v = 0; v < 4; ++v) {
         const int rr = MODE == 0 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v;
         const int64_t row = row0 + rt * 16 + rr;
-        if (row < n) Y[row + (int64_t)col * ldy] = (double)acc[rt][ct][v];
+        double val;
+        if constexpr (MODE == 1) val = acc64[rt][ct][v];
+        else val = (double)acc[rt][ct][v];
+        if (row < n) Y[row + (int64_t)col * ldy] = val;
       }
     }
 }

