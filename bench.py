@@ -122,6 +122,7 @@ def main():
     }
     if not args.no_extra:
         out.update(extra_measurements(hm, W, torch, pts, n, h, ms))
+        out.update(backward_measurement(hm, W, torch))
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(W, n)
     print(json.dumps(out), flush=True)
@@ -205,6 +206,49 @@ def extra_measurements(hm, W, torch, pts, n, h_bf16, ms_bf16):
                                    "launch_ms": round(t64 * 1e3, 3),
                                    "note": "flops of the nonzero half of the structured block"}
     return res
+
+
+def backward_measurement(hm, W, torch, n=262144, leaf=128, k=32, c=64):
+    """Backward of the compressed apply y = A_H x (the differentiation
+    workload): synthetic HBS N=262144, leaf 128, k=32 (seed 4), 64 FP32
+    right-hand sides (seed 5).  Algorithmic bytes = every input read once
+    (x, gy, U, V, D, transfers, B) + every output written once (gx, gU, gV,
+    gD, gUt, gVt, gB)."""
+    g = W.synthetic_hbs(n, leaf, k, seed=4, dtype=np.float32)
+    h = hm.hm_hbs_from_generators(g, dtype=hm.HM_F32)
+    x = hm.to_fortran(torch.from_numpy(W.gaussian((n, c), seed=5, dtype=np.float32)))
+    gy = hm.to_fortran(torch.from_numpy(W.gaussian((n, c), seed=6, dtype=np.float32)))
+    s = torch.cuda.current_stream()
+    hm.hss_apply_backward(h, x, gy)
+    hm.hss_apply(h, x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record(s)
+    for _ in range(reps):
+        hm.hss_apply_backward(h, x, gy, stream=s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    tb = e0.elapsed_time(e1) / reps * 1e-3
+    e0.record(s)
+    for _ in range(reps):
+        hm.hss_apply(h, x, stream=s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    tf = e0.elapsed_time(e1) / reps * 1e-3
+    L = int(math.ceil(math.log2(n / leaf)))
+    nn = 2 ** (L + 1)
+    nmax = -(-n // 2 ** L)
+    small = nn * (2 * 2 * k * k + k * k)          # Ut, Vt, B
+    elems_in = 2 * n * c + 2 * n * k + n * nmax + small
+    elems_out = n * c + 2 * n * k + n * nmax + small
+    bwd_bytes = 4.0 * (elems_in + elems_out)
+    fwd_bytes = 4.0 * (n * c + 2 * n * k + n * nmax + small + n * c)
+    bw = bwd_bytes / tb / 1e9
+    return {"bwd_apply_GBps": round(bw, 1), "bwd_apply_ms": round(tb * 1e3, 3),
+            "bwd_apply_hbm_frac": round(bw / PEAK_HBM_GBS, 3),
+            "fwd_apply_GBps": round(fwd_bytes / tf / 1e9, 1), "fwd_apply_ms": round(tf * 1e3, 3),
+            "apply_config": f"synthetic HBS N={n} leaf={leaf} k={k}, {c} FP32 right-hand sides"}
 
 
 def cpu_baseline(W, n):

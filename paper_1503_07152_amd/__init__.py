@@ -21,7 +21,7 @@ __all__ = [
     "Options", "KernelOperator", "DenseOperator", "HBSOperator", "CallbackOperator",
     "HBS", "HODLR", "hm_gauss", "hm_operator_apply", "hbs_compress", "hodlr_compress", "hbs_compress_batched",
     "hss_apply", "hss_apply_adjoint", "hss_apply_backward", "hodlr_apply",
-    "hm_hbs_from_generators",
+    "hm_hbs_from_generators", "hbs_from_tensors", "HBSApply", "hbs_apply",
 ]
 
 HM_OK, HM_WARN_RANK_SATURATED = 0, 1
@@ -409,3 +409,43 @@ def hm_hbs_from_generators(g: dict, dtype=HM_F64, stream=None) -> HBS:
                                       _ptr(B), _ptr(D), _stream(stream), C.byref(h)))
     torch.cuda.synchronize()
     return HBS(h)
+
+
+def hbs_from_tensors(n, leaf, U, V, Ut, Vt, B, D, stream=None) -> HBS:
+    """HBS handle from device generator tensors in the flat layout (U, V:
+    (n, k); Ut, Vt: (nn, 2k, k); B: (nn, k, k); D: (n, nmax)); FP64 or FP32
+    by U's dtype.  The library copies the data."""
+    k = U.shape[1]
+    dt = HM_F64 if U.dtype == torch.float64 else HM_F32
+    tdt = U.dtype
+    Uf, Vf, Df = to_fortran(U, tdt), to_fortran(V, tdt), to_fortran(D, tdt)
+    blk = lambda a: a.detach().to(device="cuda", dtype=tdt).transpose(1, 2).contiguous()
+    Utb, Vtb, Bb = blk(Ut), blk(Vt), blk(B)
+    h = C.c_void_p()
+    _check(lib.hm_hbs_from_generators(n, leaf, k, dt, _ptr(Uf), _ptr(Vf), _ptr(Utb), _ptr(Vtb),
+                                      _ptr(Bb), _ptr(Df), _stream(stream), C.byref(h)))
+    return HBS(h)
+
+
+class HBSApply(torch.autograd.Function):
+    """y = A_H(U, V, Ut, Vt, B, D) x with the library's forward (Fig. 7 + D)
+    and hand-written backward (gradients w.r.t. x and every generator)."""
+
+    @staticmethod
+    def forward(ctx, x, U, V, Ut, Vt, B, D, n, leaf):
+        h = hbs_from_tensors(n, leaf, U, V, Ut, Vt, B, D)
+        xf = to_fortran(x, U.dtype)
+        ctx.h = h
+        ctx.save_for_backward(xf)
+        return hss_apply(h, xf)
+
+    @staticmethod
+    def backward(ctx, gy):
+        (xf,) = ctx.saved_tensors
+        gx, g = hss_apply_backward(ctx.h, xf, gy)
+        return gx, g["U"], g["V"], g["Ut"], g["Vt"], g["B"], g["D"], None, None
+
+
+def hbs_apply(x, U, V, Ut, Vt, B, D, n, leaf):
+    """Differentiable compressed apply (see HBSApply)."""
+    return HBSApply.apply(x, U, V, Ut, Vt, B, D, n, leaf)

@@ -2,6 +2,7 @@
 // argument validation, exception-to-status translation, handle management.
 #include <cstring>
 
+#include "grad.h"
 #include "handle.h"
 
 using namespace hm;
@@ -75,6 +76,50 @@ Forest single_forest(const hm_options* o) {
 size_t dsize(int dtype) { return dtype == HM_F32 ? 4 : 8; }
 
 }  // namespace
+
+template <class T>
+static void backward_impl(const hm_hbs* h, int c, const T* x, int64_t ldx, const T* gy,
+                          int64_t ldgy, T* gx, int64_t ldgx, T* gU, T* gV, T* gUt, T* gVt, T* gB,
+                          T* gD, hipStream_t s) {
+  const Forest& f = h->f;
+  const int64_t N = f.n_total;
+  const int R = h->R;
+  const int nn = (int)f.nodes.size();
+  const size_t wb = apply_work_bytes<T>(f, h->full, R, c);
+  void *w1 = nullptr, *w2 = nullptr;
+  HIPCHK(hipMallocAsync(&w1, wb, s));
+  HIPCHK(hipMallocAsync(&w2, wb, s));
+  const HbsView<T> hv = h->view<T>();
+  // forward expansions (outgoing qh, incoming uh) of x
+  apply_forest<T>(h->d_nodes.as<Node>(), h->full, hv, false, c, x, ldx, (T*)nullptr, N, T(1),
+                  T(0), w1, nn, s, true);
+  // adjoint apply of gy: gx, and its expansions g(uh) (upward) and g(qh) (downward)
+  apply_forest<T>(h->d_nodes.as<Node>(), h->full, hv, true, c, gy, ldgy, gx, ldgx, T(1), T(0), w2,
+                  nn, s);
+  const size_t es = sizeof(T);
+  if (gUt) HIPCHK(hipMemsetAsync(gUt, 0, (size_t)(nn + 1) * 2 * R * R * es, s));
+  if (gVt) HIPCHK(hipMemsetAsync(gVt, 0, (size_t)(nn + 1) * 2 * R * R * es, s));
+  if (gB) HIPCHK(hipMemsetAsync(gB, 0, (size_t)(nn + 1) * R * R * es, s));
+  int64_t maxl = 0, minl = INT64_MAX;
+  for (int g : f.leaves) {
+    maxl = std::max<int64_t>(maxl, f.nodes[g].hi - f.nodes[g].lo);
+    minl = std::min<int64_t>(minl, f.nodes[g].hi - f.nodes[g].lo);
+  }
+  if (gD && minl < f.nmax) HIPCHK(hipMemsetAsync(gD, 0, (size_t)N * f.nmax * es, s));
+  if (f.inst[0].L == 0) {
+    if (gU) HIPCHK(hipMemsetAsync(gU, 0, (size_t)N * R * es, s));
+    if (gV) HIPCHK(hipMemsetAsync(gV, 0, (size_t)N * R * es, s));
+  }
+  const T* QH = static_cast<const T*>(w1);
+  const T* UH = QH + (size_t)R * c * nn;
+  const T* GU = static_cast<const T*>(w2);
+  const T* GQ = GU + (size_t)R * c * nn;
+  launch_grad<T>(h->d_nodes.as<Node>(), h->grad_leaves.as<int32_t>(), (int)f.leaves.size(), maxl,
+                 f.nmax, h->grad_nodes.as<int32_t>(), nn, R, c, x, ldx, gy, ldgy, QH, UH, GU, GQ,
+                 gU, gV, gUt, gVt, gB, gD, N, N, s);
+  HIPCHK(hipFreeAsync(w1, s));
+  HIPCHK(hipFreeAsync(w2, s));
+}
 
 extern "C" {
 
@@ -244,6 +289,12 @@ int hm_hbs_from_generators(int64_t n, int64_t leaf_size, int32_t k, int32_t dtyp
     cp(h->D, D, 0, (size_t)n * nmax);
     std::vector<int> mvec{f.inst[0].L};
     build_apply_lists(f, mvec, h->full, s);
+    h->grad_leaves = upload(f.leaves, s);
+    {
+      std::vector<int32_t> all(f.nodes.size());
+      for (size_t g = 0; g < all.size(); ++g) all[g] = (int32_t)g;
+      h->grad_nodes = upload(all, s);
+    }
     h->rank_u.assign(nn, 0);
     h->rank_v.assign(nn, 0);
     for (int g = 1; g < nn; ++g) h->rank_u[g] = h->rank_v[g] = k;
@@ -317,7 +368,24 @@ void hm_hbs_free(hm_hbs* h) { delete h; }
 int hss_apply_backward(const hm_hbs* h, int64_t nrhs, const void* x, int64_t ldx, const void* gy,
                        int64_t ldgy, void* gx, int64_t ldgx, void* gU, void* gV, void* gUt,
                        void* gVt, void* gB, void* gD, void* stream) {
-  return guarded([&]() -> int { HM_THROW(HM_ERR_UNSUPPORTED, "backward is not built yet"); });
+  return guarded([&] {
+    if (!h || !x || !gy || !gx || nrhs < 1) HM_THROW(HM_ERR_ARG, "backward: bad arguments");
+    const int64_t n = h->f.n_total;
+    if (ldx < n || ldgy < n || ldgx < n) HM_THROW(HM_ERR_ARG, "backward: ld < n");
+    if (nrhs > 128) HM_THROW(HM_ERR_UNSUPPORTED, "backward: nrhs %lld > 128", (long long)nrhs);
+    if (h->f.inst.size() != 1) HM_THROW(HM_ERR_ARG, "backward: single-tree handles only");
+    hipStream_t s = (hipStream_t)stream;
+    const int c = (int)nrhs;
+    if (h->dtype == HM_F64)
+      backward_impl<double>(h, c, (const double*)x, ldx, (const double*)gy, ldgy, (double*)gx,
+                            ldgx, (double*)gU, (double*)gV, (double*)gUt, (double*)gVt,
+                            (double*)gB, (double*)gD, s);
+    else
+      backward_impl<float>(h, c, (const float*)x, ldx, (const float*)gy, ldgy, (float*)gx, ldgx,
+                           (float*)gU, (float*)gV, (float*)gUt, (float*)gVt, (float*)gB,
+                           (float*)gD, s);
+    return HM_OK;
+  });
 }
 
 int hodlr_apply(const hm_hodlr* h, int32_t adjoint, int64_t nrhs, const double* x, int64_t ldx,

@@ -47,10 +47,12 @@ template <class T>
 size_t apply_work_bytes(const Forest& f, const ApplyLists& al, int R, int c);
 
 // Y = beta Y + alpha (A^(m) X [+ D X]); adjoint applies (A^(m))^* [+ D^*].
+// The expansions stay in `work`: outgoing at work, incoming at
+// work + R*c*nnodes (per node R x c, ld R).  expansions_only skips Y.
 template <class T>
 void apply_forest(const Node* d_nodes, const ApplyLists& al, const HbsView<T>& h, bool adjoint,
                   int c, const T* X, int64_t ldx, T* Y, int64_t ldy, T alpha, T beta, void* work,
-                  size_t nnodes, hipStream_t s);
+                  size_t nnodes, hipStream_t s, bool expansions_only = false);
 
 // One level of a HODLR apply (Sec. 2.7): for the frontier nodes v (one tree
 // level), Y(I_a) = beta Y(I_a) + alpha U(I_a) diag(s[b]) V(I_b)^T X(I_b) with

@@ -178,7 +178,7 @@ size_t apply_work_bytes(const Forest& f, const ApplyLists& al, int R, int c) {
 template <class T>
 void apply_forest(const Node* d_nodes, const ApplyLists& al, const HbsView<T>& h, bool adjoint,
                   int c, const T* X, int64_t ldx, T* Y, int64_t ldy, T alpha, T beta, void* work,
-                  size_t nnodes, hipStream_t s) {
+                  size_t nnodes, hipStream_t s, bool expansions_only) {
   if (al.nfront == 0 || c <= 0) return;
   const int R = h.R;
   T* QH = static_cast<T*>(work);
@@ -219,6 +219,7 @@ void apply_forest(const Node* d_nodes, const ApplyLists& al, const HbsView<T>& h
       KCHK();
     }
   }
+  if (expansions_only) return;
   const int rt = (int)((al.max_rows + TM - 1) / TM);
   hipLaunchKernelGGL(k_leaf_down<T>, dim3(rt, al.nfront, ct), dim3(256), 0, s, d_nodes, front,
                      Uin, h.ldl, R, UH, c, h.D, h.ldd, adjoint ? 1 : 0, X, ldx, Y, ldy, alpha,
@@ -347,7 +348,7 @@ void seg_tn(const Node* d_nodes, const int32_t* list, int nlist, int64_t max_row
   template size_t apply_work_bytes<T>(const Forest&, const ApplyLists&, int, int);            \
   template void apply_forest<T>(const Node*, const ApplyLists&, const HbsView<T>&, bool, int,  \
                                 const T*, int64_t, T*, int64_t, T, T, void*, size_t,           \
-                                hipStream_t);                                                  \
+                                hipStream_t, bool);                                            \
   template void seg_tn<T>(const Node*, const int32_t*, int, int64_t, int, int, const T*,       \
                           int64_t, const T*, int64_t, T*, int64_t, int64_t, T, T, void*,       \
                           hipStream_t, int);                                                   \

@@ -1,0 +1,123 @@
+// Backward of the compressed apply y = A_H x (not in the paper; the
+// derivative of Fig. 7 + D with respect to its inputs).
+//
+// With the forward expansions qh_v (outgoing) and uh_v (incoming) and the
+// expansions of the adjoint apply of gy -- whose upward pass yields
+// g(uh)_v = U^T-side accumulations and whose downward pass yields g(qh)_v --
+// every generator gradient is an outer product over the right-hand sides:
+//   gD_t  = gy_t x_t^T                     gU_t = gy_t uh_t^T     (leaves)
+//   gV_t  = x_t g(qh)_t^T                  gB[v] = g(uh)_sib(v) qh_v^T
+//   gUt_t(child a) = g(uh)_a uh_t^T        gVt_t(child a) = qh_a g(qh)_t^T
+// and gx = A_H^* gy is the adjoint apply itself.
+#include "grad.h"
+#include "tile.h"
+
+namespace hm {
+
+constexpr int GM = 64, GN = 64;
+
+// Leaves: row tiles of gU, gV and gD.
+template <class T>
+__global__ __launch_bounds__(256) void k_grad_leaf(const Node* nodes, const int32_t* leaves,
+                                                   int R, int c, const T* X, int64_t ldx,
+                                                   const T* GY, int64_t ldgy, const T* UH,
+                                                   const T* GQ, T* gU, T* gV, T* gD, int64_t ld,
+                                                   int64_t ldd) {
+  __shared__ T smem[tile_smem_elems<GM, GN>()];
+  const int g = leaves[blockIdx.y];
+  const Node nd = nodes[g];
+  const int64_t i0 = nd.lo + (int64_t)blockIdx.x * GM;
+  if (i0 >= nd.hi) return;
+  const int M = (int)min<int64_t>(GM, nd.hi - i0);
+  const int nt = (int)(nd.hi - nd.lo);
+  const int part = blockIdx.z;  // 0: gU, 1: gV, 2..: column tiles of gD
+  TileAcc<T, GM, GN> acc;
+  acc.zero();
+  if (part == 0) {
+    if (!gU || nd.level == 0) return;
+    // gU(rows) = GY(rows, :) UH_g^T  (UH_g is R x c, ld R)
+    mm_tile<T, GM, GN>(M, R, c, GY + i0, 1, ldgy, UH + (int64_t)g * R * c, R, 1, acc, smem);
+    store_tile<T, GM, GN>(M, R, gU + i0, ld, acc, T(1), T(0));
+  } else if (part == 1) {
+    if (!gV || nd.level == 0) return;
+    mm_tile<T, GM, GN>(M, R, c, X + i0, 1, ldx, GQ + (int64_t)g * R * c, R, 1, acc, smem);
+    store_tile<T, GM, GN>(M, R, gV + i0, ld, acc, T(1), T(0));
+  } else {
+    if (!gD) return;
+    const int j0 = (part - 2) * GN;
+    if (j0 >= nt) return;
+    // gD(rows, j) = sum_c GY(row, c) X(lo + j, c)
+    mm_tile<T, GM, GN>(M, nt - j0, c, GY + i0, 1, ldgy, X + nd.lo + j0, ldx, 1, acc, smem);
+    store_tile<T, GM, GN>(M, min(GN, nt - j0), gD + i0 + (int64_t)j0 * ldd, ldd, acc, T(1), T(0));
+  }
+}
+
+// Nodes: gB for every non-root node, gUt / gVt halves for children of internal nodes.
+// Output blocks are heap-indexed in the flat layout: node g -> block g + 1 of
+// its tree (single-tree handles).
+template <class T>
+__global__ __launch_bounds__(256) void k_grad_node(const Node* nodes, const int32_t* list, int R,
+                                                   int c, const T* QH, const T* UH,
+                                                   const T* GU, const T* GQ, T* gB, T* gUt,
+                                                   T* gVt) {
+  __shared__ T smem[tile_smem_elems<GM, GN>()];
+  const int v = list[blockIdx.x];
+  const Node nd = nodes[v];
+  const int part = blockIdx.y;
+  const int64_t blk = (int64_t)v + 1;
+  TileAcc<T, GM, GN> acc;
+  acc.zero();
+  const T* qh = QH + (int64_t)v * R * c;
+  if (part == 0) {
+    if (!gB || nd.parent < 0) return;
+    // gB[v] = g(uh)_sib qh_v^T
+    mm_tile<T, GM, GN>(R, R, c, GU + (int64_t)nd.sib * R * c, 1, R, qh, R, 1, acc, smem);
+    store_tile<T, GM, GN>(R, R, gB + blk * R * R, R, acc, T(1), T(0));
+  } else {
+    // part 1: gUt half of child (side 0/1), part 3/4: gVt half
+    const bool want_u = part <= 2;
+    const int side = (part - 1) % 2;
+    if (nd.left < 0 || nd.parent < 0) return;
+    if (want_u ? !gUt : !gVt) return;
+    const int a = side == 0 ? nd.left : nd.right;
+    if (want_u) {
+      mm_tile<T, GM, GN>(R, R, c, GU + (int64_t)a * R * c, 1, R, UH + (int64_t)v * R * c, R, 1,
+                         acc, smem);
+      store_tile<T, GM, GN>(R, R, gUt + blk * 2 * R * R + side * R, 2 * R, acc, T(1), T(0));
+    } else {
+      mm_tile<T, GM, GN>(R, R, c, QH + (int64_t)a * R * c, 1, R, GQ + (int64_t)v * R * c, R, 1,
+                         acc, smem);
+      store_tile<T, GM, GN>(R, R, gVt + blk * 2 * R * R + side * R, 2 * R, acc, T(1), T(0));
+    }
+  }
+}
+
+template <class T>
+void launch_grad(const Node* d_nodes, const int32_t* leaves, int nleaves, int64_t max_leaf,
+                 int nmax, const int32_t* nodes_list, int nlist, int R, int c, const T* X,
+                 int64_t ldx, const T* GY, int64_t ldgy, const T* QH, const T* UH, const T* GU,
+                 const T* GQ, T* gU, T* gV, T* gUt, T* gVt, T* gB, T* gD, int64_t ld, int64_t ldd,
+                 hipStream_t s) {
+  if (nleaves > 0) {
+    const int parts = 2 + (nmax + GN - 1) / GN;
+    hipLaunchKernelGGL(k_grad_leaf<T>, dim3((unsigned)((max_leaf + GM - 1) / GM), nleaves, parts),
+                       dim3(256), 0, s, d_nodes, leaves, R, c, X, ldx, GY, ldgy, UH, GQ, gU, gV,
+                       gD, ld, ldd);
+    KCHK();
+  }
+  if (nlist > 0 && R > 0) {
+    hipLaunchKernelGGL(k_grad_node<T>, dim3(nlist, 5), dim3(256), 0, s, d_nodes, nodes_list, R, c,
+                       QH, UH, GU, GQ, gB, gUt, gVt);
+    KCHK();
+  }
+}
+
+#define INST(T)                                                                                 \
+  template void launch_grad<T>(const Node*, const int32_t*, int, int64_t, int, const int32_t*,  \
+                               int, int, int, const T*, int64_t, const T*, int64_t, const T*,   \
+                               const T*, const T*, const T*, T*, T*, T*, T*, T*, T*, int64_t,   \
+                               int64_t, hipStream_t);
+INST(double)
+INST(float)
+
+}  // namespace hm

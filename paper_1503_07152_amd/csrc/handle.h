@@ -25,6 +25,7 @@ struct hm_hbs_s {
   std::vector<int32_t> rank_u, rank_v;      // per node
   std::vector<int32_t> skel_in, skel_out;   // per node x R (instance-local rows), -1 padded
   hm::ApplyLists full;                      // frontier = leaves
+  hm::DevBuf grad_leaves, grad_nodes;       // leaf list and all-node list (backward)
   hm_info info{};
 
   template <class T>

@@ -373,6 +373,12 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
     std::vector<int> mvec(f.inst.size());
     for (size_t i = 0; i < f.inst.size(); ++i) mvec[i] = f.inst[i].L;
     build_apply_lists(f, mvec, h->full, s);
+    h->grad_leaves = upload(f.leaves, s);
+    {
+      std::vector<int32_t> all(f.nodes.size());
+      for (size_t g = 0; g < all.size(); ++g) all[g] = (int32_t)g;
+      h->grad_nodes = upload(all, s);
+    }
     HbsView<double> hv;
     hv.Ulong = uc; hv.Vlong = vc; hv.ldl = N; hv.Ut = Ut.as<double>(); hv.Vt = Vt.as<double>();
     hv.B = B.as<double>(); hv.D = nullptr; hv.R = R;
