@@ -123,6 +123,7 @@ def main():
     if not args.no_extra:
         out.update(extra_measurements(hm, W, torch, pts, n, h, ms))
         out.update(backward_measurement(hm, W, torch))
+        out.update(batched_measurement(hm, W, torch))
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(W, n)
     print(json.dumps(out), flush=True)
@@ -249,6 +250,33 @@ def backward_measurement(hm, W, torch, n=262144, leaf=128, k=32, c=64):
             "bwd_apply_hbm_frac": round(bw / PEAK_HBM_GBS, 3),
             "fwd_apply_GBps": round(fwd_bytes / tf / 1e9, 1), "fwd_apply_ms": round(tf * 1e3, 3),
             "apply_config": f"synthetic HBS N={n} leaf={leaf} k={k}, {c} FP32 right-hand sides"}
+
+
+def batched_measurement(hm, W, torch, count=256, leaf=128, p=8):
+    """Many uneven instances: N_i log-uniform in [512, 8192] (multiples of 64),
+    k_i uniform in [8, 40] (seed 2), synthetic HBS operators; one batched call
+    against one call per instance."""
+    specs = W.batched_instances(count, seed=2)
+    ops_h = [hm.hm_hbs_from_generators(W.synthetic_hbs(n, leaf, k, seed=1000 + i))
+             for i, (n, k) in enumerate(specs)]
+    opts = [hm.Options(n, leaf, k, p, seed=2 + i) for i, (n, k) in enumerate(specs)]
+    ops = [hm.HBSOperator(h) for h in ops_h]
+    hm.hbs_compress_batched(opts[:8], ops[:8])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = hm.hbs_compress_batched(opts, ops)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    del outs
+    t0 = time.perf_counter()
+    for o, op in zip(opts, ops):
+        h = hm.hbs_compress(o, op)
+        del h
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    return {"batched_instances": count, "batched_total_n": int(sum(n for n, _ in specs)),
+            "batched_s": round(tb, 4), "batched_instances_per_s": round(count / tb, 1),
+            "sequential_s": round(ts, 4), "batched_speedup": round(ts / tb, 2)}
 
 
 def cpu_baseline(W, n):

@@ -177,10 +177,46 @@ int hbs_compress(const hm_options* opts, const hm_operator* op, void* stream, hm
 
 int hbs_compress_batched(int32_t count, const hm_options* opts, const hm_operator* ops,
                          void* stream, hm_hbs** outs) {
+  if (outs && count > 0)
+    for (int i = 0; i < count; ++i) outs[i] = nullptr;
   return guarded([&]() -> int {
     if (count < 1 || !opts || !ops || !outs) HM_THROW(HM_ERR_ARG, "batched: bad arguments");
-    for (int i = 0; i < count; ++i) outs[i] = nullptr;
-    HM_THROW(HM_ERR_UNSUPPORTED, "batched compression is not built yet");
+    hipStream_t s = (hipStream_t)stream;
+    Forest f;
+    bool all_hbs = true;
+    for (int i = 0; i < count; ++i) {
+      check_options(&opts[i]);
+      check_operator(&ops[i], opts[i].n, true);
+      if (opts[i].flags != opts[0].flags) HM_THROW(HM_ERR_ARG, "batched: flags differ");
+      all_hbs &= ops[i].kind == HM_OP_HBS;
+      forest_add_tree(f, opts[i].n, opts[i].leaf_size, opts[i].rank + opts[i].oversample,
+                      opts[i].rank, opts[i].oversample, opts[i].tol, opts[i].seed);
+    }
+    std::unique_ptr<hm_hbs_s> merged;
+    std::vector<std::unique_ptr<OpRunner>> runners;
+    std::vector<OpRunner*> rp;
+    if (all_hbs) {
+      std::vector<const hm_hbs_s*> hs;
+      for (int i = 0; i < count; ++i) hs.push_back(ops[i].hbs);
+      merged.reset(merge_hbs(hs, s));
+      runners.emplace_back(new OpRunner());
+      runners[0]->op = ops[0];
+      runners[0]->hbs = merged.get();
+      runners[0]->s = s;
+    } else {
+      for (int i = 0; i < count; ++i) {
+        runners.emplace_back(new OpRunner());
+        runners.back()->op = ops[i];
+        runners.back()->hbs = ops[i].kind == HM_OP_HBS ? ops[i].hbs : nullptr;
+        runners.back()->s = s;
+      }
+    }
+    for (auto& r : runners) rp.push_back(r.get());
+    int status = HM_OK;
+    std::unique_ptr<hm_hbs_s> res(hbs_compress_forest(f, rp, opts[0].flags, s, &status));
+    std::vector<hm_hbs_s*> parts = split_hbs(res.get(), s);
+    for (int i = 0; i < count; ++i) outs[i] = parts[i];
+    return status;
   });
 }
 

@@ -118,5 +118,9 @@ void hodlr_apply_full(const hm_hodlr_s* h, bool adjoint, int c, const double* X,
                       double* Y, int64_t ldy, hipStream_t s);
 
 void finish_handle_info(hm_hbs_s* h);
+// Block-diagonal forest operator from single-tree FP64 handles; one handle per
+// instance of a forest handle.
+hm_hbs_s* merge_hbs(const std::vector<const hm_hbs_s*>& hs, hipStream_t s);
+std::vector<hm_hbs_s*> split_hbs(const hm_hbs_s* src, hipStream_t s);
 
 }  // namespace hm

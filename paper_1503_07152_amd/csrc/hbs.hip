@@ -277,6 +277,7 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
   DevBuf Om((size_t)N * W * 8), Y((size_t)N * W * 8), M((size_t)N * 2 * R * 8);
   DevBuf Ucur((size_t)N * R * 8), Vcur((size_t)N * R * 8), Unx((size_t)N * R * 8),
       Vnx((size_t)N * R * 8);
+  DevBuf Uleaf((size_t)N * R * 8), Vleaf((size_t)N * R * 8);   // leaf bases of every instance
   DevBuf yv((size_t)nn * R * 8), zv((size_t)nn * R * 8);
   DevBuf Ut((size_t)nn * 2 * R * R * 8), Vt((size_t)nn * 2 * R * R * 8);
   DevBuf B((size_t)nn * R * R * 8), Xr((size_t)nn * 2 * R * R * 8);
@@ -358,8 +359,23 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
     if (l >= 1)
       seg_tn<double>(dn, dk, nk, lv.max_kid_rows, R, R, vn, N, vc, N, Vt.as<double>(), 2 * R * R,
                      2 * R, 1.0, 0.0, ws_seg.base(), s, 1);
+    // instances whose leaves are on level l + 1 are done peeling: keep their
+    // leaf bases (the working buffers are reused by deeper instances)
+    for (const Instance& in : f.inst) {
+      if (in.L != l + 1) continue;
+      for (int side = 0; side < 2; ++side) {
+        const double* src = side == 0 ? un : vn;
+        double* dst = (side == 0 ? Uleaf : Vleaf).as<double>();
+        HIPCHK(hipMemcpy2DAsync(dst + in.row0, N * 8, src + in.row0, N * 8, in.n * 8, R,
+                                hipMemcpyDeviceToDevice, s));
+      }
+    }
     std::swap(uc, un);
     std::swap(vc, vn);
+  }
+  if (Lmax >= 1) {
+    uc = Uleaf.as<double>();
+    vc = Vleaf.as<double>();
   }
   // ---- diagonal blocks ------------------------------------------------------------
   DevBuf D((size_t)N * nmax * 8);

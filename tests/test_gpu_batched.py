@@ -1,0 +1,41 @@
+"""GPU parity of the batched many-instance compression: uneven instances
+(sizes, ranks, depths) compressed in one level-synchronous pass must each
+equal the oracle's compression of that instance alone (same seed, same test
+matrices) and recover their exact-rank operator."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import hbs as ohbs
+from oracle import operators as oops
+
+pytestmark = pytest.mark.gpu
+hm = pytest.importorskip("paper_1503_07152_amd")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("ortho", [False, True])
+def test_batched_matches_per_instance_oracle(ortho):
+    specs = [(640, 8), (1280, 12), (2112, 20), (576, 16), (1024, 10), (4096, 30), (128, 6)]
+    leaf, p = 128, 8
+    print(f"batched {len(specs)} instances ortho={ortho}", flush=True)
+    gens = [W.synthetic_hbs(n, leaf, k, seed=100 + i) for i, (n, k) in enumerate(specs)]
+    ops_h = [hm.hm_hbs_from_generators(g) for g in gens]
+    opts = [hm.Options(n, leaf, k, p, seed=7 + i, orthonormal=ortho)
+            for i, (n, k) in enumerate(specs)]
+    outs = hm.hbs_compress_batched(opts, [hm.HBSOperator(h) for h in ops_h])
+    for i, ((n, k), g, h) in enumerate(zip(specs, gens, outs)):
+        full = ohbs.from_generators(g)
+        ho, st, _ = ohbs.compress(oops.HBSOp(full), n, leaf, k + p, 7 + i, rank=k, to_id=not ortho)
+        x = W.gaussian((n, 4), seed=3)
+        y = h.apply(torch.from_numpy(x)).cpu().numpy()
+        e_or, e_a = rel(y, ho.apply(x)), rel(y, full.apply(x))
+        print(f"  instance {i} n={n} k={k}: vs oracle {e_or:.2e} vs A {e_a:.2e}", flush=True)
+        assert e_or < 1e-11 and e_a < 1e-11
+        assert h.info()["sample_columns"] == st.columns
