@@ -65,6 +65,15 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true",
                     help="only the timed BF16 steps (for profiling runs)")
+    ap.add_argument("--sampler-only", action="store_true",
+                    help="only the BF16 sampler on one structured N x 96 block, 3 launches "
+                         "(hardware-counter runs)")
+    ap.add_argument("--apply-only", action="store_true",
+                    help="only the forward and backward compressed apply of the "
+                         "differentiation workload (profiling runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only a plain device copy of 256 MiB, 3 times (scale of the "
+                         "FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -78,6 +87,30 @@ def main():
     n = args.n
     r = K + P
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print("copy calibration: 3 x 268435456 bytes read and written", flush=True)
+        return
+    if args.apply_only:
+        print(json.dumps(backward_measurement(hm, W, torch)), flush=True)
+        return
+    if args.sampler_only:
+        pts = torch.from_numpy(W.fourier_curve_points(n, seed=SEED_PTS)).cuda()
+        c = 2 * r
+        X = hm.fortran(n, c)
+        X.copy_(torch.from_numpy(W.gaussian((n, c), seed=5)))
+        X[: n // 2, : c // 2] = 0.0
+        X[n // 2:, c // 2:] = 0.0
+        op = hm.KernelOperator(pts, "near", DELTA, hm.HM_BF16)
+        for _ in range(3):
+            hm.hm_operator_apply(op, X)
+        torch.cuda.synchronize()
+        print(f"sampler-only: 3 launches, N={n}, {c} columns", flush=True)
+        return
     pts = torch.from_numpy(W.fourier_curve_points(n, seed=SEED_PTS)).cuda()
     op_bf16 = hm.KernelOperator(pts, "near", DELTA, hm.HM_BF16)
     opts = hm.Options(n, LEAF, K, P, seed=SEED)
@@ -119,6 +152,7 @@ def main():
                    "levels": levels(n, LEAF), "sample_columns": cols},
         "compress_s_bf16": round(ms / 1e3, 4),
         "t_net_s_bf16": round((infos[-1]["t_compress_ms"] - infos[-1]["t_operator_ms"]) / 1e3, 4),
+        "jacobi_sweeps_max": infos[-1]["jacobi_sweeps"],
     }
     if not args.no_extra:
         out.update(extra_measurements(hm, W, torch, pts, n, h, ms))

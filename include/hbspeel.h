@@ -37,7 +37,7 @@ extern "C" {
 
 /* ---- status codes ------------------------------------------------------ */
 #define HM_OK 0
-#define HM_WARN_RANK_SATURATED 1   /* a revealed eps-rank reached r - p (Sec. 2.5:
+#define HM_WARN_RANK_SATURATED 1   /* a revealed eps-rank reached the cap r - p (Sec. 2.5:
                                       the sample may not have captured the block) */
 #define HM_ERR_ARG (-1)            /* invalid argument (sizes, ld, options)     */
 #define HM_ERR_ALLOC (-2)          /* device allocation failed                  */

@@ -23,11 +23,12 @@ struct PanelDesc {
   double* Cout;     // apply: rows x ncol output  Q [Cin; 0]
   int64_t ldCout;
   int32_t ncol;
-  int32_t pad_;
+  int32_t trans;    // QR: the panel is the transpose of A (A stored cols x rows);
+                    // the factored panel is written back untransposed, ld ld
 };
 
 struct SvdDesc {
-  const double* R;  // h x c (h <= c), leading dim ldR
+  const double* R;  // h x c (h <= c), leading dim ldR; c x h when trans
   int64_t ldR;
   int32_t h, c;
   double* W;        // left singular vectors, h x kout (descending singular values)
@@ -35,8 +36,8 @@ struct SvdDesc {
   double* sv;       // kout singular values
   double* X;        // right singular vectors, c x kout (may be null)
   int64_t ldX;
-  int32_t kout;
-  int32_t pad_;
+  int32_t kout;     // columns of W / X written (those beyond c are zero)
+  int32_t trans;    // 1: factor R^T (R stored c x h)
   int32_t* sweeps;  // optional: atomic max of the Jacobi sweeps used
 };
 

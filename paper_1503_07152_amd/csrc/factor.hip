@@ -22,79 +22,105 @@ constexpr int FW = FT / 64;
 
 // Unblocked Householder QR (H_j = I - tau_j v_j v_j^T, v_j(j) = 1) of one
 // panel held in LDS.  Reflectors are stored below the diagonal, R on and above.
+// Per column j, one reduction gives g_k = sum_{i>=j} A(i,j) A(i,k) for all
+// k > j and, for k = j, the squared norm below the diagonal.  With
+// beta = -sign(x0) |A(j:,j)| and v = [1; A(j+1:,j)/(x0 - beta)] one has
+// v^T A(j:,k) = (g_k - beta A(j,k)) / (x0 - beta), so the update needs no
+// second reduction.  The scaling of column j into v is deferred to the next
+// step (which never reads column j): three barriers per column.
 __global__ __launch_bounds__(FT) void k_panel_qr(const PanelDesc* descs) {
   __shared__ double sA[FAC_LDMAX * FAC_CMAX];
-  __shared__ double part[FW][64];
+  __shared__ double part[FW][FAC_CMAX];
   __shared__ double sw[FAC_CMAX];
-  __shared__ double sc[3];
+  __shared__ double sc[4];
   const PanelDesc d = descs[blockIdx.x];
   const int m = d.rows, n = d.cols;
   const int lds = (m & 1) ? m : m + 1;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int idx = tid; idx < m * n; idx += FT) {
     const int i = idx % m, j = idx / m;
-    sA[i + j * lds] = d.A[i + (int64_t)j * d.ld];
+    sA[i + j * lds] = d.trans ? d.A[j + (int64_t)i * d.ld] : d.A[i + (int64_t)j * d.ld];
   }
+  if (tid == 0) { sc[0] = 0.0; sc[1] = 0.0; sc[2] = 0.0; sc[3] = -1.0; }
   __syncthreads();
   const int h = min(m, n);
   for (int j = 0; j < h; ++j) {
-    if (wave == 0) {
-      double s = 0.0;
-      for (int i = j + 1 + lane; i < m; i += 64) {
-        const double v = sA[i + j * lds];
-        s += v * v;
-      }
-      s = wave_sum(s);
-      if (lane == 0) {
-        const double alpha = sA[j + j * lds];
-        if (s == 0.0) {
-          sc[0] = alpha; sc[1] = 0.0; sc[2] = 0.0;
-        } else {
-          const double beta = -copysign(sqrt(alpha * alpha + s), alpha);
-          sc[0] = beta;
-          sc[1] = (beta - alpha) / beta;
-          sc[2] = 1.0 / (alpha - beta);
-        }
-      }
+    // deferred scaling of the previous reflector column
+    const int jp = (int)sc[3];
+    if (jp >= 0) {
+      const double scl = sc[2], bet = sc[0];
+      if (sc[1] != 0.0)
+        for (int i = jp + 1 + tid; i < m; i += FT) sA[i + jp * lds] *= scl;
+      if (tid == 0) sA[jp + jp * lds] = bet;
     }
-    __syncthreads();
-    const double beta = sc[0], tau = sc[1], scl = sc[2];
-    if (tau != 0.0)
-      for (int i = j + 1 + tid; i < m; i += FT) sA[i + j * lds] *= scl;
-    __syncthreads();
-    if (tid == 0) sA[j + j * lds] = beta;
-    if (tau != 0.0 && j + 1 < n) {
-      const int rows = m - j;
-      const int q = (rows + FW - 1) / FW;
-      const int ib = j + wave * q, ie = min(m, ib + q);
-      for (int kb = j + 1; kb < n; kb += 64) {
-        const int k = kb + lane;
+    // partial inner products of column j with columns j..n-1 over this wave's rows
+    const int rows = m - j;
+    const int q = (rows + FW - 1) / FW;
+    const int ib = j + wave * q, ie = min(m, ib + q);
+    for (int kb = 0; kb < n - j; kb += 64) {
+      const int kk = kb + lane;
+      if (kk < n - j) {
+        const int k = j + kk;
         double s = 0.0;
-        if (k < n)
-          for (int i = ib; i < ie; ++i) {
-            const double v = (i == j) ? 1.0 : sA[i + j * lds];
-            s += v * sA[i + k * lds];
-          }
-        part[wave][lane] = s;
-        __syncthreads();
-        if (wave == 0 && k < n) {
-          double t = 0.0;
-#pragma unroll
-          for (int w = 0; w < FW; ++w) t += part[w][lane];
-          sw[k] = t;
-        }
-        __syncthreads();
-      }
-      const int nk = n - j - 1;
-      for (int idx = tid; idx < rows * nk; idx += FT) {
-        const int i = j + idx % rows, k = j + 1 + idx / rows;
-        const double v = (i == j) ? 1.0 : sA[i + j * lds];
-        sA[i + k * lds] -= tau * v * sw[k];
+        for (int i = ib; i < ie; ++i)
+          if (!(kk == 0 && i == j)) s += sA[i + j * lds] * sA[i + k * lds];
+        part[wave][kk] = s;
       }
     }
-    if (tid == 0) d.tau[j] = tau;
+    __syncthreads();
+    // combine: reflector scalars and w_k = v^T A(j:, k)
+    {
+      const double x0 = sA[j + j * lds];
+      double sig = 0.0;
+#pragma unroll
+      for (int w = 0; w < FW; ++w) sig += part[w][0];
+      double beta = x0, tau = 0.0, scl = 0.0;
+      if (sig != 0.0) {
+        beta = -copysign(sqrt(fma(x0, x0, sig)), x0);
+        tau = (beta - x0) / beta;
+        scl = 1.0 / (x0 - beta);
+      }
+      for (int kk = 1 + tid; kk < n - j; kk += FT) {
+        const int k = j + kk;
+        double g = 0.0;
+#pragma unroll
+        for (int w = 0; w < FW; ++w) g += part[w][kk];
+        sw[k] = (g - beta * sA[j + k * lds]) * scl;
+      }
+      if (tid == 0) {
+        sc[0] = beta; sc[1] = tau; sc[2] = scl; sc[3] = (double)j;
+        d.tau[j] = tau;
+      }
+    }
+    __syncthreads();
+    const double tau = sc[1], scl = sc[2];
+    if (tau != 0.0) {
+      // lanes walk the rows (j + lane + 64 t), waves the columns (j + 1 + wave + 16 u)
+      double vr[FAC_PMAX / 64];
+#pragma unroll
+      for (int t = 0; t < FAC_PMAX / 64; ++t) {
+        const int i = j + lane + 64 * t;
+        vr[t] = i < m ? (i == j ? 1.0 : sA[i + j * lds] * scl) : 0.0;
+      }
+      for (int k = j + 1 + wave; k < n; k += FW) {
+        const double tw = tau * sw[k];
+#pragma unroll
+        for (int t = 0; t < FAC_PMAX / 64; ++t) {
+          const int i = j + lane + 64 * t;
+          if (i < m) sA[i + k * lds] -= tw * vr[t];
+        }
+      }
+    }
     __syncthreads();
   }
+  if (h > 0) {
+    const int jp = h - 1;
+    const double scl = sc[2], bet = sc[0];
+    if (sc[1] != 0.0)
+      for (int i = jp + 1 + tid; i < m; i += FT) sA[i + jp * lds] *= scl;
+    if (tid == 0) sA[jp + jp * lds] = bet;
+  }
+  __syncthreads();
   for (int idx = tid; idx < m * n; idx += FT) {
     const int i = idx % m, j = idx / m;
     d.A[i + (int64_t)j * d.ld] = sA[i + j * lds];
@@ -112,11 +138,12 @@ void launch_panel_qr(const PanelDesc* d, int n, hipStream_t s) {
   KCHK();
 }
 
-// Cout = H_0 H_1 ... H_{h-1} [Cin; 0]
+// Cout = H_0 H_1 ... H_{h-1} [Cin; 0].  The next reflector is prefetched from
+// global memory into registers while the current one is applied.
 constexpr int APQ_NMAX = HM_MAX_SAMPLES;
 __global__ __launch_bounds__(FT) void k_apply_q(const PanelDesc* descs) {
   __shared__ double sO[FAC_LDMAX * APQ_NMAX];
-  __shared__ double sv[FAC_PMAX];
+  __shared__ double sv[2][FAC_PMAX];
   __shared__ double part[FW][64];
   __shared__ double sw[64];
   const PanelDesc d = descs[blockIdx.x];
@@ -127,30 +154,48 @@ __global__ __launch_bounds__(FT) void k_apply_q(const PanelDesc* descs) {
     const int i = idx % m, c = idx / m;
     sO[i + c * ldo] = (i < h) ? d.Cin[i + (int64_t)c * d.ldCin] : 0.0;
   }
+  auto vload = [&](int j) -> double {
+    if (j < 0 || tid >= m || tid < j) return 0.0;
+    return tid == j ? 1.0 : d.A[tid + (int64_t)j * d.ld];
+  };
+  if (h > 0 && tid < m) sv[0][tid] = vload(h - 1);
   __syncthreads();
+  int buf = 0;
   for (int j = h - 1; j >= 0; --j) {
+    const double vnext = vload(j - 1);
     const double tau = d.tau[j];
-    if (tau == 0.0) continue;
-    for (int i = j + tid; i < m; i += FT) sv[i] = (i == j) ? 1.0 : d.A[i + (int64_t)j * d.ld];
-    __syncthreads();
-    const int rows = m - j, q = (rows + FW - 1) / FW;
-    const int ib = j + wave * q, ie = min(m, ib + q);
-    double s = 0.0;
-    if (lane < nc)
-      for (int i = ib; i < ie; ++i) s += sv[i] * sO[i + lane * ldo];
-    part[wave][lane] = s;
-    __syncthreads();
-    if (wave == 0) {
-      double t = 0.0;
+    if (tau != 0.0) {
+      const int rows = m - j, q = (rows + FW - 1) / FW;
+      const int ib = j + wave * q, ie = min(m, ib + q);
+      double s = 0.0;
+      if (lane < nc)
+        for (int i = ib; i < ie; ++i) s += sv[buf][i] * sO[i + lane * ldo];
+      part[wave][lane] = s;
+      __syncthreads();
+      if (wave == 0) {
+        double t = 0.0;
 #pragma unroll
-      for (int w = 0; w < FW; ++w) t += part[w][lane];
-      sw[lane] = t;
+        for (int w = 0; w < FW; ++w) t += part[w][lane];
+        sw[lane] = t;
+      }
+      __syncthreads();
+      double vr[FAC_PMAX / 64];
+#pragma unroll
+      for (int t = 0; t < FAC_PMAX / 64; ++t) {
+        const int i = j + lane + 64 * t;
+        vr[t] = i < m ? sv[buf][i] : 0.0;
+      }
+      for (int cc = wave; cc < nc; cc += FW) {
+        const double tw = tau * sw[cc];
+#pragma unroll
+        for (int t = 0; t < FAC_PMAX / 64; ++t) {
+          const int i = j + lane + 64 * t;
+          if (i < m) sO[i + cc * ldo] -= tw * vr[t];
+        }
+      }
     }
-    __syncthreads();
-    for (int idx = tid; idx < rows * nc; idx += FT) {
-      const int i = j + idx % rows, c = idx / rows;
-      sO[i + c * ldo] -= tau * sv[i] * sw[c];
-    }
+    if (tid < m) sv[buf ^ 1][tid] = vnext;
+    buf ^= 1;
     __syncthreads();
   }
   for (int idx = tid; idx < m * nc; idx += FT) {
@@ -166,15 +211,37 @@ void launch_apply_q(const PanelDesc* d, int n, hipStream_t s) {
 }
 
 // ------------------------------------------------------------ Jacobi SVD --
-// One-sided (Hestenes) Jacobi on the columns of R: R Z = W diag(s).  Pairs
+// One-sided (Hestenes) Jacobi on the columns of an h x c matrix T (T = R, or
+// T = R^T when the descriptor asks for the transpose): T Z = W diag(s).  Pairs
 // follow a round-robin tournament; each 16-lane group rotates one pair, so a
-// 1024-thread workgroup treats every pair of a round (c <= 96) at once.
+// 1024-thread workgroup treats every pair of a round (c <= 96) at once.  The
+// pair's two squared norms and inner product are reduced across the group by
+// DPP row operations (no LDS round trip), which leaves the same sum in every
+// lane.
 constexpr int JAC_LD = FAC_CMAX + 1;
 constexpr int JAC_GROUPS = FT / 16;
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+// sum over the 16 lanes of a row: lane pairs (xor 1, xor 2 by quad permutes),
+// then the mirrored quad of each half-row, then the mirrored half-row
+__device__ __forceinline__ double sum16(double v) {
+  v += dpp_d<0xB1>(v);
+  v += dpp_d<0x4E>(v);
+  v += dpp_d<0x141>(v);
+  v += dpp_d<0x140>(v);
+  return v;
+}
+
 __global__ __launch_bounds__(FT) void k_jacobi(const SvdDesc* descs) {
   __shared__ double sA[FAC_CMAX * JAC_LD];
   __shared__ double sZ[FAC_CMAX * JAC_LD];
   __shared__ double snorm[FAC_CMAX];
+  __shared__ int srank[FAC_CMAX];
   __shared__ int flag;
   const SvdDesc d = descs[blockIdx.x];
   const int h = d.h, c = d.c;
@@ -183,7 +250,7 @@ __global__ __launch_bounds__(FT) void k_jacobi(const SvdDesc* descs) {
   const int grp = tid >> 4, gl = tid & 15;
   for (int idx = tid; idx < h * c; idx += FT) {
     const int i = idx % h, j = idx / h;
-    sA[i + j * JAC_LD] = d.R[i + (int64_t)j * d.ldR];
+    sA[i + j * JAC_LD] = d.trans ? d.R[j + (int64_t)i * d.ldR] : d.R[i + (int64_t)j * d.ldR];
   }
   if (wantX)
     for (int idx = tid; idx < c * c; idx += FT) {
@@ -207,20 +274,20 @@ __global__ __launch_bounds__(FT) void k_jacobi(const SvdDesc* descs) {
         double al = 0.0, be = 0.0, ga = 0.0;
         for (int i = gl; i < h; i += 16) {
           const double x = sA[i + p * JAC_LD], y = sA[i + q * JAC_LD];
-          al += x * x; be += y * y; ga += x * y;
+          al = fma(x, x, al);
+          be = fma(y, y, be);
+          ga = fma(x, y, ga);
         }
-#pragma unroll
-        for (int o = 8; o >= 1; o >>= 1) {
-          al += __shfl_xor(al, o, 16);
-          be += __shfl_xor(be, o, 16);
-          ga += __shfl_xor(ga, o, 16);
-        }
+        al = sum16(al);
+        be = sum16(be);
+        ga = sum16(ga);
         if (ga != 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
-          const double zeta = (be - al) / (2.0 * ga);
-          double tt;
-          if (fabs(zeta) > 1e150) tt = 0.5 / zeta;
-          else tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+          // rotation zeroing the pair's inner product: t = tan(theta) is the
+          // smaller root of t^2 ga + t (be - al) - ga = 0
+          const double dd = be - al;
+          const double tt = 2.0 * ga * (dd >= 0.0 ? 1.0 : -1.0) /
+                            (fabs(dd) + sqrt(fma(dd, dd, 4.0 * ga * ga)));
+          const double cs = rsqrt(fma(tt, tt, 1.0)), sn = cs * tt;
           for (int i = gl; i < h; i += 16) {
             const double x = sA[i + p * JAC_LD], y = sA[i + q * JAC_LD];
             sA[i + p * JAC_LD] = cs * x - sn * y;
@@ -238,7 +305,7 @@ __global__ __launch_bounds__(FT) void k_jacobi(const SvdDesc* descs) {
       __syncthreads();
     }
     if (flag == 0) break;
-    __syncthreads();
+    __syncthreads();  // every thread has read flag before it is reset
   }
   if (tid == 0 && d.sweeps) atomicMax(d.sweeps, sweep + 1);
   for (int j = tid; j < c; j += FT) {
@@ -247,7 +314,6 @@ __global__ __launch_bounds__(FT) void k_jacobi(const SvdDesc* descs) {
     snorm[j] = sqrt(s);
   }
   __syncthreads();
-  __shared__ int srank[FAC_CMAX];
   for (int j = tid; j < c; j += FT) {
     const double sj = snorm[j];
     int rk = 0;
@@ -255,7 +321,8 @@ __global__ __launch_bounds__(FT) void k_jacobi(const SvdDesc* descs) {
     srank[j] = rk;
   }
   __syncthreads();
-  // column j goes to position srank[j] (descending norms, ties by index)
+  // column j goes to position srank[j] (descending norms, ties by index);
+  // positions c .. kout - 1 (a matrix with fewer columns than asked) are zero
   const int rows = max(h, c);
   for (int e = tid; e < c * rows; e += FT) {
     const int i = e % rows, j = e / rows;
@@ -265,6 +332,12 @@ __global__ __launch_bounds__(FT) void k_jacobi(const SvdDesc* descs) {
     if (i == 0) d.sv[rk] = sj;
     if (i < h) d.W[i + (int64_t)rk * d.ldW] = sj > 0.0 ? sA[i + j * JAC_LD] / sj : 0.0;
     if (wantX && i < c) d.X[i + (int64_t)rk * d.ldX] = sZ[i + j * JAC_LD];
+  }
+  for (int e = tid; e < (d.kout - c) * rows; e += FT) {
+    const int i = e % rows, rk = c + e / rows;
+    if (i == 0) d.sv[rk] = 0.0;
+    if (i < h) d.W[i + (int64_t)rk * d.ldW] = 0.0;
+    if (wantX && i < c) d.X[i + (int64_t)rk * d.ldX] = 0.0;
   }
 }
 
@@ -448,7 +521,7 @@ __global__ __launch_bounds__(256) void k_cpqr_id(const Node* nodes, const Instan
   }
   if (tid == 0) {
     rank[g] = k;
-    if (in.tol > 0.0 && k > in.r - in.p && saturated) atomicAdd(saturated, 1);
+    if (in.tol > 0.0 && k >= in.r - in.p && saturated) atomicAdd(saturated, 1);
   }
 }
 
@@ -568,7 +641,7 @@ __global__ void k_truncate(const Node* nodes, const Instance* inst, const int32_
     if (threadIdx.x == 0) {
       for (int j = k; j < R; ++j) sv[(int64_t)v * R + j] = 0.0;
       rank[v] = k;
-      if (in.tol > 0.0 && k > in.r - in.p && saturated) atomicAdd(saturated, 1);
+      if (in.tol > 0.0 && k >= in.r - in.p && saturated) atomicAdd(saturated, 1);
     }
   }
 }

@@ -145,6 +145,11 @@ void node_svd(const std::vector<SvdJob>& jobs, double* M, int64_t ldm, double* U
   const size_t rfin_off = al.take((size_t)nj * FAC_CMAX * FAC_CMAX * sizeof(double));
   const size_t w_off = al.take((size_t)nj * FAC_CMAX * R * sizeof(double));
   const size_t eye_off = al.take((size_t)FAC_CMAX * R * sizeof(double));
+  // preconditioning QR of R^T per job: reflectors overwrite Rfin, R2 and tau2
+  // hold its triangle and scalars, Z the Jacobi right vectors
+  const size_t r2_off = al.take((size_t)nj * FAC_CMAX * FAC_CMAX * sizeof(double));
+  const size_t tau2_off = al.take((size_t)nj * FAC_CMAX * sizeof(double));
+  const size_t z_off = al.take((size_t)nj * FAC_CMAX * R * sizeof(double));
   ws.ensure(al.off, s);
   char* base = ws.base();
   auto S = [&](int st) { return reinterpret_cast<double*>(base + s_off[st]); };
@@ -153,10 +158,14 @@ void node_svd(const std::vector<SvdJob>& jobs, double* M, int64_t ldm, double* U
   double* Rfin = reinterpret_cast<double*>(base + rfin_off);
   double* W = reinterpret_cast<double*>(base + w_off);
   double* EYE = reinterpret_cast<double*>(base + eye_off);
+  double* R2 = reinterpret_cast<double*>(base + r2_off);
+  double* TAU2 = reinterpret_cast<double*>(base + tau2_off);
+  double* Z = reinterpret_cast<double*>(base + z_off);
   // ---- descriptors ---------------------------------------------------------
   std::vector<std::vector<PanelDesc>> pd(nst);
   std::vector<int64_t> tcount(nst, 0);
   std::vector<SvdDesc> sd;
+  std::vector<PanelDesc> pre;
   for (int q = 0; q < nj; ++q) {
     const SvdJob& jb = jobs[q];
     int64_t rrow_next = 0;  // row inside next stage buffer
@@ -185,12 +194,26 @@ void node_svd(const std::vector<SvdJob>& jobs, double* M, int64_t ldm, double* U
           d.Cin = qr_only ? EYE : W + (int64_t)q * FAC_CMAX * R;
           d.ldCin = FAC_CMAX;
           if (!qr_only) {
+            // R = R2^T Q2^T with R^T = Q2 R2; Jacobi on R2^T (h x h) gives
+            // R2^T Z = W S, so R = W S (Q2 Z)^T: W is the left factor, the
+            // right factor Q2 [Z; 0] comes from the reflectors of the
+            // preconditioning QR
+            double* r2 = R2 + (int64_t)q * FAC_CMAX * FAC_CMAX;
+            double* zq = Z + (int64_t)q * FAC_CMAX * R;
+            PanelDesc t{};
+            t.A = d.Rout; t.ld = FAC_CMAX; t.rows = jb.cols; t.cols = h; t.trans = 1;
+            t.tau = TAU2 + (int64_t)q * FAC_CMAX;
+            t.Rout = r2; t.ldR = FAC_CMAX;
+            t.Cin = zq; t.ldCin = FAC_CMAX;
+            t.Cout = X ? X + (int64_t)jb.node * 2 * R * R : nullptr; t.ldCout = 2 * R;
+            t.ncol = jb.kout;
+            pre.push_back(t);
             SvdDesc v{};
-            v.R = d.Rout; v.ldR = FAC_CMAX; v.h = h; v.c = jb.cols;
+            v.R = r2; v.ldR = FAC_CMAX; v.h = h; v.c = h; v.trans = 1;
             v.W = W + (int64_t)q * FAC_CMAX * R; v.ldW = FAC_CMAX;
             v.sv = sv + (int64_t)jb.node * R;
-            v.X = X ? X + (int64_t)jb.node * 2 * R * R : nullptr;
-            v.ldX = 2 * R;
+            v.X = X ? zq : nullptr;
+            v.ldX = FAC_CMAX;
             v.kout = jb.kout;
             v.sweeps = sweeps;
             sd.push_back(v);
@@ -217,8 +240,11 @@ void node_svd(const std::vector<SvdJob>& jobs, double* M, int64_t ldm, double* U
   for (int st = 0; st < nst; ++st) dpd[st] = kp.put(pd[st], s);
   for (int st = 0; st < nst; ++st) launch_panel_qr(dpd[st], (int)pd[st].size(), s);
   if (!qr_only) {
+    PanelDesc* dpre = kp.put(pre, s);
+    launch_panel_qr(dpre, (int)pre.size(), s);
     SvdDesc* dsd = kp.put(sd, s);
     launch_jacobi_svd(dsd, (int)sd.size(), s);
+    if (X) launch_apply_q(dpre, (int)pre.size(), s);
   }
   for (int st = nst - 1; st >= 0; --st) launch_apply_q(dpd[st], (int)pd[st].size(), s);
 }

@@ -19,8 +19,16 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
-constexpr int SMP_RT = 2;             // 16-row tiles per wave
-constexpr int SMP_ROWS = 4 * 16 * SMP_RT;  // rows per block (4 waves)
+constexpr int SMP_RT = 1;             // 16-row tiles per wave
+// Waves per block: the BF16 form needs ~80 VGPRs, so 8 waves (2 per SIMD)
+// fit; the FP32 form keeps FP32 and FP64 accumulators (~300 registers with
+// the AGPRs) and the FP64 form ~130, so they run 4 waves, one per SIMD.
+template <int MODE>
+struct SmpShape {
+  static constexpr int WAVES = MODE == 2 ? 8 : 4;
+  static constexpr int THREADS = 64 * WAVES;
+  static constexpr int ROWS = WAVES * 16 * SMP_RT;  // rows per block
+};
 constexpr int SMP_CT = SMP_MAXC / 16; // column tiles
 
 template <int MODE> struct ModeT;
@@ -97,18 +105,20 @@ __device__ __forceinline__ float entry_f32c(float xi, float yi, float xj, float 
 constexpr int SMP_FLUSH = 32;
 
 // SRC: 0 log kernel, 1 near-singular kernel, 2 dense matrix, 3 its transpose (F64 only).
-// One block = 4 waves x SMP_RT 16-row tiles; the whole X is streamed through
+// One block = SmpShape<MODE>::WAVES waves x SMP_RT 16-row tiles; the whole X is streamed through
 // LDS in K-tiles, double-buffered, the next tile prefetched into registers
 // while the current one feeds the MFMAs.
 template <int MODE, int SRC>
-__global__ __launch_bounds__(256) void k_sampler(int64_t n, int c, int cp, const double* pts,
+__global__ __launch_bounds__(SmpShape<MODE>::THREADS) void k_sampler(int64_t n, int c, int cp, const double* pts,
                                                  double kp, const double* Ad, int64_t lda,
                                                  const typename ModeT<MODE>::T* Xp,
                                                  const uint32_t* mask, double* Y, int64_t ldy) {
   typedef typename ModeT<MODE>::T T;
   constexpr int BK = ModeT<MODE>::BK;
+  constexpr int SMP_THREADS = SmpShape<MODE>::THREADS;
+  constexpr int SMP_ROWS = SmpShape<MODE>::ROWS;
   constexpr int TILE_BYTES = BK * SMP_MAXC * (int)sizeof(T);
-  constexpr int NV = (TILE_BYTES + 256 * 16 - 1) / (256 * 16);   // uint4 per thread
+  constexpr int NV = (TILE_BYTES + SMP_THREADS * 16 - 1) / (SMP_THREADS * 16);  // uint4 per thread
   __shared__ __attribute__((aligned(16))) T sX[2][BK * SMP_MAXC + 16];
   __shared__ double sP[2][2 * BK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -147,7 +157,7 @@ __global__ __launch_bounds__(256) void k_sampler(int64_t n, int c, int cp, const
     const uint4* src = reinterpret_cast<const uint4*>(Xp + kt * (int64_t)BK * cp);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const int e = tid + v * 256;
+      const int e = tid + v * SMP_THREADS;
       if (e < tile_u4) pre[v] = src[e];
     }
     if (SRC < 2 && tid < 2 * BK) {
@@ -159,7 +169,7 @@ __global__ __launch_bounds__(256) void k_sampler(int64_t n, int c, int cp, const
     uint4* dst = reinterpret_cast<uint4*>(sX[buf]);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const int e = tid + v * 256;
+      const int e = tid + v * SMP_THREADS;
       if (e < tile_u4) dst[e] = pre[v];
     }
     if (SRC < 2 && tid < 2 * BK) sP[buf][tid] = pp;
@@ -286,8 +296,9 @@ static void run_sampler(int64_t n, int c, const double* pts, double kp, const do
   hipLaunchKernelGGL(k_pack<MODE>, dim3((unsigned)nkt), dim3(256), 0, s, n, c, cp, X, ldx, Xp,
                      mask);
   KCHK();
-  hipLaunchKernelGGL((k_sampler<MODE, SRC>), dim3((unsigned)((n + SMP_ROWS - 1) / SMP_ROWS)),
-                     dim3(256), 0, s, n, c, cp, pts, kp, Ad, lda, Xp, mask, Y, ldy);
+  constexpr int rows = SmpShape<MODE>::ROWS;
+  hipLaunchKernelGGL((k_sampler<MODE, SRC>), dim3((unsigned)((n + rows - 1) / rows)),
+                     dim3(SmpShape<MODE>::THREADS), 0, s, n, c, cp, pts, kp, Ad, lda, Xp, mask, Y, ldy);
   KCHK();
 }
 

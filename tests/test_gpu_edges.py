@@ -1,0 +1,102 @@
+"""Edge cases and failure handling of the HIP path, through the C ABI.
+
+* degenerate trees: N <= leaf (L = 0: only D), one level, ragged N;
+* a user callback operator (the paper's black box) gives the same result as
+  the built-in dense operator;
+* a failing callback -> HM_ERR_CALLBACK, NaN samples -> HM_ERR_NONFINITE,
+  an operator of rank > r in tolerance mode -> HM_WARN_RANK_SATURATED
+  (Sec. 2.5: the sample may have missed part of the block);
+* the error estimate E of Sec. 5 on the GPU result stays at the tolerance.
+All error conditions are produced on the host side of the operator (values or
+return codes), never by a faulting kernel.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import hbs as ohbs
+from oracle import metrics as ometrics
+from oracle import operators as oops
+
+pytestmark = pytest.mark.gpu
+hm = pytest.importorskip("paper_1503_07152_amd")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("n,leaf", [(100, 128), (128, 128), (200, 128), (1000, 64), (1023, 64)])
+def test_degenerate_and_ragged_trees(n, leaf):
+    print(f"tree n={n} leaf={leaf}", flush=True)
+    k, p = 6, 6
+    g = W.synthetic_hbs(n, leaf, k, seed=2) if n > leaf else None
+    A = ohbs.from_generators(g).dense() if g else W.gaussian((n, n), seed=3)
+    h = hm.hbs_compress(hm.Options(n, leaf, k, p, seed=4), hm.DenseOperator(A))
+    ho, _, _ = ohbs.compress(oops.DenseOp(A), n, leaf, k + p, 4, rank=k)
+    x = W.gaussian((n, 3), seed=5)
+    y = h.apply(torch.from_numpy(x)).cpu().numpy()
+    assert rel(y, A @ x) < 1e-12 and rel(y, ho.apply(x)) < 1e-12
+    ya = h.apply(torch.from_numpy(x), adjoint=True).cpu().numpy()
+    assert rel(ya, A.T @ x) < 1e-12
+
+
+def test_callback_operator_matches_builtin():
+    n, leaf, k, p = 1024, 64, 10, 8
+    g = W.synthetic_hbs(n, leaf, k, seed=6)
+    A = ohbs.from_generators(g).dense()
+    At = torch.from_numpy(A).cuda()
+    calls = []
+
+    def matvec(adjoint, X, Y):
+        calls.append(X.shape[1])
+        Y.copy_((At.t() if adjoint else At) @ X)
+
+    h1 = hm.hbs_compress(hm.Options(n, leaf, k, p, seed=9), hm.CallbackOperator(matvec))
+    h2 = hm.hbs_compress(hm.Options(n, leaf, k, p, seed=9), hm.DenseOperator(A))
+    x = W.gaussian((n, 3), seed=7)
+    y1 = h1.apply(torch.from_numpy(x)).cpu().numpy()
+    y2 = h2.apply(torch.from_numpy(x)).cpu().numpy()
+    assert rel(y1, A @ x) < 1e-12 and rel(y1, y2) < 1e-12
+    L = h1.info()["levels"]
+    assert len(calls) == 2 * L + 1 and sum(calls) == h1.info()["sample_columns"]
+
+
+def test_failing_callback_reports_error():
+    def bad(adjoint, X, Y):
+        return 7
+    with pytest.raises(hm.HMError) as e:
+        hm.hbs_compress(hm.Options(512, 64, 8, 4, seed=1), hm.CallbackOperator(bad))
+    assert e.value.code == -4
+
+
+def test_nonfinite_samples_report_error():
+    A = W.gaussian((512, 512), seed=1)
+    A[10, 400] = np.nan
+    with pytest.raises(hm.HMError) as e:
+        hm.hbs_compress(hm.Options(512, 64, 8, 4, seed=1), hm.DenseOperator(A))
+    assert e.value.code == -5
+
+
+def test_rank_saturation_warning():
+    # a dense Gaussian matrix has full-rank off-diagonal blocks: at tol 1e-12
+    # every block's revealed rank reaches the cap r - p
+    n = 512
+    A = W.gaussian((n, n), seed=2)
+    h = hm.hbs_compress(hm.Options(n, 64, 12, 4, tol=1e-12, seed=3), hm.DenseOperator(A))
+    assert h.status == hm.HM_WARN_RANK_SATURATED
+    assert h.info()["saturated"] > 0
+    hd = hm.hodlr_compress(hm.Options(n, 64, 12, 4, tol=1e-12, seed=3), hm.DenseOperator(A))
+    assert hd.status == hm.HM_WARN_RANK_SATURATED
+
+
+def test_error_estimate_E_at_tolerance():
+    n, leaf, k, p, tol = 2048, 64, 40, 8, 1e-9
+    P = W.ellipse_points(n)
+    K = oops.KernelOp(P, "log")
+    h = hm.hbs_compress(hm.Options(n, leaf, k, p, tol=tol, seed=5),
+                        hm.KernelOperator(P, "log", 0.0, hm.HM_F64))
+    E = ometrics.estimate_E(K.apply, lambda w: h.apply(torch.from_numpy(w)).cpu().numpy(), n)
+    print(f"E = {E:.2e} (tol {tol}), ranks {h.info()['min_rank']}..{h.info()['max_rank']}")
+    assert E < 10 * tol
