@@ -46,6 +46,26 @@ PEAK_ALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # BF16 conversion (1/2): 14.5 slots
 SLOTS_PER_ENTRY = 14.5
 
+# HBM bytes of one BF16 operator apply (k_pack + k_sampler, N = 65536, 96
+# columns) from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE in KiB per
+# dispatch, summed over the two kernels), scaled by what the same counters
+# read for a plain 256 MiB device copy (FETCH_SIZE reads 0.5x the bytes moved,
+# WRITE_SIZE 1.0x).  Valid only for the sampler source they were taken on
+# (SHA-1 below); otherwise the traffic is unknown.
+SAMPLER_TRAFFIC = {"sha1": "aa6b4f2add16761414948d99627ffdd81b92c7a2",
+                   "fetch_kib": 87525.2 + 24590.5, "write_kib": 50142.6 + 12352.0,
+                   "fetch_scale": 2.0, "write_scale": 1.0}
+
+
+def sampler_traffic_bytes():
+    import hashlib
+    src = os.path.join(ROOT, "paper_1503_07152_amd", "csrc", "sampler.hip")
+    with open(src, "rb") as f:
+        if hashlib.sha1(f.read()).hexdigest() != SAMPLER_TRAFFIC["sha1"]:
+            return None
+    t = SAMPLER_TRAFFIC
+    return int((t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024)
+
 
 def levels(n, leaf):
     return 0 if n <= leaf else int(math.ceil(math.log2(n / leaf)))
@@ -221,7 +241,7 @@ def extra_measurements(hm, W, torch, pts, n, h_bf16, ms_bf16):
     achieved = entries * SLOTS_PER_ENTRY / t_launch / 1e12
     res["roofline"] = {"bound": "alu", "achieved": round(achieved, 2), "peak": round(PEAK_ALU_TOPS, 1),
                        "unit": "Tslot/s", "frac": round(achieved / PEAK_ALU_TOPS, 3),
-                       "traffic": None,
+                       "traffic": sampler_traffic_bytes() if n == N else None,
                        "kernel": "k_sampler<BF16, near> (+ k_pack)",
                        "launch_ms": round(t_launch * 1e3, 3),
                        "mfma_frac": round(2 * n * (n * c / 2) / t_launch / 1e12 /

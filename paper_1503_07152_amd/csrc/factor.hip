@@ -13,12 +13,27 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+constexpr int FT = 1024;
+constexpr int FW = FT / 64;
+
+// Sum of the FW per-wave partials p[0], p[S], p[2 S], ... as a balanced tree
+// (short dependency chain).
+template <int S>
+__device__ __forceinline__ double sum_waves(const double* p) {
+  double v[FW];
+#pragma unroll
+  for (int w = 0; w < FW; ++w) v[w] = p[w * S];
+#pragma unroll
+  for (int h = FW / 2; h >= 1; h >>= 1)
+#pragma unroll
+    for (int w = 0; w < h; ++w) v[w] += v[w + h];
+  return v[0];
+}
+
 // ------------------------------------------------------------ panel QR ----
 // The node factorisations keep a whole panel in LDS (up to ~150 KB), so only
 // one workgroup fits on a CU; 1024 threads (4 waves per SIMD) hide the LDS
 // and FP64 latencies within that workgroup.
-constexpr int FT = 1024;
-constexpr int FW = FT / 64;
 
 // Unblocked Householder QR (H_j = I - tau_j v_j v_j^T, v_j(j) = 1) of one
 // panel held in LDS.  Reflectors are stored below the diagonal, R on and above.
@@ -53,27 +68,41 @@ __global__ __launch_bounds__(FT) void k_panel_qr(const PanelDesc* descs) {
         for (int i = jp + 1 + tid; i < m; i += FT) sA[i + jp * lds] *= scl;
       if (tid == 0) sA[jp + jp * lds] = bet;
     }
-    // partial inner products of column j with columns j..n-1 over this wave's rows
+    // partial inner products of column j with columns j..n-1 over this wave's
+    // rows; fixed trip counts (rows outside the panel weigh zero, their reads
+    // are clamped into it) so the LDS reads issue back to back
     const int rows = m - j;
     const int q = (rows + FW - 1) / FW;
     const int ib = j + wave * q, ie = min(m, ib + q);
+    double cj[FAC_PMAX / FW];
+#pragma unroll
+    for (int t = 0; t < FAC_PMAX / FW; ++t) {
+      const int i = ib + t;
+      cj[t] = i < ie ? sA[i + j * lds] : 0.0;
+    }
     for (int kb = 0; kb < n - j; kb += 64) {
       const int kk = kb + lane;
-      if (kk < n - j) {
-        const int k = j + kk;
-        double s = 0.0;
-        for (int i = ib; i < ie; ++i)
-          if (!(kk == 0 && i == j)) s += sA[i + j * lds] * sA[i + k * lds];
-        part[wave][kk] = s;
+      const int k = j + min(kk, n - j - 1);
+      double bv[FAC_PMAX / FW];
+#pragma unroll
+      for (int t = 0; t < FAC_PMAX / FW; ++t) bv[t] = sA[min(ib + t, m - 1) + k * lds];
+      // the diagonal term is left out of the norm below the diagonal (k = j)
+      double s0 = ((wave == 0 && kk == 0) ? 0.0 : cj[0]) * bv[0], s1 = cj[1] * bv[1],
+             s2 = cj[2] * bv[2], s3 = cj[3] * bv[3];
+#pragma unroll
+      for (int t = 4; t < FAC_PMAX / FW; t += 4) {
+        s0 = fma(cj[t], bv[t], s0);
+        s1 = fma(cj[t + 1], bv[t + 1], s1);
+        s2 = fma(cj[t + 2], bv[t + 2], s2);
+        s3 = fma(cj[t + 3], bv[t + 3], s3);
       }
+      if (kk < n - j) part[wave][kk] = (s0 + s1) + (s2 + s3);
     }
     __syncthreads();
     // combine: reflector scalars and w_k = v^T A(j:, k)
     {
       const double x0 = sA[j + j * lds];
-      double sig = 0.0;
-#pragma unroll
-      for (int w = 0; w < FW; ++w) sig += part[w][0];
+      const double sig = sum_waves<FAC_CMAX>(&part[0][0]);
       double beta = x0, tau = 0.0, scl = 0.0;
       if (sig != 0.0) {
         beta = -copysign(sqrt(fma(x0, x0, sig)), x0);
@@ -82,9 +111,7 @@ __global__ __launch_bounds__(FT) void k_panel_qr(const PanelDesc* descs) {
       }
       for (int kk = 1 + tid; kk < n - j; kk += FT) {
         const int k = j + kk;
-        double g = 0.0;
-#pragma unroll
-        for (int w = 0; w < FW; ++w) g += part[w][kk];
+        const double g = sum_waves<FAC_CMAX>(&part[0][kk]);
         sw[k] = (g - beta * sA[j + k * lds]) * scl;
       }
       if (tid == 0) {
@@ -102,12 +129,16 @@ __global__ __launch_bounds__(FT) void k_panel_qr(const PanelDesc* descs) {
         const int i = j + lane + 64 * t;
         vr[t] = i < m ? (i == j ? 1.0 : sA[i + j * lds] * scl) : 0.0;
       }
-      for (int k = j + 1 + wave; k < n; k += FW) {
-        const double tw = tau * sw[k];
 #pragma unroll
-        for (int t = 0; t < FAC_PMAX / 64; ++t) {
-          const int i = j + lane + 64 * t;
-          if (i < m) sA[i + k * lds] -= tw * vr[t];
+      for (int u = 0; u < FAC_CMAX / FW; ++u) {
+        const int k = j + 1 + wave + FW * u;
+        if (k < n) {
+          const double tw = tau * sw[k];
+#pragma unroll
+          for (int t = 0; t < FAC_PMAX / 64; ++t) {
+            const int i = j + lane + 64 * t;
+            if (i < m) sA[i + k * lds] -= tw * vr[t];
+          }
         }
       }
     }
@@ -167,17 +198,25 @@ __global__ __launch_bounds__(FT) void k_apply_q(const PanelDesc* descs) {
     if (tau != 0.0) {
       const int rows = m - j, q = (rows + FW - 1) / FW;
       const int ib = j + wave * q, ie = min(m, ib + q);
-      double s = 0.0;
-      if (lane < nc)
-        for (int i = ib; i < ie; ++i) s += sv[buf][i] * sO[i + lane * ldo];
-      part[wave][lane] = s;
-      __syncthreads();
-      if (wave == 0) {
-        double t = 0.0;
+      const int cl = max(min(lane, nc - 1), 0);
+      double av[FAC_PMAX / FW], bv[FAC_PMAX / FW];
 #pragma unroll
-        for (int w = 0; w < FW; ++w) t += part[w][lane];
-        sw[lane] = t;
+      for (int t = 0; t < FAC_PMAX / FW; ++t) {
+        const int i = ib + t;
+        av[t] = i < ie ? sv[buf][i] : 0.0;
+        bv[t] = sO[min(i, m - 1) + cl * ldo];
       }
+      double s0 = av[0] * bv[0], s1 = av[1] * bv[1], s2 = av[2] * bv[2], s3 = av[3] * bv[3];
+#pragma unroll
+      for (int t = 4; t < FAC_PMAX / FW; t += 4) {
+        s0 = fma(av[t], bv[t], s0);
+        s1 = fma(av[t + 1], bv[t + 1], s1);
+        s2 = fma(av[t + 2], bv[t + 2], s2);
+        s3 = fma(av[t + 3], bv[t + 3], s3);
+      }
+      part[wave][lane] = lane < nc ? (s0 + s1) + (s2 + s3) : 0.0;
+      __syncthreads();
+      if (wave == 0) sw[lane] = sum_waves<64>(&part[0][lane]);
       __syncthreads();
       double vr[FAC_PMAX / 64];
 #pragma unroll
@@ -185,12 +224,16 @@ __global__ __launch_bounds__(FT) void k_apply_q(const PanelDesc* descs) {
         const int i = j + lane + 64 * t;
         vr[t] = i < m ? sv[buf][i] : 0.0;
       }
-      for (int cc = wave; cc < nc; cc += FW) {
-        const double tw = tau * sw[cc];
 #pragma unroll
-        for (int t = 0; t < FAC_PMAX / 64; ++t) {
-          const int i = j + lane + 64 * t;
-          if (i < m) sO[i + cc * ldo] -= tw * vr[t];
+      for (int u = 0; u < (APQ_NMAX + FW - 1) / FW; ++u) {
+        const int cc = wave + FW * u;
+        if (cc < nc) {
+          const double tw = tau * sw[cc];
+#pragma unroll
+          for (int t = 0; t < FAC_PMAX / 64; ++t) {
+            const int i = j + lane + 64 * t;
+            if (i < m) sO[i + cc * ldo] -= tw * vr[t];
+          }
         }
       }
     }
@@ -220,6 +263,7 @@ void launch_apply_q(const PanelDesc* d, int n, hipStream_t s) {
 // lane.
 constexpr int JAC_LD = FAC_CMAX + 1;
 constexpr int JAC_GROUPS = FT / 16;
+constexpr int JAC_RPL = FAC_CMAX / 16;  // rows per lane of a 16-lane group
 
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double v) {
@@ -259,6 +303,7 @@ __global__ __launch_bounds__(FT) void k_jacobi(const SvdDesc* descs) {
     }
   __syncthreads();
   const int n2 = c + (c & 1);
+  const int hm1 = max(h - 1, 0);
   const double tol = (double)max(h, 1) * DBL_EPSILON;
   int sweep = 0;
   for (; sweep < 40; ++sweep) {
@@ -271,12 +316,19 @@ __global__ __launch_bounds__(FT) void k_jacobi(const SvdDesc* descs) {
         const int pb = b == 0 ? 0 : 1 + (b - 1 + t) % (n2 - 1);
         const int p = min(pa, pb), q = max(pa, pb);
         if (q >= c) continue;
+        // the group's rows gl + 16 u (fixed trip count; rows past h weigh zero)
+        double xv[JAC_RPL], yv[JAC_RPL];
         double al = 0.0, be = 0.0, ga = 0.0;
-        for (int i = gl; i < h; i += 16) {
-          const double x = sA[i + p * JAC_LD], y = sA[i + q * JAC_LD];
-          al = fma(x, x, al);
-          be = fma(y, y, be);
-          ga = fma(x, y, ga);
+#pragma unroll
+        for (int u = 0; u < JAC_RPL; ++u) {
+          const int i = gl + 16 * u;
+          const int ic = min(i, hm1);
+          const double w = i < h ? 1.0 : 0.0;
+          xv[u] = w * sA[ic + p * JAC_LD];
+          yv[u] = w * sA[ic + q * JAC_LD];
+          al = fma(xv[u], xv[u], al);
+          be = fma(yv[u], yv[u], be);
+          ga = fma(xv[u], yv[u], ga);
         }
         al = sum16(al);
         be = sum16(be);
@@ -285,20 +337,52 @@ __global__ __launch_bounds__(FT) void k_jacobi(const SvdDesc* descs) {
           // rotation zeroing the pair's inner product: t = tan(theta) is the
           // smaller root of t^2 ga + t (be - al) - ga = 0
           const double dd = be - al;
-          const double tt = 2.0 * ga * (dd >= 0.0 ? 1.0 : -1.0) /
-                            (fabs(dd) + sqrt(fma(dd, dd, 4.0 * ga * ga)));
-          const double cs = rsqrt(fma(tt, tt, 1.0)), sn = cs * tt;
-          for (int i = gl; i < h; i += 16) {
-            const double x = sA[i + p * JAC_LD], y = sA[i + q * JAC_LD];
-            sA[i + p * JAC_LD] = cs * x - sn * y;
-            sA[i + q * JAC_LD] = sn * x + cs * y;
+          const double q2 = fma(dd, dd, 4.0 * ga * ga);
+          double tt, cs;
+          if (q2 > 1e-280 && q2 < 1e280) {
+            // hardware reciprocal (square root) estimates refined by Newton
+            // steps: one for t (its accuracy only sets how far the pair's
+            // inner product drops), two for cs, so that cs^2 + sn^2 = 1 to
+            // rounding without bias and the accumulated rotations stay
+            // orthogonal
+            double r = __builtin_amdgcn_rsq(q2);
+            r = r * fma(-0.5 * q2 * r, r, 1.5);
+            const double den = fabs(dd) + q2 * r;
+            double rd = __builtin_amdgcn_rcp(den);
+            rd = fma(rd, fma(-den, rd, 1.0), rd);
+            tt = 2.0 * ga * (dd >= 0.0 ? 1.0 : -1.0) * rd;
+            const double u1 = fma(tt, tt, 1.0);
+            // residual form e = 1/2 - (u1 cs / 2) cs, cs += cs e: unlike
+            // cs (3/2 - u1 cs^2 / 2) it reaches cs = 1 exactly when u1 = 1
+            // (tiny angles), so the rotations do not shrink systematically
+            cs = __builtin_amdgcn_rsq(u1);
+#pragma unroll
+            for (int it = 0; it < 2; ++it) cs = fma(cs, fma(-0.5 * u1 * cs, cs, 0.5), cs);
+          } else {
+            tt = 2.0 * ga * (dd >= 0.0 ? 1.0 : -1.0) / (fabs(dd) + sqrt(q2));
+            cs = rsqrt(fma(tt, tt, 1.0));
           }
-          if (wantX)
-            for (int i = gl; i < c; i += 16) {
-              const double x = sZ[i + p * JAC_LD], y = sZ[i + q * JAC_LD];
-              sZ[i + p * JAC_LD] = cs * x - sn * y;
-              sZ[i + q * JAC_LD] = sn * x + cs * y;
+          const double sn = cs * tt;
+#pragma unroll
+          for (int u = 0; u < JAC_RPL; ++u) {
+            const int i = gl + 16 * u;
+            if (i < h) {
+              sA[i + p * JAC_LD] = cs * xv[u] - sn * yv[u];
+              sA[i + q * JAC_LD] = sn * xv[u] + cs * yv[u];
             }
+          }
+          if (wantX) {
+#pragma unroll
+            for (int u = 0; u < JAC_RPL; ++u) {
+              const int i = gl + 16 * u;
+              const int ic = min(i, c - 1);
+              const double x = sZ[ic + p * JAC_LD], y = sZ[ic + q * JAC_LD];
+              if (i < c) {
+                sZ[i + p * JAC_LD] = cs * x - sn * y;
+                sZ[i + q * JAC_LD] = sn * x + cs * y;
+              }
+            }
+          }
           if (gl == 0) flag = 1;
         }
       }

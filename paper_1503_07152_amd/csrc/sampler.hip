@@ -19,15 +19,16 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
-constexpr int SMP_RT = 1;             // 16-row tiles per wave
-// Waves per block: the BF16 form needs ~80 VGPRs, so 8 waves (2 per SIMD)
-// fit; the FP32 form keeps FP32 and FP64 accumulators (~300 registers with
-// the AGPRs) and the FP64 form ~130, so they run 4 waves, one per SIMD.
+// Block shape per form.  BF16: ~80 VGPRs, so 8 waves (2 per SIMD) of one
+// 16-row tile each.  FP32 (FP32 and FP64 accumulators, ~420 registers with
+// the AGPRs) and FP64 (~130): 4 waves of two 16-row tiles, which halves the
+// LDS reads of X per MFMA.
 template <int MODE>
 struct SmpShape {
   static constexpr int WAVES = MODE == 2 ? 8 : 4;
+  static constexpr int RT = MODE == 2 ? 1 : 2;    // 16-row tiles per wave
   static constexpr int THREADS = 64 * WAVES;
-  static constexpr int ROWS = WAVES * 16 * SMP_RT;  // rows per block
+  static constexpr int ROWS = WAVES * 16 * RT;    // rows per block
 };
 constexpr int SMP_CT = SMP_MAXC / 16; // column tiles
 
@@ -105,8 +106,8 @@ __device__ __forceinline__ float entry_f32c(float xi, float yi, float xj, float 
 constexpr int SMP_FLUSH = 32;
 
 // SRC: 0 log kernel, 1 near-singular kernel, 2 dense matrix, 3 its transpose (F64 only).
-// One block = SmpShape<MODE>::WAVES waves x SMP_RT 16-row tiles; the whole X is streamed through
-// LDS in K-tiles, double-buffered, the next tile prefetched into registers
+// One block = SmpShape<MODE>::WAVES waves x RT 16-row tiles; the whole X is streamed
+// through LDS in K-tiles, double-buffered, the next tile prefetched into registers
 // while the current one feeds the MFMAs.
 template <int MODE, int SRC>
 __global__ __launch_bounds__(SmpShape<MODE>::THREADS) void k_sampler(int64_t n, int c, int cp, const double* pts,
@@ -117,6 +118,7 @@ __global__ __launch_bounds__(SmpShape<MODE>::THREADS) void k_sampler(int64_t n, 
   constexpr int BK = ModeT<MODE>::BK;
   constexpr int SMP_THREADS = SmpShape<MODE>::THREADS;
   constexpr int SMP_ROWS = SmpShape<MODE>::ROWS;
+  constexpr int SMP_RT = SmpShape<MODE>::RT;
   constexpr int TILE_BYTES = BK * SMP_MAXC * (int)sizeof(T);
   constexpr int NV = (TILE_BYTES + SMP_THREADS * 16 - 1) / (SMP_THREADS * 16);  // uint4 per thread
   __shared__ __attribute__((aligned(16))) T sX[2][BK * SMP_MAXC + 16];
@@ -151,35 +153,37 @@ __global__ __launch_bounds__(SmpShape<MODE>::THREADS) void k_sampler(int64_t n, 
       for (int ct = 0; ct < SMP_CT; ++ct) acc64[rt][ct] = d4{0, 0, 0, 0};
   }
   const int64_t nkt = (n + BK - 1) / BK;
+  // prefetch registers for the next K-tile (plain statements, not a lambda
+  // capture, so the array stays in VGPRs)
   uint4 pre[NV];
   double pp = 0.0;
-  auto fetch = [&](int64_t kt) {
-    const uint4* src = reinterpret_cast<const uint4*>(Xp + kt * (int64_t)BK * cp);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const int e = tid + v * SMP_THREADS;
-      if (e < tile_u4) pre[v] = src[e];
-    }
-    if (SRC < 2 && tid < 2 * BK) {
-      const int64_t j = kt * BK + tid / 2;
-      pp = j < n ? pts[2 * j + (tid & 1)] : 0.0;
-    }
-  };
-  auto stash = [&](int buf) {
-    uint4* dst = reinterpret_cast<uint4*>(sX[buf]);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const int e = tid + v * SMP_THREADS;
-      if (e < tile_u4) dst[e] = pre[v];
-    }
-    if (SRC < 2 && tid < 2 * BK) sP[buf][tid] = pp;
-  };
-  fetch(0);
-  stash(0);
+#define HM_SMP_FETCH(KT)                                                              \
+  {                                                                                   \
+    const uint4* src_ = reinterpret_cast<const uint4*>(Xp + (KT) * (int64_t)BK * cp); \
+    _Pragma("unroll") for (int v = 0; v < NV; ++v) {                                  \
+      const int e = tid + v * SMP_THREADS;                                            \
+      pre[v] = e < tile_u4 ? src_[e] : uint4{0, 0, 0, 0};                             \
+    }                                                                                 \
+    if (SRC < 2 && tid < 2 * BK) {                                                    \
+      const int64_t j_ = (KT) * BK + tid / 2;                                         \
+      pp = j_ < n ? pts[2 * j_ + (tid & 1)] : 0.0;                                    \
+    }                                                                                 \
+  }
+#define HM_SMP_STASH(BUF)                                                             \
+  {                                                                                   \
+    uint4* dst_ = reinterpret_cast<uint4*>(sX[BUF]);                                  \
+    _Pragma("unroll") for (int v = 0; v < NV; ++v) {                                  \
+      const int e = tid + v * SMP_THREADS;                                            \
+      if (e < tile_u4) dst_[e] = pre[v];                                              \
+    }                                                                                 \
+    if (SRC < 2 && tid < 2 * BK) sP[BUF][tid] = pp;                                   \
+  }
+  HM_SMP_FETCH(0)
+  HM_SMP_STASH(0)
   __syncthreads();
   for (int64_t kt = 0; kt < nkt; ++kt) {
     const int buf = (int)(kt & 1);
-    if (kt + 1 < nkt) fetch(kt + 1);
+    if (kt + 1 < nkt) HM_SMP_FETCH(kt + 1)
     const uint32_t msk = mask[kt];
     const T* xs = sX[buf];
     const double* ps = sP[buf];
@@ -258,7 +262,7 @@ __global__ __launch_bounds__(SmpShape<MODE>::THREADS) void k_sampler(int64_t n, 
           }
       }
     }
-    if (kt + 1 < nkt) stash(buf ^ 1);
+    if (kt + 1 < nkt) HM_SMP_STASH(buf ^ 1)
     __syncthreads();
   }
   // Accumulator layout (column lane % 16 of each 16 x 16 tile): item v of lane
@@ -281,6 +285,9 @@ __global__ __launch_bounds__(SmpShape<MODE>::THREADS) void k_sampler(int64_t n, 
       }
     }
 }
+
+#undef HM_SMP_FETCH
+#undef HM_SMP_STASH
 
 template <int MODE, int SRC>
 static void run_sampler(int64_t n, int c, const double* pts, double kp, const double* Ad,
