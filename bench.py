@@ -37,14 +37,16 @@ N, LEAF, K, P, DELTA, SEED_PTS, SEED = 65536, 128, 32, 16, 1e-3, 3, 3
 # MI355X published peaks
 PEAK_HBM_GBS = 8000.0
 PEAK_TF = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
-# Peak of plain vector ALU work: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
-# = 39.3e12 lane-operations/s (one instruction slot per lane per cycle,
-# non-packed; transcendentals take 4 slots).
-PEAK_ALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# instruction slots per kernel entry in the BF16/FP32 sampler: 2 FP64
-# subtractions + 2 FP64->FP32 conversions, mul, fma, sqrt (4), add, rcp (4),
-# BF16 conversion (1/2): 14.5 slots
-SLOTS_PER_ENTRY = 14.5
+# Peak of plain vector ALU work on MI355X: 256 CUs x 4 SIMDs x 32 FP32 lanes
+# x 2.4 GHz = 78.6e12 lane-slots/s for non-packed FP32 operations (the FP32
+# vector peak of 157.3 TFLOP/s counts an FMA as two); transcendentals (sqrt,
+# rcp) issue at a quarter of that rate and count 4 slots (measured on the
+# device: 61.6 T adds/s, 17.2 T reciprocals/s in a full-chip issue test).
+PEAK_ALU_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
+# instruction slots per kernel entry in the BF16 sampler (from its code):
+# 2 FP32 subtractions, mul, fma (d^2), sqrt (4), add (+delta), rcp (4), half a
+# packed BF16 conversion = 13.5 slots
+SLOTS_PER_ENTRY = 13.5
 
 # HBM bytes of one BF16 operator apply (k_pack + k_sampler, N = 65536, 96
 # columns) from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE in KiB per
@@ -52,8 +54,8 @@ SLOTS_PER_ENTRY = 14.5
 # read for a plain 256 MiB device copy (FETCH_SIZE reads 0.5x the bytes moved,
 # WRITE_SIZE 1.0x).  Valid only for the sampler source they were taken on
 # (SHA-1 below); otherwise the traffic is unknown.
-SAMPLER_TRAFFIC = {"sha1": "aa6b4f2add16761414948d99627ffdd81b92c7a2",
-                   "fetch_kib": 87525.2 + 24590.5, "write_kib": 50142.6 + 12352.0,
+SAMPLER_TRAFFIC = {"sha1": "1666965a1bfdb7e48b412f3e0d41166719ffaec6",
+                   "fetch_kib": 83280.4 + 24590.5, "write_kib": 51324.4 + 12320.0,
                    "fetch_scale": 2.0, "write_scale": 1.0}
 
 

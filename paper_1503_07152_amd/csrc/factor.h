@@ -10,12 +10,16 @@ namespace hm {
 constexpr int FAC_CMAX = 2 * HM_MAX_SAMPLES;  // columns of a node block
 constexpr int FAC_PMAX = 2 * FAC_CMAX;        // rows of a panel (two stacked triangles)
 constexpr int FAC_LDMAX = FAC_PMAX + 1;
+constexpr int QR_NB = 16;                     // strip width of the blocked QR
+constexpr int QR_TMAX = FAC_CMAX / QR_NB;     // strips per panel
 
 struct PanelDesc {
   double* A;        // panel (global, column-major): rows x cols, factored in place
   int64_t ld;
   int32_t rows, cols;
   double* tau;      // min(rows, cols) reflector scalars
+  double* T;        // compact WY factors, QR_NB x QR_NB per strip (row-major);
+                    // written by the QR, read by the apply
   double* Rout;     // R (min(rows,cols) x cols, zeros below the diagonal)
   int64_t ldR;
   const double* Cin;  // apply: h x ncol input (h = min(rows, cols))

@@ -31,23 +31,117 @@ __device__ __forceinline__ double sum_waves(const double* p) {
 }
 
 // ------------------------------------------------------------ panel QR ----
-// The node factorisations keep a whole panel in LDS (up to ~150 KB), so only
-// one workgroup fits on a CU; 1024 threads (4 waves per SIMD) hide the LDS
-// and FP64 latencies within that workgroup.
+// Blocked Householder QR (compact WY form, Schreiber-Van Loan) of one panel
+// of <= 192 x 96 held in LDS; strips of QR_NB = 16 columns.
+//
+// Strip factorisation: wave w keeps strip column j0 + w in registers (rows
+// lane + 64 t), reduces over the column with DPP / permlane operations, and
+// publishes its reflector into the panel in LDS; the other strip waves apply
+// it to their columns (and the earlier ones form the V^T V entries of T).
+// One barrier per column; the columns of T (H_j0 ... H_j0+15 = I - V T V^T,
+// T upper triangular) are formed one iteration behind.  Then the trailing
+// update A <- A - V T^T (V^T A) on FP64 MFMA 16x16x4, two to sixteen waves per
+// 16-column tile of the trailing block.
+//
+// Outputs: reflectors below the diagonal (v_j(j) = 1 implied), R on and
+// above, tau_j, the T factor of every strip (QR_NB x QR_NB, row-major by
+// strip: T + strip * QR_NB * QR_NB, entry (i, c) at i * QR_NB + c), and R.
 
-// Unblocked Householder QR (H_j = I - tau_j v_j v_j^T, v_j(j) = 1) of one
-// panel held in LDS.  Reflectors are stored below the diagonal, R on and above.
-// Per column j, one reduction gives g_k = sum_{i>=j} A(i,j) A(i,k) for all
-// k > j and, for k = j, the squared norm below the diagonal.  With
-// beta = -sign(x0) |A(j:,j)| and v = [1; A(j+1:,j)/(x0 - beta)] one has
-// v^T A(j:,k) = (g_k - beta A(j,k)) / (x0 - beta), so the update needs no
-// second reduction.  The scaling of column j into v is deferred to the next
-// step (which never reads column j): three barriers per column.
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+// sum over the 16 lanes of a row: lane pairs (xor 1, xor 2 by quad permutes),
+// then the mirrored quad of each half-row, then the mirrored half-row
+__device__ __forceinline__ double sum16(double v) {
+  v += dpp_d<0xB1>(v);
+  v += dpp_d<0x4E>(v);
+  v += dpp_d<0x141>(v);
+  v += dpp_d<0x140>(v);
+  return v;
+}
+// sum over the whole wave, the same value in every lane: rows by sum16, then
+// the gfx950 row swaps (rows 0<->1, 2<->3, then halves)
+__device__ __forceinline__ double sum64(double v) {
+  v = sum16(v);
+  {
+    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(v), __double2loint(v), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(v), __double2hiint(v), false, false);
+    v = __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+  }
+  {
+    const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(v), __double2loint(v), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(v), __double2hiint(v), false, false);
+    v = __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+  }
+  return v;
+}
+
+constexpr int QR_RT = FAC_PMAX / 64;  // row slots per lane
+
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+// 1/a from the hardware estimate and two Newton steps in residual form
+// (e = 1 - a r, r += r e): within an ulp or two for normal a
+__device__ __forceinline__ double recip_nr(double a) {
+  double r = __builtin_amdgcn_rcp(a);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) r = fma(r, fma(-a, r, 1.0), r);
+  return r;
+}
+
+// Householder scalars for the column with diagonal x0 and squared norm sig
+// below it: beta = -sign(x0) sqrt(x0^2 + sig), tau = (beta - x0) / beta,
+// scl = 1 / (x0 - beta).  The square root and reciprocals come from hardware
+// estimates refined by Newton steps (a short dependency chain); outside the
+// range where the estimates are safe, IEEE operations are used.
+__device__ __forceinline__ void householder_scalars(double x0, double sig, double& beta,
+                                                    double& tau, double& scl) {
+  const double q = fma(x0, x0, sig);
+  if (q > 1e-290 && q < 1e290) {
+    double r = __builtin_amdgcn_rsq(q);          // 1/sqrt(q)
+#pragma unroll
+    for (int it = 0; it < 2; ++it) r = fma(r, fma(-0.5 * q * r, r, 0.5), r);
+    double nrm = q * r;
+    nrm = fma(0.5 * r, fma(-nrm, nrm, q), nrm);  // one Newton step on sqrt(q)
+    beta = -copysign(nrm, x0);
+    const double d1 = x0 - beta;                 // |x0| + nrm in magnitude: no cancellation
+    scl = recip_nr(d1);
+    tau = -d1 * recip_nr(beta);
+  } else {
+    beta = -copysign(sqrt(q), x0);
+    tau = (beta - x0) / beta;
+    scl = 1.0 / (x0 - beta);
+  }
+}
+
+// Column c of the compact WY factor (Schreiber-Van Loan): T(c, c) = tau_c,
+// T(i, c) = -tau_c sum_{l = i}^{c-1} T(i, l) (v_l^T v_c) for i < c, zero below;
+// lane i of the calling wave writes row i.
+__device__ __forceinline__ void t_column(double (*sT)[QR_NB + 1], const double (*sVV)[QR_NB + 1],
+                                         const double* sTau, int c, int lane) {
+  if (lane >= QR_NB) return;
+  double acc = 0.0;
+#pragma unroll
+  for (int l = 0; l < QR_NB - 1; ++l)
+    if (l >= lane && l < c) acc = fma(sT[lane][l], sVV[l][c], acc);
+  const double tc = sTau[c];
+  sT[lane][c] = lane == c ? tc : (lane < c ? -tc * acc : 0.0);
+}
+
 __global__ __launch_bounds__(FT) void k_panel_qr(const PanelDesc* descs) {
   __shared__ double sA[FAC_LDMAX * FAC_CMAX];
-  __shared__ double part[FW][FAC_CMAX];
-  __shared__ double sw[FAC_CMAX];
-  __shared__ double sc[4];
+  __shared__ double sTau[QR_NB];
+  __shared__ double sVV[QR_NB][QR_NB + 1];
+  __shared__ double sT[QR_NB][QR_NB + 1];
   const PanelDesc d = descs[blockIdx.x];
   const int m = d.rows, n = d.cols;
   const int lds = (m & 1) ? m : m + 1;
@@ -56,102 +150,144 @@ __global__ __launch_bounds__(FT) void k_panel_qr(const PanelDesc* descs) {
     const int i = idx % m, j = idx / m;
     sA[i + j * lds] = d.trans ? d.A[j + (int64_t)i * d.ld] : d.A[i + (int64_t)j * d.ld];
   }
-  if (tid == 0) { sc[0] = 0.0; sc[1] = 0.0; sc[2] = 0.0; sc[3] = -1.0; }
   __syncthreads();
   const int h = min(m, n);
-  for (int j = 0; j < h; ++j) {
-    // deferred scaling of the previous reflector column
-    const int jp = (int)sc[3];
-    if (jp >= 0) {
-      const double scl = sc[2], bet = sc[0];
-      if (sc[1] != 0.0)
-        for (int i = jp + 1 + tid; i < m; i += FT) sA[i + jp * lds] *= scl;
-      if (tid == 0) sA[jp + jp * lds] = bet;
+  // V(r, j) of the stored panel: 1 on the diagonal, 0 above, LDS below
+  auto vget = [&](int r, int j) -> double {
+    const double x = sA[min(r, m - 1) + j * lds];
+    return r == j ? 1.0 : (r > j && r < m ? x : 0.0);
+  };
+  for (int j0 = 0; j0 < h; j0 += QR_NB) {
+    const int nbs = min(QR_NB, h - j0);
+    // ---- strip factorisation ------------------------------------------------
+    double x[QR_RT];
+    const bool mine = wave < nbs;
+    const int cw = j0 + wave;
+#pragma unroll
+    for (int t = 0; t < QR_RT; ++t) {
+      const int r = lane + 64 * t;
+      x[t] = (mine && r < m) ? sA[r + cw * lds] : 0.0;
     }
-    // partial inner products of column j with columns j..n-1 over this wave's
-    // rows; fixed trip counts (rows outside the panel weigh zero, their reads
-    // are clamped into it) so the LDS reads issue back to back
-    const int rows = m - j;
-    const int q = (rows + FW - 1) / FW;
-    const int ib = j + wave * q, ie = min(m, ib + q);
-    double cj[FAC_PMAX / FW];
+    for (int jj = 0; jj < nbs; ++jj) {
+      const int j = j0 + jj;
+      if (wave == jj) {
+        double s2 = 0.0, xj = 0.0;
 #pragma unroll
-    for (int t = 0; t < FAC_PMAX / FW; ++t) {
-      const int i = ib + t;
-      cj[t] = i < ie ? sA[i + j * lds] : 0.0;
-    }
-    for (int kb = 0; kb < n - j; kb += 64) {
-      const int kk = kb + lane;
-      const int k = j + min(kk, n - j - 1);
-      double bv[FAC_PMAX / FW];
+        for (int t = 0; t < QR_RT; ++t) {
+          const int r = lane + 64 * t;
+          s2 = (r > j) ? fma(x[t], x[t], s2) : s2;   // rows >= m hold zero
+          xj = (t == (j >> 6)) ? x[t] : xj;
+        }
+        const double x0 = readlane_d(xj, j & 63);   // A(j, j), from the lane holding row j
+        const double sig = sum64(s2);
+        double beta = x0, tau = 0.0, scl = 0.0;
+        if (sig != 0.0) householder_scalars(x0, sig, beta, tau, scl);
 #pragma unroll
-      for (int t = 0; t < FAC_PMAX / FW; ++t) bv[t] = sA[min(ib + t, m - 1) + k * lds];
-      // the diagonal term is left out of the norm below the diagonal (k = j)
-      double s0 = ((wave == 0 && kk == 0) ? 0.0 : cj[0]) * bv[0], s1 = cj[1] * bv[1],
-             s2 = cj[2] * bv[2], s3 = cj[3] * bv[3];
-#pragma unroll
-      for (int t = 4; t < FAC_PMAX / FW; t += 4) {
-        s0 = fma(cj[t], bv[t], s0);
-        s1 = fma(cj[t + 1], bv[t + 1], s1);
-        s2 = fma(cj[t + 2], bv[t + 2], s2);
-        s3 = fma(cj[t + 3], bv[t + 3], s3);
+        for (int t = 0; t < QR_RT; ++t) {
+          const int r = lane + 64 * t;
+          const double nv = r < j ? x[t] : (r == j ? beta : x[t] * scl);
+          if (r < m) sA[r + j * lds] = nv;
+          x[t] = r == j ? 1.0 : (r > j ? x[t] * scl : 0.0);   // keep v_j
+        }
+        if (lane == 0) {
+          sTau[jj] = tau;
+          d.tau[j] = tau;
+        }
       }
-      if (kk < n - j) part[wave][kk] = (s0 + s1) + (s2 + s3);
+      __syncthreads();
+      if (mine && wave != jj) {
+        double vj[QR_RT];
+#pragma unroll
+        for (int t = 0; t < QR_RT; ++t) vj[t] = vget(lane + 64 * t, j);
+        double p = 0.0;
+#pragma unroll
+        for (int t = 0; t < QR_RT; ++t) p = fma(vj[t], x[t], p);
+        p = sum64(p);
+        if (wave > jj) {
+          // apply H_j to this wave's column
+          const double tp = sTau[jj] * p;
+#pragma unroll
+          for (int t = 0; t < QR_RT; ++t) x[t] = fma(-tp, vj[t], x[t]);
+        } else if (lane == 0) {
+          sVV[wave][jj] = p;   // v_wave^T v_j (x holds v_wave)
+        }
+      }
+      // T column jj - 1 (its V^T v entries and the earlier columns are final)
+      if (jj >= 1 && wave == jj - 1) t_column(sT, sVV, sTau, jj - 1, lane);
     }
     __syncthreads();
-    // combine: reflector scalars and w_k = v^T A(j:, k)
-    {
-      const double x0 = sA[j + j * lds];
-      const double sig = sum_waves<FAC_CMAX>(&part[0][0]);
-      double beta = x0, tau = 0.0, scl = 0.0;
-      if (sig != 0.0) {
-        beta = -copysign(sqrt(fma(x0, x0, sig)), x0);
-        tau = (beta - x0) / beta;
-        scl = 1.0 / (x0 - beta);
-      }
-      for (int kk = 1 + tid; kk < n - j; kk += FT) {
-        const int k = j + kk;
-        const double g = sum_waves<FAC_CMAX>(&part[0][kk]);
-        sw[k] = (g - beta * sA[j + k * lds]) * scl;
-      }
-      if (tid == 0) {
-        sc[0] = beta; sc[1] = tau; sc[2] = scl; sc[3] = (double)j;
-        d.tau[j] = tau;
-      }
+    if (wave == 0) {
+      t_column(sT, sVV, sTau, nbs - 1, lane);
+      if (lane < QR_NB)
+#pragma unroll
+        for (int c = nbs; c < QR_NB; ++c) sT[lane][c] = 0.0;
     }
     __syncthreads();
-    const double tau = sc[1], scl = sc[2];
-    if (tau != 0.0) {
-      // lanes walk the rows (j + lane + 64 t), waves the columns (j + 1 + wave + 16 u)
-      double vr[FAC_PMAX / 64];
+    if (d.T && tid < QR_NB * QR_NB)
+      d.T[(int64_t)(j0 / QR_NB) * QR_NB * QR_NB + tid] = sT[tid / QR_NB][tid % QR_NB];
+    // ---- trailing update A <- A - V T^T (V^T A), columns j0 + nbs .. n-1 ------------
+    // FW / tiles waves per 16-column tile: each forms the whole W = V^T A(:, tile)
+    // (two accumulators, operands loaded four K-steps ahead), then updates
+    // its share of the 16-row tiles.
+    const int ntile = (n - j0 - nbs + 15) / 16;   // <= 6
+    const int wpt = ntile > 0 ? max(1, FW / ntile) : FW;   // waves per tile
+    const int tile = wave / wpt, sub = wave % wpt;
+    const int c0 = j0 + nbs + 16 * tile;
+    const bool active = tile < ntile;
+    const int cl = c0 + (lane & 15);
+    const int clc = min(cl, n - 1);
+    const int kq = lane >> 4;
+    const int bl = lane & 15;
+    d4 w2 = {0.0, 0.0, 0.0, 0.0};
+    if (active) {
+      const int nks = (m - j0 + 3) / 4;      // 4-row K-steps over rows j0 .. m-1
+      // W = V^T A(rows, tile): A-operand V^T(i = lane % 16, k), B-operand A(k, j = lane % 16)
+      d4 w0 = {0.0, 0.0, 0.0, 0.0}, w1 = {0.0, 0.0, 0.0, 0.0};
+      for (int s = 0; s < nks; s += 4) {
+        double a[4], b[4];
 #pragma unroll
-      for (int t = 0; t < FAC_PMAX / 64; ++t) {
-        const int i = j + lane + 64 * t;
-        vr[t] = i < m ? (i == j ? 1.0 : sA[i + j * lds] * scl) : 0.0;
+        for (int u = 0; u < 4; ++u) {
+          const int r = j0 + 4 * (s + u) + kq;
+          a[u] = bl < nbs ? vget(r, j0 + bl) : 0.0;
+          const double x = sA[min(r, m - 1) + clc * lds];
+          b[u] = (r < m && cl < n) ? x : 0.0;
+        }
+        w0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], w0, 0, 0, 0);
+        w1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1], b[1], w1, 0, 0, 0);
+        w0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[2], b[2], w0, 0, 0, 0);
+        w1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[3], b[3], w1, 0, 0, 0);
       }
+      const d4 w = w0 + w1;
+      // W2 = T^T W: A-operand T^T(i, k) = T(k, i); the B-operand of step s is w[s]
 #pragma unroll
-      for (int u = 0; u < FAC_CMAX / FW; ++u) {
-        const int k = j + 1 + wave + FW * u;
-        if (k < n) {
-          const double tw = tau * sw[k];
+      for (int s = 0; s < 4; ++s)
+        w2 = __builtin_amdgcn_mfma_f64_16x16x4f64(sT[4 * s + kq][bl], w[s], w2, 0, 0, 0);
+    }
+    __syncthreads();   // every W is formed before any tile changes
+    if (active) {
+      // A(rows, tile) -= V W2 on this wave's 16-row tiles; A-operand V(i, k = 4 s + lane / 16)
+      const int nrt = (m - j0 + 15) / 16;
+      for (int rt = sub; rt < nrt; rt += wpt) {
+        const int rb = j0 + 16 * rt;
+        double a[4], c[4];
 #pragma unroll
-          for (int t = 0; t < FAC_PMAX / 64; ++t) {
-            const int i = j + lane + 64 * t;
-            if (i < m) sA[i + k * lds] -= tw * vr[t];
-          }
+        for (int s = 0; s < 4; ++s) {
+          const int b = 4 * s + kq;
+          a[s] = b < nbs ? vget(rb + bl, j0 + b) : 0.0;
+          c[s] = sA[min(rb + kq + 4 * s, m - 1) + clc * lds];
+        }
+        d4 u = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) u = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], w2[s], u, 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = rb + kq + 4 * v;
+          if (r < m && cl < n) sA[r + cl * lds] = c[v] - u[v];
         }
       }
     }
     __syncthreads();
   }
-  if (h > 0) {
-    const int jp = h - 1;
-    const double scl = sc[2], bet = sc[0];
-    if (sc[1] != 0.0)
-      for (int i = jp + 1 + tid; i < m; i += FT) sA[i + jp * lds] *= scl;
-    if (tid == 0) sA[jp + jp * lds] = bet;
-  }
-  __syncthreads();
   for (int idx = tid; idx < m * n; idx += FT) {
     const int i = idx % m, j = idx / m;
     d.A[i + (int64_t)j * d.ld] = sA[i + j * lds];
@@ -169,87 +305,95 @@ void launch_panel_qr(const PanelDesc* d, int n, hipStream_t s) {
   KCHK();
 }
 
-// Cout = H_0 H_1 ... H_{h-1} [Cin; 0].  The next reflector is prefetched from
-// global memory into registers while the current one is applied.
+// Cout = H_0 H_1 ... H_{h-1} [Cin; 0] = (I - V_0 T_0 V_0^T) ... [Cin; 0], the
+// strips applied last to first.  One wave per 16-column tile of C, which stays
+// in MFMA accumulator registers (row tile rt, item v of lane l = row
+// 16 rt + l/16 + 4 v, column l % 16): W = V_b^T C (the B-operand of K-step s is
+// item s % 4 of row tile s / 4), W2 = T_b W, C -= V_b W2.  Each strip's
+// reflectors (unit diagonal and zeros made explicit) and T_b are staged in LDS
+// by the whole workgroup.
 constexpr int APQ_NMAX = HM_MAX_SAMPLES;
-__global__ __launch_bounds__(FT) void k_apply_q(const PanelDesc* descs) {
-  __shared__ double sO[FAC_LDMAX * APQ_NMAX];
-  __shared__ double sv[2][FAC_PMAX];
-  __shared__ double part[FW][64];
-  __shared__ double sw[64];
-  const PanelDesc d = descs[blockIdx.x];
+constexpr int APQ_WAVES = 4;
+__global__ __launch_bounds__(64 * APQ_WAVES) void k_apply_q(const PanelDesc* descs, int tiles) {
+  __shared__ double sV[FAC_PMAX * QR_NB];
+  __shared__ double sTb[QR_NB * QR_NB];
+  const PanelDesc d = descs[blockIdx.x / tiles];
+  const int tile = (blockIdx.x % tiles) * APQ_WAVES + (threadIdx.x >> 6);
   const int m = d.rows, h = min(d.rows, d.cols), nc = d.ncol;
-  const int ldo = (m & 1) ? m : m + 1;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int idx = tid; idx < m * nc; idx += FT) {
-    const int i = idx % m, c = idx / m;
-    sO[i + c * ldo] = (i < h) ? d.Cin[i + (int64_t)c * d.ldCin] : 0.0;
-  }
-  auto vload = [&](int j) -> double {
-    if (j < 0 || tid >= m || tid < j) return 0.0;
-    return tid == j ? 1.0 : d.A[tid + (int64_t)j * d.ld];
-  };
-  if (h > 0 && tid < m) sv[0][tid] = vload(h - 1);
-  __syncthreads();
-  int buf = 0;
-  for (int j = h - 1; j >= 0; --j) {
-    const double vnext = vload(j - 1);
-    const double tau = d.tau[j];
-    if (tau != 0.0) {
-      const int rows = m - j, q = (rows + FW - 1) / FW;
-      const int ib = j + wave * q, ie = min(m, ib + q);
-      const int cl = max(min(lane, nc - 1), 0);
-      double av[FAC_PMAX / FW], bv[FAC_PMAX / FW];
+  const int tid = threadIdx.x, lane = tid & 63, kq = lane >> 4, bl = lane & 15;
+  const int cl = 16 * tile + bl;
+  const bool act = 16 * tile < nc;
+  d4 cacc[FAC_PMAX / 16];
 #pragma unroll
-      for (int t = 0; t < FAC_PMAX / FW; ++t) {
-        const int i = ib + t;
-        av[t] = i < ie ? sv[buf][i] : 0.0;
-        bv[t] = sO[min(i, m - 1) + cl * ldo];
-      }
-      double s0 = av[0] * bv[0], s1 = av[1] * bv[1], s2 = av[2] * bv[2], s3 = av[3] * bv[3];
+  for (int rt = 0; rt < FAC_PMAX / 16; ++rt)
 #pragma unroll
-      for (int t = 4; t < FAC_PMAX / FW; t += 4) {
-        s0 = fma(av[t], bv[t], s0);
-        s1 = fma(av[t + 1], bv[t + 1], s1);
-        s2 = fma(av[t + 2], bv[t + 2], s2);
-        s3 = fma(av[t + 3], bv[t + 3], s3);
-      }
-      part[wave][lane] = lane < nc ? (s0 + s1) + (s2 + s3) : 0.0;
-      __syncthreads();
-      if (wave == 0) sw[lane] = sum_waves<64>(&part[0][lane]);
-      __syncthreads();
-      double vr[FAC_PMAX / 64];
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * rt + kq + 4 * v;
+      cacc[rt][v] = (act && r < h && cl < nc) ? d.Cin[r + (int64_t)cl * d.ldCin] : 0.0;
+    }
+  auto vs = [&](int r, int b) -> double { return r < m ? sV[r + b * FAC_PMAX] : 0.0; };
+  const int nstrips = (h + QR_NB - 1) / QR_NB;
+  for (int sb = nstrips - 1; sb >= 0; --sb) {
+    const int j0 = sb * QR_NB;
+    const int rt0 = j0 / 16;
+    __syncthreads();   // the previous strip's operands are consumed
+    for (int idx = tid; idx < m * QR_NB; idx += 64 * APQ_WAVES) {
+      const int r = idx % m, b = idx / m, j = j0 + b;
+      double v = 0.0;
+      if (j < h && r >= j) v = r == j ? 1.0 : d.A[r + (int64_t)j * d.ld];
+      sV[r + b * FAC_PMAX] = v;
+    }
+    sTb[tid] = d.T[(int64_t)sb * QR_NB * QR_NB + tid];
+    __syncthreads();
+    if (!act) continue;
+    // W = V_b^T C over rows j0 .. m-1
+    d4 w0 = {0.0, 0.0, 0.0, 0.0}, w1 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int t = 0; t < FAC_PMAX / 64; ++t) {
-        const int i = j + lane + 64 * t;
-        vr[t] = i < m ? sv[buf][i] : 0.0;
-      }
+    for (int rt = 0; rt < FAC_PMAX / 16; ++rt) {
+      if (rt >= rt0 && 16 * rt < m) {
+        double a[4];
 #pragma unroll
-      for (int u = 0; u < (APQ_NMAX + FW - 1) / FW; ++u) {
-        const int cc = wave + FW * u;
-        if (cc < nc) {
-          const double tw = tau * sw[cc];
-#pragma unroll
-          for (int t = 0; t < FAC_PMAX / 64; ++t) {
-            const int i = j + lane + 64 * t;
-            if (i < m) sO[i + cc * ldo] -= tw * vr[t];
-          }
-        }
+        for (int v = 0; v < 4; ++v) a[v] = vs(16 * rt + 4 * v + kq, bl);
+        w0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], cacc[rt][0], w0, 0, 0, 0);
+        w1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1], cacc[rt][1], w1, 0, 0, 0);
+        w0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[2], cacc[rt][2], w0, 0, 0, 0);
+        w1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[3], cacc[rt][3], w1, 0, 0, 0);
       }
     }
-    if (tid < m) sv[buf ^ 1][tid] = vnext;
-    buf ^= 1;
-    __syncthreads();
+    const d4 w = w0 + w1;
+    // W2 = T_b W
+    d4 w2 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      w2 = __builtin_amdgcn_mfma_f64_16x16x4f64(sTb[bl * QR_NB + 4 * s + kq], w[s], w2, 0, 0, 0);
+    // C -= V_b W2
+#pragma unroll
+    for (int rt = 0; rt < FAC_PMAX / 16; ++rt) {
+      if (rt >= rt0 && 16 * rt < m) {
+        double a[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) a[s] = vs(16 * rt + bl, 4 * s + kq);
+        d4 u = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) u = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], w2[s], u, 0, 0, 0);
+        cacc[rt] -= u;
+      }
+    }
   }
-  for (int idx = tid; idx < m * nc; idx += FT) {
-    const int i = idx % m, c = idx / m;
-    d.Cout[i + (int64_t)c * d.ldCout] = sO[i + c * ldo];
-  }
+  if (!act) return;
+#pragma unroll
+  for (int rt = 0; rt < FAC_PMAX / 16; ++rt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * rt + kq + 4 * v;
+      if (r < m && cl < nc) d.Cout[r + (int64_t)cl * d.ldCout] = cacc[rt][v];
+    }
 }
 
 void launch_apply_q(const PanelDesc* d, int n, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_apply_q, dim3(n), dim3(FT), 0, s, d);
+  const int tiles = (APQ_NMAX + 16 * APQ_WAVES - 1) / (16 * APQ_WAVES);
+  hipLaunchKernelGGL(k_apply_q, dim3(n * tiles), dim3(64 * APQ_WAVES), 0, s, d, tiles);
   KCHK();
 }
 
@@ -264,22 +408,6 @@ void launch_apply_q(const PanelDesc* d, int n, hipStream_t s) {
 constexpr int JAC_LD = FAC_CMAX + 1;
 constexpr int JAC_GROUPS = FT / 16;
 constexpr int JAC_RPL = FAC_CMAX / 16;  // rows per lane of a 16-lane group
-
-template <int CTRL>
-__device__ __forceinline__ double dpp_d(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-// sum over the 16 lanes of a row: lane pairs (xor 1, xor 2 by quad permutes),
-// then the mirrored quad of each half-row, then the mirrored half-row
-__device__ __forceinline__ double sum16(double v) {
-  v += dpp_d<0xB1>(v);
-  v += dpp_d<0x4E>(v);
-  v += dpp_d<0x141>(v);
-  v += dpp_d<0x140>(v);
-  return v;
-}
 
 __global__ __launch_bounds__(FT) void k_jacobi(const SvdDesc* descs) {
   __shared__ double sA[FAC_CMAX * JAC_LD];

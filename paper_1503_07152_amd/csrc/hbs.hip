@@ -133,7 +133,8 @@ void node_svd(const std::vector<SvdJob>& jobs, double* M, int64_t ldm, double* U
       srows[st] += tot;
     }
   Alloc al;
-  std::vector<size_t> s_off(nst), c_off(nst), t_off(nst);
+  std::vector<size_t> s_off(nst), c_off(nst), t_off(nst), wy_off(nst);
+  constexpr int64_t WY = (int64_t)QR_TMAX * QR_NB * QR_NB;   // T factors per panel
   std::vector<int64_t> npan(nst, 0);
   for (int q = 0; q < nj; ++q)
     for (int st = 0; st <= top[q]; ++st) npan[st] += (int64_t)stages[q][st].size();
@@ -141,6 +142,7 @@ void node_svd(const std::vector<SvdJob>& jobs, double* M, int64_t ldm, double* U
     s_off[st] = al.take((size_t)std::max<int64_t>(srows[st], 1) * cmax * sizeof(double));
     c_off[st] = al.take((size_t)std::max<int64_t>(srows[st], 1) * R * sizeof(double));
     t_off[st] = al.take((size_t)std::max<int64_t>(npan[st], 1) * cmax * sizeof(double));
+    wy_off[st] = al.take((size_t)std::max<int64_t>(npan[st], 1) * WY * sizeof(double));
   }
   const size_t rfin_off = al.take((size_t)nj * FAC_CMAX * FAC_CMAX * sizeof(double));
   const size_t w_off = al.take((size_t)nj * FAC_CMAX * R * sizeof(double));
@@ -150,17 +152,20 @@ void node_svd(const std::vector<SvdJob>& jobs, double* M, int64_t ldm, double* U
   const size_t r2_off = al.take((size_t)nj * FAC_CMAX * FAC_CMAX * sizeof(double));
   const size_t tau2_off = al.take((size_t)nj * FAC_CMAX * sizeof(double));
   const size_t z_off = al.take((size_t)nj * FAC_CMAX * R * sizeof(double));
+  const size_t wy2_off = al.take((size_t)nj * WY * sizeof(double));
   ws.ensure(al.off, s);
   char* base = ws.base();
   auto S = [&](int st) { return reinterpret_cast<double*>(base + s_off[st]); };
   auto C = [&](int st) { return reinterpret_cast<double*>(base + c_off[st]); };
   auto TAU = [&](int st) { return reinterpret_cast<double*>(base + t_off[st]); };
+  auto TWY = [&](int st) { return reinterpret_cast<double*>(base + wy_off[st]); };
   double* Rfin = reinterpret_cast<double*>(base + rfin_off);
   double* W = reinterpret_cast<double*>(base + w_off);
   double* EYE = reinterpret_cast<double*>(base + eye_off);
   double* R2 = reinterpret_cast<double*>(base + r2_off);
   double* TAU2 = reinterpret_cast<double*>(base + tau2_off);
   double* Z = reinterpret_cast<double*>(base + z_off);
+  double* TWY2 = reinterpret_cast<double*>(base + wy2_off);
   // ---- descriptors ---------------------------------------------------------
   std::vector<std::vector<PanelDesc>> pd(nst);
   std::vector<int64_t> tcount(nst, 0);
@@ -180,6 +185,7 @@ void node_svd(const std::vector<SvdJob>& jobs, double* M, int64_t ldm, double* U
         d.rows = b.rows;
         d.cols = jb.cols;
         d.tau = TAU(st) + tcount[st] * cmax;
+        d.T = TWY(st) + tcount[st] * WY;
         tcount[st]++;
         const int h = std::min(b.rows, jb.cols);
         if (st < top[q]) {
@@ -203,6 +209,7 @@ void node_svd(const std::vector<SvdJob>& jobs, double* M, int64_t ldm, double* U
             PanelDesc t{};
             t.A = d.Rout; t.ld = FAC_CMAX; t.rows = jb.cols; t.cols = h; t.trans = 1;
             t.tau = TAU2 + (int64_t)q * FAC_CMAX;
+            t.T = TWY2 + (int64_t)q * WY;
             t.Rout = r2; t.ldR = FAC_CMAX;
             t.Cin = zq; t.ldCin = FAC_CMAX;
             t.Cout = X ? X + (int64_t)jb.node * 2 * R * R : nullptr; t.ldCout = 2 * R;

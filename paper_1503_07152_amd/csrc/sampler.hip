@@ -35,16 +35,18 @@ constexpr int SMP_CT = SMP_MAXC / 16; // column tiles
 template <int MODE> struct ModeT;
 template <> struct ModeT<0> { typedef double T; static constexpr int BK = 16; };
 template <> struct ModeT<1> { typedef float T; static constexpr int BK = 16; };
-template <> struct ModeT<2> { typedef __bf16 T; static constexpr int BK = 32; };
+template <> struct ModeT<2> { typedef __bf16 T; static constexpr int BK = 64; };
 
-int sampler_bk(int mode) { return mode == 2 ? 32 : 16; }
+int sampler_bk(int mode) { return mode == 2 ? 64 : 16; }
+
+static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
 size_t sampler_pack_bytes(int mode, int64_t n, int c) {
   const int bk = sampler_bk(mode);
   const int64_t kt = (n + bk - 1) / bk;
   const int cp = ((c + 15) / 16) * 16;
   const size_t es = mode == 0 ? 8 : (mode == 1 ? 4 : 2);
-  return (size_t)kt * bk * cp * es + (size_t)kt * 4 + 512;
+  return align256((size_t)kt * bk * cp * es) + align256((size_t)kt * 4) + 512;
 }
 
 // Pack: F64/F32 tiles [kt][k][col]; BF16 tiles [kt][col][k].
@@ -121,8 +123,14 @@ __global__ __launch_bounds__(SmpShape<MODE>::THREADS) void k_sampler(int64_t n, 
   constexpr int SMP_RT = SmpShape<MODE>::RT;
   constexpr int TILE_BYTES = BK * SMP_MAXC * (int)sizeof(T);
   constexpr int NV = (TILE_BYTES + SMP_THREADS * 16 - 1) / (SMP_THREADS * 16);  // uint4 per thread
-  __shared__ __attribute__((aligned(16))) T sX[2][BK * SMP_MAXC + 16];
-  __shared__ double sP[2][2 * BK];
+  // BF16 tiles are column-major (BK contiguous k per column); a column stride
+  // of BK + 8 elements (144 bytes) spreads the 16 lanes of a B-operand read
+  // over distinct LDS banks (a stride of 128 bytes put them all on one).
+  constexpr int XLD = MODE == 2 ? BK + 8 : BK;
+  __shared__ __attribute__((aligned(16))) T sX[2][XLD * SMP_MAXC + 16];
+  // point coordinates of the K-tile: FP64 (FP64 / FP32 forms), FP32 (BF16 form)
+  __shared__ double sP[2][MODE == 2 ? 1 : 2 * BK];
+  __shared__ __attribute__((aligned(8))) float sPf[2][MODE == 2 ? 2 * BK : 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t row0 = (int64_t)blockIdx.x * SMP_ROWS + wave * 16 * SMP_RT;
   const int ct_n = cp / 16;
@@ -166,7 +174,7 @@ __global__ __launch_bounds__(SmpShape<MODE>::THREADS) void k_sampler(int64_t n, 
     }                                                                                 \
     if (SRC < 2 && tid < 2 * BK) {                                                    \
       const int64_t j_ = (KT) * BK + tid / 2;                                         \
-      pp = j_ < n ? pts[2 * j_ + (tid & 1)] : 0.0;                                    \
+      pp = j_ < n ? pts[2 * j_ + (tid & 1)] : (MODE == 2 ? 1e15 : 0.0);               \
     }                                                                                 \
   }
 #define HM_SMP_STASH(BUF)                                                             \
@@ -174,9 +182,17 @@ __global__ __launch_bounds__(SmpShape<MODE>::THREADS) void k_sampler(int64_t n, 
     uint4* dst_ = reinterpret_cast<uint4*>(sX[BUF]);                                  \
     _Pragma("unroll") for (int v = 0; v < NV; ++v) {                                  \
       const int e = tid + v * SMP_THREADS;                                            \
-      if (e < tile_u4) dst_[e] = pre[v];                                              \
+      if (e < tile_u4) {                                                              \
+        if constexpr (MODE == 2)                                                      \
+          dst_[(e / (BK / 8)) * (XLD / 8) + e % (BK / 8)] = pre[v];                   \
+        else                                                                          \
+          dst_[e] = pre[v];                                                           \
+      }                                                                               \
     }                                                                                 \
-    if (SRC < 2 && tid < 2 * BK) sP[BUF][tid] = pp;                                   \
+    if (SRC < 2 && tid < 2 * BK) {                                                    \
+      if constexpr (MODE == 2) sPf[BUF][tid] = (float)pp;                             \
+      else sP[BUF][tid] = pp;                                                         \
+    }                                                                                 \
   }
   HM_SMP_FETCH(0)
   HM_SMP_STASH(0)
@@ -224,29 +240,39 @@ __global__ __launch_bounds__(SmpShape<MODE>::THREADS) void k_sampler(int64_t n, 
           }
         }
       } else {
-        // BF16: lane holds A(row, 8*(lane/16) + e), e = 0..7, and X(8*(lane/16) + e, col).
+        // BF16: per 32-row K-step s, lane holds A(row, 32 s + 8*(lane/16) + e),
+        // e = 0..7, and X(32 s + 8*(lane/16) + e, col).  Points past n sit at
+        // 1e15 (finite entries against zero rows of X), so no bounds test.
         const int kb = 8 * (lane >> 4);
-        bf8 a[SMP_RT];
+        const float* psf = sPf[buf];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int jl = kb + e;
-          const int64_t gj = kt * BK + jl;
-          const float xj = (float)ps[2 * jl], yj = (float)ps[2 * jl + 1];
+        for (int s = 0; s < BK / 32; ++s) {
+          bf8 a[SMP_RT];
 #pragma unroll
-          for (int rt = 0; rt < SMP_RT; ++rt) {
-            float v = 0.0f;
-            if (gj < n)
-              v = entry_f32c<SRC >= 2 ? 1 : SRC>(xif[rt], yif[rt], xj, yj, gi[rt], gj, (float)kp);
-            a[rt][e] = (__bf16)v;
+          for (int e = 0; e < 8; ++e) {
+            const int jl = 32 * s + kb + e;
+            const float2 pj = *reinterpret_cast<const float2*>(&psf[2 * jl]);
+#pragma unroll
+            for (int rt = 0; rt < SMP_RT; ++rt) {
+              float v;
+              if constexpr (SRC >= 2) {
+                const int64_t gj = kt * BK + jl;
+                v = gj < n ? entry_f32c<1>(xif[rt], yif[rt], pj.x, pj.y, gi[rt], gj, (float)kp) : 0.0f;
+              } else {
+                v = entry_f32c<SRC>(xif[rt], yif[rt], pj.x, pj.y, gi[rt], kt * BK + jl, (float)kp);
+              }
+              a[rt][e] = (__bf16)v;
+            }
           }
-        }
 #pragma unroll
-        for (int ct = 0; ct < SMP_CT; ++ct) {
-          if (ct >= ct_n || !((msk >> ct) & 1u)) continue;
-          const bf8 b = *reinterpret_cast<const bf8*>(&xs[(ct * 16 + (lane & 15)) * BK + kb]);
+          for (int ct = 0; ct < SMP_CT; ++ct) {
+            if (ct >= ct_n || !((msk >> ct) & 1u)) continue;
+            const bf8 b =
+                *reinterpret_cast<const bf8*>(&xs[(ct * 16 + (lane & 15)) * XLD + 32 * s + kb]);
 #pragma unroll
-          for (int rt = 0; rt < SMP_RT; ++rt)
-            acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rt], b, acc[rt][ct], 0, 0, 0);
+            for (int rt = 0; rt < SMP_RT; ++rt)
+              acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rt], b, acc[rt][ct], 0, 0, 0);
+          }
         }
       }
     }
@@ -278,10 +304,11 @@ __global__ __launch_bounds__(SmpShape<MODE>::THREADS) void k_sampler(int64_t n, 
       for (int v = 0; v < 4; ++v) {
         const int rr = MODE == 0 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v;
         const int64_t row = row0 + rt * 16 + rr;
+        if (row >= n) continue;
         double val;
         if constexpr (MODE == 1) val = acc64[rt][ct][v];
         else val = (double)acc[rt][ct][v];
-        if (row < n) Y[row + (int64_t)col * ldy] = val;
+        Y[row + (int64_t)col * ldy] = val;
       }
     }
 }
@@ -298,14 +325,15 @@ static void run_sampler(int64_t n, int c, const double* pts, double kp, const do
   const int cp = ((c + 15) / 16) * 16;
   const int64_t nkt = (n + BK - 1) / BK;
   T* Xp = static_cast<T*>(work);
-  uint32_t* mask = reinterpret_cast<uint32_t*>(
-      static_cast<char*>(work) + (((size_t)nkt * BK * cp * sizeof(T) + 255) / 256) * 256);
+  const size_t xbytes = align256((size_t)nkt * BK * cp * sizeof(T));
+  uint32_t* mask = reinterpret_cast<uint32_t*>(static_cast<char*>(work) + xbytes);
   hipLaunchKernelGGL(k_pack<MODE>, dim3((unsigned)nkt), dim3(256), 0, s, n, c, cp, X, ldx, Xp,
                      mask);
   KCHK();
   constexpr int rows = SmpShape<MODE>::ROWS;
   hipLaunchKernelGGL((k_sampler<MODE, SRC>), dim3((unsigned)((n + rows - 1) / rows)),
-                     dim3(SmpShape<MODE>::THREADS), 0, s, n, c, cp, pts, kp, Ad, lda, Xp, mask, Y, ldy);
+                     dim3(SmpShape<MODE>::THREADS), 0, s, n, c, cp, pts, kp, Ad, lda, Xp, mask, Y,
+                     ldy);
   KCHK();
 }
 
