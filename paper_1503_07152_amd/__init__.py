@@ -227,9 +227,13 @@ class HBS:
         self.handle = handle
         self.status = status
 
+    # bound at class creation: module globals may already be cleared when
+    # the last handles are collected at interpreter exit
+    _free = lib.hm_hbs_free
+
     def __del__(self):
         if getattr(self, "handle", None):
-            lib.hm_hbs_free(self.handle)
+            type(self)._free(self.handle)
             self.handle = None
 
     def info(self):
@@ -278,9 +282,13 @@ class HODLR:
         self.handle = handle
         self.status = status
 
+    # bound at class creation: module globals may already be cleared when
+    # the last handles are collected at interpreter exit
+    _free = lib.hm_hodlr_free
+
     def __del__(self):
         if getattr(self, "handle", None):
-            lib.hm_hodlr_free(self.handle)
+            type(self)._free(self.handle)
             self.handle = None
 
     def info(self):

@@ -54,30 +54,59 @@ struct hm_hodlr_s {
 
 namespace hm {
 
-// Keeps host tables alive and their device copies until the owner is
-// destroyed (after the stream has been synchronised), so asynchronous copies
-// never race.
+// Host-to-device staging for small per-call tables (node lists, descriptors):
+// pinned host blocks and device blocks, bump-allocated, so hipMemcpyAsync stays
+// asynchronous and no allocation happens per table.  Nothing is released
+// before the Keeper is destroyed; its owner synchronises the stream first.
 struct Keeper {
-  std::deque<std::vector<char>> host;
-  std::vector<DevBuf> dev;
+  struct Pinned {
+    char* p = nullptr;
+    size_t cap = 0, used = 0;
+  };
+  std::vector<Pinned> hblk;
+  std::vector<DevBuf> dblk;
+  size_t dused = 0;
+  Keeper() = default;
+  Keeper(const Keeper&) = delete;
+  Keeper& operator=(const Keeper&) = delete;
+  ~Keeper() {
+    for (auto& b : hblk) (void)hipHostFree(b.p);
+  }
   template <class T>
   T* put(const std::vector<T>& v, hipStream_t s) {
-    const size_t b = v.size() * sizeof(T);
-    host.emplace_back(b + 16);
-    if (b) std::memcpy(host.back().data(), v.data(), b);
-    dev.emplace_back(b + 16);
-    if (b) HIPCHK(hipMemcpyAsync(dev.back().p, host.back().data(), b, hipMemcpyHostToDevice, s));
-    return dev.back().as<T>();
+    const size_t b = (v.size() * sizeof(T) + 255) / 256 * 256 + 256;
+    if (hblk.empty() || hblk.back().used + b > hblk.back().cap) {
+      Pinned pb;
+      pb.cap = std::max<size_t>(b, (size_t)1 << 20);
+      HIPCHK(hipHostMalloc((void**)&pb.p, pb.cap, hipHostMallocDefault));
+      hblk.push_back(pb);
+    }
+    if (dblk.empty() || dused + b > dblk.back().bytes) {
+      dblk.emplace_back(std::max<size_t>(b, (size_t)4 << 20));
+      dused = 0;
+    }
+    char* hp = hblk.back().p + hblk.back().used;
+    char* dp = dblk.back().as<char>() + dused;
+    hblk.back().used += b;
+    dused += b;
+    if (!v.empty()) {
+      std::memcpy(hp, v.data(), v.size() * sizeof(T));
+      HIPCHK(hipMemcpyAsync(dp, hp, v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    }
+    return reinterpret_cast<T*>(dp);
   }
 };
 
-// Growable device workspace handed out by offsets; grow() synchronises.
+// Growable device workspace handed out by offsets.  Growth does not wait for
+// the stream: the outgrown buffer may still be in use by enqueued kernels, so
+// it is kept until the workspace is destroyed.
 struct Workspace {
   DevBuf buf;
-  void ensure(size_t bytes, hipStream_t s) {
+  std::vector<DevBuf> old;
+  void ensure(size_t bytes, hipStream_t) {
     if (buf.bytes >= bytes) return;
-    HIPCHK(hipStreamSynchronize(s));
-    buf.alloc(bytes + bytes / 4);
+    if (buf.p) old.push_back(std::move(buf));
+    buf = DevBuf(bytes + bytes / 4);
   }
   char* base() const { return static_cast<char*>(buf.p); }
 };

@@ -237,10 +237,8 @@ void node_svd(const std::vector<SvdJob>& jobs, double* M, int64_t ldm, double* U
   if (qr_only) {
     std::vector<double> eye((size_t)FAC_CMAX * R, 0.0);
     for (int i = 0; i < std::min(FAC_CMAX, R); ++i) eye[i + (size_t)i * FAC_CMAX] = 1.0;
-    kp.host.emplace_back(eye.size() * sizeof(double));
-    std::memcpy(kp.host.back().data(), eye.data(), eye.size() * sizeof(double));
-    HIPCHK(hipMemcpyAsync(EYE, kp.host.back().data(), eye.size() * sizeof(double),
-                          hipMemcpyHostToDevice, s));
+    const double* eye_d = kp.put(eye, s);
+    HIPCHK(hipMemcpyAsync(EYE, eye_d, eye.size() * sizeof(double), hipMemcpyDeviceToDevice, s));
   }
   // ---- run -------------------------------------------------------------------
   std::vector<PanelDesc*> dpd(nst);
