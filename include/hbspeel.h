@@ -29,6 +29,7 @@
 #ifndef HBSPEEL_H
 #define HBSPEEL_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -106,7 +107,7 @@ typedef struct hm_operator {
 
 typedef struct hm_options {
   int64_t n;            /* matrix size N >= 1                                    */
-  int64_t leaf_size;    /* m of Sec. 2.6: intervals of more than m indices are split
+  int64_t leaf_size;    /* m of Sec. 2.7: intervals of more than m indices are split
                            (uniform depth L = ceil(log2(N/m)), left half ceil(n/2)) */
   int32_t rank;         /* k >= 1: fixed rank (tol == 0) or rank cap (tol > 0)   */
   int32_t oversample;   /* p >= 0 (Sec. 2.5); r = rank + p samples per level     */
@@ -138,6 +139,27 @@ typedef struct hm_info {
 const char* hm_last_error(void);
 /* Build identification string (static storage). */
 const char* hm_version(void);
+
+/* Device memory (not part of the method; for callers that manage device
+ * memory themselves, e.g. a framework's caching allocator).
+ * hm_set_allocator installs alloc / free for every device allocation the
+ * library makes from then on: handle generators and node tables, and per-call
+ * scratch of compress, apply and backward.  alloc(ctx, bytes, stream) returns
+ * device memory of at least `bytes` bytes, 256-byte aligned, usable by work
+ * enqueued on `stream` (the stream passed to the entry point; NULL for calls
+ * without one), or NULL on failure (the call then fails with HM_ERR_ALLOC).
+ * free(ctx, ptr, stream) returns it with the stream it was allocated for,
+ * after the library's last use of it has been enqueued on that stream, so a
+ * stream-ordered allocator may reuse it at once.  Handle memory is returned
+ * by hm_hbs_free / hm_hodlr_free: work on other streams that reads the
+ * handle must be complete by then.  Every buffer goes back to the allocator
+ * that made it, even after hm_set_allocator is called again.  alloc == NULL
+ * (with free == NULL) restores hipMalloc / hipFree (hipMallocAsync /
+ * hipFreeAsync for scratch).  Exactly one of alloc, free NULL: HM_ERR_ARG.
+ * Not to be called while other threads are inside the library. */
+typedef void* (*hm_alloc_fn)(void* ctx, size_t bytes, void* stream);
+typedef void (*hm_free_fn)(void* ctx, void* ptr, void* stream);
+int hm_set_allocator(hm_alloc_fn alloc, hm_free_fn free, void* ctx);
 
 /* ---- test matrices (Sec. 2.5; the randn of Fig. 2/4) ---------------------
  * Writes G(i, j) for rows i = row0 .. row0+nrows-1 and columns j = 0..ncols-1
@@ -213,6 +235,35 @@ int hm_hbs_from_generators(int64_t n, int64_t leaf_size, int32_t k, int32_t dtyp
 /* Copy of a handle converted to another storage dtype (HM_F64 / HM_F32). */
 int hm_hbs_convert(const hm_hbs* h, int32_t dtype, void* stream, hm_hbs** out);
 int hm_hbs_info(const hm_hbs* h, hm_info* host_out);
+/* Device views of the generators of an HBS matrix (Sec. 2.9: leaf bases U_t,
+ * V_t, the nested bases' transfer matrices, the sibling couplings B and the
+ * diagonal blocks D_t; Fig. 4 / Fig. 5 produce them).  The pointers alias the
+ * handle's own memory (no copy): valid until hm_hbs_free, read-only (handles
+ * are immutable).  Layout (column-major, R = rank_pad, nodes = 2^(L+1) - 1,
+ * node with heap number t = 1..nodes at block index t - 1):
+ *   U, V    n x R, ld n; rows I_t of leaf t hold its basis
+ *   Ut, Vt  2R x R per node (ld 2R); rows 0..R-1 couple to the left child,
+ *           R..2R-1 to the right child; used for internal non-root nodes
+ *   B       R x R per node (ld R): A(I_sib(t), I_t) = U_sib(t) B_t V_t^*
+ *           (through the nested bases above the leaves)
+ *   D       n x nmax, ld n; rows I_t of leaf t hold D_t in columns 0..n_t-1
+ * Entries beyond a node's revealed rank are zero.  Single-tree handles only
+ * (every handle returned by the entry points is one). */
+typedef struct hm_views {
+  int32_t dtype;     /* HM_F64 or HM_F32: element type of every array */
+  int32_t rank_pad;  /* R */
+  int32_t levels;    /* L */
+  int32_t nmax;      /* columns of D (largest leaf) */
+  int64_t n;         /* rows */
+  int64_t nodes;     /* 2^(L+1) - 1 */
+  const void* U;
+  const void* V;
+  const void* Ut;
+  const void* Vt;
+  const void* B;
+  const void* D;
+} hm_views;
+int hm_hbs_generators(const hm_hbs* h, hm_views* host_out);
 int hm_hodlr_info(const hm_hodlr* h, hm_info* host_out);
 /* Generators in the flat layout above with k = info.rank_pad (zero-padded
  * beyond each node's rank), written to caller device buffers of the handle's

@@ -9,10 +9,10 @@ It follows Martinsson, "Compressing rank-structured matrices via randomized
 sampling" (arXiv 1503.07152) step by step, in the paper's order and notation,
 with NumPy/LAPACK primitives (matmul, QR, SVD) as its only library steps:
 
-* ``tree``     -- the binary index tree (Sec. 2.6, Fig. 1).
+* ``tree``     -- the binary index tree (Sec. 2.7, Fig. 1).
 * ``rng``      -- Gaussian test matrices (``randn`` of Fig. 2/4) from a
                  counter-based Philox4x32-10 stream with Box-Muller.
-* ``lowrank``  -- ``qr``/``svd``/``id`` in their three modes (Sec. 2.2-2.5).
+* ``lowrank``  -- ``qr``/``svd``/``id`` in their three modes (Sec. 2.2-2.4, 2.6).
 * ``hbs``      -- HBS representation, the partial apply of Fig. 7, the
                  storage-efficient compression of Fig. 4 and the HBS-ID
                  post-sweep of Fig. 5.

@@ -1,7 +1,7 @@
 """Reference gradients of the compressed apply ``y = A_H(U, V, Ut, Vt, B, D) x``.
 
 ``A_H`` is assembled *densely* from its generators by the definition of the
-HBS format (Sec. 2.8, eq. babytelescope): long bases by explicit telescoping
+HBS format (Sec. 2.9, eq. babytelescope): long bases by explicit telescoping
 ``Ulong_t = diag(Ulong_a, Ulong_b) Ut[t]``, every sibling block
 ``A(I_sib(v), I_v) = Ulong_sib B[v] Vlong_v^T``, diagonal leaf blocks ``D``.
 Torch CPU autograd in float64 then differentiates ``<gy, A_H x>``; no sweep,

@@ -1,7 +1,7 @@
 """HBS (= HSS) matrices: representation, the apply of Fig. 7, the
 storage-efficient compression of Fig. 4 and the HBS-ID conversion of Fig. 5.
 
-Representation (Sec. 2.8, eq. babytelescope, Def. 2.2): a leaf t stores long
+Representation (Sec. 2.9, eq. babytelescope, Def. 2.2): a leaf t stores long
 bases ``U[t]`` (n_t x k_t) and ``V[t]``; a non-root, non-leaf node t stores
 short transfers ``Ut[t]``, ``Vt[t]`` of size (k_a + k_b) x k_t with
 ``Ulong_t = diag(Ulong_a, Ulong_b) Ut[t]``; every ordered sibling pair stores

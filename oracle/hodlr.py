@@ -1,13 +1,13 @@
-"""HODLR matrices and their randomized compression (Sec. 2.7, Sec. 3, Fig. 2).
+"""HODLR matrices and their randomized compression (Sec. 2.8, Sec. 3, Fig. 2).
 
 Representation: every ordered sibling pair (a, b) on levels 1..L stores
 ``A(I_a, I_b) = U[a] B[(a,b)] V[b]^*`` with orthonormal long bases U[a]
-(n_a x k) and V[b]; leaves store ``D[t]``.  (Sec. 2.7 prints the
+(n_a x k) and V[b]; leaves store ``D[t]``.  (Sec. 2.8 prints the
 factorisation as ``U_a A~_ab U_b`` and calls ``U_a`` and ``B_b``
 orthonormal; read as ``U_a B_ab V_b^*`` with U and V orthonormal.)
 
 ``A^(l)`` keeps the sibling blocks of levels 1..l and zeroes everything
-finer (Sec. 2.7); its apply costs O(l k N) (eq. dev2).
+finer (Sec. 2.8); its apply costs O(l k N) (eq. dev2).
 
 Fig. 2 uses the SVD variant (eq. SVDtogetV / SVDtogetB), so every B is
 diagonal; Fig. 2 names the third SVD output of the second call

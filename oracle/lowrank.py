@@ -1,7 +1,7 @@
-"""The functions ``qr``, ``svd`` and ``id`` of Sec. 2.5 in their modes
+"""The functions ``qr``, ``svd`` and ``id`` of Sec. 2.6 in their modes
 (full / rank k / tolerance eps), Sec. 2.2-2.4.
 
-As the paper does for small inputs (Sec. 2.5), mode 2 and mode 3 compute a
+As the paper does for small inputs (Sec. 2.6), mode 2 and mode 3 compute a
 full factorisation with LAPACK and truncate it.
 
 Reading of the tolerance (the paper states ``||A - ...|| <= eps`` with eps in

@@ -1,4 +1,4 @@
-"""Binary index tree (Sec. 2.6 "A binary tree structure", Fig. 1).
+"""Binary index tree (Sec. 2.7 "A binary tree structure", Fig. 1).
 
 The root holds ``I_1 = [0, N)``; a node's interval is split into two roughly
 equal halves, children of node t are 2t and 2t+1 (Fig. 1 numbering), and

@@ -10,6 +10,7 @@ fallback path.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
 
@@ -21,7 +22,7 @@ __all__ = [
     "Options", "KernelOperator", "DenseOperator", "HBSOperator", "CallbackOperator",
     "HBS", "HODLR", "hm_gauss", "hm_operator_apply", "hbs_compress", "hodlr_compress", "hbs_compress_batched",
     "hss_apply", "hss_apply_adjoint", "hss_apply_backward", "hodlr_apply",
-    "hm_hbs_from_generators", "hbs_from_tensors", "HBSApply", "hbs_apply",
+    "hm_hbs_from_generators", "hbs_from_tensors", "HBSApply", "hbs_apply", "use_torch_allocator",
 ]
 
 HM_OK, HM_WARN_RANK_SATURATED = 0, 1
@@ -66,6 +67,16 @@ class _Info(C.Structure):
                 ("pad_", C.c_int32)]
 
 
+class _Views(C.Structure):
+    _fields_ = [("dtype", C.c_int32), ("rank_pad", C.c_int32), ("levels", C.c_int32),
+                ("nmax", C.c_int32), ("n", C.c_int64), ("nodes", C.c_int64),
+                ("U", C.c_void_p), ("V", C.c_void_p), ("Ut", C.c_void_p), ("Vt", C.c_void_p),
+                ("B", C.c_void_p), ("D", C.c_void_p)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
 _P, _I64, _I32 = C.c_void_p, C.c_int64, C.c_int32
 _SIGS = {
     "hm_last_error": (C.c_char_p, []),
@@ -86,6 +97,8 @@ _SIGS = {
                                          C.POINTER(_P)]),
     "hm_hbs_convert": (C.c_int, [_P, _I32, _P, C.POINTER(_P)]),
     "hm_hbs_info": (C.c_int, [_P, C.POINTER(_Info)]),
+    "hm_hbs_generators": (C.c_int, [_P, C.POINTER(_Views)]),
+    "hm_set_allocator": (C.c_int, [ALLOC_FN, FREE_FN, _P]),
     "hm_hodlr_info": (C.c_int, [_P, C.POINTER(_Info)]),
     "hm_hbs_export": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "hm_hodlr_export": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
@@ -220,6 +233,61 @@ def _info(fn, handle):
     return {k: getattr(inf, k) for k, _ in _Info._fields_}
 
 
+class _DeviceArray:
+    """A device array of a handle's memory, handed to torch through the CUDA
+    array interface (zero-copy); holds the handle so the memory outlives the
+    tensor."""
+
+    def __init__(self, owner, ptr, shape, strides, dtype):
+        self.owner = owner
+        typestr = "<f8" if dtype == torch.float64 else "<f4"
+        es = 8 if dtype == torch.float64 else 4
+        self.__cuda_array_interface__ = {
+            "shape": tuple(shape), "typestr": typestr, "data": (ptr, False), "version": 2,
+            "strides": tuple(st * es for st in strides)}
+
+
+def _alias(owner, ptr, shape, strides, dtype):
+    return torch.as_tensor(_DeviceArray(owner, ptr, shape, strides, dtype), device="cuda")
+
+
+_ALLOC_STATE = {"hooks": None, "exiting": False}
+
+
+def use_torch_allocator(enable=True):
+    """Route every device allocation of the library (handle memory, per-call
+    scratch) through torch's caching allocator (``hm_set_allocator``), or back
+    to hipMalloc / hipFree.  Memory is allocated and returned on the stream
+    of the call that needs it; buffers keep the allocator that made them."""
+    if not enable:
+        _check(lib.hm_set_allocator(ALLOC_FN(), FREE_FN(), None))
+        return
+
+    def alloc(ctx, nbytes, stream):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+        except Exception:   # reported to the library as an allocation failure
+            return None
+
+    def free(ctx, ptr, stream):
+        if _ALLOC_STATE["exiting"]:
+            return   # torch may already be torn down; the process is ending
+        try:
+            torch.cuda.caching_allocator_delete(int(ptr))
+        except Exception:
+            pass
+
+    hooks = (ALLOC_FN(alloc), FREE_FN(free))
+    _check(lib.hm_set_allocator(hooks[0], hooks[1], None))
+    # every buffer made through these hooks calls them when it is freed, so
+    # they stay referenced for the life of the process
+    _ALLOC_STATE.setdefault("all", []).append(hooks)
+    _ALLOC_STATE["hooks"] = hooks
+
+
+atexit.register(lambda: _ALLOC_STATE.__setitem__("exiting", True))
+
+
 class HBS:
     """An HBS handle owned by the library."""
 
@@ -268,6 +336,23 @@ class HBS:
         out.update(rank_u=ru, rank_v=rv, skel_in=si.reshape(nn, R), skel_out=so.reshape(nn, R),
                    n=n, R=R, L=L, leaf=inf["leaf_size"], is_id=inf["is_id"])
         return out
+
+    def generators(self):
+        """Zero-copy device views of the handle's generators (``hm_hbs_generators``):
+        U, V (n, R); Ut, Vt (nodes, 2R, R) and B (nodes, R, R), node with heap
+        number t at index t - 1; D (n, nmax).  Read-only; each tensor keeps the
+        handle alive."""
+        v = _Views()
+        _check(lib.hm_hbs_generators(self.handle, C.byref(v)))
+        dt = torch.float64 if v.dtype == HM_F64 else torch.float32
+        n, R, nn = v.n, v.rank_pad, v.nodes
+        return dict(
+            U=_alias(self, v.U, (n, R), (1, n), dt), V=_alias(self, v.V, (n, R), (1, n), dt),
+            Ut=_alias(self, v.Ut, (nn, 2 * R, R), (2 * R * R, 1, 2 * R), dt),
+            Vt=_alias(self, v.Vt, (nn, 2 * R, R), (2 * R * R, 1, 2 * R), dt),
+            B=_alias(self, v.B, (nn, R, R), (R * R, 1, R), dt),
+            D=_alias(self, v.D, (n, v.nmax), (1, n), dt),
+            n=n, R=R, L=v.levels, nodes=nn)
 
     @staticmethod
     def _nmax(n, leaf, L):

@@ -86,9 +86,8 @@ static void backward_impl(const hm_hbs* h, int c, const T* x, int64_t ldx, const
   const int R = h->R;
   const int nn = (int)f.nodes.size();
   const size_t wb = apply_work_bytes<T>(f, h->full, R, c);
-  void *w1 = nullptr, *w2 = nullptr;
-  HIPCHK(hipMallocAsync(&w1, wb, s));
-  HIPCHK(hipMallocAsync(&w2, wb, s));
+  StreamBuf sb1(wb, s), sb2(wb, s);
+  void *w1 = sb1.p, *w2 = sb2.p;
   const HbsView<T> hv = h->view<T>();
   // forward expansions (outgoing qh, incoming uh) of x
   apply_forest<T>(h->d_nodes.as<Node>(), h->full, hv, false, c, x, ldx, (T*)nullptr, N, T(1),
@@ -117,8 +116,6 @@ static void backward_impl(const hm_hbs* h, int c, const T* x, int64_t ldx, const
   launch_grad<T>(h->d_nodes.as<Node>(), h->grad_leaves.as<int32_t>(), (int)f.leaves.size(), maxl,
                  f.nmax, h->grad_nodes.as<int32_t>(), nn, R, c, x, ldx, gy, ldgy, QH, UH, GU, GQ,
                  gU, gV, gUt, gVt, gB, gD, N, N, s);
-  HIPCHK(hipFreeAsync(w1, s));
-  HIPCHK(hipFreeAsync(w2, s));
 }
 
 extern "C" {
@@ -126,9 +123,23 @@ extern "C" {
 const char* hm_last_error(void) { return get_error(); }
 const char* hm_version(void) { return "hbspeel 0.1 (gfx950)"; }
 
+int hm_set_allocator(hm_alloc_fn alloc, hm_free_fn free, void* ctx) {
+  return guarded([&] {
+    if ((alloc == nullptr) != (free == nullptr))
+      HM_THROW(HM_ERR_ARG, "set_allocator: alloc and free must both be set or both be NULL");
+    AllocHook hk;
+    hk.alloc = alloc;
+    hk.free = free;
+    hk.ctx = alloc ? ctx : nullptr;
+    set_alloc_hook(hk);
+    return HM_OK;
+  });
+}
+
 int hm_gauss(uint64_t seed, int32_t level, int32_t phase, int64_t row0, int64_t nrows,
              int32_t ncols, double* out, int64_t ld, void* stream) {
   return guarded([&] {
+    StreamScope scope(stream);
     if (!out || nrows < 0 || ncols < 0 || ld < nrows || row0 < 0)
       HM_THROW(HM_ERR_ARG, "hm_gauss: bad arguments");
     launch_gauss_raw(seed, level, phase, row0, nrows, ncols, out, ld, (hipStream_t)stream);
@@ -139,6 +150,7 @@ int hm_gauss(uint64_t seed, int32_t level, int32_t phase, int64_t row0, int64_t 
 int hm_operator_apply(const hm_operator* op, int64_t n, int32_t adjoint, int64_t ncols,
                       const double* X, int64_t ldx, double* Y, int64_t ldy, void* stream) {
   return guarded([&] {
+    StreamScope scope(stream);
     if (n < 1 || ncols < 0 || !X || !Y || ldx < n || ldy < n)
       HM_THROW(HM_ERR_ARG, "operator_apply: bad arguments");
     check_operator(op, n, false);
@@ -159,6 +171,7 @@ int hm_operator_apply(const hm_operator* op, int64_t n, int32_t adjoint, int64_t
 int hbs_compress(const hm_options* opts, const hm_operator* op, void* stream, hm_hbs** out) {
   if (out) *out = nullptr;
   return guarded([&] {
+    StreamScope scope(stream);
     if (!out) HM_THROW(HM_ERR_ARG, "out is NULL");
     check_options(opts);
     check_operator(op, opts->n, false);
@@ -180,6 +193,7 @@ int hbs_compress_batched(int32_t count, const hm_options* opts, const hm_operato
   if (outs && count > 0)
     for (int i = 0; i < count; ++i) outs[i] = nullptr;
   return guarded([&]() -> int {
+    StreamScope scope(stream);
     if (count < 1 || !opts || !ops || !outs) HM_THROW(HM_ERR_ARG, "batched: bad arguments");
     hipStream_t s = (hipStream_t)stream;
     Forest f;
@@ -223,6 +237,7 @@ int hbs_compress_batched(int32_t count, const hm_options* opts, const hm_operato
 int hodlr_compress(const hm_options* opts, const hm_operator* op, void* stream, hm_hodlr** out) {
   if (out) *out = nullptr;
   return guarded([&]() -> int {
+    StreamScope scope(stream);
     if (!out) HM_THROW(HM_ERR_ARG, "out is NULL");
     check_options(opts);
     check_operator(op, opts->n, false);
@@ -239,6 +254,7 @@ int hodlr_compress(const hm_options* opts, const hm_operator* op, void* stream, 
 static int apply_impl(const hm_hbs* h, bool adjoint, int64_t nrhs, const void* x, int64_t ldx,
                       void* y, int64_t ldy, void* stream) {
   return guarded([&] {
+    StreamScope scope(stream);
     if (!h || !x || !y || nrhs < 0) HM_THROW(HM_ERR_ARG, "apply: bad arguments");
     const int64_t n = h->f.n_total;
     if (ldx < n || ldy < n) HM_THROW(HM_ERR_ARG, "apply: ld < n");
@@ -248,23 +264,17 @@ static int apply_impl(const hm_hbs* h, bool adjoint, int64_t nrhs, const void* x
     for (int64_t c0 = 0; c0 < nrhs; c0 += cmax) {
       const int c = (int)std::min<int64_t>(cmax, nrhs - c0);
       if (h->dtype == HM_F64) {
-        const size_t wb = apply_work_bytes<double>(h->f, h->full, h->R, c);
-        void* w = nullptr;
-        HIPCHK(hipMallocAsync(&w, wb, s));
+        StreamBuf w(apply_work_bytes<double>(h->f, h->full, h->R, c), s);
         apply_forest<double>(h->d_nodes.as<Node>(), h->full, h->view<double>(), adjoint, c,
                              static_cast<const double*>(x) + c0 * ldx, ldx,
-                             static_cast<double*>(y) + c0 * ldy, ldy, 1.0, 0.0, w,
+                             static_cast<double*>(y) + c0 * ldy, ldy, 1.0, 0.0, w.p,
                              h->f.nodes.size(), s);
-        HIPCHK(hipFreeAsync(w, s));
       } else {
-        const size_t wb = apply_work_bytes<float>(h->f, h->full, h->R, c);
-        void* w = nullptr;
-        HIPCHK(hipMallocAsync(&w, wb, s));
+        StreamBuf w(apply_work_bytes<float>(h->f, h->full, h->R, c), s);
         apply_forest<float>(h->d_nodes.as<Node>(), h->full, h->view<float>(), adjoint, c,
                             static_cast<const float*>(x) + c0 * ldx, ldx,
-                            static_cast<float*>(y) + c0 * ldy, ldy, 1.0f, 0.0f, w,
+                            static_cast<float*>(y) + c0 * ldy, ldy, 1.0f, 0.0f, w.p,
                             h->f.nodes.size(), s);
-        HIPCHK(hipFreeAsync(w, s));
       }
     }
     return HM_OK;
@@ -286,6 +296,7 @@ int hm_hbs_from_generators(int64_t n, int64_t leaf_size, int32_t k, int32_t dtyp
                            const void* D, void* stream, hm_hbs** out) {
   if (out) *out = nullptr;
   return guarded([&] {
+    StreamScope scope(stream);
     if (!out || n < 1 || leaf_size < 1 || k < 1 || !U || !V || !Ut || !Vt || !B || !D)
       HM_THROW(HM_ERR_ARG, "from_generators: bad arguments");
     if (dtype != HM_F64 && dtype != HM_F32) HM_THROW(HM_ERR_ARG, "dtype must be F64 or F32");
@@ -346,6 +357,7 @@ int hm_hbs_from_generators(int64_t n, int64_t leaf_size, int32_t k, int32_t dtyp
 int hm_hbs_convert(const hm_hbs* h, int32_t dtype, void* stream, hm_hbs** out) {
   if (out) *out = nullptr;
   return guarded([&]() -> int {
+    StreamScope scope(stream);
     if (!h || !out) HM_THROW(HM_ERR_ARG, "convert: bad arguments");
     HM_THROW(HM_ERR_UNSUPPORTED, "conversion is not built yet");
   });
@@ -359,10 +371,33 @@ int hm_hbs_info(const hm_hbs* h, hm_info* o) {
   });
 }
 
+int hm_hbs_generators(const hm_hbs* h, hm_views* o) {
+  return guarded([&] {
+    if (!h || !o) HM_THROW(HM_ERR_ARG, "generators: bad arguments");
+    if (h->f.inst.size() != 1) HM_THROW(HM_ERR_ARG, "generators: single-tree handles only");
+    hm_views v{};
+    v.dtype = h->dtype;
+    v.rank_pad = h->R;
+    v.levels = h->f.inst[0].L;
+    v.nmax = h->f.nmax;
+    v.n = h->f.n_total;
+    v.nodes = (int64_t)h->f.nodes.size();
+    v.U = h->U.p;
+    v.V = h->V.p;
+    v.Ut = h->Ut.p;
+    v.Vt = h->Vt.p;
+    v.B = h->B.p;
+    v.D = h->D.p;
+    *o = v;
+    return HM_OK;
+  });
+}
+
 int hm_hbs_export(const hm_hbs* h, void* U, void* V, void* Ut, void* Vt, void* B, void* D,
                   int32_t* ranks_u, int32_t* ranks_v, int32_t* skel_in, int32_t* skel_out,
                   void* stream) {
   return guarded([&] {
+    StreamScope scope(stream);
     if (!h) HM_THROW(HM_ERR_ARG, "export: NULL handle");
     hipStream_t s = (hipStream_t)stream;
     const Forest& f = h->f;
@@ -405,6 +440,7 @@ int hss_apply_backward(const hm_hbs* h, int64_t nrhs, const void* x, int64_t ldx
                        int64_t ldgy, void* gx, int64_t ldgx, void* gU, void* gV, void* gUt,
                        void* gVt, void* gB, void* gD, void* stream) {
   return guarded([&] {
+    StreamScope scope(stream);
     if (!h || !x || !gy || !gx || nrhs < 1) HM_THROW(HM_ERR_ARG, "backward: bad arguments");
     const int64_t n = h->f.n_total;
     if (ldx < n || ldgy < n || ldgx < n) HM_THROW(HM_ERR_ARG, "backward: ld < n");
@@ -427,6 +463,7 @@ int hss_apply_backward(const hm_hbs* h, int64_t nrhs, const void* x, int64_t ldx
 int hodlr_apply(const hm_hodlr* h, int32_t adjoint, int64_t nrhs, const double* x, int64_t ldx,
                 double* y, int64_t ldy, void* stream) {
   return guarded([&] {
+    StreamScope scope(stream);
     if (!h || !x || !y || nrhs < 0) HM_THROW(HM_ERR_ARG, "hodlr_apply: bad arguments");
     const int64_t n = h->f.n_total;
     if (ldx < n || ldy < n) HM_THROW(HM_ERR_ARG, "hodlr_apply: ld < n");
@@ -450,6 +487,7 @@ int hm_hodlr_info(const hm_hodlr* h, hm_info* o) {
 int hm_hodlr_export(const hm_hodlr* h, double* U, double* V, double* s, double* D, int32_t* ranks,
                     void* stream) {
   return guarded([&] {
+    StreamScope scope(stream);
     if (!h) HM_THROW(HM_ERR_ARG, "export: NULL handle");
     hipStream_t st = (hipStream_t)stream;
     const int64_t n = h->f.n_total;

@@ -54,7 +54,7 @@ void apply_forest(const Node* d_nodes, const ApplyLists& al, const HbsView<T>& h
                   int c, const T* X, int64_t ldx, T* Y, int64_t ldy, T alpha, T beta, void* work,
                   size_t nnodes, hipStream_t s, bool expansions_only = false);
 
-// One level of a HODLR apply (Sec. 2.7): for the frontier nodes v (one tree
+// One level of a HODLR apply (Sec. 2.8): for the frontier nodes v (one tree
 // level), Y(I_a) = beta Y(I_a) + alpha U(I_a) diag(s[b]) V(I_b)^T X(I_b) with
 // b = sib(a); adjoint: Y(I_b) += alpha V(I_b) diag(s[b]) U(I_a)^T X(I_a).
 template <class T>

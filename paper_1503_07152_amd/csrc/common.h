@@ -38,7 +38,7 @@ struct Error {
 #define KCHK() HIPCHK(hipGetLastError())
 
 // ------------------------------------------------------------ forest --------
-// A forest of binary index trees (Sec. 2.6) over one global row space: one
+// A forest of binary index trees (Sec. 2.7) over one global row space: one
 // tree per instance (a single compression is a forest of one tree).  Every
 // node carries global row bounds and explicit parent/child/sibling ids, so
 // kernels take node lists instead of heap arithmetic.
@@ -83,23 +83,64 @@ void forest_add_tree(Forest& f, int64_t n, int64_t leaf, int32_t r, int32_t k,
 void forest_finish(Forest& f);
 
 // ------------------------------------------------------------- memory -------
+// Device memory comes from hipMalloc / hipFree, or from the caller's allocator
+// once hm_set_allocator has installed one.  Every buffer remembers the
+// allocator that made it and the stream it was made for, and goes back to that
+// allocator on that stream, even if the allocator has been changed since.
+struct AllocHook {
+  hm_alloc_fn alloc = nullptr;
+  hm_free_fn free = nullptr;
+  void* ctx = nullptr;
+};
+AllocHook alloc_hook();
+void set_alloc_hook(const AllocHook& h);
+
+// Stream of the entry point running on this thread, handed to the caller's
+// allocator (set for the extent of a call by StreamScope; default NULL).
+hipStream_t alloc_stream();
+struct StreamScope {
+  hipStream_t prev;
+  explicit StreamScope(void* s);
+  ~StreamScope();
+  StreamScope(const StreamScope&) = delete;
+  StreamScope& operator=(const StreamScope&) = delete;
+};
+
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  AllocHook hook;             // allocator that made p (alloc == nullptr: hipMalloc)
+  hipStream_t stream = nullptr;
   DevBuf() = default;
   explicit DevBuf(size_t b) { alloc(b); }
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), hook(o.hook), stream(o.stream) {
+    o.p = nullptr;
+    o.bytes = 0;
+  }
   DevBuf& operator=(DevBuf&& o) noexcept {
     release();
-    p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0;
+    p = o.p; bytes = o.bytes; hook = o.hook; stream = o.stream;
+    o.p = nullptr; o.bytes = 0;
     return *this;
   }
   ~DevBuf() { release(); }
   void alloc(size_t b);
   void release();
   template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Per-call scratch ordered on a stream: hipMallocAsync / hipFreeAsync, or the
+// caller's allocator.
+struct StreamBuf {
+  void* p = nullptr;
+  AllocHook hook;
+  hipStream_t stream = nullptr;
+  StreamBuf(size_t b, hipStream_t s);
+  ~StreamBuf();
+  StreamBuf(const StreamBuf&) = delete;
+  StreamBuf& operator=(const StreamBuf&) = delete;
 };
 
 // Upload a host vector into a fresh device buffer (synchronous w.r.t. host

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
+#include <mutex>
 
 #include "common.h"
 
@@ -23,22 +24,74 @@ void set_error(const char* fmt, ...) {
 }
 const char* get_error() { return g_err.c_str(); }
 
+// ------------------------------------------------------------------ memory
+static std::mutex g_hook_mu;
+static AllocHook g_hook;
+static thread_local hipStream_t g_alloc_stream = nullptr;
+
+AllocHook alloc_hook() {
+  std::lock_guard<std::mutex> lk(g_hook_mu);
+  return g_hook;
+}
+void set_alloc_hook(const AllocHook& h) {
+  std::lock_guard<std::mutex> lk(g_hook_mu);
+  g_hook = h;
+}
+hipStream_t alloc_stream() { return g_alloc_stream; }
+StreamScope::StreamScope(void* s) : prev(g_alloc_stream) { g_alloc_stream = (hipStream_t)s; }
+StreamScope::~StreamScope() { g_alloc_stream = prev; }
+
 void DevBuf::alloc(size_t b) {
   release();
   if (b == 0) b = 16;
-  hipError_t e = hipMalloc(&p, b);
-  if (e != hipSuccess) {
-    p = nullptr;
-    (void)hipGetLastError();
-    HM_THROW(HM_ERR_ALLOC, "hipMalloc(%zu bytes) failed: %s", b, hipGetErrorString(e));
+  hook = alloc_hook();
+  stream = g_alloc_stream;
+  if (hook.alloc) {
+    p = hook.alloc(hook.ctx, b, stream);
+    if (!p) HM_THROW(HM_ERR_ALLOC, "caller's allocator returned NULL for %zu bytes", b);
+  } else {
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      HM_THROW(HM_ERR_ALLOC, "hipMalloc(%zu bytes) failed: %s", b, hipGetErrorString(e));
+    }
   }
   bytes = b;
 }
 
 void DevBuf::release() {
-  if (p) (void)hipFree(p);
+  if (p) {
+    if (hook.alloc)
+      hook.free(hook.ctx, p, stream);
+    else
+      (void)hipFree(p);
+  }
   p = nullptr;
   bytes = 0;
+}
+
+StreamBuf::StreamBuf(size_t b, hipStream_t s) : hook(alloc_hook()), stream(s) {
+  if (b == 0) b = 16;
+  if (hook.alloc) {
+    p = hook.alloc(hook.ctx, b, s);
+    if (!p) HM_THROW(HM_ERR_ALLOC, "caller's allocator returned NULL for %zu bytes", b);
+  } else {
+    hipError_t e = hipMallocAsync(&p, b, s);
+    if (e != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      HM_THROW(HM_ERR_ALLOC, "hipMallocAsync(%zu bytes) failed: %s", b, hipGetErrorString(e));
+    }
+  }
+}
+
+StreamBuf::~StreamBuf() {
+  if (!p) return;
+  if (hook.alloc)
+    hook.free(hook.ctx, p, stream);
+  else
+    (void)hipFreeAsync(p, stream);
 }
 
 // ------------------------------------------------------------------ forest

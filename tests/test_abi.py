@@ -21,7 +21,9 @@ def declared_functions():
 def test_header_lists_the_boundary():
     names = declared_functions()
     for must in ("hodlr_compress", "hbs_compress", "hss_apply", "hss_apply_adjoint",
-                 "hss_apply_backward", "hbs_compress_batched", "hm_gauss", "hm_operator_apply"):
+                 "hss_apply_backward", "hbs_compress_batched", "hm_gauss", "hm_operator_apply",
+                 "hm_hbs_info", "hm_hbs_generators", "hm_set_allocator", "hm_hbs_free",
+                 "hm_last_error"):
         assert must in names
 
 
@@ -69,3 +71,15 @@ def test_invalid_operator_rejected_on_host():
     assert hm.lib.hbs_compress(C.byref(opts.c), C.byref(op), None, C.byref(h)) == -1
     op.kind = hm.HM_OP_DENSE          # dense without a matrix
     assert hm.lib.hbs_compress(C.byref(opts.c), C.byref(op), None, C.byref(h)) == -1
+
+
+def test_allocator_and_views_argument_checks_on_host():
+    import paper_1503_07152_amd as hm
+    # exactly one of alloc / free set is an argument error; both NULL restores hipMalloc
+    alloc = hm.ALLOC_FN(lambda ctx, n, s: None)
+    assert hm.lib.hm_set_allocator(alloc, hm.FREE_FN(), None) == -1
+    assert hm.lib.hm_set_allocator(hm.ALLOC_FN(), hm.FREE_FN(lambda c, p, s: None), None) == -1
+    assert hm.lib.hm_set_allocator(hm.ALLOC_FN(), hm.FREE_FN(), None) == 0
+    v = hm._Views()
+    assert hm.lib.hm_hbs_generators(None, C.byref(v)) == -1
+    assert "generators" in hm.lib.hm_last_error().decode()
