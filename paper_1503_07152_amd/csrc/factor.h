@@ -29,21 +29,57 @@ struct PanelDesc {
   int32_t ncol;
   int32_t trans;    // QR: the panel is the transpose of A (A stored cols x rows);
                     // the factored panel is written back untransposed, ld ld
+  const int32_t* dyn_cols;  // optional (device): the panel has min(cols, *dyn_cols)
+                            // columns, known only on the device (a revealed rank)
+  const int32_t* perm;      // optional (device): apply writes row i of the result
+                            // to row perm[i] of Cout
+  int32_t cin_full;         // apply: Cin holds all `rows` rows (Cout = Q Cin)
+                            // instead of the first min(rows, cols)
+  int32_t pad_;
 };
 
 struct SvdDesc {
   const double* R;  // h x c (h <= c), leading dim ldR; c x h when trans
   int64_t ldR;
   int32_t h, c;
-  double* W;        // left singular vectors, h x kout (descending singular values)
+  double* W;        // left singular vectors, wrows x kout (descending singular values)
   int64_t ldW;
   double* sv;       // kout singular values
-  double* X;        // right singular vectors, c x kout (may be null)
+  double* X;        // right singular vectors, xrows x kout (may be null)
   int64_t ldX;
-  int32_t kout;     // columns of W / X written (those beyond c are zero)
+  int32_t kout;     // columns of W / X written
   int32_t trans;    // 1: factor R^T (R stored c x h)
   int32_t* sweeps;  // optional: atomic max of the Jacobi sweeps used
+  const int32_t* dyn;  // optional (device): h = c = min(c, *dyn), a revealed rank
+  int32_t wrows, xrows;  // frames the singular vectors are embedded in (>= h, >= c):
+                         // rows beyond h (c) are zero, and output columns
+                         // j >= c get the unit vector e_j (zero if j >= wrows /
+                         // xrows) with singular value 0, an orthonormal completion
+  int32_t xscaled;       // 1: X receives X diag(s) = T^T W (needs trans = 0), formed
+                         // from the converged left vectors; no rotations accumulated
+  int32_t pad_;
 };
+
+// Column-pivoted Householder QR of A = R^T (c x h, R stored h x c) that stops
+// at the numerical rank rho: the first step k >= kmin whose largest remaining
+// column norm is <= eta times the largest initial one (or any step at an
+// exactly zero remainder).  A P = Q2 [R2; *] with the dropped trailing block.
+struct QrcpDesc {
+  double* R;        // in: h x c, ld ldR; out: the reflectors of A (column k in
+                    // rows k+1 .. c-1, unit diagonal implied), c x h, ld ldR
+  int64_t ldR;
+  int32_t c, h;
+  double* tau;      // rho reflector scalars
+  double* T;        // compact WY factors per QR_NB strip (as PanelDesc.T)
+  double* R2;       // rho x h, upper trapezoidal (zero below the diagonal), ld ldR2
+  int64_t ldR2;
+  int32_t* perm;    // h: column j of A P is column perm[j] of A
+  int32_t* rho;     // the numerical rank
+  double eta;       // relative threshold (<= 0: max(c, h) eps)
+  int32_t kmin;     // steps taken whatever the threshold (stops only at a zero column)
+  int32_t pad_;
+};
+void launch_qrcp(const QrcpDesc* d, int n, hipStream_t s);
 
 void launch_panel_qr(const PanelDesc* d, int n, hipStream_t s);
 void launch_apply_q(const PanelDesc* d, int n, hipStream_t s);
@@ -57,6 +93,7 @@ void launch_build_node_block(const Node* nodes, const Instance* inst, const int3
                              const double* Lpar, int64_t ldl, const double* w, double* M,
                              int64_t ldm, hipStream_t s, int first_half_only = 0);
 // B[v] = X_v(0:r, 0:r) diag(z_v) (zero-padded to R x R); X_v at X + v*2R*R, ld 2R.
+// z == nullptr: X already holds X diag(z).
 void launch_form_b(const Node* nodes, const Instance* inst, const int32_t* kids, int nkids, int R,
                    const double* X, const double* z, double* B, hipStream_t s);
 

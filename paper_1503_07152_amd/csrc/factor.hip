@@ -143,7 +143,7 @@ __global__ __launch_bounds__(FT) void k_panel_qr(const PanelDesc* descs) {
   __shared__ double sVV[QR_NB][QR_NB + 1];
   __shared__ double sT[QR_NB][QR_NB + 1];
   const PanelDesc d = descs[blockIdx.x];
-  const int m = d.rows, n = d.cols;
+  const int m = d.rows, n = d.dyn_cols ? max(0, min(d.cols, *d.dyn_cols)) : d.cols;
   const int lds = (m & 1) ? m : m + 1;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int idx = tid; idx < m * n; idx += FT) {
@@ -319,7 +319,9 @@ __global__ __launch_bounds__(64 * APQ_WAVES) void k_apply_q(const PanelDesc* des
   __shared__ double sTb[QR_NB * QR_NB];
   const PanelDesc d = descs[blockIdx.x / tiles];
   const int tile = (blockIdx.x % tiles) * APQ_WAVES + (threadIdx.x >> 6);
-  const int m = d.rows, h = min(d.rows, d.cols), nc = d.ncol;
+  const int ncols = d.dyn_cols ? max(0, min(d.cols, *d.dyn_cols)) : d.cols;
+  const int m = d.rows, h = min(d.rows, ncols), nc = d.ncol;
+  const int hin = d.cin_full ? m : h;   // rows of Cin
   const int tid = threadIdx.x, lane = tid & 63, kq = lane >> 4, bl = lane & 15;
   const int cl = 16 * tile + bl;
   const bool act = 16 * tile < nc;
@@ -329,7 +331,7 @@ __global__ __launch_bounds__(64 * APQ_WAVES) void k_apply_q(const PanelDesc* des
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int r = 16 * rt + kq + 4 * v;
-      cacc[rt][v] = (act && r < h && cl < nc) ? d.Cin[r + (int64_t)cl * d.ldCin] : 0.0;
+      cacc[rt][v] = (act && r < hin && cl < nc) ? d.Cin[r + (int64_t)cl * d.ldCin] : 0.0;
     }
   auto vs = [&](int r, int b) -> double { return r < m ? sV[r + b * FAC_PMAX] : 0.0; };
   const int nstrips = (h + QR_NB - 1) / QR_NB;
@@ -386,7 +388,7 @@ __global__ __launch_bounds__(64 * APQ_WAVES) void k_apply_q(const PanelDesc* des
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int r = 16 * rt + kq + 4 * v;
-      if (r < m && cl < nc) d.Cout[r + (int64_t)cl * d.ldCout] = cacc[rt][v];
+      if (r < m && cl < nc) d.Cout[(d.perm ? d.perm[r] : r) + (int64_t)cl * d.ldCout] = cacc[rt][v];
     }
 }
 
@@ -397,6 +399,193 @@ void launch_apply_q(const PanelDesc* d, int n, hipStream_t s) {
   KCHK();
 }
 
+// ------------------------------------------------------------ pivoted QR --
+// Householder QR with column pivoting (Businger-Golub) of A = R^T, c x h <= 96
+// x 96 in LDS, stopped at the numerical rank: a step whose largest remaining
+// squared column norm is <= (max(c, h) eps)^2 times the largest initial one
+// ends the factorisation, and the trailing block (below that threshold) is
+// dropped.  Column swaps are logical (a column map in LDS); remaining column
+// norms are recomputed exactly at every step, so no downdating is involved.
+// One barrier per step between the reflector (wave 0) and its application to
+// the trailing columns (all waves, one column per wave at a time), one after.
+constexpr int QP_LD = FAC_CMAX + 1;
+constexpr int QP_RPL = FAC_CMAX / 16;   // rows per lane of a 16-lane group
+
+__device__ __forceinline__ double max64(double v) {
+  v = fmax(v, dpp_d<0xB1>(v));
+  v = fmax(v, dpp_d<0x4E>(v));
+  v = fmax(v, dpp_d<0x141>(v));
+  v = fmax(v, dpp_d<0x140>(v));
+  {
+    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(v), __double2loint(v), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(v), __double2hiint(v), false, false);
+    v = fmax(__hiloint2double(hi[0], lo[0]), __hiloint2double(hi[1], lo[1]));
+  }
+  {
+    const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(v), __double2loint(v), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(v), __double2hiint(v), false, false);
+    v = fmax(__hiloint2double(hi[0], lo[0]), __hiloint2double(hi[1], lo[1]));
+  }
+  return v;
+}
+
+__global__ __launch_bounds__(FT) void k_qrcp(const QrcpDesc* descs) {
+  __shared__ double sA[QP_LD * FAC_CMAX];
+  __shared__ double snrm[FAC_CMAX];
+  __shared__ int scol[FAC_CMAX];
+  __shared__ double sTau[FAC_CMAX];
+  __shared__ double sVV[QR_TMAX][QR_NB][QR_NB + 1];
+  __shared__ double sT[QR_TMAX][QR_NB][QR_NB + 1];
+  const QrcpDesc d = descs[blockIdx.x];
+  const int c = d.c, h = d.h;   // A = R^T: c rows, h columns
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int idx = tid; idx < c * h; idx += FT) {
+    const int i = idx % c, j = idx / c;
+    sA[i + j * QP_LD] = d.R[j + (int64_t)i * d.ldR];
+  }
+  for (int j = tid; j < h; j += FT) scol[j] = j;
+  __syncthreads();
+  for (int j = wave; j < h; j += FW) {
+    double s2 = 0.0;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int r = lane + 64 * t;
+      const double a = r < c ? sA[r + j * QP_LD] : 0.0;
+      s2 = fma(a, a, s2);
+    }
+    s2 = sum64(s2);
+    if (lane == 0) snrm[j] = s2;
+  }
+  __syncthreads();
+  const int kmax = min(c, h);
+  const double eta = d.eta > 0.0 ? d.eta : (double)max(c, h) * DBL_EPSILON;
+  double thr2 = 0.0;
+  int rho = kmax;
+  for (int k = 0; k < kmax; ++k) {
+    // pivot: the largest remaining squared norm, the lowest index on ties
+    // (every wave finds the same one)
+    const int j1 = k + lane, j2 = k + lane + 64;
+    const double v1 = j1 < h ? snrm[j1] : -1.0;
+    const double v2 = j2 < h ? snrm[j2] : -1.0;
+    const double vmax = max64(fmax(v1, v2));
+    const uint64_t m1 = __ballot(v1 == vmax), m2 = __ballot(v2 == vmax);
+    const int p = m1 ? k + __ffsll((unsigned long long)m1) - 1
+                     : k + 64 + __ffsll((unsigned long long)m2) - 1;
+    if (k == 0) thr2 = eta * eta * vmax;
+    if (!(vmax > 0.0) || (k >= d.kmin && !(vmax > thr2))) {   // numerical rank reached
+      rho = k;
+      break;
+    }
+    const int pk = scol[p], pp = scol[k];   // physical columns entering positions k and p
+    if (wave == 0) {
+      double x[2], s2 = 0.0, xk = 0.0;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int r = lane + 64 * t;
+        x[t] = r < c ? sA[r + pk * QP_LD] : 0.0;
+        s2 = r > k ? fma(x[t], x[t], s2) : s2;
+        xk = t == (k >> 6) ? x[t] : xk;
+      }
+      const double x0 = readlane_d(xk, k & 63);
+      const double sig = sum64(s2);
+      double beta = x0, tau = 0.0, scl = 0.0;
+      if (sig != 0.0) householder_scalars(x0, sig, beta, tau, scl);
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int r = lane + 64 * t;
+        if (r == k) sA[r + pk * QP_LD] = beta;
+        else if (r > k && r < c) sA[r + pk * QP_LD] = x[t] * scl;
+      }
+      if (lane == 0) sTau[k] = tau;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      scol[k] = pk;
+      scol[p] = pp;
+    }
+    // trailing columns: a 16-lane group per column, QP_RPL rows per lane
+    const double tk = sTau[k];
+    const int grp = tid >> 4, gl = tid & 15;
+    if (k + 1 + grp < h) {
+      double v[QP_RPL];
+#pragma unroll
+      for (int u = 0; u < QP_RPL; ++u) {
+        const int r = gl + 16 * u;
+        v[u] = r == k ? 1.0 : ((r > k && r < c) ? sA[r + pk * QP_LD] : 0.0);
+      }
+      for (int j = k + 1 + grp; j < h; j += FT / 16) {
+        const int pj = j == p ? pp : scol[j];   // scol[p] is being rewritten
+        double a[QP_RPL], w = 0.0;
+#pragma unroll
+        for (int u = 0; u < QP_RPL; ++u) {
+          const int r = gl + 16 * u;
+          a[u] = (r >= k && r < c) ? sA[r + pj * QP_LD] : 0.0;
+          w = fma(v[u], a[u], w);
+        }
+        const double tw = tk * sum16(w);
+        double n2 = 0.0;
+#pragma unroll
+        for (int u = 0; u < QP_RPL; ++u) {
+          const int r = gl + 16 * u;
+          a[u] = fma(-tw, v[u], a[u]);
+          if (r >= k && r < c) sA[r + pj * QP_LD] = a[u];
+          n2 = r > k ? fma(a[u], a[u], n2) : n2;
+        }
+        n2 = sum16(n2);
+        if (gl == 0) snrm[j] = n2;
+      }
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  // V^T V inside each strip of QR_NB reflectors, then the strip's T factor
+  const int nstr = (rho + QR_NB - 1) / QR_NB;
+  for (int e = wave; e < nstr * QR_NB * QR_NB; e += FW) {
+    const int b = e / (QR_NB * QR_NB), i = (e / QR_NB) % QR_NB, cc = e % QR_NB;
+    const int gi = QR_NB * b + i, gc = QR_NB * b + cc;
+    if (i >= cc || gc >= rho) continue;
+    const int ci = scol[gi], cj = scol[gc];
+    double s2 = 0.0;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int r = lane + 64 * t;
+      const double vi = r == gi ? 1.0 : ((r > gi && r < c) ? sA[r + ci * QP_LD] : 0.0);
+      const double vc = r == gc ? 1.0 : ((r > gc && r < c) ? sA[r + cj * QP_LD] : 0.0);
+      s2 = fma(vi, vc, s2);
+    }
+    s2 = sum64(s2);
+    if (lane == 0) sVV[b][i][cc] = s2;
+  }
+  __syncthreads();
+  if (wave < nstr) {
+    const int nbs = min(QR_NB, rho - QR_NB * wave);
+    for (int cc = 0; cc < nbs; ++cc) t_column(sT[wave], sVV[wave], sTau + QR_NB * wave, cc, lane);
+    if (lane < QR_NB)
+      for (int cc = nbs; cc < QR_NB; ++cc) sT[wave][lane][cc] = 0.0;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < nstr * QR_NB * QR_NB; idx += FT)
+    d.T[idx] = sT[idx / (QR_NB * QR_NB)][(idx / QR_NB) % QR_NB][idx % QR_NB];
+  for (int j = tid; j < h; j += FT) d.perm[j] = scol[j];
+  if (tid == 0) *d.rho = rho;
+  for (int k = tid; k < rho; k += FT) d.tau[k] = sTau[k];
+  for (int idx = tid; idx < rho * h; idx += FT) {
+    const int k = idx % rho, j = idx / rho;
+    d.R2[k + (int64_t)j * d.ldR2] = j >= k ? sA[k + scol[j] * QP_LD] : 0.0;
+  }
+  // reflectors in pivoted order over the input (read into LDS above)
+  for (int idx = tid; idx < c * rho; idx += FT) {
+    const int r = idx % c, k = idx / c;
+    if (r > k) d.R[r + (int64_t)k * d.ldR] = sA[r + scol[k] * QP_LD];
+  }
+}
+
+void launch_qrcp(const QrcpDesc* d, int n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_qrcp, dim3(n), dim3(FT), 0, s, d);
+  KCHK();
+}
+
 // ------------------------------------------------------------ Jacobi SVD --
 // One-sided (Hestenes) Jacobi on the columns of an h x c matrix T (T = R, or
 // T = R^T when the descriptor asks for the transpose): T Z = W diag(s).  Pairs
@@ -404,38 +593,22 @@ void launch_apply_q(const PanelDesc* d, int n, hipStream_t s) {
 // 1024-thread workgroup treats every pair of a round (c <= 96) at once.  The
 // pair's two squared norms and inner product are reduced across the group by
 // DPP row operations (no LDS round trip), which leaves the same sum in every
-// lane.
+// lane.  Each lane holds RPL = ceil(h / 16) rows of the pair in registers.
 constexpr int JAC_LD = FAC_CMAX + 1;
 constexpr int JAC_GROUPS = FT / 16;
-constexpr int JAC_RPL = FAC_CMAX / 16;  // rows per lane of a 16-lane group
+constexpr int JAC_RPL = FAC_CMAX / 16;  // most rows per lane of a 16-lane group
 
-__global__ __launch_bounds__(FT) void k_jacobi(const SvdDesc* descs) {
-  __shared__ double sA[FAC_CMAX * JAC_LD];
-  __shared__ double sZ[FAC_CMAX * JAC_LD];
-  __shared__ double snorm[FAC_CMAX];
-  __shared__ int srank[FAC_CMAX];
-  __shared__ int flag;
-  const SvdDesc d = descs[blockIdx.x];
-  const int h = d.h, c = d.c;
-  const bool wantX = d.X != nullptr;
+template <int RPL>
+__device__ __forceinline__ int jacobi_sweeps(double* sA, double* sZ, int h, int c, bool wantX,
+                                             int* flag) {
   const int tid = threadIdx.x;
   const int grp = tid >> 4, gl = tid & 15;
-  for (int idx = tid; idx < h * c; idx += FT) {
-    const int i = idx % h, j = idx / h;
-    sA[i + j * JAC_LD] = d.trans ? d.R[j + (int64_t)i * d.ldR] : d.R[i + (int64_t)j * d.ldR];
-  }
-  if (wantX)
-    for (int idx = tid; idx < c * c; idx += FT) {
-      const int i = idx % c, j = idx / c;
-      sZ[i + j * JAC_LD] = (i == j) ? 1.0 : 0.0;
-    }
-  __syncthreads();
   const int n2 = c + (c & 1);
   const int hm1 = max(h - 1, 0);
   const double tol = (double)max(h, 1) * DBL_EPSILON;
   int sweep = 0;
   for (; sweep < 40; ++sweep) {
-    if (tid == 0) flag = 0;
+    if (tid == 0) *flag = 0;
     __syncthreads();
     for (int t = 0; t < n2 - 1; ++t) {
       for (int pi = grp; pi < n2 / 2; pi += JAC_GROUPS) {
@@ -445,10 +618,10 @@ __global__ __launch_bounds__(FT) void k_jacobi(const SvdDesc* descs) {
         const int p = min(pa, pb), q = max(pa, pb);
         if (q >= c) continue;
         // the group's rows gl + 16 u (fixed trip count; rows past h weigh zero)
-        double xv[JAC_RPL], yv[JAC_RPL];
+        double xv[RPL], yv[RPL];
         double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
-        for (int u = 0; u < JAC_RPL; ++u) {
+        for (int u = 0; u < RPL; ++u) {
           const int i = gl + 16 * u;
           const int ic = min(i, hm1);
           const double w = i < h ? 1.0 : 0.0;
@@ -492,7 +665,7 @@ __global__ __launch_bounds__(FT) void k_jacobi(const SvdDesc* descs) {
           }
           const double sn = cs * tt;
 #pragma unroll
-          for (int u = 0; u < JAC_RPL; ++u) {
+          for (int u = 0; u < RPL; ++u) {
             const int i = gl + 16 * u;
             if (i < h) {
               sA[i + p * JAC_LD] = cs * xv[u] - sn * yv[u];
@@ -500,26 +673,68 @@ __global__ __launch_bounds__(FT) void k_jacobi(const SvdDesc* descs) {
             }
           }
           if (wantX) {
+            // rows of Z: c <= 16 JAC_RPL
 #pragma unroll
             for (int u = 0; u < JAC_RPL; ++u) {
               const int i = gl + 16 * u;
-              const int ic = min(i, c - 1);
-              const double x = sZ[ic + p * JAC_LD], y = sZ[ic + q * JAC_LD];
-              if (i < c) {
-                sZ[i + p * JAC_LD] = cs * x - sn * y;
-                sZ[i + q * JAC_LD] = sn * x + cs * y;
+              if (16 * u < c) {
+                const int ic = min(i, c - 1);
+                const double x = sZ[ic + p * JAC_LD], y = sZ[ic + q * JAC_LD];
+                if (i < c) {
+                  sZ[i + p * JAC_LD] = cs * x - sn * y;
+                  sZ[i + q * JAC_LD] = sn * x + cs * y;
+                }
               }
             }
           }
-          if (gl == 0) flag = 1;
+          if (gl == 0) *flag = 1;
         }
       }
       __syncthreads();
     }
-    if (flag == 0) break;
+    if (*flag == 0) break;
     __syncthreads();  // every thread has read flag before it is reset
   }
-  if (tid == 0 && d.sweeps) atomicMax(d.sweeps, sweep + 1);
+  return sweep + 1;
+}
+
+__global__ __launch_bounds__(FT) void k_jacobi(const SvdDesc* descs) {
+  __shared__ double sA[FAC_CMAX * JAC_LD];
+  __shared__ double sZ[FAC_CMAX * JAC_LD];
+  __shared__ double snorm[FAC_CMAX];
+  __shared__ int srank[FAC_CMAX];
+  __shared__ int flag;
+  const SvdDesc d = descs[blockIdx.x];
+  int h = d.h, c = d.c;
+  if (d.dyn) {
+    const int r = max(0, min(d.c, *d.dyn));
+    h = min(h, r);
+    c = r;
+  }
+  const bool wantX = d.X != nullptr;
+  const bool accZ = wantX && !d.xscaled;   // accumulate the rotations
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < h * c; idx += FT) {
+    const int i = idx % h, j = idx / h;
+    sA[i + j * JAC_LD] = d.trans ? d.R[j + (int64_t)i * d.ldR] : d.R[i + (int64_t)j * d.ldR];
+  }
+  if (accZ)
+    for (int idx = tid; idx < c * c; idx += FT) {
+      const int i = idx % c, j = idx / c;
+      sZ[i + j * JAC_LD] = (i == j) ? 1.0 : 0.0;
+    }
+  __syncthreads();
+  int sweeps = 0;
+  switch ((h + 15) / 16) {
+    case 1: sweeps = jacobi_sweeps<1>(sA, sZ, h, c, accZ, &flag); break;
+    case 2: sweeps = jacobi_sweeps<2>(sA, sZ, h, c, accZ, &flag); break;
+    case 3: sweeps = jacobi_sweeps<3>(sA, sZ, h, c, accZ, &flag); break;
+    case 4: sweeps = jacobi_sweeps<4>(sA, sZ, h, c, accZ, &flag); break;
+    case 5: sweeps = jacobi_sweeps<5>(sA, sZ, h, c, accZ, &flag); break;
+    case 6: sweeps = jacobi_sweeps<6>(sA, sZ, h, c, accZ, &flag); break;
+    default: break;   // h = 0: nothing to rotate
+  }
+  if (tid == 0 && d.sweeps) atomicMax(d.sweeps, sweeps);
   for (int j = tid; j < c; j += FT) {
     double s = 0.0;
     for (int i = 0; i < h; ++i) s += sA[i + j * JAC_LD] * sA[i + j * JAC_LD];
@@ -532,24 +747,43 @@ __global__ __launch_bounds__(FT) void k_jacobi(const SvdDesc* descs) {
     for (int i2 = 0; i2 < c; ++i2) rk += (snorm[i2] > sj) || (snorm[i2] == sj && i2 < j);
     srank[j] = rk;
   }
+  if (wantX && !accZ)   // T (h x c) for X diag(s) = T^T W
+    for (int idx = tid; idx < h * c; idx += FT) {
+      const int i = idx % h, j = idx / h;
+      sZ[i + j * JAC_LD] = d.R[i + (int64_t)j * d.ldR];
+    }
   __syncthreads();
-  // column j goes to position srank[j] (descending norms, ties by index);
-  // positions c .. kout - 1 (a matrix with fewer columns than asked) are zero
-  const int rows = max(h, c);
+  // column j goes to position srank[j] (descending norms, ties by index),
+  // embedded in the wrows (xrows) frame; positions c .. kout - 1 get unit
+  // vectors e_j and singular value 0
+  const int rows = max(d.wrows, wantX ? d.xrows : 0);
   for (int e = tid; e < c * rows; e += FT) {
     const int i = e % rows, j = e / rows;
     const int rk = srank[j];
     if (rk >= d.kout) continue;
     const double sj = snorm[j];
     if (i == 0) d.sv[rk] = sj;
-    if (i < h) d.W[i + (int64_t)rk * d.ldW] = sj > 0.0 ? sA[i + j * JAC_LD] / sj : 0.0;
-    if (wantX && i < c) d.X[i + (int64_t)rk * d.ldX] = sZ[i + j * JAC_LD];
+    if (i < d.wrows)
+      d.W[i + (int64_t)rk * d.ldW] = (i < h && sj > 0.0) ? sA[i + j * JAC_LD] / sj : 0.0;
+    if (wantX && i < d.xrows) {
+      double xv = 0.0;
+      if (i < c) {
+        if (accZ) {
+          xv = sZ[i + j * JAC_LD];
+        } else if (sj > 0.0) {
+          // (T^T w_j)_i with w_j = T z_j / s_j the converged column j
+          for (int l = 0; l < h; ++l) xv = fma(sZ[l + i * JAC_LD], sA[l + j * JAC_LD], xv);
+          xv /= sj;
+        }
+      }
+      d.X[i + (int64_t)rk * d.ldX] = xv;
+    }
   }
   for (int e = tid; e < (d.kout - c) * rows; e += FT) {
     const int i = e % rows, rk = c + e / rows;
     if (i == 0) d.sv[rk] = 0.0;
-    if (i < h) d.W[i + (int64_t)rk * d.ldW] = 0.0;
-    if (wantX && i < c) d.X[i + (int64_t)rk * d.ldX] = 0.0;
+    if (i < d.wrows) d.W[i + (int64_t)rk * d.ldW] = i == rk ? 1.0 : 0.0;
+    if (wantX && i < d.xrows) d.X[i + (int64_t)rk * d.ldX] = (accZ && i == rk) ? 1.0 : 0.0;
   }
 }
 
@@ -597,7 +831,7 @@ __global__ void k_form_b(const Node* nodes, const Instance* inst, const int32_t*
   double* Bv = B + (int64_t)v * R * R;
   for (int e = threadIdx.x; e < R * R; e += blockDim.x) {
     const int i = e % R, j = e / R;
-    Bv[e] = (i < r && j < r) ? Xv[i + j * 2 * R] * zv[j] : 0.0;
+    Bv[e] = (i < r && j < r) ? Xv[i + j * 2 * R] * (z ? zv[j] : 1.0) : 0.0;
   }
 }
 

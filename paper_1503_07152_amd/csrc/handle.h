@@ -127,18 +127,28 @@ struct OpRunner {
 
 // Leading left singular vectors of node blocks: for each job, the block
 // M(lo : lo+rows, 0 : cols) is factored by Householder TSQR, its triangle by
-// one-sided Jacobi, and the leading kout left singular vectors are written to
-// Uout(lo.., 0:kout) (other columns untouched), singular values to
-// sv[node*R ..], right singular vectors to X[node*2R*R ..] (ld 2R) if X.
+// a rank-revealing pivoted QR (per job: relative threshold eta, at least kmin
+// directions) and one-sided Jacobi, and the leading kout left singular
+// vectors are written to Uout(lo.., 0:kout) (other columns untouched),
+// singular values to sv[node*R ..], right singular vectors to X[node*2R*R ..]
+// (ld 2R) if X -- scaled by the singular values if x_scaled.  Directions
+// below the threshold get singular value 0 and orthonormal completions.
 // qr_only: Uout gets the first min(rows, kout) columns of Q instead.
 struct SvdJob {
   int32_t node;
   int32_t rows, cols, kout;
   int64_t lo;
+  int32_t kmin;     // directions kept whatever their size (the rank k of the instance)
+  double eta;       // relative rank threshold (<= 0: the FP64 rounding level)
 };
 void node_svd(const std::vector<SvdJob>& jobs, double* M, int64_t ldm, double* Uout, int64_t ldu,
               double* sv, double* X, int R, bool qr_only, Workspace& ws, Keeper& kp,
-              hipStream_t s, int32_t* sweeps = nullptr);
+              hipStream_t s, int32_t* sweeps = nullptr, bool x_scaled = false);
+// Relative rank threshold of the node factorisations for samples computed in
+// `dtype` (an HM_* sample type): singular values below it are not resolved by
+// the samples.  FP64: 0 (the kernels use max(c, h) eps); FP32 and BF16: the
+// unit roundoff of the type over 16.
+double sample_rank_eta(int dtype);
 
 hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t flags, hipStream_t s,
                               int* status);

@@ -82,7 +82,7 @@ struct Alloc {
 
 void node_svd(const std::vector<SvdJob>& jobs, double* M, int64_t ldm, double* Uout, int64_t ldu,
               double* sv, double* X, int R, bool qr_only, Workspace& ws, Keeper& kp,
-              hipStream_t s, int32_t* sweeps) {
+              hipStream_t s, int32_t* sweeps, bool x_scaled) {
   if (jobs.empty()) return;
   int cmax = 1;
   for (auto& j : jobs) cmax = std::max(cmax, j.cols);
@@ -147,12 +147,19 @@ void node_svd(const std::vector<SvdJob>& jobs, double* M, int64_t ldm, double* U
   const size_t rfin_off = al.take((size_t)nj * FAC_CMAX * FAC_CMAX * sizeof(double));
   const size_t w_off = al.take((size_t)nj * FAC_CMAX * R * sizeof(double));
   const size_t eye_off = al.take((size_t)FAC_CMAX * R * sizeof(double));
-  // preconditioning QR of R^T per job: reflectors overwrite Rfin, R2 and tau2
-  // hold its triangle and scalars, Z the Jacobi right vectors
+  // rank-revealing pivoted QR of R^T per job (reflectors overwrite Rfin; R2,
+  // tau2, T2 its trapezoid and factors; perm, rank), QR of R2^T (reflectors
+  // overwrite R2; R3, tau3, T3), Jacobi vectors (left Wj, right Z)
   const size_t r2_off = al.take((size_t)nj * FAC_CMAX * FAC_CMAX * sizeof(double));
   const size_t tau2_off = al.take((size_t)nj * FAC_CMAX * sizeof(double));
   const size_t z_off = al.take((size_t)nj * FAC_CMAX * R * sizeof(double));
   const size_t wy2_off = al.take((size_t)nj * WY * sizeof(double));
+  const size_t r3_off = al.take((size_t)nj * FAC_CMAX * FAC_CMAX * sizeof(double));
+  const size_t tau3_off = al.take((size_t)nj * FAC_CMAX * sizeof(double));
+  const size_t wy3_off = al.take((size_t)nj * WY * sizeof(double));
+  const size_t wj_off = al.take((size_t)nj * FAC_CMAX * R * sizeof(double));
+  constexpr int PERM_STRIDE = FAC_CMAX + 32;   // perm entries, then the rank
+  const size_t perm_off = al.take((size_t)nj * PERM_STRIDE * sizeof(int32_t));
   ws.ensure(al.off, s);
   char* base = ws.base();
   auto S = [&](int st) { return reinterpret_cast<double*>(base + s_off[st]); };
@@ -166,11 +173,17 @@ void node_svd(const std::vector<SvdJob>& jobs, double* M, int64_t ldm, double* U
   double* TAU2 = reinterpret_cast<double*>(base + tau2_off);
   double* Z = reinterpret_cast<double*>(base + z_off);
   double* TWY2 = reinterpret_cast<double*>(base + wy2_off);
+  double* R3 = reinterpret_cast<double*>(base + r3_off);
+  double* TAU3 = reinterpret_cast<double*>(base + tau3_off);
+  double* TWY3 = reinterpret_cast<double*>(base + wy3_off);
+  double* WJ = reinterpret_cast<double*>(base + wj_off);
+  int32_t* PERM = reinterpret_cast<int32_t*>(base + perm_off);
   // ---- descriptors ---------------------------------------------------------
   std::vector<std::vector<PanelDesc>> pd(nst);
   std::vector<int64_t> tcount(nst, 0);
   std::vector<SvdDesc> sd;
-  std::vector<PanelDesc> pre;
+  std::vector<QrcpDesc> qd;
+  std::vector<PanelDesc> pre, rq;
   for (int q = 0; q < nj; ++q) {
     const SvdJob& jb = jobs[q];
     int64_t rrow_next = 0;  // row inside next stage buffer
@@ -200,27 +213,44 @@ void node_svd(const std::vector<SvdJob>& jobs, double* M, int64_t ldm, double* U
           d.Cin = qr_only ? EYE : W + (int64_t)q * FAC_CMAX * R;
           d.ldCin = FAC_CMAX;
           if (!qr_only) {
-            // R = R2^T Q2^T with R^T = Q2 R2; Jacobi on R2^T (h x h) gives
-            // R2^T Z = W S, so R = W S (Q2 Z)^T: W is the left factor, the
-            // right factor Q2 [Z; 0] comes from the reflectors of the
-            // preconditioning QR
+            // R (h x c) -> R^T P = Q2 [R2; dropped], rank rho; R2^T = Q3 R3;
+            // Jacobi R3 Z = U S.  Then R = (P Q3 U) S (Q2 Z)^T up to the
+            // dropped block: the left factor is P Q3 [U 0; 0 I] (completed by
+            // the remaining columns of Q3), the right one Q2 [Z 0; 0 I]
+            double* rf = d.Rout;
             double* r2 = R2 + (int64_t)q * FAC_CMAX * FAC_CMAX;
+            double* r3 = R3 + (int64_t)q * FAC_CMAX * FAC_CMAX;
             double* zq = Z + (int64_t)q * FAC_CMAX * R;
+            double* wj = WJ + (int64_t)q * FAC_CMAX * R;
+            int32_t* perm = PERM + (int64_t)q * PERM_STRIDE;
+            int32_t* rho = perm + FAC_CMAX;
+            QrcpDesc qc{};
+            qc.R = rf; qc.ldR = FAC_CMAX; qc.c = jb.cols; qc.h = h;
+            qc.tau = TAU2 + (int64_t)q * FAC_CMAX; qc.T = TWY2 + (int64_t)q * WY;
+            qc.R2 = r2; qc.ldR2 = FAC_CMAX; qc.perm = perm; qc.rho = rho;
+            qc.eta = jb.eta; qc.kmin = jb.kmin;
+            qd.push_back(qc);
+            PanelDesc t3{};
+            t3.A = r2; t3.ld = FAC_CMAX; t3.rows = h; t3.cols = h; t3.trans = 1; t3.dyn_cols = rho;
+            t3.tau = TAU3 + (int64_t)q * FAC_CMAX; t3.T = TWY3 + (int64_t)q * WY;
+            t3.Rout = r3; t3.ldR = FAC_CMAX;
+            t3.Cin = wj; t3.ldCin = FAC_CMAX; t3.cin_full = 1;
+            t3.Cout = W + (int64_t)q * FAC_CMAX * R; t3.ldCout = FAC_CMAX; t3.perm = perm;
+            t3.ncol = jb.kout;
+            rq.push_back(t3);
             PanelDesc t{};
-            t.A = d.Rout; t.ld = FAC_CMAX; t.rows = jb.cols; t.cols = h; t.trans = 1;
-            t.tau = TAU2 + (int64_t)q * FAC_CMAX;
-            t.T = TWY2 + (int64_t)q * WY;
-            t.Rout = r2; t.ldR = FAC_CMAX;
-            t.Cin = zq; t.ldCin = FAC_CMAX;
+            t.A = rf; t.ld = FAC_CMAX; t.rows = jb.cols; t.cols = h; t.dyn_cols = rho;
+            t.tau = qc.tau; t.T = qc.T;
+            t.Cin = zq; t.ldCin = FAC_CMAX; t.cin_full = 1;
             t.Cout = X ? X + (int64_t)jb.node * 2 * R * R : nullptr; t.ldCout = 2 * R;
             t.ncol = jb.kout;
             pre.push_back(t);
             SvdDesc v{};
-            v.R = r2; v.ldR = FAC_CMAX; v.h = h; v.c = h; v.trans = 1;
-            v.W = W + (int64_t)q * FAC_CMAX * R; v.ldW = FAC_CMAX;
+            v.R = r3; v.ldR = FAC_CMAX; v.h = h; v.c = h; v.trans = 0; v.dyn = rho;
+            v.W = wj; v.ldW = FAC_CMAX; v.wrows = h;
             v.sv = sv + (int64_t)jb.node * R;
             v.X = X ? zq : nullptr;
-            v.ldX = FAC_CMAX;
+            v.ldX = FAC_CMAX; v.xrows = jb.cols; v.xscaled = x_scaled ? 1 : 0;
             v.kout = jb.kout;
             v.sweeps = sweeps;
             sd.push_back(v);
@@ -245,13 +275,22 @@ void node_svd(const std::vector<SvdJob>& jobs, double* M, int64_t ldm, double* U
   for (int st = 0; st < nst; ++st) dpd[st] = kp.put(pd[st], s);
   for (int st = 0; st < nst; ++st) launch_panel_qr(dpd[st], (int)pd[st].size(), s);
   if (!qr_only) {
-    PanelDesc* dpre = kp.put(pre, s);
-    launch_panel_qr(dpre, (int)pre.size(), s);
+    QrcpDesc* dqd = kp.put(qd, s);
+    launch_qrcp(dqd, (int)qd.size(), s);
+    PanelDesc* drq = kp.put(rq, s);
+    launch_panel_qr(drq, (int)rq.size(), s);
     SvdDesc* dsd = kp.put(sd, s);
     launch_jacobi_svd(dsd, (int)sd.size(), s);
-    if (X) launch_apply_q(dpre, (int)pre.size(), s);
+    launch_apply_q(drq, (int)rq.size(), s);
+    if (X) launch_apply_q(kp.put(pre, s), (int)pre.size(), s);
   }
   for (int st = nst - 1; st >= 0; --st) launch_apply_q(dpd[st], (int)pd[st].size(), s);
+}
+
+double sample_rank_eta(int dtype) {
+  if (dtype == HM_BF16) return std::ldexp(1.0, -8) / 16.0;
+  if (dtype == HM_F32) return std::ldexp(1.0, -24) / 16.0;
+  return 0.0;
 }
 
 // ------------------------------------------------------------ compress -----
@@ -303,6 +342,12 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
   const Instance* di = h->d_inst.as<Instance>();
   Keeper kp;
   Workspace ws_svd, ws_apply, ws_seg;
+  // rank threshold of each instance's node factorisations: its samples' precision
+  std::vector<double> eta_inst(f.inst.size(), 0.0);
+  for (size_t i = 0; i < f.inst.size(); ++i) {
+    const OpRunner* o = ops.size() == f.inst.size() ? ops[i] : ops[0];
+    eta_inst[i] = sample_rank_eta(o->op.kind == HM_OP_KERNEL ? o->op.sample_dtype : HM_F64);
+  }
   // ---- buffers ---------------------------------------------------------------
   const int W = std::max(2 * R, nmax);
   DevBuf Om((size_t)N * W * 8), Y((size_t)N * W * 8), M((size_t)N * 2 * R * 8);
@@ -364,7 +409,8 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
       const Node& nd = f.nodes[g];
       const int r = f.inst[nd.inst].r;
       const bool under_root = f.nodes[nd.parent].parent < 0;
-      jobs.push_back({g, (int)(nd.hi - nd.lo), under_root ? r : 2 * r, r, nd.lo});
+      jobs.push_back({g, (int)(nd.hi - nd.lo), under_root ? r : 2 * r, r, nd.lo,
+                      f.inst[nd.inst].k, eta_inst[nd.inst]});
     }
     launch_fill(un, N, R, N, 0.0, s);
     node_svd(jobs, m, N, un, N, yv.as<double>(), nullptr, R, false, ws_svd, kp, s,
@@ -384,9 +430,10 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
     launch_build_node_block(dn, di, dk, nk, lv.max_kid_rows, R, y, N, vc, N, zv.as<double>(), m,
                             N, s);
     launch_fill(vn, N, R, N, 0.0, s);
+    // X diag(z) directly (only that product enters B)
     node_svd(jobs, m, N, vn, N, zv.as<double>(), Xr.as<double>(), R, false, ws_svd, kp, s,
-             flag.as<int32_t>() + 2);
-    launch_form_b(dn, di, dk, nk, R, Xr.as<double>(), zv.as<double>(), B.as<double>(), s);
+             flag.as<int32_t>() + 2, true);
+    launch_form_b(dn, di, dk, nk, R, Xr.as<double>(), nullptr, B.as<double>(), s);
     if (l >= 1)
       seg_tn<double>(dn, dk, nk, lv.max_kid_rows, R, R, vn, N, vc, N, Vt.as<double>(), 2 * R * R,
                      2 * R, 1.0, 0.0, ws_seg.base(), s, 1);

@@ -80,7 +80,8 @@ hm_hodlr_s* hodlr_compress_forest(Forest f, OpRunner& op, hipStream_t s, int* st
     std::vector<SvdJob> jobs;
     for (int g : kids) {
       const Node& nd = f.nodes[g];
-      jobs.push_back({g, (int)(nd.hi - nd.lo), R, R, nd.lo});
+      jobs.push_back({g, (int)(nd.hi - nd.lo), R, R, nd.lo, f.inst[nd.inst].k,
+                      sample_rank_eta(op.op.kind == HM_OP_KERNEL ? op.op.sample_dtype : HM_F64)});
     }
     launch_fill(Uq.as<double>(), N, R, N, 0.0, s);
     node_svd(jobs, M.as<double>(), N, Uq.as<double>(), N, nullptr, nullptr, R, true, ws_svd, kp, s);

@@ -175,3 +175,29 @@ def test_mixed_precision_sampling_errors(mode, tol):
     r = _compare_compress(h, ho, n, K.apply)
     say(f"  {r}")
     assert r["vs_oracle"] < tol
+
+
+@pytest.mark.parametrize("n,leaf,k,p", [(1024, 64, 10, 10), (2000, 64, 12, 8)])
+def test_orthonormal_bases_with_rank_deficient_blocks(n, leaf, k, p):
+    """Node blocks of an operator with off-diagonal rank exactly k < r have
+    numerical rank below r: the node factorisation reveals that rank and
+    completes the r basis columns orthonormally (singular values 0), so the
+    leaf bases of the orthonormal form (Fig. 4) stay orthonormal in all r
+    columns, and the represented operator is still exact."""
+    from oracle.tree import Tree
+    say(f"orthonormal bases n={n} leaf={leaf} k={k} p={p}")
+    g = W.synthetic_hbs(n, leaf, k, seed=4)
+    h = hm.hbs_compress(hm.Options(n, leaf, k, p, seed=6, orthonormal=True),
+                        hm.HBSOperator(hm.hm_hbs_from_generators(g)))
+    e = h.export()
+    r = k + p
+    t = Tree(n, leaf)
+    U, V = e["U"].cpu().numpy(), e["V"].cpu().numpy()
+    worst = 0.0
+    for lf in t.leaves():
+        for B in (U[t.I(lf), :r], V[t.I(lf), :r]):
+            worst = max(worst, np.abs(B.T @ B - np.eye(r)).max())
+    say(f"  max |Q^T Q - I| = {worst:.1e}")
+    assert worst < 1e-12
+    ho_full = ohbs.from_generators(g)
+    assert _compare_compress(h, ho_full, n, ho_full.apply)["vs_A"] < 1e-11
