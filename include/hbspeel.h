@@ -219,8 +219,9 @@ int hodlr_apply(const hm_hodlr* h, int32_t adjoint, int64_t nrhs,
                 const double* x, int64_t ldx, double* y, int64_t ldy, void* stream);
 
 /* ---- handles ----------------------------------------------------------------
- * hm_hbs_from_generators: an HBS handle from generators of uniform rank k in
- * the flat layout (all device, column-major blocks; nn = 2^(L+1)):
+ * hm_hbs_from_generators: an HBS handle from generators of uniform rank
+ * k <= HM_MAX_SAMPLES in the flat layout (all device, column-major blocks;
+ * nn = 2^(L+1)):
  *   U, V   n x k          rows I_t of leaf t hold its basis
  *   Ut, Vt nn blocks of 2k x k (block t at offset t*2k*k); rows 0..k-1 couple
  *          to the left child 2t, rows k..2k-1 to 2t+1; used for 2 <= t < 2^L

@@ -300,7 +300,8 @@ int hm_hbs_from_generators(int64_t n, int64_t leaf_size, int32_t k, int32_t dtyp
     if (!out || n < 1 || leaf_size < 1 || k < 1 || !U || !V || !Ut || !Vt || !B || !D)
       HM_THROW(HM_ERR_ARG, "from_generators: bad arguments");
     if (dtype != HM_F64 && dtype != HM_F32) HM_THROW(HM_ERR_ARG, "dtype must be F64 or F32");
-    if (k > 64) HM_THROW(HM_ERR_UNSUPPORTED, "rank %d > 64", k);
+    if (k > HM_MAX_SAMPLES)
+      HM_THROW(HM_ERR_UNSUPPORTED, "rank %d > %d", k, HM_MAX_SAMPLES);
     hipStream_t s = (hipStream_t)stream;
     std::unique_ptr<hm_hbs_s> h(new hm_hbs_s());
     forest_add_tree(h->f, n, leaf_size, k, k, 0, 0.0, 0);

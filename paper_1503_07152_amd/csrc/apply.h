@@ -11,14 +11,20 @@ namespace hm {
 // Node lists of one apply: frontier (each active instance's nodes on its level
 // m_i) and, for l = 1 .. mmax-1, the internal nodes on level l (ancestors of
 // frontier nodes).  Built once on the host, kept on the device.
+// A node of a tree sweep with its children's / sibling's ids (one load per
+// workgroup instead of a chain of node-table lookups).
+struct TreeOp {
+  int32_t t, left, right, sib;
+};
+
 struct ApplyLists {
   DevBuf frontier;
   int nfront = 0;
   int64_t max_rows = 0;     // largest frontier node
   int chunks = 1;           // row chunks per frontier node for the V^T x reduction
-  std::vector<DevBuf> internal;   // index l (0 unused)
+  std::vector<DevBuf> internal;   // TreeOp per internal node on level l (index 0 unused)
   std::vector<int> ninternal;
-  DevBuf level1;
+  DevBuf level1;                  // TreeOp per level-1 node
   int nlevel1 = 0;
   int mmax = 0;
 };

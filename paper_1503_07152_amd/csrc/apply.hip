@@ -2,16 +2,17 @@
 #include <algorithm>
 
 #include "apply.h"
-#include "tile.h"
+#include "tile_mfma.h"
 
 namespace hm {
 
 void build_apply_lists(const Forest& f, const std::vector<int>& m, ApplyLists& out,
                        hipStream_t s) {
-  std::vector<int32_t> front, lvl1;
+  std::vector<int32_t> front;
+  std::vector<TreeOp> lvl1;
   int mmax = 0;
   for (int i = 0; i < (int)f.inst.size(); ++i) mmax = std::max(mmax, m[i]);
-  std::vector<std::vector<int32_t>> inter(std::max(mmax, 1));
+  std::vector<std::vector<TreeOp>> inter(std::max(mmax, 1));
   int64_t maxr = 0;
   for (int g = 0; g < (int)f.nodes.size(); ++g) {
     const Node& nd = f.nodes[g];
@@ -21,8 +22,9 @@ void build_apply_lists(const Forest& f, const std::vector<int>& m, ApplyLists& o
       front.push_back(g);
       maxr = std::max<int64_t>(maxr, nd.hi - nd.lo);
     }
-    if (nd.level >= 1 && nd.level < mi) inter[nd.level].push_back(g);
-    if (nd.level == 1 && mi >= 1) lvl1.push_back(g);
+    const TreeOp op{g, nd.left, nd.right, nd.sib};
+    if (nd.level >= 1 && nd.level < mi) inter[nd.level].push_back(op);
+    if (nd.level == 1 && mi >= 1) lvl1.push_back(op);
   }
   out.nfront = (int)front.size();
   out.frontier = upload(front, s);
@@ -40,25 +42,25 @@ void build_apply_lists(const Forest& f, const std::vector<int>& m, ApplyLists& o
   out.level1 = upload(lvl1, s);
 }
 
-constexpr int TM = 64, TN = 64;
+constexpr int TM = MF_T, TN = MF_T;   // output tile of the MFMA products
 
 template <class T>
 __global__ __launch_bounds__(256) void k_leaf_up(const Node* nodes, const int32_t* front,
                                                  int chunks, const T* V, int64_t ldl, int R,
                                                  const T* X, int64_t ldx, int c, T* QH, T* P) {
-  __shared__ T smem[tile_smem_elems<TM, TN>()];
+  __shared__ T smem[mf_smem_elems<T>()];
   const int ch = blockIdx.x, fi = blockIdx.y, j0 = blockIdx.z * TN;
   const int g = front[fi];
   const Node nd = nodes[g];
   const int64_t r0 = nd.lo + (int64_t)ch * APPLY_CHUNK;
   const int K = (int)max<int64_t>(0, min<int64_t>(APPLY_CHUNK, nd.hi - r0));
-  TileAcc<T, TM, TN> acc;
+  MfAcc<T> acc;
   acc.zero();
   if (nd.level > 0 && K > 0)
-    mm_tile<T, TM, TN>(R, c - j0, K, V + r0, ldl, 1, X + r0 + (int64_t)j0 * ldx, 1, ldx, acc,
+    mf_tile<T>(R, c - j0, K, V + r0, ldl, 1, X + r0 + (int64_t)j0 * ldx, 1, ldx, acc,
                        smem);
   T* out = chunks == 1 ? QH + (int64_t)g * R * c : P + ((int64_t)fi * chunks + ch) * R * c;
-  store_tile<T, TM, TN>(R, c - j0, out + (int64_t)j0 * R, R, acc, T(1), T(0));
+  mf_store<T>(R, c - j0, out + (int64_t)j0 * R, R, acc, T(1), T(0));
 }
 
 template <class T>
@@ -75,66 +77,144 @@ __global__ void k_chunk_reduce(const int32_t* front, int chunks, const T* P, int
   }
 }
 
-template <class T>
-__global__ __launch_bounds__(256) void k_tree_up(const Node* nodes, const int32_t* list,
-                                                 const T* Vt, int R, T* QH, int c) {
-  __shared__ T smem[tile_smem_elems<TM, TN>()];
-  const int g = list[blockIdx.x];
-  const int j0 = blockIdx.y * TN;
-  const Node nd = nodes[g];
-  const T* vt = Vt + (int64_t)g * 2 * R * R;
-  TileAcc<T, TM, TN> acc;
-  acc.zero();
-  mm_tile<T, TM, TN>(R, c - j0, R, vt, 2 * R, 1, QH + (int64_t)nd.left * R * c + (int64_t)j0 * R,
-                     1, R, acc, smem);
-  mm_tile<T, TM, TN>(R, c - j0, R, vt + R, 2 * R, 1,
-                     QH + (int64_t)nd.right * R * c + (int64_t)j0 * R, 1, R, acc, smem);
-  store_tile<T, TM, TN>(R, c - j0, QH + (int64_t)g * R * c + (int64_t)j0 * R, R, acc, T(1),
-                        T(0));
-}
-
-// Incoming expansion of node a from its sibling's outgoing one:
-// forward  uh_a = B[sib(a)] qh_sib ;  adjoint uh_a = B[a]^T qh_sib.
-template <class T>
-__device__ __forceinline__ void sib_term(const Node* nodes, int a, const T* B, int R,
-                                         const T* QH, int c, int j0, bool adjoint,
-                                         TileAcc<T, TM, TN>& acc, T* smem) {
-  const int s = nodes[a].sib;
-  const T* qs = QH + (int64_t)s * R * c + (int64_t)j0 * R;
-  if (!adjoint)
-    mm_tile<T, TM, TN>(R, c - j0, R, B + (int64_t)s * R * R, 1, R, qs, 1, R, acc, smem);
-  else
-    mm_tile<T, TM, TN>(R, c - j0, R, B + (int64_t)a * R * R, R, 1, qs, 1, R, acc, smem);
-}
+// ---- tree sweeps ------------------------------------------------------------
+// One node (and a tile of TRC columns) per workgroup: out (R x TRC) = A1 B1 +
+// A2 B2 with R x R coefficient blocks A_h (strided: A_h(i, k) = a_h[i sai +
+// k sak]) and expansions B_h (R x TRC, ld R), R <= HM_MAX_SAMPLES.  Every
+// operand is staged in LDS in one round (no K loop over global memory: K <=
+// 2 R_max), so a level costs one global round trip; K is padded with zeros
+// to a multiple of 8 and the product runs 8 K-steps per batch of LDS loads.
+// Thread (ti, tj) holds rows ti + 16 u and columns 2 tj, 2 tj + 1.
+constexpr int TRM = HM_MAX_SAMPLES;   // largest padded rank
+constexpr int TRC = 32;               // columns per workgroup
+constexpr int TRK = 8;                // K-steps per batch
 
 template <class T>
-__global__ __launch_bounds__(256) void k_root(const Node* nodes, const int32_t* list, const T* B,
-                                              int R, const T* QH, T* UH, int c, int adjoint) {
-  __shared__ T smem[tile_smem_elems<TM, TN>()];
-  const int a = list[blockIdx.x];
-  const int j0 = blockIdx.y * TN;
-  TileAcc<T, TM, TN> acc;
-  acc.zero();
-  sib_term<T>(nodes, a, B, R, QH, c, j0, adjoint != 0, acc, smem);
-  store_tile<T, TM, TN>(R, c - j0, UH + (int64_t)a * R * c + (int64_t)j0 * R, R, acc, T(1), T(0));
+struct TreeSmem {
+  T a[2 * TRM][TRM + 1];   // A(i, k) at a[k][i] (both halves stacked along k)
+  T b[2 * TRM][TRC];       // B(k, j)
+};
+
+template <class T>
+__device__ __forceinline__ void stage_coef(int R, int k0, const T* a, int64_t sai, int64_t sak,
+                                           TreeSmem<T>& sm) {
+  const int tid = threadIdx.x;
+  if (sai == 1) {
+    for (int e = tid; e < R * R; e += 256) {
+      const int i = e % R, k = e / R;
+      sm.a[k0 + k][i] = a[i + k * sak];
+    }
+  } else {
+    for (int e = tid; e < R * R; e += 256) {
+      const int k = e % R, i = e / R;
+      sm.a[k0 + k][i] = a[i * sai + k * sak];
+    }
+  }
+}
+
+template <class T, int NU>
+__device__ __forceinline__ void tree_mac(int Kp, int ti, int tj, const TreeSmem<T>& sm,
+                                         T (&acc)[3][2]) {
+  for (int k0 = 0; k0 < Kp; k0 += TRK) {
+    T av[TRK][NU], bv[TRK][2];
+#pragma unroll
+    for (int q = 0; q < TRK; ++q) {
+#pragma unroll
+      for (int u = 0; u < NU; ++u) av[q][u] = sm.a[k0 + q][ti + 16 * u];
+      bv[q][0] = sm.b[k0 + q][2 * tj];
+      bv[q][1] = sm.b[k0 + q][2 * tj + 1];
+    }
+#pragma unroll
+    for (int q = 0; q < TRK; ++q)
+#pragma unroll
+      for (int u = 0; u < NU; ++u) {
+        acc[u][0] = fma(av[q][u], bv[q][0], acc[u][0]);
+        acc[u][1] = fma(av[q][u], bv[q][1], acc[u][1]);
+      }
+  }
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void k_tree_down(const Node* nodes, const int32_t* list,
-                                                   const T* Ut, const T* B, int R, const T* QH,
-                                                   T* UH, int c, int adjoint) {
-  __shared__ T smem[tile_smem_elems<TM, TN>()];
-  const int t = list[blockIdx.x];
+__device__ __forceinline__ void tree_product(int R, int nc, int nparts, const T* a1, int64_t sai1,
+                                             int64_t sak1, const T* b1, const T* a2,
+                                             int64_t sai2, int64_t sak2, const T* b2, T* out,
+                                             TreeSmem<T>& sm) {
+  const int tid = threadIdx.x;
+  const int K = nparts * R;
+  const int Kp = (K + TRK - 1) / TRK * TRK;
+  stage_coef<T>(R, 0, a1, sai1, sak1, sm);
+  if (nparts == 2) stage_coef<T>(R, R, a2, sai2, sak2, sm);
+  for (int e = tid; e < (Kp - K) * TRM; e += 256) sm.a[K + e / TRM][e % TRM] = T(0);
+  for (int e = tid; e < Kp * TRC; e += 256) {
+    const int k = e % Kp, j = e / Kp;
+    const bool second = k >= R;
+    const int kk = second ? k - R : k;
+    T v = T(0);
+    if (k < K && j < nc) v = second ? b2[kk + (int64_t)j * R] : b1[kk + (int64_t)j * R];
+    sm.b[k][j] = v;
+  }
+  __syncthreads();
+  const int ti = tid & 15, tj = tid >> 4;
+  T acc[3][2];
+#pragma unroll
+  for (int u = 0; u < 3; ++u) acc[u][0] = acc[u][1] = T(0);
+  const int nu = (R + 15) / 16;
+  if (nu == 3) tree_mac<T, 3>(Kp, ti, tj, sm, acc);
+  else if (nu == 2) tree_mac<T, 2>(Kp, ti, tj, sm, acc);
+  else tree_mac<T, 1>(Kp, ti, tj, sm, acc);
+#pragma unroll
+  for (int u = 0; u < 3; ++u)
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+      const int i = ti + 16 * u, j = 2 * tj + w;
+      if (u < nu && i < R && j < nc) out[i + (int64_t)j * R] = acc[u][w];
+    }
+}
+
+// Upward pass, one level: qh_t = Vt_t^T [qh_left; qh_right].
+template <class T>
+__global__ __launch_bounds__(256) void k_tree_up(const TreeOp* list, const T* Vt, int R, T* QH,
+                                                 int c) {
+  __shared__ TreeSmem<T> sm;
+  const TreeOp op = list[blockIdx.x];
+  const int j0 = blockIdx.y * TRC;
+  const T* vt = Vt + (int64_t)op.t * 2 * R * R;
+  tree_product<T>(R, min(TRC, c - j0), 2, vt, 2 * R, 1,
+                  QH + (int64_t)op.left * R * c + (int64_t)j0 * R, vt + R, 2 * R, 1,
+                  QH + (int64_t)op.right * R * c + (int64_t)j0 * R,
+                  QH + (int64_t)op.t * R * c + (int64_t)j0 * R, sm);
+}
+
+// Incoming expansion of node a from its sibling s's outgoing one: forward
+// uh_a = B[s] qh_s, adjoint uh_a = B[a]^T qh_s; below level 1 plus the
+// parent's term Ut_t(half of a) uh_t.
+template <class T>
+__global__ __launch_bounds__(256) void k_root(const TreeOp* list, const T* B, int R, const T* QH,
+                                              T* UH, int c, int adjoint) {
+  __shared__ TreeSmem<T> sm;
+  const TreeOp op = list[blockIdx.x];
+  const int a = op.t, s = op.sib;
+  const int j0 = blockIdx.y * TRC;
+  const T* bm = adjoint ? B + (int64_t)a * R * R : B + (int64_t)s * R * R;
+  tree_product<T>(R, min(TRC, c - j0), 1, bm, adjoint ? R : 1, adjoint ? 1 : R,
+                  QH + (int64_t)s * R * c + (int64_t)j0 * R, bm, 0, 0, nullptr,
+                  UH + (int64_t)a * R * c + (int64_t)j0 * R, sm);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_tree_down(const TreeOp* list, const T* Ut, const T* B,
+                                                   int R, const T* QH, T* UH, int c,
+                                                   int adjoint) {
+  __shared__ TreeSmem<T> sm;
+  const TreeOp op = list[blockIdx.x];
   const int side = blockIdx.y;  // 0: left child, 1: right child
-  const int j0 = blockIdx.z * TN;
-  const Node nd = nodes[t];
-  const int a = side == 0 ? nd.left : nd.right;
-  TileAcc<T, TM, TN> acc;
-  acc.zero();
-  sib_term<T>(nodes, a, B, R, QH, c, j0, adjoint != 0, acc, smem);
-  mm_tile<T, TM, TN>(R, c - j0, R, Ut + (int64_t)t * 2 * R * R + side * R, 1, 2 * R,
-                     UH + (int64_t)t * R * c + (int64_t)j0 * R, 1, R, acc, smem);
-  store_tile<T, TM, TN>(R, c - j0, UH + (int64_t)a * R * c + (int64_t)j0 * R, R, acc, T(1), T(0));
+  const int j0 = blockIdx.z * TRC;
+  const int a = side == 0 ? op.left : op.right, s = side == 0 ? op.right : op.left;
+  const T* bm = adjoint ? B + (int64_t)a * R * R : B + (int64_t)s * R * R;
+  tree_product<T>(R, min(TRC, c - j0), 2, Ut + (int64_t)op.t * 2 * R * R + side * R, 1, 2 * R,
+                  UH + (int64_t)op.t * R * c + (int64_t)j0 * R, bm, adjoint ? R : 1,
+                  adjoint ? 1 : R, QH + (int64_t)s * R * c + (int64_t)j0 * R,
+                  UH + (int64_t)a * R * c + (int64_t)j0 * R, sm);
 }
 
 template <class T>
@@ -143,7 +223,7 @@ __global__ __launch_bounds__(256) void k_leaf_down(const Node* nodes, const int3
                                                    int c, const T* D, int64_t ldd, int adjoint,
                                                    const T* X, int64_t ldx, T* Y, int64_t ldy,
                                                    T alpha, T beta) {
-  __shared__ T smem[tile_smem_elems<TM, TN>()];
+  __shared__ T smem[mf_smem_elems<T>()];
   const int g = front[blockIdx.y];
   const Node nd = nodes[g];
   const int64_t i0 = nd.lo + (int64_t)blockIdx.x * TM;
@@ -151,20 +231,20 @@ __global__ __launch_bounds__(256) void k_leaf_down(const Node* nodes, const int3
   const int M = (int)min<int64_t>(TM, nd.hi - i0);
   const int j0 = blockIdx.z * TN;
   const int N = c - j0;
-  TileAcc<T, TM, TN> acc;
+  MfAcc<T> acc;
   acc.zero();
   if (nd.level > 0)
-    mm_tile<T, TM, TN>(M, N, R, U + i0, 1, ldl, UH + (int64_t)g * R * c + (int64_t)j0 * R, 1, R,
+    mf_tile<T>(M, N, R, U + i0, 1, ldl, UH + (int64_t)g * R * c + (int64_t)j0 * R, 1, R,
                        acc, smem);
   if (D) {
     const int nt = (int)(nd.hi - nd.lo);
     const T* xb = X + nd.lo + (int64_t)j0 * ldx;
     if (!adjoint)
-      mm_tile<T, TM, TN>(M, N, nt, D + i0, 1, ldd, xb, 1, ldx, acc, smem);
+      mf_tile<T>(M, N, nt, D + i0, 1, ldd, xb, 1, ldx, acc, smem);
     else
-      mm_tile<T, TM, TN>(M, N, nt, D + nd.lo + (i0 - nd.lo) * ldd, ldd, 1, xb, 1, ldx, acc, smem);
+      mf_tile<T>(M, N, nt, D + nd.lo + (i0 - nd.lo) * ldd, ldd, 1, xb, 1, ldx, acc, smem);
   }
-  store_tile<T, TM, TN>(M, N, Y + i0 + (int64_t)j0 * ldy, ldy, acc, alpha, beta);
+  mf_store<T>(M, N, Y + i0 + (int64_t)j0 * ldy, ldy, acc, alpha, beta);
 }
 
 template <class T>
@@ -181,10 +261,12 @@ void apply_forest(const Node* d_nodes, const ApplyLists& al, const HbsView<T>& h
                   size_t nnodes, hipStream_t s, bool expansions_only) {
   if (al.nfront == 0 || c <= 0) return;
   const int R = h.R;
+  if (R > TRM) HM_THROW(HM_ERR_UNSUPPORTED, "apply: padded rank %d > %d", R, TRM);
   T* QH = static_cast<T*>(work);
   T* UH = QH + (size_t)R * c * nnodes;
   T* P = UH + (size_t)R * c * nnodes;
   const int ct = (c + TN - 1) / TN;
+  const int ctt = (c + TRC - 1) / TRC;
   const T* Uin = adjoint ? h.Vlong : h.Ulong;  // incoming long basis
   const T* Vout = adjoint ? h.Ulong : h.Vlong; // outgoing long basis
   const T* Tin = adjoint ? h.Vt : h.Ut;
@@ -203,19 +285,19 @@ void apply_forest(const Node* d_nodes, const ApplyLists& al, const HbsView<T>& h
     }
     for (int l = al.mmax - 1; l >= 1; --l) {
       if (al.ninternal[l] == 0) continue;
-      hipLaunchKernelGGL(k_tree_up<T>, dim3(al.ninternal[l], ct), dim3(256), 0, s, d_nodes,
-                         al.internal[l].as<int32_t>(), Tout, R, QH, c);
+      hipLaunchKernelGGL(k_tree_up<T>, dim3(al.ninternal[l], ctt), dim3(256), 0, s,
+                         al.internal[l].as<TreeOp>(), Tout, R, QH, c);
       KCHK();
     }
     if (al.nlevel1 > 0) {
-      hipLaunchKernelGGL(k_root<T>, dim3(al.nlevel1, ct), dim3(256), 0, s, d_nodes,
-                         al.level1.as<int32_t>(), h.B, R, QH, UH, c, adjoint ? 1 : 0);
+      hipLaunchKernelGGL(k_root<T>, dim3(al.nlevel1, ctt), dim3(256), 0, s,
+                         al.level1.as<TreeOp>(), h.B, R, QH, UH, c, adjoint ? 1 : 0);
       KCHK();
     }
     for (int l = 1; l < al.mmax; ++l) {
       if (al.ninternal[l] == 0) continue;
-      hipLaunchKernelGGL(k_tree_down<T>, dim3(al.ninternal[l], 2, ct), dim3(256), 0, s, d_nodes,
-                         al.internal[l].as<int32_t>(), Tin, h.B, R, QH, UH, c, adjoint ? 1 : 0);
+      hipLaunchKernelGGL(k_tree_down<T>, dim3(al.ninternal[l], 2, ctt), dim3(256), 0, s,
+                         al.internal[l].as<TreeOp>(), Tin, h.B, R, QH, UH, c, adjoint ? 1 : 0);
       KCHK();
     }
   }
@@ -277,20 +359,20 @@ template <class T>
 __global__ __launch_bounds__(256) void k_seg_tn(const Node* nodes, const int32_t* list,
                                                 int chunks, int rows, int cols, const T* A,
                                                 int64_t lda, const T* B, int64_t ldb, T* P) {
-  __shared__ T smem[tile_smem_elems<TM, TN>()];
+  __shared__ T smem[mf_smem_elems<T>()];
   const int ch = blockIdx.x, li = blockIdx.y;
   const int i0 = (blockIdx.z % ((rows + TM - 1) / TM)) * TM;
   const int j0 = (blockIdx.z / ((rows + TM - 1) / TM)) * TN;
   const Node nd = nodes[list[li]];
   const int64_t r0 = nd.lo + (int64_t)ch * APPLY_CHUNK;
   const int K = (int)max<int64_t>(0, min<int64_t>(APPLY_CHUNK, nd.hi - r0));
-  TileAcc<T, TM, TN> acc;
+  MfAcc<T> acc;
   acc.zero();
   if (K > 0)
-    mm_tile<T, TM, TN>(rows - i0, cols - j0, K, A + r0 + (int64_t)i0 * lda, lda, 1,
+    mf_tile<T>(rows - i0, cols - j0, K, A + r0 + (int64_t)i0 * lda, lda, 1,
                        B + r0 + (int64_t)j0 * ldb, 1, ldb, acc, smem);
   T* out = P + ((int64_t)li * chunks + ch) * rows * cols;
-  store_tile<T, TM, TN>(rows - i0, cols - j0, out + i0 + (int64_t)j0 * rows, rows, acc, T(1),
+  mf_store<T>(rows - i0, cols - j0, out + i0 + (int64_t)j0 * rows, rows, acc, T(1),
                         T(0));
 }
 

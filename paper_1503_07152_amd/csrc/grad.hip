@@ -10,11 +10,11 @@
 //   gUt_t(child a) = g(uh)_a uh_t^T        gVt_t(child a) = qh_a g(qh)_t^T
 // and gx = A_H^* gy is the adjoint apply itself.
 #include "grad.h"
-#include "tile.h"
+#include "tile_mfma.h"
 
 namespace hm {
 
-constexpr int GM = 64, GN = 64;
+constexpr int GM = MF_T, GN = MF_T;
 
 // Leaves: row tiles of gU, gV and gD.
 template <class T>
@@ -23,7 +23,7 @@ __global__ __launch_bounds__(256) void k_grad_leaf(const Node* nodes, const int3
                                                    const T* GY, int64_t ldgy, const T* UH,
                                                    const T* GQ, T* gU, T* gV, T* gD, int64_t ld,
                                                    int64_t ldd) {
-  __shared__ T smem[tile_smem_elems<GM, GN>()];
+  __shared__ T smem[mf_smem_elems<T>()];
   const int g = leaves[blockIdx.y];
   const Node nd = nodes[g];
   const int64_t i0 = nd.lo + (int64_t)blockIdx.x * GM;
@@ -31,24 +31,24 @@ __global__ __launch_bounds__(256) void k_grad_leaf(const Node* nodes, const int3
   const int M = (int)min<int64_t>(GM, nd.hi - i0);
   const int nt = (int)(nd.hi - nd.lo);
   const int part = blockIdx.z;  // 0: gU, 1: gV, 2..: column tiles of gD
-  TileAcc<T, GM, GN> acc;
+  MfAcc<T> acc;
   acc.zero();
   if (part == 0) {
     if (!gU || nd.level == 0) return;
     // gU(rows) = GY(rows, :) UH_g^T  (UH_g is R x c, ld R)
-    mm_tile<T, GM, GN>(M, R, c, GY + i0, 1, ldgy, UH + (int64_t)g * R * c, R, 1, acc, smem);
-    store_tile<T, GM, GN>(M, R, gU + i0, ld, acc, T(1), T(0));
+    mf_tile<T>(M, R, c, GY + i0, 1, ldgy, UH + (int64_t)g * R * c, R, 1, acc, smem);
+    mf_store<T>(M, R, gU + i0, ld, acc, T(1), T(0));
   } else if (part == 1) {
     if (!gV || nd.level == 0) return;
-    mm_tile<T, GM, GN>(M, R, c, X + i0, 1, ldx, GQ + (int64_t)g * R * c, R, 1, acc, smem);
-    store_tile<T, GM, GN>(M, R, gV + i0, ld, acc, T(1), T(0));
+    mf_tile<T>(M, R, c, X + i0, 1, ldx, GQ + (int64_t)g * R * c, R, 1, acc, smem);
+    mf_store<T>(M, R, gV + i0, ld, acc, T(1), T(0));
   } else {
     if (!gD) return;
     const int j0 = (part - 2) * GN;
     if (j0 >= nt) return;
     // gD(rows, j) = sum_c GY(row, c) X(lo + j, c)
-    mm_tile<T, GM, GN>(M, nt - j0, c, GY + i0, 1, ldgy, X + nd.lo + j0, ldx, 1, acc, smem);
-    store_tile<T, GM, GN>(M, min(GN, nt - j0), gD + i0 + (int64_t)j0 * ldd, ldd, acc, T(1), T(0));
+    mf_tile<T>(M, nt - j0, c, GY + i0, 1, ldgy, X + nd.lo + j0, ldx, 1, acc, smem);
+    mf_store<T>(M, min(GN, nt - j0), gD + i0 + (int64_t)j0 * ldd, ldd, acc, T(1), T(0));
   }
 }
 
@@ -60,19 +60,19 @@ __global__ __launch_bounds__(256) void k_grad_node(const Node* nodes, const int3
                                                    int c, const T* QH, const T* UH,
                                                    const T* GU, const T* GQ, T* gB, T* gUt,
                                                    T* gVt) {
-  __shared__ T smem[tile_smem_elems<GM, GN>()];
+  __shared__ T smem[mf_smem_elems<T>()];
   const int v = list[blockIdx.x];
   const Node nd = nodes[v];
   const int part = blockIdx.y;
   const int64_t blk = (int64_t)v + 1;
-  TileAcc<T, GM, GN> acc;
+  MfAcc<T> acc;
   acc.zero();
   const T* qh = QH + (int64_t)v * R * c;
   if (part == 0) {
     if (!gB || nd.parent < 0) return;
     // gB[v] = g(uh)_sib qh_v^T
-    mm_tile<T, GM, GN>(R, R, c, GU + (int64_t)nd.sib * R * c, 1, R, qh, R, 1, acc, smem);
-    store_tile<T, GM, GN>(R, R, gB + blk * R * R, R, acc, T(1), T(0));
+    mf_tile<T>(R, R, c, GU + (int64_t)nd.sib * R * c, 1, R, qh, R, 1, acc, smem);
+    mf_store<T>(R, R, gB + blk * R * R, R, acc, T(1), T(0));
   } else {
     // part 1: gUt half of child (side 0/1), part 3/4: gVt half
     const bool want_u = part <= 2;
@@ -81,13 +81,13 @@ __global__ __launch_bounds__(256) void k_grad_node(const Node* nodes, const int3
     if (want_u ? !gUt : !gVt) return;
     const int a = side == 0 ? nd.left : nd.right;
     if (want_u) {
-      mm_tile<T, GM, GN>(R, R, c, GU + (int64_t)a * R * c, 1, R, UH + (int64_t)v * R * c, R, 1,
+      mf_tile<T>(R, R, c, GU + (int64_t)a * R * c, 1, R, UH + (int64_t)v * R * c, R, 1,
                          acc, smem);
-      store_tile<T, GM, GN>(R, R, gUt + blk * 2 * R * R + side * R, 2 * R, acc, T(1), T(0));
+      mf_store<T>(R, R, gUt + blk * 2 * R * R + side * R, 2 * R, acc, T(1), T(0));
     } else {
-      mm_tile<T, GM, GN>(R, R, c, QH + (int64_t)a * R * c, 1, R, GQ + (int64_t)v * R * c, R, 1,
+      mf_tile<T>(R, R, c, QH + (int64_t)a * R * c, 1, R, GQ + (int64_t)v * R * c, R, 1,
                          acc, smem);
-      store_tile<T, GM, GN>(R, R, gVt + blk * 2 * R * R + side * R, 2 * R, acc, T(1), T(0));
+      mf_store<T>(R, R, gVt + blk * 2 * R * R + side * R, 2 * R, acc, T(1), T(0));
     }
   }
 }
