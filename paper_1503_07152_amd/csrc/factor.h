@@ -57,7 +57,13 @@ struct SvdDesc {
                          // xrows) with singular value 0, an orthonormal completion
   int32_t xscaled;       // 1: X receives X diag(s) = T^T W (needs trans = 0), formed
                          // from the converged left vectors; no rotations accumulated
-  int32_t pad_;
+  int32_t gram;          // Gram form: T is the pivoted Cholesky factor L of M^T M
+                         // (h rows in pivoted order, c = min(c, *dyn) columns); the
+                         // converged columns a_j = s_j u_j give the right singular
+                         // vectors x_j = P u_j of M: X receives X diag(s), W receives
+                         // X diag(1/s^2) (so M W = U), rows scattered by perm; W
+                         // columns kout .. wrows - 1 are set to zero
+  const int32_t* perm;
 };
 
 // Column-pivoted Householder QR of A = R^T (c x h, R stored h x c) that stops
@@ -80,6 +86,26 @@ struct QrcpDesc {
   int32_t pad_;
 };
 void launch_qrcp(const QrcpDesc* d, int n, hipStream_t s);
+
+// Pivoted Cholesky of a symmetric positive semidefinite c x c matrix (the
+// Gram matrix M^T M of a node block), c <= 96: P^T G P = L L^T with L (c x
+// rho) lower trapezoidal, rows in pivoted order.  Diagonal pivoting; stops at
+// the first step k >= kneed whose largest remaining pivot is <= eta^2 times
+// the largest initial one.  A step k < kneed whose pivot is <= tau^2 times it
+// (a direction the Gram matrix cannot resolve) sets *short_flag and stops.
+struct PcholDesc {
+  const double* G;  // c x c, ld ldG (only read)
+  int64_t ldG;
+  int32_t c, kneed;
+  double eta, tau;
+  double* L;        // c x rho, ld ldL (rows in pivoted order)
+  int64_t ldL;
+  int32_t* perm;    // c: pivoted row i is row perm[i] of G
+  int32_t* rho;
+  int32_t* short_flag;
+  int32_t pad_;
+};
+void launch_pchol(const PcholDesc* d, int n, hipStream_t s);
 
 void launch_panel_qr(const PanelDesc* d, int n, hipStream_t s);
 void launch_apply_q(const PanelDesc* d, int n, hipStream_t s);

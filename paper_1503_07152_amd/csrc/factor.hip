@@ -586,6 +586,102 @@ void launch_qrcp(const QrcpDesc* d, int n, hipStream_t s) {
   KCHK();
 }
 
+// ------------------------------------------------------------ pivoted Cholesky --
+// Diagonal-pivoted Cholesky of a c x c PSD matrix in LDS (the Gram matrix of
+// a node block), stopped at the numerical rank; one step per column: every
+// wave finds the pivot (largest remaining diagonal, lowest index on ties),
+// the column of L is formed, then the trailing Schur complement is updated
+// by the whole workgroup.  Swaps are logical (a map in LDS).
+__global__ __launch_bounds__(FT) void k_pchol(const PcholDesc* descs) {
+  __shared__ double sG[QP_LD * FAC_CMAX];
+  __shared__ double sdg[FAC_CMAX];
+  __shared__ double sl[FAC_CMAX];
+  __shared__ int scol[FAC_CMAX];
+  const PcholDesc d = descs[blockIdx.x];
+  const int c = d.c;
+  const int tid = threadIdx.x, lane = tid & 63;
+  for (int idx = tid; idx < c * c; idx += FT) {
+    const int i = idx % c, j = idx / c;
+    sG[i + j * QP_LD] = d.G[i + (int64_t)j * d.ldG];
+  }
+  for (int j = tid; j < c; j += FT) {
+    scol[j] = j;
+    sdg[j] = d.G[j + (int64_t)j * d.ldG];
+  }
+  __syncthreads();
+  double thr = 0.0, thr_short = 0.0;
+  int rho = c;
+  for (int k = 0; k < c; ++k) {
+    const int j1 = k + lane, j2 = k + lane + 64;
+    const double v1 = j1 < c ? sdg[j1] : -1.0;
+    const double v2 = j2 < c ? sdg[j2] : -1.0;
+    const double vmax = max64(fmax(v1, v2));
+    const uint64_t m1 = __ballot(v1 == vmax), m2 = __ballot(v2 == vmax);
+    const int p = m1 ? k + __ffsll((unsigned long long)m1) - 1
+                     : k + 64 + __ffsll((unsigned long long)m2) - 1;
+    if (k == 0) {
+      thr = d.eta * d.eta * vmax;
+      thr_short = d.tau * d.tau * vmax;
+    }
+    if (k < d.kneed && !(vmax > thr_short)) {   // not resolvable: the caller falls back
+      if (tid == 0) atomicOr(d.short_flag, 1);
+      rho = k;
+      break;
+    }
+    if (k >= d.kneed && !(vmax > thr)) {
+      rho = k;
+      break;
+    }
+    const int pk = scol[p], pp = scol[k];
+    const double lkk = sqrt(vmax);
+    const double inv = 1.0 / lkk;
+    // column k of L: l_i = G'(i, pivot) / l_kk for logical rows i > k
+    for (int i = k + 1 + tid; i < c; i += FT) {
+      const int pi = i == p ? pp : scol[i];
+      sl[i] = sG[pi + pk * QP_LD] * inv;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      scol[k] = pk;
+      scol[p] = pp;
+    }
+    // column k of L by physical row (later swaps reorder rows, not entries)
+    for (int i = tid; i < c; i += FT) {
+      const int pi = i == k ? pk : (i == p ? pp : scol[i]);
+      d.L[pi + (int64_t)k * d.ldL] = i < k ? 0.0 : (i == k ? lkk : sl[i]);
+    }
+    // Schur complement on the trailing rows / columns
+    const int nt = c - k - 1;
+    for (int e = tid; e < nt * nt; e += FT) {
+      const int ii = k + 1 + e % nt, jj = k + 1 + e / nt;
+      const int pi = ii == p ? pp : scol[ii], pj = jj == p ? pp : scol[jj];
+      const double g = fma(-sl[ii], sl[jj], sG[pi + pj * QP_LD]);
+      sG[pi + pj * QP_LD] = g;
+      if (ii == jj) sdg[ii] = g;
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  // rows of L into the final pivoted order (through LDS)
+  for (int e = tid; e < c * rho; e += FT) {
+    const int i = e % c, k = e / c;
+    sG[i + k * QP_LD] = d.L[scol[i] + (int64_t)k * d.ldL];
+  }
+  __syncthreads();
+  for (int e = tid; e < c * rho; e += FT) {
+    const int i = e % c, k = e / c;
+    d.L[i + (int64_t)k * d.ldL] = sG[i + k * QP_LD];
+  }
+  for (int i = tid; i < c; i += FT) d.perm[i] = scol[i];
+  if (tid == 0) *d.rho = rho;
+}
+
+void launch_pchol(const PcholDesc* d, int n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_pchol, dim3(n), dim3(FT), 0, s, d);
+  KCHK();
+}
+
 // ------------------------------------------------------------ Jacobi SVD --
 // One-sided (Hestenes) Jacobi on the columns of an h x c matrix T (T = R, or
 // T = R^T when the descriptor asks for the transpose): T Z = W diag(s).  Pairs
@@ -708,11 +804,11 @@ __global__ __launch_bounds__(FT) void k_jacobi(const SvdDesc* descs) {
   int h = d.h, c = d.c;
   if (d.dyn) {
     const int r = max(0, min(d.c, *d.dyn));
-    h = min(h, r);
+    if (!d.gram) h = min(h, r);
     c = r;
   }
   const bool wantX = d.X != nullptr;
-  const bool accZ = wantX && !d.xscaled;   // accumulate the rotations
+  const bool accZ = wantX && !d.xscaled && !d.gram;   // accumulate the rotations
   const int tid = threadIdx.x;
   for (int idx = tid; idx < h * c; idx += FT) {
     const int i = idx % h, j = idx / h;
@@ -747,7 +843,7 @@ __global__ __launch_bounds__(FT) void k_jacobi(const SvdDesc* descs) {
     for (int i2 = 0; i2 < c; ++i2) rk += (snorm[i2] > sj) || (snorm[i2] == sj && i2 < j);
     srank[j] = rk;
   }
-  if (wantX && !accZ)   // T (h x c) for X diag(s) = T^T W
+  if (wantX && !accZ && !d.gram)   // T (h x c) for X diag(s) = T^T W
     for (int idx = tid; idx < h * c; idx += FT) {
       const int i = idx % h, j = idx / h;
       sZ[i + j * JAC_LD] = d.R[i + (int64_t)j * d.ldR];
@@ -756,6 +852,30 @@ __global__ __launch_bounds__(FT) void k_jacobi(const SvdDesc* descs) {
   // column j goes to position srank[j] (descending norms, ties by index),
   // embedded in the wrows (xrows) frame; positions c .. kout - 1 get unit
   // vectors e_j and singular value 0
+  if (d.gram) {
+    // x_j = P u_j: W(perm[i], rk) = a_j(i) / s_j^2, X(perm[i], rk) = a_j(i)
+    for (int e = tid; e < c * h; e += FT) {
+      const int i = e % h, j = e / h;
+      const int rk = srank[j];
+      if (rk >= d.kout) continue;
+      const double sj = snorm[j];
+      if (i == 0) d.sv[rk] = sj;
+      const double a = sA[i + j * JAC_LD];
+      const int pi = d.perm[i];
+      d.W[pi + (int64_t)rk * d.ldW] = sj > 0.0 ? a / (sj * sj) : 0.0;
+      if (wantX) d.X[pi + (int64_t)rk * d.ldX] = a;
+    }
+    for (int e = tid; e < (d.kout - c) * h; e += FT) {
+      const int i = e % h, rk = c + e / h;
+      if (i == 0) d.sv[rk] = 0.0;
+      d.W[i + (int64_t)rk * d.ldW] = 0.0;
+      if (wantX) d.X[i + (int64_t)rk * d.ldX] = 0.0;
+    }
+    // W columns kout .. wrows - 1 (a wider product shared with other nodes) are zero
+    for (int e = tid; e < (d.wrows - d.kout) * h; e += FT)
+      d.W[e % h + (int64_t)(d.kout + e / h) * d.ldW] = 0.0;
+    return;
+  }
   const int rows = max(d.wrows, wantX ? d.xrows : 0);
   for (int e = tid; e < c * rows; e += FT) {
     const int i = e % rows, j = e / rows;

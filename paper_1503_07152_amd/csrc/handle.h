@@ -123,7 +123,12 @@ struct OpRunner {
   ~OpRunner();
   void apply(bool adjoint, int64_t n, int c, const double* X, int64_t ldx, double* Y, int64_t ldy);
   double elapsed_ms();               // after stream synchronisation
+  void reset_stats();                // forget earlier calls (a compress that starts over)
 };
+
+// Internal flag of hbs_compress_forest (beside the HM_FLAG_* bits): node
+// SVDs on the Householder path only.
+constexpr int32_t HM_FLAG_INTERNAL_NO_GRAM = 1 << 30;
 
 // Leading left singular vectors of node blocks: for each job, the block
 // M(lo : lo+rows, 0 : cols) is factored by Householder TSQR, its triangle by

@@ -59,6 +59,13 @@ void OpRunner::apply(bool adjoint, int64_t n, int c, const double* X, int64_t ld
   HIPCHK(hipEventRecord(e1, s));
 }
 
+void OpRunner::reset_stats() {
+  for (auto e : ev) (void)hipEventDestroy(e);
+  ev.clear();
+  calls = 0;
+  columns = 0;
+}
+
 double OpRunner::elapsed_ms() {
   double t = 0.0;
   for (size_t i = 0; i + 1 < ev.size(); i += 2) {
@@ -287,6 +294,65 @@ void node_svd(const std::vector<SvdJob>& jobs, double* M, int64_t ldm, double* U
   for (int st = nst - 1; st >= 0; --st) launch_apply_q(dpd[st], (int)pd[st].size(), s);
 }
 
+// Node SVD from the Gram matrix, for samples of limited precision: G = M^T M
+// per node (FP64 MFMA), its pivoted Cholesky factor L (P^T G P = L L^T,
+// stopped at the numerical rank, at least kout columns), one-sided Jacobi on
+// L giving the right singular vectors X = P U_L and the singular values of
+// M, then the left ones U = M X diag(1/s).  The Gram matrix resolves
+// singular values down to about sqrt(eps) s_1, far below the noise of BF16
+// samples; a node with one of its kout leading singular values below
+// GRAM_TAU s_1 sets *short_flag (the caller then uses node_svd).
+constexpr double GRAM_TAU = 1e-5;
+
+void node_svd_gram(const std::vector<SvdJob>& jobs, const Node* dn, const int32_t* dk,
+                   int64_t max_rows, int nn, double* M, int64_t ldm, double* Uout, int64_t ldu,
+                   double* sv, double* XS, int R, Workspace& ws, Workspace& ws_seg, Keeper& kp,
+                   hipStream_t s, int32_t* sweeps, int32_t* short_flag) {
+  if (jobs.empty()) return;
+  const int nj = (int)jobs.size();
+  const int c = jobs[0].cols;
+  int kmax = 0;
+  for (auto& j : jobs) kmax = std::max(kmax, j.kout);
+  Alloc al;
+  const size_t g_off = al.take((size_t)nn * c * c * sizeof(double));
+  const size_t xi_off = al.take((size_t)nn * FAC_CMAX * R * sizeof(double));
+  const size_t l_off = al.take((size_t)nj * FAC_CMAX * FAC_CMAX * sizeof(double));
+  constexpr int PS = FAC_CMAX + 32;   // perm entries, then the rank
+  const size_t p_off = al.take((size_t)nj * PS * sizeof(int32_t));
+  ws.ensure(al.off, s);
+  char* base = ws.base();
+  double* G = reinterpret_cast<double*>(base + g_off);
+  double* XI = reinterpret_cast<double*>(base + xi_off);
+  double* L = reinterpret_cast<double*>(base + l_off);
+  int32_t* PM = reinterpret_cast<int32_t*>(base + p_off);
+  ws_seg.ensure(seg_tn_work_bytes<double>(nj, max_rows, c, c), s);
+  seg_tn<double>(dn, dk, nj, max_rows, c, c, M, ldm, M, ldm, G, (int64_t)c * c, c, 1.0, 0.0,
+                 ws_seg.base(), s);
+  std::vector<PcholDesc> pd(nj);
+  std::vector<SvdDesc> sd(nj);
+  for (int q = 0; q < nj; ++q) {
+    const SvdJob& jb = jobs[q];
+    int32_t* perm = PM + (int64_t)q * PS;
+    PcholDesc& p = pd[q];
+    p.G = G + (int64_t)jb.node * c * c; p.ldG = c; p.c = c; p.kneed = jb.kout;
+    p.eta = jb.eta; p.tau = GRAM_TAU;
+    p.L = L + (int64_t)q * FAC_CMAX * FAC_CMAX; p.ldL = FAC_CMAX;
+    p.perm = perm; p.rho = perm + FAC_CMAX; p.short_flag = short_flag;
+    SvdDesc& v = sd[q];
+    v.R = p.L; v.ldR = FAC_CMAX; v.h = c; v.c = c; v.trans = 0; v.dyn = p.rho; v.gram = 1;
+    v.perm = perm;
+    v.W = XI + (int64_t)jb.node * FAC_CMAX * R; v.ldW = FAC_CMAX;
+    v.X = XS ? XS + (int64_t)jb.node * 2 * R * R : nullptr; v.ldX = 2 * R;
+    v.sv = sv + (int64_t)jb.node * R;
+    v.kout = jb.kout; v.wrows = kmax;   // W columns kout .. kmax - 1 are zeroed
+    v.sweeps = sweeps;
+  }
+  launch_pchol(kp.put(pd, s), nj, s);
+  launch_jacobi_svd(kp.put(sd, s), nj, s);
+  launch_node_nn(dn, dk, nj, max_rows, c, kmax, M, ldm, XI, (int64_t)FAC_CMAX * R, FAC_CMAX, Uout,
+                 ldu, s, 0);
+}
+
 double sample_rank_eta(int dtype) {
   if (dtype == HM_BF16) return std::ldexp(1.0, -8) / 16.0;
   if (dtype == HM_F32) return std::ldexp(1.0, -24) / 16.0;
@@ -348,6 +414,16 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
     const OpRunner* o = ops.size() == f.inst.size() ? ops[i] : ops[0];
     eta_inst[i] = sample_rank_eta(o->op.kind == HM_OP_KERNEL ? o->op.sample_dtype : HM_F64);
   }
+  // node SVDs from Gram matrices when every instance samples in BF16 with one
+  // padded rank (uniform node blocks); else (or after a node the Gram matrix
+  // cannot resolve, see below) the Householder path
+  bool use_gram = !(flags & HM_FLAG_INTERNAL_NO_GRAM);
+  for (size_t i = 0; i < f.inst.size(); ++i) {
+    const OpRunner* o = ops.size() == f.inst.size() ? ops[i] : ops[0];
+    use_gram &= o->op.kind == HM_OP_KERNEL && o->op.sample_dtype == HM_BF16 && f.inst[i].r == R;
+  }
+  Workspace ws_gram;
+  const Forest f_in = f;   // for a rerun on the Householder path
   // ---- buffers ---------------------------------------------------------------
   const int W = std::max(2 * R, nmax);
   DevBuf Om((size_t)N * W * 8), Y((size_t)N * W * 8), M((size_t)N * 2 * R * 8);
@@ -413,8 +489,12 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
                       f.inst[nd.inst].k, eta_inst[nd.inst]});
     }
     launch_fill(un, N, R, N, 0.0, s);
-    node_svd(jobs, m, N, un, N, yv.as<double>(), nullptr, R, false, ws_svd, kp, s,
-             flag.as<int32_t>() + 2);
+    if (use_gram)
+      node_svd_gram(jobs, dn, dk, lv.max_kid_rows, nn, m, N, un, N, yv.as<double>(), nullptr, R,
+                    ws_svd, ws_gram, kp, s, flag.as<int32_t>() + 2, flag.as<int32_t>() + 3);
+    else
+      node_svd(jobs, m, N, un, N, yv.as<double>(), nullptr, R, false, ws_svd, kp, s,
+               flag.as<int32_t>() + 2);
     if (l >= 1) {
       ws_seg.ensure(seg_tn_work_bytes<double>(nk, lv.max_kid_rows, R, R), s);
       seg_tn<double>(dn, dk, nk, lv.max_kid_rows, R, R, un, N, uc, N, Ut.as<double>(),
@@ -431,8 +511,13 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
                             N, s);
     launch_fill(vn, N, R, N, 0.0, s);
     // X diag(z) directly (only that product enters B)
-    node_svd(jobs, m, N, vn, N, zv.as<double>(), Xr.as<double>(), R, false, ws_svd, kp, s,
-             flag.as<int32_t>() + 2, true);
+    if (use_gram)
+      node_svd_gram(jobs, dn, dk, lv.max_kid_rows, nn, m, N, vn, N, zv.as<double>(),
+                    Xr.as<double>(), R, ws_svd, ws_gram, kp, s, flag.as<int32_t>() + 2,
+                    flag.as<int32_t>() + 3);
+    else
+      node_svd(jobs, m, N, vn, N, zv.as<double>(), Xr.as<double>(), R, false, ws_svd, kp, s,
+               flag.as<int32_t>() + 2, true);
     launch_form_b(dn, di, dk, nk, R, Xr.as<double>(), nullptr, B.as<double>(), s);
     if (l >= 1)
       seg_tn<double>(dn, dk, nk, lv.max_kid_rows, R, R, vn, N, vc, N, Vt.as<double>(), 2 * R * R,
@@ -566,6 +651,12 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
   }
   HIPCHK(hipStreamSynchronize(s));
   if (hflag[0]) HM_THROW(HM_ERR_NONFINITE, "operator samples contain NaN or Inf");
+  if (hflag[3]) {
+    // a node block had a leading singular value the Gram matrix cannot
+    // resolve: compress again with Householder node factorisations
+    for (auto* o : ops) o->reset_stats();
+    return hbs_compress_forest(f_in, ops, flags | HM_FLAG_INTERNAL_NO_GRAM, s, status);
+  }
   if (!to_id)
     for (int g = 0; g < nn; ++g) {
       const Node& nd = f.nodes[g];
