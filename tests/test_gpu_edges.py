@@ -100,3 +100,25 @@ def test_error_estimate_E_at_tolerance():
     E = ometrics.estimate_E(K.apply, lambda w: h.apply(torch.from_numpy(w)).cpu().numpy(), n)
     print(f"E = {E:.2e} (tol {tol}), ranks {h.info()['min_rank']}..{h.info()['max_rank']}")
     assert E < 10 * tol
+
+
+def test_bf16_rank_deficient_blocks_fall_back_to_householder():
+    """BF16 samples take the Gram-matrix node SVD; blocks whose leading r
+    singular values it cannot resolve (here: two clusters of coincident
+    points, every off-diagonal block exactly rank one after rounding) make the
+    compression rerun on the Householder path, with the same accuracy as FP64
+    sampling of the same operator."""
+    n, leaf, k, p = 512, 64, 8, 4
+    P = np.zeros((n, 2))
+    P[n // 2:, 0] = 1.0
+    K = oops.KernelOp(P, "near", 1e-3)
+    x = W.gaussian((n, 3), seed=8)
+    ref = K.apply(x)
+    errs = {}
+    for name, dt in (("bf16", hm.HM_BF16), ("f64", hm.HM_F64)):
+        h = hm.hbs_compress(hm.Options(n, leaf, k, p, seed=3), hm.KernelOperator(P, "near", 1e-3, dt))
+        y = h.apply(torch.from_numpy(x)).cpu().numpy()
+        assert np.isfinite(y).all()
+        errs[name] = rel(y, ref)
+    print(f"errors {errs}")
+    assert errs["f64"] < 1e-12 and errs["bf16"] < 5e-3
