@@ -109,6 +109,10 @@ def main():
     n = args.n
     r = K + P
     torch.cuda.set_device(0)
+    # the library's device memory (compress workspaces, handles, apply scratch)
+    # comes from torch's caching allocator, as in a PyTorch program: no
+    # hipMalloc / hipFree (which synchronises) inside the timed calls
+    hm.use_torch_allocator(True)
     if args.copy_calibration:
         a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
