@@ -991,63 +991,66 @@ __global__ __launch_bounds__(256) void k_cpqr_id(const Node* nodes, const Instan
   for (int b = tid; b < n; b += 256) sperm[b] = b;
   __syncthreads();
   const int kcap = min(min(in.k, in.r), min(R, n));
+  const int lane = tid & 63, wave = tid >> 6;
+  // squared norms of the candidate columns (one thread per column)
+  for (int b = tid; b < n; b += 256) {
+    double s2 = 0.0;
+    for (int a = 0; a < R; ++a) s2 = fma(sM[a + b * ldm], sM[a + b * ldm], s2);
+    snrm[b] = s2;
+  }
+  __syncthreads();
   int k = 0;
   double ref = 0.0;
   for (int j = 0; j < kcap; ++j) {
-    for (int b = j + tid; b < n; b += 256) {
-      double s = 0.0;
-      for (int a = j; a < R; ++a) s += sM[a + b * ldm] * sM[a + b * ldm];
-      snrm[b] = s;
+    // pivot: largest remaining norm, lowest index on ties (every wave alike)
+    double bv = -1.0;
+    int bi = n;
+#pragma unroll
+    for (int q = 0; q < ID_NMAX / 64; ++q) {
+      const int b = j + lane + 64 * q;
+      if (b < n && snrm[b] > bv) { bv = snrm[b]; bi = b; }
     }
-    __syncthreads();
-    if (tid == 0) {
-      int p = j;
-      double best = snrm[j];
-      for (int b = j + 1; b < n; ++b)
-        if (snrm[b] > best) { best = snrm[b]; p = b; }
-      sk[0] = p;
-      sc[0] = sqrt(best);
-    }
-    __syncthreads();
-    const int p = sk[0];
-    const double nrm = sc[0];
+    const double vmax = max64(bv);
+    const int p = (int)(-max64(bv == vmax ? -(double)bi : -1e9));
+    const double nrm = sqrt(vmax);
     if (j == 0) ref = nrm;
     if (nrm == 0.0 || (in.tol > 0.0 && nrm <= in.tol * ref)) break;
-    if (p != j) {
-      for (int a = tid; a < R; a += 256) {
-        const double t = sM[a + j * ldm];
-        sM[a + j * ldm] = sM[a + p * ldm];
-        sM[a + p * ldm] = t;
+    __syncthreads();   // every wave has read the norms
+    if (wave == 0) {
+      // Householder reflector of the pivot column (v = x - alpha e_j, H = I - f v v^T),
+      // written into position j in its final form; old column j goes to p
+      const bool in_r = lane < R;
+      const double x = in_r ? sM[lane + p * ldm] : 0.0;
+      const double y = in_r ? sM[lane + j * ldm] : 0.0;
+      const double x0 = readlane_d(x, j);
+      const double s2 = sum64(lane >= j ? x * x : 0.0);
+      const double alpha = -copysign(sqrt(s2), x0);
+      const double vj = x0 - alpha;
+      const double vn = s2 - x0 * x0 + vj * vj;
+      if (in_r) {
+        sv[lane] = lane == j ? vj : (lane > j ? x : 0.0);
+        sM[lane + j * ldm] = lane < j ? x : (lane == j ? alpha : 0.0);
+        if (p != j) sM[lane + p * ldm] = y;
       }
-      if (tid == 0) {
+      if (lane == 0) {
+        sc[2] = vn > 0.0 ? 2.0 / vn : 0.0;
         const int t = sperm[j]; sperm[j] = sperm[p]; sperm[p] = t;
       }
     }
     __syncthreads();
-    // Householder reflector zeroing M(j+1:R, j): v = x - alpha e1, H = I - 2 v v^T / (v^T v)
-    if (tid == 0) {
-      double s = 0.0;
-      for (int a = j; a < R; ++a) s += sM[a + j * ldm] * sM[a + j * ldm];
-      const double x0 = sM[j + j * ldm];
-      const double alpha = -copysign(sqrt(s), x0);
-      for (int a = j; a < R; ++a) sv[a] = sM[a + j * ldm];
-      sv[j] = x0 - alpha;
-      const double vn = s - x0 * x0 + sv[j] * sv[j];
-      sc[1] = alpha;
-      sc[2] = vn > 0.0 ? 2.0 / vn : 0.0;
-    }
-    __syncthreads();
+    // apply H to the remaining candidates, then their norms below row j
     const double f = sc[2];
     for (int b = j + 1 + tid; b < n; b += 256) {
-      double s = 0.0;
-      for (int a = j; a < R; ++a) s += sv[a] * sM[a + b * ldm];
-      s *= f;
-      for (int a = j; a < R; ++a) sM[a + b * ldm] -= s * sv[a];
-    }
-    __syncthreads();
-    if (tid == 0) {
-      sM[j + j * ldm] = sc[1];
-      for (int a = j + 1; a < R; ++a) sM[a + j * ldm] = 0.0;
+      double s2 = 0.0;
+      for (int a = j; a < R; ++a) s2 = fma(sv[a], sM[a + b * ldm], s2);
+      s2 *= f;
+      double n2 = 0.0;
+      for (int a = j; a < R; ++a) {
+        const double v = fma(-s2, sv[a], sM[a + b * ldm]);
+        sM[a + b * ldm] = v;
+        if (a > j) n2 = fma(v, v, n2);
+      }
+      snrm[b] = n2;
     }
     __syncthreads();
     k = j + 1;
