@@ -54,8 +54,8 @@ SLOTS_PER_ENTRY = 13.5
 # read for a plain 256 MiB device copy (FETCH_SIZE reads 0.5x the bytes moved,
 # WRITE_SIZE 1.0x).  Valid only for the sampler source they were taken on
 # (SHA-1 below); otherwise the traffic is unknown.
-SAMPLER_TRAFFIC = {"sha1": "1666965a1bfdb7e48b412f3e0d41166719ffaec6",
-                   "fetch_kib": 83280.4 + 24590.5, "write_kib": 51324.4 + 12320.0,
+SAMPLER_TRAFFIC = {"sha1": "8cddf69436dd77ac4a9e4e66cff0d99cb89ef475",
+                   "fetch_kib": 82408.7 + 24590.5, "write_kib": 52577.7 + 12320.0,
                    "fetch_scale": 2.0, "write_scale": 1.0}
 
 

@@ -109,7 +109,8 @@ void launch_pchol(const PcholDesc* d, int n, hipStream_t s);
 
 void launch_panel_qr(const PanelDesc* d, int n, hipStream_t s);
 void launch_apply_q(const PanelDesc* d, int n, hipStream_t s);
-void launch_jacobi_svd(const SvdDesc* d, int n, hipStream_t s);
+// gram_only: every descriptor is in Gram form (smaller LDS footprint).
+void launch_jacobi_svd(const SvdDesc* d, int n, hipStream_t s, bool gram_only = false);
 
 // Node block of the peeling step (Fig. 4): for each child v (list), rows I_v of
 // M get [S(I_v, off : off + r), Lpar(I_v, 0:r) diag(w_parent)] with off = 0 for

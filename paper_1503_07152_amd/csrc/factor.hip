@@ -794,9 +794,12 @@ __device__ __forceinline__ int jacobi_sweeps(double* sA, double* sZ, int h, int 
   return sweep + 1;
 }
 
+// NEED_Z: the descriptors may accumulate rotations or form T^T W (a second
+// LDS matrix); without it (the Gram route) a workgroup takes half the LDS.
+template <bool NEED_Z>
 __global__ __launch_bounds__(FT) void k_jacobi(const SvdDesc* descs) {
   __shared__ double sA[FAC_CMAX * JAC_LD];
-  __shared__ double sZ[FAC_CMAX * JAC_LD];
+  __shared__ double sZ[NEED_Z ? FAC_CMAX * JAC_LD : 1];
   __shared__ double snorm[FAC_CMAX];
   __shared__ int srank[FAC_CMAX];
   __shared__ int flag;
@@ -808,7 +811,7 @@ __global__ __launch_bounds__(FT) void k_jacobi(const SvdDesc* descs) {
     c = r;
   }
   const bool wantX = d.X != nullptr;
-  const bool accZ = wantX && !d.xscaled && !d.gram;   // accumulate the rotations
+  const bool accZ = NEED_Z && wantX && !d.xscaled && !d.gram;   // accumulate the rotations
   const int tid = threadIdx.x;
   for (int idx = tid; idx < h * c; idx += FT) {
     const int i = idx % h, j = idx / h;
@@ -843,7 +846,7 @@ __global__ __launch_bounds__(FT) void k_jacobi(const SvdDesc* descs) {
     for (int i2 = 0; i2 < c; ++i2) rk += (snorm[i2] > sj) || (snorm[i2] == sj && i2 < j);
     srank[j] = rk;
   }
-  if (wantX && !accZ && !d.gram)   // T (h x c) for X diag(s) = T^T W
+  if (NEED_Z && wantX && !accZ && !d.gram)   // T (h x c) for X diag(s) = T^T W
     for (int idx = tid; idx < h * c; idx += FT) {
       const int i = idx % h, j = idx / h;
       sZ[i + j * JAC_LD] = d.R[i + (int64_t)j * d.ldR];
@@ -890,7 +893,7 @@ __global__ __launch_bounds__(FT) void k_jacobi(const SvdDesc* descs) {
       if (i < c) {
         if (accZ) {
           xv = sZ[i + j * JAC_LD];
-        } else if (sj > 0.0) {
+        } else if (NEED_Z && sj > 0.0) {
           // (T^T w_j)_i with w_j = T z_j / s_j the converged column j
           for (int l = 0; l < h; ++l) xv = fma(sZ[l + i * JAC_LD], sA[l + j * JAC_LD], xv);
           xv /= sj;
@@ -907,9 +910,12 @@ __global__ __launch_bounds__(FT) void k_jacobi(const SvdDesc* descs) {
   }
 }
 
-void launch_jacobi_svd(const SvdDesc* d, int n, hipStream_t s) {
+void launch_jacobi_svd(const SvdDesc* d, int n, hipStream_t s, bool gram_only) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_jacobi, dim3(n), dim3(FT), 0, s, d);
+  if (gram_only)
+    hipLaunchKernelGGL(k_jacobi<false>, dim3(n), dim3(FT), 0, s, d);
+  else
+    hipLaunchKernelGGL(k_jacobi<true>, dim3(n), dim3(FT), 0, s, d);
   KCHK();
 }
 

@@ -348,7 +348,7 @@ void node_svd_gram(const std::vector<SvdJob>& jobs, const Node* dn, const int32_
     v.sweeps = sweeps;
   }
   launch_pchol(kp.put(pd, s), nj, s);
-  launch_jacobi_svd(kp.put(sd, s), nj, s);
+  launch_jacobi_svd(kp.put(sd, s), nj, s, true);
   launch_node_nn(dn, dk, nj, max_rows, c, kmax, M, ldm, XI, (int64_t)FAC_CMAX * R, FAC_CMAX, Uout,
                  ldu, s, 0);
 }

@@ -111,8 +111,10 @@ constexpr int SMP_FLUSH = 32;
 // One block = SmpShape<MODE>::WAVES waves x RT 16-row tiles; the whole X is streamed
 // through LDS in K-tiles, double-buffered, the next tile prefetched into registers
 // while the current one feeds the MFMAs.
+// The FP32 form is held to two waves per SIMD (244 VGPRs, no spills): left
+// to itself the compiler took 300 registers and one wave per SIMD, 1.6x slower.
 template <int MODE, int SRC>
-__global__ __launch_bounds__(SmpShape<MODE>::THREADS) void k_sampler(int64_t n, int c, int cp, const double* pts,
+__global__ __launch_bounds__(SmpShape<MODE>::THREADS) __attribute__((amdgpu_waves_per_eu(MODE == 1 ? 2 : 1))) void k_sampler(int64_t n, int c, int cp, const double* pts,
                                                  double kp, const double* Ad, int64_t lda,
                                                  const typename ModeT<MODE>::T* Xp,
                                                  const uint32_t* mask, double* Y, int64_t ldy) {
