@@ -13,6 +13,7 @@ from __future__ import annotations
 import atexit
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 import torch
@@ -263,29 +264,45 @@ def use_torch_allocator(enable=True):
         _check(lib.hm_set_allocator(ALLOC_FN(), FREE_FN(), None))
         return
 
-    def alloc(ctx, nbytes, stream):
+    # the callbacks bind what they use: module globals are cleared during
+    # interpreter shutdown
+    def alloc(ctx, nbytes, stream, _alloc=torch.cuda.caching_allocator_alloc):
         try:
-            return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+            return _alloc(int(nbytes), stream=int(stream or 0))
         except Exception:   # reported to the library as an allocation failure
             return None
 
-    def free(ctx, ptr, stream):
-        if _ALLOC_STATE["exiting"]:
+    def free(ctx, ptr, stream, _st=_ALLOC_STATE, _delete=torch.cuda.caching_allocator_delete):
+        if _st["exiting"]:
             return   # torch may already be torn down; the process is ending
         try:
-            torch.cuda.caching_allocator_delete(int(ptr))
+            _delete(int(ptr))
         except Exception:
             pass
 
     hooks = (ALLOC_FN(alloc), FREE_FN(free))
     _check(lib.hm_set_allocator(hooks[0], hooks[1], None))
     # every buffer made through these hooks calls them when it is freed, so
-    # they stay referenced for the life of the process
-    _ALLOC_STATE.setdefault("all", []).append(hooks)
+    # the thunks must outlive every buffer: one extra reference that is
+    # never dropped keeps them alive until the process ends, whatever order
+    # shutdown clears modules in
+    C.pythonapi.Py_IncRef(C.py_object(hooks))
     _ALLOC_STATE["hooks"] = hooks
 
 
-atexit.register(lambda: _ALLOC_STATE.__setitem__("exiting", True))
+# Handles still alive when the interpreter exits are freed by an exit handler,
+# while torch (and its caching allocator, if it backs the library) is whole;
+# this handler is registered after torch's and so runs before them.
+_LIVE = weakref.WeakSet()
+
+
+def _release_at_exit():
+    for obj in list(_LIVE):
+        obj._release()
+    _ALLOC_STATE["exiting"] = True
+
+
+atexit.register(_release_at_exit)
 
 
 class HBS:
@@ -294,15 +311,18 @@ class HBS:
     def __init__(self, handle, status=HM_OK):
         self.handle = handle
         self.status = status
+        _LIVE.add(self)
 
     # bound at class creation: module globals may already be cleared when
     # the last handles are collected at interpreter exit
     _free = lib.hm_hbs_free
 
-    def __del__(self):
+    def _release(self):
         if getattr(self, "handle", None):
             type(self)._free(self.handle)
             self.handle = None
+
+    __del__ = _release
 
     def info(self):
         return _info(lib.hm_hbs_info, self.handle)
@@ -366,15 +386,18 @@ class HODLR:
     def __init__(self, handle, status=HM_OK):
         self.handle = handle
         self.status = status
+        _LIVE.add(self)
 
     # bound at class creation: module globals may already be cleared when
     # the last handles are collected at interpreter exit
     _free = lib.hm_hodlr_free
 
-    def __del__(self):
+    def _release(self):
         if getattr(self, "handle", None):
             type(self)._free(self.handle)
             self.handle = None
+
+    __del__ = _release
 
     def info(self):
         return _info(lib.hm_hodlr_info, self.handle)
