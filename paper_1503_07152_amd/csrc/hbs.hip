@@ -38,8 +38,9 @@ void OpRunner::apply(bool adjoint, int64_t n, int c, const double* X, int64_t ld
                        : op.sample_dtype == HM_BF16 ? 2 : 0;
       const int src = op.kind == HM_OP_DENSE ? (adjoint ? 3 : 2)
                       : (op.kernel_id == HM_KERNEL_LOG ? 0 : 1);
-      for (int c0 = 0; c0 < c; c0 += SMP_MAXC) {
-        const int cc = std::min(SMP_MAXC, c - c0);
+      const int cmax = sampler_max_cols(mode);
+      for (int c0 = 0; c0 < c; c0 += cmax) {
+        const int cc = std::min(cmax, c - c0);
         work.ensure(sampler_pack_bytes(mode, n, cc), s);
         sampler_apply(mode, src, n, cc, op.points, op.kparam, op.dense, op.ld,
                       X + (int64_t)c0 * ldx, ldx, Y + (int64_t)c0 * ldy, ldy, work.base(), s);
@@ -424,8 +425,27 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
   }
   Workspace ws_gram;
   const Forest f_in = f;   // for a rerun on the Householder path
+  // The first product of each level (A times the masked Gaussian Omega_l)
+  // does not depend on earlier levels.  The built-in BF16 kernel sampler
+  // evaluates every entry of A once per call, whatever the column count, so
+  // the first products of G consecutive levels go into one call of G 2R
+  // columns (up to the sampler's width and a memory cap); the Gaussian
+  // blocks and the products are the same as with one call per level.
+  int G = 1;
+  {
+    bool bf16_kernel = true;
+    for (size_t i = 0; i < f.inst.size(); ++i) {
+      const OpRunner* o = ops.size() == f.inst.size() ? ops[i] : ops[0];
+      bf16_kernel &= o->op.kind == HM_OP_KERNEL && o->op.sample_dtype == HM_BF16;
+    }
+    if (bf16_kernel && Lmax > 1 && R > 0) {
+      G = std::max(1, std::min(Lmax, sampler_max_cols(2) / (2 * R)));
+      const size_t cap = (size_t)4 << 30;   // bytes of Omega plus Y
+      while (G > 1 && (size_t)N * 2 * R * G * 16 > cap) --G;
+    }
+  }
   // ---- buffers ---------------------------------------------------------------
-  const int W = std::max(2 * R, nmax);
+  const int W = std::max(2 * R * G, nmax);
   DevBuf Om((size_t)N * W * 8), Y((size_t)N * W * 8), M((size_t)N * 2 * R * 8);
   DevBuf Ucur((size_t)N * R * 8), Vcur((size_t)N * R * 8), Unx((size_t)N * R * 8),
       Vnx((size_t)N * R * 8);
@@ -465,21 +485,32 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
     for (size_t i = 0; i < f.inst.size(); ++i) active[i] = f.inst[i].L > l;
     const int32_t* dk = kp.put(lv.kids, s);
     const int nk = (int)lv.kids.size();
-    if (f.inst.size() > 1) launch_fill(om, N, 2 * R, N, 0.0, s);
-    launch_gauss_masked(dn, di, dk, nk, lv.max_kid_rows, l, R, om, N, s);
-    apply_ops(ops, f, false, 2 * R, om, N, y, N, active);
-    launch_nonfinite_check(y, N, 2 * R, N, flag.as<int>(), s);
+    if (l % G == 0) {
+      // first products of levels l .. l + g - 1, block q of 2R columns each
+      const int g = std::min(G, Lmax - l);
+      if (f.inst.size() > 1) launch_fill(om, N, 2 * R * g, N, 0.0, s);
+      for (int q = 0; q < g; ++q) {
+        const LevelLists& lq = LL[l + q];
+        launch_gauss_masked(dn, di, q == 0 ? dk : kp.put(lq.kids, s), (int)lq.kids.size(),
+                            lq.max_kid_rows, l + q, R, om + (int64_t)q * 2 * R * N, N, s);
+      }
+      apply_ops(ops, f, false, 2 * R * g, om, N, y, N, active);
+      launch_nonfinite_check(y, N, 2 * R * g, N, flag.as<int>(), s);
+    }
+    // this level's block; it is free again once its first product is used
+    double* om_l = om + (int64_t)(l % G) * 2 * R * N;
+    double* y_l = y + (int64_t)(l % G) * 2 * R * N;
     HbsView<double> hv;
     hv.Ulong = uc; hv.Vlong = vc; hv.ldl = N; hv.Ut = Ut.as<double>(); hv.Vt = Vt.as<double>();
     hv.B = B.as<double>(); hv.D = nullptr; hv.R = R;
     if (l >= 1) {
       ws_apply.ensure(apply_work_bytes<double>(f, lv.sub, R, 2 * R), s);
-      apply_forest<double>(dn, lv.sub, hv, false, 2 * R, om, N, y, N, -1.0, 1.0, ws_apply.base(),
-                           nn, s);
+      apply_forest<double>(dn, lv.sub, hv, false, 2 * R, om_l, N, y_l, N, -1.0, 1.0,
+                           ws_apply.base(), nn, s);
     }
     // incoming bases of the children
-    launch_build_node_block(dn, di, dk, nk, lv.max_kid_rows, R, y, N, uc, N, yv.as<double>(), m,
-                            N, s);
+    launch_build_node_block(dn, di, dk, nk, lv.max_kid_rows, R, y_l, N, uc, N, yv.as<double>(),
+                            m, N, s);
     std::vector<SvdJob> jobs;
     for (int g : lv.kids) {
       const Node& nd = f.nodes[g];
@@ -501,14 +532,14 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
                      2 * R * R, 2 * R, 1.0, 0.0, ws_seg.base(), s, 1);
     }
     // outgoing bases and sibling matrices
-    launch_mask_basis(dn, di, dk, nk, lv.max_kid_rows, R, un, N, om, N, s);
-    apply_ops(ops, f, true, 2 * R, om, N, y, N, active);
-    launch_nonfinite_check(y, N, 2 * R, N, flag.as<int>(), s);
+    launch_mask_basis(dn, di, dk, nk, lv.max_kid_rows, R, un, N, om_l, N, s);
+    apply_ops(ops, f, true, 2 * R, om_l, N, y_l, N, active);
+    launch_nonfinite_check(y_l, N, 2 * R, N, flag.as<int>(), s);
     if (l >= 1)
-      apply_forest<double>(dn, lv.sub, hv, true, 2 * R, om, N, y, N, -1.0, 1.0, ws_apply.base(),
-                           nn, s);
-    launch_build_node_block(dn, di, dk, nk, lv.max_kid_rows, R, y, N, vc, N, zv.as<double>(), m,
-                            N, s);
+      apply_forest<double>(dn, lv.sub, hv, true, 2 * R, om_l, N, y_l, N, -1.0, 1.0,
+                           ws_apply.base(), nn, s);
+    launch_build_node_block(dn, di, dk, nk, lv.max_kid_rows, R, y_l, N, vc, N, zv.as<double>(),
+                            m, N, s);
     launch_fill(vn, N, R, N, 0.0, s);
     // X diag(z) directly (only that product enters B)
     if (use_gram)

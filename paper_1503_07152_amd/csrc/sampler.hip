@@ -30,7 +30,6 @@ struct SmpShape {
   static constexpr int THREADS = 64 * WAVES;
   static constexpr int ROWS = WAVES * 16 * RT;    // rows per block
 };
-constexpr int SMP_CT = SMP_MAXC / 16; // column tiles
 
 template <int MODE> struct ModeT;
 template <> struct ModeT<0> { typedef double T; static constexpr int BK = 16; };
@@ -38,6 +37,7 @@ template <> struct ModeT<1> { typedef float T; static constexpr int BK = 16; };
 template <> struct ModeT<2> { typedef __bf16 T; static constexpr int BK = 64; };
 
 int sampler_bk(int mode) { return mode == 2 ? 64 : 16; }
+int sampler_max_cols(int mode) { return mode == 2 ? SMP_MAXC_BF16 : SMP_MAXC; }
 
 static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
@@ -120,30 +120,52 @@ __device__ __forceinline__ float entry_f32c(float xi, float yi, float xj, float 
 
 // K-tiles between flushes of the FP32 MFMA accumulators into FP64 (FP32 form)
 constexpr int SMP_FLUSH = 32;
+// Column tiles handled together: their B operands are read from LDS back to
+// back, then their MFMAs issued, so one LDS latency serves SMP_GS MFMAs.  The
+// nonzero mask is tested per group (a group with any nonzero tile multiplies
+// all of its tiles, the zero ones included; the structured test matrices
+// switch whole halves of 3 tiles on and off when r = 48).  Tiles past c hold
+// stale LDS data and feed accumulators that are never stored.
+constexpr int SMP_GS = 3;
+// (depends on col % 16 only, so the LDS offsets of all column tiles differ by
+// constants)
+__device__ __forceinline__ int swz(int col) { return (col ^ ((col >> 3) & 1)) & 7; }
 
 // SRC: 0 log kernel, 1 near-singular kernel, 2 dense matrix, 3 its transpose (F64 only).
 // One block = SmpShape<MODE>::WAVES waves x RT 16-row tiles; the whole X is streamed
 // through LDS in K-tiles, double-buffered, the next tile prefetched into registers
 // while the current one feeds the MFMAs.
+// CT column tiles of 16 are held in the accumulators (c <= 16 CT); the BF16
+// form takes up to 18, so one pass over the entries serves several sample
+// blocks at once.
 // The FP32 form is held to two waves per SIMD (244 VGPRs, no spills): left
 // to itself the compiler took 300 registers and one wave per SIMD, 1.6x slower.
-template <int MODE, int SRC>
-__global__ __launch_bounds__(SmpShape<MODE>::THREADS) __attribute__((amdgpu_waves_per_eu(MODE == 1 ? 2 : 1))) void k_sampler(int64_t n, int c, int cp, const double* pts,
-                                                 double kp, const double* Ad, int64_t lda,
-                                                 const typename ModeT<MODE>::T* Xp,
-                                                 const uint32_t* mask, double* Y, int64_t ldy) {
+template <int MODE, int SRC, int CT>
+__global__ __launch_bounds__(SmpShape<MODE>::THREADS)
+__attribute__((amdgpu_waves_per_eu(MODE == 1 ? 2 : (MODE == 2 && CT > 8 ? 4 : 1)))) void k_sampler(
+    int64_t n, int c, int cp, const double* __restrict__ pts, double kp,
+    const double* __restrict__ Ad, int64_t lda, const typename ModeT<MODE>::T* __restrict__ Xp,
+    const uint32_t* __restrict__ mask, double* __restrict__ Y, int64_t ldy) {
   typedef typename ModeT<MODE>::T T;
   constexpr int BK = ModeT<MODE>::BK;
   constexpr int SMP_THREADS = SmpShape<MODE>::THREADS;
   constexpr int SMP_ROWS = SmpShape<MODE>::ROWS;
   constexpr int SMP_RT = SmpShape<MODE>::RT;
-  constexpr int TILE_BYTES = BK * SMP_MAXC * (int)sizeof(T);
+  constexpr int SMP_CT = CT;
+  constexpr int TILE_BYTES = BK * 16 * CT * (int)sizeof(T);
   constexpr int NV = (TILE_BYTES + SMP_THREADS * 16 - 1) / (SMP_THREADS * 16);  // uint4 per thread
-  // BF16 tiles are column-major (BK contiguous k per column); a column stride
-  // of BK + 8 elements (144 bytes) spreads the 16 lanes of a B-operand read
-  // over distinct LDS banks (a stride of 128 bytes put them all on one).
-  constexpr int XLD = MODE == 2 ? BK + 8 : BK;
-  __shared__ __attribute__((aligned(16))) T sX[2][XLD * SMP_MAXC + 16];
+  // BF16 tiles are column-major (BK = 64 contiguous k per column, eight
+  // 16-byte chunks); chunk q of column col sits at slot q ^ swz(col).  A
+  // B-operand read takes chunk q of 16 consecutive columns: swz is one-to-one
+  // on any 8 consecutive columns (one 128-byte bank row each) and on the even
+  // and on the odd ones of 16 (two columns per 256-byte bank row), so the
+  // reads spread over all banks with 32 or with 64 banks of 4 bytes.
+  static_assert(MODE != 2 || BK == 64, "BF16 swizzle assumes 8 chunks per column");
+  // two separate arrays, not one of two buffers: the waits that the compiler
+  // puts before LDS reads for outstanding global_load_lds writes are skipped
+  // only when the write and the read provably address different objects
+  __shared__ __attribute__((aligned(16))) T sX0[BK * 16 * CT + 16];
+  __shared__ __attribute__((aligned(16))) T sX1[BK * 16 * CT + 16];
   // point coordinates of the K-tile: FP64 (FP64 / FP32 forms), FP32 (BF16 form)
   __shared__ double sP[2][MODE == 2 ? 1 : 2 * BK];
   __shared__ __attribute__((aligned(8))) float sPf[2][MODE == 2 ? 2 * BK : 1];
@@ -177,16 +199,34 @@ __global__ __launch_bounds__(SmpShape<MODE>::THREADS) __attribute__((amdgpu_wave
       for (int ct = 0; ct < SMP_CT; ++ct) acc64[rt][ct] = d4{0, 0, 0, 0};
   }
   const int64_t nkt = (n + BK - 1) / BK;
-  // prefetch registers for the next K-tile (plain statements, not a lambda
-  // capture, so the array stays in VGPRs)
-  uint4 pre[NV];
+  // F64 / F32: prefetch registers for the next K-tile (plain statements, not
+  // a lambda capture, so the array stays in VGPRs).  BF16: the next tile goes
+  // from global memory straight into its LDS buffer (global_load_lds, 16
+  // bytes per lane; lane l of a wave fills slot base + l, so it fetches the
+  // global chunk that the swizzle puts there), waited for before the barrier
+  // that publishes it; no registers held across the MFMAs.
+  uint4 pre[MODE == 2 ? 1 : NV];
   double pp = 0.0;
 #define HM_SMP_FETCH(KT)                                                              \
   {                                                                                   \
     const uint4* src_ = reinterpret_cast<const uint4*>(Xp + (KT) * (int64_t)BK * cp); \
-    _Pragma("unroll") for (int v = 0; v < NV; ++v) {                                  \
-      const int e = tid + v * SMP_THREADS;                                            \
-      pre[v] = e < tile_u4 ? src_[e] : uint4{0, 0, 0, 0};                             \
+    if constexpr (MODE == 2) {                                                        \
+      uint4* dst_ = reinterpret_cast<uint4*>(((KT) & 1) ? sX1 : sX0);                 \
+      _Pragma("unroll") for (int v = 0; v < NV; ++v) {                                \
+        const int base_ = (v * (SMP_THREADS / 64) + wave) * 64;                       \
+        if (base_ < tile_u4) {                                                        \
+          const int d_ = base_ + lane;                                                \
+          const int e_ = (d_ & ~7) | ((d_ ^ swz(d_ >> 3)) & 7);                       \
+          __builtin_amdgcn_global_load_lds(                                           \
+              (const void*)(src_ + e_),                                               \
+              (__attribute__((address_space(3))) void*)(dst_ + base_), 16, 0, 0);     \
+        }                                                                             \
+      }                                                                               \
+    } else {                                                                          \
+      _Pragma("unroll") for (int v = 0; v < NV; ++v) {                                \
+        const int e = tid + v * SMP_THREADS;                                          \
+        pre[v] = e < tile_u4 ? src_[e] : uint4{0, 0, 0, 0};                           \
+      }                                                                               \
     }                                                                                 \
     if (SRC < 2 && tid < 2 * BK) {                                                    \
       const int64_t j_ = (KT) * BK + tid / 2;                                         \
@@ -195,14 +235,13 @@ __global__ __launch_bounds__(SmpShape<MODE>::THREADS) __attribute__((amdgpu_wave
   }
 #define HM_SMP_STASH(BUF)                                                             \
   {                                                                                   \
-    uint4* dst_ = reinterpret_cast<uint4*>(sX[BUF]);                                  \
-    _Pragma("unroll") for (int v = 0; v < NV; ++v) {                                  \
-      const int e = tid + v * SMP_THREADS;                                            \
-      if (e < tile_u4) {                                                              \
-        if constexpr (MODE == 2)                                                      \
-          dst_[(e / (BK / 8)) * (XLD / 8) + e % (BK / 8)] = pre[v];                   \
-        else                                                                          \
-          dst_[e] = pre[v];                                                           \
+    if constexpr (MODE == 2) {                                                        \
+      __builtin_amdgcn_s_waitcnt(0x0F70); /* vmcnt(0): this wave's tile loads */     \
+    } else {                                                                          \
+      uint4* dst_ = reinterpret_cast<uint4*>((BUF) ? sX1 : sX0);                      \
+      _Pragma("unroll") for (int v = 0; v < NV; ++v) {                                \
+        const int e = tid + v * SMP_THREADS;                                          \
+        if (e < tile_u4) dst_[e] = pre[v];                                            \
       }                                                                               \
     }                                                                                 \
     if (SRC < 2 && tid < 2 * BK) {                                                    \
@@ -210,14 +249,23 @@ __global__ __launch_bounds__(SmpShape<MODE>::THREADS) __attribute__((amdgpu_wave
       else sP[BUF][tid] = pp;                                                         \
     }                                                                                 \
   }
+  // the nonzero mask of a K-tile is read with its tile, one iteration ahead:
+  // a load issued after the prefetch and waited for at once would also wait
+  // for the prefetch (loads complete in order)
+  uint32_t msk_nx = mask[0];
   HM_SMP_FETCH(0)
   HM_SMP_STASH(0)
   __syncthreads();
+  // unrolled by two so that the buffer of each copy is known statically
+#pragma unroll 2
   for (int64_t kt = 0; kt < nkt; ++kt) {
     const int buf = (int)(kt & 1);
-    if (kt + 1 < nkt) HM_SMP_FETCH(kt + 1)
-    const uint32_t msk = mask[kt];
-    const T* xs = sX[buf];
+    const uint32_t msk = msk_nx;
+    if (kt + 1 < nkt) {
+      msk_nx = mask[kt + 1];
+      HM_SMP_FETCH(kt + 1)
+    }
+    const T* xs = buf ? sX1 : sX0;
     const double* ps = sP[buf];
     if (msk != 0) {
       if constexpr (MODE == 0 || MODE == 1) {
@@ -243,16 +291,25 @@ __global__ __launch_bounds__(SmpShape<MODE>::THREADS) __attribute__((amdgpu_wave
             a[rt] = v;
           }
 #pragma unroll
-          for (int ct = 0; ct < SMP_CT; ++ct) {
-            if (ct >= ct_n || !((msk >> ct) & 1u)) continue;
-            const T b = xs[jl * cp + ct * 16 + (lane & 15)];
+          for (int g0 = 0; g0 < SMP_CT; g0 += SMP_GS) {
+            if (g0 >= ct_n || !((msk >> g0) & ((1u << SMP_GS) - 1))) continue;
+            T b[SMP_GS];
 #pragma unroll
-            for (int rt = 0; rt < SMP_RT; ++rt) {
-              if constexpr (MODE == 0)
-                acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt], b, acc[rt][ct], 0, 0, 0);
-              else
-                acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt], b, acc[rt][ct], 0, 0, 0);
-            }
+            for (int t = 0; t < SMP_GS; ++t)
+              if (g0 + t < SMP_CT) b[t] = xs[jl * cp + (g0 + t) * 16 + (lane & 15)];
+#pragma unroll
+            for (int t = 0; t < SMP_GS; ++t)
+#pragma unroll
+              for (int rt = 0; rt < SMP_RT; ++rt) {
+                const int ct = g0 + t;
+                if (ct >= SMP_CT) continue;
+                if constexpr (MODE == 0)
+                  acc[rt][ct] =
+                      __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt], b[t], acc[rt][ct], 0, 0, 0);
+                else
+                  acc[rt][ct] =
+                      __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt], b[t], acc[rt][ct], 0, 0, 0);
+              }
           }
         }
       } else {
@@ -281,13 +338,23 @@ __global__ __launch_bounds__(SmpShape<MODE>::THREADS) __attribute__((amdgpu_wave
             }
           }
 #pragma unroll
-          for (int ct = 0; ct < SMP_CT; ++ct) {
-            if (ct >= ct_n || !((msk >> ct) & 1u)) continue;
-            const bf8 b =
-                *reinterpret_cast<const bf8*>(&xs[(ct * 16 + (lane & 15)) * XLD + 32 * s + kb]);
+          for (int g0 = 0; g0 < SMP_CT; g0 += SMP_GS) {
+            if (g0 >= ct_n || !((msk >> g0) & ((1u << SMP_GS) - 1))) continue;
+            bf8 b[SMP_GS];
 #pragma unroll
-            for (int rt = 0; rt < SMP_RT; ++rt)
-              acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rt], b, acc[rt][ct], 0, 0, 0);
+            for (int t = 0; t < SMP_GS; ++t) {
+              const int col = (g0 + t) * 16 + (lane & 15);
+              const int q = 4 * s + (lane >> 4);
+              if (g0 + t < SMP_CT)
+                b[t] = *reinterpret_cast<const bf8*>(&xs[col * BK + 8 * (q ^ swz(col))]);
+            }
+#pragma unroll
+            for (int t = 0; t < SMP_GS; ++t)
+#pragma unroll
+              for (int rt = 0; rt < SMP_RT; ++rt)
+                if (g0 + t < SMP_CT)
+                  acc[rt][g0 + t] =
+                      __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rt], b[t], acc[rt][g0 + t], 0, 0, 0);
           }
         }
       }
@@ -347,9 +414,16 @@ static void run_sampler(int64_t n, int c, const double* pts, double kp, const do
                      mask);
   KCHK();
   constexpr int rows = SmpShape<MODE>::ROWS;
-  hipLaunchKernelGGL((k_sampler<MODE, SRC>), dim3((unsigned)((n + rows - 1) / rows)),
-                     dim3(SmpShape<MODE>::THREADS), 0, s, n, c, cp, pts, kp, Ad, lda, Xp, mask, Y,
-                     ldy);
+  const dim3 grid((unsigned)((n + rows - 1) / rows)), block(SmpShape<MODE>::THREADS);
+  if (MODE != 2 || c <= 128)
+    hipLaunchKernelGGL((k_sampler<MODE, SRC, 8>), grid, block, 0, s, n, c, cp, pts, kp, Ad, lda,
+                       Xp, mask, Y, ldy);
+  else if (c <= 192)
+    hipLaunchKernelGGL((k_sampler<MODE, SRC, MODE == 2 ? 12 : 8>), grid, block, 0, s, n, c, cp,
+                       pts, kp, Ad, lda, Xp, mask, Y, ldy);
+  else
+    hipLaunchKernelGGL((k_sampler<MODE, SRC, MODE == 2 ? 18 : 8>), grid, block, 0, s, n, c, cp,
+                       pts, kp, Ad, lda, Xp, mask, Y, ldy);
   KCHK();
 }
 
@@ -357,7 +431,8 @@ void sampler_apply(int mode, int src, int64_t n, int c, const double* pts, doubl
                    const double* Ad, int64_t lda, const double* X, int64_t ldx, double* Y,
                    int64_t ldy, void* work, hipStream_t s) {
   if (n <= 0 || c <= 0) return;
-  if (c > SMP_MAXC) HM_THROW(HM_ERR_UNSUPPORTED, "sampler: %d columns > %d", c, SMP_MAXC);
+  if (c > sampler_max_cols(mode))
+    HM_THROW(HM_ERR_UNSUPPORTED, "sampler: %d columns > %d", c, sampler_max_cols(mode));
   if (src >= 2 && mode != 0) HM_THROW(HM_ERR_ARG, "dense operator samples in FP64 only");
 #define CASE(M, S) \
   if (mode == M && src == S) return run_sampler<M, S>(n, c, pts, kp, Ad, lda, X, ldx, Y, ldy, work, s);

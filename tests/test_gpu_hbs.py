@@ -45,7 +45,8 @@ def test_gauss_stream_matches_oracle(seed, level, phase, row0, nrows, ncols):
 @pytest.mark.parametrize("kernel,mode,n,c,tol", [
     ("near", hm.HM_F64, 1000, 96, 1e-13), ("log", hm.HM_F64, 777, 17, 1e-13),
     ("near", hm.HM_F32, 1000, 96, 2e-6), ("near", hm.HM_BF16, 1000, 96, 8e-3),
-    ("near", hm.HM_F64, 300, 128, 1e-13)])
+    ("near", hm.HM_F64, 300, 128, 1e-13), ("near", hm.HM_BF16, 1000, 192, 8e-3),
+    ("log", hm.HM_BF16, 777, 288, 8e-3), ("near", hm.HM_BF16, 1500, 300, 8e-3)])
 def test_kernel_sampler_matches_dense_product(kernel, mode, n, c, tol):
     say(f"sampler kernel={kernel} mode={mode} n={n} c={c}")
     P = W.fourier_curve_points(n, seed=3)
@@ -56,6 +57,23 @@ def test_kernel_sampler_matches_dense_product(kernel, mode, n, c, tol):
     Y = hm.hm_operator_apply(op, torch.from_numpy(X)).cpu().numpy()
     ref = K.apply(X)
     assert rel(Y, ref) < tol
+
+
+def test_bf16_wide_sampler_equals_column_slices():
+    """The BF16 sampler holds up to 288 columns in one pass over the entries
+    of A; every column is accumulated in the same order as in a narrower call,
+    so the wide product equals the products of its 16-aligned slices exactly."""
+    n, c = 1111, 288
+    say(f"wide bf16 sampler n={n} c={c}")
+    P = W.fourier_curve_points(n, seed=5)
+    X = W.gaussian((n, c), seed=6)
+    X[: n // 2, 96:144] = 0.0
+    X[n // 3:, 200:240] = 0.0
+    op = hm.KernelOperator(P, "near", 1e-3, hm.HM_BF16)
+    Y = hm.hm_operator_apply(op, torch.from_numpy(X)).cpu().numpy()
+    for c0, c1 in ((0, 96), (96, 192), (192, 288), (48, 176)):
+        Ys = hm.hm_operator_apply(op, torch.from_numpy(np.ascontiguousarray(X[:, c0:c1])))
+        assert np.array_equal(Ys.cpu().numpy(), Y[:, c0:c1]), (c0, c1)
 
 
 def test_dense_operator_and_adjoint():
@@ -175,6 +193,12 @@ def test_mixed_precision_sampling_errors(mode, tol):
     r = _compare_compress(h, ho, n, K.apply)
     say(f"  {r}")
     assert r["vs_oracle"] < tol
+    # BF16 kernel sampling puts the first products of G levels in one call
+    L = ho.tree.L
+    G = min(L, 288 // (2 * (k + p))) if mode == hm.HM_BF16 else 1
+    inf = h.info()
+    assert inf["operator_calls"] == L + -(-L // G) + 1
+    assert inf["sample_columns"] == 4 * (k + p) * L + ho.tree.nmax()
 
 
 @pytest.mark.parametrize("n,leaf,k,p", [(1024, 64, 10, 10), (2000, 64, 12, 8)])
