@@ -159,8 +159,12 @@ int hm_operator_apply(const hm_operator* op, int64_t n, int32_t adjoint, int64_t
     run.op = *op;
     run.hbs = op->kind == HM_OP_HBS ? op->hbs : nullptr;
     run.s = (hipStream_t)stream;
-    for (int64_t c0 = 0; c0 < ncols; c0 += 128) {
-      const int c = (int)std::min<int64_t>(128, ncols - c0);
+    // built-in samplers take up to sampler_max_cols columns per pass over A
+    // (the runner splits wider blocks); other operators get 128 at a time
+    const int64_t chunk =
+        op->kind == HM_OP_KERNEL ? sampler_max_cols(op->sample_dtype == HM_BF16 ? 2 : 0) : 128;
+    for (int64_t c0 = 0; c0 < ncols; c0 += chunk) {
+      const int c = (int)std::min<int64_t>(chunk, ncols - c0);
       run.apply(adjoint != 0, n, c, X + c0 * ldx, ldx, Y + c0 * ldy, ldy);
     }
     HIPCHK(hipStreamSynchronize((hipStream_t)stream));

@@ -587,25 +587,37 @@ void launch_qrcp(const QrcpDesc* d, int n, hipStream_t s) {
 }
 
 // ------------------------------------------------------------ pivoted Cholesky --
-// Diagonal-pivoted Cholesky of a c x c PSD matrix in LDS (the Gram matrix of
-// a node block), stopped at the numerical rank; one step per column: every
-// wave finds the pivot (largest remaining diagonal, lowest index on ties),
-// the column of L is formed, then the trailing Schur complement is updated
-// by the whole workgroup.  Swaps are logical (a map in LDS).
+// Diagonal-pivoted Cholesky of a c x c PSD matrix (the Gram matrix of a node
+// block), stopped at the numerical rank; one step per column.  The matrix
+// stays in registers in its original (physical) order: thread (tx, ty) of the
+// 32 x 32 workgroup holds entries (tx + 32 a, ty + 32 b), a, b < 3.  Swaps are
+// logical (a map in LDS).  Per step every wave finds the pivot (largest
+// remaining diagonal, lowest logical index on ties), the threads holding the
+// pivot column publish it scaled by 1 / l_kk, zero on rows already pivoted,
+// and every thread applies the rank-one Schur update to its nine entries
+// (rows already pivoted see a zero factor and keep their values).
 __global__ __launch_bounds__(FT) void k_pchol(const PcholDesc* descs) {
-  __shared__ double sG[QP_LD * FAC_CMAX];
-  __shared__ double sdg[FAC_CMAX];
-  __shared__ double sl[FAC_CMAX];
-  __shared__ int scol[FAC_CMAX];
+  static_assert(FT == 1024 && FAC_CMAX <= 96, "32 x 32 threads, 3 x 3 entries each");
+  __shared__ double sStage[QP_LD * FAC_CMAX];   // final row permutation of L
+  __shared__ double sdg[FAC_CMAX];              // diagonal, physical order
+  __shared__ double sl[FAC_CMAX];               // scaled pivot column, physical order
+  __shared__ int scol[FAC_CMAX];                // logical -> physical
+  __shared__ int sact[FAC_CMAX];                // physical index not yet pivoted
   const PcholDesc d = descs[blockIdx.x];
   const int c = d.c;
   const int tid = threadIdx.x, lane = tid & 63;
-  for (int idx = tid; idx < c * c; idx += FT) {
-    const int i = idx % c, j = idx / c;
-    sG[i + j * QP_LD] = d.G[i + (int64_t)j * d.ldG];
-  }
+  const int tx = tid & 31, ty = tid >> 5;
+  double g[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const int pi = tx + 32 * a, pj = ty + 32 * b;
+      g[a][b] = (pi < c && pj < c) ? d.G[pi + (int64_t)pj * d.ldG] : 0.0;
+    }
   for (int j = tid; j < c; j += FT) {
     scol[j] = j;
+    sact[j] = 1;
     sdg[j] = d.G[j + (int64_t)j * d.ldG];
   }
   __syncthreads();
@@ -613,8 +625,8 @@ __global__ __launch_bounds__(FT) void k_pchol(const PcholDesc* descs) {
   int rho = c;
   for (int k = 0; k < c; ++k) {
     const int j1 = k + lane, j2 = k + lane + 64;
-    const double v1 = j1 < c ? sdg[j1] : -1.0;
-    const double v2 = j2 < c ? sdg[j2] : -1.0;
+    const double v1 = j1 < c ? sdg[scol[j1]] : -1.0;
+    const double v2 = j2 < c ? sdg[scol[j2]] : -1.0;
     const double vmax = max64(fmax(v1, v2));
     const uint64_t m1 = __ballot(v1 == vmax), m2 = __ballot(v2 == vmax);
     const int p = m1 ? k + __ffsll((unsigned long long)m1) - 1
@@ -635,42 +647,52 @@ __global__ __launch_bounds__(FT) void k_pchol(const PcholDesc* descs) {
     const int pk = scol[p], pp = scol[k];
     const double lkk = sqrt(vmax);
     const double inv = 1.0 / lkk;
-    // column k of L: l_i = G'(i, pivot) / l_kk for logical rows i > k
-    for (int i = k + 1 + tid; i < c; i += FT) {
-      const int pi = i == p ? pp : scol[i];
-      sl[i] = sG[pi + pk * QP_LD] * inv;
+    // the pivot column, scaled, on the rows still to be pivoted
+    if (ty == (pk & 31)) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int pi = tx + 32 * a;
+        double gv = 0.0;
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+          if (b == (pk >> 5)) gv = g[a][b];
+        if (pi < c) sl[pi] = (sact[pi] && pi != pk) ? gv * inv : 0.0;
+      }
     }
     __syncthreads();
     if (tid == 0) {
       scol[k] = pk;
       scol[p] = pp;
+      sact[pk] = 0;
     }
-    // column k of L by physical row (later swaps reorder rows, not entries)
-    for (int i = tid; i < c; i += FT) {
-      const int pi = i == k ? pk : (i == p ? pp : scol[i]);
-      d.L[pi + (int64_t)k * d.ldL] = i < k ? 0.0 : (i == k ? lkk : sl[i]);
+    // column k of L by physical row (the rows are put in pivot order at the end)
+    for (int i = tid; i < c; i += FT) d.L[i + (int64_t)k * d.ldL] = i == pk ? lkk : sl[i];
+    // Schur complement: g(i, j) -= l_i l_j (zero factor on pivoted rows)
+    double li[3], lj[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      li[a] = tx + 32 * a < c ? sl[tx + 32 * a] : 0.0;
+      lj[a] = ty + 32 * a < c ? sl[ty + 32 * a] : 0.0;
     }
-    // Schur complement on the trailing rows / columns
-    const int nt = c - k - 1;
-    for (int e = tid; e < nt * nt; e += FT) {
-      const int ii = k + 1 + e % nt, jj = k + 1 + e / nt;
-      const int pi = ii == p ? pp : scol[ii], pj = jj == p ? pp : scol[jj];
-      const double g = fma(-sl[ii], sl[jj], sG[pi + pj * QP_LD]);
-      sG[pi + pj * QP_LD] = g;
-      if (ii == jj) sdg[ii] = g;
-    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        g[a][b] = fma(-li[a], lj[b], g[a][b]);
+        if (tx + 32 * a == ty + 32 * b && tx + 32 * a < c) sdg[tx + 32 * a] = g[a][b];
+      }
     __syncthreads();
   }
   __syncthreads();
   // rows of L into the final pivoted order (through LDS)
   for (int e = tid; e < c * rho; e += FT) {
     const int i = e % c, k = e / c;
-    sG[i + k * QP_LD] = d.L[scol[i] + (int64_t)k * d.ldL];
+    sStage[i + k * QP_LD] = d.L[scol[i] + (int64_t)k * d.ldL];
   }
   __syncthreads();
   for (int e = tid; e < c * rho; e += FT) {
     const int i = e % c, k = e / c;
-    d.L[i + (int64_t)k * d.ldL] = sG[i + k * QP_LD];
+    d.L[i + (int64_t)k * d.ldL] = sStage[i + k * QP_LD];
   }
   for (int i = tid; i < c; i += FT) d.perm[i] = scol[i];
   if (tid == 0) *d.rho = rho;
@@ -687,50 +709,72 @@ void launch_pchol(const PcholDesc* d, int n, hipStream_t s) {
 // T = R^T when the descriptor asks for the transpose): T Z = W diag(s).  Pairs
 // follow a round-robin tournament; each 16-lane group rotates one pair, so a
 // 1024-thread workgroup treats every pair of a round (c <= 96) at once.  The
-// pair's two squared norms and inner product are reduced across the group by
-// DPP row operations (no LDS round trip), which leaves the same sum in every
-// lane.  Each lane holds RPL = ceil(h / 16) rows of the pair in registers.
+// squared column norms are kept in LDS: computed at the start of each sweep
+// and, after a rotation by t = tan(theta), updated as |x|^2 - t g and
+// |y|^2 + t g (g = x.y; exact for the t that zeroes the pair's inner
+// product), so a pair needs only its inner product, reduced across the group
+// by DPP row operations (no LDS round trip).  Each lane holds RPL = ceil(h /
+// 16) rows of the pair in registers.
 constexpr int JAC_LD = FAC_CMAX + 1;
-constexpr int JAC_GROUPS = FT / 16;
-constexpr int JAC_RPL = FAC_CMAX / 16;  // most rows per lane of a 16-lane group
+constexpr int JAC_G = 16;                      // lanes per pair
+constexpr int JAC_FT = FT;
+constexpr int JAC_GROUPS = JAC_FT / JAC_G;
+constexpr int JAC_RPL = FAC_CMAX / JAC_G;      // most rows per lane
+static_assert(JAC_GROUPS >= FAC_CMAX / 2, "one group per pair of a round");
 
 template <int RPL>
-__device__ __forceinline__ int jacobi_sweeps(double* sA, double* sZ, int h, int c, bool wantX,
-                                             int* flag) {
+__device__ __forceinline__ int jacobi_sweeps(double* sA, double* sZ, double* sN, int h, int c,
+                                             bool wantX, int* flag) {
   const int tid = threadIdx.x;
-  const int grp = tid >> 4, gl = tid & 15;
+  const int grp = tid / JAC_G, gl = tid % JAC_G;
   const int n2 = c + (c & 1);
   const int hm1 = max(h - 1, 0);
   const double tol = (double)max(h, 1) * DBL_EPSILON;
   int sweep = 0;
   for (; sweep < 40; ++sweep) {
     if (tid == 0) *flag = 0;
+    // squared column norms, fresh each sweep (the updates drift by rounding)
+    for (int j = grp; j < c; j += JAC_GROUPS) {
+      double nn = 0.0;
+#pragma unroll
+      for (int u = 0; u < RPL; ++u) {
+        const int i = gl + JAC_G * u;
+        const double v = i < h ? sA[min(i, hm1) + j * JAC_LD] : 0.0;
+        nn = fma(v, v, nn);
+      }
+      nn = sum16(nn);
+      if (gl == 0) sN[j] = nn;
+    }
     __syncthreads();
     for (int t = 0; t < n2 - 1; ++t) {
       for (int pi = grp; pi < n2 / 2; pi += JAC_GROUPS) {
         const int a = pi, b = n2 - 1 - pi;
-        const int pa = a == 0 ? 0 : 1 + (a - 1 + t) % (n2 - 1);
-        const int pb = b == 0 ? 0 : 1 + (b - 1 + t) % (n2 - 1);
+        // tournament positions 1 + (a - 1 + t) mod (n2 - 1), a - 1 + t < 2 (n2 - 1)
+        int xa = a - 1 + t, xb = b - 1 + t;
+        if (xa >= n2 - 1) xa -= n2 - 1;
+        if (xb >= n2 - 1) xb -= n2 - 1;
+        const int pa = a == 0 ? 0 : 1 + xa;
+        const int pb = b == 0 ? 0 : 1 + xb;
         const int p = min(pa, pb), q = max(pa, pb);
         if (q >= c) continue;
         // the group's rows gl + 16 u (fixed trip count; rows past h weigh zero)
         double xv[RPL], yv[RPL];
-        double al = 0.0, be = 0.0, ga = 0.0;
+        double ga = 0.0;
 #pragma unroll
         for (int u = 0; u < RPL; ++u) {
-          const int i = gl + 16 * u;
+          const int i = gl + JAC_G * u;
           const int ic = min(i, hm1);
           const double w = i < h ? 1.0 : 0.0;
           xv[u] = w * sA[ic + p * JAC_LD];
           yv[u] = w * sA[ic + q * JAC_LD];
-          al = fma(xv[u], xv[u], al);
-          be = fma(yv[u], yv[u], be);
           ga = fma(xv[u], yv[u], ga);
         }
-        al = sum16(al);
-        be = sum16(be);
         ga = sum16(ga);
-        if (ga != 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
+        const double al = sN[p], be = sN[q];
+        // |ga| > tol |x| |y|, from the hardware reciprocal square roots (a
+        // threshold needs no correct rounding)
+        if (ga != 0.0 && al > 0.0 && be > 0.0 &&
+            fabs(ga) * __builtin_amdgcn_rsq(al) * __builtin_amdgcn_rsq(be) > tol) {
           // rotation zeroing the pair's inner product: t = tan(theta) is the
           // smaller root of t^2 ga + t (be - al) - ga = 0
           const double dd = be - al;
@@ -762,18 +806,18 @@ __device__ __forceinline__ int jacobi_sweeps(double* sA, double* sZ, int h, int 
           const double sn = cs * tt;
 #pragma unroll
           for (int u = 0; u < RPL; ++u) {
-            const int i = gl + 16 * u;
+            const int i = gl + JAC_G * u;
             if (i < h) {
               sA[i + p * JAC_LD] = cs * xv[u] - sn * yv[u];
               sA[i + q * JAC_LD] = sn * xv[u] + cs * yv[u];
             }
           }
           if (wantX) {
-            // rows of Z: c <= 16 JAC_RPL
+            // rows of Z: c <= JAC_G JAC_RPL
 #pragma unroll
             for (int u = 0; u < JAC_RPL; ++u) {
-              const int i = gl + 16 * u;
-              if (16 * u < c) {
+              const int i = gl + JAC_G * u;
+              if (JAC_G * u < c) {
                 const int ic = min(i, c - 1);
                 const double x = sZ[ic + p * JAC_LD], y = sZ[ic + q * JAC_LD];
                 if (i < c) {
@@ -783,7 +827,11 @@ __device__ __forceinline__ int jacobi_sweeps(double* sA, double* sZ, int h, int 
               }
             }
           }
-          if (gl == 0) *flag = 1;
+          if (gl == 0) {
+            sN[p] = fma(-tt, ga, al);
+            sN[q] = fma(tt, ga, be);
+            *flag = 1;
+          }
         }
       }
       __syncthreads();
@@ -797,10 +845,11 @@ __device__ __forceinline__ int jacobi_sweeps(double* sA, double* sZ, int h, int 
 // NEED_Z: the descriptors may accumulate rotations or form T^T W (a second
 // LDS matrix); without it (the Gram route) a workgroup takes half the LDS.
 template <bool NEED_Z>
-__global__ __launch_bounds__(FT) void k_jacobi(const SvdDesc* descs) {
+__global__ __launch_bounds__(JAC_FT) void k_jacobi(const SvdDesc* descs) {
   __shared__ double sA[FAC_CMAX * JAC_LD];
   __shared__ double sZ[NEED_Z ? FAC_CMAX * JAC_LD : 1];
   __shared__ double snorm[FAC_CMAX];
+  __shared__ double sN[FAC_CMAX];
   __shared__ int srank[FAC_CMAX];
   __shared__ int flag;
   const SvdDesc d = descs[blockIdx.x];
@@ -813,41 +862,41 @@ __global__ __launch_bounds__(FT) void k_jacobi(const SvdDesc* descs) {
   const bool wantX = d.X != nullptr;
   const bool accZ = NEED_Z && wantX && !d.xscaled && !d.gram;   // accumulate the rotations
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < h * c; idx += FT) {
+  for (int idx = tid; idx < h * c; idx += JAC_FT) {
     const int i = idx % h, j = idx / h;
     sA[i + j * JAC_LD] = d.trans ? d.R[j + (int64_t)i * d.ldR] : d.R[i + (int64_t)j * d.ldR];
   }
   if (accZ)
-    for (int idx = tid; idx < c * c; idx += FT) {
+    for (int idx = tid; idx < c * c; idx += JAC_FT) {
       const int i = idx % c, j = idx / c;
       sZ[i + j * JAC_LD] = (i == j) ? 1.0 : 0.0;
     }
   __syncthreads();
   int sweeps = 0;
-  switch ((h + 15) / 16) {
-    case 1: sweeps = jacobi_sweeps<1>(sA, sZ, h, c, accZ, &flag); break;
-    case 2: sweeps = jacobi_sweeps<2>(sA, sZ, h, c, accZ, &flag); break;
-    case 3: sweeps = jacobi_sweeps<3>(sA, sZ, h, c, accZ, &flag); break;
-    case 4: sweeps = jacobi_sweeps<4>(sA, sZ, h, c, accZ, &flag); break;
-    case 5: sweeps = jacobi_sweeps<5>(sA, sZ, h, c, accZ, &flag); break;
-    case 6: sweeps = jacobi_sweeps<6>(sA, sZ, h, c, accZ, &flag); break;
+  switch ((h + JAC_G - 1) / JAC_G) {
+    case 1: sweeps = jacobi_sweeps<1>(sA, sZ, sN, h, c, accZ, &flag); break;
+    case 2: sweeps = jacobi_sweeps<2>(sA, sZ, sN, h, c, accZ, &flag); break;
+    case 3: sweeps = jacobi_sweeps<3>(sA, sZ, sN, h, c, accZ, &flag); break;
+    case 4: sweeps = jacobi_sweeps<4>(sA, sZ, sN, h, c, accZ, &flag); break;
+    case 5: sweeps = jacobi_sweeps<5>(sA, sZ, sN, h, c, accZ, &flag); break;
+    case 6: sweeps = jacobi_sweeps<6>(sA, sZ, sN, h, c, accZ, &flag); break;
     default: break;   // h = 0: nothing to rotate
   }
   if (tid == 0 && d.sweeps) atomicMax(d.sweeps, sweeps);
-  for (int j = tid; j < c; j += FT) {
+  for (int j = tid; j < c; j += JAC_FT) {
     double s = 0.0;
     for (int i = 0; i < h; ++i) s += sA[i + j * JAC_LD] * sA[i + j * JAC_LD];
     snorm[j] = sqrt(s);
   }
   __syncthreads();
-  for (int j = tid; j < c; j += FT) {
+  for (int j = tid; j < c; j += JAC_FT) {
     const double sj = snorm[j];
     int rk = 0;
     for (int i2 = 0; i2 < c; ++i2) rk += (snorm[i2] > sj) || (snorm[i2] == sj && i2 < j);
     srank[j] = rk;
   }
   if (NEED_Z && wantX && !accZ && !d.gram)   // T (h x c) for X diag(s) = T^T W
-    for (int idx = tid; idx < h * c; idx += FT) {
+    for (int idx = tid; idx < h * c; idx += JAC_FT) {
       const int i = idx % h, j = idx / h;
       sZ[i + j * JAC_LD] = d.R[i + (int64_t)j * d.ldR];
     }
@@ -857,7 +906,7 @@ __global__ __launch_bounds__(FT) void k_jacobi(const SvdDesc* descs) {
   // vectors e_j and singular value 0
   if (d.gram) {
     // x_j = P u_j: W(perm[i], rk) = a_j(i) / s_j^2, X(perm[i], rk) = a_j(i)
-    for (int e = tid; e < c * h; e += FT) {
+    for (int e = tid; e < c * h; e += JAC_FT) {
       const int i = e % h, j = e / h;
       const int rk = srank[j];
       if (rk >= d.kout) continue;
@@ -868,19 +917,19 @@ __global__ __launch_bounds__(FT) void k_jacobi(const SvdDesc* descs) {
       d.W[pi + (int64_t)rk * d.ldW] = sj > 0.0 ? a / (sj * sj) : 0.0;
       if (wantX) d.X[pi + (int64_t)rk * d.ldX] = a;
     }
-    for (int e = tid; e < (d.kout - c) * h; e += FT) {
+    for (int e = tid; e < (d.kout - c) * h; e += JAC_FT) {
       const int i = e % h, rk = c + e / h;
       if (i == 0) d.sv[rk] = 0.0;
       d.W[i + (int64_t)rk * d.ldW] = 0.0;
       if (wantX) d.X[i + (int64_t)rk * d.ldX] = 0.0;
     }
     // W columns kout .. wrows - 1 (a wider product shared with other nodes) are zero
-    for (int e = tid; e < (d.wrows - d.kout) * h; e += FT)
+    for (int e = tid; e < (d.wrows - d.kout) * h; e += JAC_FT)
       d.W[e % h + (int64_t)(d.kout + e / h) * d.ldW] = 0.0;
     return;
   }
   const int rows = max(d.wrows, wantX ? d.xrows : 0);
-  for (int e = tid; e < c * rows; e += FT) {
+  for (int e = tid; e < c * rows; e += JAC_FT) {
     const int i = e % rows, j = e / rows;
     const int rk = srank[j];
     if (rk >= d.kout) continue;
@@ -902,7 +951,7 @@ __global__ __launch_bounds__(FT) void k_jacobi(const SvdDesc* descs) {
       d.X[i + (int64_t)rk * d.ldX] = xv;
     }
   }
-  for (int e = tid; e < (d.kout - c) * rows; e += FT) {
+  for (int e = tid; e < (d.kout - c) * rows; e += JAC_FT) {
     const int i = e % rows, rk = c + e / rows;
     if (i == 0) d.sv[rk] = 0.0;
     if (i < d.wrows) d.W[i + (int64_t)rk * d.ldW] = i == rk ? 1.0 : 0.0;
@@ -913,9 +962,9 @@ __global__ __launch_bounds__(FT) void k_jacobi(const SvdDesc* descs) {
 void launch_jacobi_svd(const SvdDesc* d, int n, hipStream_t s, bool gram_only) {
   if (n <= 0) return;
   if (gram_only)
-    hipLaunchKernelGGL(k_jacobi<false>, dim3(n), dim3(FT), 0, s, d);
+    hipLaunchKernelGGL(k_jacobi<false>, dim3(n), dim3(JAC_FT), 0, s, d);
   else
-    hipLaunchKernelGGL(k_jacobi<true>, dim3(n), dim3(FT), 0, s, d);
+    hipLaunchKernelGGL(k_jacobi<true>, dim3(n), dim3(JAC_FT), 0, s, d);
   KCHK();
 }
 
