@@ -41,12 +41,21 @@ int sampler_max_cols(int mode) { return mode == 2 ? SMP_MAXC_BF16 : SMP_MAXC; }
 
 static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
+// K-splits of the narrow BF16 form (see run_sampler)
+constexpr int SMP_KSPLIT = 3;
+static int sampler_ksplit(int mode, int64_t n, int c) {
+  const int64_t nkt = (n + sampler_bk(mode) - 1) / sampler_bk(mode);
+  return (mode == 2 && c <= 128) ? (int)std::min<int64_t>(SMP_KSPLIT, nkt) : 1;
+}
+
 size_t sampler_pack_bytes(int mode, int64_t n, int c) {
   const int bk = sampler_bk(mode);
   const int64_t kt = (n + bk - 1) / bk;
   const int cp = ((c + 15) / 16) * 16;
   const size_t es = mode == 0 ? 8 : (mode == 1 ? 4 : 2);
-  return align256((size_t)kt * bk * cp * es) + align256((size_t)kt * 4) + 512;
+  const int ks = sampler_ksplit(mode, n, c);
+  return align256((size_t)kt * bk * cp * es) + align256((size_t)kt * 4) +
+         (ks > 1 ? align256((size_t)ks * n * c * 8) : 0) + 512;
 }
 
 // Pack: F64/F32 tiles [kt][k][col]; BF16 tiles [kt][col][k].
@@ -145,7 +154,8 @@ __global__ __launch_bounds__(SmpShape<MODE>::THREADS)
 __attribute__((amdgpu_waves_per_eu(MODE == 1 ? 2 : (MODE == 2 && CT > 8 ? 4 : 1)))) void k_sampler(
     int64_t n, int c, int cp, const double* __restrict__ pts, double kp,
     const double* __restrict__ Ad, int64_t lda, const typename ModeT<MODE>::T* __restrict__ Xp,
-    const uint32_t* __restrict__ mask, double* __restrict__ Y, int64_t ldy) {
+    const uint32_t* __restrict__ mask, double* __restrict__ Y, int64_t ldy, int64_t kt_chunk,
+    double* __restrict__ Ypart) {
   typedef typename ModeT<MODE>::T T;
   constexpr int BK = ModeT<MODE>::BK;
   constexpr int SMP_THREADS = SmpShape<MODE>::THREADS;
@@ -207,11 +217,11 @@ __attribute__((amdgpu_waves_per_eu(MODE == 1 ? 2 : (MODE == 2 && CT > 8 ? 4 : 1)
   // that publishes it; no registers held across the MFMAs.
   uint4 pre[MODE == 2 ? 1 : NV];
   double pp = 0.0;
-#define HM_SMP_FETCH(KT)                                                              \
+#define HM_SMP_FETCH(KT, BUF)                                                         \
   {                                                                                   \
     const uint4* src_ = reinterpret_cast<const uint4*>(Xp + (KT) * (int64_t)BK * cp); \
     if constexpr (MODE == 2) {                                                        \
-      uint4* dst_ = reinterpret_cast<uint4*>(((KT) & 1) ? sX1 : sX0);                 \
+      uint4* dst_ = reinterpret_cast<uint4*>((BUF) ? sX1 : sX0);                      \
       _Pragma("unroll") for (int v = 0; v < NV; ++v) {                                \
         const int base_ = (v * (SMP_THREADS / 64) + wave) * 64;                       \
         if (base_ < tile_u4) {                                                        \
@@ -252,18 +262,26 @@ __attribute__((amdgpu_waves_per_eu(MODE == 1 ? 2 : (MODE == 2 && CT > 8 ? 4 : 1)
   // the nonzero mask of a K-tile is read with its tile, one iteration ahead:
   // a load issued after the prefetch and waited for at once would also wait
   // for the prefetch (loads complete in order)
-  uint32_t msk_nx = mask[0];
-  HM_SMP_FETCH(0)
-  HM_SMP_STASH(0)
+  // K-tiles kt_beg .. kt_end - 1 of this split (blockIdx.y); kk counts them
+  const int64_t kt_beg = (int64_t)blockIdx.y * kt_chunk;
+  const int64_t kt_end = min(nkt, kt_beg + kt_chunk);
+  const int64_t nkk = max(kt_end - kt_beg, (int64_t)0);
+  uint32_t msk_nx = 0;
+  if (nkk > 0) {
+    msk_nx = mask[kt_beg];
+    HM_SMP_FETCH(kt_beg, 0)
+    HM_SMP_STASH(0)
+  }
   __syncthreads();
   // unrolled by two so that the buffer of each copy is known statically
 #pragma unroll 2
-  for (int64_t kt = 0; kt < nkt; ++kt) {
-    const int buf = (int)(kt & 1);
+  for (int64_t kk = 0; kk < nkk; ++kk) {
+    const int64_t kt = kt_beg + kk;
+    const int buf = (int)(kk & 1);
     const uint32_t msk = msk_nx;
-    if (kt + 1 < nkt) {
+    if (kk + 1 < nkk) {
       msk_nx = mask[kt + 1];
-      HM_SMP_FETCH(kt + 1)
+      HM_SMP_FETCH(kt + 1, buf ^ 1)
     }
     const T* xs = buf ? sX1 : sX0;
     const double* ps = sP[buf];
@@ -360,7 +378,7 @@ __attribute__((amdgpu_waves_per_eu(MODE == 1 ? 2 : (MODE == 2 && CT > 8 ? 4 : 1)
       }
     }
     if constexpr (MODE == 1) {
-      if ((kt % SMP_FLUSH) == SMP_FLUSH - 1 || kt + 1 == nkt) {
+      if ((kk % SMP_FLUSH) == SMP_FLUSH - 1 || kk + 1 == nkk) {
 #pragma unroll
         for (int rt = 0; rt < SMP_RT; ++rt)
 #pragma unroll
@@ -371,9 +389,13 @@ __attribute__((amdgpu_waves_per_eu(MODE == 1 ? 2 : (MODE == 2 && CT > 8 ? 4 : 1)
           }
       }
     }
-    if (kt + 1 < nkt) HM_SMP_STASH(buf ^ 1)
+    if (kk + 1 < nkk) HM_SMP_STASH(buf ^ 1)
     __syncthreads();
   }
+  // one split writes Y; several write their partial sums, added in split
+  // order by k_sum_parts
+  double* Yo = gridDim.y > 1 ? Ypart + (int64_t)blockIdx.y * n * c : Y;
+  const int64_t ldo = gridDim.y > 1 ? n : ldy;
   // Accumulator layout (column lane % 16 of each 16 x 16 tile): item v of lane
   // l holds row 4*(l/16) + v for the FP32-accumulating instructions and row
   // l/16 + 4*v for v_mfma_f64_16x16x4f64 (checked on gfx950 with identity inputs).
@@ -391,9 +413,20 @@ __attribute__((amdgpu_waves_per_eu(MODE == 1 ? 2 : (MODE == 2 && CT > 8 ? 4 : 1)
         double val;
         if constexpr (MODE == 1) val = acc64[rt][ct][v];
         else val = (double)acc[rt][ct][v];
-        Y[row + (int64_t)col * ldy] = val;
+        Yo[row + (int64_t)col * ldo] = val;
       }
     }
+}
+
+// Y = sum of the ks partial products (n x c each, ld n), in split order
+__global__ void k_sum_parts(int64_t n, int c, int ks, const double* __restrict__ Yp,
+                            double* __restrict__ Y, int64_t ldy) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * c) return;
+  const int64_t i = e % n, j = e / n;
+  double v = Yp[e];
+  for (int q = 1; q < ks; ++q) v += Yp[(int64_t)q * n * c + e];
+  Y[i + j * ldy] = v;
 }
 
 #undef HM_SMP_FETCH
@@ -413,18 +446,34 @@ static void run_sampler(int64_t n, int c, const double* pts, double kp, const do
   hipLaunchKernelGGL(k_pack<MODE>, dim3((unsigned)nkt), dim3(256), 0, s, n, c, cp, X, ldx, Xp,
                      mask);
   KCHK();
+  // The narrow BF16 form (74 VGPRs: six waves per SIMD) splits the K-tiles in
+  // SMP_KSPLIT parts, one block row each: 65536 rows give 512 blocks of 8
+  // waves, four per SIMD, which the split raises to the six the registers
+  // allow.  The wider forms are held to four waves per SIMD by their
+  // registers, which 512 blocks already fill.
+  const int ks = sampler_ksplit(MODE, n, c);
+  const int64_t kt_chunk = (nkt + ks - 1) / ks;
+  double* Yp = ks > 1 ? reinterpret_cast<double*>(static_cast<char*>(work) + xbytes +
+                                                  align256((size_t)nkt * 4))
+                      : nullptr;
   constexpr int rows = SmpShape<MODE>::ROWS;
-  const dim3 grid((unsigned)((n + rows - 1) / rows)), block(SmpShape<MODE>::THREADS);
+  const dim3 grid((unsigned)((n + rows - 1) / rows), (unsigned)ks), block(SmpShape<MODE>::THREADS);
   if (MODE != 2 || c <= 128)
     hipLaunchKernelGGL((k_sampler<MODE, SRC, 8>), grid, block, 0, s, n, c, cp, pts, kp, Ad, lda,
-                       Xp, mask, Y, ldy);
+                       Xp, mask, Y, ldy, kt_chunk, Yp);
   else if (c <= 192)
     hipLaunchKernelGGL((k_sampler<MODE, SRC, MODE == 2 ? 12 : 8>), grid, block, 0, s, n, c, cp,
-                       pts, kp, Ad, lda, Xp, mask, Y, ldy);
+                       pts, kp, Ad, lda, Xp, mask, Y, ldy, kt_chunk, Yp);
   else
     hipLaunchKernelGGL((k_sampler<MODE, SRC, MODE == 2 ? 18 : 8>), grid, block, 0, s, n, c, cp,
-                       pts, kp, Ad, lda, Xp, mask, Y, ldy);
+                       pts, kp, Ad, lda, Xp, mask, Y, ldy, kt_chunk, Yp);
   KCHK();
+  if (ks > 1) {
+    const int64_t tot = n * c;
+    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, c, ks,
+                       Yp, Y, ldy);
+    KCHK();
+  }
 }
 
 void sampler_apply(int mode, int src, int64_t n, int c, const double* pts, double kp,

@@ -61,8 +61,11 @@ def test_kernel_sampler_matches_dense_product(kernel, mode, n, c, tol):
 
 def test_bf16_wide_sampler_equals_column_slices():
     """The BF16 sampler holds up to 288 columns in one pass over the entries
-    of A; every column is accumulated in the same order as in a narrower call,
-    so the wide product equals the products of its 16-aligned slices exactly."""
+    of A.  A wide call (one FP32 accumulator per element over all of K) and
+    narrow calls on its slices (the K-tiles split in three, FP32 parts summed
+    in FP64) add the same exact BF16 x BF16 products in different orders, so
+    they agree to FP32 accumulation error: sqrt(n) u32 relative for random
+    signs, bounded here at 2e-5 (n = 1111)."""
     n, c = 1111, 288
     say(f"wide bf16 sampler n={n} c={c}")
     P = W.fourier_curve_points(n, seed=5)
@@ -73,7 +76,7 @@ def test_bf16_wide_sampler_equals_column_slices():
     Y = hm.hm_operator_apply(op, torch.from_numpy(X)).cpu().numpy()
     for c0, c1 in ((0, 96), (96, 192), (192, 288), (48, 176)):
         Ys = hm.hm_operator_apply(op, torch.from_numpy(np.ascontiguousarray(X[:, c0:c1])))
-        assert np.array_equal(Ys.cpu().numpy(), Y[:, c0:c1]), (c0, c1)
+        assert rel(Ys.cpu().numpy(), Y[:, c0:c1]) < 2e-5, (c0, c1)
 
 
 def test_dense_operator_and_adjoint():
