@@ -48,14 +48,16 @@ PEAK_ALU_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
 # packed BF16 conversion = 13.5 slots
 SLOTS_PER_ENTRY = 13.5
 
-# HBM bytes of one BF16 operator apply (k_pack + k_sampler, N = 65536, 96
-# columns) from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE in KiB per
-# dispatch, summed over the two kernels), scaled by what the same counters
-# read for a plain 256 MiB device copy (FETCH_SIZE reads 0.5x the bytes moved,
-# WRITE_SIZE 1.0x).  Valid only for the sampler source they were taken on
-# (SHA-1 below); otherwise the traffic is unknown.
-SAMPLER_TRAFFIC = {"sha1": "8cddf69436dd77ac4a9e4e66cff0d99cb89ef475",
-                   "fetch_kib": 82408.7 + 24590.5, "write_kib": 52577.7 + 12320.0,
+# HBM bytes of one BF16 operator apply (k_pack + k_sampler + k_sum_parts,
+# N = 65536, 96 columns) from two rocprofv3 --pmc passes (FETCH_SIZE,
+# WRITE_SIZE in KiB per dispatch, summed over the three kernels), scaled by
+# what the same counters read for a plain 256 MiB device copy (FETCH_SIZE
+# reads 0.5x the bytes moved, WRITE_SIZE 1.0x).  Most of it is the three
+# K-split partial products (written, read back, summed).  Valid only for the
+# sampler source they were taken on (SHA-1 below); otherwise unknown.
+SAMPLER_TRAFFIC = {"sha1": "ab58e166a4f2bd8638c58eeb8240f53337afe2f9",
+                   "fetch_kib": 24590.9 + 96448.4 + 73746.6,
+                   "write_kib": 12320.0 + 148646.0 + 49152.0,
                    "fetch_scale": 2.0, "write_scale": 1.0}
 
 
@@ -248,7 +250,7 @@ def extra_measurements(hm, W, torch, pts, n, h_bf16, ms_bf16):
     res["roofline"] = {"bound": "alu", "achieved": round(achieved, 2), "peak": round(PEAK_ALU_TOPS, 1),
                        "unit": "Tslot/s", "frac": round(achieved / PEAK_ALU_TOPS, 3),
                        "traffic": sampler_traffic_bytes() if n == N else None,
-                       "kernel": "k_sampler<BF16, near> (+ k_pack)",
+                       "kernel": "k_sampler<BF16, near> (+ k_pack, k_sum_parts)",
                        "launch_ms": round(t_launch * 1e3, 3),
                        "mfma_frac": round(2 * n * (n * c / 2) / t_launch / 1e12 /
                                           PEAK_TF["bf16"], 4)}

@@ -176,7 +176,8 @@ int hm_gauss(uint64_t seed, int32_t level, int32_t phase, int64_t row0,
 /* ---- operators ----------------------------------------------------------------
  * Y = A X (adjoint = 0) or A^* X through the operator `op` (any kind), exactly
  * as the compression samples it: X, Y device FP64 n x ncols column-major.  For
- * HM_OP_KERNEL the product runs in op->sample_dtype and is returned in FP64. */
+ * HM_OP_KERNEL the product runs in op->sample_dtype and is returned in FP64.
+ * Enqueued on `stream`; returns without waiting for it. */
 int hm_operator_apply(const hm_operator* op, int64_t n, int32_t adjoint, int64_t ncols,
                       const double* X, int64_t ldx, double* Y, int64_t ldy, void* stream);
 

@@ -430,9 +430,15 @@ def hm_gauss(seed, level, phase, row0, nrows, ncols, out=None, stream=None):
 
 
 def hm_operator_apply(op, x, adjoint=False, stream=None):
-    """Y = A X (or A^* X) through a built-in or callback operator."""
+    """Y = A X (or A^* X) through a built-in or callback operator, enqueued on
+    `stream` (torch's current stream by default) without waiting for it."""
     xf = to_fortran(x, torch.float64)
     y = fortran(xf.shape[0], xf.shape[1])
+    if stream is not None:
+        # the temporaries belong to the current stream; keep them until the
+        # work on `stream` is done
+        xf.record_stream(stream)
+        y.record_stream(stream)
     _check(lib.hm_operator_apply(C.byref(op.c), xf.shape[0], 1 if adjoint else 0, xf.shape[1],
                                  _ptr(xf), _ld(xf), _ptr(y), _ld(y), _stream(stream)))
     return y

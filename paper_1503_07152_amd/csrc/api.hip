@@ -167,7 +167,6 @@ int hm_operator_apply(const hm_operator* op, int64_t n, int32_t adjoint, int64_t
       const int c = (int)std::min<int64_t>(chunk, ncols - c0);
       run.apply(adjoint != 0, n, c, X + c0 * ldx, ldx, Y + c0 * ldy, ldy);
     }
-    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
     return HM_OK;
   });
 }
