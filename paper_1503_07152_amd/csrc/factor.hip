@@ -1019,7 +1019,15 @@ void launch_form_b(const Node* nodes, const Instance* inst, const int32_t* kids,
 
 // ------------------------------------------------------------ CPQR / ID ---
 constexpr int ID_NMAX = 256;  // candidates per node (leaf rows or 2R)
-__global__ __launch_bounds__(256) void k_cpqr_id(const Node* nodes, const Instance* inst,
+constexpr int ID_T = 1024;    // threads: four lanes per candidate column
+static_assert(HM_MAX_SAMPLES <= 48 && ID_T == 4 * ID_NMAX, "12 rows per lane");
+// sum over the four lanes of a quad (the lanes of one candidate column)
+__device__ __forceinline__ double quad_sum(double v) {
+  v += dpp_d<0xB1>(v);
+  v += dpp_d<0x4E>(v);
+  return v;
+}
+__global__ __launch_bounds__(ID_T) void k_cpqr_id(const Node* nodes, const Instance* inst,
                                                  const int32_t* list, int parent_mode, int R,
                                                  const double* Src, int64_t lds, const double* w,
                                                  double* P, int64_t ldp, double* samp,
@@ -1039,19 +1047,27 @@ __global__ __launch_bounds__(256) void k_cpqr_id(const Node* nodes, const Instan
   const double* src = parent_mode ? Src + (int64_t)g * 2 * R * R : Src + nd.lo;
   const int64_t ls = parent_mode ? 2 * R : lds;
   const double* wv = w + (int64_t)g * R;
-  for (int idx = tid; idx < n * R; idx += 256) {
+  for (int idx = tid; idx < n * R; idx += ID_T) {
     const int b = idx % n, a = idx / n;  // candidate b, sample dim a
     sM[a + b * ldm] = src[b + (int64_t)a * ls] * wv[a];
   }
-  for (int b = tid; b < n; b += 256) sperm[b] = b;
+  for (int b = tid; b < n; b += ID_T) sperm[b] = b;
   __syncthreads();
   const int kcap = min(min(in.k, in.r), min(R, n));
   const int lane = tid & 63, wave = tid >> 6;
-  // squared norms of the candidate columns (one thread per column)
-  for (int b = tid; b < n; b += 256) {
+  // squared norms of the candidate columns: lane q of column b's quad takes
+  // rows q, q + 4, ...
+  {
+    const int b = tid >> 2, q = tid & 3;
     double s2 = 0.0;
-    for (int a = 0; a < R; ++a) s2 = fma(sM[a + b * ldm], sM[a + b * ldm], s2);
-    snrm[b] = s2;
+#pragma unroll
+    for (int i = 0; i < HM_MAX_SAMPLES / 4; ++i) {
+      const int a = q + 4 * i;
+      const double x = (b < n && a < R) ? sM[a + b * ldm] : 0.0;
+      s2 = fma(x, x, s2);
+    }
+    s2 = quad_sum(s2);
+    if (b < n && q == 0) snrm[b] = s2;
   }
   __syncthreads();
   int k = 0;
@@ -1093,25 +1109,41 @@ __global__ __launch_bounds__(256) void k_cpqr_id(const Node* nodes, const Instan
       }
     }
     __syncthreads();
-    // apply H to the remaining candidates, then their norms below row j
+    // apply H to the remaining candidates, then their norms below row j: a
+    // quad per candidate, lane q on rows j + q, j + q + 4, ... (at most 12),
+    // the partial sums added across the quad
     const double f = sc[2];
-    for (int b = j + 1 + tid; b < n; b += 256) {
+    {
+      const int b = j + 1 + (tid >> 2), q = tid & 3;
+      const bool colok = b < n;
+      double xs[HM_MAX_SAMPLES / 4];
       double s2 = 0.0;
-      for (int a = j; a < R; ++a) s2 = fma(sv[a], sM[a + b * ldm], s2);
-      s2 *= f;
-      double n2 = 0.0;
-      for (int a = j; a < R; ++a) {
-        const double v = fma(-s2, sv[a], sM[a + b * ldm]);
-        sM[a + b * ldm] = v;
-        if (a > j) n2 = fma(v, v, n2);
+#pragma unroll
+      for (int i = 0; i < HM_MAX_SAMPLES / 4; ++i) {
+        const int a = j + q + 4 * i;
+        const bool act = colok && a < R;
+        xs[i] = act ? sM[a + b * ldm] : 0.0;
+        s2 = fma(act ? sv[a] : 0.0, xs[i], s2);
       }
-      snrm[b] = n2;
+      s2 = quad_sum(s2) * f;
+      double n2 = 0.0;
+#pragma unroll
+      for (int i = 0; i < HM_MAX_SAMPLES / 4; ++i) {
+        const int a = j + q + 4 * i;
+        if (colok && a < R) {
+          const double v = fma(-s2, sv[a], xs[i]);
+          sM[a + b * ldm] = v;
+          if (a > j) n2 = fma(v, v, n2);
+        }
+      }
+      n2 = quad_sum(n2);
+      if (colok && q == 0) snrm[b] = n2;
     }
     __syncthreads();
     k = j + 1;
   }
   // T = R11^{-1} R12, column by column (back substitution); stored in place of R12.
-  for (int b = k + tid; b < n; b += 256) {
+  for (int b = k + tid; b < n; b += ID_T) {
     for (int a = k - 1; a >= 0; --a) {
       double s = sM[a + b * ldm];
       for (int c2 = a + 1; c2 < k; ++c2) s -= sM[a + c2 * ldm] * sM[c2 + b * ldm];
@@ -1122,19 +1154,19 @@ __global__ __launch_bounds__(256) void k_cpqr_id(const Node* nodes, const Instan
   // P (n x R): row perm[b] = e_b (b < k) or T(:, b)^T (b >= k); columns >= k zero.
   double* Pout = parent_mode ? P + (int64_t)g * 2 * R * R : P + nd.lo;
   const int64_t lp = parent_mode ? 2 * R : ldp;
-  for (int idx = tid; idx < n * R; idx += 256) {
+  for (int idx = tid; idx < n * R; idx += ID_T) {
     const int b = idx % n, col = idx / n;
     double v = 0.0;
     if (col < k) v = (b < k) ? (b == col ? 1.0 : 0.0) : sM[col + b * ldm];
     Pout[sperm[b] + (int64_t)col * lp] = v;
   }
   double* sp = samp + (int64_t)g * R * R;
-  for (int idx = tid; idx < R * R; idx += 256) {
+  for (int idx = tid; idx < R * R; idx += ID_T) {
     const int i = idx % R, a = idx / R;
     sp[idx] = (i < k) ? src[sperm[i] + (int64_t)a * ls] : 0.0;
   }
   int32_t* sk_out = skel + (int64_t)g * R;
-  for (int i = tid; i < R; i += 256) {
+  for (int i = tid; i < R; i += ID_T) {
     int id = -1;
     if (i < k) {
       const int cnd = sperm[i];
@@ -1154,7 +1186,7 @@ void launch_cpqr_id(const Node* nodes, const Instance* inst, const int32_t* list
                     double* P, int64_t ldp, double* samp, int32_t* rank, int32_t* skel,
                     int32_t* saturated, hipStream_t s) {
   if (nlist <= 0) return;
-  hipLaunchKernelGGL(k_cpqr_id, dim3(nlist), dim3(256), 0, s, nodes, inst, list, parent_mode, R,
+  hipLaunchKernelGGL(k_cpqr_id, dim3(nlist), dim3(ID_T), 0, s, nodes, inst, list, parent_mode, R,
                      Src, lds, w, P, ldp, samp, rank, skel, saturated);
   KCHK();
 }
