@@ -129,7 +129,10 @@ typedef struct hm_info {
   int32_t operator_calls;/* operator invocations: 2 L + 1 (Omega_1, Omega_2 merged);
                             L + ceil(L / G) + 1 for the built-in kernel operator
                             sampled in BF16, whose first products of G = min(L,
-                            floor(288 / 2r)) levels share one call           */
+                            floor(288 / 2r)) levels share one call; one fewer
+                            when every instance has L levels and 2r + n_max <=
+                            288 (the block-identity product joins the last
+                            level's second call: the kernel is symmetric)    */
   int32_t saturated;     /* nodes whose revealed rank reached r - p               */
   double t_compress_ms;  /* wall time of the compress call                        */
   double t_operator_ms;  /* time inside the operator (T_compress - T_net)         */

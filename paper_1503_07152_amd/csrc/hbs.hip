@@ -430,10 +430,11 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
   // evaluates every entry of A once per call, whatever the column count, so
   // the first products of G consecutive levels go into one call of G 2R
   // columns (up to the sampler's width and a memory cap); the Gaussian
-  // blocks and the products are the same as with one call per level.
+  // blocks are the same as with one call per level, and so are the products
+  // up to the order of their FP32 accumulation.
   int G = 1;
+  bool bf16_kernel = true;
   {
-    bool bf16_kernel = true;
     for (size_t i = 0; i < f.inst.size(); ++i) {
       const OpRunner* o = ops.size() == f.inst.size() ? ops[i] : ops[0];
       bf16_kernel &= o->op.kind == HM_OP_KERNEL && o->op.sample_dtype == HM_BF16;
@@ -444,8 +445,17 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
       while (G > 1 && (size_t)N * 2 * R * G * 16 > cap) --G;
     }
   }
+  // The block-identity product of the diagonal step does not depend on the
+  // peeling either; for the same sampler (built-in kernels are symmetric, so
+  // A and A* are one product) it rides with the last level's second product
+  // when every instance peels down to that level.
+  bool fuse_diag = bf16_kernel && Lmax >= 1 && 2 * R + nmax <= sampler_max_cols(2);
+  for (const Instance& in : f.inst) fuse_diag &= in.L == Lmax;
+  const int32_t* d_leaves = kp.put(f.leaves, s);
+  int64_t max_leaf = 0;
+  for (int g : f.leaves) max_leaf = std::max<int64_t>(max_leaf, f.nodes[g].hi - f.nodes[g].lo);
   // ---- buffers ---------------------------------------------------------------
-  const int W = std::max(2 * R * G, nmax);
+  const int W = std::max(std::max(2 * R * G, nmax), fuse_diag ? 2 * R + nmax : 0);
   DevBuf Om((size_t)N * W * 8), Y((size_t)N * W * 8), M((size_t)N * 2 * R * 8);
   DevBuf Ucur((size_t)N * R * 8), Vcur((size_t)N * R * 8), Unx((size_t)N * R * 8),
       Vnx((size_t)N * R * 8);
@@ -532,9 +542,19 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
                      2 * R * R, 2 * R, 1.0, 0.0, ws_seg.base(), s, 1);
     }
     // outgoing bases and sibling matrices
+    int c2 = 2 * R;
+    if (fuse_diag && l == Lmax - 1) {
+      // every first-product block is consumed by now: the second product takes
+      // columns 0 .. 2R-1, the block identity the next n_max
+      om_l = om;
+      y_l = y;
+      launch_block_eye(dn, d_leaves, (int)f.leaves.size(), max_leaf, nmax, om + (int64_t)2 * R * N,
+                       N, s);
+      c2 = 2 * R + nmax;
+    }
     launch_mask_basis(dn, di, dk, nk, lv.max_kid_rows, R, un, N, om_l, N, s);
-    apply_ops(ops, f, true, 2 * R, om_l, N, y_l, N, active);
-    launch_nonfinite_check(y_l, N, 2 * R, N, flag.as<int>(), s);
+    apply_ops(ops, f, true, c2, om_l, N, y_l, N, active);
+    launch_nonfinite_check(y_l, N, c2, N, flag.as<int>(), s);
     if (l >= 1)
       apply_forest<double>(dn, lv.sub, hv, true, 2 * R, om_l, N, y_l, N, -1.0, 1.0,
                            ws_apply.base(), nn, s);
@@ -574,12 +594,19 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
   // ---- diagonal blocks ------------------------------------------------------------
   DevBuf D((size_t)N * nmax * 8);
   {
-    const int32_t* dl = kp.put(f.leaves, s);
-    int64_t maxl = 0;
-    for (int g : f.leaves) maxl = std::max<int64_t>(maxl, f.nodes[g].hi - f.nodes[g].lo);
-    launch_block_eye(dn, dl, (int)f.leaves.size(), maxl, nmax, om, N, s);
-    apply_ops(ops, f, false, nmax, om, N, D.as<double>(), N, {});
-    launch_nonfinite_check(D.as<double>(), N, nmax, N, flag.as<int>(), s);
+    const int32_t* dl = d_leaves;
+    const int64_t maxl = max_leaf;
+    double* om_eye = om;
+    if (fuse_diag) {
+      // taken with the last second product
+      om_eye = om + (int64_t)2 * R * N;
+      HIPCHK(hipMemcpyAsync(D.p, y + (int64_t)2 * R * N, (size_t)N * nmax * 8,
+                            hipMemcpyDeviceToDevice, s));
+    } else {
+      launch_block_eye(dn, dl, (int)f.leaves.size(), maxl, nmax, om, N, s);
+      apply_ops(ops, f, false, nmax, om, N, D.as<double>(), N, {});
+      launch_nonfinite_check(D.as<double>(), N, nmax, N, flag.as<int>(), s);
+    }
     std::vector<int> mvec(f.inst.size());
     for (size_t i = 0; i < f.inst.size(); ++i) mvec[i] = f.inst[i].L;
     build_apply_lists(f, mvec, h->full, s);
@@ -594,7 +621,7 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
     hv.B = B.as<double>(); hv.D = nullptr; hv.R = R;
     if (Lmax >= 1) {
       ws_apply.ensure(apply_work_bytes<double>(f, h->full, R, nmax), s);
-      apply_forest<double>(dn, h->full, hv, false, nmax, om, N, D.as<double>(), N, -1.0, 1.0,
+      apply_forest<double>(dn, h->full, hv, false, nmax, om_eye, N, D.as<double>(), N, -1.0, 1.0,
                            ws_apply.base(), nn, s);
     }
     launch_zero_dpad(dn, dl, (int)f.leaves.size(), maxl, nmax, D.as<double>(), N, s);

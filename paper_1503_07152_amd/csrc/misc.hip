@@ -323,11 +323,16 @@ void launch_fill_f(float* p, int64_t count, float v, hipStream_t s) {
   KCHK();
 }
 
+// one thread per row and group of NF_COLS columns (independent loads in flight)
+constexpr int NF_COLS = 8;
 __global__ void k_nonfinite(const double* p, int64_t rows, int64_t cols, int64_t ld, int* flag) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= rows) return;
+  const int64_t j0 = (int64_t)blockIdx.y * NF_COLS;
   bool bad = false;
-  for (int64_t j = 0; j < cols; ++j) bad |= !isfinite(p[i + j * ld]);
+#pragma unroll
+  for (int q = 0; q < NF_COLS; ++q)
+    if (j0 + q < cols) bad |= !isfinite(p[i + (j0 + q) * ld]);
   if (bad) atomicOr(flag, 1);
 }
 
@@ -335,8 +340,9 @@ void launch_nonfinite_check(const double* p, int64_t rows, int64_t cols, int64_t
                             hipStream_t s) {
   if (rows <= 0 || cols <= 0) return;
   const int nt = 256;
-  hipLaunchKernelGGL(k_nonfinite, dim3((unsigned)((rows + nt - 1) / nt)), dim3(nt), 0, s, p, rows,
-                     cols, ld, flag);
+  hipLaunchKernelGGL(k_nonfinite,
+                     dim3((unsigned)((rows + nt - 1) / nt), (unsigned)((cols + NF_COLS - 1) / NF_COLS)),
+                     dim3(nt), 0, s, p, rows, cols, ld, flag);
   KCHK();
 }
 
