@@ -39,3 +39,27 @@ def test_batched_matches_per_instance_oracle(ortho):
         print(f"  instance {i} n={n} k={k}: vs oracle {e_or:.2e} vs A {e_a:.2e}", flush=True)
         assert e_or < 1e-11 and e_a < 1e-11
         assert h.info()["sample_columns"] == st.columns
+
+
+def test_batched_bf16_kernel_uneven_depths():
+    """Built-in kernel operators sampled in BF16 over a forest whose instances
+    have different depths: the first products of several levels share calls
+    (instances that stop peeling earlier get zero test blocks), and the
+    block-identity product keeps its own call.  Each instance must reach the
+    BF16 accuracy of its single-instance compression."""
+    specs = [(2048, 3), (512, 5), (1024, 7)]
+    leaf, k, p = 128, 16, 8
+    print(f"batched bf16 kernel {len(specs)} instances", flush=True)
+    pts = [W.fourier_curve_points(n, seed=s) for n, s in specs]
+    mk = lambda P: hm.KernelOperator(P, "near", 1e-3, hm.HM_BF16)
+    opts = [hm.Options(n, leaf, k, p, seed=11 + i) for i, (n, _) in enumerate(specs)]
+    outs = hm.hbs_compress_batched(opts, [mk(P) for P in pts])
+    for i, ((n, _), P, h) in enumerate(zip(specs, pts, outs)):
+        K = oops.KernelOp(P, "near", 1e-3)
+        x = W.gaussian((n, 3), seed=5)
+        ref = K.apply(x)
+        e_b = rel(h.apply(torch.from_numpy(x)).cpu().numpy(), ref)
+        h1 = hm.hbs_compress(opts[i], mk(P))
+        e_1 = rel(h1.apply(torch.from_numpy(x)).cpu().numpy(), ref)
+        print(f"  instance {i} n={n}: batched {e_b:.2e} single {e_1:.2e}", flush=True)
+        assert e_b < 1e-2 and e_b < 1.5 * e_1 + 1e-4

@@ -46,7 +46,11 @@ def test_gauss_stream_matches_oracle(seed, level, phase, row0, nrows, ncols):
     ("near", hm.HM_F64, 1000, 96, 1e-13), ("log", hm.HM_F64, 777, 17, 1e-13),
     ("near", hm.HM_F32, 1000, 96, 2e-6), ("near", hm.HM_BF16, 1000, 96, 8e-3),
     ("near", hm.HM_F64, 300, 128, 1e-13), ("near", hm.HM_BF16, 1000, 192, 8e-3),
-    ("log", hm.HM_BF16, 777, 288, 8e-3), ("near", hm.HM_BF16, 1500, 300, 8e-3)])
+    ("log", hm.HM_BF16, 777, 288, 8e-3), ("near", hm.HM_BF16, 1500, 300, 8e-3),
+    # K-split edges of the narrow BF16 form: 2 K-tiles (two parts), 1 K-tile
+    # (no split), 3 K-tiles with a one-row last tile
+    ("near", hm.HM_BF16, 100, 96, 8e-3), ("near", hm.HM_BF16, 50, 40, 8e-3),
+    ("log", hm.HM_BF16, 129, 128, 8e-3)])
 def test_kernel_sampler_matches_dense_product(kernel, mode, n, c, tol):
     say(f"sampler kernel={kernel} mode={mode} n={n} c={c}")
     P = W.fourier_curve_points(n, seed=3)
