@@ -19,10 +19,10 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
-// Block shape per form.  BF16: ~80 VGPRs, so 8 waves (2 per SIMD) of one
-// 16-row tile each.  FP32 (FP32 and FP64 accumulators, ~420 registers with
-// the AGPRs) and FP64 (~130): 4 waves of two 16-row tiles, which halves the
-// LDS reads of X per MFMA.
+// Block shape per form.  BF16: 72 (8 column tiles) to 120 (18) VGPRs, so 8
+// waves (2 per SIMD) of one 16-row tile each.  FP32 (FP32 and FP64
+// accumulators, ~420 registers with the AGPRs) and FP64 (~190): 4 waves of
+// two 16-row tiles, which halves the LDS reads of X per MFMA.
 template <int MODE>
 struct SmpShape {
   static constexpr int WAVES = MODE == 2 ? 8 : 4;
@@ -141,8 +141,9 @@ constexpr int SMP_GS = 3;
 __device__ __forceinline__ int swz(int col) { return (col ^ ((col >> 3) & 1)) & 7; }
 
 // SRC: 0 log kernel, 1 near-singular kernel, 2 dense matrix, 3 its transpose (F64 only).
-// One block = SmpShape<MODE>::WAVES waves x RT 16-row tiles; the whole X is streamed
-// through LDS in K-tiles, double-buffered, the next tile prefetched into registers
+// One block = SmpShape<MODE>::WAVES waves x RT 16-row tiles; X is streamed
+// through LDS in K-tiles (the K-tiles of split blockIdx.y), double-buffered,
+// the next tile in flight (registers for F64 / F32, global_load_lds for BF16)
 // while the current one feeds the MFMAs.
 // CT column tiles of 16 are held in the accumulators (c <= 16 CT); the BF16
 // form takes up to 18, so one pass over the entries serves several sample
