@@ -55,9 +55,9 @@ SLOTS_PER_ENTRY = 13.5
 # reads 0.5x the bytes moved, WRITE_SIZE 1.0x).  Most of it is the three
 # K-split partial products (written, read back, summed).  Valid only for the
 # sampler source they were taken on (SHA-1 below); otherwise unknown.
-SAMPLER_TRAFFIC = {"sha1": "ab58e166a4f2bd8638c58eeb8240f53337afe2f9",
-                   "fetch_kib": 24590.9 + 96448.4 + 73746.6,
-                   "write_kib": 12320.0 + 148646.0 + 49152.0,
+SAMPLER_TRAFFIC = {"sha1": "ccd8b683386b3325e55a31dcc936cac39c3c7669",
+                   "fetch_kib": 24590.8 + 96446.5 + 73746.7,
+                   "write_kib": 12320.0 + 148705.4 + 49152.0,
                    "fetch_scale": 2.0, "write_scale": 1.0}
 
 
