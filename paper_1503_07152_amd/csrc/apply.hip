@@ -95,19 +95,39 @@ struct TreeSmem {
   T b[2 * TRM][TRC];       // B(k, j)
 };
 
+// Staging loops run over fixed trip counts (R <= 64 along the unit stride,
+// four rows per pass of 256 threads): all of a thread's global loads are
+// issued before the first LDS store, so a stage costs one memory latency
+// rather than one per element.
 template <class T>
 __device__ __forceinline__ void stage_coef(int R, int k0, const T* a, int64_t sai, int64_t sak,
                                            TreeSmem<T>& sm) {
+  static_assert(TRM <= 64, "one 64-lane row per coefficient column");
   const int tid = threadIdx.x;
-  if (sai == 1) {
-    for (int e = tid; e < R * R; e += 256) {
-      const int i = e % R, k = e / R;
-      sm.a[k0 + k][i] = a[i + k * sak];
+  const int lo = tid & 63, hi = tid >> 6;
+  constexpr int NQ = TRM / 4;
+  T v[NQ];
+  if (sai == 1) {   // i along the unit stride: lane lo takes row i = lo of columns k
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int k = hi + 4 * q;
+      v[q] = (lo < R && k < R) ? a[lo + (int64_t)k * sak] : T(0);
     }
-  } else {
-    for (int e = tid; e < R * R; e += 256) {
-      const int k = e % R, i = e / R;
-      sm.a[k0 + k][i] = a[i * sai + k * sak];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int k = hi + 4 * q;
+      if (lo < R && k < R) sm.a[k0 + k][lo] = v[q];
+    }
+  } else {          // k along the unit stride
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int i = hi + 4 * q;
+      v[q] = (lo < R && i < R) ? a[(int64_t)i * sai + (int64_t)lo * sak] : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int i = hi + 4 * q;
+      if (lo < R && i < R) sm.a[k0 + lo][i] = v[q];
     }
   }
 }
@@ -145,13 +165,30 @@ __device__ __forceinline__ void tree_product(int R, int nc, int nparts, const T*
   stage_coef<T>(R, 0, a1, sai1, sak1, sm);
   if (nparts == 2) stage_coef<T>(R, R, a2, sai2, sak2, sm);
   for (int e = tid; e < (Kp - K) * TRM; e += 256) sm.a[K + e / TRM][e % TRM] = T(0);
-  for (int e = tid; e < Kp * TRC; e += 256) {
-    const int k = e % Kp, j = e / Kp;
-    const bool second = k >= R;
-    const int kk = second ? k - R : k;
-    T v = T(0);
-    if (k < K && j < nc) v = second ? b2[kk + (int64_t)j * R] : b1[kk + (int64_t)j * R];
-    sm.b[k][j] = v;
+  {
+    // B (Kp x TRC, Kp <= 2 TRM = 96): lane kl = tid % 32 takes k = kl + 32 h,
+    // column j = tid / 32 + 8 w
+    static_assert(2 * TRM <= 96 && TRC == 32, "B staging covers 96 x 32");
+    const int kl = tid & 31, jl = tid >> 5;
+    T bv[3][4];
+#pragma unroll
+    for (int h = 0; h < 3; ++h)
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const int k = kl + 32 * h, j = jl + 8 * w;
+        const bool second = k >= R;
+        const int kk = second ? k - R : k;
+        T v = T(0);
+        if (k < K && j < nc) v = second ? b2[kk + (int64_t)j * R] : b1[kk + (int64_t)j * R];
+        bv[h][w] = v;
+      }
+#pragma unroll
+    for (int h = 0; h < 3; ++h)
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const int k = kl + 32 * h;
+        if (k < Kp) sm.b[k][jl + 8 * w] = bv[h][w];
+      }
   }
   __syncthreads();
   const int ti = tid & 15, tj = tid >> 4;
