@@ -978,10 +978,20 @@ __global__ void k_build_node_block(const Node* nodes, const Instance* inst, cons
   if (i >= nd.hi) return;
   const int r = inst[nd.inst].r;
   const int off = nd.is_left ? 0 : R;
-  for (int j = 0; j < r; ++j) M[i + (int64_t)j * ldm] = S[i + (int64_t)(off + j) * lds];
+  // fixed trip counts (r <= HM_MAX_SAMPLES): every load in flight before the stores
+  double v[HM_MAX_SAMPLES];
+#pragma unroll
+  for (int j = 0; j < HM_MAX_SAMPLES; ++j) v[j] = j < r ? S[i + (int64_t)(off + j) * lds] : 0.0;
+#pragma unroll
+  for (int j = 0; j < HM_MAX_SAMPLES; ++j)
+    if (j < r) M[i + (int64_t)j * ldm] = v[j];
   if (!first_half_only && nodes[nd.parent].parent >= 0) {
     const double* wp = w + (int64_t)nd.parent * R;
-    for (int j = 0; j < r; ++j) M[i + (int64_t)(r + j) * ldm] = Lpar[i + (int64_t)j * ldl] * wp[j];
+#pragma unroll
+    for (int j = 0; j < HM_MAX_SAMPLES; ++j) v[j] = j < r ? Lpar[i + (int64_t)j * ldl] * wp[j] : 0.0;
+#pragma unroll
+    for (int j = 0; j < HM_MAX_SAMPLES; ++j)
+      if (j < r) M[i + (int64_t)(r + j) * ldm] = v[j];
   }
 }
 

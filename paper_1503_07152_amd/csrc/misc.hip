@@ -249,7 +249,13 @@ __global__ void k_mask_basis(const Node* nodes, const Instance* inst, const int3
   const int off = nd.is_left ? R : 0;
   const int oth = nd.is_left ? 0 : R;
   for (int j = 0; j < R; ++j) Om[i + (int64_t)(oth + j) * ld] = 0.0;
-  for (int j = 0; j < R; ++j) Om[i + (int64_t)(off + j) * ld] = j < r ? U[i + (int64_t)j * ldu] : 0.0;
+  // fixed trip count (R <= HM_MAX_SAMPLES): every load in flight before the stores
+  double v[HM_MAX_SAMPLES];
+#pragma unroll
+  for (int j = 0; j < HM_MAX_SAMPLES; ++j) v[j] = j < r ? U[i + (int64_t)j * ldu] : 0.0;
+#pragma unroll
+  for (int j = 0; j < HM_MAX_SAMPLES; ++j)
+    if (j < R) Om[i + (int64_t)(off + j) * ld] = v[j];
 }
 
 void launch_mask_basis(const Node* nodes, const Instance* inst, const int32_t* kids, int nkids,
