@@ -728,7 +728,6 @@ __device__ __forceinline__ int jacobi_sweeps(double* sA, double* sZ, double* sN,
   const int tid = threadIdx.x;
   const int grp = tid / JAC_G, gl = tid % JAC_G;
   const int n2 = c + (c & 1);
-  const int hm1 = max(h - 1, 0);
   const double tol = (double)max(h, 1) * DBL_EPSILON;
   int sweep = 0;
   for (; sweep < 40; ++sweep) {
@@ -738,8 +737,7 @@ __device__ __forceinline__ int jacobi_sweeps(double* sA, double* sZ, double* sN,
       double nn = 0.0;
 #pragma unroll
       for (int u = 0; u < RPL; ++u) {
-        const int i = gl + JAC_G * u;
-        const double v = i < h ? sA[min(i, hm1) + j * JAC_LD] : 0.0;
+        const double v = sA[gl + JAC_G * u + j * JAC_LD];
         nn = fma(v, v, nn);
       }
       nn = sum16(nn);
@@ -757,16 +755,15 @@ __device__ __forceinline__ int jacobi_sweeps(double* sA, double* sZ, double* sN,
         const int pb = b == 0 ? 0 : 1 + xb;
         const int p = min(pa, pb), q = max(pa, pb);
         if (q >= c) continue;
-        // the group's rows gl + 16 u (fixed trip count; rows past h weigh zero)
+        // the group's rows gl + 16 u (fixed trip count; rows h .. 16 RPL - 1
+        // hold zeros, which the rotations keep)
         double xv[RPL], yv[RPL];
         double ga = 0.0;
 #pragma unroll
         for (int u = 0; u < RPL; ++u) {
           const int i = gl + JAC_G * u;
-          const int ic = min(i, hm1);
-          const double w = i < h ? 1.0 : 0.0;
-          xv[u] = w * sA[ic + p * JAC_LD];
-          yv[u] = w * sA[ic + q * JAC_LD];
+          xv[u] = sA[i + p * JAC_LD];
+          yv[u] = sA[i + q * JAC_LD];
           ga = fma(xv[u], yv[u], ga);
         }
         ga = sum16(ga);
@@ -807,10 +804,8 @@ __device__ __forceinline__ int jacobi_sweeps(double* sA, double* sZ, double* sN,
 #pragma unroll
           for (int u = 0; u < RPL; ++u) {
             const int i = gl + JAC_G * u;
-            if (i < h) {
-              sA[i + p * JAC_LD] = cs * xv[u] - sn * yv[u];
-              sA[i + q * JAC_LD] = sn * xv[u] + cs * yv[u];
-            }
+            sA[i + p * JAC_LD] = cs * xv[u] - sn * yv[u];
+            sA[i + q * JAC_LD] = sn * xv[u] + cs * yv[u];
           }
           if (wantX) {
             // rows of Z: c <= JAC_G JAC_RPL
@@ -865,6 +860,12 @@ __global__ __launch_bounds__(JAC_FT) void k_jacobi(const SvdDesc* descs) {
   for (int idx = tid; idx < h * c; idx += JAC_FT) {
     const int i = idx % h, j = idx / h;
     sA[i + j * JAC_LD] = d.trans ? d.R[j + (int64_t)i * d.ldR] : d.R[i + (int64_t)j * d.ldR];
+  }
+  // rows h .. FAC_CMAX - 1 are zero: the sweeps read and rotate whole groups
+  // of 16 rows without tests
+  for (int idx = tid; idx < (FAC_CMAX - h) * c; idx += JAC_FT) {
+    const int i = h + idx % (FAC_CMAX - h), j = idx / (FAC_CMAX - h);
+    sA[i + j * JAC_LD] = 0.0;
   }
   if (accZ)
     for (int idx = tid; idx < c * c; idx += JAC_FT) {
