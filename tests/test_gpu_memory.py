@@ -102,3 +102,23 @@ def test_torch_caching_allocator_backs_library_memory():
     again, handles = _run_all(g, n, leaf, k, p)
     for kk in ref:
         assert torch.allclose(again[kk], ref[kk], rtol=1e-13, atol=1e-13 * float(ref[kk].abs().max())), kk
+
+
+def test_operator_apply_back_to_back_under_torch_allocator():
+    """hm_operator_apply returns without waiting; its scratch (packed X, the
+    K-split partial products) goes back to torch's pool on the stream, so calls
+    enqueued back to back, each with fresh scratch, must all give the first
+    call's result."""
+    n, c = 3000, 96
+    print(f"back-to-back operator applies n={n} c={c}", flush=True)
+    P = W.fourier_curve_points(n, seed=8)
+    X = torch.from_numpy(W.gaussian((n, c), seed=9)).cuda()
+    try:
+        hm.use_torch_allocator(True)
+        op = hm.KernelOperator(P, "near", 1e-3, hm.HM_BF16)
+        ys = [hm.hm_operator_apply(op, X) for _ in range(6)]
+        torch.cuda.synchronize()
+        for y in ys[1:]:
+            assert torch.equal(y, ys[0])
+    finally:
+        hm.use_torch_allocator(False)
