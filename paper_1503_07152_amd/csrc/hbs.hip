@@ -390,6 +390,37 @@ static void apply_ops(std::vector<OpRunner*>& ops, const Forest& f, bool adjoint
   }
 }
 
+// A second stream for work independent of the main stream's: fork() makes it
+// wait for everything enqueued on the main stream so far, join() makes the
+// main stream wait for everything enqueued on it.  Default priority; the
+// stream and its events are released when the object goes out of scope (the
+// caller synchronises the main stream before returning).
+struct SideStream {
+  hipStream_t main, st = nullptr;
+  hipEvent_t e_fork = nullptr, e_join = nullptr;
+  explicit SideStream(hipStream_t m) : main(m) {
+    HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&e_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&e_join, hipEventDisableTiming));
+  }
+  SideStream(const SideStream&) = delete;
+  SideStream& operator=(const SideStream&) = delete;
+  ~SideStream() {
+    if (e_join) (void)hipEventDestroy(e_join);
+    if (e_fork) (void)hipEventDestroy(e_fork);
+    if (st) (void)hipStreamDestroy(st);
+  }
+  hipStream_t stream() const { return st; }
+  void fork() {
+    HIPCHK(hipEventRecord(e_fork, main));
+    HIPCHK(hipStreamWaitEvent(st, e_fork, 0));
+  }
+  void join() {
+    HIPCHK(hipEventRecord(e_join, st));
+    HIPCHK(hipStreamWaitEvent(main, e_join, 0));
+  }
+};
+
 hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t flags, hipStream_t s,
                               int* status) {
   auto t0 = std::chrono::steady_clock::now();
@@ -638,7 +669,7 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
     DevBuf Unew((size_t)N * R * 8), Vnew((size_t)N * R * 8);
     DevBuf Utn((size_t)nn * 2 * R * R * 8), Vtn((size_t)nn * 2 * R * R * 8);
     DevBuf Bn((size_t)nn * R * R * 8), sU((size_t)nn * R * R * 8), sV((size_t)nn * R * R * 8);
-    DevBuf Tmp((size_t)nn * 2 * R * R * 8);
+    DevBuf TmpU((size_t)nn * 2 * R * R * 8), TmpV((size_t)nn * 2 * R * R * 8);
     HIPCHK(hipMemsetAsync(Unew.p, 0, Unew.bytes, s));
     HIPCHK(hipMemsetAsync(Vnew.p, 0, Vnew.bytes, s));
     HIPCHK(hipMemsetAsync(Utn.p, 0, Utn.bytes, s));
@@ -649,26 +680,43 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
     for (int g : f.leaves)
       if (f.nodes[g].level > 0) lv.push_back(g);
     const int32_t* dl = kp.put(lv, s);
-    int32_t* sat = flag.as<int32_t>() + 1;
-    launch_cpqr_id(dn, di, dl, (int)lv.size(), 0, R, uc, N, yv.as<double>(), Unew.as<double>(), N,
-                   sU.as<double>(), rk_u.as<int32_t>(), sk_in.as<int32_t>(), sat, s);
-    launch_cpqr_id(dn, di, dl, (int)lv.size(), 0, R, vc, N, zv.as<double>(), Vnew.as<double>(), N,
-                   sV.as<double>(), rk_v.as<int32_t>(), sk_out.as<int32_t>(), sat, s);
+    std::vector<std::pair<const int32_t*, int>> dpar(Lmax);
     for (int l = Lmax - 1; l >= 1; --l) {
       std::vector<int32_t> par;
       for (int g : f.level[l])
         if (f.nodes[g].left >= 0) par.push_back(g);
-      if (par.empty()) continue;
-      const int32_t* dp = kp.put(par, s);
-      launch_utmp(dn, dp, (int)par.size(), R, sU.as<double>(), Ut.as<double>(), Tmp.as<double>(), s);
-      launch_cpqr_id(dn, di, dp, (int)par.size(), 1, R, Tmp.as<double>(), 2 * R, yv.as<double>(),
-                     Utn.as<double>(), 2 * R, sU.as<double>(), rk_u.as<int32_t>(),
-                     sk_in.as<int32_t>(), sat, s);
-      launch_utmp(dn, dp, (int)par.size(), R, sV.as<double>(), Vt.as<double>(), Tmp.as<double>(), s);
-      launch_cpqr_id(dn, di, dp, (int)par.size(), 1, R, Tmp.as<double>(), 2 * R, zv.as<double>(),
-                     Vtn.as<double>(), 2 * R, sV.as<double>(), rk_v.as<int32_t>(),
-                     sk_out.as<int32_t>(), sat, s);
+      dpar[l] = {par.empty() ? nullptr : kp.put(par, s), (int)par.size()};
     }
+    int32_t* sat = flag.as<int32_t>() + 1;
+    // The U and the V chains of the sweep share nothing but read-only inputs
+    // and the saturation counter (atomic): the V chain runs on a second
+    // stream, forked after every input and node list is enqueued on s and
+    // joined before B^skel, so the coarse levels' latency-bound IDs of the
+    // two sides overlap.
+    SideStream side(s);
+    auto chain = [&](bool vside, hipStream_t st) {
+      const double* basis = vside ? vc : uc;
+      const double* wts = vside ? zv.as<double>() : yv.as<double>();
+      double* newb = vside ? Vnew.as<double>() : Unew.as<double>();
+      double* samp = vside ? sV.as<double>() : sU.as<double>();
+      double* tnew = vside ? Vtn.as<double>() : Utn.as<double>();
+      const double* told = vside ? Vt.as<double>() : Ut.as<double>();
+      double* tmp = vside ? TmpV.as<double>() : TmpU.as<double>();
+      int32_t* rk = vside ? rk_v.as<int32_t>() : rk_u.as<int32_t>();
+      int32_t* sk = vside ? sk_out.as<int32_t>() : sk_in.as<int32_t>();
+      launch_cpqr_id(dn, di, dl, (int)lv.size(), 0, R, basis, N, wts, newb, N, samp, rk, sk, sat,
+                     st);
+      for (int l = Lmax - 1; l >= 1; --l) {
+        if (dpar[l].second == 0) continue;
+        launch_utmp(dn, dpar[l].first, dpar[l].second, R, samp, told, tmp, st);
+        launch_cpqr_id(dn, di, dpar[l].first, dpar[l].second, 1, R, tmp, 2 * R, wts, tnew, 2 * R,
+                       samp, rk, sk, sat, st);
+      }
+    };
+    side.fork();
+    chain(false, s);
+    chain(true, side.stream());
+    side.join();
     std::vector<int32_t> nonroot;
     for (int g = 0; g < nn; ++g)
       if (f.nodes[g].parent >= 0) nonroot.push_back(g);
