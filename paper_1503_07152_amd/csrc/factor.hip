@@ -1093,6 +1093,9 @@ __global__ __launch_bounds__(ID_T) void k_cpqr_id(const Node* nodes, const Insta
       if (b < n && snrm[b] > bv) { bv = snrm[b]; bi = b; }
     }
     const double vmax = max64(bv);
+    // no candidate left with a comparable norm (all NaN: non-finite samples,
+    // reported by the caller) stops the factorisation here: p would be n
+    if (!(vmax >= 0.0)) break;
     const int p = (int)(-max64(bv == vmax ? -(double)bi : -1e9));
     const double nrm = sqrt(vmax);
     if (j == 0) ref = nrm;
