@@ -6,6 +6,9 @@
 #include <cmath>
 #include <cstring>
 
+#include <map>
+#include <mutex>
+
 #include "handle.h"
 
 namespace hm {
@@ -392,14 +395,29 @@ static void apply_ops(std::vector<OpRunner*>& ops, const Forest& f, bool adjoint
 
 // A second stream for work independent of the main stream's: fork() makes it
 // wait for everything enqueued on the main stream so far, join() makes the
-// main stream wait for everything enqueued on it.  Default priority; the
-// stream and its events are released when the object goes out of scope (the
-// caller synchronises the main stream before returning).
+// main stream wait for everything enqueued on it.  The stream (default
+// priority) is created once per device and kept for the life of the process
+// (creating one per call costs milliseconds on first use); calls that share
+// it from several host threads are ordered on it, each joined by its own
+// events, which are released when the object goes out of scope.
+static hipStream_t side_stream_for_current_device() {
+  static std::mutex mu;
+  static std::map<int, hipStream_t> streams;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = streams.find(dev);
+  if (it != streams.end()) return it->second;
+  hipStream_t st = nullptr;
+  HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  streams[dev] = st;
+  return st;
+}
+
 struct SideStream {
   hipStream_t main, st = nullptr;
   hipEvent_t e_fork = nullptr, e_join = nullptr;
-  explicit SideStream(hipStream_t m) : main(m) {
-    HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  explicit SideStream(hipStream_t m) : main(m), st(side_stream_for_current_device()) {
     HIPCHK(hipEventCreateWithFlags(&e_fork, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&e_join, hipEventDisableTiming));
   }
@@ -408,7 +426,6 @@ struct SideStream {
   ~SideStream() {
     if (e_join) (void)hipEventDestroy(e_join);
     if (e_fork) (void)hipEventDestroy(e_fork);
-    if (st) (void)hipStreamDestroy(st);
   }
   hipStream_t stream() const { return st; }
   void fork() {
