@@ -126,13 +126,16 @@ typedef struct hm_info {
   int32_t dtype;         /* storage type of the generators                        */
   int64_t storage_reals; /* reals needed at the revealed ranks (M of Sec. 5)      */
   int64_t sample_columns;/* columns sent to the operator (4 r L + n_max)          */
-  int32_t operator_calls;/* operator invocations: 2 L + 1 (Omega_1, Omega_2 merged);
-                            L + ceil(L / G) + 1 for the built-in kernel operator
-                            sampled in BF16, whose first products of G = min(L,
-                            floor(288 / 2r)) levels share one call; one fewer
-                            when every instance has L levels and 2r + n_max <=
-                            288 (the block-identity product joins the last
-                            level's second call: the kernel is symmetric)    */
+  int32_t operator_calls;/* operator invocations: 2 L + 1 (Omega_1, Omega_2 merged).
+                            Fewer for the built-in kernel operator sampled in
+                            BF16 (symmetric, so A and A* are one product), whose
+                            calls take up to 288 columns: one call takes the
+                            first products of G = min(L, floor(288 / 2r))
+                            levels, each level's second call those of the next
+                            levels that fit beside its 2r columns, and the last
+                            level's second call the block identity when every
+                            instance has L levels and 2r + n_max <= 288;
+                            L + 1 calls when all first products fit so       */
   int32_t saturated;     /* nodes whose revealed rank reached r - p               */
   double t_compress_ms;  /* wall time of the compress call                        */
   double t_operator_ms;  /* time inside the operator (T_compress - T_net)         */

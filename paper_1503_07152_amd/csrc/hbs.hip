@@ -476,35 +476,115 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
   // The first product of each level (A times the masked Gaussian Omega_l)
   // does not depend on earlier levels.  The built-in BF16 kernel sampler
   // evaluates every entry of A once per call, whatever the column count, so
-  // the first products of G consecutive levels go into one call of G 2R
-  // columns (up to the sampler's width and a memory cap); the Gaussian
-  // blocks are the same as with one call per level, and so are the products
-  // up to the order of their FP32 accumulation.
-  int G = 1;
+  // first products share calls, up to the sampler's width: one call takes
+  // those of G consecutive levels, and a level's second call (A* Psi; the
+  // built-in kernels are symmetric, so A and A* are one product) takes those
+  // of as many of the next levels as fit beside its own columns.  The
+  // Gaussian blocks are the same as with one call per level, and so are the
+  // products up to the order of their FP32 accumulation.
   bool bf16_kernel = true;
-  {
-    for (size_t i = 0; i < f.inst.size(); ++i) {
-      const OpRunner* o = ops.size() == f.inst.size() ? ops[i] : ops[0];
-      bf16_kernel &= o->op.kind == HM_OP_KERNEL && o->op.sample_dtype == HM_BF16;
-    }
-    if (bf16_kernel && Lmax > 1 && R > 0) {
-      G = std::max(1, std::min(Lmax, sampler_max_cols(2) / (2 * R)));
-      const size_t cap = (size_t)4 << 30;   // bytes of Omega plus Y
-      while (G > 1 && (size_t)N * 2 * R * G * 16 > cap) --G;
-    }
+  for (size_t i = 0; i < f.inst.size(); ++i) {
+    const OpRunner* o = ops.size() == f.inst.size() ? ops[i] : ops[0];
+    bf16_kernel &= o->op.kind == HM_OP_KERNEL && o->op.sample_dtype == HM_BF16;
   }
+  const int cmax = sampler_max_cols(2);
   // The block-identity product of the diagonal step does not depend on the
-  // peeling either; for the same sampler (built-in kernels are symmetric, so
-  // A and A* are one product) it rides with the last level's second product
-  // when every instance peels down to that level.
-  bool fuse_diag = bf16_kernel && Lmax >= 1 && 2 * R + nmax <= sampler_max_cols(2);
+  // peeling either; for the same sampler it rides with the last level's
+  // second product when every instance peels down to that level.
+  bool fuse_diag = bf16_kernel && Lmax >= 1 && 2 * R + nmax <= cmax;
   for (const Instance& in : f.inst) fuse_diag &= in.L == Lmax;
   const int32_t* d_leaves = kp.put(f.leaves, s);
   int64_t max_leaf = 0;
   for (int g : f.leaves) max_leaf = std::max<int64_t>(max_leaf, f.nodes[g].hi - f.nodes[g].lo);
+  // ---- call plan and column windows -------------------------------------------
+  // Every sampler call of the peeling reads and writes a window of columns
+  // (N x width of Omega and of Y).  Per level l: fw/fc, window and first
+  // column of its first product; ng, first products its first call takes
+  // (0: no such call); sw/sc, window and column of its second product
+  // (followed by the block identity on the last level when fused, then by
+  // nr first products of levels rf ..).  A window is taken again once every
+  // level that reads it is done; a level reads its first product before its
+  // second call is enqueued, so a second product that carries nothing else
+  // takes the first product's columns.
+  struct Plan {
+    std::vector<int> fw, fc, ng, sw, sc, nr, rf;
+    int nwin = 1, width = 0;
+  };
+  auto plan_calls = [&](int gfirst, bool ride) {
+    Plan p;
+    for (auto* v : {&p.fw, &p.fc, &p.ng, &p.sw, &p.sc, &p.nr, &p.rf}) v->assign(Lmax, 0);
+    std::vector<int> busy;   // last level reading each window (Lmax: the diagonal step)
+    auto take = [&busy](int from, int last) {   // a window no level >= from reads
+      for (size_t w = 0; w < busy.size(); ++w)
+        if (busy[w] < from) {
+          busy[w] = last;
+          return (int)w;
+        }
+      busy.push_back(last);
+      return (int)busy.size() - 1;
+    };
+    int next = 0;   // first level whose first product is not planned yet
+    for (int l = 0; l < Lmax; ++l) {
+      if (next == l) {
+        const int g = std::min(gfirst, Lmax - l);
+        const int w = take(l, l + g - 1);
+        for (int q = 0; q < g; ++q) {
+          p.fw[l + q] = w;
+          p.fc[l + q] = 2 * R * q;
+        }
+        p.ng[l] = g;
+        next = l + g;
+        p.width = std::max(p.width, 2 * R * g);
+      }
+      const bool diag = fuse_diag && l == Lmax - 1;
+      const int c2 = 2 * R + (diag ? nmax : 0);
+      const int nf = ride ? std::min(Lmax - next, std::max(0, (cmax - c2) / (2 * R))) : 0;
+      if (!diag && nf == 0) {
+        p.sw[l] = p.fw[l];
+        p.sc[l] = p.fc[l];
+        continue;
+      }
+      const int w = take(l + 1, diag ? Lmax : std::max(l, next + nf - 1));
+      p.sw[l] = w;
+      p.sc[l] = 0;
+      p.nr[l] = nf;
+      p.rf[l] = next;
+      for (int q = 0; q < nf; ++q) {
+        p.fw[next + q] = w;
+        p.fc[next + q] = c2 + 2 * R * q;
+      }
+      next += nf;
+      p.width = std::max(p.width, c2 + 2 * R * nf);
+    }
+    p.width = std::max(p.width, nmax);
+    p.nwin = std::max<int>(1, (int)busy.size());
+    return p;
+  };
+  const size_t cap = (size_t)4 << 30;   // bytes of the windows (Omega plus Y)
+  auto plan_bytes = [&](const Plan& p) { return (size_t)p.nwin * N * p.width * 16; };
+  Plan pl = plan_calls(1, false);
+  if (bf16_kernel && Lmax > 1 && R > 0) {
+    int G = std::max(1, std::min(Lmax, cmax / (2 * R)));
+    Plan pr = plan_calls(G, true);
+    if (plan_bytes(pr) <= cap) {
+      pl = pr;
+    } else {
+      while (G > 1 && (size_t)N * 2 * R * G * 16 > cap) --G;
+      pl = plan_calls(G, false);
+    }
+  }
   // ---- buffers ---------------------------------------------------------------
-  const int W = std::max(std::max(2 * R * G, nmax), fuse_diag ? 2 * R + nmax : 0);
-  DevBuf Om((size_t)N * W * 8), Y((size_t)N * W * 8), M((size_t)N * 2 * R * 8);
+  std::vector<DevBuf> OmW, YW;
+  for (int w = 0; w < pl.nwin; ++w) {
+    OmW.emplace_back((size_t)N * pl.width * 8);
+    YW.emplace_back((size_t)N * pl.width * 8);
+    // rows of instances no longer peeling are not sampled but still checked
+    // for non-finite values: they start at zero
+    if (f.inst.size() > 1) HIPCHK(hipMemsetAsync(YW[w].p, 0, YW[w].bytes, s));
+  }
+  auto om_at = [&](int w, int col) { return OmW[w].as<double>() + (int64_t)col * N; };
+  auto y_at = [&](int w, int col) { return YW[w].as<double>() + (int64_t)col * N; };
+  DevBuf M((size_t)N * 2 * R * 8);
   DevBuf Ucur((size_t)N * R * 8), Vcur((size_t)N * R * 8), Unx((size_t)N * R * 8),
       Vnx((size_t)N * R * 8);
   DevBuf Uleaf((size_t)N * R * 8), Vleaf((size_t)N * R * 8);   // leaf bases of every instance
@@ -519,8 +599,6 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
   HIPCHK(hipMemsetAsync(Vt.p, 0, Vt.bytes, s));
   HIPCHK(hipMemsetAsync(B.p, 0, B.bytes, s));
   HIPCHK(hipMemsetAsync(Xr.p, 0, Xr.bytes, s));
-  double* om = Om.as<double>();
-  double* y = Y.as<double>();
   double* m = M.as<double>();
   double *uc = Ucur.as<double>(), *vc = Vcur.as<double>(), *un = Unx.as<double>(),
          *vn = Vnx.as<double>();
@@ -536,28 +614,38 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
     }
     if (l >= 1) build_apply_lists(f, mvec, LL[l].sub, s);
   }
+  std::vector<const int32_t*> dkid(Lmax);
+  for (int l = 0; l < Lmax; ++l) dkid[l] = kp.put(LL[l].kids, s);
+  // Gaussian blocks of levels l0 .. l0 + g - 1 into consecutive 2R-column
+  // blocks of om (zero outside the nodes of the instances peeling there)
+  auto gauss_levels = [&](int l0, int g, double* om) {
+    if (f.inst.size() > 1) launch_fill(om, N, 2 * R * g, N, 0.0, s);
+    for (int q = 0; q < g; ++q) {
+      const LevelLists& lq = LL[l0 + q];
+      launch_gauss_masked(dn, di, dkid[l0 + q], (int)lq.kids.size(), lq.max_kid_rows, l0 + q, R,
+                          om + (int64_t)q * 2 * R * N, N, s);
+    }
+  };
+  double* diag_om = nullptr;   // the block identity and its product, when fused
+  double* diag_y = nullptr;
   // ---- Fig. 4: peeling, level by level ------------------------------------------
   for (int l = 0; l < Lmax; ++l) {
     LevelLists& lv = LL[l];
     std::vector<int> active(f.inst.size(), 0);
     for (size_t i = 0; i < f.inst.size(); ++i) active[i] = f.inst[i].L > l;
-    const int32_t* dk = kp.put(lv.kids, s);
+    const int32_t* dk = dkid[l];
     const int nk = (int)lv.kids.size();
-    if (l % G == 0) {
+    if (pl.ng[l]) {
       // first products of levels l .. l + g - 1, block q of 2R columns each
-      const int g = std::min(G, Lmax - l);
-      if (f.inst.size() > 1) launch_fill(om, N, 2 * R * g, N, 0.0, s);
-      for (int q = 0; q < g; ++q) {
-        const LevelLists& lq = LL[l + q];
-        launch_gauss_masked(dn, di, q == 0 ? dk : kp.put(lq.kids, s), (int)lq.kids.size(),
-                            lq.max_kid_rows, l + q, R, om + (int64_t)q * 2 * R * N, N, s);
-      }
-      apply_ops(ops, f, false, 2 * R * g, om, N, y, N, active);
-      launch_nonfinite_check(y, N, 2 * R * g, N, flag.as<int>(), s);
+      const int g = pl.ng[l];
+      double* ow = om_at(pl.fw[l], pl.fc[l]);
+      double* yw = y_at(pl.fw[l], pl.fc[l]);
+      gauss_levels(l, g, ow);
+      apply_ops(ops, f, false, 2 * R * g, ow, N, yw, N, active);
+      launch_nonfinite_check(yw, N, 2 * R * g, N, flag.as<int>(), s);
     }
-    // this level's block; it is free again once its first product is used
-    double* om_l = om + (int64_t)(l % G) * 2 * R * N;
-    double* y_l = y + (int64_t)(l % G) * 2 * R * N;
+    double* om_l = om_at(pl.fw[l], pl.fc[l]);
+    double* y_l = y_at(pl.fw[l], pl.fc[l]);
     HbsView<double> hv;
     hv.Ulong = uc; hv.Vlong = vc; hv.ldl = N; hv.Ut = Ut.as<double>(); hv.Vt = Vt.as<double>();
     hv.B = B.as<double>(); hv.D = nullptr; hv.R = R;
@@ -589,17 +677,20 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
       seg_tn<double>(dn, dk, nk, lv.max_kid_rows, R, R, un, N, uc, N, Ut.as<double>(),
                      2 * R * R, 2 * R, 1.0, 0.0, ws_seg.base(), s, 1);
     }
-    // outgoing bases and sibling matrices
+    // outgoing bases and sibling matrices: Psi in columns 0 .. 2R-1 of the
+    // second call, then the block identity (last level, fused), then the
+    // Gaussian blocks of the first products it carries
+    om_l = om_at(pl.sw[l], pl.sc[l]);
+    y_l = y_at(pl.sw[l], pl.sc[l]);
     int c2 = 2 * R;
     if (fuse_diag && l == Lmax - 1) {
-      // every first-product block is consumed by now: the second product takes
-      // columns 0 .. 2R-1, the block identity the next n_max
-      om_l = om;
-      y_l = y;
-      launch_block_eye(dn, d_leaves, (int)f.leaves.size(), max_leaf, nmax, om + (int64_t)2 * R * N,
-                       N, s);
+      diag_om = om_l + (int64_t)2 * R * N;
+      diag_y = y_l + (int64_t)2 * R * N;
+      launch_block_eye(dn, d_leaves, (int)f.leaves.size(), max_leaf, nmax, diag_om, N, s);
       c2 = 2 * R + nmax;
     }
+    if (pl.nr[l]) gauss_levels(pl.rf[l], pl.nr[l], om_l + (int64_t)c2 * N);
+    c2 += 2 * R * pl.nr[l];
     launch_mask_basis(dn, di, dk, nk, lv.max_kid_rows, R, un, N, om_l, N, s);
     apply_ops(ops, f, true, c2, om_l, N, y_l, N, active);
     launch_nonfinite_check(y_l, N, c2, N, flag.as<int>(), s);
@@ -644,15 +735,14 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
   {
     const int32_t* dl = d_leaves;
     const int64_t maxl = max_leaf;
-    double* om_eye = om;
+    double* om_eye = om_at(0, 0);
     if (fuse_diag) {
       // taken with the last second product
-      om_eye = om + (int64_t)2 * R * N;
-      HIPCHK(hipMemcpyAsync(D.p, y + (int64_t)2 * R * N, (size_t)N * nmax * 8,
-                            hipMemcpyDeviceToDevice, s));
+      om_eye = diag_om;
+      HIPCHK(hipMemcpyAsync(D.p, diag_y, (size_t)N * nmax * 8, hipMemcpyDeviceToDevice, s));
     } else {
-      launch_block_eye(dn, dl, (int)f.leaves.size(), maxl, nmax, om, N, s);
-      apply_ops(ops, f, false, nmax, om, N, D.as<double>(), N, {});
+      launch_block_eye(dn, dl, (int)f.leaves.size(), maxl, nmax, om_eye, N, s);
+      apply_ops(ops, f, false, nmax, om_eye, N, D.as<double>(), N, {});
       launch_nonfinite_check(D.as<double>(), N, nmax, N, flag.as<int>(), s);
     }
     std::vector<int> mvec(f.inst.size());

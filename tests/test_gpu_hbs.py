@@ -201,11 +201,22 @@ def test_mixed_precision_sampling_errors(mode, tol):
     say(f"  {r}")
     assert r["vs_oracle"] < tol
     # BF16 kernel sampling puts the first products of G levels in one call,
-    # and the block-identity product in the last level's second call
+    # those of the next levels into the second calls while they fit in 288
+    # columns, and the block-identity product in the last level's second call
     L = ho.tree.L
-    G = min(L, 288 // (2 * (k + p))) if mode == hm.HM_BF16 else 1
     inf = h.info()
-    assert inf["operator_calls"] == L + -(-L // G) + (0 if mode == hm.HM_BF16 else 1)
+    if mode == hm.HM_BF16:
+        r2, nmax = 2 * (k + p), ho.tree.nmax()
+        calls, nxt = L, 0
+        for lev in range(L):
+            if nxt == lev:
+                calls += 1
+                nxt += min(288 // r2, L - lev)
+            c2 = r2 + (nmax if lev == L - 1 else 0)
+            nxt += min(L - nxt, (288 - c2) // r2)
+        assert inf["operator_calls"] == calls
+    else:
+        assert inf["operator_calls"] == 2 * L + 1
     assert inf["sample_columns"] == 4 * (k + p) * L + ho.tree.nmax()
 
 
