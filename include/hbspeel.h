@@ -132,9 +132,10 @@ typedef struct hm_info {
                             calls take up to 288 columns: one call takes the
                             first products of G = min(L, floor(288 / 2r))
                             levels, each level's second call those of the next
-                            levels that fit beside its 2r columns, and the last
-                            level's second call the block identity when every
-                            instance has L levels and 2r + n_max <= 288;
+                            levels that fit beside its 2r columns; when every
+                            instance has L levels and 2r + n_max <= 288 the
+                            block identity rides in second calls too (spare
+                            columns of the narrow ones, else the last level's);
                             L + 1 calls when all first products fit so       */
   int32_t saturated;     /* nodes whose revealed rank reached r - p               */
   double t_compress_ms;  /* wall time of the compress call                        */

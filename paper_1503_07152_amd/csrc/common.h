@@ -170,9 +170,12 @@ void launch_gauss_masked(const Node* nodes, const Instance* inst, const int32_t*
 void launch_mask_basis(const Node* nodes, const Instance* inst, const int32_t* kids,
                        int nkids, int64_t max_rows, int R, const double* U, int64_t ldu,
                        double* Om, int64_t ld, hipStream_t s);
-// Block identity of the diagonal extraction: Om(I_t, 0:n_t) = I for leaves t.
+// Block identity of the diagonal extraction: Om(I_t, 0:n_t) = I for leaves t,
+// n_max columns; or only its columns j0 .. j0 + nc - 1 (nc < 0: to n_max),
+// written to columns 0 .. nc - 1 of Om.
 void launch_block_eye(const Node* nodes, const int32_t* leaves, int nleaves,
-                      int64_t max_rows, int nmax, double* Om, int64_t ld, hipStream_t s);
+                      int64_t max_rows, int nmax, double* Om, int64_t ld, hipStream_t s,
+                      int j0 = 0, int nc = -1);
 
 // Zero D(I_t, n_t : nmax) of leaves smaller than nmax.
 void launch_zero_dpad(const Node* nodes, const int32_t* leaves, int nleaves, int64_t max_rows,

@@ -489,8 +489,10 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
   }
   const int cmax = sampler_max_cols(2);
   // The block-identity product of the diagonal step does not depend on the
-  // peeling either; for the same sampler it rides with the last level's
-  // second product when every instance peels down to that level.
+  // peeling either; for the same sampler it rides with second products when
+  // every instance peels down to the last level: split over the spare
+  // columns of the narrow calls (second products that carry nothing else)
+  // when these hold it, else with the last level's second product.
   bool fuse_diag = bf16_kernel && Lmax >= 1 && 2 * R + nmax <= cmax;
   for (const Instance& in : f.inst) fuse_diag &= in.L == Lmax;
   const int32_t* d_leaves = kp.put(f.leaves, s);
@@ -501,18 +503,20 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
   // (N x width of Omega and of Y).  Per level l: fw/fc, window and first
   // column of its first product; ng, first products its first call takes
   // (0: no such call); sw/sc, window and column of its second product
-  // (followed by the block identity on the last level when fused, then by
-  // nr first products of levels rf ..).  A window is taken again once every
-  // level that reads it is done; a level reads its first product before its
-  // second call is enqueued, so a second product that carries nothing else
-  // takes the first product's columns.
+  // (followed by ec[l] columns e0[l] .. of the block identity, copied into D
+  // after the call, then by nr first products of levels rf ..).  A window is
+  // taken again once every level that reads it is done; a level reads its
+  // first product before its second call is enqueued, so a second product
+  // that carries nothing else takes the first product's columns.
   struct Plan {
-    std::vector<int> fw, fc, ng, sw, sc, nr, rf;
+    std::vector<int> fw, fc, ng, sw, sc, nr, rf, ec, e0;
     int nwin = 1, width = 0;
   };
-  auto plan_calls = [&](int gfirst, bool ride) {
+  auto plan_calls = [&](int gfirst, bool ride, const std::vector<int>& ec) {
     Plan p;
-    for (auto* v : {&p.fw, &p.fc, &p.ng, &p.sw, &p.sc, &p.nr, &p.rf}) v->assign(Lmax, 0);
+    for (auto* v : {&p.fw, &p.fc, &p.ng, &p.sw, &p.sc, &p.nr, &p.rf, &p.e0}) v->assign(Lmax, 0);
+    p.ec = ec;
+    for (int l = 1; l < Lmax; ++l) p.e0[l] = p.e0[l - 1] + ec[l - 1];
     std::vector<int> busy;   // last level reading each window (Lmax: the diagonal step)
     auto take = [&busy](int from, int last) {   // a window no level >= from reads
       for (size_t w = 0; w < busy.size(); ++w)
@@ -536,15 +540,14 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
         next = l + g;
         p.width = std::max(p.width, 2 * R * g);
       }
-      const bool diag = fuse_diag && l == Lmax - 1;
-      const int c2 = 2 * R + (diag ? nmax : 0);
+      const int c2 = 2 * R + ec[l];
       const int nf = ride ? std::min(Lmax - next, std::max(0, (cmax - c2) / (2 * R))) : 0;
-      if (!diag && nf == 0) {
+      if (ec[l] == 0 && nf == 0) {
         p.sw[l] = p.fw[l];
         p.sc[l] = p.fc[l];
         continue;
       }
-      const int w = take(l + 1, diag ? Lmax : std::max(l, next + nf - 1));
+      const int w = take(l + 1, std::max(l, next + nf - 1));
       p.sw[l] = w;
       p.sc[l] = 0;
       p.nr[l] = nf;
@@ -562,15 +565,37 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
   };
   const size_t cap = (size_t)4 << 30;   // bytes of the windows (Omega plus Y)
   auto plan_bytes = [&](const Plan& p) { return (size_t)p.nwin * N * p.width * 16; };
-  Plan pl = plan_calls(1, false);
+  // block-identity columns per second call: all of them on the last level,
+  // or spread over the narrow calls' spare columns (first fit, in level order)
+  auto eye_last = [&]() {
+    std::vector<int> ec(Lmax, 0);
+    if (fuse_diag) ec[Lmax - 1] = nmax;
+    return ec;
+  };
+  auto eye_spread = [&](const Plan& p, std::vector<int>& ec) {
+    ec.assign(Lmax, 0);
+    int rem = nmax;
+    for (int l = 0; l < Lmax && rem > 0; ++l) {
+      if (p.nr[l] != 0 || 2 * R >= SMP_NARROW_BF16) continue;
+      ec[l] = std::min(rem, SMP_NARROW_BF16 - 2 * R);
+      rem -= ec[l];
+    }
+    return rem == 0;
+  };
+  Plan pl = plan_calls(1, false, eye_last());
   if (bf16_kernel && Lmax > 1 && R > 0) {
     int G = std::max(1, std::min(Lmax, cmax / (2 * R)));
-    Plan pr = plan_calls(G, true);
+    Plan pr = plan_calls(G, true, eye_last());
+    std::vector<int> ec;
+    if (fuse_diag && eye_spread(pr, ec)) {
+      Plan ps = plan_calls(G, true, ec);
+      if (plan_bytes(ps) <= cap) pr = ps;
+    }
     if (plan_bytes(pr) <= cap) {
       pl = pr;
     } else {
       while (G > 1 && (size_t)N * 2 * R * G * 16 > cap) --G;
-      pl = plan_calls(G, false);
+      pl = plan_calls(G, false, eye_last());
     }
   }
   // ---- buffers ---------------------------------------------------------------
@@ -626,8 +651,7 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
                           om + (int64_t)q * 2 * R * N, N, s);
     }
   };
-  double* diag_om = nullptr;   // the block identity and its product, when fused
-  double* diag_y = nullptr;
+  DevBuf D((size_t)N * nmax * 8);   // diagonal blocks (sampled with the peeling when fused)
   // ---- Fig. 4: peeling, level by level ------------------------------------------
   for (int l = 0; l < Lmax; ++l) {
     LevelLists& lv = LL[l];
@@ -682,18 +706,19 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
     // Gaussian blocks of the first products it carries
     om_l = om_at(pl.sw[l], pl.sc[l]);
     y_l = y_at(pl.sw[l], pl.sc[l]);
-    int c2 = 2 * R;
-    if (fuse_diag && l == Lmax - 1) {
-      diag_om = om_l + (int64_t)2 * R * N;
-      diag_y = y_l + (int64_t)2 * R * N;
-      launch_block_eye(dn, d_leaves, (int)f.leaves.size(), max_leaf, nmax, diag_om, N, s);
-      c2 = 2 * R + nmax;
-    }
+    const int ec = pl.ec[l];
+    if (ec)
+      launch_block_eye(dn, d_leaves, (int)f.leaves.size(), max_leaf, nmax,
+                       om_l + (int64_t)2 * R * N, N, s, pl.e0[l], ec);
+    int c2 = 2 * R + ec;
     if (pl.nr[l]) gauss_levels(pl.rf[l], pl.nr[l], om_l + (int64_t)c2 * N);
     c2 += 2 * R * pl.nr[l];
     launch_mask_basis(dn, di, dk, nk, lv.max_kid_rows, R, un, N, om_l, N, s);
     apply_ops(ops, f, true, c2, om_l, N, y_l, N, active);
     launch_nonfinite_check(y_l, N, c2, N, flag.as<int>(), s);
+    if (ec)
+      HIPCHK(hipMemcpyAsync(D.as<double>() + (int64_t)pl.e0[l] * N, y_l + (int64_t)2 * R * N,
+                            (size_t)N * ec * 8, hipMemcpyDeviceToDevice, s));
     if (l >= 1)
       apply_forest<double>(dn, lv.sub, hv, true, 2 * R, om_l, N, y_l, N, -1.0, 1.0,
                            ws_apply.base(), nn, s);
@@ -731,17 +756,13 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
     vc = Vleaf.as<double>();
   }
   // ---- diagonal blocks ------------------------------------------------------------
-  DevBuf D((size_t)N * nmax * 8);
   {
     const int32_t* dl = d_leaves;
     const int64_t maxl = max_leaf;
+    // every window is free now; the block identity is needed whole below
     double* om_eye = om_at(0, 0);
-    if (fuse_diag) {
-      // taken with the last second product
-      om_eye = diag_om;
-      HIPCHK(hipMemcpyAsync(D.p, diag_y, (size_t)N * nmax * 8, hipMemcpyDeviceToDevice, s));
-    } else {
-      launch_block_eye(dn, dl, (int)f.leaves.size(), maxl, nmax, om_eye, N, s);
+    launch_block_eye(dn, dl, (int)f.leaves.size(), maxl, nmax, om_eye, N, s);
+    if (!fuse_diag) {
       apply_ops(ops, f, false, nmax, om_eye, N, D.as<double>(), N, {});
       launch_nonfinite_check(D.as<double>(), N, nmax, N, flag.as<int>(), s);
     }

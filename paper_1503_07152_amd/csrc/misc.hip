@@ -268,21 +268,23 @@ void launch_mask_basis(const Node* nodes, const Instance* inst, const int32_t* k
   KCHK();
 }
 
-__global__ void k_block_eye(const Node* nodes, const int32_t* leaves, int nmax, double* Om,
+__global__ void k_block_eye(const Node* nodes, const int32_t* leaves, int j0, int nc, double* Om,
                             int64_t ld) {
   const Node nd = nodes[leaves[blockIdx.y]];
   const int64_t i = nd.lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= nd.hi) return;
   const int64_t li = i - nd.lo;
-  for (int j = 0; j < nmax; ++j) Om[i + (int64_t)j * ld] = (j == li) ? 1.0 : 0.0;
+  for (int j = 0; j < nc; ++j) Om[i + (int64_t)j * ld] = (j0 + j == li) ? 1.0 : 0.0;
 }
 
 void launch_block_eye(const Node* nodes, const int32_t* leaves, int nleaves, int64_t max_rows,
-                      int nmax, double* Om, int64_t ld, hipStream_t s) {
+                      int nmax, double* Om, int64_t ld, hipStream_t s, int j0, int nc) {
   if (nleaves <= 0) return;
+  if (nc < 0) nc = nmax - j0;
+  if (j0 < 0 || nc <= 0 || j0 + nc > nmax) return;
   const int nt = 256;
   hipLaunchKernelGGL(k_block_eye, dim3((unsigned)((max_rows + nt - 1) / nt), nleaves), dim3(nt),
-                     0, s, nodes, leaves, nmax, Om, ld);
+                     0, s, nodes, leaves, j0, nc, Om, ld);
   KCHK();
 }
 

@@ -6,6 +6,7 @@ namespace hm {
 
 constexpr int SMP_MAXC = 128;       // columns per sampler launch, F64 / F32 forms
 constexpr int SMP_MAXC_BF16 = 288;  // BF16 form (entries evaluated once for all columns)
+constexpr int SMP_NARROW_BF16 = 128;  // widest BF16 call of the narrow form (split over K)
 
 int sampler_max_cols(int mode);
 

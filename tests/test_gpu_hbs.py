@@ -188,9 +188,12 @@ def test_compress_kernel_matches_oracle_fp64(kernel, n, leaf, k, p, tol):
                                        r2["vs_oracle"] < 2.5 * ortho_err)
 
 
-@pytest.mark.parametrize("mode,tol", [(hm.HM_F64, 1e-10), (hm.HM_F32, 1e-5), (hm.HM_BF16, 5e-3)])
-def test_mixed_precision_sampling_errors(mode, tol):
-    n, leaf, k, p, seed = 2048, 128, 32, 16, 3
+# n = 4096 (L = 5): the block-identity product is split over the spare
+# columns of four narrow second-product calls
+@pytest.mark.parametrize("mode,tol,n", [(hm.HM_F64, 1e-10, 2048), (hm.HM_F32, 1e-5, 2048),
+                                        (hm.HM_BF16, 5e-3, 2048), (hm.HM_BF16, 5e-3, 4096)])
+def test_mixed_precision_sampling_errors(mode, tol, n):
+    leaf, k, p, seed = 128, 32, 16, 3
     say(f"mixed precision mode={mode} n={n}")
     P = W.fourier_curve_points(n, seed=3)
     K = oops.KernelOp(P, "near")
