@@ -151,8 +151,10 @@ void node_svd(const std::vector<SvdJob>& jobs, double* M, int64_t ldm, double* U
               hipStream_t s, int32_t* sweeps = nullptr, bool x_scaled = false);
 // Relative rank threshold of the node factorisations for samples computed in
 // `dtype` (an HM_* sample type): singular values below it are not resolved by
-// the samples.  FP64: 0 (the kernels use max(c, h) eps); FP32 and BF16: the
-// unit roundoff of the type over 16.
+// the samples.  FP64: 0 (the kernels use max(c, h) eps); FP32: 2^-24 / 16;
+// BF16: 2^-11, a quarter of the BF16 rounding unit (a sample against a
+// Gaussian column carries noise of about 2^-9 / sqrt(3) times the Frobenius
+// norm of the sampled block).
 double sample_rank_eta(int dtype);
 
 hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t flags, hipStream_t s,

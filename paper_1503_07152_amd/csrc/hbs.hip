@@ -358,7 +358,7 @@ void node_svd_gram(const std::vector<SvdJob>& jobs, const Node* dn, const int32_
 }
 
 double sample_rank_eta(int dtype) {
-  if (dtype == HM_BF16) return std::ldexp(1.0, -8) / 16.0;
+  if (dtype == HM_BF16) return std::ldexp(1.0, -8) / 8.0;
   if (dtype == HM_F32) return std::ldexp(1.0, -24) / 16.0;
   return 0.0;
 }
