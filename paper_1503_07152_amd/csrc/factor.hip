@@ -718,13 +718,15 @@ void launch_pchol(const PcholDesc* d, int n, hipStream_t s) {
 constexpr int JAC_LD = FAC_CMAX + 1;
 constexpr int JAC_G = 16;                      // lanes per pair
 constexpr int JAC_FT = FT;
-constexpr int JAC_GROUPS = JAC_FT / JAC_G;
 constexpr int JAC_RPL = FAC_CMAX / JAC_G;      // most rows per lane
-static_assert(JAC_GROUPS >= FAC_CMAX / 2, "one group per pair of a round");
+static_assert(JAC_FT / JAC_G >= FAC_CMAX / 2, "one group per pair of a round");
 
-template <int RPL>
+// JFT threads: JFT / 16 groups, each taking the pairs grp, grp + JFT / 16, ..
+// of a round in turn (the pairs of a round are disjoint)
+template <int RPL, int JFT>
 __device__ __forceinline__ int jacobi_sweeps(double* sA, double* sZ, double* sN, int h, int c,
                                              bool wantX, int* flag) {
+  constexpr int JAC_GROUPS = JFT / JAC_G;
   const int tid = threadIdx.x;
   const int grp = tid / JAC_G, gl = tid % JAC_G;
   const int n2 = c + (c & 1);
@@ -838,9 +840,15 @@ __device__ __forceinline__ int jacobi_sweeps(double* sA, double* sZ, double* sN,
 }
 
 // NEED_Z: the descriptors may accumulate rotations or form T^T W (a second
-// LDS matrix); without it (the Gram route) a workgroup takes half the LDS.
+// LDS matrix); without it (the Gram route) a workgroup takes half the LDS and
+// 512 threads (pairs beyond 32 in a second pass per round), so that two
+// workgroups fit a CU: the leaf level has more nodes than the GPU has CUs.
 template <bool NEED_Z>
-__global__ __launch_bounds__(JAC_FT) void k_jacobi(const SvdDesc* descs) {
+constexpr int jacobi_threads() { return NEED_Z ? JAC_FT : JAC_FT / 2; }
+
+template <bool NEED_Z>
+__global__ __launch_bounds__(jacobi_threads<NEED_Z>()) void k_jacobi(const SvdDesc* descs) {
+  constexpr int JFT = jacobi_threads<NEED_Z>();
   __shared__ double sA[FAC_CMAX * JAC_LD];
   __shared__ double sZ[NEED_Z ? FAC_CMAX * JAC_LD : 1];
   __shared__ double snorm[FAC_CMAX];
@@ -857,47 +865,47 @@ __global__ __launch_bounds__(JAC_FT) void k_jacobi(const SvdDesc* descs) {
   const bool wantX = d.X != nullptr;
   const bool accZ = NEED_Z && wantX && !d.xscaled && !d.gram;   // accumulate the rotations
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < h * c; idx += JAC_FT) {
+  for (int idx = tid; idx < h * c; idx += JFT) {
     const int i = idx % h, j = idx / h;
     sA[i + j * JAC_LD] = d.trans ? d.R[j + (int64_t)i * d.ldR] : d.R[i + (int64_t)j * d.ldR];
   }
   // rows h .. FAC_CMAX - 1 are zero: the sweeps read and rotate whole groups
   // of 16 rows without tests
-  for (int idx = tid; idx < (FAC_CMAX - h) * c; idx += JAC_FT) {
+  for (int idx = tid; idx < (FAC_CMAX - h) * c; idx += JFT) {
     const int i = h + idx % (FAC_CMAX - h), j = idx / (FAC_CMAX - h);
     sA[i + j * JAC_LD] = 0.0;
   }
   if (accZ)
-    for (int idx = tid; idx < c * c; idx += JAC_FT) {
+    for (int idx = tid; idx < c * c; idx += JFT) {
       const int i = idx % c, j = idx / c;
       sZ[i + j * JAC_LD] = (i == j) ? 1.0 : 0.0;
     }
   __syncthreads();
   int sweeps = 0;
   switch ((h + JAC_G - 1) / JAC_G) {
-    case 1: sweeps = jacobi_sweeps<1>(sA, sZ, sN, h, c, accZ, &flag); break;
-    case 2: sweeps = jacobi_sweeps<2>(sA, sZ, sN, h, c, accZ, &flag); break;
-    case 3: sweeps = jacobi_sweeps<3>(sA, sZ, sN, h, c, accZ, &flag); break;
-    case 4: sweeps = jacobi_sweeps<4>(sA, sZ, sN, h, c, accZ, &flag); break;
-    case 5: sweeps = jacobi_sweeps<5>(sA, sZ, sN, h, c, accZ, &flag); break;
-    case 6: sweeps = jacobi_sweeps<6>(sA, sZ, sN, h, c, accZ, &flag); break;
+    case 1: sweeps = jacobi_sweeps<1, JFT>(sA, sZ, sN, h, c, accZ, &flag); break;
+    case 2: sweeps = jacobi_sweeps<2, JFT>(sA, sZ, sN, h, c, accZ, &flag); break;
+    case 3: sweeps = jacobi_sweeps<3, JFT>(sA, sZ, sN, h, c, accZ, &flag); break;
+    case 4: sweeps = jacobi_sweeps<4, JFT>(sA, sZ, sN, h, c, accZ, &flag); break;
+    case 5: sweeps = jacobi_sweeps<5, JFT>(sA, sZ, sN, h, c, accZ, &flag); break;
+    case 6: sweeps = jacobi_sweeps<6, JFT>(sA, sZ, sN, h, c, accZ, &flag); break;
     default: break;   // h = 0: nothing to rotate
   }
   if (tid == 0 && d.sweeps) atomicMax(d.sweeps, sweeps);
-  for (int j = tid; j < c; j += JAC_FT) {
+  for (int j = tid; j < c; j += JFT) {
     double s = 0.0;
     for (int i = 0; i < h; ++i) s += sA[i + j * JAC_LD] * sA[i + j * JAC_LD];
     snorm[j] = sqrt(s);
   }
   __syncthreads();
-  for (int j = tid; j < c; j += JAC_FT) {
+  for (int j = tid; j < c; j += JFT) {
     const double sj = snorm[j];
     int rk = 0;
     for (int i2 = 0; i2 < c; ++i2) rk += (snorm[i2] > sj) || (snorm[i2] == sj && i2 < j);
     srank[j] = rk;
   }
   if (NEED_Z && wantX && !accZ && !d.gram)   // T (h x c) for X diag(s) = T^T W
-    for (int idx = tid; idx < h * c; idx += JAC_FT) {
+    for (int idx = tid; idx < h * c; idx += JFT) {
       const int i = idx % h, j = idx / h;
       sZ[i + j * JAC_LD] = d.R[i + (int64_t)j * d.ldR];
     }
@@ -907,7 +915,7 @@ __global__ __launch_bounds__(JAC_FT) void k_jacobi(const SvdDesc* descs) {
   // vectors e_j and singular value 0
   if (d.gram) {
     // x_j = P u_j: W(perm[i], rk) = a_j(i) / s_j^2, X(perm[i], rk) = a_j(i)
-    for (int e = tid; e < c * h; e += JAC_FT) {
+    for (int e = tid; e < c * h; e += JFT) {
       const int i = e % h, j = e / h;
       const int rk = srank[j];
       if (rk >= d.kout) continue;
@@ -918,19 +926,19 @@ __global__ __launch_bounds__(JAC_FT) void k_jacobi(const SvdDesc* descs) {
       d.W[pi + (int64_t)rk * d.ldW] = sj > 0.0 ? a / (sj * sj) : 0.0;
       if (wantX) d.X[pi + (int64_t)rk * d.ldX] = a;
     }
-    for (int e = tid; e < (d.kout - c) * h; e += JAC_FT) {
+    for (int e = tid; e < (d.kout - c) * h; e += JFT) {
       const int i = e % h, rk = c + e / h;
       if (i == 0) d.sv[rk] = 0.0;
       d.W[i + (int64_t)rk * d.ldW] = 0.0;
       if (wantX) d.X[i + (int64_t)rk * d.ldX] = 0.0;
     }
     // W columns kout .. wrows - 1 (a wider product shared with other nodes) are zero
-    for (int e = tid; e < (d.wrows - d.kout) * h; e += JAC_FT)
+    for (int e = tid; e < (d.wrows - d.kout) * h; e += JFT)
       d.W[e % h + (int64_t)(d.kout + e / h) * d.ldW] = 0.0;
     return;
   }
   const int rows = max(d.wrows, wantX ? d.xrows : 0);
-  for (int e = tid; e < c * rows; e += JAC_FT) {
+  for (int e = tid; e < c * rows; e += JFT) {
     const int i = e % rows, j = e / rows;
     const int rk = srank[j];
     if (rk >= d.kout) continue;
@@ -952,7 +960,7 @@ __global__ __launch_bounds__(JAC_FT) void k_jacobi(const SvdDesc* descs) {
       d.X[i + (int64_t)rk * d.ldX] = xv;
     }
   }
-  for (int e = tid; e < (d.kout - c) * rows; e += JAC_FT) {
+  for (int e = tid; e < (d.kout - c) * rows; e += JFT) {
     const int i = e % rows, rk = c + e / rows;
     if (i == 0) d.sv[rk] = 0.0;
     if (i < d.wrows) d.W[i + (int64_t)rk * d.ldW] = i == rk ? 1.0 : 0.0;
@@ -963,9 +971,9 @@ __global__ __launch_bounds__(JAC_FT) void k_jacobi(const SvdDesc* descs) {
 void launch_jacobi_svd(const SvdDesc* d, int n, hipStream_t s, bool gram_only) {
   if (n <= 0) return;
   if (gram_only)
-    hipLaunchKernelGGL(k_jacobi<false>, dim3(n), dim3(JAC_FT), 0, s, d);
+    hipLaunchKernelGGL(k_jacobi<false>, dim3(n), dim3(jacobi_threads<false>()), 0, s, d);
   else
-    hipLaunchKernelGGL(k_jacobi<true>, dim3(n), dim3(JAC_FT), 0, s, d);
+    hipLaunchKernelGGL(k_jacobi<true>, dim3(n), dim3(jacobi_threads<true>()), 0, s, d);
   KCHK();
 }
 
