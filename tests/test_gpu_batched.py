@@ -63,3 +63,27 @@ def test_batched_bf16_kernel_uneven_depths():
         e_1 = rel(h1.apply(torch.from_numpy(x)).cpu().numpy(), ref)
         print(f"  instance {i} n={n}: batched {e_b:.2e} single {e_1:.2e}", flush=True)
         assert e_b < 1e-2 and e_b < 1.5 * e_1 + 1e-4
+
+
+def test_batched_bf16_kernel_equal_depths():
+    """Built-in kernel operators sampled in BF16 over a forest of instances of
+    one depth (n = 4096, L = 5, r = 48): the second products carry first
+    products of later levels, and the block-identity product is split over
+    the spare columns of the narrow second-product calls.  Each instance must
+    reach the BF16 accuracy of its single-instance compression."""
+    n, leaf, k, p = 4096, 128, 32, 16
+    seeds = [3, 8, 13]
+    print(f"batched bf16 kernel {len(seeds)} instances n={n}", flush=True)
+    pts = [W.fourier_curve_points(n, seed=s) for s in seeds]
+    mk = lambda P: hm.KernelOperator(P, "near", 1e-3, hm.HM_BF16)
+    opts = [hm.Options(n, leaf, k, p, seed=21 + i) for i in range(len(seeds))]
+    outs = hm.hbs_compress_batched(opts, [mk(P) for P in pts])
+    for i, (P, h) in enumerate(zip(pts, outs)):
+        K = oops.KernelOp(P, "near", 1e-3)
+        x = W.gaussian((n, 3), seed=5)
+        ref = K.apply(x)
+        e_b = rel(h.apply(torch.from_numpy(x)).cpu().numpy(), ref)
+        h1 = hm.hbs_compress(opts[i], mk(P))
+        e_1 = rel(h1.apply(torch.from_numpy(x)).cpu().numpy(), ref)
+        print(f"  instance {i}: batched {e_b:.2e} single {e_1:.2e}", flush=True)
+        assert e_b < 1e-2 and e_b < 1.5 * e_1 + 1e-4
