@@ -36,6 +36,9 @@ class HBS:
         self.B = {}                      # (a, b) -> B_ab
         self.D = {}                      # leaf diagonal blocks
         self.skel_in, self.skel_out = {}, {}   # HBS-ID skeletons (global rows)
+        # pivot margins of each node's ID (lowrank.cpqr), for comparing
+        # skeletons with another implementation
+        self.gaps_in, self.gaps_out = {}, {}
         self.is_id = False
 
     # ranks ------------------------------------------------------------------
@@ -285,8 +288,10 @@ def hbs_id(h: HBS, y: dict, z: dict, rank: int | None, tol: float | None, r: int
     for t in tree.leaves():
         Ytmp = h.U[t] * y[t][None, :]
         Ztmp = h.V[t] * z[t][None, :]
-        Jin, Pin = lowrank.id_rows(Ytmp, kmax, eps)
-        Jout, Pout = lowrank.id_rows(Ztmp, kmax, eps)
+        gi, go = [], []
+        Jin, Pin = lowrank.id_rows(Ytmp, kmax, eps, gi)
+        Jout, Pout = lowrank.id_rows(Ztmp, kmax, eps, go)
+        h.gaps_in[t], h.gaps_out[t] = np.array(gi), np.array(go)
         Usamp[t] = h.U[t][Jin]
         Vsamp[t] = h.V[t][Jout]
         newU[t], newV[t] = Pin, Pout
@@ -300,8 +305,10 @@ def hbs_id(h: HBS, y: dict, z: dict, rank: int | None, tol: float | None, r: int
             kva_old = h.rank_v(a)
             Utmp = np.vstack([Usamp[a] @ h.Ut[t][:ka_old], Usamp[b] @ h.Ut[t][ka_old:]])
             Vtmp = np.vstack([Vsamp[a] @ h.Vt[t][:kva_old], Vsamp[b] @ h.Vt[t][kva_old:]])
-            Jin, Pin = lowrank.id_rows(Utmp * y[t][None, :], kmax, eps)
-            Jout, Pout = lowrank.id_rows(Vtmp * z[t][None, :], kmax, eps)
+            gi, go = [], []
+            Jin, Pin = lowrank.id_rows(Utmp * y[t][None, :], kmax, eps, gi)
+            Jout, Pout = lowrank.id_rows(Vtmp * z[t][None, :], kmax, eps, go)
+            h.gaps_in[t], h.gaps_out[t] = np.array(gi), np.array(go)
             newB[(a, b)] = Usamp[a] @ h.B[(a, b)] @ Vsamp[b].T
             newB[(b, a)] = Usamp[b] @ h.B[(b, a)] @ Vsamp[a].T
             Usamp[t] = Utmp[Jin]

@@ -45,11 +45,15 @@ def svd(A: np.ndarray, k: int | None = None, eps: float | None = None):
     return U[:, :keep], s[:keep], Vt[:keep].T
 
 
-def cpqr(M: np.ndarray, kmax: int, eps: float | None = None):
+def cpqr(M: np.ndarray, kmax: int, eps: float | None = None, gaps: list | None = None):
     """Column-pivoted Householder QR of M (m x n), at most ``kmax`` steps,
     stopping early when the largest remaining residual column norm is
     ``<= eps * |R_11|``.  Returns ``(perm, k, R)`` with ``M[:, perm] ~ Q R``,
-    R of shape (k, n) upper trapezoidal in pivoted order."""
+    R of shape (k, n) upper trapezoidal in pivoted order.
+    If ``gaps`` is a list, step j appends ``(n1 - n2) / |R_11|``, the margin
+    by which the chosen pivot's residual norm n1 beat the runner-up's n2
+    (0 with a single candidate left): a pivot decided by a margin far above
+    the rounding of the input is the same in any correct implementation."""
     A = np.array(M, dtype=np.float64, copy=True)
     m, n = A.shape
     perm = np.arange(n)
@@ -64,6 +68,9 @@ def cpqr(M: np.ndarray, kmax: int, eps: float | None = None):
             ref = nrm
         if nrm == 0.0 or (eps is not None and nrm <= eps * ref):
             break
+        if gaps is not None:
+            rest = np.delete(norms, p - j)
+            gaps.append((nrm - (rest.max() if rest.size else nrm)) / ref)
         if p != j:
             A[:, [j, p]] = A[:, [p, j]]
             perm[[j, p]] = perm[[p, j]]
@@ -82,14 +89,15 @@ def cpqr(M: np.ndarray, kmax: int, eps: float | None = None):
     return perm, k, R
 
 
-def id_rows(Y: np.ndarray, kmax: int, eps: float | None = None):
+def id_rows(Y: np.ndarray, kmax: int, eps: float | None = None, gaps: list | None = None):
     """``[T, J] = id(Y^*, .)`` of Sec. 4.3 (eq. buildTJ), in the form used to
     make interpolative bases: returns ``(J, P)`` where ``J`` lists the k
     skeleton rows of Y and ``P`` (n x k) satisfies ``Y ~ P Y[J, :]`` with
-    ``P[J, :] = I_k`` (P is the transpose of the ID's X)."""
+    ``P[J, :] = I_k`` (P is the transpose of the ID's X).  ``gaps``: see
+    ``cpqr``."""
     Mt = Y.T                                   # r x n; columns = rows of Y
     n = Mt.shape[1]
-    perm, k, R = cpqr(Mt, kmax, eps)
+    perm, k, R = cpqr(Mt, kmax, eps, gaps)
     J = perm[:k].copy()
     X = np.zeros((k, n))
     if k > 0:

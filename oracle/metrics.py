@@ -5,9 +5,6 @@
   uniformly on the sphere (normalised Gaussians from phase 1 of the counter
   stream; the paper says "uniform on the unit sphere").
 * ``rel_fro`` -- ``||X - Y||_F / ||Y||_F`` of dense matrices.
-* ``rel_fro_probe`` -- Gaussian-probe estimate of the same ratio for
-  operators too large to densify:
-  ``||M||_F^2 = E ||M g||^2`` for standard Gaussian g.
 """
 from __future__ import annotations
 
@@ -29,9 +26,3 @@ def estimate_E(apply_exact, apply_comp, n: int, seed: int = 12345,
 def rel_fro(X: np.ndarray, Y: np.ndarray) -> float:
     return float(np.linalg.norm(X - Y) / np.linalg.norm(Y))
 
-
-def rel_fro_probe(apply_x, apply_y, n: int, seed: int = 777, count: int = 64) -> float:
-    G = rng.gaussian_block(seed, 0, np.arange(n), count, phase=1)
-    a = apply_x(G)
-    b = apply_y(G)
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
