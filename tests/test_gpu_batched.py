@@ -87,3 +87,41 @@ def test_batched_bf16_kernel_equal_depths():
         e_1 = rel(h1.apply(torch.from_numpy(x)).cpu().numpy(), ref)
         print(f"  instance {i}: batched {e_b:.2e} single {e_1:.2e}", flush=True)
         assert e_b < 1e-2 and e_b < 1.5 * e_1 + 1e-4
+
+
+def c3_oversample(k, r_max=48):
+    """Oversampling of a batch instance: 10 where k + 10 fits the library's
+    sample limit r <= 48, else 48 - k (k = 39, 40)."""
+    return min(10, r_max - k)
+
+
+@pytest.mark.timeout(600)
+def test_batched_c3_instances_match_oracle():
+    """The first 32 instances of the uneven batch (N log-uniform in
+    [512, 8192] in multiples of 64, k uniform in 8..40, leaf 128, seed 2),
+    compressed together: every instance equals the oracle's compression of it
+    alone and recovers its exact-rank operator, with revealed ranks exactly
+    k at every node."""
+    specs = W.batched_instances(256, seed=2)[:32]
+    leaf = 128
+    print(f"batched C3 subset: {len(specs)} instances, total N {sum(n for n, _ in specs)}",
+          flush=True)
+    gens = [W.synthetic_hbs(n, leaf, k, seed=1000 + i) for i, (n, k) in enumerate(specs)]
+    ops_h = [hm.hm_hbs_from_generators(g) for g in gens]
+    opts = [hm.Options(n, leaf, k, c3_oversample(k), seed=2000 + i)
+            for i, (n, k) in enumerate(specs)]
+    outs = hm.hbs_compress_batched(opts, [hm.HBSOperator(h) for h in ops_h])
+    worst_or, worst_a = 0.0, 0.0
+    for i, ((n, k), g, h) in enumerate(zip(specs, gens, outs)):
+        full = ohbs.from_generators(g)
+        ho, st, _ = ohbs.compress(oops.HBSOp(full), n, leaf, k + c3_oversample(k), 2000 + i,
+                                  rank=k)
+        x = W.gaussian((n, 4), seed=3)
+        y = h.apply(torch.from_numpy(x)).cpu().numpy()
+        e_or, e_a = rel(y, ho.apply(x)), rel(y, full.apply(x))
+        worst_or, worst_a = max(worst_or, e_or), max(worst_a, e_a)
+        assert e_or < 1e-11 and e_a < 1e-11, (i, n, k, e_or, e_a)
+        inf = h.info()
+        assert inf["sample_columns"] == st.columns
+        assert inf["min_rank"] == k and inf["max_rank"] == k
+    print(f"  worst: vs oracle {worst_or:.2e}, vs A {worst_a:.2e}", flush=True)

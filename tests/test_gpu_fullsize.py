@@ -9,14 +9,26 @@ those rows against all N columns, FP64):
   matrices (wide form), and the FP64 sampler;
 * the compressed operator from BF16 and from FP64 sampling (Fig. 4 + Fig. 5),
   applied to Gaussian vectors: BF16 within its sampling precision, FP64
-  within the k = 32 truncation error (2e-7 to 3.4e-7 on this workload).
+  within the k = 32 truncation error (2e-7 to 3.4e-7 on this workload);
+* both forms (HBS-ID and orthonormal) against the FP64 oracle's compression
+  of the same workload, stored in ``tests/golden/near_n65536_oracle.npz`` by
+  ``tests/golden/make_oracle_fixture.py`` (oracle only): entry by entry on
+  1024 sampled rows x 8 probes, FP64 within the 1e-10 target or 3x the
+  oracle's own spread under 1e-13 relative sample noise, BF16 within 5e-3;
+  ranks, the skeletons over the oracle's decided pivots, and the HBS-ID
+  structure (identity rows, nested skeletons, B^skel = A(skel)).
 """
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
 
 import workloads as W
 from oracle import operators as oops
+
+import parity_util as PU
 
 pytestmark = pytest.mark.gpu
 hm = pytest.importorskip("paper_1503_07152_amd")
@@ -83,3 +95,77 @@ def test_fullsize_compress_on_sampled_rows(workload):
         print(f"  sampled-row error {e:.2e}, ranks {inf['min_rank']}..{inf['max_rank']}", flush=True)
         assert e < tol
         assert inf["min_rank"] == K and inf["max_rank"] == K
+
+
+FIXTURE = os.path.join(os.path.dirname(__file__), "golden", "near_n65536_oracle.npz")
+
+
+@pytest.fixture(scope="module")
+def oracle_fixture():
+    if not os.path.exists(FIXTURE):
+        pytest.skip("oracle fixture not generated")
+    z = np.load(FIXTURE, allow_pickle=False)
+    d = {k: z[k] for k in z.files}
+    d["meta"] = json.loads(str(d["meta"]))
+    assert d["meta"]["n"] == N and d["meta"]["k"] == K and d["meta"]["p"] == P
+    return d
+
+
+class _FixtureOracle:
+    """Skeletons and pivot margins of the stored oracle run, in the shape
+    the prefix comparison reads (pivot margins are only needed as decided
+    prefix lengths, which the fixture stores)."""
+
+    def __init__(self, d):
+        from oracle.tree import Tree
+        self.tree = Tree(N, LEAF)
+        nn = 2 ** (self.tree.L + 1)
+        self.skel_in = {t: d["skel_in"][t, :d["rank_u"][t]] for t in range(2, nn)}
+        self.skel_out = {t: d["skel_out"][t, :d["rank_v"][t]] for t in range(2, nn)}
+        # margins: 1 over the decided prefix, 0 after it
+        mk = lambda pre, rk: np.r_[np.ones(pre), np.zeros(rk - pre)]
+        self.gaps_in = {t: mk(d["prefix_in"][t], d["rank_u"][t]) for t in range(2, nn)}
+        self.gaps_out = {t: mk(d["prefix_out"][t], d["rank_v"][t]) for t in range(2, nn)}
+
+
+@pytest.mark.parametrize("dt", [hm.HM_F64, hm.HM_BF16])
+def test_fullsize_compress_matches_oracle_fixture(workload, oracle_fixture, dt):
+    P_, _, _ = workload
+    d = oracle_fixture
+    rows = d["rows"]
+    x = W.gaussian((N, d["meta"]["probes"]), seed=d["meta"]["probe_seed"])
+    scale = float(np.abs(d["y_A"]).max())
+    K_ = oops.KernelOp(P_, "near", DELTA)
+    for ortho in (False, True):
+        name = "orthonormal" if ortho else "HBS-ID"
+        key = "y_ortho" if ortho else "y_id"
+        print(f"full-size compress N={N} dtype={dt} {name} vs oracle fixture", flush=True)
+        h = hm.hbs_compress(hm.Options(N, LEAF, K, P, seed=3, orthonormal=ortho),
+                            hm.KernelOperator(P_, "near", DELTA, dt))
+        y = h.apply(torch.from_numpy(x)).cpu().numpy()[rows]
+        ref = d[key]
+        gap, gap_f = PU.max_rel(y, ref, scale), rel(y, ref)
+        spread = max(PU.max_rel(a, ref, scale) for a in d[key + "_noise"])
+        spread_f = max(rel(a, ref) for a in d[key + "_noise"])
+        print(f"  GPU vs oracle: max {gap:.2e} (Frobenius {gap_f:.2e}); oracle spread max "
+              f"{spread:.2e} (Frobenius {spread_f:.2e}); vs A: GPU {rel(y, d['y_A']):.2e}, "
+              f"oracle {rel(ref, d['y_A']):.2e}", flush=True)
+        if dt == hm.HM_F64:
+            assert gap_f < 1e-10 or (gap <= PU.SPREAD_FACTOR * spread
+                                     and gap_f <= PU.SPREAD_FACTOR * spread_f)
+        else:
+            assert gap_f < 5e-3
+        if ortho:
+            continue
+        e = h.export()
+        nn = 2 ** (e["L"] + 1)
+        assert np.array_equal(e["rank_u"][2:nn], d["rank_u"][2:nn])
+        assert np.array_equal(e["rank_v"][2:nn], d["rank_v"][2:nn])
+        err = PU.hbs_id_structure(e, K_.entries)
+        print(f"  max|B^skel - A(skel)| = {err:.2e}", flush=True)
+        assert err < (1e-8 if dt == hm.HM_F64 else 2e-2)
+        if dt == hm.HM_F64:
+            bad, cmp = PU.skeleton_prefix_mismatches(e, _FixtureOracle(d))
+            print(f"  decided skeleton prefixes equal on {cmp - len(bad)}/{cmp} nodes "
+                  f"{bad[:4]}", flush=True)
+            assert not bad

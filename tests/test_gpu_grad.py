@@ -36,7 +36,12 @@ def tensors(g, dtype=torch.float64):
     return {k: torch.from_numpy(np.ascontiguousarray(g[k])).to("cuda", dtype) for k in KEYS}
 
 
-@pytest.mark.parametrize("n,leaf,k,c", [(2048, 128, 8, 3), (1000, 64, 6, 2)])
+# (2048, 32, 32, 64/65): the shape of the benchmark's apply (k = 32, 64
+# right-hand sides, one more for a ragged column tile) at L = 6 levels:
+# two or three 32-column groups in the tree kernels and K-chunks in the
+# gradient outer products
+@pytest.mark.parametrize("n,leaf,k,c", [(2048, 128, 8, 3), (1000, 64, 6, 2), (2048, 32, 32, 64),
+                                        (2048, 32, 32, 65)])
 def test_backward_matches_reference_fp64(n, leaf, k, c):
     say(f"backward fp64 n={n} leaf={leaf} k={k} c={c}")
     g = W.synthetic_hbs(n, leaf, k, seed=3)
@@ -124,3 +129,34 @@ def test_backward_fp32_against_fp64_reference():
         e = rel(g32[kk].double().cpu().numpy(), g64[kk].cpu().numpy())
         say(f"  fp32 grad {kk}: {e:.2e}")
         assert e < 1e-5, kk
+
+
+def test_backward_fp32_full_size_against_oracle():
+    """The benchmark's shape (synthetic HBS N = 262144, leaf 128, k = 32, 64
+    FP32 right-hand sides, L = 11), checked where the oracle can follow at
+    that size: gx = A_H^* gy against the oracle's FP64 adjoint apply (Fig. 7
+    with U and V exchanged), and gD_t = gy_t x_t^T, the definition, entry by
+    entry on every leaf."""
+    from oracle import hbs as ohbs
+    n, leaf, k, c = 262144, 128, 32, 64
+    say(f"backward fp32 full size n={n} k={k} c={c}")
+    g = W.synthetic_hbs(n, leaf, k, seed=4)
+    x = W.gaussian((n, c), seed=5).astype(np.float32)
+    gy = W.gaussian((n, c), seed=6).astype(np.float32)
+    h = hm.hm_hbs_from_generators(g, dtype=hm.HM_F32)
+    gx, gr = hm.hss_apply_backward(h, torch.from_numpy(x), torch.from_numpy(gy))
+    gx = gx.double().cpu().numpy()
+    ho = ohbs.from_generators(g)
+    want = ho.apply_adjoint(gy.astype(np.float64))
+    e = rel(gx, want)
+    say(f"  gx vs oracle adjoint apply: {e:.2e}")
+    assert e < 1e-5
+    gD = gr["D"].double().cpu().numpy()
+    worst = 0.0
+    for t in ho.tree.leaves():
+        I = ho.tree.I(t)
+        m = ho.tree.size(t)
+        ref = gy[I].astype(np.float64) @ x[I].astype(np.float64).T
+        worst = max(worst, float(np.abs(gD[I, :m] - ref).max() / np.abs(ref).max()))
+    say(f"  gD max entry error {worst:.2e}")
+    assert worst < 1e-5

@@ -202,3 +202,60 @@ def test_storage_linear_in_n():
         h, _, _ = hbs.compress(operators.DenseOp(A), n, 64, r=16, seed=1, rank=8)
         per.append(h.storage_reals() / n)
     assert max(per) / min(per) < 1.15
+
+
+def _export_like(ho, R):
+    """The oracle's HBS-ID form in the layout of the library's export (heap
+    indexed, ranks padded to R), to check the parity helpers themselves."""
+    import torch
+    t_ = ho.tree
+    L, n = t_.L, t_.n
+    nn = 2 ** (L + 1)
+    U, V = np.zeros((n, R)), np.zeros((n, R))
+    Ut, Vt = np.zeros((nn, 2 * R, R)), np.zeros((nn, 2 * R, R))
+    B = np.zeros((nn, R, R))
+    ru, rv = np.zeros(nn, np.int32), np.zeros(nn, np.int32)
+    si, so = np.full((nn, R), -1, np.int32), np.full((nn, R), -1, np.int32)
+    for t in range(2, nn):
+        ru[t], rv[t] = ho.rank_u(t), ho.rank_v(t)
+        si[t, :ru[t]], so[t, :rv[t]] = ho.skel_in[t], ho.skel_out[t]
+        if t in ho.U:
+            U[t_.I(t), :ru[t]], V[t_.I(t), :rv[t]] = ho.U[t], ho.V[t]
+        else:
+            a, b = 2 * t, 2 * t + 1
+            for M, src, ka, kb in ((Ut, ho.Ut[t], ho.rank_u(a), ho.rank_u(b)),
+                                   (Vt, ho.Vt[t], ho.rank_v(a), ho.rank_v(b))):
+                M[t, :ka, :src.shape[1]] = src[:ka]
+                M[t, R:R + kb, :src.shape[1]] = src[ka:]
+        Bb = ho.B[(t ^ 1, t)]
+        B[t, :Bb.shape[0], :Bb.shape[1]] = Bb
+    T = torch.from_numpy
+    return dict(U=T(U), V=T(V), Ut=T(Ut), Vt=T(Vt), B=T(B), rank_u=ru, rank_v=rv, skel_in=si,
+                skel_out=so, L=L, R=R)
+
+
+def test_parity_helpers_accept_the_oracle_and_catch_planted_errors():
+    """The structural checks the GPU tests apply (identity rows, nested
+    skeletons, B^skel = A(skel)) and the skeleton-prefix comparison accept
+    the oracle's own exact HBS-ID, and catch a swapped skeleton and a
+    perturbed B^skel (mistakes planted in a copy of the oracle's output)."""
+    import parity_util as PU
+    n, leaf, k, p = 512, 64, 8, 6
+    g = W.synthetic_hbs(n, leaf, k, seed=3)
+    hf = hbs.from_generators(g)
+    A = hf.dense()
+    ho, _, _ = hbs.compress(operators.HBSOp(hf), n, leaf, k + p, 2, rank=k)
+    ent = lambda r, c: A[np.ix_(r, c)]
+    e = _export_like(ho, k + p)
+    assert PU.hbs_id_structure(e, ent) < 1e-12
+    assert PU.skeleton_prefix_mismatches(e, ho)[0] == []
+    e2 = _export_like(ho, k + p)
+    e2["B"][5, 0, 0] += 1e-6 * float(np.abs(A).max())
+    assert PU.hbs_id_structure(e2, ent) > 1e-7
+    e3 = _export_like(ho, k + p)
+    leaf0 = 2 ** ho.tree.L
+    e3["skel_in"][leaf0, [0, 1]] = e3["skel_in"][leaf0, [1, 0]]
+    bad, _ = PU.skeleton_prefix_mismatches(e3, ho)
+    assert bad and bad[0][1] == leaf0
+    with pytest.raises(AssertionError):
+        PU.hbs_id_structure(e3, ent)
