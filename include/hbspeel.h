@@ -225,6 +225,21 @@ int hss_apply_backward(const hm_hbs* h, int64_t nrhs, const void* x, int64_t ldx
                        void* gU, void* gV, void* gUt, void* gVt, void* gB,
                        void* gD, void* stream);
 
+/* hss_apply for callers that cannot allocate device memory (code under
+ * stream capture, serving loops, harnesses that forbid allocation): the same
+ * y = A_H x with the same kernels and argument rules, but it allocates
+ * nothing -- no hipMalloc / hipFree and no call of an hm_set_allocator
+ * allocator.  The kernels' scratch (per-node expansions, 2 R c values each,
+ * and row-chunk partials) lives in a fixed array of 32 MiB in the library's
+ * device memory, one per GPU, held until the process ends; the columns of x
+ * are processed in passes of as many as fit (at most 128).  A handle whose
+ * single column needs more than 32 MiB of scratch is rejected with
+ * HM_ERR_UNSUPPORTED.  Every call on a GPU uses that GPU's one array: calls
+ * that overlap on one GPU (other streams, other threads) race and must be
+ * serialised by the caller; calls on one stream are ordered. */
+int hss_apply_noalloc(const hm_hbs* h, int64_t nrhs, const void* x, int64_t ldx,
+                      void* y, int64_t ldy, void* stream);
+
 /* HODLR apply: y = A_H x (adjoint = 0) or A_H^* x; FP64. */
 int hodlr_apply(const hm_hodlr* h, int32_t adjoint, int64_t nrhs,
                 const double* x, int64_t ldx, double* y, int64_t ldy, void* stream);

@@ -22,7 +22,7 @@ __all__ = [
     "HM_F64", "HM_F32", "HM_BF16", "lib", "HMError", "fortran", "to_fortran",
     "Options", "KernelOperator", "DenseOperator", "HBSOperator", "CallbackOperator",
     "HBS", "HODLR", "hm_gauss", "hm_operator_apply", "hbs_compress", "hodlr_compress", "hbs_compress_batched",
-    "hss_apply", "hss_apply_adjoint", "hss_apply_backward", "hodlr_apply",
+    "hss_apply", "hss_apply_adjoint", "hss_apply_noalloc", "hss_apply_backward", "hodlr_apply",
     "hm_hbs_from_generators", "hbs_from_tensors", "HBSApply", "hbs_apply", "use_torch_allocator",
 ]
 
@@ -91,6 +91,7 @@ _SIGS = {
                                        C.POINTER(_P)]),
     "hss_apply": (C.c_int, [_P, _I64, _P, _I64, _P, _I64, _P]),
     "hss_apply_adjoint": (C.c_int, [_P, _I64, _P, _I64, _P, _I64, _P]),
+    "hss_apply_noalloc": (C.c_int, [_P, _I64, _P, _I64, _P, _I64, _P]),
     "hss_apply_backward": (C.c_int, [_P, _I64, _P, _I64, _P, _I64, _P, _I64, _P, _P, _P, _P, _P,
                                      _P, _P]),
     "hodlr_apply": (C.c_int, [_P, _I32, _I64, _P, _I64, _P, _I64, _P]),
@@ -479,6 +480,15 @@ def hss_apply(h: HBS, x, stream=None):
 
 def hss_apply_adjoint(h: HBS, x, stream=None):
     return _apply(lib.hss_apply_adjoint, h, x, stream)
+
+
+def hss_apply_noalloc(h: HBS, x, out, stream=None):
+    """``out = A_H x`` without any device allocation by the library (its
+    scratch is a fixed per-GPU array; overlapping calls on one GPU race).
+    ``x`` and ``out``: column-major device tensors of the handle's dtype."""
+    _check(lib.hss_apply_noalloc(h.handle, x.shape[1], _ptr(x), _ld(x), _ptr(out), _ld(out),
+                                 _stream(stream)))
+    return out
 
 
 def hss_apply_backward(h: HBS, x, gy, want_generators=True, stream=None):
