@@ -5,18 +5,24 @@ matrix A(i,j) = 1/(|x_i - x_j| + 1e-3) on N = 65536 points of a smooth
 random-Fourier closed curve (8 modes, amplitude 0.2, seed 3), leaf 128
 (L = 9 levels), rank k = 32, oversampling p = 16 (r = 48 samples per level),
 HBS-ID output.  The operator is sampled on BF16 MFMA with FP32 accumulation;
-node factorisations (Householder TSQR, Jacobi SVD, pivoted-QR ID) run in FP64.
+node factorisations (Gram/Householder, Jacobi SVD, pivoted-QR ID) run in FP64.
 
 One step = one full ``hbs_compress`` call (test matrices, operator samples,
 telescoping subtraction, node factorisations, transfers, diagonal blocks,
 HBS-ID sweep) with the points already resident in HBM.
 
-Reported: ``value`` = GFLOP/s of the compression, counting the operator
-products as dense N x N x c products (2 N^2 per sampled column, the paper's
-T_mult cost) plus nothing else (the net factorisation work is ~1% and is not
-counted); compress seconds of the BF16, FP32 and FP64 forms; accuracy of each
-form on sampled rows against the exact matrix; the dominant kernel's
-roofline; the CPU oracle on a bounded sample of the same products.
+Reported: ``value`` = GFLOP/s of the compression counting the method's own
+operator work: each structured test block [Omega_2 | Omega_1] of 2r columns
+has N/2 nonzero rows per column (N^2 flops per column), 4 r L such columns in
+all, plus the block identity (2 N^2 in all): (4 r L + 2) N^2 flops per step
+(the net factorisation work, ~1 %, is not counted); the dense-equivalent
+figure (2 N^2 per sampled column) is reported beside it.  Compress seconds of
+the BF16, FP32 and FP64 forms (median of timed calls after a warm-up call);
+accuracy of each form against the FP64 oracle's compression of the same
+workload (``tests/golden/near_n65536_oracle.npz``, written by the oracle) and
+against the exact matrix on sampled rows; the dominant kernel's roofline;
+the differentiation, synthetic-HBS and batched workloads; the CPU oracle's
+full compression of the same workload at N = 32768.
 """
 from __future__ import annotations
 
@@ -48,26 +54,29 @@ PEAK_ALU_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
 # packed BF16 conversion = 13.5 slots
 SLOTS_PER_ENTRY = 13.5
 
-# HBM bytes of one BF16 operator apply (k_pack + k_sampler + k_sum_parts,
-# N = 65536, 96 columns) from two rocprofv3 --pmc passes (FETCH_SIZE,
-# WRITE_SIZE in KiB per dispatch, summed over the three kernels), scaled by
-# what the same counters read for a plain 256 MiB device copy (FETCH_SIZE
-# reads 0.5x the bytes moved, WRITE_SIZE 1.0x).  Most of it is the three
-# K-split partial products (written, read back, summed).  Valid only for the
-# sampler source they were taken on (SHA-1 below); otherwise unknown.
-SAMPLER_TRAFFIC = {"sha1": "ccd8b683386b3325e55a31dcc936cac39c3c7669",
-                   "fetch_kib": 24590.8 + 96446.5 + 73746.7,
-                   "write_kib": 12320.0 + 148705.4 + 49152.0,
-                   "fetch_scale": 2.0, "write_scale": 1.0}
+# HBM bytes of one BF16 operator apply at N = 65536 from two rocprofv3 --pmc
+# passes (FETCH_SIZE, WRITE_SIZE in KiB per dispatch, summed over the kernels
+# of the call), scaled by what the same counters read for a plain 256 MiB
+# device copy (FETCH_SIZE reads 0.5x the bytes moved, WRITE_SIZE 1.0x).
+# Valid only for the sampler source they were taken on (SHA-1); otherwise
+# reported as unknown (null).
+SAMPLER_TRAFFIC = {
+    96: {"sha1": "ccd8b683386b3325e55a31dcc936cac39c3c7669",
+         "fetch_kib": 24590.8 + 96446.5 + 73746.7,
+         "write_kib": 12320.0 + 148705.4 + 49152.0,
+         "fetch_scale": 2.0, "write_scale": 1.0},
+}
 
 
-def sampler_traffic_bytes():
+def sampler_traffic_bytes(c):
     import hashlib
+    t = SAMPLER_TRAFFIC.get(c)
+    if t is None:
+        return None
     src = os.path.join(ROOT, "paper_1503_07152_amd", "csrc", "sampler.hip")
     with open(src, "rb") as f:
-        if hashlib.sha1(f.read()).hexdigest() != SAMPLER_TRAFFIC["sha1"]:
+        if hashlib.sha1(f.read()).hexdigest() != t["sha1"]:
             return None
-    t = SAMPLER_TRAFFIC
     return int((t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024)
 
 
@@ -80,17 +89,38 @@ def sample_columns(n, leaf, r):
     return 4 * r * L + -(-n // 2 ** L)
 
 
+def method_flops(n, leaf, r):
+    """Operator work of one compression as the method defines it: the
+    structured blocks (N/2 nonzero rows per column, 4 r L columns) and the
+    block identity (one nonzero per leaf per column: 2 N^2 in all)."""
+    return (4.0 * r * levels(n, leaf) + 2.0) * float(n) * n
+
+
+def structured_block(W, n, c, nblocks, seed):
+    """A test block of `nblocks` levels' [Omega_2 | Omega_1] patterns side by
+    side (levels 0, 1, 2, ...): per 2r-column block b, rows in the first half
+    of each node at depth b+1 use the block's second half of the columns."""
+    X = W.gaussian((n, c), seed=seed)
+    w = c // nblocks
+    for b in range(nblocks):
+        odd = (np.arange(n) // (n >> (b + 1))) % 2 == 1
+        X[~odd, w * b + w // 2: w * (b + 1)] = 0.0
+        X[odd, w * b: w * b + w // 2] = 0.0
+    return X
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=N)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true",
                     help="only the timed BF16 steps (for profiling runs)")
-    ap.add_argument("--sampler-only", action="store_true",
-                    help="only the BF16 sampler on one structured N x 96 block, 3 launches "
+    ap.add_argument("--sampler-only", type=int, default=0, metavar="C",
+                    help="only the BF16 sampler on one structured N x C block (C = 96: one "
+                         "level, narrow form; 288: three levels, wide form), 3 launches "
                          "(hardware-counter runs)")
     ap.add_argument("--apply-only", action="store_true",
                     help="only the forward and backward compressed apply of the "
@@ -128,11 +158,8 @@ def main():
         return
     if args.sampler_only:
         pts = torch.from_numpy(W.fourier_curve_points(n, seed=SEED_PTS)).cuda()
-        c = 2 * r
-        X = hm.fortran(n, c)
-        X.copy_(torch.from_numpy(W.gaussian((n, c), seed=5)))
-        X[: n // 2, : c // 2] = 0.0
-        X[n // 2:, c // 2:] = 0.0
+        c = args.sampler_only
+        X = hm.to_fortran(structured_block(W, n, c, max(1, c // (2 * r)), seed=5))
         op = hm.KernelOperator(pts, "near", DELTA, hm.HM_BF16)
         for _ in range(3):
             hm.hm_operator_apply(op, X)
@@ -162,10 +189,12 @@ def main():
     ms = (t1 - t0) * 1e3 / args.steps
     cols = sample_columns(n, LEAF, r)
     assert infos[-1]["sample_columns"] == cols, (infos[-1]["sample_columns"], cols)
-    flops = 2.0 * n * n * cols
-    value = flops / (ms * 1e-3) / 1e9
-    print(f"timed: {ms:.1f} ms/step, {value:.0f} GFLOP/s; operator share "
-          f"{infos[-1]['t_operator_ms'] / infos[-1]['t_compress_ms']:.2f}", flush=True)
+    value = method_flops(n, LEAF, r) / (ms * 1e-3) / 1e9
+    dense_equiv = 2.0 * n * n * cols / (ms * 1e-3) / 1e9
+    t_net = float(np.median([i["t_compress_ms"] - i["t_operator_ms"] for i in infos]))
+    t_cmp = float(np.median([i["t_compress_ms"] for i in infos]))
+    print(f"timed: {ms:.1f} ms/step, {value:.0f} GFLOP/s (method flops), "
+          f"{dense_equiv:.0f} dense-equivalent; net share {t_net / t_cmp:.2f}", flush=True)
 
     out = {
         "metric": "HBS compress s + GFLOP/s at N=65536,k=32 vs FP64 GPU; rel error; bwd apply GB/s",
@@ -178,94 +207,130 @@ def main():
                                "sampling, FP64 factorisations",
                    "n": n, "leaf": LEAF, "rank": K, "oversample": P,
                    "levels": levels(n, LEAF), "sample_columns": cols},
+        "flop_model": "(4 r L + 2) N^2 per compress: structured test blocks with N/2 nonzero "
+                      "rows per column, plus the block identity",
+        "dense_equiv_GFLOPs": round(dense_equiv, 1),
         "compress_s_bf16": round(ms / 1e3, 4),
-        "t_net_s_bf16": round((infos[-1]["t_compress_ms"] - infos[-1]["t_operator_ms"]) / 1e3, 4),
+        "t_net_s_bf16": round(t_net / 1e3, 4),
+        "net_share_bf16": round(t_net / t_cmp, 3),
+        "operator_calls_bf16": infos[-1]["operator_calls"],
         "jacobi_sweeps_max": infos[-1]["jacobi_sweeps"],
     }
     if not args.no_extra:
         out.update(extra_measurements(hm, W, torch, pts, n, h, ms))
         out.update(backward_measurement(hm, W, torch))
+        out.update(synthetic_hbs_measurement(hm, W, torch))
         out.update(batched_measurement(hm, W, torch))
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(W, n)
+        out["cpu_baseline"] = cpu_baseline(W)
+        out["cpu_product_sample"] = cpu_product_sample(W, n)
     print(json.dumps(out), flush=True)
+
+
+def _median_compress(hm, torch, opts, op, calls):
+    """Median wall time of `calls` compress calls after one warm-up call
+    (first launches of each kernel, workspace growth)."""
+    h = hm.hbs_compress(opts, op)
+    del h
+    ts = []
+    for _ in range(calls):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = hm.hbs_compress(opts, op)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts)), h
+
+
+def _event_time(torch, s, fn, reps):
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    e0.record(s)
+    for _ in range(reps):
+        fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps * 1e-3
 
 
 def extra_measurements(hm, W, torch, pts, n, h_bf16, ms_bf16):
     from oracle import operators as oops   # exact entries of A on sampled rows only
     res = {}
-    # ---- other precisions, one compress each ---------------------------------
+    # ---- other precisions: median of 10 calls each after a warm-up -----------
     forms = {"bf16": h_bf16}
     times = {"bf16": ms_bf16 / 1e3}
     for name, dt in (("f32", hm.HM_F32), ("f64", hm.HM_F64)):
         op = hm.KernelOperator(pts, "near", DELTA, dt)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        hh = hm.hbs_compress(hm.Options(n, LEAF, K, P, seed=SEED), op)
-        torch.cuda.synchronize()
-        times[name] = time.perf_counter() - t0
-        forms[name] = hh
-        print(f"{name} form: {times[name] * 1e3:.1f} ms", flush=True)
+        times[name], forms[name] = _median_compress(hm, torch, hm.Options(n, LEAF, K, P, seed=SEED),
+                                                    op, 10)
+        print(f"{name} form: {times[name] * 1e3:.1f} ms (median of 10)", flush=True)
     res["compress_s_f32"] = round(times["f32"], 4)
     res["compress_s_f64"] = round(times["f64"], 4)
     res["speedup_bf16_vs_f64_gpu"] = round(times["f64"] / times["bf16"], 2)
     res["speedup_f32_vs_f64_gpu"] = round(times["f64"] / times["f32"], 2)
-    # ---- accuracy on sampled rows against the exact matrix --------------------
-    Kop = oops.KernelOp(pts.cpu().numpy(), "near", DELTA)
-    rows = np.random.default_rng(0).choice(n, 256, replace=False)
-    w = W.gaussian((n, 4), seed=21)
-    exact = Kop.entries(rows, np.arange(n)) @ w
-    for name, hh in forms.items():
-        y = hh.apply(torch.from_numpy(w)).cpu().numpy()[rows]
-        res[f"rel_err_{name}_vs_A_sampled_rows"] = float(np.linalg.norm(y - exact) /
-                                                          np.linalg.norm(exact))
-    yb = forms["bf16"].apply(torch.from_numpy(w)).cpu().numpy()
-    y64 = forms["f64"].apply(torch.from_numpy(w)).cpu().numpy()
-    y32 = forms["f32"].apply(torch.from_numpy(w)).cpu().numpy()
-    res["rel_err_bf16_vs_f64_gpu"] = float(np.linalg.norm(yb - y64) / np.linalg.norm(y64))
-    res["rel_err_f32_vs_f64_gpu"] = float(np.linalg.norm(y32 - y64) / np.linalg.norm(y64))
+    r = K + P
+    for name in ("f32", "f64"):
+        res[f"GFLOPs_{name}"] = round(method_flops(n, LEAF, r) / times[name] / 1e9, 1)
+    # ---- accuracy: against the FP64 oracle's compression of this workload
+    # (stored by the oracle) and against the exact matrix, on its sampled rows
+    fx = os.path.join(ROOT, "tests", "golden", "near_n65536_oracle.npz")
+    if n == N and os.path.exists(fx):
+        z = np.load(fx, allow_pickle=False)
+        meta = json.loads(str(z["meta"]))
+        rows = z["rows"]
+        w = W.gaussian((n, meta["probes"]), seed=meta["probe_seed"])
+        rl = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        spread = max(rl(a, z["y_id"]) for a in z["y_id_noise"])
+        for name, hh in forms.items():
+            y = hh.apply(torch.from_numpy(w)).cpu().numpy()[rows]
+            res[f"rel_err_{name}_vs_oracle"] = rl(y, z["y_id"])
+            res[f"rel_err_{name}_vs_A"] = rl(y, z["y_A"])
+        res["oracle_vs_A"] = rl(z["y_id"], z["y_A"])
+        res["oracle_rounding_spread"] = spread
+        res["accuracy_sample"] = (f"{len(rows)} sampled rows x {meta['probes']} Gaussian probes; "
+                                  "oracle spread = its change under 1e-13 relative sample noise")
+    else:
+        Kop = oops.KernelOp(pts.cpu().numpy(), "near", DELTA)
+        rows = np.random.default_rng(0).choice(n, 256, replace=False)
+        w = W.gaussian((n, 4), seed=21)
+        exact = Kop.entries(rows, np.arange(n)) @ w
+        for name, hh in forms.items():
+            y = hh.apply(torch.from_numpy(w)).cpu().numpy()[rows]
+            res[f"rel_err_{name}_vs_A"] = float(np.linalg.norm(y - exact) / np.linalg.norm(exact))
     inf = forms["bf16"].info()
     res["ranks"] = [inf["min_rank"], inf["max_rank"]]
     res["storage_reals_per_dof"] = round(inf["storage_reals"] / n, 1)
-    # ---- dominant kernel: the BF16 sampler, timed live with HIP events --------
-    c = 2 * (K + P)
-    X = hm.fortran(n, c)
-    X.copy_(torch.from_numpy(W.gaussian((n, c), seed=5)))
-    half = n // 2
-    X[:half, :c // 2] = 0.0          # structured like [Omega_2 | Omega_1]
-    X[half:, c // 2:] = 0.0
+    # ---- dominant kernel: the BF16 sampler in its wide form (three levels'
+    # test blocks, 288 columns: the calls that take most of a step), timed
+    # live with HIP events on the stream it is launched on ------------------
     s = torch.cuda.current_stream()
-    hm.hm_operator_apply(hm.KernelOperator(pts, "near", DELTA, hm.HM_BF16), X)
-    reps = 5
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     op = hm.KernelOperator(pts, "near", DELTA, hm.HM_BF16)
-    e0.record(s)
-    for _ in range(reps):
-        hm.hm_operator_apply(op, X, stream=s)
-    e1.record(s)
-    torch.cuda.synchronize()
-    t_launch = e0.elapsed_time(e1) / reps * 1e-3
     entries = float(n) * n
-    achieved = entries * SLOTS_PER_ENTRY / t_launch / 1e12
-    res["roofline"] = {"bound": "alu", "achieved": round(achieved, 2), "peak": round(PEAK_ALU_TOPS, 1),
-                       "unit": "Tslot/s", "frac": round(achieved / PEAK_ALU_TOPS, 3),
-                       "traffic": sampler_traffic_bytes() if n == N else None,
-                       "kernel": "k_sampler<BF16, near> (+ k_pack, k_sum_parts)",
-                       "launch_ms": round(t_launch * 1e3, 3),
-                       "mfma_frac": round(2 * n * (n * c / 2) / t_launch / 1e12 /
-                                          PEAK_TF["bf16"], 4)}
-    # FP64 form of the same kernel, MFMA-bound
+    for c, key in ((6 * r, "roofline"), (2 * r, "roofline_narrow_sampler")):
+        nb = c // (2 * r)
+        X = hm.to_fortran(structured_block(W, n, c, nb, seed=5))
+        t = _event_time(torch, s, lambda: hm.hm_operator_apply(op, X, stream=s), 5)
+        achieved = entries * SLOTS_PER_ENTRY / t / 1e12
+        mflops = 2.0 * entries * c / 2          # nonzero half of every structured block
+        res[key] = {"bound": "alu", "achieved": round(achieved, 2),
+                    "peak": round(PEAK_ALU_TOPS, 1), "unit": "Tslot/s",
+                    "frac": round(achieved / PEAK_ALU_TOPS, 3),
+                    "traffic": sampler_traffic_bytes(c) if n == N else None,
+                    "kernel": f"k_sampler<BF16, near> {c} columns (+ k_pack"
+                              f"{', k_sum_parts' if c <= 128 else ''})",
+                    "launch_ms": round(t * 1e3, 3),
+                    "mfma_frac": round(mflops / t / 1e12 / PEAK_TF["bf16"], 4),
+                    "algorithmic_bytes": int(2 * 8 * n * c + 8 * n)}
+        print(f"sampler {c} columns: {t * 1e3:.3f} ms, ALU frac {achieved / PEAK_ALU_TOPS:.3f}",
+              flush=True)
+    # FP64 form of the same kernel (one level), MFMA-bound
+    X = hm.to_fortran(structured_block(W, n, 2 * r, 1, seed=5))
     op64 = hm.KernelOperator(pts, "near", DELTA, hm.HM_F64)
-    hm.hm_operator_apply(op64, X, stream=s)
-    e0.record(s)
-    for _ in range(2):
-        hm.hm_operator_apply(op64, X, stream=s)
-    e1.record(s)
-    torch.cuda.synchronize()
-    t64 = e0.elapsed_time(e1) / 2 * 1e-3
-    res["roofline_f64_sampler"] = {"bound": "mfma", "achieved": round(2 * n * (n * c / 2) / t64 / 1e12, 2),
+    t64 = _event_time(torch, s, lambda: hm.hm_operator_apply(op64, X, stream=s), 2)
+    fl = 2.0 * entries * r
+    res["roofline_f64_sampler"] = {"bound": "mfma", "achieved": round(fl / t64 / 1e12, 2),
                                    "peak": PEAK_TF["f64"], "unit": "TFLOP/s",
-                                   "frac": round(2 * n * (n * c / 2) / t64 / 1e12 / PEAK_TF["f64"], 3),
+                                   "frac": round(fl / t64 / 1e12 / PEAK_TF["f64"], 3),
                                    "launch_ms": round(t64 * 1e3, 3),
                                    "note": "flops of the nonzero half of the structured block"}
     return res
@@ -282,23 +347,8 @@ def backward_measurement(hm, W, torch, n=262144, leaf=128, k=32, c=64):
     x = hm.to_fortran(torch.from_numpy(W.gaussian((n, c), seed=5, dtype=np.float32)))
     gy = hm.to_fortran(torch.from_numpy(W.gaussian((n, c), seed=6, dtype=np.float32)))
     s = torch.cuda.current_stream()
-    hm.hss_apply_backward(h, x, gy)
-    hm.hss_apply(h, x)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps = 10
-    e0.record(s)
-    for _ in range(reps):
-        hm.hss_apply_backward(h, x, gy, stream=s)
-    e1.record(s)
-    torch.cuda.synchronize()
-    tb = e0.elapsed_time(e1) / reps * 1e-3
-    e0.record(s)
-    for _ in range(reps):
-        hm.hss_apply(h, x, stream=s)
-    e1.record(s)
-    torch.cuda.synchronize()
-    tf = e0.elapsed_time(e1) / reps * 1e-3
+    tb = _event_time(torch, s, lambda: hm.hss_apply_backward(h, x, gy, stream=s), 10)
+    tf = _event_time(torch, s, lambda: hm.hss_apply(h, x, stream=s), 10)
     L = int(math.ceil(math.log2(n / leaf)))
     nn = 2 ** (L + 1)
     nmax = -(-n // 2 ** L)
@@ -311,17 +361,40 @@ def backward_measurement(hm, W, torch, n=262144, leaf=128, k=32, c=64):
     return {"bwd_apply_GBps": round(bw, 1), "bwd_apply_ms": round(tb * 1e3, 3),
             "bwd_apply_hbm_frac": round(bw / PEAK_HBM_GBS, 3),
             "fwd_apply_GBps": round(fwd_bytes / tf / 1e9, 1), "fwd_apply_ms": round(tf * 1e3, 3),
+            "fwd_apply_hbm_frac": round(fwd_bytes / tf / 1e9 / PEAK_HBM_GBS, 3),
             "apply_config": f"synthetic HBS N={n} leaf={leaf} k={k}, {c} FP32 right-hand sides"}
 
 
-def batched_measurement(hm, W, torch, count=256, leaf=128, p=8):
+def synthetic_hbs_measurement(hm, W, torch, n=16384, leaf=64, k=30, p=10):
+    """The FP64 HBS workload: synthetic HBS of rank exactly 30 with nested
+    bases (seed 1), N = 16384, leaf 64, p = 10, applied in O(N k) as the
+    black box; median of 10 compress calls, exact-recovery error on 8
+    Gaussian probes against the operator itself."""
+    g = W.synthetic_hbs(n, leaf, k, seed=1)
+    op_h = hm.hm_hbs_from_generators(g)
+    opts = hm.Options(n, leaf, k, p, seed=1)
+    t, h = _median_compress(hm, torch, opts, hm.HBSOperator(op_h), 10)
+    x = torch.from_numpy(W.gaussian((n, 8), seed=99))
+    y = h.apply(x).cpu().numpy()
+    ya = op_h.apply(x).cpu().numpy()
+    inf = h.info()
+    return {"hbs_f64_n16384_compress_s": round(t, 4),
+            "hbs_f64_n16384_t_net_s": round((inf["t_compress_ms"] - inf["t_operator_ms"]) / 1e3, 4),
+            "hbs_f64_n16384_rel_err_vs_A": float(np.linalg.norm(y - ya) / np.linalg.norm(ya)),
+            "hbs_f64_n16384_ranks": [inf["min_rank"], inf["max_rank"]],
+            "hbs_f64_n16384_config": f"synthetic HBS N={n} leaf={leaf} k={k} p={p}, FP64"}
+
+
+def batched_measurement(hm, W, torch, count=256, leaf=128):
     """Many uneven instances: N_i log-uniform in [512, 8192] (multiples of 64),
-    k_i uniform in [8, 40] (seed 2), synthetic HBS operators; one batched call
-    against one call per instance."""
+    k_i uniform in [8, 40] (seed 2), synthetic HBS operators, p_i = min(10,
+    48 - k_i), factors stored in FP32; one batched call against one call per
+    instance; exact-recovery error of every instance on 4 Gaussian probes."""
     specs = W.batched_instances(count, seed=2)
     ops_h = [hm.hm_hbs_from_generators(W.synthetic_hbs(n, leaf, k, seed=1000 + i))
              for i, (n, k) in enumerate(specs)]
-    opts = [hm.Options(n, leaf, k, p, seed=2 + i) for i, (n, k) in enumerate(specs)]
+    opts = [hm.Options(n, leaf, k, min(10, 48 - k), seed=2000 + i, store_dtype=hm.HM_F32)
+            for i, (n, k) in enumerate(specs)]
     ops = [hm.HBSOperator(h) for h in ops_h]
     hm.hbs_compress_batched(opts[:8], ops[:8])
     torch.cuda.synchronize()
@@ -329,6 +402,12 @@ def batched_measurement(hm, W, torch, count=256, leaf=128, p=8):
     outs = hm.hbs_compress_batched(opts, ops)
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
+    errs = []
+    for (n, _), hh, ho in zip(specs, outs, ops_h):
+        x = torch.from_numpy(W.gaussian((n, 4), seed=3))
+        y = hh.apply(x).double()
+        ya = ho.apply(x)
+        errs.append(float(torch.linalg.norm(y - ya) / torch.linalg.norm(ya)))
     del outs
     t0 = time.perf_counter()
     for o, op in zip(opts, ops):
@@ -338,36 +417,59 @@ def batched_measurement(hm, W, torch, count=256, leaf=128, p=8):
     ts = time.perf_counter() - t0
     return {"batched_instances": count, "batched_total_n": int(sum(n for n, _ in specs)),
             "batched_s": round(tb, 4), "batched_instances_per_s": round(count / tb, 1),
-            "sequential_s": round(ts, 4), "batched_speedup": round(ts / tb, 2)}
+            "sequential_s": round(ts, 4), "batched_speedup": round(ts / tb, 2),
+            "batched_rel_err_max": max(errs), "batched_rel_err_median": float(np.median(errs)),
+            "batched_storage": "fp32"}
 
 
-def cpu_baseline(W, n):
-    """The FP64 oracle's operator product (the dominant step of the
-    compression) on a bounded sample: 1024 of the N rows against all N columns
-    and 96 sampled columns; scaled to GFLOP/s with the same 2 N^2 per column
-    count as ``value``."""
-    from oracle import operators as oops
+def _threads():
     try:
         from threadpoolctl import threadpool_info
-        threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+        return max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
     except Exception:  # noqa: BLE001
-        threads = 1
+        return 1
+
+
+def cpu_baseline(W, n=32768):
+    """The FP64 oracle's full compression (Fig. 4 + Fig. 5, NumPy/LAPACK) of
+    the benchmark workload at N = 32768 (same curve law, kernel, leaf, k, p,
+    seeds; L = 8), one run, on the host's cores (row tiles of the kernel
+    product on one thread each, BLAS single-threaded inside them); GFLOP/s by
+    the same method flop count as ``value``."""
+    from oracle import hbs as ohbs
+    from oracle import operators as oops
+    from threadpoolctl import threadpool_limits
+    cores = len(os.sched_getaffinity(0))
     pts = W.fourier_curve_points(n, seed=SEED_PTS)
-    Kop = oops.KernelOp(pts, "near", DELTA, tile=256)
+    op = oops.KernelOp(pts, "near", DELTA, workers=cores)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        ohbs.compress(op, n, LEAF, K + P, SEED, rank=K)
+        dt = time.perf_counter() - t0
+    return {"value": round(method_flops(n, LEAF, K + P) / dt / 1e9, 2), "unit": "GFLOP/s",
+            "cores": cores, "kind": "oracle",
+            "sample": f"oracle's full HBS-ID compression of the benchmark workload at N={n} "
+                      f"(leaf {LEAF}, k {K}, p {P}; {dt:.1f} s, {cores} threads); FP64 NumPy"}
+
+
+def cpu_product_sample(W, n):
+    """The oracle's operator product (the dominant step) on a bounded sample:
+    1024 of the N rows against all N columns and 96 columns, in GFLOP/s of
+    a dense product."""
+    from oracle import operators as oops
+    pts = W.fourier_curve_points(n, seed=SEED_PTS)
     X = W.gaussian((n, 96), seed=5)
-    rows = 1024
     sub = oops.KernelOp(pts, "near", DELTA, tile=256)
     t0 = time.perf_counter()
     done = 0
-    for i0 in range(0, rows, 256):
-        idx = np.arange(i0, min(i0 + 256, rows))
+    for i0 in range(0, 1024, 256):
+        idx = np.arange(i0, min(i0 + 256, 1024))
         _ = sub.entries(idx, np.arange(n)) @ X
         done += len(idx)
     dt = time.perf_counter() - t0
-    gflops = 2.0 * done * n * 96 / dt / 1e9
-    return {"value": round(gflops, 2), "unit": "GFLOP/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"oracle kernel-matrix product, {done} of {n} rows x {n} columns x 96 "
-                      f"columns ({dt:.1f} s); FP64 NumPy"}
+    return {"value": round(2.0 * done * n * 96 / dt / 1e9, 2), "unit": "GFLOP/s",
+            "cores": int(_threads()),
+            "sample": f"{done} of {n} rows x {n} columns x 96 columns ({dt:.1f} s)"}
 
 
 if __name__ == "__main__":

@@ -74,23 +74,31 @@ typedef struct hm_hodlr_s hm_hodlr;
 
 /*
  * Black-box product (Sec. 1, "T_mult"; applied to N x ncols blocks as in
- * Sec. 5.3).  Must write Y = A X (adjoint = 0) or Y = A^* X (adjoint = 1),
- * X and Y FP64 device arrays (n x ncols, column-major, leading dims ldx, ldy)
- * owned by the library for the duration of the call.  The work must be
- * enqueued on `stream` (a hipStream_t) or finished before returning; the
- * pointers must not be kept.  Return 0 on success; any other value aborts
- * the compression with HM_ERR_CALLBACK.
+ * Sec. 5.3).  Must write Y = A X (adjoint = 0) or Y = A^* X (adjoint = 1) for
+ * X, Y device arrays (n x ncols, column-major, leading dims ldx, ldy) owned by
+ * the library for the duration of the call.  `dtype` is the operator's
+ * sample_dtype and fixes the element types:
+ *   HM_F64   X double, Y double
+ *   HM_F32   X float,  Y float
+ *   HM_BF16  X bfloat16 (uint16 bit patterns), Y float (FP32 accumulation)
+ * The library rounds its FP64 test block to the sample type (round to nearest
+ * even) and reads Y back into FP64 samples; node factorisations stay FP64.
+ * The work must be enqueued on `stream` (a hipStream_t) or finished before
+ * returning; the pointers must not be kept.  Return 0 on success; any other
+ * value aborts the compression with HM_ERR_CALLBACK.
  */
 typedef int (*hm_matvec_fn)(void* user, int adjoint, int64_t n, int64_t ncols,
-                            const double* X, int64_t ldx, double* Y, int64_t ldy,
-                            void* stream);
+                            const void* X, int64_t ldx, void* Y, int64_t ldy,
+                            int32_t dtype, void* stream);
 
 typedef struct hm_operator {
   int32_t kind;          /* HM_OP_*                                              */
-  int32_t sample_dtype;  /* HM_OP_KERNEL: precision of the sampling product:
+  int32_t sample_dtype;  /* precision of the sampling product, HM_OP_KERNEL:
                             HM_F64 (FP64 MFMA), HM_F32 (FP32 MFMA),
-                            HM_BF16 (BF16 MFMA, FP32 accumulation).  The samples
-                            are returned in FP64 in every case.                 */
+                            HM_BF16 (BF16 MFMA, FP32 accumulation);
+                            HM_OP_CALLBACK: the types the callback receives
+                            (see hm_matvec_fn).  The samples are returned in
+                            FP64 in every case.                                 */
   hm_matvec_fn fn;       /* HM_OP_CALLBACK                                       */
   void* user;            /* HM_OP_CALLBACK: passed back to fn                    */
   const double* points;  /* HM_OP_KERNEL: device, n points as (x0,y0,x1,y1,...)  */
@@ -115,6 +123,9 @@ typedef struct hm_options {
                            |R_jj| > eps |R_11|); 0 selects fixed rank k          */
   uint64_t seed;        /* key of the Philox4x32-10 Gaussian stream               */
   int32_t flags;        /* HM_FLAG_*                                             */
+  int32_t store_dtype;  /* HBS handles: HM_F64 (default) or HM_F32 -- the node
+                           factorisations run in FP64, the resulting generators
+                           are stored (and applied) in this type.  HODLR: HM_F64 */
 } hm_options;
 
 typedef struct hm_info {
@@ -259,7 +270,9 @@ int hm_hbs_from_generators(int64_t n, int64_t leaf_size, int32_t k, int32_t dtyp
                            const void* U, const void* V, const void* Ut,
                            const void* Vt, const void* B, const void* D,
                            void* stream, hm_hbs** out);
-/* Copy of a handle converted to another storage dtype (HM_F64 / HM_F32). */
+/* Copy of a handle with its generators converted to another storage dtype
+ * (HM_F64 / HM_F32, rounded to nearest); structure, ranks and skeletons are
+ * kept.  The copy is complete when the call returns. */
 int hm_hbs_convert(const hm_hbs* h, int32_t dtype, void* stream, hm_hbs** out);
 int hm_hbs_info(const hm_hbs* h, hm_info* host_out);
 /* Device views of the generators of an HBS matrix (Sec. 2.9: leaf bases U_t,

@@ -42,7 +42,7 @@ if not os.path.exists(_LIB_PATH):
 lib = C.CDLL(_LIB_PATH)
 
 MATVEC = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.c_int64, C.c_int64, C.c_void_p, C.c_int64,
-                     C.c_void_p, C.c_int64, C.c_void_p)
+                     C.c_void_p, C.c_int64, C.c_int32, C.c_void_p)
 
 
 class _Operator(C.Structure):
@@ -55,7 +55,7 @@ class _Operator(C.Structure):
 class _Options(C.Structure):
     _fields_ = [("n", C.c_int64), ("leaf_size", C.c_int64), ("rank", C.c_int32),
                 ("oversample", C.c_int32), ("tol", C.c_double), ("seed", C.c_uint64),
-                ("flags", C.c_int32)]
+                ("flags", C.c_int32), ("store_dtype", C.c_int32)]
 
 
 class _Info(C.Structure):
@@ -160,9 +160,10 @@ def _ld(t):
 
 
 class Options:
-    def __init__(self, n, leaf_size, rank, oversample=10, tol=0.0, seed=0, orthonormal=False):
+    def __init__(self, n, leaf_size, rank, oversample=10, tol=0.0, seed=0, orthonormal=False,
+                 store_dtype=HM_F64):
         self.c = _Options(n, leaf_size, rank, oversample, tol, seed,
-                          HM_FLAG_ORTHONORMAL if orthonormal else 0)
+                          HM_FLAG_ORTHONORMAL if orthonormal else 0, store_dtype)
 
 
 class KernelOperator:
@@ -200,24 +201,35 @@ class HBSOperator:
 class _DevArray:
     """Raw device buffer seen by torch through __cuda_array_interface__."""
 
-    def __init__(self, ptr, rows, cols, ld):
+    def __init__(self, ptr, rows, cols, ld, typestr="<f8"):
         self.__cuda_array_interface__ = {
-            "shape": (cols, ld), "typestr": "<f8", "data": (ptr, False), "version": 2,
+            "shape": (cols, ld), "typestr": typestr, "data": (ptr, False), "version": 2,
             "strides": None}
+
+
+# element types of the callback's X and Y per sample dtype (BF16 bit
+# patterns travel as int16 and are viewed as bfloat16)
+_CB_TYPES = {HM_F64: ("<f8", "<f8", None), HM_F32: ("<f4", "<f4", None),
+             HM_BF16: ("<i2", "<f4", torch.bfloat16)}
 
 
 class CallbackOperator:
     """User black box: ``fn(adjoint: bool, X, Y)`` with X, Y n x c column-major
-    float64 tensors that alias library buffers; must write ``Y = A X`` (or
-    ``A^* X``) on the current stream and return None (or 0)."""
+    device tensors that alias library buffers; must write ``Y = A X`` (or
+    ``A^* X``) on the current stream and return None (or 0).  ``sample_dtype``
+    sets their types: HM_F64 (float64 / float64), HM_F32 (float32 / float32),
+    HM_BF16 (X bfloat16, Y float32)."""
 
-    def __init__(self, fn):
+    def __init__(self, fn, sample_dtype=HM_F64):
         self.fn = fn
 
-        def tramp(user, adjoint, n, ncols, X, ldx, Y, ldy, stream):
+        def tramp(user, adjoint, n, ncols, X, ldx, Y, ldy, dtype, stream):
             try:
-                Xt = torch.as_tensor(_DevArray(X, n, ncols, ldx), device="cuda").t()[:n]
-                Yt = torch.as_tensor(_DevArray(Y, n, ncols, ldy), device="cuda").t()[:n]
+                tx, ty, view = _CB_TYPES[dtype]
+                Xt = torch.as_tensor(_DevArray(X, n, ncols, ldx, tx), device="cuda").t()[:n]
+                if view is not None:
+                    Xt = Xt.view(view)
+                Yt = torch.as_tensor(_DevArray(Y, n, ncols, ldy, ty), device="cuda").t()[:n]
                 rc = self.fn(bool(adjoint), Xt, Yt)
                 return int(rc or 0)
             except Exception:  # noqa: BLE001 -- a failing callback aborts the compression
@@ -226,6 +238,7 @@ class CallbackOperator:
         self._tramp = MATVEC(tramp)
         self.c = _Operator()
         self.c.kind = HM_OP_CALLBACK
+        self.c.sample_dtype = sample_dtype
         self.c.fn = self._tramp
 
 
@@ -374,6 +387,12 @@ class HBS:
             B=_alias(self, v.B, (nn, R, R), (R * R, 1, R), dt),
             D=_alias(self, v.D, (n, v.nmax), (1, n), dt),
             n=n, R=R, L=v.levels, nodes=nn)
+
+    def convert(self, dtype, stream=None):
+        """Copy with the generators stored in ``dtype`` (HM_F64 / HM_F32)."""
+        h = C.c_void_p()
+        _check(lib.hm_hbs_convert(self.handle, dtype, _stream(stream), C.byref(h)))
+        return HBS(h)
 
     @staticmethod
     def _nmax(n, leaf, L):

@@ -36,6 +36,8 @@ void check_options(const hm_options* o) {
     HM_THROW(HM_ERR_UNSUPPORTED, "rank + oversample = %d > %d", o->rank + o->oversample,
              HM_MAX_SAMPLES);
   if (o->n > ((int64_t)1 << 31)) HM_THROW(HM_ERR_UNSUPPORTED, "n > 2^31");
+  if (o->store_dtype != HM_F64 && o->store_dtype != HM_F32)
+    HM_THROW(HM_ERR_ARG, "store_dtype = %d (HM_F64 or HM_F32)", o->store_dtype);
   if (o->n > o->leaf_size && o->leaf_size > 256)
     HM_THROW(HM_ERR_UNSUPPORTED, "leaf_size %lld > 256", (long long)o->leaf_size);
 }
@@ -46,6 +48,8 @@ void check_operator(const hm_operator* op, int64_t n, bool builtin_only) {
     case HM_OP_CALLBACK:
       if (builtin_only) HM_THROW(HM_ERR_ARG, "callback operators are not allowed here");
       if (!op->fn) HM_THROW(HM_ERR_ARG, "callback operator without function");
+      if (op->sample_dtype != HM_F64 && op->sample_dtype != HM_F32 && op->sample_dtype != HM_BF16)
+        HM_THROW(HM_ERR_ARG, "bad sample dtype %d", op->sample_dtype);
       break;
     case HM_OP_KERNEL:
       if (!op->points) HM_THROW(HM_ERR_ARG, "kernel operator without points");
@@ -184,9 +188,15 @@ int hbs_compress(const hm_options* opts, const hm_operator* op, void* stream, hm
     run.s = (hipStream_t)stream;
     std::vector<OpRunner*> ops{&run};
     int status = HM_OK;
-    hm_hbs_s* h = hbs_compress_forest(single_forest(opts), ops, opts->flags, (hipStream_t)stream,
-                                      &status);
-    *out = h;
+    std::unique_ptr<hm_hbs_s> h(hbs_compress_forest(single_forest(opts), ops, opts->flags,
+                                                    (hipStream_t)stream, &status));
+    if (opts->store_dtype == HM_F32) {
+      // factors computed in FP64, stored in FP32
+      const double t = h->info.t_compress_ms;
+      h.reset(convert_hbs(h.get(), HM_F32, (hipStream_t)stream));
+      h->info.t_compress_ms = t;
+    }
+    *out = h.release();
     return status;
   });
 }
@@ -205,6 +215,8 @@ int hbs_compress_batched(int32_t count, const hm_options* opts, const hm_operato
       check_options(&opts[i]);
       check_operator(&ops[i], opts[i].n, true);
       if (opts[i].flags != opts[0].flags) HM_THROW(HM_ERR_ARG, "batched: flags differ");
+      if (opts[i].store_dtype != opts[0].store_dtype)
+        HM_THROW(HM_ERR_ARG, "batched: store_dtype differs");
       all_hbs &= ops[i].kind == HM_OP_HBS;
       forest_add_tree(f, opts[i].n, opts[i].leaf_size, opts[i].rank + opts[i].oversample,
                       opts[i].rank, opts[i].oversample, opts[i].tol, opts[i].seed);
@@ -231,8 +243,18 @@ int hbs_compress_batched(int32_t count, const hm_options* opts, const hm_operato
     for (auto& r : runners) rp.push_back(r.get());
     int status = HM_OK;
     std::unique_ptr<hm_hbs_s> res(hbs_compress_forest(f, rp, opts[0].flags, s, &status));
-    std::vector<hm_hbs_s*> parts = split_hbs(res.get(), s);
-    for (int i = 0; i < count; ++i) outs[i] = parts[i];
+    std::vector<std::unique_ptr<hm_hbs_s>> parts;
+    for (hm_hbs_s* p : split_hbs(res.get(), s)) parts.emplace_back(p);
+    res.reset();
+    if (opts[0].store_dtype == HM_F32) {  // factors computed in FP64, stored in FP32
+      std::vector<std::unique_ptr<hm_hbs_s>> f64;
+      for (auto& p : parts) {
+        f64.emplace_back(p.release());
+        p.reset(convert_hbs(f64.back().get(), HM_F32, s, false));
+      }
+      HIPCHK(hipStreamSynchronize(s));   // before the FP64 sources are freed
+    }
+    for (int i = 0; i < count; ++i) outs[i] = parts[i].release();
     return status;
   });
 }
@@ -244,6 +266,7 @@ int hodlr_compress(const hm_options* opts, const hm_operator* op, void* stream, 
     if (!out) HM_THROW(HM_ERR_ARG, "out is NULL");
     check_options(opts);
     check_operator(op, opts->n, false);
+    if (opts->store_dtype != HM_F64) HM_THROW(HM_ERR_ARG, "HODLR handles are stored in FP64");
     OpRunner run;
     run.op = *op;
     run.hbs = op->kind == HM_OP_HBS ? op->hbs : nullptr;
@@ -363,7 +386,9 @@ int hm_hbs_convert(const hm_hbs* h, int32_t dtype, void* stream, hm_hbs** out) {
   return guarded([&]() -> int {
     StreamScope scope(stream);
     if (!h || !out) HM_THROW(HM_ERR_ARG, "convert: bad arguments");
-    HM_THROW(HM_ERR_UNSUPPORTED, "conversion is not built yet");
+    if (dtype != HM_F64 && dtype != HM_F32) HM_THROW(HM_ERR_ARG, "convert: dtype must be F64 or F32");
+    *out = convert_hbs(h, dtype, (hipStream_t)stream);
+    return HM_OK;
   });
 }
 

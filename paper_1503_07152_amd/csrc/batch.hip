@@ -186,4 +186,34 @@ std::vector<hm_hbs_s*> split_hbs(const hm_hbs_s* src, hipStream_t s) {
   return res;
 }
 
+// Copy of a handle with its generators in another storage type (FP64 <->
+// FP32); structure, ranks, skeletons and statistics are kept.
+hm_hbs_s* convert_hbs(const hm_hbs_s* src, int dtype, hipStream_t s, bool sync) {
+  std::unique_ptr<hm_hbs_s> h(new hm_hbs_s());
+  h->f = src->f;
+  h->R = src->R;
+  h->dtype = dtype;
+  h->is_id = src->is_id;
+  h->d_nodes = upload(h->f.nodes, s);
+  h->d_inst = upload(h->f.inst, s);
+  const size_t es = dtype == HM_F32 ? 4 : 8;
+  const size_t ses = src->dtype == HM_F32 ? 4 : 8;
+  for (auto pr : {std::make_pair(&src->U, &h->U), std::make_pair(&src->V, &h->V),
+                  std::make_pair(&src->Ut, &h->Ut), std::make_pair(&src->Vt, &h->Vt),
+                  std::make_pair(&src->B, &h->B), std::make_pair(&src->D, &h->D)}) {
+    const int64_t cnt = (int64_t)(pr.first->bytes / ses);
+    *pr.second = DevBuf(std::max<size_t>((size_t)cnt * es, 256));
+    launch_convert(pr.first->p, src->dtype, cnt, pr.second->p, dtype, cnt, cnt, 1, s);
+  }
+  h->rank_u = src->rank_u;
+  h->rank_v = src->rank_v;
+  h->skel_in = src->skel_in;
+  h->skel_out = src->skel_out;
+  finish_lists(h.get(), s);
+  if (sync) HIPCHK(hipStreamSynchronize(s));
+  h->info = src->info;
+  h->info.dtype = dtype;
+  return h.release();
+}
+
 }  // namespace hm

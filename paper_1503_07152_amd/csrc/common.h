@@ -181,6 +181,10 @@ void launch_block_eye(const Node* nodes, const int32_t* leaves, int nleaves,
 void launch_zero_dpad(const Node* nodes, const int32_t* leaves, int nleaves, int64_t max_rows,
                       int nmax, double* D, int64_t ld, hipStream_t s);
 void launch_fill(double* p, int64_t rows, int64_t cols, int64_t ld, double v, hipStream_t s);
+// dst (rows x cols, type ddt, ld ldd) = src (type sdt, ld lds); HM_F64 / HM_F32
+// sources, HM_F64 / HM_F32 / HM_BF16 destinations.
+void launch_convert(const void* src, int sdt, int64_t lds, void* dst, int ddt, int64_t ldd,
+                    int64_t rows, int64_t cols, hipStream_t s);
 void launch_fill_f(float* p, int64_t count, float v, hipStream_t s);
 void launch_nonfinite_check(const double* p, int64_t rows, int64_t cols, int64_t ld,
                             int* flag, hipStream_t s);

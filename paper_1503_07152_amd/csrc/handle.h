@@ -117,7 +117,9 @@ struct OpRunner {
   const hm_hbs_s* hbs = nullptr;     // HM_OP_HBS
   hipStream_t s = nullptr;
   Workspace work;
-  std::vector<hipEvent_t> ev;        // pairs around each call
+  Workspace cvt;                     // callback blocks in the sample type
+  std::vector<hipEvent_t> ev;        // pairs around each call (created once, reused)
+  size_t nev = 0;                    // events recorded since the last reset
   int calls = 0;
   int64_t columns = 0;
   ~OpRunner();
@@ -152,9 +154,10 @@ void node_svd(const std::vector<SvdJob>& jobs, double* M, int64_t ldm, double* U
 // Relative rank threshold of the node factorisations for samples computed in
 // `dtype` (an HM_* sample type): singular values below it are not resolved by
 // the samples.  FP64: 0 (the kernels use max(c, h) eps); FP32: 2^-24 / 16;
-// BF16: 2^-11, a quarter of the BF16 rounding unit (a sample against a
-// Gaussian column carries noise of about 2^-9 / sqrt(3) times the Frobenius
-// norm of the sampled block).
+// BF16: 2^-11, an eighth of the BF16 unit roundoff u = 2^-8 (entries and test
+// matrix are both rounded to BF16, each with a relative error uniform in
+// [-u, u], so a sample against a Gaussian column carries noise of about
+// u sqrt(2/3) = 3.2e-3 times the norm of the sampled row block).
 double sample_rank_eta(int dtype);
 
 hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t flags, hipStream_t s,
@@ -168,5 +171,9 @@ void finish_handle_info(hm_hbs_s* h);
 // instance of a forest handle.
 hm_hbs_s* merge_hbs(const std::vector<const hm_hbs_s*>& hs, hipStream_t s);
 std::vector<hm_hbs_s*> split_hbs(const hm_hbs_s* src, hipStream_t s);
+// Copy of a handle with generators stored in `dtype` (HM_F64 / HM_F32); the
+// copy is complete once the stream has passed the call (sync: waits for it).
+// The source must stay alive until then.
+hm_hbs_s* convert_hbs(const hm_hbs_s* src, int dtype, hipStream_t s, bool sync = true);
 
 }  // namespace hm

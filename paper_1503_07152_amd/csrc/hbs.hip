@@ -20,17 +20,37 @@ OpRunner::~OpRunner() {
 
 void OpRunner::apply(bool adjoint, int64_t n, int c, const double* X, int64_t ldx, double* Y,
                      int64_t ldy) {
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
-  ev.push_back(e0);
-  ev.push_back(e1);
+  if (nev + 2 > ev.size()) {
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    ev.push_back(e0);
+    HIPCHK(hipEventCreate(&e1));
+    ev.push_back(e1);
+  }
+  hipEvent_t e0 = ev[nev], e1 = ev[nev + 1];
+  nev += 2;
   HIPCHK(hipEventRecord(e0, s));
   ++calls;
   columns += c;
   switch (op.kind) {
     case HM_OP_CALLBACK: {
-      const int rc = op.fn(op.user, adjoint ? 1 : 0, n, c, X, ldx, Y, ldy, (void*)s);
+      const int dt = op.sample_dtype;
+      int rc;
+      if (dt == HM_F64) {
+        rc = op.fn(op.user, adjoint ? 1 : 0, n, c, X, ldx, Y, ldy, HM_F64, (void*)s);
+      } else {
+        // the user's product runs in the sample type: X in FP32 or BF16,
+        // Y in FP32 (the accumulation type of a BF16 product), read back
+        // into the FP64 samples
+        const size_t xb = (size_t)n * c * (dt == HM_F32 ? 4 : 2);
+        const size_t xoff = (xb + 255) / 256 * 256;
+        cvt.ensure(xoff + (size_t)n * c * 4, s);
+        void* Xc = cvt.base();
+        float* Yc = reinterpret_cast<float*>(cvt.base() + xoff);
+        launch_convert(X, HM_F64, ldx, Xc, dt, n, n, c, s);
+        rc = op.fn(op.user, adjoint ? 1 : 0, n, c, Xc, n, Yc, n, dt, (void*)s);
+        if (rc == 0) launch_convert(Yc, HM_F32, n, Y, HM_F64, ldy, n, c, s);
+      }
       if (rc != 0) HM_THROW(HM_ERR_CALLBACK, "matvec callback returned %d", rc);
       break;
     }
@@ -64,15 +84,14 @@ void OpRunner::apply(bool adjoint, int64_t n, int c, const double* X, int64_t ld
 }
 
 void OpRunner::reset_stats() {
-  for (auto e : ev) (void)hipEventDestroy(e);
-  ev.clear();
+  nev = 0;
   calls = 0;
   columns = 0;
 }
 
 double OpRunner::elapsed_ms() {
   double t = 0.0;
-  for (size_t i = 0; i + 1 < ev.size(); i += 2) {
+  for (size_t i = 0; i + 1 < nev; i += 2) {
     float ms = 0.0f;
     if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess) t += ms;
   }
@@ -461,7 +480,8 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
   std::vector<double> eta_inst(f.inst.size(), 0.0);
   for (size_t i = 0; i < f.inst.size(); ++i) {
     const OpRunner* o = ops.size() == f.inst.size() ? ops[i] : ops[0];
-    eta_inst[i] = sample_rank_eta(o->op.kind == HM_OP_KERNEL ? o->op.sample_dtype : HM_F64);
+    eta_inst[i] = sample_rank_eta(
+        o->op.kind == HM_OP_KERNEL || o->op.kind == HM_OP_CALLBACK ? o->op.sample_dtype : HM_F64);
   }
   // node SVDs from Gram matrices when every instance samples in BF16 with one
   // padded rank (uniform node blocks); else (or after a node the Gram matrix

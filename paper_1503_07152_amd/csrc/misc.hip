@@ -2,6 +2,7 @@
 // matrices to the children of a level, block identity of the diagonal
 // extraction, fills, the non-finite check, forest construction, errors and
 // device buffers.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
@@ -328,6 +329,40 @@ __global__ void k_fill_f(float* p, int64_t count, float v) {
 void launch_fill_f(float* p, int64_t count, float v, hipStream_t s) {
   if (count <= 0) return;
   hipLaunchKernelGGL(k_fill_f, dim3(1024), dim3(256), 0, s, p, count, v);
+  KCHK();
+}
+
+// Element type conversion of a column-major block: FP64 <-> FP32, and FP64 ->
+// BF16 (round to nearest even on the FP32 value's bits; NaN kept quiet).
+__device__ __forceinline__ uint16_t f32_to_bf16_bits(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__global__ void k_convert(const void* src, int sdt, int64_t lds, void* dst, int ddt, int64_t ldd,
+                          int64_t rows, int64_t cols) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= rows) return;
+  for (int64_t j = blockIdx.y; j < cols; j += gridDim.y) {
+    double v;
+    if (sdt == HM_F64) v = static_cast<const double*>(src)[i + j * lds];
+    else v = (double)static_cast<const float*>(src)[i + j * lds];
+    if (ddt == HM_F64) static_cast<double*>(dst)[i + j * ldd] = v;
+    else if (ddt == HM_F32) static_cast<float*>(dst)[i + j * ldd] = (float)v;
+    else static_cast<uint16_t*>(dst)[i + j * ldd] = f32_to_bf16_bits((float)v);
+  }
+}
+
+void launch_convert(const void* src, int sdt, int64_t lds, void* dst, int ddt, int64_t ldd,
+                    int64_t rows, int64_t cols, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return;
+  if (sdt == HM_BF16) HM_THROW(HM_ERR_ARG, "convert: BF16 is an output type only");
+  const int nt = 256;
+  hipLaunchKernelGGL(k_convert,
+                     dim3((unsigned)((rows + nt - 1) / nt), (unsigned)std::min<int64_t>(cols, 64)),
+                     dim3(nt), 0, s, src, sdt, lds, dst, ddt, ldd, rows, cols);
   KCHK();
 }
 

@@ -125,3 +125,16 @@ def test_batched_c3_instances_match_oracle():
         assert inf["sample_columns"] == st.columns
         assert inf["min_rank"] == k and inf["max_rank"] == k
     print(f"  worst: vs oracle {worst_or:.2e}, vs A {worst_a:.2e}", flush=True)
+    # FP32 storage of the same batch: factors computed in FP64, stored and
+    # applied in FP32, within 1e-5 of the oracle
+    opts32 = [hm.Options(n, leaf, k, c3_oversample(k), seed=2000 + i, store_dtype=hm.HM_F32)
+              for i, (n, k) in enumerate(specs)]
+    outs32 = hm.hbs_compress_batched(opts32, [hm.HBSOperator(h) for h in ops_h])
+    worst32 = 0.0
+    for i, ((n, k), g, h) in enumerate(zip(specs, gens, outs32)):
+        assert h.info()["dtype"] == hm.HM_F32
+        x = W.gaussian((n, 4), seed=3)
+        y = h.apply(torch.from_numpy(x.astype(np.float32))).double().cpu().numpy()
+        worst32 = max(worst32, rel(y, ohbs.from_generators(g).apply(x)))
+    print(f"  FP32 storage: worst vs A {worst32:.2e}", flush=True)
+    assert worst32 < 1e-5

@@ -63,6 +63,65 @@ def test_callback_operator_matches_builtin():
     assert len(calls) == 2 * L + 1 and sum(calls) == h1.info()["sample_columns"]
 
 
+@pytest.mark.parametrize("dt,tol", [(hm.HM_F32, 1e-5), (hm.HM_BF16, 5e-3)])
+def test_callback_in_lower_precision_matches_oracle(dt, tol):
+    """A user black box sampled in FP32 or BF16 (the callback receives its
+    test block in that type and returns FP32 products): the orthonormal form
+    (Fig. 4) must meet the accuracy of that sampling precision against the
+    FP64 oracle, as the built-in kernel operator does."""
+    n, leaf, k, p, seed = 2048, 128, 32, 16, 3
+    P = W.fourier_curve_points(n, seed=3)
+    K = oops.KernelOp(P, "near")
+    A = torch.from_numpy(K.dense()).cuda()
+    A32, A16 = A.float(), A.to(torch.bfloat16).float()
+    seen = []
+
+    def matvec(adjoint, X, Y):
+        seen.append((X.dtype, Y.dtype))
+        if X.dtype == torch.bfloat16:
+            Y.copy_(A16 @ X.float())       # BF16 x BF16 products, FP32 sums
+        else:
+            Y.copy_(A32 @ X)
+
+    h = hm.hbs_compress(hm.Options(n, leaf, k, p, seed=seed, orthonormal=True),
+                        hm.CallbackOperator(matvec, dt))
+    want = (torch.bfloat16 if dt == hm.HM_BF16 else torch.float32, torch.float32)
+    assert seen and all(s_ == want for s_ in seen)
+    ho, _, _ = ohbs.compress(K, n, leaf, k + p, seed, rank=k, to_id=False)
+    x = W.gaussian((n, 8), seed=99)
+    y = h.apply(torch.from_numpy(x)).cpu().numpy()
+    e = rel(y, ho.apply(x))
+    print(f"callback dtype {dt}: vs oracle {e:.2e}", flush=True)
+    assert e < tol
+
+
+def test_fp32_storage_and_conversion():
+    """Factors computed in FP64 and stored in FP32 (store_dtype), and the
+    conversion of a handle both ways: FP32 storage applies within FP32
+    rounding of the FP64 form and of the exact operator."""
+    n, leaf, k, p = 2048, 64, 12, 8
+    g = W.synthetic_hbs(n, leaf, k, seed=2)
+    op = hm.HBSOperator(hm.hm_hbs_from_generators(g))
+    h64 = hm.hbs_compress(hm.Options(n, leaf, k, p, seed=4), op)
+    h32 = hm.hbs_compress(hm.Options(n, leaf, k, p, seed=4, store_dtype=hm.HM_F32), op)
+    assert h32.info()["dtype"] == hm.HM_F32 and h64.info()["dtype"] == hm.HM_F64
+    x = W.gaussian((n, 4), seed=5)
+    ya = ohbs.from_generators(g).apply(x)
+    y64 = h64.apply(torch.from_numpy(x)).cpu().numpy()
+    y32 = h32.apply(torch.from_numpy(x.astype(np.float32))).double().cpu().numpy()
+    assert rel(y32, ya) < 1e-5 and rel(y32, y64) < 1e-5
+    c32 = h64.convert(hm.HM_F32)
+    yc = c32.apply(torch.from_numpy(x.astype(np.float32))).double().cpu().numpy()
+    assert rel(yc, y32) < 1e-6
+    back = c32.convert(hm.HM_F64)
+    assert back.info()["dtype"] == hm.HM_F64
+    assert rel(back.apply(torch.from_numpy(x)).cpu().numpy(), y64) < 1e-6
+    e = c32.export()
+    assert np.array_equal(e["skel_in"], h64.export()["skel_in"])
+    with pytest.raises(hm.HMError):
+        hm.hbs_compress(hm.Options(n, leaf, k, p, seed=4, store_dtype=7), op)
+
+
 def test_failing_callback_reports_error():
     def bad(adjoint, X, Y):
         return 7
