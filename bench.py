@@ -125,6 +125,9 @@ def main():
     ap.add_argument("--apply-only", action="store_true",
                     help="only the forward and backward compressed apply of the "
                          "differentiation workload (profiling runs)")
+    ap.add_argument("--torch-alloc", action="store_true",
+                    help="route the library's device memory through torch's caching "
+                         "allocator instead of the library's own block cache")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only a plain device copy of 256 MiB, 3 times (scale of the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
@@ -141,10 +144,11 @@ def main():
     n = args.n
     r = K + P
     torch.cuda.set_device(0)
-    # the library's device memory (compress workspaces, handles, apply scratch)
-    # comes from torch's caching allocator, as in a PyTorch program: no
-    # hipMalloc / hipFree (which synchronises) inside the timed calls
-    hm.use_torch_allocator(True)
+    # the library's device memory (compress workspaces, handles) comes from
+    # its own block cache (after the warm-up no hipMalloc / hipFree inside the
+    # timed calls), or from torch's caching allocator on request
+    if args.torch_alloc:
+        hm.use_torch_allocator(True)
     if args.copy_calibration:
         a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)

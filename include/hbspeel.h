@@ -175,12 +175,18 @@ const char* hm_version(void);
  * by hm_hbs_free / hm_hodlr_free: work on other streams that reads the
  * handle must be complete by then.  Every buffer goes back to the allocator
  * that made it, even after hm_set_allocator is called again.  alloc == NULL
- * (with free == NULL) restores hipMalloc / hipFree (hipMallocAsync /
- * hipFreeAsync for scratch).  Exactly one of alloc, free NULL: HM_ERR_ARG.
- * Not to be called while other threads are inside the library. */
+ * (with free == NULL) restores the default: hipMalloc'd blocks that the
+ * library keeps when they are released and hands out again to allocations of
+ * the same rounded size for the same stream (stream order makes the reuse
+ * safe), and hipMallocAsync / hipFreeAsync for scratch.  Exactly one of
+ * alloc, free NULL: HM_ERR_ARG.  Not to be called while other threads are
+ * inside the library. */
 typedef void* (*hm_alloc_fn)(void* ctx, size_t bytes, void* stream);
 typedef void (*hm_free_fn)(void* ctx, void* ptr, void* stream);
 int hm_set_allocator(hm_alloc_fn alloc, hm_free_fn free, void* ctx);
+/* Returns the device blocks the default allocator keeps for reuse to the
+ * driver (hipFree, after waiting for the device).  Blocks in use stay. */
+int hm_release_cached_memory(void);
 
 /* ---- test matrices (Sec. 2.5; the randn of Fig. 2/4) ---------------------
  * Writes G(i, j) for rows i = row0 .. row0+nrows-1 and columns j = 0..ncols-1

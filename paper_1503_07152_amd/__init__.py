@@ -101,6 +101,7 @@ _SIGS = {
     "hm_hbs_info": (C.c_int, [_P, C.POINTER(_Info)]),
     "hm_hbs_generators": (C.c_int, [_P, C.POINTER(_Views)]),
     "hm_set_allocator": (C.c_int, [ALLOC_FN, FREE_FN, _P]),
+    "hm_release_cached_memory": (C.c_int, []),
     "hm_hodlr_info": (C.c_int, [_P, C.POINTER(_Info)]),
     "hm_hbs_export": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "hm_hodlr_export": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),

@@ -140,6 +140,13 @@ int hm_set_allocator(hm_alloc_fn alloc, hm_free_fn free, void* ctx) {
   });
 }
 
+int hm_release_cached_memory(void) {
+  return guarded([&] {
+    release_cached_memory();
+    return HM_OK;
+  });
+}
+
 int hm_gauss(uint64_t seed, int32_t level, int32_t phase, int64_t row0, int64_t nrows,
              int32_t ncols, double* out, int64_t ld, void* stream) {
   return guarded([&] {
@@ -243,18 +250,9 @@ int hbs_compress_batched(int32_t count, const hm_options* opts, const hm_operato
     for (auto& r : runners) rp.push_back(r.get());
     int status = HM_OK;
     std::unique_ptr<hm_hbs_s> res(hbs_compress_forest(f, rp, opts[0].flags, s, &status));
-    std::vector<std::unique_ptr<hm_hbs_s>> parts;
-    for (hm_hbs_s* p : split_hbs(res.get(), s)) parts.emplace_back(p);
-    res.reset();
-    if (opts[0].store_dtype == HM_F32) {  // factors computed in FP64, stored in FP32
-      std::vector<std::unique_ptr<hm_hbs_s>> f64;
-      for (auto& p : parts) {
-        f64.emplace_back(p.release());
-        p.reset(convert_hbs(f64.back().get(), HM_F32, s, false));
-      }
-      HIPCHK(hipStreamSynchronize(s));   // before the FP64 sources are freed
-    }
-    for (int i = 0; i < count; ++i) outs[i] = parts[i].release();
+    // factors computed in FP64; each instance's handle stored in store_dtype
+    std::vector<hm_hbs_s*> parts = split_hbs(res.get(), s, opts[0].store_dtype);
+    for (int i = 0; i < count; ++i) outs[i] = parts[i];
     return status;
   });
 }

@@ -12,17 +12,23 @@
 namespace hm {
 
 // Copy of row arrays (U, V, D) or per-node blocks (transfers 2R x R, sibling
-// matrices R x R) between handles of different padded rank.
+// matrices R x R) between handles of different padded rank; FP64 source,
+// FP64 or FP32 destination.
 struct CopyDesc {
   const double* src;
-  double* dst;
+  void* dst;
   int64_t src_ld, dst_ld;  // row arrays: leading dimensions
   int64_t count;           // row arrays: rows; block arrays: blocks
   int32_t cols;            // row arrays: columns copied
   int32_t Rs, Rd;          // block arrays: source / destination padded rank
   int32_t kind;            // 0 rows, 1 transfer blocks, 2 square blocks
-  int32_t pad_;
+  int32_t dst_f32;         // destination stored in FP32
 };
+
+__device__ __forceinline__ void copy_store(const CopyDesc& d, int64_t i, double v) {
+  if (d.dst_f32) static_cast<float*>(d.dst)[i] = (float)v;
+  else static_cast<double*>(d.dst)[i] = v;
+}
 
 __global__ void k_copy(const CopyDesc* descs) {
   const CopyDesc d = descs[blockIdx.y];
@@ -31,7 +37,7 @@ __global__ void k_copy(const CopyDesc* descs) {
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
       const int64_t i = e % d.count, j = e / d.count;
-      d.dst[i + j * d.dst_ld] = d.src[i + j * d.src_ld];
+      copy_store(d, i + j * d.dst_ld, d.src[i + j * d.src_ld]);
     }
     return;
   }
@@ -49,7 +55,7 @@ __global__ void k_copy(const CopyDesc* descs) {
     const int r = (int)(e % per) % rows, c = (int)((e % per) / rows);
     const int rs = (d.kind == 1 && r >= Rm) ? d.Rs + (r - Rm) : r;
     const int rd = (d.kind == 1 && r >= Rm) ? d.Rd + (r - Rm) : r;
-    d.dst[b * dblk + rd + (int64_t)c * dld] = d.src[b * sblk + rs + (int64_t)c * sld];
+    copy_store(d, b * dblk + rd + (int64_t)c * dld, d.src[b * sblk + rs + (int64_t)c * sld]);
   }
 }
 
@@ -123,9 +129,11 @@ hm_hbs_s* merge_hbs(const std::vector<const hm_hbs_s*>& hs, hipStream_t s) {
 }
 
 // One handle per instance of a forest handle, each at padded rank r_i.
-std::vector<hm_hbs_s*> split_hbs(const hm_hbs_s* src, hipStream_t s) {
+std::vector<hm_hbs_s*> split_hbs(const hm_hbs_s* src, hipStream_t s, int dtype) {
   const Forest& F = src->f;
   const int R = src->R;
+  const size_t es = dtype == HM_F32 ? 4 : 8;
+  const int32_t f32 = dtype == HM_F32 ? 1 : 0;
   std::vector<std::unique_ptr<hm_hbs_s>> out;
   std::vector<CopyDesc> cd;
   for (size_t i = 0; i < F.inst.size(); ++i) {
@@ -138,24 +146,24 @@ std::vector<hm_hbs_s*> split_hbs(const hm_hbs_s* src, hipStream_t s) {
     const int nn = (int)f.nodes.size();
     const int Ri = in.r;
     h->R = Ri;
-    h->dtype = HM_F64;
+    h->dtype = dtype;
     h->is_id = src->is_id;
     h->d_nodes = upload(f.nodes, s);
     h->d_inst = upload(f.inst, s);
-    h->U = DevBuf((size_t)n * Ri * 8);
-    h->V = DevBuf((size_t)n * Ri * 8);
-    h->Ut = DevBuf((size_t)nn * 2 * Ri * Ri * 8);
-    h->Vt = DevBuf((size_t)nn * 2 * Ri * Ri * 8);
-    h->B = DevBuf((size_t)nn * Ri * Ri * 8);
-    h->D = DevBuf((size_t)n * f.nmax * 8);
+    h->U = DevBuf((size_t)n * Ri * es);
+    h->V = DevBuf((size_t)n * Ri * es);
+    h->Ut = DevBuf((size_t)nn * 2 * Ri * Ri * es);
+    h->Vt = DevBuf((size_t)nn * 2 * Ri * Ri * es);
+    h->B = DevBuf((size_t)nn * Ri * Ri * es);
+    h->D = DevBuf((size_t)n * f.nmax * es);
     for (DevBuf* b : {&h->Ut, &h->Vt, &h->B}) HIPCHK(hipMemsetAsync(b->p, 0, b->bytes, s));
     const int64_t r0 = in.row0, g0 = in.root;
-    cd.push_back({src->U.as<double>() + r0, h->U.as<double>(), F.n_total, n, n, Ri, 0, 0, 0, 0});
-    cd.push_back({src->V.as<double>() + r0, h->V.as<double>(), F.n_total, n, n, Ri, 0, 0, 0, 0});
-    cd.push_back({src->D.as<double>() + r0, h->D.as<double>(), F.n_total, n, n, f.nmax, 0, 0, 0, 0});
-    cd.push_back({src->Ut.as<double>() + g0 * 2 * R * R, h->Ut.as<double>(), 0, 0, nn, 0, R, Ri, 1, 0});
-    cd.push_back({src->Vt.as<double>() + g0 * 2 * R * R, h->Vt.as<double>(), 0, 0, nn, 0, R, Ri, 1, 0});
-    cd.push_back({src->B.as<double>() + g0 * R * R, h->B.as<double>(), 0, 0, nn, 0, R, Ri, 2, 0});
+    cd.push_back({src->U.as<double>() + r0, h->U.p, F.n_total, n, n, Ri, 0, 0, 0, f32});
+    cd.push_back({src->V.as<double>() + r0, h->V.p, F.n_total, n, n, Ri, 0, 0, 0, f32});
+    cd.push_back({src->D.as<double>() + r0, h->D.p, F.n_total, n, n, f.nmax, 0, 0, 0, f32});
+    cd.push_back({src->Ut.as<double>() + g0 * 2 * R * R, h->Ut.p, 0, 0, nn, 0, R, Ri, 1, f32});
+    cd.push_back({src->Vt.as<double>() + g0 * 2 * R * R, h->Vt.p, 0, 0, nn, 0, R, Ri, 1, f32});
+    cd.push_back({src->B.as<double>() + g0 * R * R, h->B.p, 0, 0, nn, 0, R, Ri, 2, f32});
     h->rank_u.assign(src->rank_u.begin() + g0, src->rank_u.begin() + g0 + nn);
     h->rank_v.assign(src->rank_v.begin() + g0, src->rank_v.begin() + g0 + nn);
     h->skel_in.assign((size_t)nn * Ri, -1);

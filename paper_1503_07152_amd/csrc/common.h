@@ -83,10 +83,11 @@ void forest_add_tree(Forest& f, int64_t n, int64_t leaf, int32_t r, int32_t k,
 void forest_finish(Forest& f);
 
 // ------------------------------------------------------------- memory -------
-// Device memory comes from hipMalloc / hipFree, or from the caller's allocator
-// once hm_set_allocator has installed one.  Every buffer remembers the
-// allocator that made it and the stream it was made for, and goes back to that
-// allocator on that stream, even if the allocator has been changed since.
+// Device memory comes from the library's cache of hipMalloc'd blocks (see
+// DevBuf::alloc), or from the caller's allocator once hm_set_allocator has
+// installed one.  Every buffer remembers the allocator that made it and the
+// stream it was made for, and goes back to that allocator on that stream, even
+// if the allocator has been changed since.
 struct AllocHook {
   hm_alloc_fn alloc = nullptr;
   hm_free_fn free = nullptr;
@@ -109,20 +110,23 @@ struct StreamScope {
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
-  AllocHook hook;             // allocator that made p (alloc == nullptr: hipMalloc)
+  size_t cap = 0;             // size of the block (default allocator's cache class)
+  AllocHook hook;             // allocator that made p (alloc == nullptr: the library's cache)
   hipStream_t stream = nullptr;
   DevBuf() = default;
   explicit DevBuf(size_t b) { alloc(b); }
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), hook(o.hook), stream(o.stream) {
+  DevBuf(DevBuf&& o) noexcept
+      : p(o.p), bytes(o.bytes), cap(o.cap), hook(o.hook), stream(o.stream) {
     o.p = nullptr;
     o.bytes = 0;
+    o.cap = 0;
   }
   DevBuf& operator=(DevBuf&& o) noexcept {
     release();
-    p = o.p; bytes = o.bytes; hook = o.hook; stream = o.stream;
-    o.p = nullptr; o.bytes = 0;
+    p = o.p; bytes = o.bytes; cap = o.cap; hook = o.hook; stream = o.stream;
+    o.p = nullptr; o.bytes = 0; o.cap = 0;
     return *this;
   }
   ~DevBuf() { release(); }
@@ -143,14 +147,21 @@ struct StreamBuf {
   StreamBuf& operator=(const StreamBuf&) = delete;
 };
 
-// Upload a host vector into a fresh device buffer (synchronous w.r.t. host
-// memory: the copy is staged before return).
+// Frees the default allocator's cached device blocks (waits for the device).
+void release_cached_memory();
+
+// Host-to-device copy through pinned staging memory, enqueued on `s`
+// without waiting for it: `src` may be reused as soon as the call returns.
+// Staging chunks are kept for the process and reused once the copy out of
+// them has completed.
+void stage_h2d(void* dst, const void* src, size_t bytes, hipStream_t s);
+
+// Upload a host vector into a fresh device buffer (enqueued on s; the host
+// vector may be freed on return).
 template <class T>
 DevBuf upload(const std::vector<T>& v, hipStream_t s) {
   DevBuf b(v.size() * sizeof(T) + 16);
-  if (!v.empty())
-    HIPCHK(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
-  HIPCHK(hipStreamSynchronize(s));
+  if (!v.empty()) stage_h2d(b.p, v.data(), v.size() * sizeof(T), s);
   return b;
 }
 

@@ -1037,20 +1037,25 @@ void launch_form_b(const Node* nodes, const Instance* inst, const int32_t* kids,
 }
 
 // ------------------------------------------------------------ CPQR / ID ---
-constexpr int ID_NMAX = 256;  // candidates per node (leaf rows or 2R)
-constexpr int ID_T = 1024;    // threads: four lanes per candidate column
-static_assert(HM_MAX_SAMPLES <= 48 && ID_T == 4 * ID_NMAX, "12 rows per lane");
+// Threads NT: four lanes per candidate column, so at most NT / 4 candidates
+// per node: 1024 for leaves (rows, at most 256), 384 for parents (2R <= 96
+// candidates; fewer waves meet at each of the ID's barriers)
+constexpr int ID_T_LEAF = 1024;
+constexpr int ID_T_PARENT = 4 * 2 * HM_MAX_SAMPLES;
+static_assert(HM_MAX_SAMPLES <= 48, "12 rows per lane");
 // sum over the four lanes of a quad (the lanes of one candidate column)
 __device__ __forceinline__ double quad_sum(double v) {
   v += dpp_d<0xB1>(v);
   v += dpp_d<0x4E>(v);
   return v;
 }
+template <int ID_T>
 __global__ __launch_bounds__(ID_T) void k_cpqr_id(const Node* nodes, const Instance* inst,
                                                  const int32_t* list, int parent_mode, int R,
                                                  const double* Src, int64_t lds, const double* w,
                                                  double* P, int64_t ldp, double* samp,
                                                  int32_t* rank, int32_t* skel, int32_t* saturated) {
+  constexpr int ID_NMAX = ID_T / 4;
   __shared__ double sM[(HM_MAX_SAMPLES + 1) * ID_NMAX];  // M = W^T, R x n, ld R+1
   __shared__ double snrm[ID_NMAX];
   __shared__ int sperm[ID_NMAX];
@@ -1096,7 +1101,7 @@ __global__ __launch_bounds__(ID_T) void k_cpqr_id(const Node* nodes, const Insta
     double bv = -1.0;
     int bi = n;
 #pragma unroll
-    for (int q = 0; q < ID_NMAX / 64; ++q) {
+    for (int q = 0; q < (ID_NMAX + 63) / 64; ++q) {
       const int b = j + lane + 64 * q;
       if (b < n && snrm[b] > bv) { bv = snrm[b]; bi = b; }
     }
@@ -1208,8 +1213,12 @@ void launch_cpqr_id(const Node* nodes, const Instance* inst, const int32_t* list
                     double* P, int64_t ldp, double* samp, int32_t* rank, int32_t* skel,
                     int32_t* saturated, hipStream_t s) {
   if (nlist <= 0) return;
-  hipLaunchKernelGGL(k_cpqr_id, dim3(nlist), dim3(ID_T), 0, s, nodes, inst, list, parent_mode, R,
-                     Src, lds, w, P, ldp, samp, rank, skel, saturated);
+  if (parent_mode)
+    hipLaunchKernelGGL(k_cpqr_id<ID_T_PARENT>, dim3(nlist), dim3(ID_T_PARENT), 0, s, nodes, inst,
+                       list, parent_mode, R, Src, lds, w, P, ldp, samp, rank, skel, saturated);
+  else
+    hipLaunchKernelGGL(k_cpqr_id<ID_T_LEAF>, dim3(nlist), dim3(ID_T_LEAF), 0, s, nodes, inst, list,
+                       parent_mode, R, Src, lds, w, P, ldp, samp, rank, skel, saturated);
   KCHK();
 }
 

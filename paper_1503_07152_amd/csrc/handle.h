@@ -54,45 +54,27 @@ struct hm_hodlr_s {
 
 namespace hm {
 
-// Host-to-device staging for small per-call tables (node lists, descriptors):
-// pinned host blocks and device blocks, bump-allocated, so hipMemcpyAsync stays
-// asynchronous and no allocation happens per table.  Nothing is released
-// before the Keeper is destroyed; its owner synchronises the stream first.
+// Device copies of small per-call tables (node lists, descriptors): device
+// blocks, bump-allocated, filled through the pinned staging of stage_h2d, so
+// the copies stay asynchronous and no allocation happens per table.  Nothing
+// is released before the Keeper is destroyed; its owner synchronises the
+// stream first.
 struct Keeper {
-  struct Pinned {
-    char* p = nullptr;
-    size_t cap = 0, used = 0;
-  };
-  std::vector<Pinned> hblk;
   std::vector<DevBuf> dblk;
   size_t dused = 0;
   Keeper() = default;
   Keeper(const Keeper&) = delete;
   Keeper& operator=(const Keeper&) = delete;
-  ~Keeper() {
-    for (auto& b : hblk) (void)hipHostFree(b.p);
-  }
   template <class T>
   T* put(const std::vector<T>& v, hipStream_t s) {
     const size_t b = (v.size() * sizeof(T) + 255) / 256 * 256 + 256;
-    if (hblk.empty() || hblk.back().used + b > hblk.back().cap) {
-      Pinned pb;
-      pb.cap = std::max<size_t>(b, (size_t)1 << 20);
-      HIPCHK(hipHostMalloc((void**)&pb.p, pb.cap, hipHostMallocDefault));
-      hblk.push_back(pb);
-    }
     if (dblk.empty() || dused + b > dblk.back().bytes) {
       dblk.emplace_back(std::max<size_t>(b, (size_t)4 << 20));
       dused = 0;
     }
-    char* hp = hblk.back().p + hblk.back().used;
     char* dp = dblk.back().as<char>() + dused;
-    hblk.back().used += b;
     dused += b;
-    if (!v.empty()) {
-      std::memcpy(hp, v.data(), v.size() * sizeof(T));
-      HIPCHK(hipMemcpyAsync(dp, hp, v.size() * sizeof(T), hipMemcpyHostToDevice, s));
-    }
+    if (!v.empty()) stage_h2d(dp, v.data(), v.size() * sizeof(T), s);
     return reinterpret_cast<T*>(dp);
   }
 };
@@ -168,9 +150,9 @@ void hodlr_apply_full(const hm_hodlr_s* h, bool adjoint, int c, const double* X,
 
 void finish_handle_info(hm_hbs_s* h);
 // Block-diagonal forest operator from single-tree FP64 handles; one handle per
-// instance of a forest handle.
+// instance of an FP64 forest handle, stored in `dtype` (HM_F64 / HM_F32).
 hm_hbs_s* merge_hbs(const std::vector<const hm_hbs_s*>& hs, hipStream_t s);
-std::vector<hm_hbs_s*> split_hbs(const hm_hbs_s* src, hipStream_t s);
+std::vector<hm_hbs_s*> split_hbs(const hm_hbs_s* src, hipStream_t s, int dtype = HM_F64);
 // Copy of a handle with generators stored in `dtype` (HM_F64 / HM_F32); the
 // copy is complete once the stream has passed the call (sync: waits for it).
 // The source must stay alive until then.

@@ -6,6 +6,8 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
+#include <deque>
+#include <map>
 #include <mutex>
 
 #include "common.h"
@@ -42,6 +44,45 @@ hipStream_t alloc_stream() { return g_alloc_stream; }
 StreamScope::StreamScope(void* s) : prev(g_alloc_stream) { g_alloc_stream = (hipStream_t)s; }
 StreamScope::~StreamScope() { g_alloc_stream = prev; }
 
+// Device memory cache of the default allocator (no caller allocator
+// installed): a released buffer is kept, by device, stream and rounded size,
+// and handed out again to an allocation of that size made for the same
+// stream, which stream order makes safe.  Sizes round up to a power of two
+// below 1 MiB and to a multiple of 2 MiB above.  When hipMalloc fails, the
+// cached blocks are freed (after a device synchronisation) and it is retried.
+namespace {
+struct CacheKey {
+  int dev;
+  hipStream_t s;
+  size_t bytes;
+  bool operator<(const CacheKey& o) const {
+    if (dev != o.dev) return dev < o.dev;
+    if (s != o.s) return s < o.s;
+    return bytes < o.bytes;
+  }
+};
+std::mutex g_cache_mu;
+std::map<CacheKey, std::vector<void*>> g_cache;
+
+size_t cache_round(size_t b) {
+  if (b >= ((size_t)1 << 20)) {
+    const size_t m = (size_t)2 << 20;
+    return (b + m - 1) / m * m;
+  }
+  size_t r = 256;
+  while (r < b) r <<= 1;
+  return r;
+}
+
+void cache_trim() {   // caller holds g_cache_mu
+  if (g_cache.empty()) return;
+  (void)hipDeviceSynchronize();
+  for (auto& kv : g_cache)
+    for (void* p : kv.second) (void)hipFree(p);
+  g_cache.clear();
+}
+}  // namespace
+
 void DevBuf::alloc(size_t b) {
   release();
   if (b == 0) b = 16;
@@ -50,26 +91,55 @@ void DevBuf::alloc(size_t b) {
   if (hook.alloc) {
     p = hook.alloc(hook.ctx, b, stream);
     if (!p) HM_THROW(HM_ERR_ALLOC, "caller's allocator returned NULL for %zu bytes", b);
-  } else {
-    hipError_t e = hipMalloc(&p, b);
-    if (e != hipSuccess) {
-      p = nullptr;
-      (void)hipGetLastError();
-      HM_THROW(HM_ERR_ALLOC, "hipMalloc(%zu bytes) failed: %s", b, hipGetErrorString(e));
-    }
+    bytes = b;
+    return;
+  }
+  const size_t rb = cache_round(b);
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  auto it = g_cache.find(CacheKey{dev, stream, rb});
+  if (it != g_cache.end() && !it->second.empty()) {
+    p = it->second.back();
+    it->second.pop_back();
+    bytes = b;
+    cap = rb;
+    return;
+  }
+  hipError_t e = hipMalloc(&p, rb);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    cache_trim();
+    e = hipMalloc(&p, rb);
+  }
+  if (e != hipSuccess) {
+    p = nullptr;
+    (void)hipGetLastError();
+    HM_THROW(HM_ERR_ALLOC, "hipMalloc(%zu bytes) failed: %s", rb, hipGetErrorString(e));
   }
   bytes = b;
+  cap = rb;
 }
 
 void DevBuf::release() {
   if (p) {
-    if (hook.alloc)
+    if (hook.alloc) {
       hook.free(hook.ctx, p, stream);
-    else
-      (void)hipFree(p);
+    } else {
+      int dev = 0;
+      if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+      std::lock_guard<std::mutex> lk(g_cache_mu);
+      g_cache[CacheKey{dev, stream, cap}].push_back(p);
+    }
   }
   p = nullptr;
   bytes = 0;
+  cap = 0;
+}
+
+void release_cached_memory() {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  cache_trim();
 }
 
 StreamBuf::StreamBuf(size_t b, hipStream_t s) : hook(alloc_hook()), stream(s) {
@@ -93,6 +163,54 @@ StreamBuf::~StreamBuf() {
     hook.free(hook.ctx, p, stream);
   else
     (void)hipFreeAsync(p, stream);
+}
+
+// ------------------------------------------------------------ staging ------
+namespace {
+struct PinChunk {
+  char* p = nullptr;
+  size_t cap = 0;
+  hipEvent_t ev = nullptr;
+  int dev = -1;
+};
+std::mutex g_pin_mu;
+std::deque<PinChunk> g_pin_busy;   // copies in flight, in order of use
+std::vector<PinChunk> g_pin_free;
+constexpr size_t kPinChunk = (size_t)64 << 10;
+}  // namespace
+
+void stage_h2d(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_pin_mu);
+  while (!g_pin_busy.empty() && hipEventQuery(g_pin_busy.front().ev) == hipSuccess) {
+    g_pin_free.push_back(g_pin_busy.front());
+    g_pin_busy.pop_front();
+  }
+  (void)hipGetLastError();   // hipEventQuery's hipErrorNotReady
+  PinChunk c;
+  for (size_t i = 0; i < g_pin_free.size(); ++i)
+    if (g_pin_free[i].cap >= bytes && g_pin_free[i].dev == dev) {
+      c = g_pin_free[i];
+      g_pin_free[i] = g_pin_free.back();
+      g_pin_free.pop_back();
+      break;
+    }
+  if (!c.p) {
+    c.cap = std::max(kPinChunk, (bytes + kPinChunk - 1) / kPinChunk * kPinChunk);
+    c.dev = dev;
+    HIPCHK(hipHostMalloc((void**)&c.p, c.cap, hipHostMallocDefault));
+    const hipError_t e = hipEventCreateWithFlags(&c.ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      (void)hipHostFree(c.p);
+      HM_THROW(HM_ERR_HIP, "hipEventCreate failed: %s", hipGetErrorString(e));
+    }
+  }
+  std::memcpy(c.p, src, bytes);
+  g_pin_busy.push_back(c);   // from here the chunk is owned by the queue
+  HIPCHK(hipMemcpyAsync(dst, c.p, bytes, hipMemcpyHostToDevice, s));
+  HIPCHK(hipEventRecord(c.ev, s));
 }
 
 // ------------------------------------------------------------------ forest
