@@ -224,6 +224,7 @@ def main():
         out.update(extra_measurements(hm, W, torch, pts, n, h, ms))
         out.update(backward_measurement(hm, W, torch))
         out.update(synthetic_hbs_measurement(hm, W, torch))
+        out.update(product_measurement(hm, W, torch))
         out.update(batched_measurement(hm, W, torch))
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(W)
@@ -387,6 +388,27 @@ def synthetic_hbs_measurement(hm, W, torch, n=16384, leaf=64, k=30, p=10):
             "hbs_f64_n16384_rel_err_vs_A": float(np.linalg.norm(y - ya) / np.linalg.norm(ya)),
             "hbs_f64_n16384_ranks": [inf["min_rank"], inf["max_rank"]],
             "hbs_f64_n16384_config": f"synthetic HBS N={n} leaf={leaf} k={k} p={p}, FP64"}
+
+
+def product_measurement(hm, W, torch, n=16384, leaf=64, k=15, p=10):
+    """Recompression of a product of two compressed operators (Sec. 5.2):
+    two synthetic HBS of rank 15 (seeds 21, 22), N = 16384, leaf 64; the
+    black box applies both in turn, its HBS rank is 30 (compressed with
+    k = 30, p = 10); median of 5 calls, error on 8 probes against the
+    product itself."""
+    d1 = hm.hm_hbs_from_generators(W.synthetic_hbs(n, leaf, k, seed=21))
+    d2 = hm.hm_hbs_from_generators(W.synthetic_hbs(n, leaf, k, seed=22))
+    op = hm.HBSProductOperator(d1, d2)
+    t, h = _median_compress(hm, torch, hm.Options(n, leaf, 2 * k, p, seed=13), op, 5)
+    x = torch.from_numpy(W.gaussian((n, 8), seed=99))
+    y = h.apply(x)
+    ya = hm.hm_operator_apply(op, x)
+    inf = h.info()
+    return {"hbs_product_n16384_compress_s": round(t, 4),
+            "hbs_product_n16384_rel_err": float(torch.linalg.norm(y - ya) / torch.linalg.norm(ya)),
+            "hbs_product_n16384_ranks": [inf["min_rank"], inf["max_rank"]],
+            "hbs_product_n16384_config": f"product of two synthetic HBS N={n} leaf={leaf} "
+                                         f"k={k}, recompressed at k={2 * k} p={p}, FP64"}
 
 
 def batched_measurement(hm, W, torch, count=256, leaf=128):

@@ -65,6 +65,8 @@ extern "C" {
 #define HM_OP_KERNEL 1     /* built-in kernel matrix on 2-D points, tiled MFMA */
 #define HM_OP_DENSE 2      /* explicit N x N matrix                            */
 #define HM_OP_HBS 3        /* a matrix held as an HBS handle, applied in O(N k) */
+#define HM_OP_HBS_PRODUCT 4 /* the product hbs * hbs2 of two HBS handles, each
+                               applied in O(N k) (Sec. 5.2, operator multiplication) */
 
 #define HM_KERNEL_LOG 0    /* A(i,j) = log|x_i - x_j| (i != j), A(i,i) = 1       */
 #define HM_KERNEL_NEAR 1   /* A(i,j) = 1 / (|x_i - x_j| + kparam) (all i, j)     */
@@ -106,7 +108,9 @@ typedef struct hm_operator {
   double kparam;         /* HM_OP_KERNEL: delta of HM_KERNEL_NEAR                */
   const double* dense;   /* HM_OP_DENSE: device, n x n column-major FP64         */
   int64_t ld;            /* HM_OP_DENSE: leading dimension                       */
-  const hm_hbs* hbs;     /* HM_OP_HBS: an FP64 handle                            */
+  const hm_hbs* hbs;     /* HM_OP_HBS, HM_OP_HBS_PRODUCT: an FP64 handle (left factor) */
+  const hm_hbs* hbs2;    /* HM_OP_HBS_PRODUCT: the right factor, an FP64 handle of
+                            the same size: A x = hbs (hbs2 x), A^* x = hbs2^* (hbs^* x) */
 } hm_operator;
 
 /* Flags */
@@ -152,7 +156,9 @@ typedef struct hm_info {
   double t_compress_ms;  /* wall time of the compress call                        */
   double t_operator_ms;  /* time inside the operator (T_compress - T_net)         */
   int32_t jacobi_sweeps; /* most one-sided Jacobi sweeps any node SVD needed       */
-  int32_t pad_;
+  int32_t adapt_rounds;  /* hbs_compress_adaptive: compressions run (else 1)      */
+  double err_estimate;   /* hbs_compress_adaptive: the final posterior estimate E
+                            of Sec. 5 (else -1)                                   */
 } hm_info;
 
 /* ---- library ------------------------------------------------------------- */
@@ -216,11 +222,29 @@ int hodlr_compress(const hm_options* opts, const hm_operator* op, void* stream,
 int hbs_compress(const hm_options* opts, const hm_operator* op, void* stream,
                  hm_hbs** out);
 
+/* Adaptive sampling (the paper fixes the samples per level in advance and
+ * notes that adaptive rank determination could be built in, Sec. 4.3;
+ * Remark 1.1 and Sec. 2.5 on the failure risk): tolerance mode (opts->tol >
+ * 0) with opts->rank as the first rank cap k.  After each compression, if a
+ * node's revealed rank reached the cap k (HM_WARN_RANK_SATURATED: the r = k +
+ * p samples may not have captured its block) or the posterior estimate E of
+ * Sec. 5 exceeds e_target, the cap doubles (to at most HM_MAX_SAMPLES - p) and
+ * the compression runs again with the same seed (the Gaussian blocks are
+ * defined by row, column and level, so the first columns of every level's
+ * block stay the same).  E = max over 10 probe vectors w of |A w - A_H w| /
+ * |A w|, the probes from phase 1 of the Gaussian stream keyed by opts->seed.
+ * Returns HM_OK, or HM_WARN_RANK_SATURATED if the cap reached its limit with
+ * a node still saturated or E > e_target.  hm_info: adapt_rounds,
+ * err_estimate; sample_columns, operator_calls and the times add up all
+ * rounds (the probes' 10 columns per round not included). */
+int hbs_compress_adaptive(const hm_options* opts, const hm_operator* op, double e_target,
+                          void* stream, hm_hbs** out);
+
 /* Many independent HBS compressions (count instances of uneven N and rank),
  * level-synchronous: each level's sampling, peeling and node factorisations
  * of all instances run in the same batched launches.  Every operator must be
- * a built-in (HM_OP_HBS / HM_OP_KERNEL / HM_OP_DENSE).  outs: host array of
- * count handle pointers. */
+ * HM_OP_HBS, HM_OP_KERNEL or HM_OP_DENSE; all instances share flags and
+ * store_dtype.  outs: host array of count handle pointers. */
 int hbs_compress_batched(int32_t count, const hm_options* opts,
                          const hm_operator* ops, void* stream, hm_hbs** outs);
 

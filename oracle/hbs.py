@@ -24,7 +24,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import lowrank, rng
+from . import lowrank, metrics, rng
 from .tree import Tree
 
 
@@ -261,6 +261,32 @@ def compress(op, n: int, leaf: int, r: int, seed: int, rank: int | None = None,
     if to_id:
         hbs_id(h, y, z, rank=rank, tol=tol, r=r)
     return h, stats, extras
+
+
+def compress_adaptive(op, n: int, leaf: int, k0: int, p: int, seed: int, tol: float,
+                      e_target: float, r_max: int = 48):
+    """Adaptive sampling around Fig. 4/5 (the paper fixes the samples per
+    level in advance, to be picked above any numerical rank met, and notes
+    that adaptive rank determination could be built in; Sec. 4.3, Remark 1.1
+    on the failure risk, Sec. 2.5): compress in tolerance mode with rank cap
+    k and r = k + p samples per level; if some node's revealed eps-rank
+    reaches the cap (the samples may not have captured its block), or the
+    posterior estimate E of Sec. 5 (ten probes, phase 1 of the stream keyed
+    by ``seed``) exceeds ``e_target``, double the cap (at most r_max - p) and
+    compress again.  The Gaussian blocks are defined by (row, column, level),
+    so a larger r keeps the first columns of every level's block.  Returns
+    ``(h, rounds)`` with ``rounds`` a list of ``(k, saturated, E)``."""
+    k = k0
+    rounds = []
+    while True:
+        h, st, _ = compress(op, n, leaf, k + p, seed, rank=k, tol=tol)
+        nodes = range(2, 2 ** (h.tree.L + 1))
+        sat = any(h.rank_u(t) >= k or h.rank_v(t) >= k for t in nodes)
+        E = metrics.estimate_E(op.apply, h.apply, n, seed=seed)
+        rounds.append((k, sat, E))
+        if (not sat and E <= e_target) or k + p >= r_max:
+            return h, rounds
+        k = min(2 * k, r_max - p)
 
 
 def _copy_hbs(h: HBS) -> HBS:

@@ -7,6 +7,9 @@
   ``"log"``: ``log|x_i - x_j|`` off the diagonal, 1 on it;
   ``"near"``: ``1 / (|x_i - x_j| + delta)`` everywhere (delta = 1e-3 default).
 * ``HBSOp``    -- a matrix given in HBS form, applied in O(N k) (Fig. 7 + D).
+* ``ProductOp`` -- the product ``A1 A2`` of two black boxes (Sec. 5.2,
+  operator multiplication: a product of compressed operators, recompressed
+  from products with vectors alone).
 * ``PerturbedOp`` -- another operator whose every output entry is multiplied
   by ``1 + d`` with ``d`` uniform in ``[-rel, rel]``: the products a sampler
   with rounding error of that size could return.  Running the compression
@@ -105,6 +108,22 @@ class HBSOp:
 
     def apply_adjoint(self, X):
         return self.h.apply_adjoint(X)
+
+
+class ProductOp:
+    """``x -> A1 (A2 x)`` and ``x -> A2^* (A1^* x)``."""
+
+    def __init__(self, op1, op2):
+        if op1.n != op2.n:
+            raise ValueError("factor sizes differ")
+        self.op1, self.op2 = op1, op2
+        self.n = op1.n
+
+    def apply(self, X):
+        return self.op1.apply(self.op2.apply(X))
+
+    def apply_adjoint(self, X):
+        return self.op2.apply_adjoint(self.op1.apply_adjoint(X))
 
 
 class PerturbedOp:

@@ -20,15 +20,17 @@ import torch
 
 __all__ = [
     "HM_F64", "HM_F32", "HM_BF16", "lib", "HMError", "fortran", "to_fortran",
-    "Options", "KernelOperator", "DenseOperator", "HBSOperator", "CallbackOperator",
-    "HBS", "HODLR", "hm_gauss", "hm_operator_apply", "hbs_compress", "hodlr_compress", "hbs_compress_batched",
+    "Options", "KernelOperator", "DenseOperator", "HBSOperator", "HBSProductOperator",
+    "CallbackOperator",
+    "HBS", "HODLR", "hm_gauss", "hm_operator_apply", "hbs_compress", "hbs_compress_adaptive",
+    "hodlr_compress", "hbs_compress_batched",
     "hss_apply", "hss_apply_adjoint", "hss_apply_noalloc", "hss_apply_backward", "hodlr_apply",
     "hm_hbs_from_generators", "hbs_from_tensors", "HBSApply", "hbs_apply", "use_torch_allocator",
 ]
 
 HM_OK, HM_WARN_RANK_SATURATED = 0, 1
 HM_F64, HM_F32, HM_BF16 = 0, 1, 2
-HM_OP_CALLBACK, HM_OP_KERNEL, HM_OP_DENSE, HM_OP_HBS = 0, 1, 2, 3
+HM_OP_CALLBACK, HM_OP_KERNEL, HM_OP_DENSE, HM_OP_HBS, HM_OP_HBS_PRODUCT = 0, 1, 2, 3, 4
 HM_KERNEL_LOG, HM_KERNEL_NEAR = 0, 1
 HM_FLAG_ORTHONORMAL = 1
 HM_MAX_SAMPLES = 48
@@ -49,7 +51,7 @@ class _Operator(C.Structure):
     _fields_ = [("kind", C.c_int32), ("sample_dtype", C.c_int32), ("fn", MATVEC),
                 ("user", C.c_void_p), ("points", C.c_void_p), ("kernel_id", C.c_int32),
                 ("kparam", C.c_double), ("dense", C.c_void_p), ("ld", C.c_int64),
-                ("hbs", C.c_void_p)]
+                ("hbs", C.c_void_p), ("hbs2", C.c_void_p)]
 
 
 class _Options(C.Structure):
@@ -65,7 +67,7 @@ class _Info(C.Structure):
                 ("sample_columns", C.c_int64), ("operator_calls", C.c_int32),
                 ("saturated", C.c_int32), ("t_compress_ms", C.c_double),
                 ("t_operator_ms", C.c_double), ("jacobi_sweeps", C.c_int32),
-                ("pad_", C.c_int32)]
+                ("adapt_rounds", C.c_int32), ("err_estimate", C.c_double)]
 
 
 class _Views(C.Structure):
@@ -86,6 +88,8 @@ _SIGS = {
     "hm_operator_apply": (C.c_int, [C.POINTER(_Operator), _I64, _I32, _I64, _P, _I64, _P, _I64,
                                     _P]),
     "hbs_compress": (C.c_int, [C.POINTER(_Options), C.POINTER(_Operator), _P, C.POINTER(_P)]),
+    "hbs_compress_adaptive": (C.c_int, [C.POINTER(_Options), C.POINTER(_Operator), C.c_double,
+                                        _P, C.POINTER(_P)]),
     "hodlr_compress": (C.c_int, [C.POINTER(_Options), C.POINTER(_Operator), _P, C.POINTER(_P)]),
     "hbs_compress_batched": (C.c_int, [_I32, C.POINTER(_Options), C.POINTER(_Operator), _P,
                                        C.POINTER(_P)]),
@@ -197,6 +201,19 @@ class HBSOperator:
         self.c = _Operator()
         self.c.kind = HM_OP_HBS
         self.c.hbs = h.handle
+
+
+class HBSProductOperator:
+    """The product ``h1 @ h2`` of two FP64 HBS handles as a black box (Sec. 5.2:
+    recompressing a product of compressed operators); each factor is applied
+    in O(N k)."""
+
+    def __init__(self, h1, h2):
+        self.h1, self.h2 = h1, h2
+        self.c = _Operator()
+        self.c.kind = HM_OP_HBS_PRODUCT
+        self.c.hbs = h1.handle
+        self.c.hbs2 = h2.handle
 
 
 class _DevArray:
@@ -468,6 +485,15 @@ def hm_operator_apply(op, x, adjoint=False, stream=None):
 def hbs_compress(opts: Options, op, stream=None) -> HBS:
     h = C.c_void_p()
     rc = _check(lib.hbs_compress(C.byref(opts.c), C.byref(op.c), _stream(stream), C.byref(h)))
+    return HBS(h, rc)
+
+
+def hbs_compress_adaptive(opts: Options, op, e_target, stream=None) -> HBS:
+    """Adaptive sampling: doubles the rank cap (from opts' rank) while a node
+    saturates or the posterior estimate E exceeds ``e_target``."""
+    h = C.c_void_p()
+    rc = _check(lib.hbs_compress_adaptive(C.byref(opts.c), C.byref(op.c), e_target,
+                                          _stream(stream), C.byref(h)))
     return HBS(h, rc)
 
 

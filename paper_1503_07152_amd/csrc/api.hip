@@ -1,5 +1,6 @@
 // extern "C" entry points of libhbspeel (declared in include/hbspeel.h):
 // argument validation, exception-to-status translation, handle management.
+#include <cmath>
 #include <cstring>
 
 #include "grad.h"
@@ -64,6 +65,12 @@ void check_operator(const hm_operator* op, int64_t n, bool builtin_only) {
     case HM_OP_HBS:
       if (!op->hbs || op->hbs->f.n_total != n || op->hbs->dtype != HM_F64)
         HM_THROW(HM_ERR_ARG, "HBS operator: null, size mismatch or not FP64");
+      break;
+    case HM_OP_HBS_PRODUCT:
+      if (builtin_only) HM_THROW(HM_ERR_ARG, "HBS product operators are not allowed here");
+      for (const hm_hbs* x : {op->hbs, op->hbs2})
+        if (!x || x->f.n_total != n || x->dtype != HM_F64 || x->f.inst.size() != 1)
+          HM_THROW(HM_ERR_ARG, "HBS product operator: null, size mismatch or not FP64");
       break;
     default:
       HM_THROW(HM_ERR_ARG, "unknown operator kind %d", op->kind);
@@ -202,6 +209,86 @@ int hbs_compress(const hm_options* opts, const hm_operator* op, void* stream, hm
       const double t = h->info.t_compress_ms;
       h.reset(convert_hbs(h.get(), HM_F32, (hipStream_t)stream));
       h->info.t_compress_ms = t;
+    }
+    *out = h.release();
+    return status;
+  });
+}
+
+// Posterior error estimate E of Sec. 5 for the handle h of the operator run:
+// max over 10 probe columns w (phase 1 of the Gaussian stream keyed by seed)
+// of |A w - A_H w| / |A w|.
+static double estimate_E(const hm_hbs_s* h, OpRunner& run, uint64_t seed, hipStream_t s) {
+  const int64_t n = h->f.n_total;
+  const int c = 10;
+  DevBuf W((size_t)n * c * 8), Ya((size_t)n * c * 8), Yh((size_t)n * c * 8), nr(2 * c * 8);
+  launch_gauss_raw(seed, 0, 1, 0, n, c, W.as<double>(), n, s);
+  run.apply(false, n, c, W.as<double>(), n, Ya.as<double>(), n);
+  StreamBuf w(apply_work_bytes<double>(h->f, h->full, h->R, c), s);
+  apply_forest<double>(h->d_nodes.as<Node>(), h->full, h->view<double>(), false, c, W.as<double>(),
+                       n, Yh.as<double>(), n, 1.0, 0.0, w.p, h->f.nodes.size(), s);
+  launch_col_err2(Ya.as<double>(), n, Yh.as<double>(), n, n, c, nr.as<double>(), s);
+  double hn[2 * c];
+  HIPCHK(hipMemcpyAsync(hn, nr.p, sizeof(hn), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  double E = 0.0;
+  for (int j = 0; j < c; ++j) {
+    const double e = hn[2 * j + 1] > 0.0 ? std::sqrt(hn[2 * j] / hn[2 * j + 1]) : 0.0;
+    E = std::isnan(e) ? e : std::max(E, e);
+    if (std::isnan(E)) break;
+  }
+  return E;
+}
+
+int hbs_compress_adaptive(const hm_options* opts, const hm_operator* op, double e_target,
+                          void* stream, hm_hbs** out) {
+  if (out) *out = nullptr;
+  return guarded([&]() -> int {
+    StreamScope scope(stream);
+    if (!out) HM_THROW(HM_ERR_ARG, "out is NULL");
+    check_options(opts);
+    check_operator(op, opts->n, false);
+    if (!(opts->tol > 0.0)) HM_THROW(HM_ERR_ARG, "adaptive: tolerance mode (tol > 0) required");
+    if (!(e_target > 0.0)) HM_THROW(HM_ERR_ARG, "adaptive: e_target must be positive");
+    if (opts->flags & HM_FLAG_ORTHONORMAL)
+      HM_THROW(HM_ERR_ARG, "adaptive: ranks are revealed by the HBS-ID sweep");
+    hipStream_t s = (hipStream_t)stream;
+    hm_options o = *opts;
+    std::unique_ptr<hm_hbs_s> h;
+    int status = HM_OK, rounds = 0, calls = 0;
+    int64_t cols = 0;
+    double t_ms = 0.0, op_ms = 0.0, E = 0.0;
+    for (;;) {
+      OpRunner run;
+      run.op = *op;
+      run.hbs = op->kind == HM_OP_HBS ? op->hbs : nullptr;
+      run.s = s;
+      std::vector<OpRunner*> ops{&run};
+      h.reset(hbs_compress_forest(single_forest(&o), ops, o.flags, s, &status));
+      ++rounds;
+      calls += h->info.operator_calls;
+      cols += h->info.sample_columns;
+      t_ms += h->info.t_compress_ms;
+      op_ms += h->info.t_operator_ms;
+      E = estimate_E(h.get(), run, o.seed, s);
+      const bool ok = status != HM_WARN_RANK_SATURATED && E <= e_target;
+      if (ok || o.rank + o.oversample >= HM_MAX_SAMPLES) {
+        if (!ok) status = HM_WARN_RANK_SATURATED;
+        break;
+      }
+      o.rank = std::min(2 * o.rank, HM_MAX_SAMPLES - o.oversample);
+    }
+    h->info.adapt_rounds = rounds;
+    h->info.err_estimate = E;
+    h->info.operator_calls = calls;
+    h->info.sample_columns = cols;
+    h->info.t_compress_ms = t_ms;
+    h->info.t_operator_ms = op_ms;
+    if (o.store_dtype == HM_F32) {
+      const hm_info keep = h->info;
+      h.reset(convert_hbs(h.get(), HM_F32, s));
+      h->info = keep;
+      h->info.dtype = HM_F32;
     }
     *out = h.release();
     return status;

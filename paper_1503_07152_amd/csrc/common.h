@@ -192,6 +192,9 @@ void launch_block_eye(const Node* nodes, const int32_t* leaves, int nleaves,
 void launch_zero_dpad(const Node* nodes, const int32_t* leaves, int nleaves, int64_t max_rows,
                       int nmax, double* D, int64_t ld, hipStream_t s);
 void launch_fill(double* p, int64_t rows, int64_t cols, int64_t ld, double v, hipStream_t s);
+// out[2j] = ||A(:,j) - B(:,j)||^2 and out[2j+1] = ||A(:,j)||^2 (device, FP64)
+void launch_col_err2(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t rows,
+                     int cols, double* out, hipStream_t s);
 // dst (rows x cols, type ddt, ld ldd) = src (type sdt, ld lds); HM_F64 / HM_F32
 // sources, HM_F64 / HM_F32 / HM_BF16 destinations.
 void launch_convert(const void* src, int sdt, int64_t lds, void* dst, int ddt, int64_t ldd,

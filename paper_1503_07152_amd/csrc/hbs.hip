@@ -77,6 +77,24 @@ void OpRunner::apply(bool adjoint, int64_t n, int c, const double* X, int64_t ld
                            Y, ldy, 1.0, 0.0, work.base(), h->f.nodes.size(), s);
       break;
     }
+    case HM_OP_HBS_PRODUCT: {
+      // A X = H1 (H2 X), A^* X = H2^* (H1^* X): two fast applies through an
+      // N x c intermediate
+      const hm_hbs_s* first = adjoint ? op.hbs : op.hbs2;
+      const hm_hbs_s* second = adjoint ? op.hbs2 : op.hbs;
+      const size_t w1 = apply_work_bytes<double>(first->f, first->full, first->R, c);
+      const size_t w2 = apply_work_bytes<double>(second->f, second->full, second->R, c);
+      const size_t tmp = ((size_t)n * c * 8 + 255) / 256 * 256;
+      work.ensure(tmp + std::max(w1, w2), s);
+      double* T = reinterpret_cast<double*>(work.base());
+      apply_forest<double>(first->d_nodes.as<Node>(), first->full, first->view<double>(), adjoint,
+                           c, X, ldx, T, n, 1.0, 0.0, work.base() + tmp,
+                           first->f.nodes.size(), s);
+      apply_forest<double>(second->d_nodes.as<Node>(), second->full, second->view<double>(),
+                           adjoint, c, T, n, Y, ldy, 1.0, 0.0, work.base() + tmp,
+                           second->f.nodes.size(), s);
+      break;
+    }
     default:
       HM_THROW(HM_ERR_ARG, "unknown operator kind %d", op.kind);
   }
@@ -938,6 +956,8 @@ void finish_handle_info(hm_hbs_s* h) {
   const Forest& f = h->f;
   hm_info& in = h->info;
   in.n = f.n_total;
+  in.adapt_rounds = 1;
+  in.err_estimate = -1.0;
   in.leaf_size = f.inst.empty() ? 0 : f.inst[0].leaf;
   in.levels = f.max_levels;
   in.rank_pad = h->R;

@@ -151,6 +151,8 @@ hm_hodlr_s* hodlr_compress_forest(Forest f, OpRunner& op, hipStream_t s, int* st
   inf.sample_columns = op.columns;
   inf.operator_calls = op.calls;
   inf.saturated = hflag[1];
+  inf.adapt_rounds = 1;
+  inf.err_estimate = -1.0;
   inf.t_operator_ms = op.elapsed_ms();
   inf.t_compress_ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();

@@ -484,6 +484,41 @@ void launch_convert(const void* src, int sdt, int64_t lds, void* dst, int ddt, i
   KCHK();
 }
 
+// out[2j] = ||a_j - b_j||^2, out[2j + 1] = ||a_j||^2 for the columns of two
+// rows x cols blocks: one workgroup per column
+__global__ __launch_bounds__(256) void k_col_err2(const double* A, int64_t lda, const double* B,
+                                                  int64_t ldb, int64_t rows, double* out) {
+  __shared__ double sd[256], sa[256];
+  const int j = blockIdx.x;
+  double d2 = 0.0, a2 = 0.0;
+  for (int64_t i = threadIdx.x; i < rows; i += 256) {
+    const double a = A[i + j * lda], d = a - B[i + j * ldb];
+    d2 = fma(d, d, d2);
+    a2 = fma(a, a, a2);
+  }
+  sd[threadIdx.x] = d2;
+  sa[threadIdx.x] = a2;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      sd[threadIdx.x] += sd[threadIdx.x + w];
+      sa[threadIdx.x] += sa[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[2 * j] = sd[0];
+    out[2 * j + 1] = sa[0];
+  }
+}
+
+void launch_col_err2(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t rows,
+                     int cols, double* out, hipStream_t s) {
+  if (cols <= 0) return;
+  hipLaunchKernelGGL(k_col_err2, dim3(cols), dim3(256), 0, s, A, lda, B, ldb, rows, out);
+  KCHK();
+}
+
 // one thread per row and group of NF_COLS columns (independent loads in flight)
 constexpr int NF_COLS = 8;
 __global__ void k_nonfinite(const double* p, int64_t rows, int64_t cols, int64_t ld, int* flag) {

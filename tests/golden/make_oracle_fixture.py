@@ -20,7 +20,10 @@ pickles):
   padded) and ``prefix_in``, ``prefix_out``: the number of leading pivots of
   each node's ID decided by a margin above ``gap_floor`` (``lowrank.cpqr``);
   ``skel_in_noise``/``skel_out_noise``: the noisy runs' skeletons;
-* ``meta``: JSON text with the configuration, wall times and thread counts.
+* ``meta``: JSON text with the configuration, wall times, thread counts, the
+  errors against A and spreads, and ``bskel_err``: the largest
+  ``|B^skel - A(skel_in, skel_out)|`` of the clean run's HBS-ID form over all
+  sibling pairs, relative to the largest entry of A met (eq. ben1).
 
 Usage: ``python tests/golden/make_oracle_fixture.py [--n N] [--out PATH]``
 (about 10 minutes per compression on 8 cores at N = 65536).
@@ -108,6 +111,13 @@ def main():
 
     h0, ex0, t_clean = run(op, "clean")
     meta["t_compress_s"] = t_clean
+    worst, amax = 0.0, 0.0
+    for (a_, b_), Bab in h0.B.items():
+        Aab = op.entries(h0.skel_in[a_], h0.skel_out[b_])
+        worst = max(worst, float(np.abs(Bab - Aab).max()))
+        amax = max(amax, float(np.abs(Aab).max()))
+    meta["bskel_err"] = worst / amax
+    print(f"B^skel vs A(skel): {worst / amax:.2e}", flush=True)
     nn = 2 ** (h0.tree.L + 1)
     res["rows"] = rows.astype(np.int64)
     res["y_A"] = y_A

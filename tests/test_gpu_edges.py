@@ -181,3 +181,35 @@ def test_bf16_rank_deficient_blocks_fall_back_to_householder():
         errs[name] = rel(y, ref)
     print(f"errors {errs}")
     assert errs["f64"] < 1e-12 and errs["bf16"] < 5e-3
+
+
+@pytest.mark.parametrize("case", ["synthetic", "log"])
+def test_adaptive_sampling_matches_oracle(case):
+    """Adaptive sampling (hbs_compress_adaptive) against the oracle's
+    compress_adaptive on the same inputs and seeds: the same number of
+    rounds (caps doubling while a node saturates or E > e_target), the same
+    final ranks, and the same represented operator."""
+    if case == "synthetic":
+        n, leaf, k0, p, seed, tol, et = 2048, 64, 8, 8, 7, 1e-10, 1e-10
+        g = W.synthetic_hbs(n, leaf, 20, seed=3)
+        op = hm.HBSOperator(hm.hm_hbs_from_generators(g))
+        oop = oops.HBSOp(ohbs.from_generators(g))
+    else:
+        n, leaf, k0, p, seed, tol, et = 1024, 64, 6, 8, 5, 1e-10, 1e-9
+        P = W.ellipse_points(n)
+        op = hm.KernelOperator(P, "log", 1e-3, hm.HM_F64)
+        oop = oops.KernelOp(P, "log")
+    h = hm.hbs_compress_adaptive(hm.Options(n, leaf, k0, p, tol=tol, seed=seed), op, et)
+    ho, rounds = ohbs.compress_adaptive(oop, n, leaf, k0, p, seed, tol, et)
+    inf = h.info()
+    print(f"adaptive {case}: GPU rounds {inf['adapt_rounds']} E {inf['err_estimate']:.2e}; "
+          f"oracle {rounds}", flush=True)
+    assert h.status == 0
+    assert inf["adapt_rounds"] == len(rounds)
+    assert inf["err_estimate"] <= et
+    e = h.export()
+    for t in range(2, 2 ** (ho.tree.L + 1)):
+        assert e["rank_u"][t] == ho.rank_u(t) and e["rank_v"][t] == ho.rank_v(t)
+    x = W.gaussian((n, 8), seed=99)
+    y = h.apply(torch.from_numpy(x)).cpu().numpy()
+    assert rel(y, ho.apply(x)) < 1e-10

@@ -162,8 +162,15 @@ def test_fullsize_compress_matches_oracle_fixture(workload, oracle_fixture, dt):
         assert np.array_equal(e["rank_u"][2:nn], d["rank_u"][2:nn])
         assert np.array_equal(e["rank_v"][2:nn], d["rank_v"][2:nn])
         err = PU.hbs_id_structure(e, K_.entries)
-        print(f"  max|B^skel - A(skel)| = {err:.2e}", flush=True)
-        assert err < (1e-8 if dt == hm.HM_F64 else 2e-2)
+        err_o = d["meta"].get("bskel_err")
+        print(f"  max|B^skel - A(skel)| = {err:.2e} (oracle {err_o})", flush=True)
+        # B^skel equals A(skel) up to the orthonormal form's error on those
+        # entries: FP64 within 10x the oracle's own, BF16 within its sampling
+        # precision
+        if dt == hm.HM_F64 and err_o is not None:
+            assert err <= 10 * err_o
+        else:
+            assert err < 2e-2
         if dt == hm.HM_F64:
             bad, cmp = PU.skeleton_prefix_mismatches(e, _FixtureOracle(d))
             print(f"  decided skeleton prefixes equal on {cmp - len(bad)}/{cmp} nodes "

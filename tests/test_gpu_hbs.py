@@ -330,3 +330,34 @@ def test_synthetic_hbs_full_size_n16384():
     err = PU.hbs_id_structure(e, ent)
     say(f"  max|B^skel - A(skel)| = {err:.2e}")
     assert err < 1e-11
+
+
+@pytest.mark.parametrize("n,leaf,k,p", [(2048, 64, 8, 10), (1000, 64, 6, 8)])
+def test_compress_hbs_product_matches_oracle(n, leaf, k, p):
+    """Recompression of a product of two compressed operators (Sec. 5.2): the
+    black box applies both GPU handles in turn; its HBS rank is 2k.  The
+    GPU's HBS-ID form of the product equals the oracle's compression of the
+    same product entry by entry and the dense product, with ranks 2k."""
+    say(f"HBS product n={n} leaf={leaf} k={k} p={p}")
+    g1, g2 = W.synthetic_hbs(n, leaf, k, seed=21), W.synthetic_hbs(n, leaf, k, seed=22)
+    d1, d2 = hm.hm_hbs_from_generators(g1), hm.hm_hbs_from_generators(g2)
+    seed, rk = 13, 2 * k
+    h = hm.hbs_compress(hm.Options(n, leaf, rk, p, seed=seed), hm.HBSProductOperator(d1, d2))
+    o1, o2 = ohbs.from_generators(g1), ohbs.from_generators(g2)
+    A = o1.dense() @ o2.dense()
+    ho, st, _ = ohbs.compress(oops.ProductOp(oops.HBSOp(o1), oops.HBSOp(o2)), n, leaf, rk + p,
+                              seed, rank=rk)
+    Ag, Ao = dense_gpu(h, n), ho.dense()
+    scale = np.abs(A).max()
+    e_or, e_A = PU.max_rel(Ag, Ao, scale), PU.max_rel(Ag, A, scale)
+    say(f"  max|GPU - oracle| {e_or:.2e}, max|GPU - A| {e_A:.2e}")
+    assert e_or < 1e-12 and e_A < 1e-12
+    inf = h.info()
+    assert inf["min_rank"] == rk and inf["max_rank"] == rk
+    assert inf["sample_columns"] == st.columns
+    # the product operator itself, both directions
+    x = W.gaussian((n, 5), seed=3)
+    op = hm.HBSProductOperator(d1, d2)
+    assert rel(hm.hm_operator_apply(op, torch.from_numpy(x)).cpu().numpy(), A @ x) < 1e-13
+    assert rel(hm.hm_operator_apply(op, torch.from_numpy(x), adjoint=True).cpu().numpy(),
+               A.T @ x) < 1e-13

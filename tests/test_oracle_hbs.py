@@ -259,3 +259,53 @@ def test_parity_helpers_accept_the_oracle_and_catch_planted_errors():
     assert bad and bad[0][1] == leaf0
     with pytest.raises(AssertionError):
         PU.hbs_id_structure(e3, ent)
+
+
+def test_product_of_hbs_operators_has_rank_2k():
+    """Sec. 5.2 (operator multiplication): the product of two HBS operators
+    of rank k with nested bases is HBS of rank at most 2k -- the incoming
+    basis of a node t must span H1(I_t, I_t) U2_t and U1_t, both nested in
+    the children's.  Compressing the product black box recovers it exactly
+    at rank 2k and not at 2k - 1 (a pin of the product operator and of the
+    compression on a black box that is not itself given in HBS form)."""
+    n, leaf, k, p = 1024, 64, 6, 8
+    h1 = hbs.from_generators(W.synthetic_hbs(n, leaf, k, seed=11))
+    h2 = hbs.from_generators(W.synthetic_hbs(n, leaf, k, seed=12))
+    A = h1.dense() @ h2.dense()
+    op = operators.ProductOp(operators.HBSOp(h1), operators.HBSOp(h2))
+    x = W.gaussian((n, 3), seed=1)
+    assert np.allclose(op.apply(x), A @ x, rtol=0, atol=1e-12 * np.abs(A).max() * n)
+    assert np.allclose(op.apply_adjoint(x), A.T @ x, rtol=0, atol=1e-12 * np.abs(A).max() * n)
+    ho, _, _ = hbs.compress(op, n, leaf, 2 * k + p, 5, rank=2 * k)
+    assert np.abs(ho.dense() - A).max() < 1e-13 * np.abs(A).max()
+    ho1, _, _ = hbs.compress(op, n, leaf, 2 * k - 1 + p, 5, rank=2 * k - 1)
+    assert np.abs(ho1.dense() - A).max() > 1e-6 * np.abs(A).max()
+
+
+def test_adaptive_sampling_grows_the_cap_until_ranks_are_revealed():
+    """Adaptive sampling: a synthetic HBS operator of rank exactly 20,
+    compressed in tolerance mode from a cap of 8 (r = 16): the revealed
+    ranks saturate at caps 8 and 16 (no block of rank 20 fits), so the cap
+    doubles twice; at 32 every node reveals rank exactly 20, E is at
+    rounding level and the operator is recovered exactly."""
+    n, leaf = 1024, 64
+    hf = hbs.from_generators(W.synthetic_hbs(n, leaf, 20, seed=3))
+    h, rounds = hbs.compress_adaptive(operators.HBSOp(hf), n, leaf, 8, 8, 7, 1e-10, 1e-10)
+    assert [r[0] for r in rounds] == [8, 16, 32]
+    assert [r[1] for r in rounds] == [True, True, False]
+    assert rounds[0][2] > 1e-3 and rounds[-1][2] < 1e-13
+    for t in range(2, 2 ** (h.tree.L + 1)):
+        assert h.rank_u(t) == 20 and h.rank_v(t) == 20
+    A = hf.dense()
+    assert np.abs(h.dense() - A).max() < 1e-13 * np.abs(A).max()
+
+
+def test_adaptive_sampling_stops_at_the_sample_limit():
+    """When the cap reaches r_max - p with a node still saturated, the last
+    compression is returned as it is (the caller is told)."""
+    n, leaf = 1024, 64
+    hf = hbs.from_generators(W.synthetic_hbs(n, leaf, 30, seed=4))
+    h, rounds = hbs.compress_adaptive(operators.HBSOp(hf), n, leaf, 6, 8, 7, 1e-10, 1e-10,
+                                      r_max=32)
+    assert [r[0] for r in rounds] == [6, 12, 24]
+    assert rounds[-1][1] is True
