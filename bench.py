@@ -125,6 +125,8 @@ def main():
     ap.add_argument("--apply-only", action="store_true",
                     help="only the forward and backward compressed apply of the "
                          "differentiation workload (profiling runs)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (built-in schedule)")
     ap.add_argument("--torch-alloc", action="store_true",
                     help="route the library's device memory through torch's caching "
                          "allocator instead of the library's own block cache")
@@ -175,6 +177,11 @@ def main():
     opts = hm.Options(n, LEAF, K, P, seed=SEED)
     print(f"bench: HBS compress N={n} leaf={LEAF} k={K} p={P} BF16 sampling; "
           f"warmup {args.warmup}, steps {args.steps}", flush=True)
+    tune = None
+    if not args.no_tune:
+        # schedule chosen by the library's autotuner for this shape (not timed)
+        tune = hm.autotune(opts, op_bf16, reps=2)
+        print(f"autotune: {tune}", flush=True)
 
     for i in range(args.warmup):
         h = hm.hbs_compress(opts, op_bf16)
@@ -219,6 +226,7 @@ def main():
         "net_share_bf16": round(t_net / t_cmp, 3),
         "operator_calls_bf16": infos[-1]["operator_calls"],
         "jacobi_sweeps_max": infos[-1]["jacobi_sweeps"],
+        "autotune": tune,
     }
     if not args.no_extra:
         out.update(extra_measurements(hm, W, torch, pts, n, h, ms))

@@ -240,6 +240,27 @@ int hbs_compress(const hm_options* opts, const hm_operator* op, void* stream,
 int hbs_compress_adaptive(const hm_options* opts, const hm_operator* op, double e_target,
                           void* stream, hm_hbs** out);
 
+/* Autotuner of the compression's schedule and tiles for one workload shape
+ * (N, samples r, levels, largest leaf, sampler).  For the built-in kernel
+ * operator sampled in BF16 it times hbs_compress under every combination of:
+ *   gfirst  levels whose first products share one sampler call (1 .. 288 / 2r)
+ *   ride    later first products a second-product call may carry (0 .. 2)
+ *   ksplit  K-splits of the narrow sampler form (2, 3, 4)
+ * (reps timed calls each after one warm-up call, the fastest counted), then
+ * keeps the fastest for every later hbs_compress of that shape in this
+ * process; other operators have one schedule.  The choices change only the
+ * order of the FP32 sums of the BF16 products.  out (host): the choice
+ * (0 / -1: the built-in default), candidates timed, and the default's and
+ * the best's time in ms.  reps == 0 restores the built-in defaults for the
+ * shape without timing anything.  Not to be called while other threads
+ * compress. */
+typedef struct hm_tune {
+  int32_t gfirst, ride, ksplit, candidates;
+  double t_default_ms, t_best_ms;
+} hm_tune;
+int hm_autotune(const hm_options* opts, const hm_operator* op, int32_t reps, void* stream,
+                hm_tune* out);
+
 /* Many independent HBS compressions (count instances of uneven N and rank),
  * level-synchronous: each level's sampling, peeling and node factorisations
  * of all instances run in the same batched launches.  Every operator must be

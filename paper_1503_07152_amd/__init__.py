@@ -23,7 +23,7 @@ __all__ = [
     "Options", "KernelOperator", "DenseOperator", "HBSOperator", "HBSProductOperator",
     "CallbackOperator",
     "HBS", "HODLR", "hm_gauss", "hm_operator_apply", "hbs_compress", "hbs_compress_adaptive",
-    "hodlr_compress", "hbs_compress_batched",
+    "hodlr_compress", "hbs_compress_batched", "autotune",
     "hss_apply", "hss_apply_adjoint", "hss_apply_noalloc", "hss_apply_backward", "hodlr_apply",
     "hm_hbs_from_generators", "hbs_from_tensors", "HBSApply", "hbs_apply", "use_torch_allocator",
 ]
@@ -77,6 +77,12 @@ class _Views(C.Structure):
                 ("B", C.c_void_p), ("D", C.c_void_p)]
 
 
+class _Tune(C.Structure):
+    _fields_ = [("gfirst", C.c_int32), ("ride", C.c_int32), ("ksplit", C.c_int32),
+                ("candidates", C.c_int32), ("t_default_ms", C.c_double),
+                ("t_best_ms", C.c_double)]
+
+
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
 
@@ -106,6 +112,8 @@ _SIGS = {
     "hm_hbs_generators": (C.c_int, [_P, C.POINTER(_Views)]),
     "hm_set_allocator": (C.c_int, [ALLOC_FN, FREE_FN, _P]),
     "hm_release_cached_memory": (C.c_int, []),
+    "hm_autotune": (C.c_int, [C.POINTER(_Options), C.POINTER(_Operator), C.c_int32, _P,
+                              C.POINTER(_Tune)]),
     "hm_hodlr_info": (C.c_int, [_P, C.POINTER(_Info)]),
     "hm_hbs_export": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "hm_hodlr_export": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
@@ -495,6 +503,14 @@ def hbs_compress_adaptive(opts: Options, op, e_target, stream=None) -> HBS:
     rc = _check(lib.hbs_compress_adaptive(C.byref(opts.c), C.byref(op.c), e_target,
                                           _stream(stream), C.byref(h)))
     return HBS(h, rc)
+
+
+def autotune(opts: Options, op, reps=2, stream=None):
+    """Pick the fastest compression schedule for this workload shape (kept for
+    later ``hbs_compress`` calls of the shape); returns the choice and times."""
+    t = _Tune()
+    _check(lib.hm_autotune(C.byref(opts.c), C.byref(op.c), reps, _stream(stream), C.byref(t)))
+    return {k: getattr(t, k) for k, _ in _Tune._fields_}
 
 
 def hodlr_compress(opts: Options, op, stream=None) -> HODLR:

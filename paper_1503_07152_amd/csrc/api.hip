@@ -1,5 +1,6 @@
 // extern "C" entry points of libhbspeel (declared in include/hbspeel.h):
 // argument validation, exception-to-status translation, handle management.
+#include <chrono>
 #include <cmath>
 #include <cstring>
 
@@ -292,6 +293,72 @@ int hbs_compress_adaptive(const hm_options* opts, const hm_operator* op, double 
     }
     *out = h.release();
     return status;
+  });
+}
+
+int hm_autotune(const hm_options* opts, const hm_operator* op, int32_t reps, void* stream,
+                hm_tune* out) {
+  return guarded([&]() -> int {
+    StreamScope scope(stream);
+    if (!out || reps < 0) HM_THROW(HM_ERR_ARG, "autotune: bad arguments");
+    check_options(opts);
+    check_operator(op, opts->n, false);
+    hipStream_t s = (hipStream_t)stream;
+    Forest f = single_forest(opts);
+    forest_finish(f);
+    const int R = opts->rank + opts->oversample;
+    const bool bf16 = op->kind == HM_OP_KERNEL && op->sample_dtype == HM_BF16;
+    const TuneKey key = tune_key(f, bf16, R);
+    if (reps == 0) {   // back to the built-in defaults for this shape
+      tune_store(key, TuneParams{});
+      *out = hm_tune{0, -1, 0, 0, 0.0, 0.0};
+      return HM_OK;
+    }
+    std::vector<TuneParams> cand{TuneParams{}};    // the built-in defaults first
+    if (bf16 && f.max_levels > 1) {
+      const int cmax = sampler_max_cols(2);
+      const int gmax = std::max(1, std::min(f.max_levels, cmax / (2 * R)));
+      const int rmax = std::max(0, (cmax - 2 * R) / (2 * R));
+      for (int g = 1; g <= gmax; ++g)
+        for (int rd = 0; rd <= rmax; ++rd)
+          for (int ks : {2, 3, 4}) cand.push_back(TuneParams{g, rd, ks});
+    }
+    auto run_once = [&](const TuneParams& tp) {
+      tune_store(key, tp);
+      OpRunner run;
+      run.op = *op;
+      run.hbs = op->kind == HM_OP_HBS ? op->hbs : nullptr;
+      run.s = s;
+      std::vector<OpRunner*> ops{&run};
+      int status = HM_OK;
+      HIPCHK(hipStreamSynchronize(s));
+      const auto t0 = std::chrono::steady_clock::now();
+      std::unique_ptr<hm_hbs_s> h(hbs_compress_forest(single_forest(opts), ops,
+                                                      opts->flags | HM_FLAG_INTERNAL_NO_FALLBACK,
+                                                      s, &status));
+      return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+          .count();
+    };
+    (void)run_once(cand[0]);    // first launches, buffer growth
+    double best = 0.0, t_def = 0.0;
+    size_t bi = 0;
+    for (size_t c = 0; c < cand.size(); ++c) {
+      double t = 1e300;
+      for (int q = 0; q < reps; ++q) t = std::min(t, run_once(cand[c]));
+      if (c == 0) t_def = t;
+      if (c == 0 || t < best) {
+        best = t;
+        bi = c;
+      }
+    }
+    tune_store(key, cand[bi]);
+    out->gfirst = cand[bi].gfirst;
+    out->ride = cand[bi].ride;
+    out->ksplit = cand[bi].ksplit;
+    out->candidates = (int32_t)cand.size();
+    out->t_default_ms = t_def;
+    out->t_best_ms = best;
+    return HM_OK;
   });
 }
 

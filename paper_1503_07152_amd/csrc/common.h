@@ -147,6 +147,32 @@ struct StreamBuf {
   StreamBuf& operator=(const StreamBuf&) = delete;
 };
 
+// ------------------------------------------------------------- tuning -----
+// Schedule and tile choices of a compression that do not change what it
+// computes (only the order of FP32 sums in the BF16 sampler): picked by
+// hm_autotune per workload shape, used by later compressions of that shape.
+struct TuneParams {
+  int32_t gfirst = 0;   // most levels whose first products share a call (0: sampler width)
+  int32_t ride = -1;    // most later first products a second-product call carries (-1: all that fit)
+  int32_t ksplit = 0;   // K-splits of the narrow BF16 sampler (0: built-in default)
+};
+struct TuneKey {
+  int64_t n;
+  int32_t r, levels, nmax, instances, sampler;   // sampler: 1 = BF16 kernel operator
+  bool operator<(const TuneKey& o) const;
+};
+bool tune_lookup(const TuneKey& k, TuneParams* out);
+void tune_store(const TuneKey& k, const TuneParams& p);
+// Parameters in effect on this thread (set for the extent of a compression).
+const TuneParams& tune_current();
+struct TuneScope {
+  TuneParams prev;
+  explicit TuneScope(const TuneParams& p);
+  ~TuneScope();
+  TuneScope(const TuneScope&) = delete;
+  TuneScope& operator=(const TuneScope&) = delete;
+};
+
 // Frees the default allocator's cached device blocks (waits for the device).
 void release_cached_memory();
 

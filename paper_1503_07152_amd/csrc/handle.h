@@ -113,6 +113,9 @@ struct OpRunner {
 // Internal flag of hbs_compress_forest (beside the HM_FLAG_* bits): node
 // SVDs on the Householder path only.
 constexpr int32_t HM_FLAG_INTERNAL_NO_GRAM = 1 << 30;
+// Internal flag: no Householder rerun after a node the Gram matrix cannot
+// resolve (timing runs of the tuner).
+constexpr int32_t HM_FLAG_INTERNAL_NO_FALLBACK = 1 << 29;
 
 // Leading left singular vectors of node blocks: for each job, the block
 // M(lo : lo+rows, 0 : cols) is factored by Householder TSQR, its triangle by
@@ -144,6 +147,10 @@ double sample_rank_eta(int dtype);
 
 hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t flags, hipStream_t s,
                               int* status);
+// Key of the tuning table for a compression of forest f (after forest_finish)
+// with padded rank R; bf16_kernel: every operator is the built-in kernel
+// sampled in BF16 (the schedules the tuner chooses between exist only then).
+TuneKey tune_key(const Forest& f, bool bf16_kernel, int R);
 hm_hodlr_s* hodlr_compress_forest(Forest f, OpRunner& op, hipStream_t s, int* status);
 void hodlr_apply_full(const hm_hodlr_s* h, bool adjoint, int c, const double* X, int64_t ldx,
                       double* Y, int64_t ldy, hipStream_t s);

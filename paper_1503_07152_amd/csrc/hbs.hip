@@ -475,6 +475,17 @@ struct SideStream {
   }
 };
 
+TuneKey tune_key(const Forest& f, bool bf16_kernel, int R) {
+  TuneKey k;
+  k.n = f.n_total;
+  k.r = R;
+  k.levels = f.max_levels;
+  k.nmax = f.nmax;
+  k.instances = (int32_t)f.inst.size();
+  k.sampler = bf16_kernel ? 1 : 0;
+  return k;
+}
+
 hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t flags, hipStream_t s,
                               int* status) {
   auto t0 = std::chrono::steady_clock::now();
@@ -526,6 +537,11 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
     bf16_kernel &= o->op.kind == HM_OP_KERNEL && o->op.sample_dtype == HM_BF16;
   }
   const int cmax = sampler_max_cols(2);
+  // schedule and tile choices for this workload shape (hm_autotune), in
+  // effect for the whole compression
+  TuneParams tp;
+  (void)tune_lookup(tune_key(f, bf16_kernel, R), &tp);
+  TuneScope tune_scope(tp);
   // The block-identity product of the diagonal step does not depend on the
   // peeling either; for the same sampler it rides with second products when
   // every instance peels down to the last level: split over the spare
@@ -579,7 +595,8 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
         p.width = std::max(p.width, 2 * R * g);
       }
       const int c2 = 2 * R + ec[l];
-      const int nf = ride ? std::min(Lmax - next, std::max(0, (cmax - c2) / (2 * R))) : 0;
+      int nf = ride ? std::min(Lmax - next, std::max(0, (cmax - c2) / (2 * R))) : 0;
+      if (tp.ride >= 0) nf = std::min(nf, tp.ride);
       if (ec[l] == 0 && nf == 0) {
         p.sw[l] = p.fw[l];
         p.sc[l] = p.fc[l];
@@ -623,6 +640,7 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
   Plan pl = plan_calls(1, false, eye_last());
   if (bf16_kernel && Lmax > 1 && R > 0) {
     int G = std::max(1, std::min(Lmax, cmax / (2 * R)));
+    if (tp.gfirst > 0) G = std::min(G, tp.gfirst);
     Plan pr = plan_calls(G, true, eye_last());
     std::vector<int> ec;
     if (fuse_diag && eye_spread(pr, ec)) {
@@ -923,7 +941,7 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
   }
   HIPCHK(hipStreamSynchronize(s));
   if (hflag[0]) HM_THROW(HM_ERR_NONFINITE, "operator samples contain NaN or Inf");
-  if (hflag[3]) {
+  if (hflag[3] && !(flags & HM_FLAG_INTERNAL_NO_FALLBACK)) {
     // a node block had a leading singular value the Gram matrix cannot
     // resolve: compress again with Householder node factorisations
     for (auto* o : ops) o->reset_stats();

@@ -165,6 +165,37 @@ StreamBuf::~StreamBuf() {
     (void)hipFreeAsync(p, stream);
 }
 
+// ------------------------------------------------------------- tuning -----
+bool TuneKey::operator<(const TuneKey& o) const {
+  if (n != o.n) return n < o.n;
+  if (r != o.r) return r < o.r;
+  if (levels != o.levels) return levels < o.levels;
+  if (nmax != o.nmax) return nmax < o.nmax;
+  if (instances != o.instances) return instances < o.instances;
+  return sampler < o.sampler;
+}
+
+namespace {
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneParams> g_tune;
+thread_local TuneParams g_tune_cur;
+}  // namespace
+
+bool tune_lookup(const TuneKey& k, TuneParams* out) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(k);
+  if (it == g_tune.end()) return false;
+  *out = it->second;
+  return true;
+}
+void tune_store(const TuneKey& k, const TuneParams& p) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[k] = p;
+}
+const TuneParams& tune_current() { return g_tune_cur; }
+TuneScope::TuneScope(const TuneParams& p) : prev(g_tune_cur) { g_tune_cur = p; }
+TuneScope::~TuneScope() { g_tune_cur = prev; }
+
 // ------------------------------------------------------------ staging ------
 namespace {
 struct PinChunk {

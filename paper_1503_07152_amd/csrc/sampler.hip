@@ -45,7 +45,8 @@ static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 constexpr int SMP_KSPLIT = 3;
 static int sampler_ksplit(int mode, int64_t n, int c) {
   const int64_t nkt = (n + sampler_bk(mode) - 1) / sampler_bk(mode);
-  return (mode == 2 && c <= 128) ? (int)std::min<int64_t>(SMP_KSPLIT, nkt) : 1;
+  const int ks = tune_current().ksplit > 0 ? tune_current().ksplit : SMP_KSPLIT;
+  return (mode == 2 && c <= 128) ? (int)std::min<int64_t>(ks, nkt) : 1;
 }
 
 size_t sampler_pack_bytes(int mode, int64_t n, int c) {
@@ -55,7 +56,7 @@ size_t sampler_pack_bytes(int mode, int64_t n, int c) {
   const size_t es = mode == 0 ? 8 : (mode == 1 ? 4 : 2);
   const int ks = sampler_ksplit(mode, n, c);
   return align256((size_t)kt * bk * cp * es) + align256((size_t)kt * 4) +
-         (ks > 1 ? align256((size_t)ks * n * c * 8) : 0) + 512;
+         (ks > 1 ? align256((size_t)ks * n * c * 4) : 0) + 512;
 }
 
 // Pack: F64/F32 tiles [kt][k][col]; BF16 tiles [kt][col][k].
@@ -156,7 +157,7 @@ __attribute__((amdgpu_waves_per_eu(MODE == 1 ? 2 : (MODE == 2 && CT > 8 ? 4 : 1)
     int64_t n, int c, int cp, const double* __restrict__ pts, double kp,
     const double* __restrict__ Ad, int64_t lda, const typename ModeT<MODE>::T* __restrict__ Xp,
     const uint32_t* __restrict__ mask, double* __restrict__ Y, int64_t ldy, int64_t kt_chunk,
-    double* __restrict__ Ypart) {
+    float* __restrict__ Ypart) {
   typedef typename ModeT<MODE>::T T;
   constexpr int BK = ModeT<MODE>::BK;
   constexpr int SMP_THREADS = SmpShape<MODE>::THREADS;
@@ -393,10 +394,10 @@ __attribute__((amdgpu_waves_per_eu(MODE == 1 ? 2 : (MODE == 2 && CT > 8 ? 4 : 1)
     if (kk + 1 < nkk) HM_SMP_STASH(buf ^ 1)
     __syncthreads();
   }
-  // one split writes Y; several write their partial sums, added in split
-  // order by k_sum_parts
-  double* Yo = gridDim.y > 1 ? Ypart + (int64_t)blockIdx.y * n * c : Y;
-  const int64_t ldo = gridDim.y > 1 ? n : ldy;
+  // one split writes Y; several (BF16 form only) write their FP32 partial
+  // sums, added in FP64 in split order by k_sum_parts
+  const bool part = gridDim.y > 1;
+  float* Yq = part ? Ypart + (int64_t)blockIdx.y * n * c : nullptr;
   // Accumulator layout (column lane % 16 of each 16 x 16 tile): item v of lane
   // l holds row 4*(l/16) + v for the FP32-accumulating instructions and row
   // l/16 + 4*v for v_mfma_f64_16x16x4f64 (checked on gfx950 with identity inputs).
@@ -411,22 +412,27 @@ __attribute__((amdgpu_waves_per_eu(MODE == 1 ? 2 : (MODE == 2 && CT > 8 ? 4 : 1)
         const int rr = MODE == 0 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v;
         const int64_t row = row0 + rt * 16 + rr;
         if (row >= n) continue;
-        double val;
-        if constexpr (MODE == 1) val = acc64[rt][ct][v];
-        else val = (double)acc[rt][ct][v];
-        Yo[row + (int64_t)col * ldo] = val;
+        if constexpr (MODE == 1) {
+          Y[row + (int64_t)col * ldy] = acc64[rt][ct][v];
+        } else if constexpr (MODE == 2) {
+          if (part) Yq[row + (int64_t)col * n] = acc[rt][ct][v];
+          else Y[row + (int64_t)col * ldy] = (double)acc[rt][ct][v];
+        } else {
+          Y[row + (int64_t)col * ldy] = acc[rt][ct][v];
+        }
       }
     }
 }
 
-// Y = sum of the ks partial products (n x c each, ld n), in split order
-__global__ void k_sum_parts(int64_t n, int c, int ks, const double* __restrict__ Yp,
+// Y = sum of the ks FP32 partial products (n x c each, ld n), in FP64, in
+// split order
+__global__ void k_sum_parts(int64_t n, int c, int ks, const float* __restrict__ Yp,
                             double* __restrict__ Y, int64_t ldy) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n * c) return;
   const int64_t i = e % n, j = e / n;
-  double v = Yp[e];
-  for (int q = 1; q < ks; ++q) v += Yp[(int64_t)q * n * c + e];
+  double v = (double)Yp[e];
+  for (int q = 1; q < ks; ++q) v += (double)Yp[(int64_t)q * n * c + e];
   Y[i + j * ldy] = v;
 }
 
@@ -454,9 +460,9 @@ static void run_sampler(int64_t n, int c, const double* pts, double kp, const do
   // registers, which 512 blocks already fill.
   const int ks = sampler_ksplit(MODE, n, c);
   const int64_t kt_chunk = (nkt + ks - 1) / ks;
-  double* Yp = ks > 1 ? reinterpret_cast<double*>(static_cast<char*>(work) + xbytes +
-                                                  align256((size_t)nkt * 4))
-                      : nullptr;
+  float* Yp = ks > 1 ? reinterpret_cast<float*>(static_cast<char*>(work) + xbytes +
+                                                align256((size_t)nkt * 4))
+                     : nullptr;
   constexpr int rows = SmpShape<MODE>::ROWS;
   const dim3 grid((unsigned)((n + rows - 1) / rows), (unsigned)ks), block(SmpShape<MODE>::THREADS);
   if (MODE != 2 || c <= 128)

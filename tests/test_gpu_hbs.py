@@ -361,3 +361,29 @@ def test_compress_hbs_product_matches_oracle(n, leaf, k, p):
     assert rel(hm.hm_operator_apply(op, torch.from_numpy(x)).cpu().numpy(), A @ x) < 1e-13
     assert rel(hm.hm_operator_apply(op, torch.from_numpy(x), adjoint=True).cpu().numpy(),
                A.T @ x) < 1e-13
+
+
+def test_autotune_picks_a_schedule_that_keeps_the_result():
+    """The autotuner times every schedule of the BF16 kernel workload's
+    shape (first products per call, later first products per second call,
+    K-splits of the narrow sampler), keeps the fastest for later compressions
+    of that shape, and the result stays within BF16 sampling accuracy of the
+    oracle (the schedules differ only in the order of FP32 sums)."""
+    n, leaf, k, p, seed = 4096, 128, 32, 16, 3
+    P = W.fourier_curve_points(n, seed=3)
+    op = hm.KernelOperator(P, "near", 1e-3, hm.HM_BF16)
+    opts = hm.Options(n, leaf, k, p, seed=seed, orthonormal=True)
+    try:
+        t = hm.autotune(opts, op, reps=1)
+        say(f"autotune: {t}")
+        assert t["candidates"] == 1 + 3 * 3 * 3
+        assert t["t_best_ms"] <= t["t_default_ms"]
+        assert 0 <= t["gfirst"] <= 3 and -1 <= t["ride"] <= 2 and t["ksplit"] in (0, 2, 3, 4)
+        h = hm.hbs_compress(opts, op)
+        ho, _, _ = ohbs.compress(oops.KernelOp(P, "near"), n, leaf, k + p, seed, rank=k,
+                                 to_id=False)
+        r = _compare_compress(h, ho, n)
+        say(f"  tuned compress vs oracle {r['vs_oracle']:.2e}")
+        assert r["vs_oracle"] < 5e-3
+    finally:
+        hm.autotune(opts, op, reps=0)      # back to the defaults for this shape
