@@ -229,6 +229,13 @@ def main():
         "autotune": tune,
     }
     if not args.no_extra:
+        # the Fig. 5 sweep as one persistent launch (device work queue over
+        # levels and sides) instead of level by level
+        tp, hp = _median_compress(hm, torch, hm.Options(n, LEAF, K, P, seed=SEED,
+                                                        persistent_id=True), op_bf16, 5)
+        out["compress_s_bf16_persistent_id"] = round(tp, 4)
+        print(f"persistent ID sweep: {tp * 1e3:.1f} ms (median of 5)", flush=True)
+        del hp
         out.update(extra_measurements(hm, W, torch, pts, n, h, ms))
         out.update(backward_measurement(hm, W, torch))
         out.update(synthetic_hbs_measurement(hm, W, torch))
@@ -431,29 +438,40 @@ def batched_measurement(hm, W, torch, count=256, leaf=128):
             for i, (n, k) in enumerate(specs)]
     ops = [hm.HBSOperator(h) for h in ops_h]
     hm.hbs_compress_batched(opts[:8], ops[:8])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    outs = hm.hbs_compress_batched(opts, ops)
-    torch.cuda.synchronize()
-    tb = time.perf_counter() - t0
-    errs = []
-    for (n, _), hh, ho in zip(specs, outs, ops_h):
-        x = torch.from_numpy(W.gaussian((n, 4), seed=3))
-        y = hh.apply(x).double()
-        ya = ho.apply(x)
-        errs.append(float(torch.linalg.norm(y - ya) / torch.linalg.norm(ya)))
-    del outs
+    res = {}
+    for tag, pers in (("", False), ("_persistent_id", True)):
+        for o in opts:
+            o.c.flags = hm.HM_FLAG_PERSISTENT_ID if pers else 0
+        hm.hbs_compress_batched(opts, ops)       # warm-up of this form
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        outs = hm.hbs_compress_batched(opts, ops)
+        torch.cuda.synchronize()
+        res["batched_s" + tag] = round(time.perf_counter() - t0, 4)
+        errs = []
+        for (n, _), hh, ho in zip(specs, outs, ops_h):
+            x = torch.from_numpy(W.gaussian((n, 4), seed=3))
+            y = hh.apply(x).double()
+            ya = ho.apply(x)
+            errs.append(float(torch.linalg.norm(y - ya) / torch.linalg.norm(ya)))
+        res["batched_rel_err_max" + tag] = max(errs)
+        if not tag:
+            res["batched_rel_err_median"] = float(np.median(errs))
+        del outs
+    for o in opts:
+        o.c.flags = 0
+    tb = res["batched_s"]
     t0 = time.perf_counter()
     for o, op in zip(opts, ops):
         h = hm.hbs_compress(o, op)
         del h
     torch.cuda.synchronize()
     ts = time.perf_counter() - t0
-    return {"batched_instances": count, "batched_total_n": int(sum(n for n, _ in specs)),
-            "batched_s": round(tb, 4), "batched_instances_per_s": round(count / tb, 1),
-            "sequential_s": round(ts, 4), "batched_speedup": round(ts / tb, 2),
-            "batched_rel_err_max": max(errs), "batched_rel_err_median": float(np.median(errs)),
-            "batched_storage": "fp32"}
+    res.update({"batched_instances": count, "batched_total_n": int(sum(n for n, _ in specs)),
+                "batched_instances_per_s": round(count / tb, 1),
+                "sequential_s": round(ts, 4), "batched_speedup": round(ts / tb, 2),
+                "batched_storage": "fp32"})
+    return res
 
 
 def _threads():

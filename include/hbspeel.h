@@ -116,6 +116,12 @@ typedef struct hm_operator {
 /* Flags */
 #define HM_FLAG_ORTHONORMAL 1  /* hbs_compress: stop after Fig. 4 (orthonormal
                                   nested bases, r columns per node), no Fig. 5 */
+#define HM_FLAG_PERSISTENT_ID 2 /* run the Fig. 5 sweep as one persistent launch
+                                  over every level, side and instance (a device work
+                                  queue; a parent is taken up once both children are
+                                  done) instead of the default level by level (two
+                                  launches per level and side, the two sides on two
+                                  streams); same result */
 
 typedef struct hm_options {
   int64_t n;            /* matrix size N >= 1                                    */

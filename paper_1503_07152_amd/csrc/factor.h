@@ -137,6 +137,31 @@ void launch_cpqr_id(const Node* nodes, const Instance* inst, const int32_t* list
                     int parent_mode, int R, const double* Src, int64_t lds, const double* w,
                     double* P, int64_t ldp, double* samp, int32_t* rank, int32_t* skel,
                     int32_t* saturated, hipStream_t s);
+// The whole Fig. 5 sweep (both sides, every level and instance) in one
+// persistent launch: items (node, side) in order of decreasing level; a
+// workgroup takes items from *next until none is left, a parent item after
+// both children of its side are done (done[2 node + side] set).  done (2 *
+// nodes int32) and *next must be zero at launch; *err is set if a wait ran
+// past its limit (the sweep's results are then invalid).  Per side: leaf
+// interpolation bases into P (rows I_t, ld ldb), parent transfers into Pt
+// (block t, 2R x R), samp_t, rank_t, skel_t as launch_cpqr_id.
+struct IdItem {
+  int32_t node, side;
+};
+struct IdSide {
+  const double* basis;   // leaf long bases (N x R, ld ldb)
+  const double* w;       // per-node weights (y or z), R each
+  const double* told;    // transfers of the orthonormal form (2R x R per node)
+  double* P;             // leaf interpolation bases (N x R, ld ldb)
+  double* Pt;            // parent interpolation transfers (2R x R per node)
+  double* samp;          // samp_t (R x R per node)
+  int32_t* rank;
+  int32_t* skel;
+};
+void launch_id_sweep(const Node* nodes, const Instance* inst, const IdItem* items, int nitems,
+                     const IdSide& u, const IdSide& v, int R, int64_t ldb, int32_t* done,
+                     int32_t* next, int32_t* err, int32_t* saturated, int workgroups,
+                     hipStream_t s);
 // Utmp_t(side R + i, :) = samp_child(i, :) Tr_t(side R : side R + R, :)  (Fig. 5)
 void launch_utmp(const Node* nodes, const int32_t* list, int nlist, int R, const double* samp,
                  const double* Tr, double* Utmp, hipStream_t s);

@@ -1049,34 +1049,29 @@ __device__ __forceinline__ double quad_sum(double v) {
   v += dpp_d<0x4E>(v);
   return v;
 }
+// LDS of one node's ID with ID_T threads (at most ID_T / 4 candidates)
 template <int ID_T>
-__global__ __launch_bounds__(ID_T) void k_cpqr_id(const Node* nodes, const Instance* inst,
-                                                 const int32_t* list, int parent_mode, int R,
-                                                 const double* Src, int64_t lds, const double* w,
-                                                 double* P, int64_t ldp, double* samp,
-                                                 int32_t* rank, int32_t* skel, int32_t* saturated) {
+struct IdShared {
+  double M[(HM_MAX_SAMPLES + 1) * (ID_T / 4)];  // M = W^T, R x n, ld R+1
+  double nrm[ID_T / 4];
+  int perm[ID_T / 4];
+  double v[HM_MAX_SAMPLES];
+  double c[4];
+};
+
+// The ID of one node from its weighted candidate matrix, already in sm.M
+// (candidate b, sample dimension a at a + b (R + 1); sm.perm the identity):
+// column-pivoted Householder QR of W^* in LDS, T = R11^-1 R12, outputs as
+// launch_cpqr_id describes.  src / ls: the unweighted candidate rows (global
+// or LDS), read for samp_t.  All ID_T threads of the workgroup call it.
+template <int ID_T>
+__device__ void id_core(double* sM, double* snrm, int* sperm, double* sv, double* sc,
+                        const Node& nd, const Instance& in, int g, int parent_mode, int R, int n,
+                        const double* src, int64_t ls, double* P, int64_t ldp, double* samp,
+                        int32_t* rank, int32_t* skel, int32_t* saturated) {
   constexpr int ID_NMAX = ID_T / 4;
-  __shared__ double sM[(HM_MAX_SAMPLES + 1) * ID_NMAX];  // M = W^T, R x n, ld R+1
-  __shared__ double snrm[ID_NMAX];
-  __shared__ int sperm[ID_NMAX];
-  __shared__ double sv[HM_MAX_SAMPLES];
-  __shared__ double sc[4];
-  __shared__ int sk[2];
-  const int g = list[blockIdx.x];
-  const Node nd = nodes[g];
-  const Instance in = inst[nd.inst];
   const int tid = threadIdx.x;
   const int ldm = R + 1;
-  const int n = parent_mode ? 2 * R : (int)(nd.hi - nd.lo);
-  const double* src = parent_mode ? Src + (int64_t)g * 2 * R * R : Src + nd.lo;
-  const int64_t ls = parent_mode ? 2 * R : lds;
-  const double* wv = w + (int64_t)g * R;
-  for (int idx = tid; idx < n * R; idx += ID_T) {
-    const int b = idx % n, a = idx / n;  // candidate b, sample dim a
-    sM[a + b * ldm] = src[b + (int64_t)a * ls] * wv[a];
-  }
-  for (int b = tid; b < n; b += ID_T) sperm[b] = b;
-  __syncthreads();
   const int kcap = min(min(in.k, in.r), min(R, n));
   const int lane = tid & 63, wave = tid >> 6;
   // squared norms of the candidate columns: lane q of column b's quad takes
@@ -1206,6 +1201,188 @@ __global__ __launch_bounds__(ID_T) void k_cpqr_id(const Node* nodes, const Insta
     rank[g] = k;
     if (in.tol > 0.0 && k >= in.r - in.p && saturated) atomicAdd(saturated, 1);
   }
+}
+
+template <int ID_T>
+__global__ __launch_bounds__(ID_T) void k_cpqr_id(const Node* nodes, const Instance* inst,
+                                                 const int32_t* list, int parent_mode, int R,
+                                                 const double* Src, int64_t lds, const double* w,
+                                                 double* P, int64_t ldp, double* samp,
+                                                 int32_t* rank, int32_t* skel, int32_t* saturated) {
+  __shared__ IdShared<ID_T> sm;
+  const int g = list[blockIdx.x];
+  const Node nd = nodes[g];
+  const Instance in = inst[nd.inst];
+  const int tid = threadIdx.x;
+  const int ldm = R + 1;
+  const int n = parent_mode ? 2 * R : (int)(nd.hi - nd.lo);
+  const double* src = parent_mode ? Src + (int64_t)g * 2 * R * R : Src + nd.lo;
+  const int64_t ls = parent_mode ? 2 * R : lds;
+  const double* wv = w + (int64_t)g * R;
+  for (int idx = tid; idx < n * R; idx += ID_T) {
+    const int b = idx % n, a = idx / n;  // candidate b, sample dim a
+    sm.M[a + b * ldm] = src[b + (int64_t)a * ls] * wv[a];
+  }
+  for (int b = tid; b < n; b += ID_T) sm.perm[b] = b;
+  __syncthreads();
+  id_core<ID_T>(sm.M, sm.nrm, sm.perm, sm.v, sm.c, nd, in, g, parent_mode, R, n, src, ls, P, ldp,
+                samp, rank, skel, saturated);
+}
+
+// ---- the whole Fig. 5 sweep in one persistent launch --------------------------
+// Work items (node, side) in order of decreasing level, over every instance of
+// the forest; each workgroup takes the next item from a device counter until
+// none is left.  A leaf item is ready at once; a parent item waits until both
+// children of its side are done (their samp_t, skeletons and ranks are
+// published with a release at agent scope and read after an acquire), builds
+// Utmp = diag(samp_left, samp_right) Tr_t in LDS (k_utmp) and runs the ID on
+// it (parent mode of k_cpqr_id).  Items are taken in an order in which every
+// item's children were taken before it, by workgroups that are running, so
+// every wait ends; a wait longer than the spin limit (never expected) marks
+// the item done without doing it and sets *err, so that no workgroup waits
+// forever.
+constexpr int IDS_T = 1024;
+constexpr int IDS_SPIN_LIMIT = 1 << 20;
+
+// LDS of the sweep: a leaf item's candidate matrix ((R + 1) x 256), or a
+// parent item's ((R + 1) x 2R) followed by samp_left | samp_right (R x R
+// each), Tr_t and Utmp_t (2R x R each)
+constexpr int IDS_RAW_LEAF = (HM_MAX_SAMPLES + 1) * (IDS_T / 4);
+constexpr int IDS_RAW_PARENT =
+    (HM_MAX_SAMPLES + 1) * 2 * HM_MAX_SAMPLES + 6 * HM_MAX_SAMPLES * HM_MAX_SAMPLES;
+constexpr int IDS_RAW = IDS_RAW_LEAF > IDS_RAW_PARENT ? IDS_RAW_LEAF : IDS_RAW_PARENT;
+
+// Polls with relaxed coherent loads (an acquire per poll would invalidate
+// the L2 of the XCD each time, slowing every other workgroup there); the
+// acquire follows once the flag is seen.
+__device__ __forceinline__ bool id_wait(int32_t* flag) {
+  for (int it = 0; it < IDS_SPIN_LIMIT; ++it) {
+    if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return true;
+    __builtin_amdgcn_s_sleep(2);
+  }
+  return false;
+}
+
+__global__ __launch_bounds__(IDS_T) void k_id_sweep(const Node* nodes, const Instance* inst,
+                                                   const IdItem* items, int nitems,
+                                                   IdSide side0, IdSide side1, int R,
+                                                   int64_t ldb, int32_t* done, int32_t* next,
+                                                   int32_t* err, int32_t* saturated) {
+  __shared__ double raw[IDS_RAW];
+  __shared__ double snrm[IDS_T / 4];
+  __shared__ int sperm[IDS_T / 4];
+  __shared__ double sv[HM_MAX_SAMPLES];
+  __shared__ double sc[4];
+  __shared__ int s_item, s_ok;
+  const int tid = threadIdx.x;
+  const int ldm = R + 1;
+  const int RR = R * R;
+  double* sM = raw;
+  double* sA = raw + (R + 1) * 2 * R;   // parent items only
+  double* sT = sA + 2 * RR;
+  double* sU = sT + 2 * RR;
+  // Control flow in this loop stays uniform across the workgroup (scalar
+  // conditions only, outside id_core's own uniform loops): a branch on the
+  // thread index around the loop's barriers would be structured by the
+  // compiler so that thread 0's steps (taking an item, publishing one) run
+  // only once the other lanes have left the loop, while those lanes loop on
+  // at its barriers with a stale item.  The steps that need one thread are
+  // done by all lanes of wave 0, under a branch on the wave index read into a
+  // scalar register.
+  const int wave_u = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid & 63;
+  for (;;) {
+    if (wave_u == 0) {
+      // lane 0 adds 1, the others 0: lane 0's result is the counter's old value
+      const int v = atomicAdd(next, lane == 0 ? 1 : 0);
+      s_item = __builtin_amdgcn_readfirstlane(v);
+    }
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
+    __syncthreads();   // every thread has the index before wave 0 takes the next
+    if (it >= nitems) break;
+    const IdItem itm = items[it];
+    const IdSide sd = itm.side ? side1 : side0;
+    const int g = itm.node;
+    const Node nd = nodes[g];
+    const Instance in = inst[nd.inst];
+    const bool parent = nd.left >= 0;
+    const double* wv = sd.w + (int64_t)g * R;
+    if (!parent) {
+      const int n = (int)(nd.hi - nd.lo);
+      const double* src = sd.basis + nd.lo;
+      for (int idx = tid; idx < n * R; idx += IDS_T) {
+        const int b = idx % n, a = idx / n;
+        sM[a + b * ldm] = src[b + (int64_t)a * ldb] * wv[a];
+      }
+      for (int b = tid; b < n; b += IDS_T) sperm[b] = b;
+      __syncthreads();
+      id_core<IDS_T>(sM, snrm, sperm, sv, sc, nd, in, g, 0, R, n, src, ldb, sd.P, ldb, sd.samp,
+                     sd.rank, sd.skel, saturated);
+    } else {
+      const int n = 2 * R;
+      if (wave_u == 0) {
+        const bool a = id_wait(done + 2 * nd.left + itm.side);
+        const bool b = id_wait(done + 2 * nd.right + itm.side);
+        const int okw = __builtin_amdgcn_readfirstlane((a && b) ? 1 : 0);
+        s_ok = okw;
+        if (!okw) atomicOr(err, 1);
+      }
+      __syncthreads();
+      const bool go = __builtin_amdgcn_readfirstlane(s_ok) != 0;
+      // every thread acquires the children's results for itself
+      (void)__hip_atomic_load(done + 2 * nd.left + itm.side, __ATOMIC_ACQUIRE,
+                              __HIP_MEMORY_SCOPE_AGENT);
+      (void)__hip_atomic_load(done + 2 * nd.right + itm.side, __ATOMIC_ACQUIRE,
+                              __HIP_MEMORY_SCOPE_AGENT);
+      if (go) {
+        const double* sl = sd.samp + (int64_t)nd.left * RR;
+        const double* sr = sd.samp + (int64_t)nd.right * RR;
+        const double* tr = sd.told + (int64_t)g * 2 * RR;
+        for (int e = tid; e < RR; e += IDS_T) {
+          sA[e] = sl[e];
+          sA[RR + e] = sr[e];
+        }
+        for (int e = tid; e < 2 * RR; e += IDS_T) sT[e] = tr[e];
+        __syncthreads();
+        // Utmp(side R + i, j) = sum_m samp_side(i, m) Tr(side R + m, j)
+        for (int e = tid; e < 2 * RR; e += IDS_T) {
+          const int row = e % (2 * R), j = e / (2 * R);
+          const int side = row >= R ? 1 : 0, i = row - side * R;
+          const double* sa = sA + side * RR;
+          double acc = 0.0;
+          for (int m = 0; m < R; ++m) acc = fma(sa[i + m * R], sT[side * R + m + j * 2 * R], acc);
+          sU[row + j * 2 * R] = acc;
+        }
+        __syncthreads();
+        for (int idx = tid; idx < n * R; idx += IDS_T) {
+          const int b = idx % n, a = idx / n;
+          sM[a + b * ldm] = sU[b + a * 2 * R] * wv[a];
+        }
+        for (int b = tid; b < n; b += IDS_T) sperm[b] = b;
+        __syncthreads();
+        id_core<IDS_T>(sM, snrm, sperm, sv, sc, nd, in, g, 1, R, n, sU, 2 * R, sd.Pt, 2 * R,
+                       sd.samp, sd.rank, sd.skel, saturated);
+      }
+    }
+    // publish: every thread's stores (released at agent scope), then the
+    // item's flag (wave 0's lanes all store the same 1)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (wave_u == 0)
+      __hip_atomic_store(done + 2 * g + itm.side, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+void launch_id_sweep(const Node* nodes, const Instance* inst, const IdItem* items, int nitems,
+                     const IdSide& u, const IdSide& v, int R, int64_t ldb, int32_t* done,
+                     int32_t* next, int32_t* err, int32_t* saturated, int workgroups,
+                     hipStream_t s) {
+  if (nitems <= 0) return;
+  const int grid = std::max(1, std::min(workgroups, nitems));
+  hipLaunchKernelGGL(k_id_sweep, dim3(grid), dim3(IDS_T), 0, s, nodes, inst, items, nitems, u, v,
+                     R, ldb, done, next, err, saturated);
+  KCHK();
 }
 
 void launch_cpqr_id(const Node* nodes, const Instance* inst, const int32_t* list, int nlist,

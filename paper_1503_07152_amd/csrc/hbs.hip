@@ -451,6 +451,21 @@ static hipStream_t side_stream_for_current_device() {
   return st;
 }
 
+// Compute units of the current device (cached per device).
+static int device_cu_count() {
+  static std::mutex mu;
+  static std::map<int, int> cus;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cus.find(dev);
+  if (it != cus.end()) return it->second;
+  int n = 0;
+  HIPCHK(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev));
+  cus[dev] = std::max(1, n);
+  return cus[dev];
+}
+
 struct SideStream {
   hipStream_t main, st = nullptr;
   hipEvent_t e_fork = nullptr, e_join = nullptr;
@@ -672,8 +687,8 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
   DevBuf yv((size_t)nn * R * 8), zv((size_t)nn * R * 8);
   DevBuf Ut((size_t)nn * 2 * R * R * 8), Vt((size_t)nn * 2 * R * R * 8);
   DevBuf B((size_t)nn * R * R * 8), Xr((size_t)nn * 2 * R * R * 8);
-  DevBuf flag(16);
-  HIPCHK(hipMemsetAsync(flag.p, 0, 16, s));
+  DevBuf flag(32);   // non-finite, saturated, Jacobi sweeps, Gram fallback, ID-sweep wait limit
+  HIPCHK(hipMemsetAsync(flag.p, 0, 32, s));
   HIPCHK(hipMemsetAsync(yv.p, 0, yv.bytes, s));
   HIPCHK(hipMemsetAsync(zv.p, 0, zv.bytes, s));
   HIPCHK(hipMemsetAsync(Ut.p, 0, Ut.bytes, s));
@@ -877,30 +892,50 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
     // stream, forked after every input and node list is enqueued on s and
     // joined before B^skel, so the coarse levels' latency-bound IDs of the
     // two sides overlap.
-    SideStream side(s);
-    auto chain = [&](bool vside, hipStream_t st) {
-      const double* basis = vside ? vc : uc;
-      const double* wts = vside ? zv.as<double>() : yv.as<double>();
-      double* newb = vside ? Vnew.as<double>() : Unew.as<double>();
-      double* samp = vside ? sV.as<double>() : sU.as<double>();
-      double* tnew = vside ? Vtn.as<double>() : Utn.as<double>();
-      const double* told = vside ? Vt.as<double>() : Ut.as<double>();
-      double* tmp = vside ? TmpV.as<double>() : TmpU.as<double>();
-      int32_t* rk = vside ? rk_v.as<int32_t>() : rk_u.as<int32_t>();
-      int32_t* sk = vside ? sk_out.as<int32_t>() : sk_in.as<int32_t>();
-      launch_cpqr_id(dn, di, dl, (int)lv.size(), 0, R, basis, N, wts, newb, N, samp, rk, sk, sat,
-                     st);
-      for (int l = Lmax - 1; l >= 1; --l) {
-        if (dpar[l].second == 0) continue;
-        launch_utmp(dn, dpar[l].first, dpar[l].second, R, samp, told, tmp, st);
-        launch_cpqr_id(dn, di, dpar[l].first, dpar[l].second, 1, R, tmp, 2 * R, wts, tnew, 2 * R,
-                       samp, rk, sk, sat, st);
-      }
-    };
-    side.fork();
-    chain(false, s);
-    chain(true, side.stream());
-    side.join();
+    if (!(flags & HM_FLAG_PERSISTENT_ID)) {
+      SideStream side(s);
+      auto chain = [&](bool vside, hipStream_t st) {
+        const double* basis = vside ? vc : uc;
+        const double* wts = vside ? zv.as<double>() : yv.as<double>();
+        double* newb = vside ? Vnew.as<double>() : Unew.as<double>();
+        double* samp = vside ? sV.as<double>() : sU.as<double>();
+        double* tnew = vside ? Vtn.as<double>() : Utn.as<double>();
+        const double* told = vside ? Vt.as<double>() : Ut.as<double>();
+        double* tmp = vside ? TmpV.as<double>() : TmpU.as<double>();
+        int32_t* rk = vside ? rk_v.as<int32_t>() : rk_u.as<int32_t>();
+        int32_t* sk = vside ? sk_out.as<int32_t>() : sk_in.as<int32_t>();
+        launch_cpqr_id(dn, di, dl, (int)lv.size(), 0, R, basis, N, wts, newb, N, samp, rk, sk, sat,
+                       st);
+        for (int l = Lmax - 1; l >= 1; --l) {
+          if (dpar[l].second == 0) continue;
+          launch_utmp(dn, dpar[l].first, dpar[l].second, R, samp, told, tmp, st);
+          launch_cpqr_id(dn, di, dpar[l].first, dpar[l].second, 1, R, tmp, 2 * R, wts, tnew, 2 * R,
+                         samp, rk, sk, sat, st);
+        }
+      };
+      side.fork();
+      chain(false, s);
+      chain(true, side.stream());
+      side.join();
+    } else {
+      // one persistent launch for both sides, every level and instance
+      std::vector<IdItem> items;
+      for (int l = Lmax; l >= 1; --l)
+        for (int g : f.level[l]) {
+          items.push_back(IdItem{g, 0});
+          items.push_back(IdItem{g, 1});
+        }
+      const IdItem* ditems = kp.put(items, s);
+      DevBuf sync((size_t)(2 * nn + 2) * 4);
+      HIPCHK(hipMemsetAsync(sync.p, 0, sync.bytes, s));
+      int32_t* done = sync.as<int32_t>();
+      const IdSide su{uc, yv.as<double>(), Ut.as<double>(), Unew.as<double>(), Utn.as<double>(),
+                      sU.as<double>(), rk_u.as<int32_t>(), sk_in.as<int32_t>()};
+      const IdSide sv{vc, zv.as<double>(), Vt.as<double>(), Vnew.as<double>(), Vtn.as<double>(),
+                      sV.as<double>(), rk_v.as<int32_t>(), sk_out.as<int32_t>()};
+      launch_id_sweep(dn, di, ditems, (int)items.size(), su, sv, R, N, done, done + 2 * nn,
+                      flag.as<int32_t>() + 4, sat, device_cu_count(), s);
+    }
     std::vector<int32_t> nonroot;
     for (int g = 0; g < nn; ++g)
       if (f.nodes[g].parent >= 0) nonroot.push_back(g);
@@ -927,8 +962,8 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
   h->D = std::move(D);
   h->f = f;
   // ---- status, ranks, statistics ------------------------------------------------
-  int hflag[4] = {0, 0, 0, 0};
-  HIPCHK(hipMemcpyAsync(hflag, flag.p, 16, hipMemcpyDeviceToHost, s));
+  int hflag[5] = {0, 0, 0, 0, 0};
+  HIPCHK(hipMemcpyAsync(hflag, flag.p, 20, hipMemcpyDeviceToHost, s));
   h->rank_u.assign(nn, 0);
   h->rank_v.assign(nn, 0);
   h->skel_in.assign((size_t)nn * R, -1);
@@ -941,6 +976,7 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
   }
   HIPCHK(hipStreamSynchronize(s));
   if (hflag[0]) HM_THROW(HM_ERR_NONFINITE, "operator samples contain NaN or Inf");
+  if (hflag[4]) HM_THROW(HM_ERR_HIP, "HBS-ID sweep: a dependency wait ran past its limit");
   if (hflag[3] && !(flags & HM_FLAG_INTERNAL_NO_FALLBACK)) {
     // a node block had a leading singular value the Gram matrix cannot
     // resolve: compress again with Householder node factorisations

@@ -138,3 +138,33 @@ def test_batched_c3_instances_match_oracle():
         worst32 = max(worst32, rel(y, ohbs.from_generators(g).apply(x)))
     print(f"  FP32 storage: worst vs A {worst32:.2e}", flush=True)
     assert worst32 < 1e-5
+
+
+def test_persistent_id_sweep_equals_level_synchronous():
+    """The Fig. 5 sweep as one persistent launch over every level, side and
+    instance (HM_FLAG_PERSISTENT_ID: work items taken from a device counter,
+    a parent after both its children) and level by level (the default, one
+    launch per level and side): on exact-rank instances of the uneven batch
+    both give the same ranks and the same represented operators, each equal
+    to the operator itself."""
+    specs = W.batched_instances(256, seed=2)[:16]
+    leaf = 128
+    print(f"persistent vs level-synchronous ID sweep, {len(specs)} instances", flush=True)
+    gens = [W.synthetic_hbs(n, leaf, k, seed=3000 + i) for i, (n, k) in enumerate(specs)]
+    ops_h = [hm.hm_hbs_from_generators(g) for g in gens]
+    mk = lambda pers: [hm.Options(n, leaf, k, c3_oversample(k), seed=4000 + i, persistent_id=pers)
+                       for i, (n, k) in enumerate(specs)]
+    outs_p = hm.hbs_compress_batched(mk(True), [hm.HBSOperator(h) for h in ops_h])
+    outs_l = hm.hbs_compress_batched(mk(False), [hm.HBSOperator(h) for h in ops_h])
+    worst = 0.0
+    for (n, k), g, hp, hl in zip(specs, gens, outs_p, outs_l):
+        ep, el = hp.export(), hl.export()
+        assert np.array_equal(ep["rank_u"], el["rank_u"]) and np.array_equal(ep["rank_v"], el["rank_v"])
+        x = W.gaussian((n, 4), seed=3)
+        yp = hp.apply(torch.from_numpy(x)).cpu().numpy()
+        yl = hl.apply(torch.from_numpy(x)).cpu().numpy()
+        ya = ohbs.from_generators(g).apply(x)
+        worst = max(worst, rel(yp, yl))
+        assert rel(yp, ya) < 1e-11 and rel(yl, ya) < 1e-11
+    print(f"  worst persistent vs level-synchronous: {worst:.2e}", flush=True)
+    assert worst < 1e-12
