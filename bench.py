@@ -369,6 +369,13 @@ def backward_measurement(hm, W, torch, n=262144, leaf=128, k=32, c=64):
     s = torch.cuda.current_stream()
     tb = _event_time(torch, s, lambda: hm.hss_apply_backward(h, x, gy, stream=s), 10)
     tf = _event_time(torch, s, lambda: hm.hss_apply(h, x, stream=s), 10)
+    # the allocation-free forward apply captured once in a HIP graph and replayed
+    y = hm.fortran(n, c, torch.float32)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        hm.hss_apply_noalloc(h, x, y, stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    tg = _event_time(torch, s, g.replay, 10)
     L = int(math.ceil(math.log2(n / leaf)))
     nn = 2 ** (L + 1)
     nmax = -(-n // 2 ** L)
@@ -382,6 +389,7 @@ def backward_measurement(hm, W, torch, n=262144, leaf=128, k=32, c=64):
             "bwd_apply_hbm_frac": round(bw / PEAK_HBM_GBS, 3),
             "fwd_apply_GBps": round(fwd_bytes / tf / 1e9, 1), "fwd_apply_ms": round(tf * 1e3, 3),
             "fwd_apply_hbm_frac": round(fwd_bytes / tf / 1e9 / PEAK_HBM_GBS, 3),
+            "fwd_apply_graph_ms": round(tg * 1e3, 3),
             "apply_config": f"synthetic HBS N={n} leaf={leaf} k={k}, {c} FP32 right-hand sides"}
 
 

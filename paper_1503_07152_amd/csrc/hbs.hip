@@ -501,8 +501,23 @@ TuneKey tune_key(const Forest& f, bool bf16_kernel, int R) {
   return k;
 }
 
+namespace {
+constexpr int kRetryHouseholder = 1 << 20;   // internal status of one attempt
+}
+
+static hm_hbs_s* compress_attempt(Forest f, std::vector<OpRunner*>& ops, int32_t flags,
+                                  hipStream_t s, int* status);
+
 hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t flags, hipStream_t s,
                               int* status) {
+  hm_hbs_s* h = compress_attempt(f, ops, flags, s, status);
+  if (h || *status != kRetryHouseholder) return h;
+  for (auto* o : ops) o->reset_stats();
+  return compress_attempt(f, ops, flags | HM_FLAG_INTERNAL_NO_GRAM, s, status);
+}
+
+static hm_hbs_s* compress_attempt(Forest f, std::vector<OpRunner*>& ops, int32_t flags,
+                                  hipStream_t s, int* status) {
   auto t0 = std::chrono::steady_clock::now();
   forest_finish(f);
   std::unique_ptr<hm_hbs_s> h(new hm_hbs_s());
@@ -536,7 +551,6 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
     use_gram &= o->op.kind == HM_OP_KERNEL && o->op.sample_dtype == HM_BF16 && f.inst[i].r == R;
   }
   Workspace ws_gram;
-  const Forest f_in = f;   // for a rerun on the Householder path
   // The first product of each level (A times the masked Gaussian Omega_l)
   // does not depend on earlier levels.  The built-in BF16 kernel sampler
   // evaluates every entry of A once per call, whatever the column count, so
@@ -617,7 +631,9 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
         p.sc[l] = p.fc[l];
         continue;
       }
-      const int w = take(l + 1, std::max(l, next + nf - 1));
+      // read by level l (its second product, then the block-identity
+      // columns copied out) and by the levels whose first products it carries
+      const int w = take(l + 1, nf > 0 ? std::max(l, next + nf - 1) : l);
       p.sw[l] = w;
       p.sc[l] = 0;
       p.nr[l] = nf;
@@ -979,9 +995,10 @@ hm_hbs_s* hbs_compress_forest(Forest f, std::vector<OpRunner*>& ops, int32_t fla
   if (hflag[4]) HM_THROW(HM_ERR_HIP, "HBS-ID sweep: a dependency wait ran past its limit");
   if (hflag[3] && !(flags & HM_FLAG_INTERNAL_NO_FALLBACK)) {
     // a node block had a leading singular value the Gram matrix cannot
-    // resolve: compress again with Householder node factorisations
-    for (auto* o : ops) o->reset_stats();
-    return hbs_compress_forest(f_in, ops, flags | HM_FLAG_INTERNAL_NO_GRAM, s, status);
+    // resolve: the caller compresses again with Householder node
+    // factorisations, after this attempt's buffers are released
+    *status = kRetryHouseholder;
+    return nullptr;
   }
   if (!to_id)
     for (int g = 0; g < nn; ++g) {

@@ -87,3 +87,29 @@ def test_noalloc_apply_rejects_bad_arguments():
     assert rc == -1 and b"ld" in hm.lib.hm_last_error()
     assert hm.lib.hss_apply_noalloc(None, 2, C.c_void_p(x.data_ptr()), 512,
                                     C.c_void_p(y.data_ptr()), 512, s) == -1
+
+
+def test_noalloc_apply_replays_in_a_captured_graph():
+    """The allocation-free apply captured in a HIP graph (torch.cuda.graph on
+    its capture stream) and replayed three times, with new right-hand sides
+    copied in and eager work between the replays: every replay equals the
+    eager hss_apply of the same input."""
+    n, leaf, k, c = 8192, 128, 32, 16
+    h = hm.hm_hbs_from_generators(W.synthetic_hbs(n, leaf, k, seed=8))
+    x = hm.fortran(n, c)
+    y = hm.fortran(n, c)
+    x.copy_(torch.from_numpy(W.gaussian((n, c), seed=1)))
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        hm.hss_apply_noalloc(h, x, y, stream=torch.cuda.current_stream())
+    for rep in range(3):
+        xn = W.gaussian((n, c), seed=10 + rep)
+        x.copy_(torch.from_numpy(xn))
+        g.replay()
+        torch.cuda.synchronize()
+        want = hm.hss_apply(h, torch.from_numpy(xn)).cpu().numpy()
+        _ = torch.ones(1000, device="cuda").sum().item()      # eager work between replays
+        e = rel(y.cpu().numpy(), want)
+        say(f"  graph replay {rep}: vs eager apply {e:.2e}")
+        assert e < 1e-14
