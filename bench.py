@@ -237,6 +237,7 @@ def main():
         print(f"persistent ID sweep: {tp * 1e3:.1f} ms (median of 5)", flush=True)
         del hp
         out.update(extra_measurements(hm, W, torch, pts, n, h, ms))
+        out.update(solver_measurement(hm, W, torch, h, n))
         out.update(backward_measurement(hm, W, torch))
         out.update(synthetic_hbs_measurement(hm, W, torch))
         out.update(product_measurement(hm, W, torch))
@@ -391,6 +392,37 @@ def backward_measurement(hm, W, torch, n=262144, leaf=128, k=32, c=64):
             "fwd_apply_hbm_frac": round(fwd_bytes / tf / 1e9 / PEAK_HBM_GBS, 3),
             "fwd_apply_graph_ms": round(tg * 1e3, 3),
             "apply_config": f"synthetic HBS N={n} leaf={leaf} k={k}, {c} FP32 right-hand sides"}
+
+
+def solver_measurement(hm, W, torch, h, n):
+    """The direct solver on the compressed kernel matrix of the headline
+    step (HBS-ID form, N = 65536, leaf 128, k = 32): factor (median of 5),
+    solve with 1 and 64 right-hand sides (event-timed on the current stream,
+    10 repetitions), and the residual |A_H x - b| / |b| through the apply."""
+    f = hm.hbs_factor(h)
+    del f
+    ts = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f = hm.hbs_factor(h)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    s = torch.cuda.current_stream()
+    res = {"solver_factor_s": round(float(np.median(ts)), 4)}
+    for c in (1, 64):
+        b = torch.from_numpy(W.gaussian((n, c), seed=5)).cuda()
+        t = _event_time(torch, s, lambda: f.solve(b), 10)
+        x = f.solve(b)
+        r = float(torch.linalg.norm(h.apply(x) - b) / torch.linalg.norm(b))
+        res[f"solver_solve_ms_rhs{c}"] = round(t * 1e3, 3)
+        res[f"solver_residual_rhs{c}"] = r
+    res["solver_config"] = (f"HBS direct solver on the BF16-sampled HBS-ID form, N={n} "
+                            f"leaf={LEAF} k={K}, FP64")
+    print(f"solver: factor {res['solver_factor_s'] * 1e3:.1f} ms, solve "
+          f"{res['solver_solve_ms_rhs1']:.2f} / {res['solver_solve_ms_rhs64']:.2f} ms "
+          f"(1 / 64 rhs), residual {res['solver_residual_rhs64']:.1e}", flush=True)
+    return res
 
 
 def synthetic_hbs_measurement(hm, W, torch, n=16384, leaf=64, k=30, p=10):

@@ -46,6 +46,7 @@ extern "C" {
 #define HM_ERR_CALLBACK (-4)       /* the user's matvec callback returned != 0  */
 #define HM_ERR_NONFINITE (-5)      /* NaN/Inf in an operator sample             */
 #define HM_ERR_UNSUPPORTED (-6)    /* size beyond a documented limit            */
+#define HM_ERR_SINGULAR (-7)       /* hbs_factor: a block had a zero pivot      */
 
 /* ---- element types ------------------------------------------------------ */
 #define HM_F64 0
@@ -73,6 +74,7 @@ extern "C" {
 
 typedef struct hm_hbs_s hm_hbs;
 typedef struct hm_hodlr_s hm_hodlr;
+typedef struct hm_hbs_factor_s hm_hbs_factor;
 
 /*
  * Black-box product (Sec. 1, "T_mult"; applied to N x ncols blocks as in
@@ -307,6 +309,32 @@ int hss_apply_backward(const hm_hbs* h, int64_t nrhs, const void* x, int64_t ldx
  * serialised by the caller; calls on one stream are ordered. */
 int hss_apply_noalloc(const hm_hbs* h, int64_t nrhs, const void* x, int64_t ldx,
                       void* y, int64_t ldy, void* stream);
+
+/* Direct solver for an HBS matrix (the consumer of the compressed form the
+ * paper names in Sec. 1; the algorithm is the one of Gillman, Young and
+ * Martinsson for HBS matrices).  hbs_factor builds, from the leaves up, per
+ * node Dh = (V^* D^-1 U)^-1, E = D^-1 U Dh, F^* = Dh V^* D^-1 and
+ * G = D^-1 - D^-1 U Dh V^* D^-1, where a parent's D is [Dh_a B_ab; B_ba Dh_b]
+ * and its U, V are its transfer matrices, and inverts the root's block: then
+ * A^-1 = E (Dh + A~)^-1 F^* + G level by level.  Requirements: an FP64,
+ * single-tree handle with at least one level, every non-root node of the same
+ * incoming and outgoing rank k (fixed-rank compressions and handles from
+ * generators), leaves of at most 128 rows.  Block inversions are Gauss-Jordan
+ * with partial pivoting; a zero or non-finite pivot gives HM_ERR_SINGULAR.
+ * Other handles give HM_ERR_ARG (dtype, forest, rank 0) or HM_ERR_UNSUPPORTED
+ * (mixed ranks, larger leaves).  No pivoting happens across levels, so the
+ * error grows with the conditioning of the D blocks and of V^* D^-1 U, not
+ * only with cond(A).  The factor is independent of the handle (which may be
+ * freed) and owned by the library (hm_hbs_factor_free; NULL is a no-op);
+ * hbs_factor returns when it is complete.  Device memory: 8 (3 N k + N nmax
+ * + nodes (k^2 + 8 k^2)) bytes, plus the same again as work during the call.
+ * hbs_solve: x = A_H^-1 b for an n x nrhs FP64 block b (device, column-major,
+ * leading dims >= n; HM_ERR_ARG otherwise); enqueued on `stream`, in chunks
+ * of 128 columns; x and b must not overlap. */
+int hbs_factor(const hm_hbs* h, void* stream, hm_hbs_factor** out);
+int hbs_solve(const hm_hbs_factor* f, int64_t nrhs, const double* b, int64_t ldb, double* x,
+              int64_t ldx, void* stream);
+void hm_hbs_factor_free(hm_hbs_factor* f);
 
 /* HODLR apply: y = A_H x (adjoint = 0) or A_H^* x; FP64. */
 int hodlr_apply(const hm_hodlr* h, int32_t adjoint, int64_t nrhs,

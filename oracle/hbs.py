@@ -353,6 +353,13 @@ def hbs_id(h: HBS, y: dict, z: dict, rank: int | None, tol: float | None, r: int
     return h
 
 
+def solve(h: HBS, b: np.ndarray) -> np.ndarray:
+    """``x = A_H^-1 b`` by its plain definition: LU (LAPACK) of the densified
+    represented matrix (small N only); the reference for the fast direct
+    solver built on the compressed form."""
+    return np.linalg.solve(h.dense(), np.asarray(b, dtype=np.float64))
+
+
 # ---------------------------------------------------------------------------
 # Building an HBS from flat generator arrays (the synthetic operators)
 # ---------------------------------------------------------------------------

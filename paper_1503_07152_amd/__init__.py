@@ -23,7 +23,7 @@ __all__ = [
     "Options", "KernelOperator", "DenseOperator", "HBSOperator", "HBSProductOperator",
     "CallbackOperator",
     "HBS", "HODLR", "hm_gauss", "hm_operator_apply", "hbs_compress", "hbs_compress_adaptive",
-    "hodlr_compress", "hbs_compress_batched", "autotune",
+    "hodlr_compress", "hbs_compress_batched", "autotune", "hbs_factor", "HBSFactor",
     "hss_apply", "hss_apply_adjoint", "hss_apply_noalloc", "hss_apply_backward", "hodlr_apply",
     "hm_hbs_from_generators", "hbs_from_tensors", "HBSApply", "hbs_apply", "use_torch_allocator",
 ]
@@ -118,6 +118,9 @@ _SIGS = {
     "hm_hbs_export": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "hm_hodlr_export": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "hm_hbs_free": (None, [_P]),
+    "hbs_factor": (C.c_int, [_P, _P, C.POINTER(_P)]),
+    "hbs_solve": (C.c_int, [_P, _I64, _P, _I64, _P, _I64, _P]),
+    "hm_hbs_factor_free": (None, [_P]),
     "hm_hodlr_free": (None, [_P]),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -427,6 +430,37 @@ class HBS:
 
     def apply(self, x, adjoint=False, stream=None):
         return (hss_apply_adjoint if adjoint else hss_apply)(self, x, stream=stream)
+
+
+class HBSFactor:
+    """A factorisation of the inverse of an HBS matrix (``hbs_factor``);
+    ``solve(b)`` returns ``A_H^-1 b`` (FP64)."""
+
+    def __init__(self, handle):
+        self.handle = handle
+        _LIVE.add(self)
+
+    _free = lib.hm_hbs_factor_free
+
+    def _release(self):
+        if getattr(self, "handle", None):
+            type(self)._free(self.handle)
+            self.handle = None
+
+    __del__ = _release
+
+    def solve(self, b, stream=None):
+        bf = to_fortran(b, torch.float64)
+        x = fortran(bf.shape[0], bf.shape[1])
+        _check(lib.hbs_solve(self.handle, bf.shape[1], _ptr(bf), _ld(bf), _ptr(x), _ld(x),
+                             _stream(stream)))
+        return x
+
+
+def hbs_factor(h, stream=None) -> HBSFactor:
+    f = C.c_void_p()
+    _check(lib.hbs_factor(h.handle, _stream(stream), C.byref(f)))
+    return HBSFactor(f)
 
 
 class HODLR:

@@ -309,3 +309,15 @@ def test_adaptive_sampling_stops_at_the_sample_limit():
                                       r_max=32)
     assert [r[0] for r in rounds] == [6, 12, 24]
     assert rounds[-1][1] is True
+
+
+def test_dense_solve_of_the_represented_matrix():
+    """The solver reference is the plain definition x = A_H^-1 b: its
+    residual A_H x - b vanishes to rounding (relative to |A_H| |x|)."""
+    n, leaf, k = 512, 64, 8
+    h = hbs.from_generators(W.synthetic_hbs(n, leaf, k, seed=5))
+    b = W.gaussian((n, 3), seed=1)
+    x = hbs.solve(h, b)
+    A = h.dense()
+    res = np.linalg.norm(A @ x - b) / (np.linalg.norm(A) * np.linalg.norm(x))
+    assert res < 1e-15
