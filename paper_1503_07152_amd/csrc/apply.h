@@ -8,13 +8,22 @@
 
 namespace hm {
 
-// Node lists of one apply: frontier (each active instance's nodes on its level
-// m_i) and, for l = 1 .. mmax-1, the internal nodes on level l (ancestors of
-// frontier nodes).  Built once on the host, kept on the device.
-// A node of a tree sweep with its children's / sibling's ids (one load per
-// workgroup instead of a chain of node-table lookups).
-struct TreeOp {
-  int32_t t, left, right, sib;
+// Node lists of one apply: the frontier (each active instance's nodes on its
+// level m_i) and the tree sweeps over the internal nodes (levels 1 .. m_i - 1,
+// ancestors of frontier nodes) cut into bands of levels.  Built once on the
+// host, kept on the device.
+// A subtree of a tree sweep taken by one workgroup of a band kernel: its
+// nodes in breadth-first order (ids[0] the subtree root, the children of
+// entry b at 2b + 1 and 2b + 2) down to `depth` levels below the root;
+// info = depth | has_parent << 8 (down sweep: the root's own incoming
+// expansion contributes).  Unused ids are -1.
+constexpr int BAND_DMAX = 3;
+struct BandJob {
+  int32_t info;
+  int32_t ids[(2 << BAND_DMAX) - 1];
+};
+struct BandRange {
+  int off, n;   // jobs [off, off + n) of one launch
 };
 
 struct ApplyLists {
@@ -22,11 +31,12 @@ struct ApplyLists {
   int nfront = 0;
   int64_t max_rows = 0;     // largest frontier node
   int chunks = 1;           // row chunks per frontier node for the V^T x reduction
-  std::vector<DevBuf> internal;   // TreeOp per internal node on level l (index 0 unused)
-  std::vector<int> ninternal;
-  DevBuf level1;                  // TreeOp per level-1 node
-  int nlevel1 = 0;
   int mmax = 0;
+  // Band launches for band depths D = 1 .. BAND_DMAX (index D), in launch
+  // order: up = finest band first, down = the roots' band first; all jobs in
+  // one device array.
+  DevBuf bands;
+  std::vector<BandRange> up_band[BAND_DMAX + 1], down_band[BAND_DMAX + 1];
 };
 
 constexpr int APPLY_CHUNK = 256;

@@ -9,37 +9,68 @@ namespace hm {
 void build_apply_lists(const Forest& f, const std::vector<int>& m, ApplyLists& out,
                        hipStream_t s) {
   std::vector<int32_t> front;
-  std::vector<TreeOp> lvl1;
   int mmax = 0;
   for (int i = 0; i < (int)f.inst.size(); ++i) mmax = std::max(mmax, m[i]);
-  std::vector<std::vector<TreeOp>> inter(std::max(mmax, 1));
   int64_t maxr = 0;
   for (int g = 0; g < (int)f.nodes.size(); ++g) {
     const Node& nd = f.nodes[g];
     const int mi = m[nd.inst];
-    if (mi < 0) continue;
-    if (nd.level == mi) {
+    if (mi >= 0 && nd.level == mi) {
       front.push_back(g);
       maxr = std::max<int64_t>(maxr, nd.hi - nd.lo);
     }
-    const TreeOp op{g, nd.left, nd.right, nd.sib};
-    if (nd.level >= 1 && nd.level < mi) inter[nd.level].push_back(op);
-    if (nd.level == 1 && mi >= 1) lvl1.push_back(op);
   }
   out.nfront = (int)front.size();
   out.frontier = upload(front, s);
   out.max_rows = maxr;
   out.chunks = (int)std::max<int64_t>(1, (maxr + APPLY_CHUNK - 1) / APPLY_CHUNK);
   out.mmax = mmax;
-  out.internal.clear();
-  out.ninternal.assign(std::max(mmax, 1), 0);
-  out.internal.resize(std::max(mmax, 1));
-  for (int l = 1; l < mmax; ++l) {
-    out.ninternal[l] = (int)inter[l].size();
-    out.internal[l] = upload(inter[l], s);
+  // Bands.  Up: levels [lo, hi] from the deepest internal level M = mmax - 1
+  // upwards, one job per internal node on level lo, down to min(hi, m_i - 1)
+  // (its children below are inputs).  Down: jobs rooted on levels 0, D, 2D ...
+  // (instance roots or internal nodes), each computing the incoming
+  // expansions of its descendants down to D levels below (at most to m_i).
+  std::vector<BandJob> jobs;
+  auto job = [&](int g, int d, int info) {
+    BandJob jb;
+    jb.info = info;
+    for (int32_t& x : jb.ids) x = -1;
+    jb.ids[0] = g;
+    for (int b = 0; b < (1 << d) - 1; ++b) {
+      const Node& nd = f.nodes[jb.ids[b]];
+      jb.ids[2 * b + 1] = nd.left;
+      jb.ids[2 * b + 2] = nd.right;
+    }
+    jobs.push_back(jb);
+  };
+  const int M = mmax - 1;
+  for (int D = 1; D <= BAND_DMAX; ++D) {
+    out.up_band[D].clear();
+    out.down_band[D].clear();
+    for (int hi = M; hi >= 1; hi -= D) {
+      const int lo = std::max(1, hi - D + 1);
+      BandRange br{(int)jobs.size(), 0};
+      for (int g : f.level[lo]) {
+        const int mi = m[f.nodes[g].inst];
+        if (mi < 0 || lo >= mi) continue;
+        job(g, std::min(hi, mi - 1) - lo + 1, std::min(hi, mi - 1) - lo + 1);
+      }
+      br.n = (int)jobs.size() - br.off;
+      if (br.n > 0) out.up_band[D].push_back(br);
+    }
+    for (int lo = 0; lo <= M; lo += D) {
+      BandRange br{(int)jobs.size(), 0};
+      for (int g : f.level[lo]) {
+        const int mi = m[f.nodes[g].inst];
+        if (mi < 1 || lo >= mi) continue;
+        const int d = std::min(D, mi - lo);
+        job(g, d, d | (lo >= 1 ? 1 << 8 : 0));
+      }
+      br.n = (int)jobs.size() - br.off;
+      if (br.n > 0) out.down_band[D].push_back(br);
+    }
   }
-  out.nlevel1 = (int)lvl1.size();
-  out.level1 = upload(lvl1, s);
+  out.bands = upload(jobs, s);
 }
 
 constexpr int TM = MF_T, TN = MF_T;   // output tile of the MFMA products
@@ -77,181 +108,326 @@ __global__ void k_chunk_reduce(const int32_t* front, int chunks, const T* P, int
   }
 }
 
-// ---- tree sweeps ------------------------------------------------------------
-// One node (and a tile of TRC columns) per workgroup: out (R x TRC) = A1 B1 +
-// A2 B2 with R x R coefficient blocks A_h (strided: A_h(i, k) = a_h[i sai +
-// k sak]) and expansions B_h (R x TRC, ld R), R <= HM_MAX_SAMPLES.  Every
-// operand is staged in LDS in one round (no K loop over global memory: K <=
-// 2 R_max), so a level costs one global round trip; K is padded with zeros
-// to a multiple of 8 and the product runs 8 K-steps per batch of LDS loads.
-// Thread (ti, tj) holds rows ti + 16 u and columns 2 tj, 2 tj + 1.
+// ---- tree sweeps: band kernels ---------------------------------------------
+// Several tree levels per launch.  A workgroup takes one subtree (BandJob) and
+// a tile of BC columns, stages every operand it needs in LDS in one round
+// (coefficient blocks as A(i, k) at k * RP + i, expansions as (k, j) at
+// k * VP + j, rows padded with zeros to R4 = a multiple of 4), then runs the
+// node products level by level out of LDS on the matrix cores (16 x 16 output
+// tiles, MFMA 16x16x4; the tiles of one level's products spread over the
+// four waves), writing each result to global memory (for the other sweep and
+// the leaves) and, when a product above needs it, to LDS.
+// Up: qh_t = Vt_t^T [qh_a; qh_b].  Down: for child a of t with sibling s,
+// uh_a = Ut_t(half of a) uh_t + B[s] qh_s (forward) or B[a]^T qh_s (adjoint);
+// the children of a root take only the second term.
 constexpr int TRM = HM_MAX_SAMPLES;   // largest padded rank
-constexpr int TRC = 32;               // columns per workgroup
-constexpr int TRK = 8;                // K-steps per batch
 
+template <class T> struct BandCfg;
+template <> struct BandCfg<float> { static constexpr int BC = 32; };
+template <> struct BandCfg<double> { static constexpr int BC = 16; };
+
+// LDS elements of an up band / a down band of depth d (rows R4 per block).
+constexpr int band_up_elems(int R4, int BC, int d) {
+  return ((2 << d) - 1) * R4 * (BC + 1) + ((1 << d) - 1) * 2 * R4 * (R4 + 1);
+}
+constexpr int band_down_elems(int R4, int BC, int d) {
+  return 2 * ((2 << d) - 1) * R4 * (BC + 1) + ((2 << d) - 2) * 2 * R4 * (R4 + 1);
+}
+constexpr int BAND_LDS_MAX = 158 * 1024;   // of the 160 KiB per workgroup
+constexpr int BAND_SLACK = 64;             // tile rows read past the last block
 template <class T>
-struct TreeSmem {
-  T a[2 * TRM][TRM + 1];   // A(i, k) at a[k][i] (both halves stacked along k)
-  T b[2 * TRM][TRC];       // B(k, j)
+constexpr int band_depth_up(int RC) {
+  int d = BAND_DMAX;
+  while (d > 1 &&
+         (band_up_elems(RC, BandCfg<T>::BC, d) + BAND_SLACK) * (int)sizeof(T) > BAND_LDS_MAX)
+    --d;
+  return d;
+}
+template <class T>
+constexpr int band_depth_down(int RC) {
+  int d = BAND_DMAX;
+  while (d > 1 &&
+         (band_down_elems(RC, BandCfg<T>::BC, d) + BAND_SLACK) * (int)sizeof(T) > BAND_LDS_MAX)
+    --d;
+  return d;
+}
+
+// e / d for 0 <= e < 2^32 / d (d <= 2^16): one high multiply.
+struct FastDiv {
+  uint32_t m;
+  __device__ explicit FastDiv(uint32_t d) : m(0xFFFFFFFFu / d + 1u) {}
+  __device__ __forceinline__ int div(int e) const { return (int)__umulhi((uint32_t)e, m); }
 };
 
-// Staging loops run over fixed trip counts (R <= 64 along the unit stride,
-// four rows per pass of 256 threads): all of a thread's global loads are
-// issued before the first LDS store, so a stage costs one memory latency
-// rather than one per element.
-template <class T>
-__device__ __forceinline__ void stage_coef(int R, int k0, const T* a, int64_t sai, int64_t sak,
-                                           TreeSmem<T>& sm) {
-  static_assert(TRM <= 64, "one 64-lane row per coefficient column");
-  const int tid = threadIdx.x;
-  const int lo = tid & 63, hi = tid >> 6;
-  constexpr int NQ = TRM / 4;
-  T v[NQ];
-  if (sai == 1) {   // i along the unit stride: lane lo takes row i = lo of columns k
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int k = hi + 4 * q;
-      v[q] = (lo < R && k < R) ? a[lo + (int64_t)k * sak] : T(0);
-    }
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int k = hi + 4 * q;
-      if (lo < R && k < R) sm.a[k0 + k][lo] = v[q];
-    }
-  } else {          // k along the unit stride
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int i = hi + 4 * q;
-      v[q] = (lo < R && i < R) ? a[(int64_t)i * sai + (int64_t)lo * sak] : T(0);
-    }
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int i = hi + 4 * q;
-      if (lo < R && i < R) sm.a[k0 + lo][i] = v[q];
-    }
-  }
-}
+template <class T, int V>
+struct alignas(sizeof(T) * V) BandVec {
+  T v[V];
+};
 
-template <class T, int NU>
-__device__ __forceinline__ void tree_mac(int Kp, int ti, int tj, const TreeSmem<T>& sm,
-                                         T (&acc)[3][2]) {
-  for (int k0 = 0; k0 < Kp; k0 += TRK) {
-    T av[TRK][NU], bv[TRK][2];
+// Chunks e in [0, n) of V consecutive source elements: map(e, p, d0, ds) gives
+// the source address and the LDS offsets d0, d0 + ds, ... of the chunk's
+// elements.  NB chunks per thread are loaded before any is stored.
+template <class T, int V, int NB, class Map>
+__device__ __forceinline__ void band_stage(int n, T* lds, Map map) {
+  for (int base = 0; base < n; base += 256 * NB) {
+    BandVec<T, V> v[NB];
+    int d0[NB], ds[NB];
 #pragma unroll
-    for (int q = 0; q < TRK; ++q) {
-#pragma unroll
-      for (int u = 0; u < NU; ++u) av[q][u] = sm.a[k0 + q][ti + 16 * u];
-      bv[q][0] = sm.b[k0 + q][2 * tj];
-      bv[q][1] = sm.b[k0 + q][2 * tj + 1];
-    }
-#pragma unroll
-    for (int q = 0; q < TRK; ++q)
-#pragma unroll
-      for (int u = 0; u < NU; ++u) {
-        acc[u][0] = fma(av[q][u], bv[q][0], acc[u][0]);
-        acc[u][1] = fma(av[q][u], bv[q][1], acc[u][1]);
+    for (int q = 0; q < NB; ++q) {
+      const int e = base + q * 256 + (int)threadIdx.x;
+      d0[q] = -1;
+      ds[q] = 0;
+      if (e < n) {
+        const T* p;
+        map(e, p, d0[q], ds[q]);
+        v[q] = *reinterpret_cast<const BandVec<T, V>*>(p);
       }
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+      if (d0[q] >= 0)
+#pragma unroll
+        for (int t = 0; t < V; ++t) lds[d0[q] + t * ds[q]] = v[q].v[t];
   }
 }
 
+// acc += A(r0 + 0..15, 0:4 nk4) B(0:4 nk4, c0 + 0..15) on the matrix cores:
+// a = &A(r0, 0) with A(i, k) at k * RP + i; b = &B(0, c0) with B(k, j) at
+// k * VP + j.
 template <class T>
-__device__ __forceinline__ void tree_product(int R, int nc, int nparts, const T* a1, int64_t sai1,
-                                             int64_t sak1, const T* b1, const T* a2,
-                                             int64_t sai2, int64_t sak2, const T* b2, T* out,
-                                             TreeSmem<T>& sm) {
-  const int tid = threadIdx.x;
-  const int K = nparts * R;
-  const int Kp = (K + TRK - 1) / TRK * TRK;
-  stage_coef<T>(R, 0, a1, sai1, sak1, sm);
-  if (nparts == 2) stage_coef<T>(R, R, a2, sai2, sak2, sm);
-  for (int e = tid; e < (Kp - K) * TRM; e += 256) sm.a[K + e / TRM][e % TRM] = T(0);
+__device__ __forceinline__ void band_tile(int nk4, int RP, int VP, const T* a, const T* b,
+                                          typename MfTraits<T>::acc_t& acc) {
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  a += lk * RP + li;
+  b += lk * VP + li;
+  int s = 0;
+  for (; s + 4 <= nk4; s += 4) {
+    T av[4], bv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      av[u] = a[u * 4 * RP];
+      bv[u] = b[u * 4 * VP];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc = MfTraits<T>::step(av[u], bv[u], acc);
+    a += 16 * RP;
+    b += 16 * VP;
+  }
+  for (; s < nk4; ++s) {
+    acc = MfTraits<T>::step(a[0], b[0], acc);
+    a += 4 * RP;
+    b += 4 * VP;
+  }
+}
+
+// Tile (rt, ct) of a product: rows rt*16 + ..., columns ct*16 + ... of the
+// node's R x nc block (global, ld R) and, if lds_blk, of its LDS block.
+template <class T>
+__device__ __forceinline__ void band_put(const typename MfTraits<T>::acc_t& acc, int rt, int ct,
+                                         int R, int nc, T* out, T* lds_blk, int VP) {
+  const int lane = threadIdx.x & 63;
+  const int j = ct * 16 + (lane & 15);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = rt * 16 + MfTraits<T>::row(lane, v);
+    if (i < R && j < nc) {
+      out[i + (int64_t)j * R] = acc[v];
+      if (lds_blk) lds_blk[i * VP + j] = acc[v];
+    }
+  }
+}
+
+// Zero rows R .. R4-1 of nblk blocks of `rows` rows (pitch P) at lds, block
+// stride bs; rows_off: first padded row of each half (up to two halves).
+template <class T>
+__device__ __forceinline__ void band_zero_pad(T* lds, int nblk, int bs, int P, int R, int R4,
+                                              int halves) {
+  const int pr = R4 - R;
+  if (pr == 0) return;
+  const int per = halves * pr * P;
+  for (int e = threadIdx.x; e < nblk * per; e += 256) {
+    const int q = e / per, r = e - q * per;
+    const int h = r / (pr * P), r2 = r - h * pr * P;
+    const int row = h * R4 + R + r2 / P, col = r2 % P;
+    lds[q * bs + row * P + col] = T(0);
+  }
+}
+
+template <class T, int RC, int V>
+__global__ __launch_bounds__(256) void k_band_up(const BandJob* jobs, const T* Tout, int R,
+                                                 T* QH, int c) {
+  typedef MfTraits<T> Tr;
+  constexpr int BC = BandCfg<T>::BC, CT = BC / 16;
+  constexpr int DM = band_depth_up<T>(RC);
+  __shared__ T lds[band_up_elems(RC, BC, DM) + BAND_SLACK];
+  __shared__ int sids[16];
+  const int tid = threadIdx.x, wave = tid >> 6;
+  if (tid < 16) sids[tid] = tid == 0 ? jobs[blockIdx.x].info : jobs[blockIdx.x].ids[tid - 1];
+  __syncthreads();
+  const int d = sids[0] & 0xff;
+  const int* ids = sids + 1;
+  const int j0 = blockIdx.y * BC, nc = min(BC, c - j0);
+  const int R4 = (R + 3) & ~3, VP = BC + 1, RP = R4 + 1;
+  const int nprod = (1 << d) - 1, nnode = (2 << d) - 1;
+  T* vals = lds;                         // node b: R4 x VP at b * R4 * VP
+  T* cf = lds + nnode * R4 * VP;         // product p: 2 R4 x RP at p * 2 R4 * RP
+  band_zero_pad(vals, nnode, R4 * VP, VP, R, R4, 1);
+  band_zero_pad(cf, nprod, 2 * R4 * RP, RP, R, R4, 2);
   {
-    // B (Kp x TRC, Kp <= 2 TRM = 96): lane kl = tid % 32 takes k = kl + 32 h,
-    // column j = tid / 32 + 8 w
-    static_assert(2 * TRM <= 96 && TRC == 32, "B staging covers 96 x 32");
-    const int kl = tid & 31, jl = tid >> 5;
-    T bv[3][4];
-#pragma unroll
-    for (int h = 0; h < 3; ++h)
-#pragma unroll
-      for (int w = 0; w < 4; ++w) {
-        const int k = kl + 32 * h, j = jl + 8 * w;
-        const bool second = k >= R;
-        const int kk = second ? k - R : k;
-        T v = T(0);
-        if (k < K && j < nc) v = second ? b2[kk + (int64_t)j * R] : b1[kk + (int64_t)j * R];
-        bv[h][w] = v;
+    // the qh blocks of the children below the band (R x nc, contiguous), then
+    // the transfer blocks Tout_t (2R x R, ld 2R) as A(i, k) = Tout_t(k, i)
+    const int cin = R * nc / V, ccf = 2 * R * R / V;
+    const int n1 = (nnode - nprod) * cin;
+    const FastDiv din(cin), dcf(ccf), dr(R), d2r(2 * R);
+    band_stage<T, V, 24>(n1 + nprod * ccf, lds, [&](int e, const T*& p, int& d0, int& ds) {
+      if (e < n1) {
+        const int q = din.div(e), rem = (e - q * cin) * V;
+        const int jj = dr.div(rem), i = rem - jj * R;
+        p = QH + (int64_t)ids[nprod + q] * R * c + (int64_t)j0 * R + rem;
+        d0 = (nprod + q) * R4 * VP + i * VP + jj;
+        ds = VP;
+      } else {
+        const int e2 = e - n1, q = dcf.div(e2), rem = (e2 - q * ccf) * V;
+        const int i = d2r.div(rem), k = rem - i * 2 * R;
+        const int kk = k < R ? k : k - R + R4;
+        p = Tout + (int64_t)ids[q] * 2 * R * R + rem;
+        d0 = nnode * R4 * VP + q * 2 * R4 * RP + kk * RP + i;
+        ds = RP;
       }
-#pragma unroll
-    for (int h = 0; h < 3; ++h)
-#pragma unroll
-      for (int w = 0; w < 4; ++w) {
-        const int k = kl + 32 * h;
-        if (k < Kp) sm.b[k][jl + 8 * w] = bv[h][w];
-      }
+    });
   }
   __syncthreads();
-  const int ti = tid & 15, tj = tid >> 4;
-  T acc[3][2];
-#pragma unroll
-  for (int u = 0; u < 3; ++u) acc[u][0] = acc[u][1] = T(0);
-  const int nu = (R + 15) / 16;
-  if (nu == 3) tree_mac<T, 3>(Kp, ti, tj, sm, acc);
-  else if (nu == 2) tree_mac<T, 2>(Kp, ti, tj, sm, acc);
-  else tree_mac<T, 1>(Kp, ti, tj, sm, acc);
-#pragma unroll
-  for (int u = 0; u < 3; ++u)
-#pragma unroll
-    for (int w = 0; w < 2; ++w) {
-      const int i = ti + 16 * u, j = 2 * tj + w;
-      if (u < nu && i < R && j < nc) out[i + (int64_t)j * R] = acc[u][w];
+  const int NT = (R + 15) / 16, tiles = NT * CT;
+  for (int j = d - 1; j >= 0; --j) {
+    const int p0 = (1 << j) - 1, ntile = (1 << j) * tiles;
+    for (int q = wave; q < ntile; q += 4) {
+      const int p = p0 + q / tiles, r = q % tiles, rt = r / CT, ct = r % CT;
+      typename Tr::acc_t acc = {0, 0, 0, 0};
+      band_tile<T>(2 * R4 / 4, RP, VP, cf + p * 2 * R4 * RP + rt * 16,
+                   vals + (2 * p + 1) * R4 * VP + ct * 16, acc);
+      band_put<T>(acc, rt, ct, R, nc, QH + (int64_t)ids[p] * R * c + (int64_t)j0 * R,
+                  j > 0 ? vals + p * R4 * VP : nullptr, VP);
     }
+    __syncthreads();
+  }
 }
 
-// Upward pass, one level: qh_t = Vt_t^T [qh_left; qh_right].
-template <class T>
-__global__ __launch_bounds__(256) void k_tree_up(const TreeOp* list, const T* Vt, int R, T* QH,
-                                                 int c) {
-  __shared__ TreeSmem<T> sm;
-  const TreeOp op = list[blockIdx.x];
-  const int j0 = blockIdx.y * TRC;
-  const T* vt = Vt + (int64_t)op.t * 2 * R * R;
-  tree_product<T>(R, min(TRC, c - j0), 2, vt, 2 * R, 1,
-                  QH + (int64_t)op.left * R * c + (int64_t)j0 * R, vt + R, 2 * R, 1,
-                  QH + (int64_t)op.right * R * c + (int64_t)j0 * R,
-                  QH + (int64_t)op.t * R * c + (int64_t)j0 * R, sm);
-}
-
-// Incoming expansion of node a from its sibling s's outgoing one: forward
-// uh_a = B[s] qh_s, adjoint uh_a = B[a]^T qh_s; below level 1 plus the
-// parent's term Ut_t(half of a) uh_t.
-template <class T>
-__global__ __launch_bounds__(256) void k_root(const TreeOp* list, const T* B, int R, const T* QH,
-                                              T* UH, int c, int adjoint) {
-  __shared__ TreeSmem<T> sm;
-  const TreeOp op = list[blockIdx.x];
-  const int a = op.t, s = op.sib;
-  const int j0 = blockIdx.y * TRC;
-  const T* bm = adjoint ? B + (int64_t)a * R * R : B + (int64_t)s * R * R;
-  tree_product<T>(R, min(TRC, c - j0), 1, bm, adjoint ? R : 1, adjoint ? 1 : R,
-                  QH + (int64_t)s * R * c + (int64_t)j0 * R, bm, 0, 0, nullptr,
-                  UH + (int64_t)a * R * c + (int64_t)j0 * R, sm);
-}
-
-template <class T>
-__global__ __launch_bounds__(256) void k_tree_down(const TreeOp* list, const T* Ut, const T* B,
-                                                   int R, const T* QH, T* UH, int c,
+template <class T, int RC, int V>
+__global__ __launch_bounds__(256) void k_band_down(const BandJob* jobs, const T* Tin,
+                                                   const T* B, int R, const T* QH, T* UH, int c,
                                                    int adjoint) {
-  __shared__ TreeSmem<T> sm;
-  const TreeOp op = list[blockIdx.x];
-  const int side = blockIdx.y;  // 0: left child, 1: right child
-  const int j0 = blockIdx.z * TRC;
-  const int a = side == 0 ? op.left : op.right, s = side == 0 ? op.right : op.left;
-  const T* bm = adjoint ? B + (int64_t)a * R * R : B + (int64_t)s * R * R;
-  tree_product<T>(R, min(TRC, c - j0), 2, Ut + (int64_t)op.t * 2 * R * R + side * R, 1, 2 * R,
-                  UH + (int64_t)op.t * R * c + (int64_t)j0 * R, bm, adjoint ? R : 1,
-                  adjoint ? 1 : R, QH + (int64_t)s * R * c + (int64_t)j0 * R,
-                  UH + (int64_t)a * R * c + (int64_t)j0 * R, sm);
+  typedef MfTraits<T> Tr;
+  constexpr int BC = BandCfg<T>::BC, CT = BC / 16;
+  constexpr int DM = band_depth_down<T>(RC);
+  __shared__ T lds[band_down_elems(RC, BC, DM) + BAND_SLACK];
+  __shared__ int sids[16];
+  const int tid = threadIdx.x, wave = tid >> 6;
+  if (tid < 16) sids[tid] = tid == 0 ? jobs[blockIdx.x].info : jobs[blockIdx.x].ids[tid - 1];
+  __syncthreads();
+  const int d = sids[0] & 0xff;
+  const bool has_parent = (sids[0] >> 8) & 1;
+  const int* ids = sids + 1;
+  const int j0 = blockIdx.y * BC, nc = min(BC, c - j0);
+  const int R4 = (R + 3) & ~3, VP = BC + 1, RP = R4 + 1;
+  const int nnode = (2 << d) - 1;
+  T* uhv = lds;                          // node b: R4 x VP
+  T* qhv = lds + nnode * R4 * VP;        // node b: R4 x VP
+  T* cf = lds + 2 * nnode * R4 * VP;     // node b >= 1: 2 R4 x RP at (b - 1) * 2 R4 * RP
+  band_zero_pad(uhv, 2 * nnode, R4 * VP, VP, R, R4, 1);
+  band_zero_pad(cf, nnode - 1, 2 * R4 * RP, RP, R, R4, 2);
+  {
+    // uh of the root (if it has a parent), qh of every node below it (each is
+    // a sibling), per node b >= 1 the parent's transfer half (A rows 0..R-1)
+    // and the sibling coupling (A rows R4 ..)
+    const int cin = R * nc / V, crr = R * R / V;
+    const int n0 = has_parent ? cin : 0;
+    const int n1 = n0 + (nnode - 1) * cin, n2 = n1 + (nnode - 1) * crr;
+    const int n3 = n2 + (nnode - 1) * crr;
+    const FastDiv din(cin), drr(crr), dr(R);
+    const int cfo = 2 * nnode * R4 * VP;
+    band_stage<T, V, 24>(n3, lds, [&](int e, const T*& p, int& d0, int& ds) {
+      if (e < n1) {
+        const int e1 = e < n0 ? e : e - n0;
+        const int q = e < n0 ? 0 : din.div(e1), rem = (e1 - q * cin) * V;
+        const int jj = dr.div(rem), i = rem - jj * R;
+        const int b = e < n0 ? 0 : 1 + q;
+        p = (e < n0 ? (const T*)UH : QH) + (int64_t)ids[b] * R * c + (int64_t)j0 * R + rem;
+        d0 = (e < n0 ? 0 : nnode * R4 * VP + b * R4 * VP) + i * VP + jj;
+        ds = VP;
+      } else if (e < n2) {
+        const int e2 = e - n1, q = drr.div(e2), rem = (e2 - q * crr) * V;
+        const int k = dr.div(rem), i = rem - k * R;
+        const int b = 1 + q, side = (b & 1) ? 0 : 1;
+        p = Tin + (int64_t)ids[(b - 1) >> 1] * 2 * R * R + side * R + i + (int64_t)k * 2 * R;
+        d0 = cfo + q * 2 * R4 * RP + k * RP + i;
+        ds = 1;
+      } else {
+        const int e3 = e - n2, q = drr.div(e3), rem = (e3 - q * crr) * V;
+        const int hi = dr.div(rem), lo = rem - hi * R;
+        const int b = 1 + q, sib = (b & 1) ? b + 1 : b - 1;
+        // forward A(i, k) = B[sib](i, k) = B[sib][i + k R]; adjoint A(i, k) = B[b][k + i R]
+        p = B + (int64_t)ids[adjoint ? b : sib] * R * R + rem;
+        d0 = cfo + q * 2 * R4 * RP + (adjoint ? (R4 + lo) * RP + hi : (R4 + hi) * RP + lo);
+        ds = adjoint ? RP : 1;
+      }
+    });
+  }
+  __syncthreads();
+  const int NT = (R + 15) / 16, tiles = NT * CT;
+  for (int j = 1; j <= d; ++j) {
+    const bool up_term = j >= 2 || has_parent;
+    const int b0 = (1 << j) - 1, ntile = (1 << j) * tiles;
+    for (int q = wave; q < ntile; q += 4) {
+      const int b = b0 + q / tiles, r = q % tiles, rt = r / CT, ct = r % CT;
+      const int par = (b - 1) >> 1, sib = (b & 1) ? b + 1 : b - 1;
+      const T* cb = cf + (b - 1) * 2 * R4 * RP + rt * 16;
+      typename Tr::acc_t acc = {0, 0, 0, 0};
+      if (up_term) band_tile<T>(R4 / 4, RP, VP, cb, uhv + par * R4 * VP + ct * 16, acc);
+      band_tile<T>(R4 / 4, RP, VP, cb + R4 * RP, qhv + sib * R4 * VP + ct * 16, acc);
+      band_put<T>(acc, rt, ct, R, nc, UH + (int64_t)ids[b] * R * c + (int64_t)j0 * R,
+                  j < d ? uhv + b * R4 * VP : nullptr, VP);
+    }
+    __syncthreads();
+  }
+}
+
+template <class T, int RC, int V>
+void run_bands(const ApplyLists& al, const HbsView<T>& h, bool adjoint, int c, T* QH, T* UH,
+               hipStream_t s) {
+  constexpr int BC = BandCfg<T>::BC;
+  constexpr int DU = band_depth_up<T>(RC), DD = band_depth_down<T>(RC);
+  const int ctt = (c + BC - 1) / BC;
+  const BandJob* jobs = al.bands.as<BandJob>();
+  const T* Tin = adjoint ? h.Vt : h.Ut;
+  const T* Tout = adjoint ? h.Ut : h.Vt;
+  for (const BandRange& b : al.up_band[DU]) {
+    hipLaunchKernelGGL((k_band_up<T, RC, V>), dim3(b.n, ctt), dim3(256), 0, s, jobs + b.off, Tout,
+                       h.R, QH, c);
+    KCHK();
+  }
+  for (const BandRange& b : al.down_band[DD]) {
+    hipLaunchKernelGGL((k_band_down<T, RC, V>), dim3(b.n, ctt), dim3(256), 0, s, jobs + b.off,
+                       Tin, h.B, h.R, (const T*)QH, UH, c, adjoint ? 1 : 0);
+    KCHK();
+  }
+}
+
+// Vector staging (16-byte loads) needs R a multiple of the vector width and
+// 16-byte aligned operand arrays.
+template <class T>
+void run_bands_any(const ApplyLists& al, const HbsView<T>& h, bool adjoint, int c, T* QH, T* UH,
+                   hipStream_t s) {
+  constexpr int V = 16 / sizeof(T);
+  auto al16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+  const bool vec = h.R % V == 0 && al16(QH) && al16(UH) && al16(h.Ut) && al16(h.Vt) &&
+                   al16(h.B);
+  if (h.R <= 32) {
+    if (vec) run_bands<T, 32, V>(al, h, adjoint, c, QH, UH, s);
+    else run_bands<T, 32, 1>(al, h, adjoint, c, QH, UH, s);
+  } else {
+    if (vec) run_bands<T, TRM, V>(al, h, adjoint, c, QH, UH, s);
+    else run_bands<T, TRM, 1>(al, h, adjoint, c, QH, UH, s);
+  }
 }
 
 template <class T>
@@ -299,15 +475,14 @@ void apply_forest(const Node* d_nodes, const ApplyLists& al, const HbsView<T>& h
   if (al.nfront == 0 || c <= 0) return;
   const int R = h.R;
   if (R > TRM) HM_THROW(HM_ERR_UNSUPPORTED, "apply: padded rank %d > %d", R, TRM);
+  if (al.mmax >= 1 && al.bands.bytes == 0)
+    HM_THROW(HM_ERR_ARG, "apply: band lists missing");
   T* QH = static_cast<T*>(work);
   T* UH = QH + (size_t)R * c * nnodes;
   T* P = UH + (size_t)R * c * nnodes;
   const int ct = (c + TN - 1) / TN;
-  const int ctt = (c + TRC - 1) / TRC;
   const T* Uin = adjoint ? h.Vlong : h.Ulong;  // incoming long basis
   const T* Vout = adjoint ? h.Ulong : h.Vlong; // outgoing long basis
-  const T* Tin = adjoint ? h.Vt : h.Ut;
-  const T* Tout = adjoint ? h.Ut : h.Vt;
   const int* front = al.frontier.as<int32_t>();
   if (al.mmax >= 1 && R > 0) {
     hipLaunchKernelGGL(k_leaf_up<T>, dim3(al.chunks, al.nfront, ct), dim3(256), 0, s, d_nodes,
@@ -320,23 +495,7 @@ void apply_forest(const Node* d_nodes, const ApplyLists& al, const HbsView<T>& h
                          dim3(256), 0, s, front, al.chunks, P, n, QH, T(1), T(0), n);
       KCHK();
     }
-    for (int l = al.mmax - 1; l >= 1; --l) {
-      if (al.ninternal[l] == 0) continue;
-      hipLaunchKernelGGL(k_tree_up<T>, dim3(al.ninternal[l], ctt), dim3(256), 0, s,
-                         al.internal[l].as<TreeOp>(), Tout, R, QH, c);
-      KCHK();
-    }
-    if (al.nlevel1 > 0) {
-      hipLaunchKernelGGL(k_root<T>, dim3(al.nlevel1, ctt), dim3(256), 0, s,
-                         al.level1.as<TreeOp>(), h.B, R, QH, UH, c, adjoint ? 1 : 0);
-      KCHK();
-    }
-    for (int l = 1; l < al.mmax; ++l) {
-      if (al.ninternal[l] == 0) continue;
-      hipLaunchKernelGGL(k_tree_down<T>, dim3(al.ninternal[l], 2, ctt), dim3(256), 0, s,
-                         al.internal[l].as<TreeOp>(), Tin, h.B, R, QH, UH, c, adjoint ? 1 : 0);
-      KCHK();
-    }
+    run_bands_any<T>(al, h, adjoint, c, QH, UH, s);
   }
   if (expansions_only) return;
   const int rt = (int)((al.max_rows + TM - 1) / TM);
