@@ -2,6 +2,7 @@
 #include <algorithm>
 
 #include "apply.h"
+#include "stage.h"
 #include "tile_mfma.h"
 
 namespace hm {
@@ -150,45 +151,6 @@ constexpr int band_depth_down(int RC) {
          (band_down_elems(RC, BandCfg<T>::BC, d) + BAND_SLACK) * (int)sizeof(T) > BAND_LDS_MAX)
     --d;
   return d;
-}
-
-// e / d for 0 <= e < 2^32 / d (d <= 2^16): one high multiply.
-struct FastDiv {
-  uint32_t m;
-  __device__ explicit FastDiv(uint32_t d) : m(0xFFFFFFFFu / d + 1u) {}
-  __device__ __forceinline__ int div(int e) const { return (int)__umulhi((uint32_t)e, m); }
-};
-
-template <class T, int V>
-struct alignas(sizeof(T) * V) BandVec {
-  T v[V];
-};
-
-// Chunks e in [0, n) of V consecutive source elements: map(e, p, d0, ds) gives
-// the source address and the LDS offsets d0, d0 + ds, ... of the chunk's
-// elements.  NB chunks per thread are loaded before any is stored.
-template <class T, int V, int NB, class Map>
-__device__ __forceinline__ void band_stage(int n, T* lds, Map map) {
-  for (int base = 0; base < n; base += 256 * NB) {
-    BandVec<T, V> v[NB];
-    int d0[NB], ds[NB];
-#pragma unroll
-    for (int q = 0; q < NB; ++q) {
-      const int e = base + q * 256 + (int)threadIdx.x;
-      d0[q] = -1;
-      ds[q] = 0;
-      if (e < n) {
-        const T* p;
-        map(e, p, d0[q], ds[q]);
-        v[q] = *reinterpret_cast<const BandVec<T, V>*>(p);
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < NB; ++q)
-      if (d0[q] >= 0)
-#pragma unroll
-        for (int t = 0; t < V; ++t) lds[d0[q] + t * ds[q]] = v[q].v[t];
-  }
 }
 
 // acc += A(r0 + 0..15, 0:4 nk4) B(0:4 nk4, c0 + 0..15) on the matrix cores:
@@ -460,6 +422,148 @@ __global__ __launch_bounds__(256) void k_leaf_down(const Node* nodes, const int3
   mf_store<T>(M, N, Y + i0 + (int64_t)j0 * ldy, ldy, acc, alpha, beta);
 }
 
+// ---- forward leaf product, one workgroup per (frontier node, column tile) ---
+// For frontier nodes of at most LEAF_MAX rows: the B operand of the whole
+// product (UH_g stacked over X(I_g, :)) is staged in LDS in one round with
+// 16-byte loads where aligned; wave w of eight takes rows 16 w .. 16 w + 15 of
+// the node and every column of the tile, reading its A operand (U and D rows,
+// 16 consecutive rows per lane group) straight from global memory with the
+// next 64 K-values in flight while the current ones feed the MFMAs; the result
+// goes through LDS so that the stores run along the rows.
+constexpr int LEAF_MAX = 128;
+template <class T> struct LeafCfg;
+template <> struct LeafCfg<float> { static constexpr int BN = 64, BP = 80; };
+template <> struct LeafCfg<double> { static constexpr int BN = 32, BP = 40; };
+constexpr int LEAF_KMAX = ((HM_MAX_SAMPLES + LEAF_MAX + 31) / 32) * 32;
+constexpr int LEAF_CP = LEAF_MAX + 4;   // pitch of the column-major result tile
+
+// acc[t] += A(16 w + .., 0:K) B(0:K, 16 t + ..) for wave w of 8; A(i, k) from
+// aload(i, k) (zero for i >= m or k >= K), B(k, j) = sB[k * BP + j] with rows
+// up to K rounded to 32 zero-filled.  The A values of the next two groups of
+// 32 K are in flight while a group feeds the MFMAs.
+template <class T, int CT, int BP, class ALoad>
+__device__ __forceinline__ void leaf_mma(int m, int K, const T* sB, ALoad aload,
+                                         typename MfTraits<T>::acc_t (&acc)[CT]) {
+  typedef MfTraits<T> Tr;
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  const int i = 16 * (threadIdx.x >> 6) + li;
+  T a0[8], a1[8], a2[8];
+  auto fetch = [&](int kg, T (&a)[8]) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int k = kg + 4 * s + lk;
+      a[s] = (i < m && k < K) ? aload(i, k) : T(0);
+    }
+  };
+  fetch(0, a0);
+  fetch(32, a1);
+  for (int kg = 0; kg < K; kg += 32) {
+    fetch(kg + 64, a2);
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const T* b = sB + (kg + 4 * s + lk) * BP + li;
+      T bv[CT];
+#pragma unroll
+      for (int t = 0; t < CT; ++t) bv[t] = b[16 * t];
+#pragma unroll
+      for (int t = 0; t < CT; ++t) acc[t] = Tr::step(a0[s], bv[t], acc[t]);
+    }
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      a0[s] = a1[s];
+      a1[s] = a2[s];
+    }
+  }
+}
+
+// Y(I_g, j0 + 0:nc) = alpha (U(I_g, :) UH_g + D_g X(I_g, :)) + beta Y (the U
+// term for non-root nodes, the D term if D; D is not transposed here).
+template <class T>
+__global__ __launch_bounds__(512) void k_leaf_down2(const Node* nodes, const int32_t* front,
+                                                    const T* U, int64_t ldl, int R, const T* UH,
+                                                    int c, const T* D, int64_t ldd,
+                                                    const T* X, int64_t ldx, T* Y, int64_t ldy,
+                                                    T alpha, T beta) {
+  typedef MfTraits<T> Tr;
+  constexpr int BN = LeafCfg<T>::BN, BP = LeafCfg<T>::BP, CT = BN / 16;
+  constexpr int V = 16 / sizeof(T);
+  constexpr int LDS_ELEMS = LEAF_KMAX * BP > BN * LEAF_CP ? LEAF_KMAX * BP : BN * LEAF_CP;
+  __shared__ __attribute__((aligned(16))) T sB[LDS_ELEMS];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int g = front[blockIdx.x];
+  const Node nd = nodes[g];
+  const int64_t lo = nd.lo;
+  const int nt = (int)(nd.hi - nd.lo);
+  const int j0 = blockIdx.y * BN, nc = min(BN, c - j0);
+  const int KU = (nd.level > 0 && R > 0) ? R : 0, KD = D ? nt : 0, K = KU + KD;
+  const int KP = (K + 31) & ~31;
+  // stage B: rows 0..KU-1 = UH_g(:, tile), rows KU..K-1 = X(I_g, tile), zero to KP
+  for (int e = tid; e < (KP - K) * BP; e += 512) sB[K * BP + e] = T(0);
+  const bool vec = ((uintptr_t)X & 15) == 0 && ((uintptr_t)UH & 15) == 0 && lo % V == 0 &&
+                   ldx % V == 0 && nt % V == 0 && R % V == 0;
+  if (vec) {
+    const int cu = KU / V, cx = KD / V;   // chunks per column
+    const int n1 = cu * nc, n2 = n1 + cx * nc;
+    const FastDiv du(cu > 0 ? cu : 1), dx(cx > 0 ? cx : 1);
+    band_stage<T, V, 8, 512>(n2, sB, [&](int e, const T*& p, int& d0, int& ds) {
+      if (e < n1) {
+        const int j = du.div(e), k = (e - j * cu) * V;
+        p = UH + (int64_t)g * R * c + (int64_t)(j0 + j) * R + k;
+        d0 = k * BP + j;
+      } else {
+        const int e2 = e - n1, j = dx.div(e2), k = (e2 - j * cx) * V;
+        p = X + lo + k + (int64_t)(j0 + j) * ldx;
+        d0 = (KU + k) * BP + j;
+      }
+      ds = BP;
+    });
+  } else {
+    const int n1 = KU * nc, n2 = n1 + KD * nc;
+    const FastDiv du(KU > 0 ? KU : 1), dx(KD > 0 ? KD : 1);
+    band_stage<T, 1, 16, 512>(n2, sB, [&](int e, const T*& p, int& d0, int& ds) {
+      if (e < n1) {
+        const int j = du.div(e), k = e - j * KU;
+        p = UH + (int64_t)g * R * c + (int64_t)(j0 + j) * R + k;
+        d0 = k * BP + j;
+      } else {
+        const int e2 = e - n1, j = dx.div(e2), k = e2 - j * KD;
+        p = X + lo + k + (int64_t)(j0 + j) * ldx;
+        d0 = (KU + k) * BP + j;
+      }
+      ds = 0;
+    });
+  }
+  __syncthreads();
+  typename Tr::acc_t acc[CT];
+#pragma unroll
+  for (int t = 0; t < CT; ++t) acc[t] = typename Tr::acc_t{0, 0, 0, 0};
+  if (16 * w < nt && K > 0) {
+    const T* Ul = U + lo;
+    const T* Dl = D + lo;
+    leaf_mma<T, CT, BP>(nt, K, sB, [&](int i, int k) {
+      return k < KU ? Ul[i + (int64_t)k * ldl] : Dl[i + (int64_t)(k - KU) * ldd];
+    }, acc);
+  }
+  __syncthreads();
+  // result tile, column-major in LDS, then stores along the rows
+  T* sC = sB;
+#pragma unroll
+  for (int t = 0; t < CT; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 16 * w + Tr::row(lane, v), j = 16 * t + (lane & 15);
+      sC[j * LEAF_CP + i] = acc[t][v];
+    }
+  __syncthreads();
+  const int i = tid & 127;
+  if (i < nt)
+    for (int j = tid >> 7; j < nc; j += 4) {
+      T* y = Y + lo + i + (int64_t)(j0 + j) * ldy;
+      const T r = alpha * sC[j * LEAF_CP + i];
+      *y = beta == T(0) ? r : r + beta * *y;
+    }
+}
+
 template <class T>
 size_t apply_work_bytes(const Forest& f, const ApplyLists& al, int R, int c) {
   const size_t per = (size_t)R * c * sizeof(T);
@@ -498,6 +602,16 @@ void apply_forest(const Node* d_nodes, const ApplyLists& al, const HbsView<T>& h
     run_bands_any<T>(al, h, adjoint, c, QH, UH, s);
   }
   if (expansions_only) return;
+  // the transposed D reads of the adjoint are uncoalesced from global memory:
+  // that case stays on the K-chunked LDS tiles of k_leaf_down
+  if (al.max_rows <= LEAF_MAX && !(adjoint && h.D)) {
+    constexpr int BN = LeafCfg<T>::BN;
+    hipLaunchKernelGGL(k_leaf_down2<T>, dim3(al.nfront, (c + BN - 1) / BN), dim3(512), 0, s,
+                       d_nodes, front, Uin, h.ldl, R, UH, c, h.D, h.ldd, X, ldx, Y, ldy, alpha,
+                       beta);
+    KCHK();
+    return;
+  }
   const int rt = (int)((al.max_rows + TM - 1) / TM);
   hipLaunchKernelGGL(k_leaf_down<T>, dim3(rt, al.nfront, ct), dim3(256), 0, s, d_nodes, front,
                      Uin, h.ldl, R, UH, c, h.D, h.ldd, adjoint ? 1 : 0, X, ldx, Y, ldy, alpha,
