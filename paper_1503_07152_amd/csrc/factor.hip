@@ -723,17 +723,20 @@ static_assert(JAC_FT / JAC_G >= FAC_CMAX / 2, "one group per pair of a round");
 
 // JFT threads: JFT / 16 groups, each taking the pairs grp, grp + JFT / 16, ..
 // of a round in turn (the pairs of a round are disjoint)
+// A pair is rotated while |x.y| > tol |x| |y|.  With stop > 0 the sweeps also
+// end after a sweep in which no pair had |x.y| > stop |x| |y|: cyclic Jacobi
+// converges quadratically, so the next sweep would start from inner products
+// of order stop^2 (the check sweep that finds no rotation is saved).
 template <int RPL, int JFT>
 __device__ __forceinline__ int jacobi_sweeps(double* sA, double* sZ, double* sN, int h, int c,
-                                             bool wantX, int* flag) {
+                                             bool wantX, int* flag, double tol, double stop) {
   constexpr int JAC_GROUPS = JFT / JAC_G;
   const int tid = threadIdx.x;
   const int grp = tid / JAC_G, gl = tid % JAC_G;
   const int n2 = c + (c & 1);
-  const double tol = (double)max(h, 1) * DBL_EPSILON;
   int sweep = 0;
   for (; sweep < 40; ++sweep) {
-    if (tid == 0) *flag = 0;
+    if (tid == 0) flag[0] = flag[1] = 0;
     // squared column norms, fresh each sweep (the updates drift by rounding)
     for (int j = grp; j < c; j += JAC_GROUPS) {
       double nn = 0.0;
@@ -772,8 +775,11 @@ __device__ __forceinline__ int jacobi_sweeps(double* sA, double* sZ, double* sN,
         const double al = sN[p], be = sN[q];
         // |ga| > tol |x| |y|, from the hardware reciprocal square roots (a
         // threshold needs no correct rounding)
-        if (ga != 0.0 && al > 0.0 && be > 0.0 &&
-            fabs(ga) * __builtin_amdgcn_rsq(al) * __builtin_amdgcn_rsq(be) > tol) {
+        const double ratio = (ga != 0.0 && al > 0.0 && be > 0.0)
+                                 ? fabs(ga) * __builtin_amdgcn_rsq(al) * __builtin_amdgcn_rsq(be)
+                                 : 0.0;
+        if (ratio > stop && stop > 0.0 && gl == 0) flag[1] = 1;
+        if (ratio > tol) {
           // rotation zeroing the pair's inner product: t = tan(theta) is the
           // smaller root of t^2 ga + t (be - al) - ga = 0
           const double dd = be - al;
@@ -827,14 +833,14 @@ __device__ __forceinline__ int jacobi_sweeps(double* sA, double* sZ, double* sN,
           if (gl == 0) {
             sN[p] = fma(-tt, ga, al);
             sN[q] = fma(tt, ga, be);
-            *flag = 1;
+            flag[0] = 1;
           }
         }
       }
       __syncthreads();
     }
-    if (*flag == 0) break;
-    __syncthreads();  // every thread has read flag before it is reset
+    if (flag[0] == 0 || (stop > 0.0 && flag[1] == 0)) break;
+    __syncthreads();  // every thread has read the flags before they are reset
   }
   return sweep + 1;
 }
@@ -854,7 +860,7 @@ __global__ __launch_bounds__(jacobi_threads<NEED_Z>()) void k_jacobi(const SvdDe
   __shared__ double snorm[FAC_CMAX];
   __shared__ double sN[FAC_CMAX];
   __shared__ int srank[FAC_CMAX];
-  __shared__ int flag;
+  __shared__ int flag[2];
   const SvdDesc d = descs[blockIdx.x];
   int h = d.h, c = d.c;
   if (d.dyn) {
@@ -881,14 +887,21 @@ __global__ __launch_bounds__(jacobi_threads<NEED_Z>()) void k_jacobi(const SvdDe
       sZ[i + j * JAC_LD] = (i == j) ? 1.0 : 0.0;
     }
   __syncthreads();
+  // Householder route: rotate to rounding level.  Gram route (samples with
+  // BF16 noise, ~1e-3): the columns of U = M Z diag(1/s) are orthonormal to
+  // the rotation tolerance (U^T U - I = the scaled off-diagonal of Z^T G Z),
+  // so 1e-12 is ample; sweeps stop once the largest inner product met in a
+  // sweep is below 1e-6.
+  const double tol = d.gram ? 1e-12 : (double)max(h, 1) * DBL_EPSILON;
+  const double stop = d.gram ? 1e-6 : 0.0;
   int sweeps = 0;
   switch ((h + JAC_G - 1) / JAC_G) {
-    case 1: sweeps = jacobi_sweeps<1, JFT>(sA, sZ, sN, h, c, accZ, &flag); break;
-    case 2: sweeps = jacobi_sweeps<2, JFT>(sA, sZ, sN, h, c, accZ, &flag); break;
-    case 3: sweeps = jacobi_sweeps<3, JFT>(sA, sZ, sN, h, c, accZ, &flag); break;
-    case 4: sweeps = jacobi_sweeps<4, JFT>(sA, sZ, sN, h, c, accZ, &flag); break;
-    case 5: sweeps = jacobi_sweeps<5, JFT>(sA, sZ, sN, h, c, accZ, &flag); break;
-    case 6: sweeps = jacobi_sweeps<6, JFT>(sA, sZ, sN, h, c, accZ, &flag); break;
+    case 1: sweeps = jacobi_sweeps<1, JFT>(sA, sZ, sN, h, c, accZ, flag, tol, stop); break;
+    case 2: sweeps = jacobi_sweeps<2, JFT>(sA, sZ, sN, h, c, accZ, flag, tol, stop); break;
+    case 3: sweeps = jacobi_sweeps<3, JFT>(sA, sZ, sN, h, c, accZ, flag, tol, stop); break;
+    case 4: sweeps = jacobi_sweeps<4, JFT>(sA, sZ, sN, h, c, accZ, flag, tol, stop); break;
+    case 5: sweeps = jacobi_sweeps<5, JFT>(sA, sZ, sN, h, c, accZ, flag, tol, stop); break;
+    case 6: sweeps = jacobi_sweeps<6, JFT>(sA, sZ, sN, h, c, accZ, flag, tol, stop); break;
     default: break;   // h = 0: nothing to rotate
   }
   if (tid == 0 && d.sweeps) atomicMax(d.sweeps, sweeps);

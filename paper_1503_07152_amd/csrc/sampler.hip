@@ -19,14 +19,18 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
-// Block shape per form.  BF16: 72 (8 column tiles) to 120 (18) VGPRs, so 8
-// waves (2 per SIMD) of one 16-row tile each.  FP32 (FP32 and FP64
-// accumulators, ~420 registers with the AGPRs) and FP64 (~190): 4 waves of
-// two 16-row tiles, which halves the LDS reads of X per MFMA.
-template <int MODE>
+// Block shape per form.  BF16 up to 12 column tiles (72 to 90 VGPRs): 8
+// waves of one 16-row tile each.  The widest BF16 form (18 column tiles, ~207
+// VGPRs, two waves per SIMD): 8 waves of two 16-row tiles, 256 rows per
+// block, which halves the X tiles each CU streams per row and lets every B
+// operand read from LDS feed two MFMAs (4-6 % faster than one row tile per
+// wave at 288 columns; two row tiles with 4 waves gain nothing, and the
+// narrower forms lose by it).  FP32 (FP32 and FP64 accumulators, ~420
+// registers with the AGPRs) and FP64 (~190): 4 waves of two 16-row tiles.
+template <int MODE, int CT>
 struct SmpShape {
   static constexpr int WAVES = MODE == 2 ? 8 : 4;
-  static constexpr int RT = MODE == 2 ? 1 : 2;    // 16-row tiles per wave
+  static constexpr int RT = (MODE == 2 && CT <= 12) ? 1 : 2;    // 16-row tiles per wave
   static constexpr int THREADS = 64 * WAVES;
   static constexpr int ROWS = WAVES * 16 * RT;    // rows per block
 };
@@ -142,7 +146,7 @@ constexpr int SMP_GS = 3;
 __device__ __forceinline__ int swz(int col) { return (col ^ ((col >> 3) & 1)) & 7; }
 
 // SRC: 0 log kernel, 1 near-singular kernel, 2 dense matrix, 3 its transpose (F64 only).
-// One block = SmpShape<MODE>::WAVES waves x RT 16-row tiles; X is streamed
+// One block = SmpShape<MODE, CT>::WAVES waves x RT 16-row tiles; X is streamed
 // through LDS in K-tiles (the K-tiles of split blockIdx.y), double-buffered,
 // the next tile in flight (registers for F64 / F32, global_load_lds for BF16)
 // while the current one feeds the MFMAs.
@@ -152,17 +156,19 @@ __device__ __forceinline__ int swz(int col) { return (col ^ ((col >> 3) & 1)) & 
 // The FP32 form is held to two waves per SIMD (244 VGPRs, no spills): left
 // to itself the compiler took 300 registers and one wave per SIMD, 1.6x slower.
 template <int MODE, int SRC, int CT>
-__global__ __launch_bounds__(SmpShape<MODE>::THREADS)
-__attribute__((amdgpu_waves_per_eu(MODE == 1 ? 2 : (MODE == 2 && CT > 8 ? 4 : 1)))) void k_sampler(
+__global__ __launch_bounds__((SmpShape<MODE, CT>::THREADS))
+__attribute__((amdgpu_waves_per_eu(MODE == 1 ? 2
+                                   : (MODE == 2 && CT > 12 ? 2 : (MODE == 2 && CT > 8 ? 4 : 1)))))
+void k_sampler(
     int64_t n, int c, int cp, const double* __restrict__ pts, double kp,
     const double* __restrict__ Ad, int64_t lda, const typename ModeT<MODE>::T* __restrict__ Xp,
     const uint32_t* __restrict__ mask, double* __restrict__ Y, int64_t ldy, int64_t kt_chunk,
     float* __restrict__ Ypart) {
   typedef typename ModeT<MODE>::T T;
   constexpr int BK = ModeT<MODE>::BK;
-  constexpr int SMP_THREADS = SmpShape<MODE>::THREADS;
-  constexpr int SMP_ROWS = SmpShape<MODE>::ROWS;
-  constexpr int SMP_RT = SmpShape<MODE>::RT;
+  constexpr int SMP_THREADS = SmpShape<MODE, CT>::THREADS;
+  constexpr int SMP_ROWS = SmpShape<MODE, CT>::ROWS;
+  constexpr int SMP_RT = SmpShape<MODE, CT>::RT;
   constexpr int SMP_CT = CT;
   constexpr int TILE_BYTES = BK * 16 * CT * (int)sizeof(T);
   constexpr int NV = (TILE_BYTES + SMP_THREADS * 16 - 1) / (SMP_THREADS * 16);  // uint4 per thread
@@ -463,18 +469,20 @@ static void run_sampler(int64_t n, int c, const double* pts, double kp, const do
   float* Yp = ks > 1 ? reinterpret_cast<float*>(static_cast<char*>(work) + xbytes +
                                                 align256((size_t)nkt * 4))
                      : nullptr;
-  constexpr int rows = SmpShape<MODE>::ROWS;
-  const dim3 grid((unsigned)((n + rows - 1) / rows), (unsigned)ks), block(SmpShape<MODE>::THREADS);
+  auto launch = [&](auto kern, auto shape) {
+    typedef decltype(shape) Sh;
+    const dim3 grid((unsigned)((n + Sh::ROWS - 1) / Sh::ROWS), (unsigned)ks), block(Sh::THREADS);
+    hipLaunchKernelGGL(kern, grid, block, 0, s, n, c, cp, pts, kp, Ad, lda, Xp, mask, Y, ldy,
+                       kt_chunk, Yp);
+    KCHK();
+  };
+  constexpr int CT12 = MODE == 2 ? 12 : 8, CT18 = MODE == 2 ? 18 : 8;
   if (MODE != 2 || c <= 128)
-    hipLaunchKernelGGL((k_sampler<MODE, SRC, 8>), grid, block, 0, s, n, c, cp, pts, kp, Ad, lda,
-                       Xp, mask, Y, ldy, kt_chunk, Yp);
+    launch(k_sampler<MODE, SRC, 8>, SmpShape<MODE, 8>());
   else if (c <= 192)
-    hipLaunchKernelGGL((k_sampler<MODE, SRC, MODE == 2 ? 12 : 8>), grid, block, 0, s, n, c, cp,
-                       pts, kp, Ad, lda, Xp, mask, Y, ldy, kt_chunk, Yp);
+    launch(k_sampler<MODE, SRC, CT12>, SmpShape<MODE, CT12>());
   else
-    hipLaunchKernelGGL((k_sampler<MODE, SRC, MODE == 2 ? 18 : 8>), grid, block, 0, s, n, c, cp,
-                       pts, kp, Ad, lda, Xp, mask, Y, ldy, kt_chunk, Yp);
-  KCHK();
+    launch(k_sampler<MODE, SRC, CT18>, SmpShape<MODE, CT18>());
   if (ks > 1) {
     const int64_t tot = n * c;
     hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, c, ks,
