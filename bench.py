@@ -54,17 +54,22 @@ PEAK_ALU_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
 # packed BF16 conversion = 13.5 slots
 SLOTS_PER_ENTRY = 13.5
 
-# HBM bytes of one BF16 operator apply at N = 65536 from two rocprofv3 --pmc
-# passes (FETCH_SIZE, WRITE_SIZE in KiB per dispatch, summed over the kernels
-# of the call), scaled by what the same counters read for a plain 256 MiB
-# device copy (FETCH_SIZE reads 0.5x the bytes moved, WRITE_SIZE 1.0x).
+# HBM bytes of one BF16 operator apply at N = 65536 (96 columns: k_pack,
+# k_sampler, k_sum_parts; 288 columns: k_pack, k_sampler) from two rocprofv3
+# --pmc passes (FETCH_SIZE, WRITE_SIZE in KiB per dispatch, summed over the
+# kernels of the call), scaled by what the same counters read for a plain
+# 256 MiB device copy (FETCH_SIZE reads 0.5x the bytes moved, WRITE_SIZE 1.0x).
 # Valid only for the sampler source they were taken on (SHA-1); otherwise
 # reported as unknown (null).
 SAMPLER_TRAFFIC = {
-    96: {"sha1": "ccd8b683386b3325e55a31dcc936cac39c3c7669",
-         "fetch_kib": 24590.8 + 96446.5 + 73746.7,
-         "write_kib": 12320.0 + 148705.4 + 49152.0,
+    96: {"sha1": "d3cb4a07aceb989cc85533415719783fa98d9c8a",
+         "fetch_kib": 24591.2 + 93679.6 + 36882.5,
+         "write_kib": 12320.0 + 73728.0 + 49152.0,
          "fetch_scale": 2.0, "write_scale": 1.0},
+    288: {"sha1": "d3cb4a07aceb989cc85533415719783fa98d9c8a",
+          "fetch_kib": 73743.4 + 152244.5,
+          "write_kib": 36896.4 + 150127.3,
+          "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
 

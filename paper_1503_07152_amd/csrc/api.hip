@@ -321,7 +321,7 @@ int hm_autotune(const hm_options* opts, const hm_operator* op, int32_t reps, voi
       const int rmax = std::max(0, (cmax - 2 * R) / (2 * R));
       for (int g = 1; g <= gmax; ++g)
         for (int rd = 0; rd <= rmax; ++rd)
-          for (int ks : {2, 3, 4}) cand.push_back(TuneParams{g, rd, ks});
+          for (int ks : {1, 2, 3, 4, 8}) cand.push_back(TuneParams{g, rd, ks});
     }
     auto run_once = [&](const TuneParams& tp) {
       tune_store(key, tp);

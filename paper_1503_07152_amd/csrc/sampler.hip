@@ -45,7 +45,10 @@ int sampler_max_cols(int mode) { return mode == 2 ? SMP_MAXC_BF16 : SMP_MAXC; }
 
 static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
-// K-splits of the narrow BF16 form (see run_sampler)
+// K-splits of the narrow BF16 form (see run_sampler).  Split counts that
+// divide 8 map onto XCD groups (k_sampler); measured at 96 columns that cuts
+// the sampler's fetch from 183 to 160 MB per call at equal time, and three
+// splits stay the fastest default.
 constexpr int SMP_KSPLIT = 3;
 static int sampler_ksplit(int mode, int64_t n, int c) {
   const int64_t nkt = (n + sampler_bk(mode) - 1) / sampler_bk(mode);
@@ -147,7 +150,7 @@ __device__ __forceinline__ int swz(int col) { return (col ^ ((col >> 3) & 1)) & 
 
 // SRC: 0 log kernel, 1 near-singular kernel, 2 dense matrix, 3 its transpose (F64 only).
 // One block = SmpShape<MODE, CT>::WAVES waves x RT 16-row tiles; X is streamed
-// through LDS in K-tiles (the K-tiles of split blockIdx.y), double-buffered,
+// through LDS in K-tiles (the K-tiles of split sp), double-buffered,
 // the next tile in flight (registers for F64 / F32, global_load_lds for BF16)
 // while the current one feeds the MFMAs.
 // CT column tiles of 16 are held in the accumulators (c <= 16 CT); the BF16
@@ -188,7 +191,18 @@ void k_sampler(
   __shared__ double sP[2][MODE == 2 ? 1 : 2 * BK];
   __shared__ __attribute__((aligned(8))) float sPf[2][MODE == 2 ? 2 * BK : 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t row0 = (int64_t)blockIdx.x * SMP_ROWS + wave * 16 * SMP_RT;
+  // Row block rb and K-split sp of this workgroup.  Workgroups go to the 8
+  // XCDs round-robin by linear id; when the split count divides 8, the linear
+  // id is mapped so that every block of split sp runs on the XCDs x = sp
+  // (mod splits), whose L2s then stream only that split's part of X.
+  int rb = blockIdx.x, sp = blockIdx.y;
+  if (gridDim.y > 1 && 8 % gridDim.y == 0 && (gridDim.x * gridDim.y) % 8 == 0) {
+    const int ks = gridDim.y, L = blockIdx.x + blockIdx.y * gridDim.x;
+    const int x = L & 7, q = L >> 3;
+    sp = x % ks;
+    rb = q * (8 / ks) + x / ks;
+  }
+  const int64_t row0 = (int64_t)rb * SMP_ROWS + wave * 16 * SMP_RT;
   const int ct_n = cp / 16;
   const int tile_u4 = BK * cp * (int)sizeof(T) / 16;
   double xi[SMP_RT], yi[SMP_RT];
@@ -270,8 +284,8 @@ void k_sampler(
   // the nonzero mask of a K-tile is read with its tile, one iteration ahead:
   // a load issued after the prefetch and waited for at once would also wait
   // for the prefetch (loads complete in order)
-  // K-tiles kt_beg .. kt_end - 1 of this split (blockIdx.y); kk counts them
-  const int64_t kt_beg = (int64_t)blockIdx.y * kt_chunk;
+  // K-tiles kt_beg .. kt_end - 1 of this split (sp); kk counts them
+  const int64_t kt_beg = (int64_t)sp * kt_chunk;
   const int64_t kt_end = min(nkt, kt_beg + kt_chunk);
   const int64_t nkk = max(kt_end - kt_beg, (int64_t)0);
   uint32_t msk_nx = 0;
@@ -403,7 +417,7 @@ void k_sampler(
   // one split writes Y; several (BF16 form only) write their FP32 partial
   // sums, added in FP64 in split order by k_sum_parts
   const bool part = gridDim.y > 1;
-  float* Yq = part ? Ypart + (int64_t)blockIdx.y * n * c : nullptr;
+  float* Yq = part ? Ypart + (int64_t)sp * n * c : nullptr;
   // Accumulator layout (column lane % 16 of each 16 x 16 tile): item v of lane
   // l holds row 4*(l/16) + v for the FP32-accumulating instructions and row
   // l/16 + 4*v for v_mfma_f64_16x16x4f64 (checked on gfx950 with identity inputs).
@@ -459,11 +473,11 @@ static void run_sampler(int64_t n, int c, const double* pts, double kp, const do
   hipLaunchKernelGGL(k_pack<MODE>, dim3((unsigned)nkt), dim3(256), 0, s, n, c, cp, X, ldx, Xp,
                      mask);
   KCHK();
-  // The narrow BF16 form (74 VGPRs: six waves per SIMD) splits the K-tiles in
-  // SMP_KSPLIT parts, one block row each: 65536 rows give 512 blocks of 8
-  // waves, four per SIMD, which the split raises to the six the registers
-  // allow.  The wider forms are held to four waves per SIMD by their
-  // registers, which 512 blocks already fill.
+  // The narrow BF16 form (72 VGPRs: seven waves per SIMD) splits the K-tiles
+  // in SMP_KSPLIT parts (or the tuned count), one block row each: 65536 rows
+  // give 512 blocks of 8 waves, four per SIMD, which the split raises to what
+  // the registers allow.  The wider forms are held to fewer waves per SIMD by
+  // their registers, which 512 (256) blocks already fill.
   const int ks = sampler_ksplit(MODE, n, c);
   const int64_t kt_chunk = (nkt + ks - 1) / ks;
   float* Yp = ks > 1 ? reinterpret_cast<float*>(static_cast<char*>(work) + xbytes +

@@ -376,9 +376,10 @@ def test_autotune_picks_a_schedule_that_keeps_the_result():
     try:
         t = hm.autotune(opts, op, reps=1)
         say(f"autotune: {t}")
-        assert t["candidates"] == 1 + 3 * 3 * 3
+        # defaults + (first-product groups 1-3) x (riding blocks 0-2) x (K-splits 1, 2, 3, 4, 8)
+        assert t["candidates"] == 1 + 3 * 3 * 5
         assert t["t_best_ms"] <= t["t_default_ms"]
-        assert 0 <= t["gfirst"] <= 3 and -1 <= t["ride"] <= 2 and t["ksplit"] in (0, 2, 3, 4)
+        assert 0 <= t["gfirst"] <= 3 and -1 <= t["ride"] <= 2 and t["ksplit"] in (0, 1, 2, 3, 4, 8)
         h = hm.hbs_compress(opts, op)
         ho, _, _ = ohbs.compress(oops.KernelOp(P, "near"), n, leaf, k + p, seed, rank=k,
                                  to_id=False)
