@@ -101,12 +101,11 @@ static void backward_impl(const hm_hbs* h, int c, const T* x, int64_t ldx, const
   StreamBuf sb1(wb, s), sb2(wb, s);
   void *w1 = sb1.p, *w2 = sb2.p;
   const HbsView<T> hv = h->view<T>();
-  // forward expansions (outgoing qh, incoming uh) of x
-  apply_forest<T>(h->d_nodes.as<Node>(), h->full, hv, false, c, x, ldx, (T*)nullptr, N, T(1),
-                  T(0), w1, nn, s, true);
-  // adjoint apply of gy: gx, and its expansions g(uh) (upward) and g(qh) (downward)
-  apply_forest<T>(h->d_nodes.as<Node>(), h->full, hv, true, c, gy, ldgy, gx, ldgx, T(1), T(0), w2,
-                  nn, s);
+  // forward expansions (outgoing qh, incoming uh) of x, and the adjoint apply
+  // of gy: gx with its expansions g(uh) (upward) and g(qh) (downward); the
+  // two sets of tree sweeps share their launches
+  apply_forest_pair<T>(h->d_nodes.as<Node>(), h->full, hv, c, x, ldx, w1, gy, ldgy, gx, ldgx, w2,
+                       nn, s);
   const size_t es = sizeof(T);
   if (gUt) HIPCHK(hipMemsetAsync(gUt, 0, (size_t)(nn + 1) * 2 * R * R * es, s));
   if (gVt) HIPCHK(hipMemsetAsync(gVt, 0, (size_t)(nn + 1) * 2 * R * R * es, s));

@@ -70,6 +70,14 @@ void apply_forest(const Node* d_nodes, const ApplyLists& al, const HbsView<T>& h
                   int c, const T* X, int64_t ldx, T* Y, int64_t ldy, T alpha, T beta, void* work,
                   size_t nnodes, hipStream_t s, bool expansions_only = false);
 
+// The expansions of the forward apply of X (as apply_forest with
+// expansions_only, at work_x) and the adjoint apply Y = A_H^* G with its
+// expansions (at work_g), the tree sweeps of both in the same launches.
+template <class T>
+void apply_forest_pair(const Node* d_nodes, const ApplyLists& al, const HbsView<T>& h, int c,
+                       const T* X, int64_t ldx, void* work_x, const T* G, int64_t ldg, T* Y,
+                       int64_t ldy, void* work_g, size_t nnodes, hipStream_t s);
+
 // One level of a HODLR apply (Sec. 2.8): for the frontier nodes v (one tree
 // level), Y(I_a) = beta Y(I_a) + alpha U(I_a) diag(s[b]) V(I_b)^T X(I_b) with
 // b = sib(a); adjoint: Y(I_b) += alpha V(I_b) diag(s[b]) U(I_a)^T X(I_a).

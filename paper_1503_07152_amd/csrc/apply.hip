@@ -217,8 +217,12 @@ __device__ __forceinline__ void band_zero_pad(T* lds, int nblk, int bs, int P, i
 
 template <class T, int RC, int V>
 __global__ __launch_bounds__(256) void k_band_up(const BandJob* jobs, const T* Tout, int R,
-                                                 T* QH, int c) {
+                                                 T* QH, int c, const T* Tout2, T* QH2) {
   typedef MfTraits<T> Tr;
+  if (blockIdx.z) {   // the second sweep of a pair (same tree, other operands)
+    Tout = Tout2;
+    QH = QH2;
+  }
   constexpr int BC = BandCfg<T>::BC, CT = BC / 16;
   constexpr int DM = band_depth_up<T>(RC);
   __shared__ T lds[band_up_elems(RC, BC, DM) + BAND_SLACK];
@@ -277,8 +281,15 @@ __global__ __launch_bounds__(256) void k_band_up(const BandJob* jobs, const T* T
 template <class T, int RC, int V>
 __global__ __launch_bounds__(256) void k_band_down(const BandJob* jobs, const T* Tin,
                                                    const T* B, int R, const T* QH, T* UH, int c,
-                                                   int adjoint) {
+                                                   int adjoint, const T* Tin2, const T* QH2,
+                                                   T* UH2, int adjoint2) {
   typedef MfTraits<T> Tr;
+  if (blockIdx.z) {   // the second sweep of a pair
+    Tin = Tin2;
+    QH = QH2;
+    UH = UH2;
+    adjoint = adjoint2;
+  }
   constexpr int BC = BandCfg<T>::BC, CT = BC / 16;
   constexpr int DM = band_depth_down<T>(RC);
   __shared__ T lds[band_down_elems(RC, BC, DM) + BAND_SLACK];
@@ -353,23 +364,35 @@ __global__ __launch_bounds__(256) void k_band_down(const BandJob* jobs, const T*
   }
 }
 
+// The sweeps of one apply, or of two applies on the same tree side by side
+// (pair: the second as blockIdx.z = 1 of the same launches).
+template <class T>
+struct BandSweep {
+  bool adjoint;
+  T* QH;
+  T* UH;
+};
+
 template <class T, int RC, int V>
-void run_bands(const ApplyLists& al, const HbsView<T>& h, bool adjoint, int c, T* QH, T* UH,
-               hipStream_t s) {
+void run_bands(const ApplyLists& al, const HbsView<T>& h, int c, const BandSweep<T>& a,
+               const BandSweep<T>* b, hipStream_t s) {
   constexpr int BC = BandCfg<T>::BC;
   constexpr int DU = band_depth_up<T>(RC), DD = band_depth_down<T>(RC);
   const int ctt = (c + BC - 1) / BC;
   const BandJob* jobs = al.bands.as<BandJob>();
-  const T* Tin = adjoint ? h.Vt : h.Ut;
-  const T* Tout = adjoint ? h.Ut : h.Vt;
-  for (const BandRange& b : al.up_band[DU]) {
-    hipLaunchKernelGGL((k_band_up<T, RC, V>), dim3(b.n, ctt), dim3(256), 0, s, jobs + b.off, Tout,
-                       h.R, QH, c);
+  auto tin = [&](const BandSweep<T>& w) { return w.adjoint ? h.Vt : h.Ut; };
+  auto tout = [&](const BandSweep<T>& w) { return w.adjoint ? h.Ut : h.Vt; };
+  const BandSweep<T>& b2 = b ? *b : a;
+  const unsigned nz = b ? 2 : 1;
+  for (const BandRange& r : al.up_band[DU]) {
+    hipLaunchKernelGGL((k_band_up<T, RC, V>), dim3(r.n, ctt, nz), dim3(256), 0, s, jobs + r.off,
+                       tout(a), h.R, a.QH, c, tout(b2), b2.QH);
     KCHK();
   }
-  for (const BandRange& b : al.down_band[DD]) {
-    hipLaunchKernelGGL((k_band_down<T, RC, V>), dim3(b.n, ctt), dim3(256), 0, s, jobs + b.off,
-                       Tin, h.B, h.R, (const T*)QH, UH, c, adjoint ? 1 : 0);
+  for (const BandRange& r : al.down_band[DD]) {
+    hipLaunchKernelGGL((k_band_down<T, RC, V>), dim3(r.n, ctt, nz), dim3(256), 0, s, jobs + r.off,
+                       tin(a), h.B, h.R, (const T*)a.QH, a.UH, c, a.adjoint ? 1 : 0, tin(b2),
+                       (const T*)b2.QH, b2.UH, b2.adjoint ? 1 : 0);
     KCHK();
   }
 }
@@ -377,18 +400,18 @@ void run_bands(const ApplyLists& al, const HbsView<T>& h, bool adjoint, int c, T
 // Vector staging (16-byte loads) needs R a multiple of the vector width and
 // 16-byte aligned operand arrays.
 template <class T>
-void run_bands_any(const ApplyLists& al, const HbsView<T>& h, bool adjoint, int c, T* QH, T* UH,
-                   hipStream_t s) {
+void run_bands_any(const ApplyLists& al, const HbsView<T>& h, int c, const BandSweep<T>& a,
+                   const BandSweep<T>* b, hipStream_t s) {
   constexpr int V = 16 / sizeof(T);
   auto al16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
-  const bool vec = h.R % V == 0 && al16(QH) && al16(UH) && al16(h.Ut) && al16(h.Vt) &&
-                   al16(h.B);
+  bool vec = h.R % V == 0 && al16(a.QH) && al16(a.UH) && al16(h.Ut) && al16(h.Vt) && al16(h.B);
+  if (b) vec = vec && al16(b->QH) && al16(b->UH);
   if (h.R <= 32) {
-    if (vec) run_bands<T, 32, V>(al, h, adjoint, c, QH, UH, s);
-    else run_bands<T, 32, 1>(al, h, adjoint, c, QH, UH, s);
+    if (vec) run_bands<T, 32, V>(al, h, c, a, b, s);
+    else run_bands<T, 32, 1>(al, h, c, a, b, s);
   } else {
-    if (vec) run_bands<T, TRM, V>(al, h, adjoint, c, QH, UH, s);
-    else run_bands<T, TRM, 1>(al, h, adjoint, c, QH, UH, s);
+    if (vec) run_bands<T, TRM, V>(al, h, c, a, b, s);
+    else run_bands<T, TRM, 1>(al, h, c, a, b, s);
   }
 }
 
@@ -572,51 +595,95 @@ size_t apply_work_bytes(const Forest& f, const ApplyLists& al, int R, int c) {
   return b + 256;
 }
 
+// Outgoing expansions on the frontier: QH_v = V_v^T X(I_v) (chunk partials
+// for frontier nodes of more than APPLY_CHUNK rows reduced into QH).
+template <class T>
+static void leaf_up_launch(const Node* d_nodes, const ApplyLists& al, const T* Vout,
+                           int64_t ldl, int R, int c, const T* X, int64_t ldx, T* QH, T* P,
+                           hipStream_t s) {
+  const int ct = (c + TN - 1) / TN;
+  const int* front = al.frontier.as<int32_t>();
+  hipLaunchKernelGGL(k_leaf_up<T>, dim3(al.chunks, al.nfront, ct), dim3(256), 0, s, d_nodes,
+                     front, al.chunks, Vout, ldl, R, X, ldx, c, QH, P);
+  KCHK();
+  if (al.chunks > 1) {
+    const int64_t n = (int64_t)R * c;
+    hipLaunchKernelGGL(k_chunk_reduce<T>, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 64),
+                                               al.nfront),
+                       dim3(256), 0, s, front, al.chunks, P, n, QH, T(1), T(0), n);
+    KCHK();
+  }
+}
+
+// Y(I_v) = beta Y + alpha (U_v UH_v + D_v X(I_v)) on the frontier (D_v^T with
+// adjoint).
+template <class T>
+static void leaf_down_launch(const Node* d_nodes, const ApplyLists& al, const HbsView<T>& h,
+                             bool adjoint, const T* Uin, int c, const T* UH, const T* X,
+                             int64_t ldx, T* Y, int64_t ldy, T alpha, T beta, hipStream_t s) {
+  const int* front = al.frontier.as<int32_t>();
+  // the transposed D reads of the adjoint are uncoalesced from global memory:
+  // that case stays on the K-chunked LDS tiles of k_leaf_down
+  if (al.max_rows <= LEAF_MAX && !(adjoint && h.D)) {
+    constexpr int BN = LeafCfg<T>::BN;
+    hipLaunchKernelGGL(k_leaf_down2<T>, dim3(al.nfront, (c + BN - 1) / BN), dim3(512), 0, s,
+                       d_nodes, front, Uin, h.ldl, h.R, UH, c, h.D, h.ldd, X, ldx, Y, ldy, alpha,
+                       beta);
+    KCHK();
+    return;
+  }
+  const int ct = (c + TN - 1) / TN;
+  const int rt = (int)((al.max_rows + TM - 1) / TM);
+  hipLaunchKernelGGL(k_leaf_down<T>, dim3(rt, al.nfront, ct), dim3(256), 0, s, d_nodes, front,
+                     Uin, h.ldl, h.R, UH, c, h.D, h.ldd, adjoint ? 1 : 0, X, ldx, Y, ldy, alpha,
+                     beta);
+  KCHK();
+}
+
+template <class T>
+static void apply_checks(const ApplyLists& al, int R) {
+  if (R > TRM) HM_THROW(HM_ERR_UNSUPPORTED, "apply: padded rank %d > %d", R, TRM);
+  if (al.mmax >= 1 && al.bands.bytes == 0)
+    HM_THROW(HM_ERR_ARG, "apply: band lists missing");
+}
+
 template <class T>
 void apply_forest(const Node* d_nodes, const ApplyLists& al, const HbsView<T>& h, bool adjoint,
                   int c, const T* X, int64_t ldx, T* Y, int64_t ldy, T alpha, T beta, void* work,
                   size_t nnodes, hipStream_t s, bool expansions_only) {
   if (al.nfront == 0 || c <= 0) return;
   const int R = h.R;
-  if (R > TRM) HM_THROW(HM_ERR_UNSUPPORTED, "apply: padded rank %d > %d", R, TRM);
-  if (al.mmax >= 1 && al.bands.bytes == 0)
-    HM_THROW(HM_ERR_ARG, "apply: band lists missing");
+  apply_checks<T>(al, R);
   T* QH = static_cast<T*>(work);
   T* UH = QH + (size_t)R * c * nnodes;
   T* P = UH + (size_t)R * c * nnodes;
-  const int ct = (c + TN - 1) / TN;
   const T* Uin = adjoint ? h.Vlong : h.Ulong;  // incoming long basis
   const T* Vout = adjoint ? h.Ulong : h.Vlong; // outgoing long basis
-  const int* front = al.frontier.as<int32_t>();
   if (al.mmax >= 1 && R > 0) {
-    hipLaunchKernelGGL(k_leaf_up<T>, dim3(al.chunks, al.nfront, ct), dim3(256), 0, s, d_nodes,
-                       front, al.chunks, Vout, h.ldl, R, X, ldx, c, QH, P);
-    KCHK();
-    if (al.chunks > 1) {
-      const int64_t n = (int64_t)R * c;
-      hipLaunchKernelGGL(k_chunk_reduce<T>, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 64),
-                                                 al.nfront),
-                         dim3(256), 0, s, front, al.chunks, P, n, QH, T(1), T(0), n);
-      KCHK();
-    }
-    run_bands_any<T>(al, h, adjoint, c, QH, UH, s);
+    leaf_up_launch<T>(d_nodes, al, Vout, h.ldl, R, c, X, ldx, QH, P, s);
+    run_bands_any<T>(al, h, c, BandSweep<T>{adjoint, QH, UH}, nullptr, s);
   }
   if (expansions_only) return;
-  // the transposed D reads of the adjoint are uncoalesced from global memory:
-  // that case stays on the K-chunked LDS tiles of k_leaf_down
-  if (al.max_rows <= LEAF_MAX && !(adjoint && h.D)) {
-    constexpr int BN = LeafCfg<T>::BN;
-    hipLaunchKernelGGL(k_leaf_down2<T>, dim3(al.nfront, (c + BN - 1) / BN), dim3(512), 0, s,
-                       d_nodes, front, Uin, h.ldl, R, UH, c, h.D, h.ldd, X, ldx, Y, ldy, alpha,
-                       beta);
-    KCHK();
-    return;
+  leaf_down_launch<T>(d_nodes, al, h, adjoint, Uin, c, UH, X, ldx, Y, ldy, alpha, beta, s);
+}
+
+template <class T>
+void apply_forest_pair(const Node* d_nodes, const ApplyLists& al, const HbsView<T>& h, int c,
+                       const T* X, int64_t ldx, void* work_x, const T* G, int64_t ldg, T* Y,
+                       int64_t ldy, void* work_g, size_t nnodes, hipStream_t s) {
+  if (al.nfront == 0 || c <= 0) return;
+  const int R = h.R;
+  apply_checks<T>(al, R);
+  const size_t blk = (size_t)R * c * nnodes;
+  T* QX = static_cast<T*>(work_x);
+  T* QG = static_cast<T*>(work_g);
+  if (al.mmax >= 1 && R > 0) {
+    leaf_up_launch<T>(d_nodes, al, h.Vlong, h.ldl, R, c, X, ldx, QX, QX + 2 * blk, s);
+    leaf_up_launch<T>(d_nodes, al, h.Ulong, h.ldl, R, c, G, ldg, QG, QG + 2 * blk, s);
+    const BandSweep<T> adj{true, QG, QG + blk};
+    run_bands_any<T>(al, h, c, BandSweep<T>{false, QX, QX + blk}, &adj, s);
   }
-  const int rt = (int)((al.max_rows + TM - 1) / TM);
-  hipLaunchKernelGGL(k_leaf_down<T>, dim3(rt, al.nfront, ct), dim3(256), 0, s, d_nodes, front,
-                     Uin, h.ldl, R, UH, c, h.D, h.ldd, adjoint ? 1 : 0, X, ldx, Y, ldy, alpha,
-                     beta);
-  KCHK();
+  leaf_down_launch<T>(d_nodes, al, h, true, h.Vlong, c, QG + blk, G, ldg, Y, ldy, T(1), T(0), s);
 }
 
 // ------------------------------------------------------------ HODLR level --
@@ -741,6 +808,9 @@ void seg_tn(const Node* d_nodes, const int32_t* list, int nlist, int64_t max_row
   template void apply_forest<T>(const Node*, const ApplyLists&, const HbsView<T>&, bool, int,  \
                                 const T*, int64_t, T*, int64_t, T, T, void*, size_t,           \
                                 hipStream_t, bool);                                            \
+  template void apply_forest_pair<T>(const Node*, const ApplyLists&, const HbsView<T>&, int,    \
+                                     const T*, int64_t, void*, const T*, int64_t, T*, int64_t, \
+                                     void*, size_t, hipStream_t);                               \
   template void seg_tn<T>(const Node*, const int32_t*, int, int64_t, int, int, const T*,       \
                           int64_t, const T*, int64_t, T*, int64_t, int64_t, T, T, void*,       \
                           hipStream_t, int);                                                   \
