@@ -289,7 +289,9 @@ int hss_apply_adjoint(const hm_hbs* h, int64_t nrhs, const void* x, int64_t ldx,
 /* Backward of y = A_H x (not in the paper): given gy, writes gx = A_H^* gy and
  * the gradients of <gy, A_H x> with respect to the generators in the flat
  * layout of hm_hbs_from_generators (any of the generator outputs may be NULL
- * to skip it).  Same dtype rules as hss_apply. */
+ * to skip it).  Every entry of each requested output is written (blocks that
+ * no node owns, and D columns past a leaf's size, are set to zero), so the
+ * outputs need no initialisation.  Same dtype rules as hss_apply. */
 int hss_apply_backward(const hm_hbs* h, int64_t nrhs, const void* x, int64_t ldx,
                        const void* gy, int64_t ldgy, void* gx, int64_t ldgx,
                        void* gU, void* gV, void* gUt, void* gVt, void* gB,

@@ -168,6 +168,15 @@ def to_fortran(x, dtype=None, device="cuda"):
     return out
 
 
+def _device_fortran(x, dtype):
+    """``x`` itself when it already is a column-major device tensor of
+    ``dtype``, else a column-major device copy."""
+    if isinstance(x, torch.Tensor) and x.dim() == 2 and x.stride(0) == 1 and x.dtype == dtype \
+            and x.is_cuda:
+        return x
+    return to_fortran(x, dtype)
+
+
 def _ld(t):
     """Leading dimension of a column-major 2-D tensor."""
     if t.dim() != 2 or t.stride(0) != 1:
@@ -565,7 +574,7 @@ def hbs_compress_batched(opts_list, ops_list, stream=None):
 
 def _apply(fn, h, x, stream):
     dt = torch.float64 if h.info()["dtype"] == HM_F64 else torch.float32
-    xf = x if (x.dim() == 2 and x.stride(0) == 1 and x.dtype == dt and x.is_cuda) else to_fortran(x, dt)
+    xf = _device_fortran(x, dt)
     y = fortran(xf.shape[0], xf.shape[1], dt)
     _check(fn(h.handle, xf.shape[1], _ptr(xf), _ld(xf), _ptr(y), _ld(y), _stream(stream)))
     return y
@@ -594,15 +603,16 @@ def hss_apply_backward(h: HBS, x, gy, want_generators=True, stream=None):
     dt = torch.float64 if inf["dtype"] == HM_F64 else torch.float32
     n, R, L = inf["n"], inf["rank_pad"], inf["levels"]
     nn = 2 ** (L + 1)
-    xf = to_fortran(x, dt)
-    gyf = to_fortran(gy, dt)
+    xf = _device_fortran(x, dt)
+    gyf = _device_fortran(gy, dt)
     gx = fortran(n, xf.shape[1], dt)
     g = None
     if want_generators:
+        # the library writes every entry (zeroing the blocks no node owns)
         g = dict(U=fortran(n, R, dt), V=fortran(n, R, dt),
-                 Ut=torch.zeros((nn, R, 2 * R), dtype=dt, device="cuda"),
-                 Vt=torch.zeros((nn, R, 2 * R), dtype=dt, device="cuda"),
-                 B=torch.zeros((nn, R, R), dtype=dt, device="cuda"),
+                 Ut=torch.empty((nn, R, 2 * R), dtype=dt, device="cuda"),
+                 Vt=torch.empty((nn, R, 2 * R), dtype=dt, device="cuda"),
+                 B=torch.empty((nn, R, R), dtype=dt, device="cuda"),
                  D=fortran(n, HBS._nmax(n, inf["leaf_size"], L), dt))
     gp = (lambda k: _ptr(g[k]) if g else None)
     _check(lib.hss_apply_backward(h.handle, xf.shape[1], _ptr(xf), _ld(xf), _ptr(gyf), _ld(gyf),

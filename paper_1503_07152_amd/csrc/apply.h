@@ -24,6 +24,7 @@ struct BandJob {
 };
 struct BandRange {
   int off, n;   // jobs [off, off + n) of one launch
+  int depth;    // the largest job depth among them (sizes the launch's LDS)
 };
 
 struct ApplyLists {

@@ -50,22 +50,25 @@ void build_apply_lists(const Forest& f, const std::vector<int>& m, ApplyLists& o
     out.down_band[D].clear();
     for (int hi = M; hi >= 1; hi -= D) {
       const int lo = std::max(1, hi - D + 1);
-      BandRange br{(int)jobs.size(), 0};
+      BandRange br{(int)jobs.size(), 0, 0};
       for (int g : f.level[lo]) {
         const int mi = m[f.nodes[g].inst];
         if (mi < 0 || lo >= mi) continue;
-        job(g, std::min(hi, mi - 1) - lo + 1, std::min(hi, mi - 1) - lo + 1);
+        const int d = std::min(hi, mi - 1) - lo + 1;
+        job(g, d, d);
+        br.depth = std::max(br.depth, d);
       }
       br.n = (int)jobs.size() - br.off;
       if (br.n > 0) out.up_band[D].push_back(br);
     }
     for (int lo = 0; lo <= M; lo += D) {
-      BandRange br{(int)jobs.size(), 0};
+      BandRange br{(int)jobs.size(), 0, 0};
       for (int g : f.level[lo]) {
         const int mi = m[f.nodes[g].inst];
         if (mi < 1 || lo >= mi) continue;
         const int d = std::min(D, mi - lo);
         job(g, d, d | (lo >= 1 ? 1 << 8 : 0));
+        br.depth = std::max(br.depth, d);
       }
       br.n = (int)jobs.size() - br.off;
       if (br.n > 0) out.down_band[D].push_back(br);
@@ -215,7 +218,7 @@ __device__ __forceinline__ void band_zero_pad(T* lds, int nblk, int bs, int P, i
   }
 }
 
-template <class T, int RC, int V>
+template <class T, int RC, int V, int DM>
 __global__ __launch_bounds__(256) void k_band_up(const BandJob* jobs, const T* Tout, int R,
                                                  T* QH, int c, const T* Tout2, T* QH2) {
   typedef MfTraits<T> Tr;
@@ -224,7 +227,7 @@ __global__ __launch_bounds__(256) void k_band_up(const BandJob* jobs, const T* T
     QH = QH2;
   }
   constexpr int BC = BandCfg<T>::BC, CT = BC / 16;
-  constexpr int DM = band_depth_up<T>(RC);
+  static_assert(DM >= 1 && DM <= band_depth_up<T>(RC), "band depth beyond the LDS");
   __shared__ T lds[band_up_elems(RC, BC, DM) + BAND_SLACK];
   __shared__ int sids[16];
   const int tid = threadIdx.x, wave = tid >> 6;
@@ -278,7 +281,7 @@ __global__ __launch_bounds__(256) void k_band_up(const BandJob* jobs, const T* T
   }
 }
 
-template <class T, int RC, int V>
+template <class T, int RC, int V, int DM>
 __global__ __launch_bounds__(256) void k_band_down(const BandJob* jobs, const T* Tin,
                                                    const T* B, int R, const T* QH, T* UH, int c,
                                                    int adjoint, const T* Tin2, const T* QH2,
@@ -291,7 +294,7 @@ __global__ __launch_bounds__(256) void k_band_down(const BandJob* jobs, const T*
     adjoint = adjoint2;
   }
   constexpr int BC = BandCfg<T>::BC, CT = BC / 16;
-  constexpr int DM = band_depth_down<T>(RC);
+  static_assert(DM >= 1 && DM <= band_depth_down<T>(RC), "band depth beyond the LDS");
   __shared__ T lds[band_down_elems(RC, BC, DM) + BAND_SLACK];
   __shared__ int sids[16];
   const int tid = threadIdx.x, wave = tid >> 6;
@@ -384,16 +387,28 @@ void run_bands(const ApplyLists& al, const HbsView<T>& h, int c, const BandSweep
   auto tout = [&](const BandSweep<T>& w) { return w.adjoint ? h.Ut : h.Vt; };
   const BandSweep<T>& b2 = b ? *b : a;
   const unsigned nz = b ? 2 : 1;
-  for (const BandRange& r : al.up_band[DU]) {
-    hipLaunchKernelGGL((k_band_up<T, RC, V>), dim3(r.n, ctt, nz), dim3(256), 0, s, jobs + r.off,
-                       tout(a), h.R, a.QH, c, tout(b2), b2.QH);
+  // each launch sized to its band's depth (a shallow band, such as the last
+  // downward one, takes less LDS and runs more workgroups per CU)
+  auto up = [&](auto kern, const BandRange& r) {
+    hipLaunchKernelGGL(kern, dim3(r.n, ctt, nz), dim3(256), 0, s, jobs + r.off, tout(a), h.R,
+                       a.QH, c, tout(b2), b2.QH);
     KCHK();
+  };
+  auto down = [&](auto kern, const BandRange& r) {
+    hipLaunchKernelGGL(kern, dim3(r.n, ctt, nz), dim3(256), 0, s, jobs + r.off, tin(a), h.B, h.R,
+                       (const T*)a.QH, a.UH, c, a.adjoint ? 1 : 0, tin(b2), (const T*)b2.QH,
+                       b2.UH, b2.adjoint ? 1 : 0);
+    KCHK();
+  };
+  for (const BandRange& r : al.up_band[DU]) {
+    if (r.depth <= 1) up(k_band_up<T, RC, V, 1>, r);
+    else if (r.depth == 2 || DU == 2) up(k_band_up<T, RC, V, DU >= 2 ? 2 : 1>, r);
+    else up(k_band_up<T, RC, V, DU>, r);
   }
   for (const BandRange& r : al.down_band[DD]) {
-    hipLaunchKernelGGL((k_band_down<T, RC, V>), dim3(r.n, ctt, nz), dim3(256), 0, s, jobs + r.off,
-                       tin(a), h.B, h.R, (const T*)a.QH, a.UH, c, a.adjoint ? 1 : 0, tin(b2),
-                       (const T*)b2.QH, b2.UH, b2.adjoint ? 1 : 0);
-    KCHK();
+    if (r.depth <= 1) down(k_band_down<T, RC, V, 1>, r);
+    else if (r.depth == 2 || DD == 2) down(k_band_down<T, RC, V, DD >= 2 ? 2 : 1>, r);
+    else down(k_band_down<T, RC, V, DD>, r);
   }
 }
 
