@@ -107,9 +107,7 @@ static void backward_impl(const hm_hbs* h, int c, const T* x, int64_t ldx, const
   apply_forest_pair<T>(h->d_nodes.as<Node>(), h->full, hv, c, x, ldx, w1, gy, ldgy, gx, ldgx, w2,
                        nn, s);
   const size_t es = sizeof(T);
-  if (gUt) HIPCHK(hipMemsetAsync(gUt, 0, (size_t)(nn + 1) * 2 * R * R * es, s));
-  if (gVt) HIPCHK(hipMemsetAsync(gVt, 0, (size_t)(nn + 1) * 2 * R * R * es, s));
-  if (gB) HIPCHK(hipMemsetAsync(gB, 0, (size_t)(nn + 1) * R * R * es, s));
+  // gUt, gVt, gB: every block is written by the node-gradient kernel
   int64_t maxl = 0, minl = INT64_MAX;
   for (int g : f.leaves) {
     maxl = std::max<int64_t>(maxl, f.nodes[g].hi - f.nodes[g].lo);

@@ -54,7 +54,8 @@ __global__ __launch_bounds__(256) void k_grad_leaf(const Node* nodes, const int3
 
 // Nodes: gB for every non-root node, gUt / gVt halves for children of internal nodes.
 // Output blocks are heap-indexed in the flat layout: node g -> block g + 1 of
-// its tree (single-tree handles).
+// its tree (single-tree handles).  The blocks no node owns (gB of the root,
+// gUt / gVt of the root and of the leaves, and block 0) are written as zeros.
 template <class T>
 __global__ __launch_bounds__(256) void k_grad_node(const Node* nodes, const int32_t* list, int R,
                                                    int c, const T* QH, const T* UH,
@@ -69,7 +70,12 @@ __global__ __launch_bounds__(256) void k_grad_node(const Node* nodes, const int3
   acc.zero();
   const T* qh = QH + (int64_t)v * R * c;
   if (part == 0) {
-    if (!gB || nd.parent < 0) return;
+    if (!gB) return;
+    if (nd.parent < 0) {
+      mf_store<T>(R, R, gB + blk * R * R, R, acc, T(1), T(0));
+      mf_store<T>(R, R, gB, R, acc, T(1), T(0));
+      return;
+    }
     // gB[v] = g(uh)_sib qh_v^T
     mf_tile<T>(R, R, c, GU + (int64_t)nd.sib * R * c, 1, R, qh, R, 1, acc, smem);
     mf_store<T>(R, R, gB + blk * R * R, R, acc, T(1), T(0));
@@ -77,8 +83,13 @@ __global__ __launch_bounds__(256) void k_grad_node(const Node* nodes, const int3
     // part 1: gUt half of child (side 0/1), part 3/4: gVt half
     const bool want_u = part <= 2;
     const int side = (part - 1) % 2;
-    if (nd.left < 0 || nd.parent < 0) return;
     if (want_u ? !gUt : !gVt) return;
+    if (nd.left < 0 || nd.parent < 0) {
+      T* gt = want_u ? gUt : gVt;
+      mf_store<T>(R, R, gt + blk * 2 * R * R + side * R, 2 * R, acc, T(1), T(0));
+      if (nd.parent < 0) mf_store<T>(R, R, gt + side * R, 2 * R, acc, T(1), T(0));
+      return;
+    }
     const int a = side == 0 ? nd.left : nd.right;
     if (want_u) {
       mf_tile<T>(R, R, c, GU + (int64_t)a * R * c, 1, R, UH + (int64_t)v * R * c, R, 1,

@@ -160,3 +160,44 @@ def test_backward_fp32_full_size_against_oracle():
         worst = max(worst, float(np.abs(gD[I, :m] - ref).max() / np.abs(ref).max()))
     say(f"  gD max entry error {worst:.2e}")
     assert worst < 1e-5
+
+
+def test_backward_writes_every_output_entry():
+    """The outputs need no initialisation: with every output prefilled with NaN,
+    the blocks no node owns (gB of the root, gUt / gVt of the root and the
+    leaves, block 0) and the D columns past a ragged leaf's size come back as
+    exact zeros, and the owned entries equal those of a call on zeroed outputs."""
+    n, leaf, k, c = 1000, 64, 6, 3
+    say("backward writes every entry n=1000")
+    g = W.synthetic_hbs(n, leaf, k, seed=9)
+    h = hm.hm_hbs_from_generators(g)
+    inf = h.info()
+    R, L = inf["rank_pad"], inf["levels"]
+    nn = 2 ** (L + 1)
+    nmax = hm.HBS._nmax(n, leaf, L)
+    x = hm.to_fortran(torch.from_numpy(W.gaussian((n, c), seed=1)))
+    gy = hm.to_fortran(torch.from_numpy(W.gaussian((n, c), seed=2)))
+
+    def run(fill):
+        out = dict(gx=hm.fortran(n, c), U=hm.fortran(n, R), V=hm.fortran(n, R),
+                   Ut=torch.empty((nn, R, 2 * R), dtype=torch.float64, device="cuda"),
+                   Vt=torch.empty((nn, R, 2 * R), dtype=torch.float64, device="cuda"),
+                   B=torch.empty((nn, R, R), dtype=torch.float64, device="cuda"),
+                   D=hm.fortran(n, nmax))
+        for t in out.values():
+            t.fill_(fill)
+        p = hm._ptr
+        hm._check(hm.lib.hss_apply_backward(
+            h.handle, c, p(x), hm._ld(x), p(gy), hm._ld(gy), p(out["gx"]), hm._ld(out["gx"]),
+            p(out["U"]), p(out["V"]), p(out["Ut"]), p(out["Vt"]), p(out["B"]), p(out["D"]),
+            hm._stream(None)))
+        torch.cuda.synchronize()
+        return {kk: v.cpu().numpy() for kk, v in out.items()}
+
+    a, z = run(float("nan")), run(0.0)
+    for kk in a:
+        assert np.isfinite(a[kk]).all(), kk
+        np.testing.assert_array_equal(a[kk], z[kk], err_msg=kk)
+    for kk in ("Ut", "Vt"):
+        assert not a[kk][:2].any() and not a[kk][2 ** L:].any(), kk
+    assert not a["B"][:2].any()
