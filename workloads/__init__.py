@@ -26,6 +26,12 @@ synthetic stand-ins replace them):
   ``N(0,1) * 2**-level``, leaf diagonal blocks ``N(0,1) + 8 I``.
 * batched instances: ``N_i = 64 * round(exp(U[ln 512, ln 8192]) / 64)``,
   ``k_i ~ U{8..40}``.
+* conduction grid of nested dissection (Sec. 5.4, geometry of Fig. 13): a grid of
+  ``height`` rows and ``width`` (= 41) columns of nodes; every bar between two
+  neighbouring nodes has a conductivity drawn from U[1, 2].  Horizontal bars
+  ``ch[i, j]`` join nodes (i, j) and (i, j+1); vertical bars ``cv[i, j]`` join
+  (i, j) and (i+1, j).  Only the conductivities are made here; the matrix
+  they define is each consumer's own.
 
 The synthetic operators are *defined* on the uniform binary partition of
 ``[0, N)``: depth ``L = ceil(log2(N / leaf))`` (0 if ``N <= leaf``), every
@@ -179,3 +185,17 @@ def gaussian(shape, seed: int, dtype=np.float64) -> np.ndarray:
     """Gaussian array from PCG64(seed) (right-hand sides, upstream gradients)."""
     rng = np.random.default_rng(seed)
     return np.asarray(rng.standard_normal(shape), dtype=dtype)
+
+
+def grid_conductivities(height: int, width: int = 41, seed: int = 7):
+    """Bar conductivities of the ``height`` x ``width`` conduction grid, drawn
+    from U[1, 2] with PCG64(seed): ``ch`` is ``height x (width - 1)``
+    (horizontal bars), ``cv`` is ``(height - 1) x width`` (vertical bars),
+    both C-ordered FP64 (``ch[i, j]`` joins nodes (i, j) and (i, j + 1),
+    ``cv[i, j]`` joins (i, j) and (i + 1, j))."""
+    if height < 1 or width < 3 or width % 2 == 0:
+        raise ValueError("height >= 1 and an odd width >= 3")
+    rng = np.random.default_rng(seed)
+    ch = rng.uniform(1.0, 2.0, size=(height, width - 1))
+    cv = rng.uniform(1.0, 2.0, size=(max(height - 1, 0), width))
+    return np.ascontiguousarray(ch), np.ascontiguousarray(cv)
