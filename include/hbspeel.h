@@ -68,6 +68,8 @@ extern "C" {
 #define HM_OP_HBS 3        /* a matrix held as an HBS handle, applied in O(N k) */
 #define HM_OP_HBS_PRODUCT 4 /* the product hbs * hbs2 of two HBS handles, each
                                applied in O(N k) (Sec. 5.2, operator multiplication) */
+#define HM_OP_FRONTAL 5    /* the frontal matrix of nested dissection held in an
+                              hm_frontal handle (Sec. 5.4), symmetric */
 
 #define HM_KERNEL_LOG 0    /* A(i,j) = log|x_i - x_j| (i != j), A(i,i) = 1       */
 #define HM_KERNEL_NEAR 1   /* A(i,j) = 1 / (|x_i - x_j| + kparam) (all i, j)     */
@@ -75,6 +77,7 @@ extern "C" {
 typedef struct hm_hbs_s hm_hbs;
 typedef struct hm_hodlr_s hm_hodlr;
 typedef struct hm_hbs_factor_s hm_hbs_factor;
+typedef struct hm_frontal_s hm_frontal;
 
 /*
  * Black-box product (Sec. 1, "T_mult"; applied to N x ncols blocks as in
@@ -113,6 +116,7 @@ typedef struct hm_operator {
   const hm_hbs* hbs;     /* HM_OP_HBS, HM_OP_HBS_PRODUCT: an FP64 handle (left factor) */
   const hm_hbs* hbs2;    /* HM_OP_HBS_PRODUCT: the right factor, an FP64 handle of
                             the same size: A x = hbs (hbs2 x), A^* x = hbs2^* (hbs^* x) */
+  const hm_frontal* frontal; /* HM_OP_FRONTAL: a handle of height n               */
 } hm_operator;
 
 /* Flags */
@@ -337,6 +341,35 @@ int hbs_factor(const hm_hbs* h, void* stream, hm_hbs_factor** out);
 int hbs_solve(const hm_hbs_factor* f, int64_t nrhs, const double* b, int64_t ldb, double* x,
               int64_t ldx, void* stream);
 void hm_hbs_factor_free(hm_hbs_factor* f);
+
+/* ---- frontal matrix of nested dissection (Sec. 5.4, Fig. 13) -----------------
+ * The black box of that section: a conduction grid of `height` rows and
+ * `width` (odd; 41 in the paper) columns of nodes, a bar between every two
+ * neighbouring nodes, B the network's matrix (graph Laplacian: the sum of the
+ * conductivities of a node's bars on the diagonal, minus the bar's
+ * conductivity between neighbours), I3 the middle column (by row), I1 / I2
+ * the columns left / right of it, and
+ *   A = B33 - B31 B11^-1 B13 - B32 B22^-1 B23     (height x height, symmetric).
+ * hm_frontal_create factors B11 and B22 on the device (block cyclic
+ * reduction over grid rows, FP64) and returns when the factor is complete.
+ * ch: device, height x (width - 1) C-ordered, ch[i (width-1) + j] joins nodes
+ * (i, j) and (i, j+1); cv: device, (height - 1) x width C-ordered, cv[i width +
+ * j] joins (i, j) and (i+1, j) (may be NULL when height == 1).  Both are read
+ * during the call only.  Conductivities must be positive and finite; a
+ * non-positive pivot gives HM_ERR_SINGULAR.  width > 65 gives
+ * HM_ERR_UNSUPPORTED, other bad sizes HM_ERR_ARG.  With w = (width - 1) / 2,
+ * the handle holds 8 (6 w^2 + 3) height bytes of device memory (2 GB per 100k
+ * rows at width 41) and the call uses 32 w^2 height bytes more as work.
+ * hm_frontal_apply: Y = A X for X, Y device, column-major, height x ncols,
+ * leading dims >= height (HM_ERR_ARG otherwise); FP64; enqueued on `stream`,
+ * in passes of at most 128 columns with a work block of 16 w height c bytes
+ * for c columns; X and Y must not overlap.  The handle is also an operator
+ * (HM_OP_FRONTAL) for the compressions.  hm_frontal_free(NULL) is a no-op. */
+int hm_frontal_create(int64_t height, int32_t width, const double* ch, const double* cv,
+                      void* stream, hm_frontal** out);
+int hm_frontal_apply(const hm_frontal* f, int64_t ncols, const double* X, int64_t ldx, double* Y,
+                     int64_t ldy, void* stream);
+void hm_frontal_free(hm_frontal* f);
 
 /* HODLR apply: y = A_H x (adjoint = 0) or A_H^* x; FP64. */
 int hodlr_apply(const hm_hodlr* h, int32_t adjoint, int64_t nrhs,

@@ -21,7 +21,7 @@ import torch
 __all__ = [
     "HM_F64", "HM_F32", "HM_BF16", "lib", "HMError", "fortran", "to_fortran",
     "Options", "KernelOperator", "DenseOperator", "HBSOperator", "HBSProductOperator",
-    "CallbackOperator",
+    "CallbackOperator", "Frontal", "FrontalOperator", "frontal_create",
     "HBS", "HODLR", "hm_gauss", "hm_operator_apply", "hbs_compress", "hbs_compress_adaptive",
     "hodlr_compress", "hbs_compress_batched", "autotune", "hbs_factor", "HBSFactor",
     "hss_apply", "hss_apply_adjoint", "hss_apply_noalloc", "hss_apply_backward", "hodlr_apply",
@@ -31,6 +31,7 @@ __all__ = [
 HM_OK, HM_WARN_RANK_SATURATED = 0, 1
 HM_F64, HM_F32, HM_BF16 = 0, 1, 2
 HM_OP_CALLBACK, HM_OP_KERNEL, HM_OP_DENSE, HM_OP_HBS, HM_OP_HBS_PRODUCT = 0, 1, 2, 3, 4
+HM_OP_FRONTAL = 5
 HM_KERNEL_LOG, HM_KERNEL_NEAR = 0, 1
 HM_FLAG_ORTHONORMAL, HM_FLAG_PERSISTENT_ID = 1, 2
 HM_MAX_SAMPLES = 48
@@ -51,7 +52,7 @@ class _Operator(C.Structure):
     _fields_ = [("kind", C.c_int32), ("sample_dtype", C.c_int32), ("fn", MATVEC),
                 ("user", C.c_void_p), ("points", C.c_void_p), ("kernel_id", C.c_int32),
                 ("kparam", C.c_double), ("dense", C.c_void_p), ("ld", C.c_int64),
-                ("hbs", C.c_void_p), ("hbs2", C.c_void_p)]
+                ("hbs", C.c_void_p), ("hbs2", C.c_void_p), ("frontal", C.c_void_p)]
 
 
 class _Options(C.Structure):
@@ -122,6 +123,9 @@ _SIGS = {
     "hbs_solve": (C.c_int, [_P, _I64, _P, _I64, _P, _I64, _P]),
     "hm_hbs_factor_free": (None, [_P]),
     "hm_hodlr_free": (None, [_P]),
+    "hm_frontal_create": (C.c_int, [_I64, _I32, _P, _P, _P, C.POINTER(_P)]),
+    "hm_frontal_apply": (C.c_int, [_P, _I64, _P, _I64, _P, _I64, _P]),
+    "hm_frontal_free": (None, [_P]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(lib, _name)
@@ -470,6 +474,59 @@ def hbs_factor(h, stream=None) -> HBSFactor:
     f = C.c_void_p()
     _check(lib.hbs_factor(h.handle, _stream(stream), C.byref(f)))
     return HBSFactor(f)
+
+
+class Frontal:
+    """The frontal matrix of nested dissection (Sec. 5.4) of a conduction grid
+    with bar conductivities ``ch`` (height x (width-1)) and ``cv``
+    ((height-1) x width), factored on the device (``hm_frontal_create``);
+    ``apply(x)`` returns ``A x`` (FP64)."""
+
+    def __init__(self, handle, height):
+        self.handle = handle
+        self.n = height
+        _LIVE.add(self)
+
+    _free = lib.hm_frontal_free
+
+    def _release(self):
+        if getattr(self, "handle", None):
+            type(self)._free(self.handle)
+            self.handle = None
+
+    __del__ = _release
+
+    def apply(self, x, stream=None):
+        xf = to_fortran(x, torch.float64)
+        y = fortran(xf.shape[0], xf.shape[1])
+        _check(lib.hm_frontal_apply(self.handle, xf.shape[1], _ptr(xf), _ld(xf), _ptr(y), _ld(y),
+                                    _stream(stream)))
+        return y
+
+
+def frontal_create(ch, cv, stream=None) -> Frontal:
+    ch = torch.as_tensor(ch, dtype=torch.float64).to("cuda").contiguous()
+    height, wm1 = ch.shape
+    cvp = None
+    if height > 1:
+        cv = torch.as_tensor(cv, dtype=torch.float64).to("cuda").contiguous()
+        if tuple(cv.shape) != (height - 1, wm1 + 1):
+            raise ValueError(f"cv has shape {tuple(cv.shape)}, expected {(height - 1, wm1 + 1)}")
+        cvp = cv.data_ptr()
+    f = C.c_void_p()
+    _check(lib.hm_frontal_create(height, wm1 + 1, ch.data_ptr(), cvp, _stream(stream),
+                                 C.byref(f)))
+    return Frontal(f, height)
+
+
+class FrontalOperator:
+    """A ``Frontal`` handle as the black box of a compression (symmetric)."""
+
+    def __init__(self, f):
+        self.f = f
+        self.c = _Operator()
+        self.c.kind = HM_OP_FRONTAL
+        self.c.frontal = f.handle
 
 
 class HODLR:

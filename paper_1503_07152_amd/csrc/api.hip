@@ -73,6 +73,11 @@ void check_operator(const hm_operator* op, int64_t n, bool builtin_only) {
         if (!x || x->f.n_total != n || x->dtype != HM_F64 || x->f.inst.size() != 1)
           HM_THROW(HM_ERR_ARG, "HBS product operator: null, size mismatch or not FP64");
       break;
+    case HM_OP_FRONTAL:
+      if (builtin_only) HM_THROW(HM_ERR_ARG, "frontal operators are not allowed here");
+      if (!op->frontal || frontal_n(op->frontal) != n)
+        HM_THROW(HM_ERR_ARG, "frontal operator: null or height != n");
+      break;
     default:
       HM_THROW(HM_ERR_ARG, "unknown operator kind %d", op->kind);
   }

@@ -52,7 +52,16 @@ struct hm_hodlr_s {
   hm_info info{};
 };
 
+struct hm_frontal_s;   // frontal.hip
+
 namespace hm {
+
+// Frontal-matrix black box (frontal.hip): Y = A X for ncols columns, with a
+// work block of frontal_work_bytes(f, ncols) bytes.
+void frontal_apply(const hm_frontal_s* f, int64_t ncols, const double* X, int64_t ldx, double* Y,
+                   int64_t ldy, void* work, hipStream_t s);
+size_t frontal_work_bytes(const hm_frontal_s* f, int64_t ncols);
+int64_t frontal_n(const hm_frontal_s* f);
 
 // Device copies of small per-call tables (node lists, descriptors): device
 // blocks, bump-allocated, filled through the pinned staging of stage_h2d, so

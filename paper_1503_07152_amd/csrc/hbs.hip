@@ -95,6 +95,12 @@ void OpRunner::apply(bool adjoint, int64_t n, int c, const double* X, int64_t ld
                            second->f.nodes.size(), s);
       break;
     }
+    case HM_OP_FRONTAL: {
+      // symmetric: A^* X = A X
+      work.ensure(frontal_work_bytes(op.frontal, c), s);
+      frontal_apply(op.frontal, c, X, ldx, Y, ldy, work.base(), s);
+      break;
+    }
     default:
       HM_THROW(HM_ERR_ARG, "unknown operator kind %d", op.kind);
   }

@@ -83,3 +83,20 @@ def test_allocator_and_views_argument_checks_on_host():
     v = hm._Views()
     assert hm.lib.hm_hbs_generators(None, C.byref(v)) == -1
     assert "generators" in hm.lib.hm_last_error().decode()
+
+
+@pytest.mark.parametrize("height,width,ch,cv,code", [
+    (0, 41, 1, 1, -1),        # no rows
+    (8, 40, 1, 1, -1),        # even width: no middle column
+    (8, 1, 1, 1, -1),         # no sides
+    (8, 67, 1, 1, -6),        # sides wider than 32 columns
+    (8, 41, None, 1, -1),     # no conductivities
+    (8, 41, 1, None, -1),     # vertical bars missing with more than one row
+])
+def test_frontal_arguments_rejected_on_host(height, width, ch, cv, code):
+    import paper_1503_07152_amd as hm
+    f = C.c_void_p(123)
+    rc = hm.lib.hm_frontal_create(height, width, ch, cv, None, C.byref(f))
+    assert rc == code
+    assert f.value is None
+    assert hm.lib.hm_frontal_apply(None, 1, 1, 8, 1, 8, None) == -1
