@@ -362,8 +362,9 @@ void hm_hbs_factor_free(hm_hbs_factor* f);
  * rows at width 41) and the call uses 32 w^2 height bytes more as work.
  * hm_frontal_apply: Y = A X for X, Y device, column-major, height x ncols,
  * leading dims >= height (HM_ERR_ARG otherwise); FP64; enqueued on `stream`,
- * in passes of at most 128 columns with a work block of 16 w height c bytes
- * for c columns; X and Y must not overlap.  The handle is also an operator
+ * in passes of at most 128 columns with a work block of about
+ * 8 (2 wp + 5) height c bytes for c columns (wp: w rounded up to a multiple
+ * of 4); X and Y must not overlap.  The handle is also an operator
  * (HM_OP_FRONTAL) for the compressions.  hm_frontal_free(NULL) is a no-op. */
 int hm_frontal_create(int64_t height, int32_t width, const double* ch, const double* cv,
                       void* stream, hm_frontal** out);

@@ -36,8 +36,10 @@
 struct hm_frontal_s {
   int64_t H = 0;
   int W = 0, w = 0;
+  int wp = 0;            // w rounded up to a multiple of 4
   int levels = 0;        // reduction levels: n_levels == 1
   hm::DevBuf fac;        // [side][row][Dinv | gam | del], w x w column-major each
+  hm::DevBuf edge;       // [side][row][gam(w-1, :) | del(w-1, :) | Dinv(w-1, w-1), 0]
   hm::DevBuf bars;       // [row][cL, cR, cv_mid]: the middle column's bars
 };
 
@@ -89,10 +91,17 @@ __device__ inline int64_t fr_blk(int side, int64_t H, int64_t i, int w) {
   return ((int64_t)side * H + i) * w * w;
 }
 
+// Factor blocks: row i of a side holds Dinv, gam, del as wp x wp blocks
+// (column-major, ld wp, zero past w), so the solve reads them without bounds.
+__device__ inline int64_t fr_fac(int side, int64_t H, int64_t i, int wp) {
+  return ((int64_t)side * H + i) * 3 * wp * wp;
+}
+
 // Eliminated rows of level l (odd p; p = 0 at the root): Dinv, gam, del.
+// Also the row's edge entries (see the solve), zero-padded to wp.
 __global__ __launch_bounds__(256) void k_fr_elim(const double* Dw, const double* Cw, double* fac,
-                                                 int64_t H, int w, int64_t s, int64_t n, int root,
-                                                 int32_t* bad) {
+                                                 double* edge, int64_t H, int w, int wp,
+                                                 int64_t s, int64_t n, int root, int32_t* bad) {
   constexpr int LD = FR_WMAX + 1;
   __shared__ double A[FR_WMAX * LD];
   __shared__ double Cm[FR_WMAX * LD];   // C_{q-1}
@@ -129,9 +138,15 @@ __global__ __launch_bounds__(256) void k_fr_elim(const double* Dw, const double*
     }
     __syncthreads();
   }
-  double* F = fac + 3 * fr_blk(side, H, i, w);
-  for (int e = tid; e < per; e += 256) {
-    const int r = e % w, c = e / w;
+  double* F = fac + fr_fac(side, H, i, wp);
+  double* E = edge + (2 * wp + 2) * ((int64_t)side * H + i);
+  const int pp = wp * wp;
+  for (int e = tid; e < pp; e += 256) {
+    const int r = e % wp, c = e / wp;
+    if (r >= w || c >= w) {
+      F[e] = F[pp + e] = F[2 * pp + e] = 0.0;
+      continue;
+    }
     double g = 0.0, d = 0.0;
     for (int k = 0; k < w; ++k) {
       const double a = A[r + k * LD];
@@ -139,15 +154,28 @@ __global__ __launch_bounds__(256) void k_fr_elim(const double* Dw, const double*
       d = fma(a, Cp[k + c * LD], d);   // Dinv C_q
     }
     F[e] = A[r + c * LD];
-    F[per + e] = g;
-    F[2 * per + e] = d;
+    F[pp + e] = g;
+    F[2 * pp + e] = d;
+    if (r == w - 1) {
+      E[c] = g;
+      E[wp + c] = d;
+    }
+  }
+  for (int j = w + tid; j < wp; j += 256) {
+    E[j] = 0.0;
+    E[wp + j] = 0.0;
+  }
+  if (tid == 0) {
+    E[2 * wp] = A[(w - 1) + (w - 1) * LD];
+    E[2 * wp + 1] = 0.0;
   }
   if (fail && tid == 0) atomicOr(bad, 1);
 }
 
 // Kept rows of level l (even p): the reduced D_p and C_p.
 __global__ __launch_bounds__(256) void k_fr_reduce(double* Dw, double* Cw, const double* fac,
-                                                   int64_t H, int w, int64_t s, int64_t n) {
+                                                   int64_t H, int w, int wp, int64_t s,
+                                                   int64_t n) {
   constexpr int LD = FR_WMAX + 1;
   __shared__ double Cm[FR_WMAX * LD];   // C_{p-1}
   __shared__ double Dm[FR_WMAX * LD];   // del_{p-1}
@@ -163,10 +191,11 @@ __global__ __launch_bounds__(256) void k_fr_reduce(double* Dw, double* Cw, const
   for (int e = tid; e < per; e += 256) {
     const int r = e % w, k = e / w;
     Cm[r + k * LD] = has_prev ? Cw[fr_blk(side, H, i - s, w) + e] : 0.0;
-    Dm[r + k * LD] = has_prev ? fac[3 * fr_blk(side, H, i - s, w) + 2 * per + e] : 0.0;
+    const int f = r + k * wp, pp = wp * wp;
+    Dm[r + k * LD] = has_prev ? fac[fr_fac(side, H, i - s, wp) + 2 * pp + f] : 0.0;
     Cs[r + k * LD] = Cw[fr_blk(side, H, i, w) + e];
-    Gp[r + k * LD] = has_next ? fac[3 * fr_blk(side, H, i + s, w) + per + e] : 0.0;
-    Dp[r + k * LD] = has_next ? fac[3 * fr_blk(side, H, i + s, w) + 2 * per + e] : 0.0;
+    Gp[r + k * LD] = has_next ? fac[fr_fac(side, H, i + s, wp) + pp + f] : 0.0;
+    Dp[r + k * LD] = has_next ? fac[fr_fac(side, H, i + s, wp) + 2 * pp + f] : 0.0;
   }
   __syncthreads();
   double* D = Dw + fr_blk(side, H, i, w);
@@ -185,146 +214,236 @@ __global__ __launch_bounds__(256) void k_fr_reduce(double* Dw, double* Cw, const
 }
 
 // ---- solve ----------------------------------------------------------------------
-// Right-hand sides Z[side][row][column][j] (w per column, contiguous per row).
-__device__ inline int64_t fr_rhs(int side, int64_t H, int64_t i, int m, int w) {
-  return (((int64_t)side * H + i) * m) * w;
+// Right-hand sides Z[side][row][column][j]: WP entries per column (w rounded
+// up to a multiple of 4, the entries past w zero), contiguous per row, so a
+// column is whole 16-byte vectors.  The level-0 kernels read the last rows of
+// gam and del and the last diagonal entry of Dinv from the edge array:
+// edge[side][row] = [gam(w-1, :) | del(w-1, :) | Dinv(w-1, w-1), 0], each row
+// zero-padded to WP.
+__device__ inline int64_t fr_rhs(int side, int64_t H, int64_t i, int m, int wp) {
+  return (((int64_t)side * H + i) * m) * wp;
 }
 
-// Level-0 reduction: the level-1 right-hand side of every even row p from the
-// sparse level-0 one (b_i = g_i e_{w-1}, g_i = c_link(i) x_i):
-//   b_p = g_p e_{w-1} - g_{p-1} del_{p-1}^T e_{w-1} - g_{p+1} gam_{p+1}^T e_{w-1}.
-__global__ __launch_bounds__(256) void k_fr_fwd0(const double* X, int64_t ldx, int m,
-                                                 const double* fac, const double* bars,
-                                                 double* Z, int64_t H, int w) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t neven = (H + 1) / 2;
-  const int64_t per_row = (int64_t)m * w;
-  if (e >= 2 * neven * per_row) return;
-  const int side = (int)(e / (neven * per_row));
-  const int64_t p = 2 * ((e / per_row) % neven);
-  const int c = (int)((e % per_row) / w), j = (int)(e % w);
-  const int per = w * w;
-  auto g = [&](int64_t i) { return bars[3 * i + side] * X[i + (int64_t)c * ldx]; };
-  double b = j == w - 1 ? g(p) : 0.0;
-  if (p >= 1) b = fma(-fac[3 * fr_blk(side, H, p - 1, w) + 2 * per + (w - 1) + j * w], g(p - 1), b);
-  if (p + 1 < H) b = fma(-fac[3 * fr_blk(side, H, p + 1, w) + per + (w - 1) + j * w], g(p + 1), b);
-  Z[fr_rhs(side, H, p, m, w) + (int64_t)c * w + j] = b;
+template <int WP>
+__device__ inline void fr_load(double (&v)[WP], const double* src) {
+#pragma unroll
+  for (int j = 0; j < WP; j += 2) {
+    const double2 t = *reinterpret_cast<const double2*>(src + j);
+    v[j] = t.x;
+    v[j + 1] = t.y;
+  }
 }
 
-// One level l >= 1 of the solve on a column chunk of one row (blockIdx.x: the
-// row's index among the rows the step writes, blockIdx.y: the chunk,
-// blockIdx.z: the side).  mode 0 reduction (even p): b_p -= del_{p-1}^T
-// b_{p-1} + gam_{p+1}^T b_{p+1}; mode 1 back substitution (odd p):
-// x_p = Dinv_p b_p - gam_p x_{p-1} - del_p x_{p+1}; mode 2 root: x_0 = Dinv_0 b_0.
-// Thread (rg, cg) holds rows 4rg..4rg+3 and columns 2cg, 2cg+1 of the chunk;
-// operands staged in LDS (matrices transposed for the reduction so that both
-// modes read M(r, k) at k LDM + r), the result written back through LDS so
-// the stores are contiguous.
+template <int WP>
+__device__ inline void fr_store(double* dst, const double (&v)[WP]) {
+#pragma unroll
+  for (int j = 0; j < WP; j += 2) *reinterpret_cast<double2*>(dst + j) = make_double2(v[j], v[j + 1]);
+}
+
+// Level-1 right-hand side of the even row j, built from the sparse level-0
+// one (b_i = g_i e_{w-1}, g_i = c_link(i) x_i):
+//   b1_j = g_j e_{w-1} - g_{j-1} del_{j-1}^T e_{w-1} - g_{j+1} gam_{j+1}^T e_{w-1}
+// for the column c of this lane, from x transposed (XT[j m + c] = x_j(c), so
+// that the lanes' reads are contiguous).  It is never stored: the level-1
+// steps rebuild it from x.
+template <int WP>
+__device__ inline void fr_b1(double (&b)[WP], const double* XT, int m, int c,
+                             const double* edge, const double* bars, int side, int64_t H,
+                             int64_t j, int w) {
+  constexpr int EW = 2 * WP + 2;
+  const double gj = bars[3 * j + side] * XT[j * m + c];
+#pragma unroll
+  for (int r = 0; r < WP; ++r) b[r] = r == w - 1 ? gj : 0.0;
+  double d[WP];
+  if (j >= 1) {
+    const double g = bars[3 * (j - 1) + side] * XT[(j - 1) * m + c];
+    fr_load<WP>(d, edge + EW * ((int64_t)side * H + j - 1) + WP);
+#pragma unroll
+    for (int r = 0; r < WP; ++r) b[r] = fma(-d[r], g, b[r]);
+  }
+  if (j + 1 < H) {
+    const double g = bars[3 * (j + 1) + side] * XT[(j + 1) * m + c];
+    fr_load<WP>(d, edge + EW * ((int64_t)side * H + j + 1));
+#pragma unroll
+    for (int r = 0; r < WP; ++r) b[r] = fma(-d[r], g, b[r]);
+  }
+}
+
+// What the level-0 back substitution needs of the solution x_e of an even
+// row e (per column): P_e = (x_e(w-1), del_{e-1}(w-1, :) x_e,
+// gam_{e+1}(w-1, :) x_e, 0) -- the row's own entry next to the middle and its
+// terms in the odd rows e-1 and e+1.  P[side][column][e / 2][4].
+template <int WP>
+__device__ inline void fr_put_p(double* P, const double (&x)[WP], const double* edge, int side,
+                                int64_t H, int64_t e, int m, int c, int w) {
+  constexpr int EW = 2 * WP + 2;
+  double p0 = 0.0, p1 = 0.0, p2 = 0.0;
+#pragma unroll
+  for (int r = 0; r < WP; ++r)
+    if (r == w - 1) p0 = x[r];
+  double d[WP];
+  if (e >= 1) {
+    fr_load<WP>(d, edge + EW * ((int64_t)side * H + e - 1) + WP);
+#pragma unroll
+    for (int r = 0; r < WP; ++r) p1 = fma(d[r], x[r], p1);
+  }
+  if (e + 1 < H) {
+    fr_load<WP>(d, edge + EW * ((int64_t)side * H + e + 1));
+#pragma unroll
+    for (int r = 0; r < WP; ++r) p2 = fma(d[r], x[r], p2);
+  }
+  const int64_t Hh = (H + 1) / 2;
+  double* dst = P + (((int64_t)side * m + c) * Hh + e / 2) * 4;
+  *reinterpret_cast<double2*>(dst) = make_double2(p0, p1);
+  *reinterpret_cast<double2*>(dst + 2) = make_double2(p2, 0.0);
+}
+
+// One level l >= 1 of the solve for one row and 64 columns (one column per
+// lane; blockIdx.y: the group of columns, blockIdx.z: the side).  mode 0
+// reduction (even p): b_p -= del_{p-1}^T b_{p-1} + gam_{p+1}^T b_{p+1};
+// mode 1 back substitution (odd p): x_p = Dinv_p b_p - gam_p x_{p-1} -
+// del_p x_{p+1}; mode 2 root: x_0 = Dinv_0 b_0.  LVL1 (level 1): the
+// right-hand sides b are rebuilt from x (fr_b1), and a back substitution or
+// root writes only P (no finer level reads its x); otherwise b comes from Z
+// and a back substitution or root writes x to Z and P.  The row's matrices
+// are staged in LDS (read there as broadcasts); each lane holds its columns
+// of the three right-hand sides in registers.  Rows are taken in an
+// XCD-aware order: workgroups dispatched to one XCD (every 8th) handle a
+// contiguous run of rows, so the neighbours two rows share meet in that
+// XCD's L2.
 struct FrStep {
   int64_t H, s, n;
-  int w, m, cw;        // cw: chunk width (columns per workgroup, even)
+  int w, m;
   int mode;
+  const double* XT;
+  const double* edge;
+  const double* bars;
+  double* P;
 };
 
-__global__ __launch_bounds__(256) void k_fr_step(const double* fac, double* Z, FrStep a) {
-  extern __shared__ double lds[];
-  const int w = a.w, RG = (w + 3) / 4, LDM = 4 * RG, LDV = a.cw + 2;
-  double* sM = lds;                    // 3 matrices, LDM x w each (k LDM + r)
-  double* sV = lds + 3 * LDM * w;      // 3 chunks, w x LDV each (k LDV + c)
+template <int WP, bool LVL1>
+__global__ __launch_bounds__(64) void k_fr_step(const double* __restrict__ fac,
+                                                double* __restrict__ Z, FrStep a) {
+  constexpr int PP = WP * WP;
+  __shared__ double sM[3 * PP];   // M_t(r, k) at t PP + r + k WP (the factor's own layout)
   const int side = blockIdx.z;
-  const int tid = threadIdx.x;
-  const int64_t p = a.mode == 2 ? 0 : 2 * (int64_t)blockIdx.x + (a.mode == 1 ? 1 : 0);
+  const int lane = threadIdx.x;
+  const int64_t T = gridDim.x;
+  int64_t x = blockIdx.x;
+  if ((T & 7) == 0) x = (x & 7) * (T >> 3) + (x >> 3);
+  const int64_t p = a.mode == 2 ? 0 : 2 * x + (a.mode == 1 ? 1 : 0);
   const int64_t i = p * a.s;
-  const int c0 = blockIdx.y * a.cw;
-  const int cw = min(a.cw, a.m - c0);
-  const int per = w * w;
+  const int w = a.w;
   const bool has_prev = a.mode != 2 && p >= 1, has_next = a.mode != 2 && p + 1 < a.n;
-  // operands: t = 0 the row itself, 1 its previous, 2 its next active row
-  const int64_t rows[3] = {i, i - a.s, i + a.s};
-  const bool live[3] = {true, has_prev, has_next};
-  const double* Fs = fac + 3 * fr_blk(side, a.H, 0, w);
-  // matrices: reduction: -, del_{p-1}^T, gam_{p+1}^T; back substitution:
-  // Dinv_p, gam_p, del_p (all of row p)
-  for (int e = tid; e < 3 * per; e += 256) {
-    const int t = e / per, rk = e % per, r = rk % w, k = rk / w;
-    double v = 0.0;
-    if (a.mode == 0) {
-      if (t == 1 && has_prev) v = Fs[3 * (i - a.s) * per + 2 * per + k + r * w];
-      if (t == 2 && has_next) v = Fs[3 * (i + a.s) * per + per + k + r * w];
-    } else if (t == 0 || (t == 1 && has_prev) || (t == 2 && has_next)) {
-      v = Fs[3 * i * per + t * per + rk];
-    }
-    sM[t * LDM * w + k * LDM + r] = v;
+  // matrices: reduction: -, del_{p-1}, gam_{p+1}; back substitution:
+  // Dinv_p, gam_p, del_p (contiguous).  16-byte loads, all issued before
+  // the LDS stores.
+  const double* src[3];
+  if (a.mode == 0) {
+    src[0] = nullptr;
+    src[1] = has_prev ? fac + fr_fac(side, a.H, i - a.s, WP) + 2 * PP : nullptr;
+    src[2] = has_next ? fac + fr_fac(side, a.H, i + a.s, WP) + PP : nullptr;
+  } else {
+    src[0] = fac + fr_fac(side, a.H, i, WP);
+    src[1] = has_prev ? src[0] + PP : nullptr;
+    src[2] = has_next ? src[0] + 2 * PP : nullptr;
   }
-  for (int t = 0; t < 3; ++t) {
-    if (!live[t]) continue;
-    const double* src = Z + fr_rhs(side, a.H, rows[t], a.m, w) + (int64_t)c0 * w;
-    for (int e = tid; e < cw * w; e += 256) {
-      const int c = e / w, k = e % w;
-      sV[t * w * LDV + k * LDV + c] = src[e];
-    }
+  constexpr int NM = (3 * PP / 2 + 63) / 64;
+  double2 mv[NM];
+#pragma unroll
+  for (int it = 0; it < NM; ++it) {
+    const int e = 2 * (lane + 64 * it), t = e / PP;
+    mv[it] = (t < 3 && src[t]) ? *reinterpret_cast<const double2*>(src[t] + (e - t * PP))
+                               : make_double2(0.0, 0.0);
   }
-  __syncthreads();
-  const int rg = tid % RG, cg = tid / RG;
-  const bool act = cg * 2 < cw;
-  double acc[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+#pragma unroll
+  for (int it = 0; it < NM; ++it) {
+    const int e = 2 * (lane + 64 * it);
+    if (e < 3 * PP) *reinterpret_cast<double2*>(sM + e) = mv[it];
+  }
+  const int c = blockIdx.y * 64 + lane;
+  const bool act = c < a.m;
+  double v0[WP], v1[WP], v2[WP];
+#pragma unroll
+  for (int j = 0; j < WP; ++j) v0[j] = v1[j] = v2[j] = 0.0;
+  auto rhs = [&](int64_t row) { return Z + fr_rhs(side, a.H, row, a.m, WP) + (int64_t)c * WP; };
   if (act) {
-    for (int t = 0; t < 3; ++t) {
-      if (!live[t]) continue;
-      const double sign = t == 0 ? 1.0 : -1.0;
-      const double* M = sM + t * LDM * w + 4 * rg;
-      const double* V = sV + t * w * LDV + 2 * cg;
-      if (t == 0 && a.mode == 0) {
-        for (int u = 0; u < 4; ++u)
-          if (4 * rg + u < w) {
-            acc[u][0] = V[(4 * rg + u) * LDV];
-            acc[u][1] = V[(4 * rg + u) * LDV + 1];
-          }
-        continue;
+    if (LVL1) {
+      fr_b1<WP>(v0, a.XT, a.m, c, a.edge, a.bars, side, a.H, i, w);
+      // neighbours: level-1 right-hand sides (reduction) or solutions
+      if (a.mode == 0) {
+        if (has_prev) fr_b1<WP>(v1, a.XT, a.m, c, a.edge, a.bars, side, a.H, i - a.s, w);
+        if (has_next) fr_b1<WP>(v2, a.XT, a.m, c, a.edge, a.bars, side, a.H, i + a.s, w);
+      } else {
+        if (has_prev) fr_load<WP>(v1, rhs(i - a.s));
+        if (has_next) fr_load<WP>(v2, rhs(i + a.s));
       }
-      for (int k = 0; k < w; ++k) {
-        const double2 v = *reinterpret_cast<const double2*>(V + k * LDV);
-        const double2 m01 = *reinterpret_cast<const double2*>(M + k * LDM);
-        const double2 m23 = *reinterpret_cast<const double2*>(M + k * LDM + 2);
-        const double mm[4] = {sign * m01.x, sign * m01.y, sign * m23.x, sign * m23.y};
-        for (int u = 0; u < 4; ++u) {
-          acc[u][0] = fma(mm[u], v.x, acc[u][0]);
-          acc[u][1] = fma(mm[u], v.y, acc[u][1]);
-        }
-      }
+    } else {
+      fr_load<WP>(v0, rhs(i));
+      if (has_prev) fr_load<WP>(v1, rhs(i - a.s));
+      if (has_next) fr_load<WP>(v2, rhs(i + a.s));
     }
   }
   __syncthreads();
-  // result through the first chunk's LDS, then contiguous stores
-  if (act)
-    for (int u = 0; u < 4; ++u)
-      if (4 * rg + u < w) {
-        sV[(4 * rg + u) * LDV + 2 * cg] = acc[u][0];
-        sV[(4 * rg + u) * LDV + 2 * cg + 1] = acc[u][1];
+  if (!act) return;
+  double acc[WP];
+  if (a.mode == 0) {
+    // acc(r) = v0(r) - sum_k del(k, r) v1(k) - sum_k gam(k, r) v2(k)
+#pragma unroll
+    for (int r = 0; r < WP; ++r) {
+      double t = v0[r];
+#pragma unroll
+      for (int k = 0; k < WP; k += 2) {
+        const double2 m1 = *reinterpret_cast<const double2*>(sM + PP + k + r * WP);
+        const double2 m2 = *reinterpret_cast<const double2*>(sM + 2 * PP + k + r * WP);
+        t = fma(-m1.x, v1[k], t);
+        t = fma(-m1.y, v1[k + 1], t);
+        t = fma(-m2.x, v2[k], t);
+        t = fma(-m2.y, v2[k + 1], t);
       }
-  __syncthreads();
-  double* dst = Z + fr_rhs(side, a.H, i, a.m, w) + (int64_t)c0 * w;
-  for (int e = tid; e < cw * w; e += 256) {
-    const int c = e / w, k = e % w;
-    dst[e] = sV[k * LDV + c];
+      acc[r] = t;
+    }
+    fr_store<WP>(rhs(i), acc);
+    return;
   }
+  // acc(r) = sum_k Dinv(r, k) v0(k) - gam(r, k) v1(k) - del(r, k) v2(k)
+#pragma unroll
+  for (int r = 0; r < WP; ++r) acc[r] = 0.0;
+#pragma unroll
+  for (int k = 0; k < WP; ++k) {
+#pragma unroll
+    for (int r = 0; r < WP; r += 2) {
+      const double2 m0 = *reinterpret_cast<const double2*>(sM + r + k * WP);
+      const double2 m1 = *reinterpret_cast<const double2*>(sM + PP + r + k * WP);
+      const double2 m2 = *reinterpret_cast<const double2*>(sM + 2 * PP + r + k * WP);
+      acc[r] = fma(m0.x, v0[k], acc[r]);
+      acc[r + 1] = fma(m0.y, v0[k], acc[r + 1]);
+      acc[r] = fma(-m1.x, v1[k], acc[r]);
+      acc[r + 1] = fma(-m1.y, v1[k], acc[r + 1]);
+      acc[r] = fma(-m2.x, v2[k], acc[r]);
+      acc[r + 1] = fma(-m2.y, v2[k], acc[r + 1]);
+    }
+  }
+  if (!LVL1) fr_store<WP>(rhs(i), acc);
+  fr_put_p<WP>(a.P, acc, a.edge, side, a.H, i, a.m, c, w);
 }
 
 // Level-0 back substitution of the column next to the middle, fused with the
 // output: per grid row i and column c,
 //   x_i(w-1) = Dinv_i(w-1, w-1) g_i - gam_i(w-1, :) x_{i-1} - del_i(w-1, :) x_{i+1}
-// for rows eliminated at level 0 (odd i, or the only row), x_i(w-1) from the
-// solve otherwise, and
+// for rows eliminated at level 0 (odd i, or the only row; the two products
+// come from P of the even neighbours), x_i(w-1) from P otherwise, and
 //   (A x)_i = (B33 x)_i - cL_i x^L_i(w-1) - cR_i x^R_i(w-1).
+template <int WP>
 __global__ __launch_bounds__(256) void k_fr_out(const double* X, int64_t ldx, double* Y,
-                                                int64_t ldy, int m, const double* fac,
-                                                const double* bars, const double* Z, int64_t H,
-                                                int w) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= H * m) return;
-  const int64_t i = e / m;
-  const int c = (int)(e % m);
-  const int per = w * w;
+                                                int64_t ldy, int m, const double* edge,
+                                                const double* bars, const double* P, int64_t H) {
+  constexpr int EW = 2 * WP + 2;
+  // one thread per row and column, rows fastest (contiguous x, y and P)
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= H) return;
+  const int64_t Hh = (H + 1) / 2;
   const double xi = X[i + (int64_t)c * ldx];
   const double cL = bars[3 * i], cR = bars[3 * i + 1];
   const double up = i >= 1 ? bars[3 * (i - 1) + 2] : 0.0, dn = bars[3 * i + 2];
@@ -334,20 +453,14 @@ __global__ __launch_bounds__(256) void k_fr_out(const double* X, int64_t ldx, do
   const bool elim0 = (i & 1) || H == 1;
   for (int side = 0; side < 2; ++side) {
     const double cl = side == 0 ? cL : cR;
+    const double* Ps = P + ((int64_t)side * m + c) * Hh * 4;
     double xs;
     if (elim0) {
-      const double* F = fac + 3 * fr_blk(side, H, i, w);
-      xs = F[(w - 1) + (w - 1) * w] * (cl * xi);
-      if (i >= 1) {
-        const double* zp = Z + fr_rhs(side, H, i - 1, m, w) + (int64_t)c * w;
-        for (int j = 0; j < w; ++j) xs = fma(-F[per + (w - 1) + j * w], zp[j], xs);
-      }
-      if (i + 1 < H) {
-        const double* zn = Z + fr_rhs(side, H, i + 1, m, w) + (int64_t)c * w;
-        for (int j = 0; j < w; ++j) xs = fma(-F[2 * per + (w - 1) + j * w], zn[j], xs);
-      }
+      xs = edge[EW * ((int64_t)side * H + i) + 2 * WP] * (cl * xi);
+      if (i >= 1) xs -= Ps[((i - 1) / 2) * 4 + 2];
+      if (i + 1 < H) xs -= Ps[((i + 1) / 2) * 4 + 1];
     } else {
-      xs = Z[fr_rhs(side, H, i, m, w) + (int64_t)c * w + (w - 1)];
+      xs = Ps[(i / 2) * 4];
     }
     y = fma(-cl, xs, y);
   }
@@ -356,66 +469,102 @@ __global__ __launch_bounds__(256) void k_fr_out(const double* X, int64_t ldx, do
 
 static unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
-static size_t fr_step_lds(int w, int cw) {
-  const int RG = (w + 3) / 4;
-  return (size_t)(3 * 4 * RG * w + 3 * w * (cw + 2)) * sizeof(double);
-}
-
-// Chunk width of k_fr_step: two columns per thread over 256 / RG threads,
-// fewer if the operands would pass 64 KB of LDS.
-static int fr_chunk(int w) {
-  int cw = 2 * (256 / ((w + 3) / 4));
-  while (cw > 2 && fr_step_lds(w, cw) > 65536) cw -= 2;
-  return cw;
-}
-
 // Columns per pass of the apply (bounds the right-hand-side workspace).
 constexpr int FR_COLS = 128;
 
-void frontal_apply(const hm_frontal_s* f, int64_t ncols, const double* X, int64_t ldx, double* Y,
-                   int64_t ldy, void* work, hipStream_t s) {
+static size_t fr_z_bytes(const hm_frontal_s* f, int m) {
+  return ((size_t)(2 * f->H * m * f->wp) * sizeof(double) + 255) / 256 * 256;
+}
+
+static size_t fr_p_bytes(const hm_frontal_s* f, int m) {
+  return ((size_t)(2 * ((f->H + 1) / 2) * m * 4) * sizeof(double) + 255) / 256 * 256;
+}
+
+// XT[j m + c] = X(j, c): 64 x 64 tiles through LDS, both sides contiguous.
+__global__ __launch_bounds__(256) void k_fr_transpose(const double* X, int64_t ldx, int64_t H,
+                                                      int m, double* XT) {
+  __shared__ double t[64][65];
+  const int64_t j0 = (int64_t)blockIdx.x * 64;
+  const int c0 = blockIdx.y * 64;
+  const int tx = threadIdx.x % 64, ty = threadIdx.x / 64;
+  for (int cc = ty; cc < 64; cc += 4)
+    if (c0 + cc < m && j0 + tx < H) t[cc][tx] = X[j0 + tx + (int64_t)(c0 + cc) * ldx];
+  __syncthreads();
+  for (int jj = ty; jj < 64; jj += 4)
+    if (j0 + jj < H && c0 + tx < m) XT[(j0 + jj) * m + c0 + tx] = t[tx][jj];
+}
+
+template <int WP>
+static void frontal_apply_wp(const hm_frontal_s* f, int64_t ncols, const double* X, int64_t ldx,
+                             double* Y, int64_t ldy, void* work, hipStream_t s) {
   const int64_t H = f->H;
   const int w = f->w;
   const double* fac = f->fac.as<double>();
+  const double* edge = f->edge.as<double>();
   const double* bars = f->bars.as<double>();
-  double* Z = static_cast<double*>(work);
-  const int cwmax = fr_chunk(w);
-  const size_t lds = fr_step_lds(w, cwmax);
   for (int64_t c0 = 0; c0 < ncols; c0 += FR_COLS) {
     const int m = (int)std::min<int64_t>(FR_COLS, ncols - c0);
+    double* Z = static_cast<double*>(work);
+    double* P = reinterpret_cast<double*>(static_cast<char*>(work) + fr_z_bytes(f, m));
+    double* XT =
+        reinterpret_cast<double*>(static_cast<char*>(work) + fr_z_bytes(f, m) + fr_p_bytes(f, m));
     const double* Xc = X + c0 * ldx;
     double* Yc = Y + c0 * ldy;
     if (f->levels >= 1) {
-      const int64_t neven = (H + 1) / 2;
-      hipLaunchKernelGGL(k_fr_fwd0, dim3(nblk(2 * neven * m * w)), dim3(256), 0, s, Xc, ldx, m,
-                         fac, bars, Z, H, w);
+      hipLaunchKernelGGL(k_fr_transpose, dim3((unsigned)((H + 63) / 64), (m + 63) / 64),
+                         dim3(256), 0, s, Xc, ldx, H, m, XT);
       KCHK();
-      const int cw = std::min(cwmax, m + (m & 1));
-      const unsigned chunks = (unsigned)((m + cw - 1) / cw);
-      auto step = [&](int mode, int64_t stride, int64_t n, int64_t rows) {
+      const unsigned groups = (unsigned)((m + 63) / 64);
+      auto step = [&](bool lvl1, int mode, int64_t stride, int64_t n, int64_t rows) {
         if (rows <= 0) return;
-        FrStep a{H, stride, n, w, m, cw, mode};
-        hipLaunchKernelGGL(k_fr_step, dim3((unsigned)rows, chunks, 2), dim3(256), lds, s, fac, Z,
-                           a);
+        FrStep a{H, stride, n, w, m, mode, XT, edge, bars, P};
+        if (lvl1)
+          hipLaunchKernelGGL((k_fr_step<WP, true>), dim3((unsigned)rows, groups, 2), dim3(64), 0,
+                             s, fac, Z, a);
+        else
+          hipLaunchKernelGGL((k_fr_step<WP, false>), dim3((unsigned)rows, groups, 2), dim3(64),
+                             0, s, fac, Z, a);
         KCHK();
       };
       // n_l: active rows of level l
-      std::vector<int64_t> nl(f->levels + 1);
+      const int L = f->levels;
+      std::vector<int64_t> nl(L + 1);
       nl[0] = H;
-      for (int l = 1; l <= f->levels; ++l) nl[l] = (nl[l - 1] + 1) / 2;
-      for (int l = 1; l < f->levels; ++l) step(0, (int64_t)1 << l, nl[l], (nl[l] + 1) / 2);
-      step(2, (int64_t)1 << f->levels, 1, 1);
-      for (int l = f->levels - 1; l >= 1; --l) step(1, (int64_t)1 << l, nl[l], nl[l] / 2);
+      for (int l = 1; l <= L; ++l) nl[l] = (nl[l - 1] + 1) / 2;
+      if (L == 1) {
+        step(true, 2, 2, 1, 1);
+      } else {
+        step(true, 0, 2, nl[1], (nl[1] + 1) / 2);
+        for (int l = 2; l < L; ++l) step(false, 0, (int64_t)1 << l, nl[l], (nl[l] + 1) / 2);
+        step(false, 2, (int64_t)1 << L, 1, 1);
+        for (int l = L - 1; l >= 2; --l) step(false, 1, (int64_t)1 << l, nl[l], nl[l] / 2);
+        step(true, 1, 2, nl[1], nl[1] / 2);
+      }
     }
-    hipLaunchKernelGGL(k_fr_out, dim3(nblk(H * m)), dim3(256), 0, s, Xc, ldx, Yc, ldy, m, fac,
-                       bars, Z, H, w);
+    hipLaunchKernelGGL(k_fr_out<WP>, dim3(nblk(H), m), dim3(256), 0, s, Xc, ldx, Yc, ldy, m,
+                       edge, bars, P, H);
     KCHK();
   }
 }
 
+void frontal_apply(const hm_frontal_s* f, int64_t ncols, const double* X, int64_t ldx, double* Y,
+                   int64_t ldy, void* work, hipStream_t s) {
+  switch (f->wp) {
+    case 4: frontal_apply_wp<4>(f, ncols, X, ldx, Y, ldy, work, s); break;
+    case 8: frontal_apply_wp<8>(f, ncols, X, ldx, Y, ldy, work, s); break;
+    case 12: frontal_apply_wp<12>(f, ncols, X, ldx, Y, ldy, work, s); break;
+    case 16: frontal_apply_wp<16>(f, ncols, X, ldx, Y, ldy, work, s); break;
+    case 20: frontal_apply_wp<20>(f, ncols, X, ldx, Y, ldy, work, s); break;
+    case 24: frontal_apply_wp<24>(f, ncols, X, ldx, Y, ldy, work, s); break;
+    case 28: frontal_apply_wp<28>(f, ncols, X, ldx, Y, ldy, work, s); break;
+    case 32: frontal_apply_wp<32>(f, ncols, X, ldx, Y, ldy, work, s); break;
+    default: HM_THROW(HM_ERR_ARG, "frontal: padded side width %d", f->wp);
+  }
+}
+
 size_t frontal_work_bytes(const hm_frontal_s* f, int64_t ncols) {
-  const int64_t m = std::min<int64_t>(FR_COLS, std::max<int64_t>(ncols, 1));
-  return (size_t)(2 * f->H * m * f->w) * sizeof(double);
+  const int m = (int)std::min<int64_t>(FR_COLS, std::max<int64_t>(ncols, 1));
+  return fr_z_bytes(f, m) + fr_p_bytes(f, m) + (size_t)(f->H * m) * sizeof(double);
 }
 
 int64_t frontal_n(const hm_frontal_s* f) { return f->H; }
@@ -447,12 +596,14 @@ int hm_frontal_create(int64_t height, int32_t width, const double* ch, const dou
     F->H = H;
     F->W = width;
     F->w = w;
+    F->wp = (w + 3) / 4 * 4;
     int L = 0;
     for (int64_t n = H; n > 1; n = (n + 1) / 2) ++L;
     F->levels = L;
     const int64_t per = (int64_t)w * w;
-    F->fac = DevBuf((size_t)(2 * H * 3 * per) * sizeof(double));
+    F->fac = DevBuf((size_t)(2 * H * 3 * F->wp * F->wp) * sizeof(double));
     F->bars = DevBuf((size_t)(3 * H) * sizeof(double));
+    F->edge = DevBuf((size_t)(2 * H * (2 * F->wp + 2)) * sizeof(double));
     DevBuf Dw((size_t)(2 * H * per) * sizeof(double)), Cw((size_t)(2 * H * per) * sizeof(double));
     DevBuf bad(256);
     HIPCHK(hipMemsetAsync(bad.p, 0, 16, s));
@@ -464,17 +615,18 @@ int hm_frontal_create(int64_t height, int32_t width, const double* ch, const dou
     for (int l = 0; l < L; ++l) {
       const int64_t st = (int64_t)1 << l;
       hipLaunchKernelGGL(k_fr_elim, dim3((unsigned)(n / 2), 1, 2), dim3(256), 0, s,
-                         Dw.as<double>(), Cw.as<double>(), F->fac.as<double>(), H, w, st, n, 0,
-                         bad.as<int32_t>());
+                         Dw.as<double>(), Cw.as<double>(), F->fac.as<double>(),
+                         F->edge.as<double>(), H, w, F->wp, st, n, 0, bad.as<int32_t>());
       KCHK();
       hipLaunchKernelGGL(k_fr_reduce, dim3((unsigned)((n + 1) / 2), 1, 2), dim3(256), 0, s,
-                         Dw.as<double>(), Cw.as<double>(), F->fac.as<double>(), H, w, st, n);
+                         Dw.as<double>(), Cw.as<double>(), F->fac.as<double>(), H, w, F->wp, st,
+                         n);
       KCHK();
       n = (n + 1) / 2;
     }
     hipLaunchKernelGGL(k_fr_elim, dim3(1, 1, 2), dim3(256), 0, s, Dw.as<double>(),
-                       Cw.as<double>(), F->fac.as<double>(), H, w, (int64_t)1 << L, 1, 1,
-                       bad.as<int32_t>());
+                       Cw.as<double>(), F->fac.as<double>(), F->edge.as<double>(), H, w, F->wp,
+                       (int64_t)1 << L, 1, 1, bad.as<int32_t>());
     KCHK();
     int hb[4] = {0, 0, 0, 0};
     HIPCHK(hipMemcpyAsync(hb, bad.p, 16, hipMemcpyDeviceToHost, s));
