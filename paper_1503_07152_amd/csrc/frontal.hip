@@ -298,19 +298,24 @@ __device__ inline void fr_put_p(double* P, const double (&x)[WP], const double* 
   *reinterpret_cast<double2*>(dst + 2) = make_double2(p2, 0.0);
 }
 
-// One level l >= 1 of the solve for one row and 64 columns (one column per
-// lane; blockIdx.y: the group of columns, blockIdx.z: the side).  mode 0
-// reduction (even p): b_p -= del_{p-1}^T b_{p-1} + gam_{p+1}^T b_{p+1};
-// mode 1 back substitution (odd p): x_p = Dinv_p b_p - gam_p x_{p-1} -
-// del_p x_{p+1}; mode 2 root: x_0 = Dinv_0 b_0.  LVL1 (level 1): the
-// right-hand sides b are rebuilt from x (fr_b1), and a back substitution or
-// root writes only P (no finer level reads its x); otherwise b comes from Z
-// and a back substitution or root writes x to Z and P.  The row's matrices
-// are staged in LDS (read there as broadcasts); each lane holds its columns
-// of the three right-hand sides in registers.  Rows are taken in an
-// XCD-aware order: workgroups dispatched to one XCD (every 8th) handle a
-// contiguous run of rows, so the neighbours two rows share meet in that
-// XCD's L2.
+// One level l >= 1 of the solve for one row and 64 columns (blockIdx.y: the
+// group of columns, blockIdx.z: the side).  mode 0 reduction (even p):
+// b_p -= del_{p-1}^T b_{p-1} + gam_{p+1}^T b_{p+1}; mode 1 back substitution
+// (odd p): x_p = Dinv_p b_p - gam_p x_{p-1} - del_p x_{p+1}; mode 2 root:
+// x_0 = Dinv_0 b_0.  LVL1 (level 1): the right-hand sides b are rebuilt from
+// x (fr_b1's formula), and a back substitution or root writes only P (no
+// finer level reads its x); otherwise b comes from Z and a back substitution
+// or root writes x to Z and P.
+//
+// Two waves of 64 lanes; lane (g, q) = (lane / 16, lane % 16) of wave v
+// holds output rows g RB .. g RB + RB - 1 (RB = WP / 4) of the two columns
+// c0 + 32 v + q + 16 u (u = 0, 1), and each right-hand side's two columns
+// whole in registers.  The row's matrices are staged in LDS as L_t(r, k),
+// row r contiguous (transposed from the factor where the product needs it),
+// so every 16-byte LDS read feeds four FMAs: two entries, two columns.  Rows
+// are taken in an XCD-aware order: workgroups dispatched to one XCD (every
+// 8th) handle a contiguous run of rows, so the neighbours two rows share meet
+// in that XCD's L2.
 struct FrStep {
   int64_t H, s, n;
   int w, m;
@@ -322,12 +327,15 @@ struct FrStep {
 };
 
 template <int WP, bool LVL1>
-__global__ __launch_bounds__(64) void k_fr_step(const double* __restrict__ fac,
-                                                double* __restrict__ Z, FrStep a) {
-  constexpr int PP = WP * WP;
-  __shared__ double sM[3 * PP];   // M_t(r, k) at t PP + r + k WP (the factor's own layout)
+__global__ __launch_bounds__(128) void
+k_fr_step(const double* __restrict__ fac, double* __restrict__ Z, FrStep a) {
+  constexpr int PP = WP * WP, RB = WP / 4, EW = 2 * WP + 2;
+  __shared__ __attribute__((aligned(16))) double sL[3 * PP];   // L_t(r, k) at t PP + r WP + k
+  __shared__ __attribute__((aligned(16))) double sE[3 * 2 * WP];  // level 1: edge rows
+  __shared__ double sP[3][4][64];                                  // P partial sums per group
   const int side = blockIdx.z;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int g = lane >> 4, q = lane & 15;
   const int64_t T = gridDim.x;
   int64_t x = blockIdx.x;
   if ((T & 7) == 0) x = (x & 7) * (T >> 3) + (x >> 3);
@@ -335,9 +343,9 @@ __global__ __launch_bounds__(64) void k_fr_step(const double* __restrict__ fac,
   const int64_t i = p * a.s;
   const int w = a.w;
   const bool has_prev = a.mode != 2 && p >= 1, has_next = a.mode != 2 && p + 1 < a.n;
-  // matrices: reduction: -, del_{p-1}, gam_{p+1}; back substitution:
-  // Dinv_p, gam_p, del_p (contiguous).  16-byte loads, all issued before
-  // the LDS stores.
+  // ---- matrices: reduction: -, del_{p-1}, gam_{p+1}, L_t(r, k) = M_t(k, r)
+  // (a straight copy of the column-major blocks); back substitution / root:
+  // Dinv_p, gam_p, del_p, L_t(r, k) = M_t(r, k) (transposed while staged)
   const double* src[3];
   if (a.mode == 0) {
     src[0] = nullptr;
@@ -348,84 +356,186 @@ __global__ __launch_bounds__(64) void k_fr_step(const double* __restrict__ fac,
     src[1] = has_prev ? src[0] + PP : nullptr;
     src[2] = has_next ? src[0] + 2 * PP : nullptr;
   }
-  constexpr int NM = (3 * PP / 2 + 63) / 64;
+  constexpr int NM = (3 * PP / 2 + 127) / 128;
   double2 mv[NM];
 #pragma unroll
   for (int it = 0; it < NM; ++it) {
-    const int e = 2 * (lane + 64 * it), t = e / PP;
+    const int e = 2 * (tid + 128 * it), t = e / PP;
     mv[it] = (t < 3 && src[t]) ? *reinterpret_cast<const double2*>(src[t] + (e - t * PP))
                                : make_double2(0.0, 0.0);
   }
+  if (LVL1) {
+    // edge rows of the right-hand sides rebuilt here: slot 0 row i, slots 1, 2
+    // rows i -+ s (reduction only): [del_{j-1}(w-1, :) | gam_{j+1}(w-1, :)]
+    for (int e = tid; e < 3 * 2 * WP; e += 128) {
+      const int slot = e / (2 * WP), h = (e / WP) & 1, k = e % WP;
+      const int64_t j = slot == 0 ? i : (slot == 1 ? i - a.s : i + a.s);
+      const bool live = slot == 0 || (a.mode == 0 && (slot == 1 ? has_prev : has_next));
+      const int64_t nb = h == 0 ? j - 1 : j + 1;
+      sE[e] = (live && nb >= 0 && nb < a.H)
+                  ? a.edge[EW * ((int64_t)side * a.H + nb) + (h == 0 ? WP : 0) + k]
+                  : 0.0;
+    }
+  }
 #pragma unroll
   for (int it = 0; it < NM; ++it) {
-    const int e = 2 * (lane + 64 * it);
-    if (e < 3 * PP) *reinterpret_cast<double2*>(sM + e) = mv[it];
-  }
-  const int c = blockIdx.y * 64 + lane;
-  const bool act = c < a.m;
-  double v0[WP], v1[WP], v2[WP];
-#pragma unroll
-  for (int j = 0; j < WP; ++j) v0[j] = v1[j] = v2[j] = 0.0;
-  auto rhs = [&](int64_t row) { return Z + fr_rhs(side, a.H, row, a.m, WP) + (int64_t)c * WP; };
-  if (act) {
-    if (LVL1) {
-      fr_b1<WP>(v0, a.XT, a.m, c, a.edge, a.bars, side, a.H, i, w);
-      // neighbours: level-1 right-hand sides (reduction) or solutions
-      if (a.mode == 0) {
-        if (has_prev) fr_b1<WP>(v1, a.XT, a.m, c, a.edge, a.bars, side, a.H, i - a.s, w);
-        if (has_next) fr_b1<WP>(v2, a.XT, a.m, c, a.edge, a.bars, side, a.H, i + a.s, w);
-      } else {
-        if (has_prev) fr_load<WP>(v1, rhs(i - a.s));
-        if (has_next) fr_load<WP>(v2, rhs(i + a.s));
-      }
+    const int e = 2 * (tid + 128 * it), t = e / PP;
+    if (t >= 3) continue;
+    const int rk = e - t * PP;
+    if (a.mode == 0) {
+      *reinterpret_cast<double2*>(sL + e) = mv[it];
     } else {
-      fr_load<WP>(v0, rhs(i));
-      if (has_prev) fr_load<WP>(v1, rhs(i - a.s));
-      if (has_next) fr_load<WP>(v2, rhs(i + a.s));
+      const int r = rk % WP, k = rk / WP;   // storage (r, k), (r + 1, k)
+      sL[t * PP + r * WP + k] = mv[it].x;
+      sL[t * PP + (r + 1) * WP + k] = mv[it].y;
     }
   }
   __syncthreads();
-  if (!act) return;
-  double acc[WP];
-  if (a.mode == 0) {
-    // acc(r) = v0(r) - sum_k del(k, r) v1(k) - sum_k gam(k, r) v2(k)
+  int col[2];
+  bool cok[2];
 #pragma unroll
-    for (int r = 0; r < WP; ++r) {
-      double t = v0[r];
+  for (int u = 0; u < 2; ++u) {
+    col[u] = blockIdx.y * 64 + wv * 32 + q + 16 * u;
+    cok[u] = col[u] < a.m;
+  }
+  auto rhs = [&](int64_t row, int c) {
+    return Z + fr_rhs(side, a.H, row, a.m, WP) + (int64_t)c * WP;
+  };
+  // g-values of the level-1 right-hand side of row j (see fr_b1): b1_j(k, c) =
+  // [k = w-1] gj(c) - gm(c) del_{j-1}(w-1, k) - gp(c) gam_{j+1}(w-1, k)
+  struct G3 { double j[2], m[2], p[2]; };
+  auto gvals = [&](int64_t j) {
+    G3 r;
 #pragma unroll
-      for (int k = 0; k < WP; k += 2) {
-        const double2 m1 = *reinterpret_cast<const double2*>(sM + PP + k + r * WP);
-        const double2 m2 = *reinterpret_cast<const double2*>(sM + 2 * PP + k + r * WP);
-        t = fma(-m1.x, v1[k], t);
-        t = fma(-m1.y, v1[k + 1], t);
-        t = fma(-m2.x, v2[k], t);
-        t = fma(-m2.y, v2[k + 1], t);
+    for (int u = 0; u < 2; ++u) {
+      const int c = cok[u] ? col[u] : 0;
+      r.j[u] = cok[u] ? a.bars[3 * j + side] * a.XT[j * a.m + c] : 0.0;
+      r.m[u] = (cok[u] && j >= 1) ? a.bars[3 * (j - 1) + side] * a.XT[(j - 1) * a.m + c] : 0.0;
+      r.p[u] = (cok[u] && j + 1 < a.H) ? a.bars[3 * (j + 1) + side] * a.XT[(j + 1) * a.m + c]
+                                        : 0.0;
+    }
+    return r;
+  };
+  auto b1 = [&](const G3& gg, int slot, int k, int u) {
+    const double* E = sE + slot * 2 * WP;
+    const double t = k == w - 1 ? gg.j[u] : 0.0;
+    return fma(-gg.p[u], E[WP + k], fma(-gg.m[u], E[k], t));
+  };
+  // acc(rr, u) += sign sum_k L_t(g RB + rr, k) v(k, u), the right-hand side
+  // streamed in chunks of four k (loaded from Z, or rebuilt for level 1)
+  double acc[RB][2];
+  auto product = [&](int t, bool rebuilt, const G3& gg, int slot, int64_t row, double sign) {
+    constexpr int NC = WP / 4;
+    const double* L = sL + t * PP + g * RB * WP;
+    const double* sp0 = rhs(row, cok[0] ? col[0] : 0);
+    const double* sp1 = rhs(row, cok[1] ? col[1] : 0);
+    // every load of the right-hand side first (all in flight together) ...
+    double v[NC][4][2];
+#pragma unroll
+    for (int kc = 0; kc < NC; ++kc) {
+      if (rebuilt) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int u = 0; u < 2; ++u) v[kc][e][u] = b1(gg, slot, 4 * kc + e, u);
+      } else {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const double2 t0 = cok[0] ? *reinterpret_cast<const double2*>(sp0 + 4 * kc + 2 * h)
+                                    : make_double2(0.0, 0.0);
+          const double2 t1 = cok[1] ? *reinterpret_cast<const double2*>(sp1 + 4 * kc + 2 * h)
+                                    : make_double2(0.0, 0.0);
+          v[kc][2 * h][0] = t0.x;
+          v[kc][2 * h + 1][0] = t0.y;
+          v[kc][2 * h][1] = t1.x;
+          v[kc][2 * h + 1][1] = t1.y;
+        }
       }
-      acc[r] = t;
     }
-    fr_store<WP>(rhs(i), acc);
-    return;
+    // ... then the products chunk by chunk, the LDS reads of a chunk held
+    // back to it (the compiler barrier keeps them from all being hoisted
+    // into registers at once)
+#pragma unroll
+    for (int kc = 0; kc < NC; ++kc) {
+      asm volatile("" ::: "memory");
+#pragma unroll
+      for (int rr = 0; rr < RB; ++rr) {
+        const double2 m01 = *reinterpret_cast<const double2*>(L + rr * WP + 4 * kc);
+        const double2 m23 = *reinterpret_cast<const double2*>(L + rr * WP + 4 * kc + 2);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          double d = m01.x * v[kc][0][u];
+          d = fma(m01.y, v[kc][1][u], d);
+          d = fma(m23.x, v[kc][2][u], d);
+          d = fma(m23.y, v[kc][3][u], d);
+          acc[rr][u] = fma(sign, d, acc[rr][u]);
+        }
+      }
+    }
+    asm volatile("" ::: "memory");
+  };
+  const G3 g0 = LVL1 ? gvals(i) : G3{};
+  if (a.mode == 0) {
+    // acc = b_p on the lane's rows
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const double* sp = rhs(i, cok[u] ? col[u] : 0) + g * RB;
+#pragma unroll
+      for (int rr = 0; rr < RB; ++rr)
+        acc[rr][u] = LVL1 ? b1(g0, 0, g * RB + rr, u) : (cok[u] ? sp[rr] : 0.0);
+    }
+    if (has_prev) product(1, LVL1, LVL1 ? gvals(i - a.s) : G3{}, 1, i - a.s, -1.0);
+    if (has_next) product(2, LVL1, LVL1 ? gvals(i + a.s) : G3{}, 2, i + a.s, -1.0);
+  } else {
+#pragma unroll
+    for (int rr = 0; rr < RB; ++rr) acc[rr][0] = acc[rr][1] = 0.0;
+    product(0, LVL1, g0, 0, i, 1.0);
+    if (has_prev) product(1, false, g0, 0, i - a.s, -1.0);
+    if (has_next) product(2, false, g0, 0, i + a.s, -1.0);
   }
-  // acc(r) = sum_k Dinv(r, k) v0(k) - gam(r, k) v1(k) - del(r, k) v2(k)
+  // results: x (or the reduced b) of the lane's rows to Z
+  if (a.mode == 0 || !LVL1) {
 #pragma unroll
-  for (int r = 0; r < WP; ++r) acc[r] = 0.0;
+    for (int u = 0; u < 2; ++u) {
+      if (!cok[u]) continue;
+      double* dp = rhs(i, col[u]) + g * RB;
 #pragma unroll
-  for (int k = 0; k < WP; ++k) {
-#pragma unroll
-    for (int r = 0; r < WP; r += 2) {
-      const double2 m0 = *reinterpret_cast<const double2*>(sM + r + k * WP);
-      const double2 m1 = *reinterpret_cast<const double2*>(sM + PP + r + k * WP);
-      const double2 m2 = *reinterpret_cast<const double2*>(sM + 2 * PP + r + k * WP);
-      acc[r] = fma(m0.x, v0[k], acc[r]);
-      acc[r + 1] = fma(m0.y, v0[k], acc[r + 1]);
-      acc[r] = fma(-m1.x, v1[k], acc[r]);
-      acc[r + 1] = fma(-m1.y, v1[k], acc[r + 1]);
-      acc[r] = fma(-m2.x, v2[k], acc[r]);
-      acc[r + 1] = fma(-m2.y, v2[k], acc[r + 1]);
+      for (int rr = 0; rr < RB; ++rr) dp[rr] = acc[rr][u];
     }
   }
-  if (!LVL1) fr_store<WP>(rhs(i), acc);
-  fr_put_p<WP>(a.P, acc, a.edge, side, a.H, i, a.m, c, w);
+  if (a.mode == 0) return;
+  // P of row i: x(w-1), del_{i-1}(w-1, :) x, gam_{i+1}(w-1, :) x, summed over
+  // the four row groups through LDS
+  const double* Ed = i >= 1 ? a.edge + EW * ((int64_t)side * a.H + i - 1) + WP : nullptr;
+  const double* Eg = i + 1 < a.H ? a.edge + EW * ((int64_t)side * a.H + i + 1) : nullptr;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    double p0 = 0.0, p1 = 0.0, p2 = 0.0;
+#pragma unroll
+    for (int rr = 0; rr < RB; ++rr) {
+      const int r = g * RB + rr;
+      if (r == w - 1) p0 = acc[rr][u];
+      if (Ed) p1 = fma(Ed[r], acc[rr][u], p1);
+      if (Eg) p2 = fma(Eg[r], acc[rr][u], p2);
+    }
+    const int cl = wv * 32 + q + 16 * u;   // column within the workgroup
+    sP[0][g][cl] = p0;
+    sP[1][g][cl] = p1;
+    sP[2][g][cl] = p2;
+  }
+  __syncthreads();
+  if (tid < 64) {
+    const int c = blockIdx.y * 64 + tid;
+    if (c < a.m) {
+      double pv[3];
+#pragma unroll
+      for (int h = 0; h < 3; ++h) pv[h] = sP[h][0][tid] + sP[h][1][tid] + sP[h][2][tid] + sP[h][3][tid];
+      const int64_t Hh = (a.H + 1) / 2;
+      double* dst = a.P + (((int64_t)side * a.m + c) * Hh + i / 2) * 4;
+      *reinterpret_cast<double2*>(dst) = make_double2(pv[0], pv[1]);
+      *reinterpret_cast<double2*>(dst + 2) = make_double2(pv[2], 0.0);
+    }
+  }
 }
 
 // Level-0 back substitution of the column next to the middle, fused with the
@@ -519,10 +629,10 @@ static void frontal_apply_wp(const hm_frontal_s* f, int64_t ncols, const double*
         if (rows <= 0) return;
         FrStep a{H, stride, n, w, m, mode, XT, edge, bars, P};
         if (lvl1)
-          hipLaunchKernelGGL((k_fr_step<WP, true>), dim3((unsigned)rows, groups, 2), dim3(64), 0,
+          hipLaunchKernelGGL((k_fr_step<WP, true>), dim3((unsigned)rows, groups, 2), dim3(128), 0,
                              s, fac, Z, a);
         else
-          hipLaunchKernelGGL((k_fr_step<WP, false>), dim3((unsigned)rows, groups, 2), dim3(64),
+          hipLaunchKernelGGL((k_fr_step<WP, false>), dim3((unsigned)rows, groups, 2), dim3(128),
                              0, s, fac, Z, a);
         KCHK();
       };
