@@ -441,28 +441,31 @@ def solver_measurement(hm, W, torch, h, n):
 def frontal_apply_bytes(H, w, m):
     """Algorithmic bytes of one apply of the frontal black box (Sec. 5.4) to m
     columns: block cyclic reduction over H grid rows on each side, every array
-    a kernel touches counted once per kernel.  x and y once each, x's
-    transposed copy written and read once; per side, the level-1 reduction
-    reads del and gam of the rows it eliminates (w x w FP64 each) and writes
-    the level-2 right-hand sides; each coarser level reads its active rows'
-    right-hand sides (wp entries per column, wp = w rounded up to 4) and two
-    matrices per kept row, writes the kept rows; the root and each back
-    substitution read their rows' Dinv, gam, del and right-hand sides and the
-    neighbours' solutions, write x and the 4-entry projection P the output
-    needs (level 1: P only); the output kernel reads P and x, writes y."""
+    a kernel touches counted once per kernel.  x read twice (transposed copy,
+    output) and its transposed copy written and read once, y written once.
+    Per side: the level-1 reduction reads its rows' level-1 operators (7 wp
+    FP64 each, wp = w rounded up to 4) and writes the level-2 right-hand
+    sides (wp entries per column); each coarser level reads its active rows'
+    right-hand sides once and two w x w matrices per kept row, writes the
+    kept rows; the root and each back substitution of level >= 2 read their
+    rows' Dinv, gam, del and right-hand sides and the neighbours' solutions
+    once, write x and the 4-entry projection P; the level-1 back substitution
+    reads its operators (6 wp + 9) and the level-2 rows' solutions, writes P;
+    the output kernel reads P, writes y."""
     wp = (w + 3) // 4 * 4
     R, Mb, Pb = 8 * wp * m, 8 * w * w, 32 * m
     nl = [H]
     while nl[-1] > 1:
         nl.append((nl[-1] + 1) // 2)
     L = len(nl) - 1
-    total = 3 * 8 * H * m + 8 * H * m          # x, XT written and read; y
+    total = 2 * 8 * H * m + 2 * 8 * H * m + 8 * H * m     # x twice, XT, y
     side = 0
     if L == 1:
-        side += Mb + Pb
+        side += 8 * (6 * wp + 9) + Pb
     elif L >= 2:
         n1 = nl[1]
-        side += 2 * Mb * ((n1 + 1) // 2) + R * ((n1 + 1) // 2)
+        kept1, odd1 = (n1 + 1) // 2, n1 // 2
+        side += kept1 * (8 * 7 * wp + R)
         for l in range(2, L):
             kept = (nl[l] + 1) // 2
             side += nl[l] * R + 2 * Mb * kept + kept * R
@@ -470,7 +473,7 @@ def frontal_apply_bytes(H, w, m):
         for l in range(2, L):
             odd = nl[l] // 2
             side += nl[l] * R + 3 * Mb * odd + odd * (R + Pb)
-        side += ((n1 + 1) // 2) * R + 3 * Mb * (n1 // 2) + (n1 // 2) * Pb
+        side += kept1 * R + odd1 * (8 * (6 * wp + 9) + Pb)
     total += 2 * side + 2 * ((H + 1) // 2) * Pb   # both sides; P read by the output
     return float(total)
 

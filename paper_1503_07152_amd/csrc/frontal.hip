@@ -25,10 +25,14 @@
 // del_q x_{q+1}, level by level.
 //
 // The products with A solve only for right-hand sides on the column next to
-// the middle (B13 x) and read only that column of the solution, so level 0 is
-// taken apart: its reduction builds the level-1 right-hand side straight from
-// x (a rank-one update per row) and its back substitution computes only that
-// column, fused with B33 x and the sum that forms A x.
+// the middle (B13 x) and read only that column of the solution, so levels 0
+// and 1 are taken apart: the level-0 right-hand sides are never formed (each
+// is g_i e_{w-1}, g_i = c_link(i) x_i), the level-1 steps use small operators
+// built once with the factor (the level-2 right-hand side of a row is a
+// combination of seven g's, and a level-1 back substitution only needs the
+// three projections of its solution that level 0 reads), and level 0's back
+// substitution computes only the column next to the middle, fused with B33 x
+// and the sum that forms A x.
 #include <algorithm>
 
 #include "handle.h"
@@ -40,6 +44,8 @@ struct hm_frontal_s {
   int levels = 0;        // reduction levels: n_levels == 1
   hm::DevBuf fac;        // [side][row][Dinv | gam | del], w x w column-major each
   hm::DevBuf edge;       // [side][row][gam(w-1, :) | del(w-1, :) | Dinv(w-1, w-1), 0]
+  hm::DevBuf ops;        // level-1 operators: [side][level-1 position][recw]
+  int recw = 0;
   hm::DevBuf bars;       // [row][cL, cR, cv_mid]: the middle column's bars
 };
 
@@ -213,6 +219,130 @@ __global__ __launch_bounds__(256) void k_fr_reduce(double* Dw, double* Cw, const
   }
 }
 
+// Level-1 operators, built once after the factorisation.  The level-1
+// right-hand sides are sparse combinations of x: b1_j = g_j e - g_{j-1} Ed_{j-1}
+// - g_{j+1} Eg_{j+1} (g_j = c_link(j) x_j, e = e_{w-1}, Ed_j = del_j(w-1, :)^T,
+// Eg_j = gam_j(w-1, :)^T of the rows eliminated at level 0), so both level-1
+// steps collapse to small fixed operators per row:
+//  * reduction at row i (level-1 position p = i / 2 even):
+//      b2_i = sum_{d=0..6} g_{i+d-3} W_d,  W_3 = e,
+//      W_2 = -Ed_{i-1} + del_{i-2}^T Eg_{i-1},  W_1 = -del_{i-2}^T e,
+//      W_0 = del_{i-2}^T Ed_{i-3},  W_4 = -Eg_{i+1} + gam_{i+2}^T Ed_{i+1},
+//      W_5 = -gam_{i+2}^T e,  W_6 = gam_{i+2}^T Eg_{i+3}  (absent rows: 0);
+//  * back substitution at row i (p odd, or p = 0 when level 1 is the root):
+//    the output needs only P_i = Q_i x_i (rows e^T, Ed_{i-1}^T, Eg_{i+1}^T),
+//      P_i = sum_{d=0..2} S_d g_{i+d-1} - A x_{i-2} - B x_{i+2},
+//      A = Q_i gam_i, B = Q_i del_i, S_d = Q_i Dinv_i c_d,
+//      c = (-Ed_{i-1}, e, -Eg_{i+1}).
+// Record of (side, p): W_0..W_6 (wp each), or A, B (3 x wp each, row-major)
+// and S (3 x 3, S[q][d]).
+__global__ __launch_bounds__(256) void k_fr_lvl1_ops(const double* fac, const double* edge,
+                                                     double* ops, int64_t H, int w, int wp,
+                                                     int recw) {
+  constexpr int WM = FR_WMAX;
+  __shared__ double M0[WM * WM], M1[WM * WM], M2[WM * WM];   // ld wp
+  __shared__ double E[6][WM];
+  __shared__ double Yd[3][WM];
+  const int side = blockIdx.z, tid = threadIdx.x;
+  const int64_t p = blockIdx.x, i = 2 * p;
+  const int pp = wp * wp, EW = 2 * wp + 2;
+  const int64_t n1 = (H + 1) / 2;
+  auto ed = [&](int64_t j) -> const double* {
+    return (j >= 0 && j < H) ? edge + EW * ((int64_t)side * H + j) + wp : nullptr;
+  };
+  auto eg = [&](int64_t j) -> const double* {
+    return (j >= 0 && j < H) ? edge + EW * ((int64_t)side * H + j) : nullptr;
+  };
+  double* R = ops + ((int64_t)side * n1 + p) * recw;
+  if (!(p & 1) && n1 > 1) {
+    const bool prv = p >= 1, nxt = i + 2 < H;
+    for (int e = tid; e < pp; e += 256) {
+      M1[e] = prv ? fac[fr_fac(side, H, i - 2, wp) + 2 * pp + e] : 0.0;   // del_{i-2}
+      M2[e] = nxt ? fac[fr_fac(side, H, i + 2, wp) + pp + e] : 0.0;       // gam_{i+2}
+    }
+    for (int e = tid; e < 6 * wp; e += 256) {
+      const int slot = e / wp, k = e % wp;
+      const double* src = slot == 0 ? ed(i - 3) : slot == 1 ? ed(i - 1) : slot == 2 ? eg(i - 1)
+                        : slot == 3 ? ed(i + 1) : slot == 4 ? eg(i + 1) : eg(i + 3);
+      E[slot][k] = src ? src[k] : 0.0;
+    }
+    __syncthreads();
+    for (int r = tid; r < wp; r += 256) {
+      double w0 = 0.0, w1 = 0.0, w2 = 0.0, w4 = 0.0, w5 = 0.0, w6 = 0.0;
+      if (r < w) {
+        for (int k = 0; k < w; ++k) {
+          w0 = fma(M1[k + r * wp], E[0][k], w0);
+          w2 = fma(M1[k + r * wp], E[2][k], w2);
+          w4 = fma(M2[k + r * wp], E[3][k], w4);
+          w6 = fma(M2[k + r * wp], E[5][k], w6);
+        }
+        w1 = -M1[(w - 1) + r * wp];
+        w5 = -M2[(w - 1) + r * wp];
+        w2 -= E[1][r];
+        w4 -= E[4][r];
+      }
+      R[0 * wp + r] = w0;
+      R[1 * wp + r] = w1;
+      R[2 * wp + r] = w2;
+      R[3 * wp + r] = r == w - 1 ? 1.0 : 0.0;
+      R[4 * wp + r] = w4;
+      R[5 * wp + r] = w5;
+      R[6 * wp + r] = w6;
+    }
+    return;
+  }
+  // back substitution (or the root): Dinv_i, gam_i, del_i of row i
+  for (int e = tid; e < pp; e += 256) {
+    const int64_t b = fr_fac(side, H, i, wp);
+    M0[e] = fac[b + e];
+    M1[e] = fac[b + pp + e];
+    M2[e] = fac[b + 2 * pp + e];
+  }
+  for (int e = tid; e < 2 * wp; e += 256) {
+    const int slot = e / wp, k = e % wp;
+    const double* src = slot == 0 ? ed(i - 1) : eg(i + 1);
+    E[slot][k] = src ? src[k] : 0.0;
+  }
+  __syncthreads();
+  // Yd_d = Dinv_i c_d
+  for (int r = tid; r < w; r += 256) {
+    double y0 = 0.0, y2 = 0.0;
+    for (int k = 0; k < w; ++k) {
+      y0 = fma(-M0[r + k * wp], E[0][k], y0);
+      y2 = fma(-M0[r + k * wp], E[1][k], y2);
+    }
+    Yd[0][r] = y0;
+    Yd[1][r] = M0[r + (w - 1) * wp];
+    Yd[2][r] = y2;
+  }
+  __syncthreads();
+  for (int k = tid; k < wp; k += 256) {
+    double a1 = 0.0, a2 = 0.0, b1 = 0.0, b2 = 0.0;
+    for (int r = 0; r < w; ++r) {
+      a1 = fma(E[0][r], M1[r + k * wp], a1);
+      a2 = fma(E[1][r], M1[r + k * wp], a2);
+      b1 = fma(E[0][r], M2[r + k * wp], b1);
+      b2 = fma(E[1][r], M2[r + k * wp], b2);
+    }
+    R[0 * wp + k] = M1[(w - 1) + k * wp];
+    R[1 * wp + k] = a1;
+    R[2 * wp + k] = a2;
+    R[3 * wp + k] = M2[(w - 1) + k * wp];
+    R[4 * wp + k] = b1;
+    R[5 * wp + k] = b2;
+  }
+  if (tid < 9) {
+    const int q = tid / 3, d = tid % 3;
+    double sv = 0.0;
+    if (q == 0) {
+      sv = Yd[d][w - 1];
+    } else {
+      for (int r = 0; r < w; ++r) sv = fma(E[q - 1][r], Yd[d][r], sv);
+    }
+    R[6 * wp + tid] = sv;
+  }
+}
+
 // ---- solve ----------------------------------------------------------------------
 // Right-hand sides Z[side][row][column][j]: WP entries per column (w rounded
 // up to a multiple of 4, the entries past w zero), contiguous per row, so a
@@ -240,98 +370,136 @@ __device__ inline void fr_store(double* dst, const double (&v)[WP]) {
   for (int j = 0; j < WP; j += 2) *reinterpret_cast<double2*>(dst + j) = make_double2(v[j], v[j + 1]);
 }
 
-// Level-1 right-hand side of the even row j, built from the sparse level-0
-// one (b_i = g_i e_{w-1}, g_i = c_link(i) x_i):
-//   b1_j = g_j e_{w-1} - g_{j-1} del_{j-1}^T e_{w-1} - g_{j+1} gam_{j+1}^T e_{w-1}
-// for the column c of this lane, from x transposed (XT[j m + c] = x_j(c), so
-// that the lanes' reads are contiguous).  It is never stored: the level-1
-// steps rebuild it from x.
+// Level-1 reduction from the level-1 operators (k_fr_lvl1_ops): the level-2
+// right-hand side of row i = 4 x, b2_i = sum_d g_{i+d-3} W_d, one column per
+// lane (x transposed: XT[j m + c] = x_j(c), contiguous over the lanes), W in
+// LDS read as broadcasts; 64 columns per workgroup.
 template <int WP>
-__device__ inline void fr_b1(double (&b)[WP], const double* XT, int m, int c,
-                             const double* edge, const double* bars, int side, int64_t H,
-                             int64_t j, int w) {
-  constexpr int EW = 2 * WP + 2;
-  const double gj = bars[3 * j + side] * XT[j * m + c];
+__global__ __launch_bounds__(64) void k_fr_l1fwd(const double* __restrict__ ops, int recw,
+                                                 double* __restrict__ Z, const double* XT,
+                                                 const double* bars, int64_t H, int m) {
+  __shared__ __attribute__((aligned(16))) double sW[7 * WP];
+  __shared__ __attribute__((aligned(16))) double sB[64 * WP];   // the result, for contiguous stores
+  const int side = blockIdx.z, lane = threadIdx.x;
+  const int64_t T = gridDim.x;
+  int64_t x = blockIdx.x;
+  if ((T & 7) == 0) x = (x & 7) * (T >> 3) + (x >> 3);
+  const int64_t p = 2 * x, i = 2 * p;
+  const int64_t n1 = (H + 1) / 2;
+  const double* R = ops + ((int64_t)side * n1 + p) * recw;
+  for (int e = lane; e < 7 * WP; e += 64) sW[e] = R[e];
+  const int c = blockIdx.y * 64 + lane;
+  double gv[7];
 #pragma unroll
-  for (int r = 0; r < WP; ++r) b[r] = r == w - 1 ? gj : 0.0;
-  double d[WP];
-  if (j >= 1) {
-    const double g = bars[3 * (j - 1) + side] * XT[(j - 1) * m + c];
-    fr_load<WP>(d, edge + EW * ((int64_t)side * H + j - 1) + WP);
-#pragma unroll
-    for (int r = 0; r < WP; ++r) b[r] = fma(-d[r], g, b[r]);
+  for (int d = 0; d < 7; ++d) {
+    const int64_t j = i + d - 3;
+    gv[d] = (c < m && j >= 0 && j < H) ? bars[3 * j + side] * XT[j * m + c] : 0.0;
   }
-  if (j + 1 < H) {
-    const double g = bars[3 * (j + 1) + side] * XT[(j + 1) * m + c];
-    fr_load<WP>(d, edge + EW * ((int64_t)side * H + j + 1));
+  __syncthreads();
 #pragma unroll
-    for (int r = 0; r < WP; ++r) b[r] = fma(-d[r], g, b[r]);
+  for (int r = 0; r < WP; r += 2) {
+    double b0 = 0.0, b1 = 0.0;
+#pragma unroll
+    for (int d = 0; d < 7; ++d) {
+      const double2 wv = *reinterpret_cast<const double2*>(sW + d * WP + r);
+      b0 = fma(wv.x, gv[d], b0);
+      b1 = fma(wv.y, gv[d], b1);
+    }
+    *reinterpret_cast<double2*>(sB + lane * WP + r) = make_double2(b0, b1);
   }
+  __syncthreads();
+  // the group's columns are contiguous in Z: 16-byte stores, consecutive over the lanes
+  const int c0 = blockIdx.y * 64;
+  const int nv = (min(64, m - c0) * WP) / 2;
+  double2* dst = reinterpret_cast<double2*>(Z + fr_rhs(side, H, i, m, WP) + (int64_t)c0 * WP);
+  for (int e = lane; e < nv; e += 64) dst[e] = reinterpret_cast<const double2*>(sB)[e];
 }
 
-// What the level-0 back substitution needs of the solution x_e of an even
-// row e (per column): P_e = (x_e(w-1), del_{e-1}(w-1, :) x_e,
-// gam_{e+1}(w-1, :) x_e, 0) -- the row's own entry next to the middle and its
-// terms in the odd rows e-1 and e+1.  P[side][column][e / 2][4].
+// Level-1 back substitution from the level-1 operators: P_i = sum_d S_d
+// g_{i+d-1} - A x_{i-2} - B x_{i+2} for row i = 2 p (p odd; p = 0 when level 1
+// is the root), one column per lane.
 template <int WP>
-__device__ inline void fr_put_p(double* P, const double (&x)[WP], const double* edge, int side,
-                                int64_t H, int64_t e, int m, int c, int w) {
-  constexpr int EW = 2 * WP + 2;
-  double p0 = 0.0, p1 = 0.0, p2 = 0.0;
+__global__ __launch_bounds__(64) void k_fr_l1bwd(const double* __restrict__ ops, int recw,
+                                                 const double* __restrict__ Z, double* P,
+                                                 const double* XT, const double* bars, int64_t H,
+                                                 int m, int root) {
+  __shared__ __attribute__((aligned(16))) double sA[6 * WP + 9];
+  const int side = blockIdx.z, lane = threadIdx.x;
+  const int64_t T = gridDim.x;
+  int64_t x = blockIdx.x;
+  if ((T & 7) == 0) x = (x & 7) * (T >> 3) + (x >> 3);
+  const int64_t p = root ? 0 : 2 * x + 1, i = 2 * p;
+  const int64_t n1 = (H + 1) / 2;
+  const double* R = ops + ((int64_t)side * n1 + p) * recw;
+  for (int e = lane; e < 6 * WP + 9; e += 64) sA[e] = R[e];
+  const int c = blockIdx.y * 64 + lane;
+  const bool act = c < m;
+  const bool prv = !root, nxt = !root && i + 2 < H;
+  double gv[3];
 #pragma unroll
-  for (int r = 0; r < WP; ++r)
-    if (r == w - 1) p0 = x[r];
-  double d[WP];
-  if (e >= 1) {
-    fr_load<WP>(d, edge + EW * ((int64_t)side * H + e - 1) + WP);
-#pragma unroll
-    for (int r = 0; r < WP; ++r) p1 = fma(d[r], x[r], p1);
+  for (int d = 0; d < 3; ++d) {
+    const int64_t j = i + d - 1;
+    gv[d] = (act && j >= 0 && j < H) ? bars[3 * j + side] * XT[j * m + c] : 0.0;
   }
-  if (e + 1 < H) {
-    fr_load<WP>(d, edge + EW * ((int64_t)side * H + e + 1));
+  double xm[WP], xp[WP];
 #pragma unroll
-    for (int r = 0; r < WP; ++r) p2 = fma(d[r], x[r], p2);
+  for (int k = 0; k < WP; ++k) xm[k] = xp[k] = 0.0;
+  if (act && prv) fr_load<WP>(xm, Z + fr_rhs(side, H, i - 2, m, WP) + (int64_t)c * WP);
+  if (act && nxt) fr_load<WP>(xp, Z + fr_rhs(side, H, i + 2, m, WP) + (int64_t)c * WP);
+  __syncthreads();
+  if (!act) return;
+  double pv[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    double t = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) t = fma(sA[6 * WP + 3 * q + d], gv[d], t);
+#pragma unroll
+    for (int k = 0; k < WP; k += 2) {
+      const double2 a2 = *reinterpret_cast<const double2*>(sA + q * WP + k);
+      const double2 b2 = *reinterpret_cast<const double2*>(sA + 3 * WP + q * WP + k);
+      t = fma(-a2.x, xm[k], t);
+      t = fma(-a2.y, xm[k + 1], t);
+      t = fma(-b2.x, xp[k], t);
+      t = fma(-b2.y, xp[k + 1], t);
+    }
+    pv[q] = t;
   }
-  const int64_t Hh = (H + 1) / 2;
-  double* dst = P + (((int64_t)side * m + c) * Hh + e / 2) * 4;
-  *reinterpret_cast<double2*>(dst) = make_double2(p0, p1);
-  *reinterpret_cast<double2*>(dst + 2) = make_double2(p2, 0.0);
+  double* dst = P + (((int64_t)side * m + c) * ((H + 1) / 2) + i / 2) * 4;
+  *reinterpret_cast<double2*>(dst) = make_double2(pv[0], pv[1]);
+  *reinterpret_cast<double2*>(dst + 2) = make_double2(pv[2], 0.0);
 }
 
-// One level l >= 1 of the solve for one row and 64 columns (blockIdx.y: the
+// One level l >= 2 of the solve for one row and 64 columns (blockIdx.y: the
 // group of columns, blockIdx.z: the side).  mode 0 reduction (even p):
 // b_p -= del_{p-1}^T b_{p-1} + gam_{p+1}^T b_{p+1}; mode 1 back substitution
 // (odd p): x_p = Dinv_p b_p - gam_p x_{p-1} - del_p x_{p+1}; mode 2 root:
-// x_0 = Dinv_0 b_0.  LVL1 (level 1): the right-hand sides b are rebuilt from
-// x (fr_b1's formula), and a back substitution or root writes only P (no
-// finer level reads its x); otherwise b comes from Z and a back substitution
-// or root writes x to Z and P.
+// x_0 = Dinv_0 b_0.  A back substitution or root writes x to Z and the
+// 4-entry projection P_i = (x_i(w-1), Ed_{i-1}^T x_i, Eg_{i+1}^T x_i, 0) the
+// output kernel reads.
 //
 // Two waves of 64 lanes; lane (g, q) = (lane / 16, lane % 16) of wave v
 // holds output rows g RB .. g RB + RB - 1 (RB = WP / 4) of the two columns
-// c0 + 32 v + q + 16 u (u = 0, 1), and each right-hand side's two columns
-// whole in registers.  The row's matrices are staged in LDS as L_t(r, k),
-// row r contiguous (transposed from the factor where the product needs it),
-// so every 16-byte LDS read feeds four FMAs: two entries, two columns.  Rows
-// are taken in an XCD-aware order: workgroups dispatched to one XCD (every
-// 8th) handle a contiguous run of rows, so the neighbours two rows share meet
-// in that XCD's L2.
+// c0 + 32 v + q + 16 u (u = 0, 1).  The row's matrices are staged in LDS as
+// L_t(r, k), row r contiguous (transposed from the factor where the product
+// needs it), so every 16-byte LDS read feeds four FMAs: two entries, two
+// columns.  A right-hand side's loads are all issued before its products.
+// Rows are taken in an XCD-aware order: workgroups dispatched to one XCD
+// (every 8th) handle a contiguous run of rows, so the neighbours two rows
+// share meet in that XCD's L2.
 struct FrStep {
   int64_t H, s, n;
   int w, m;
   int mode;
-  const double* XT;
   const double* edge;
-  const double* bars;
   double* P;
 };
 
-template <int WP, bool LVL1>
-__global__ __launch_bounds__(128) void
-k_fr_step(const double* __restrict__ fac, double* __restrict__ Z, FrStep a) {
+template <int WP>
+__global__ __launch_bounds__(128) void k_fr_step(const double* __restrict__ fac,
+                                                 double* __restrict__ Z, FrStep a) {
   constexpr int PP = WP * WP, RB = WP / 4, EW = 2 * WP + 2;
   __shared__ __attribute__((aligned(16))) double sL[3 * PP];   // L_t(r, k) at t PP + r WP + k
-  __shared__ __attribute__((aligned(16))) double sE[3 * 2 * WP];  // level 1: edge rows
   __shared__ double sP[3][4][64];                                  // P partial sums per group
   const int side = blockIdx.z;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -364,19 +532,6 @@ k_fr_step(const double* __restrict__ fac, double* __restrict__ Z, FrStep a) {
     mv[it] = (t < 3 && src[t]) ? *reinterpret_cast<const double2*>(src[t] + (e - t * PP))
                                : make_double2(0.0, 0.0);
   }
-  if (LVL1) {
-    // edge rows of the right-hand sides rebuilt here: slot 0 row i, slots 1, 2
-    // rows i -+ s (reduction only): [del_{j-1}(w-1, :) | gam_{j+1}(w-1, :)]
-    for (int e = tid; e < 3 * 2 * WP; e += 128) {
-      const int slot = e / (2 * WP), h = (e / WP) & 1, k = e % WP;
-      const int64_t j = slot == 0 ? i : (slot == 1 ? i - a.s : i + a.s);
-      const bool live = slot == 0 || (a.mode == 0 && (slot == 1 ? has_prev : has_next));
-      const int64_t nb = h == 0 ? j - 1 : j + 1;
-      sE[e] = (live && nb >= 0 && nb < a.H)
-                  ? a.edge[EW * ((int64_t)side * a.H + nb) + (h == 0 ? WP : 0) + k]
-                  : 0.0;
-    }
-  }
 #pragma unroll
   for (int it = 0; it < NM; ++it) {
     const int e = 2 * (tid + 128 * it), t = e / PP;
@@ -401,30 +556,9 @@ k_fr_step(const double* __restrict__ fac, double* __restrict__ Z, FrStep a) {
   auto rhs = [&](int64_t row, int c) {
     return Z + fr_rhs(side, a.H, row, a.m, WP) + (int64_t)c * WP;
   };
-  // g-values of the level-1 right-hand side of row j (see fr_b1): b1_j(k, c) =
-  // [k = w-1] gj(c) - gm(c) del_{j-1}(w-1, k) - gp(c) gam_{j+1}(w-1, k)
-  struct G3 { double j[2], m[2], p[2]; };
-  auto gvals = [&](int64_t j) {
-    G3 r;
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int c = cok[u] ? col[u] : 0;
-      r.j[u] = cok[u] ? a.bars[3 * j + side] * a.XT[j * a.m + c] : 0.0;
-      r.m[u] = (cok[u] && j >= 1) ? a.bars[3 * (j - 1) + side] * a.XT[(j - 1) * a.m + c] : 0.0;
-      r.p[u] = (cok[u] && j + 1 < a.H) ? a.bars[3 * (j + 1) + side] * a.XT[(j + 1) * a.m + c]
-                                        : 0.0;
-    }
-    return r;
-  };
-  auto b1 = [&](const G3& gg, int slot, int k, int u) {
-    const double* E = sE + slot * 2 * WP;
-    const double t = k == w - 1 ? gg.j[u] : 0.0;
-    return fma(-gg.p[u], E[WP + k], fma(-gg.m[u], E[k], t));
-  };
-  // acc(rr, u) += sign sum_k L_t(g RB + rr, k) v(k, u), the right-hand side
-  // streamed in chunks of four k (loaded from Z, or rebuilt for level 1)
+  // acc(rr, u) += sign sum_k L_t(g RB + rr, k) v(k, u)
   double acc[RB][2];
-  auto product = [&](int t, bool rebuilt, const G3& gg, int slot, int64_t row, double sign) {
+  auto product = [&](int t, int64_t row, double sign) {
     constexpr int NC = WP / 4;
     const double* L = sL + t * PP + g * RB * WP;
     const double* sp0 = rhs(row, cok[0] ? col[0] : 0);
@@ -432,26 +566,18 @@ k_fr_step(const double* __restrict__ fac, double* __restrict__ Z, FrStep a) {
     // every load of the right-hand side first (all in flight together) ...
     double v[NC][4][2];
 #pragma unroll
-    for (int kc = 0; kc < NC; ++kc) {
-      if (rebuilt) {
+    for (int kc = 0; kc < NC; ++kc)
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-#pragma unroll
-          for (int u = 0; u < 2; ++u) v[kc][e][u] = b1(gg, slot, 4 * kc + e, u);
-      } else {
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const double2 t0 = cok[0] ? *reinterpret_cast<const double2*>(sp0 + 4 * kc + 2 * h)
-                                    : make_double2(0.0, 0.0);
-          const double2 t1 = cok[1] ? *reinterpret_cast<const double2*>(sp1 + 4 * kc + 2 * h)
-                                    : make_double2(0.0, 0.0);
-          v[kc][2 * h][0] = t0.x;
-          v[kc][2 * h + 1][0] = t0.y;
-          v[kc][2 * h][1] = t1.x;
-          v[kc][2 * h + 1][1] = t1.y;
-        }
+      for (int h = 0; h < 2; ++h) {
+        const double2 t0 = cok[0] ? *reinterpret_cast<const double2*>(sp0 + 4 * kc + 2 * h)
+                                  : make_double2(0.0, 0.0);
+        const double2 t1 = cok[1] ? *reinterpret_cast<const double2*>(sp1 + 4 * kc + 2 * h)
+                                  : make_double2(0.0, 0.0);
+        v[kc][2 * h][0] = t0.x;
+        v[kc][2 * h + 1][0] = t0.y;
+        v[kc][2 * h][1] = t1.x;
+        v[kc][2 * h + 1][1] = t1.y;
       }
-    }
     // ... then the products chunk by chunk, the LDS reads of a chunk held
     // back to it (the compiler barrier keeps them from all being hoisted
     // into registers at once)
@@ -474,38 +600,33 @@ k_fr_step(const double* __restrict__ fac, double* __restrict__ Z, FrStep a) {
     }
     asm volatile("" ::: "memory");
   };
-  const G3 g0 = LVL1 ? gvals(i) : G3{};
   if (a.mode == 0) {
     // acc = b_p on the lane's rows
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const double* sp = rhs(i, cok[u] ? col[u] : 0) + g * RB;
 #pragma unroll
-      for (int rr = 0; rr < RB; ++rr)
-        acc[rr][u] = LVL1 ? b1(g0, 0, g * RB + rr, u) : (cok[u] ? sp[rr] : 0.0);
+      for (int rr = 0; rr < RB; ++rr) acc[rr][u] = cok[u] ? sp[rr] : 0.0;
     }
-    if (has_prev) product(1, LVL1, LVL1 ? gvals(i - a.s) : G3{}, 1, i - a.s, -1.0);
-    if (has_next) product(2, LVL1, LVL1 ? gvals(i + a.s) : G3{}, 2, i + a.s, -1.0);
+    if (has_prev) product(1, i - a.s, -1.0);
+    if (has_next) product(2, i + a.s, -1.0);
   } else {
 #pragma unroll
     for (int rr = 0; rr < RB; ++rr) acc[rr][0] = acc[rr][1] = 0.0;
-    product(0, LVL1, g0, 0, i, 1.0);
-    if (has_prev) product(1, false, g0, 0, i - a.s, -1.0);
-    if (has_next) product(2, false, g0, 0, i + a.s, -1.0);
+    product(0, i, 1.0);
+    if (has_prev) product(1, i - a.s, -1.0);
+    if (has_next) product(2, i + a.s, -1.0);
   }
   // results: x (or the reduced b) of the lane's rows to Z
-  if (a.mode == 0 || !LVL1) {
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      if (!cok[u]) continue;
-      double* dp = rhs(i, col[u]) + g * RB;
+  for (int u = 0; u < 2; ++u) {
+    if (!cok[u]) continue;
+    double* dp = rhs(i, col[u]) + g * RB;
 #pragma unroll
-      for (int rr = 0; rr < RB; ++rr) dp[rr] = acc[rr][u];
-    }
+    for (int rr = 0; rr < RB; ++rr) dp[rr] = acc[rr][u];
   }
   if (a.mode == 0) return;
-  // P of row i: x(w-1), del_{i-1}(w-1, :) x, gam_{i+1}(w-1, :) x, summed over
-  // the four row groups through LDS
+  // P of row i, summed over the four row groups through LDS
   const double* Ed = i >= 1 ? a.edge + EW * ((int64_t)side * a.H + i - 1) + WP : nullptr;
   const double* Eg = i + 1 < a.H ? a.edge + EW * ((int64_t)side * a.H + i + 1) : nullptr;
 #pragma unroll
@@ -529,7 +650,8 @@ k_fr_step(const double* __restrict__ fac, double* __restrict__ Z, FrStep a) {
     if (c < a.m) {
       double pv[3];
 #pragma unroll
-      for (int h = 0; h < 3; ++h) pv[h] = sP[h][0][tid] + sP[h][1][tid] + sP[h][2][tid] + sP[h][3][tid];
+      for (int h = 0; h < 3; ++h)
+        pv[h] = sP[h][0][tid] + sP[h][1][tid] + sP[h][2][tid] + sP[h][3][tid];
       const int64_t Hh = (a.H + 1) / 2;
       double* dst = a.P + (((int64_t)side * a.m + c) * Hh + i / 2) * 4;
       *reinterpret_cast<double2*>(dst) = make_double2(pv[0], pv[1]);
@@ -625,15 +747,12 @@ static void frontal_apply_wp(const hm_frontal_s* f, int64_t ncols, const double*
                          dim3(256), 0, s, Xc, ldx, H, m, XT);
       KCHK();
       const unsigned groups = (unsigned)((m + 63) / 64);
-      auto step = [&](bool lvl1, int mode, int64_t stride, int64_t n, int64_t rows) {
+      const double* ops = f->ops.as<double>();
+      auto step = [&](int mode, int64_t stride, int64_t n, int64_t rows) {
         if (rows <= 0) return;
-        FrStep a{H, stride, n, w, m, mode, XT, edge, bars, P};
-        if (lvl1)
-          hipLaunchKernelGGL((k_fr_step<WP, true>), dim3((unsigned)rows, groups, 2), dim3(128), 0,
-                             s, fac, Z, a);
-        else
-          hipLaunchKernelGGL((k_fr_step<WP, false>), dim3((unsigned)rows, groups, 2), dim3(128),
-                             0, s, fac, Z, a);
+        FrStep a{H, stride, n, w, m, mode, edge, P};
+        hipLaunchKernelGGL(k_fr_step<WP>, dim3((unsigned)rows, groups, 2), dim3(128), 0, s, fac,
+                           Z, a);
         KCHK();
       };
       // n_l: active rows of level l
@@ -642,13 +761,19 @@ static void frontal_apply_wp(const hm_frontal_s* f, int64_t ncols, const double*
       nl[0] = H;
       for (int l = 1; l <= L; ++l) nl[l] = (nl[l - 1] + 1) / 2;
       if (L == 1) {
-        step(true, 2, 2, 1, 1);
+        hipLaunchKernelGGL(k_fr_l1bwd<WP>, dim3(1, groups, 2), dim3(64), 0, s, ops, f->recw, Z,
+                           P, XT, bars, H, m, 1);
+        KCHK();
       } else {
-        step(true, 0, 2, nl[1], (nl[1] + 1) / 2);
-        for (int l = 2; l < L; ++l) step(false, 0, (int64_t)1 << l, nl[l], (nl[l] + 1) / 2);
-        step(false, 2, (int64_t)1 << L, 1, 1);
-        for (int l = L - 1; l >= 2; --l) step(false, 1, (int64_t)1 << l, nl[l], nl[l] / 2);
-        step(true, 1, 2, nl[1], nl[1] / 2);
+        hipLaunchKernelGGL(k_fr_l1fwd<WP>, dim3((unsigned)((nl[1] + 1) / 2), groups, 2), dim3(64),
+                           0, s, ops, f->recw, Z, XT, bars, H, m);
+        KCHK();
+        for (int l = 2; l < L; ++l) step(0, (int64_t)1 << l, nl[l], (nl[l] + 1) / 2);
+        step(2, (int64_t)1 << L, 1, 1);
+        for (int l = L - 1; l >= 2; --l) step(1, (int64_t)1 << l, nl[l], nl[l] / 2);
+        hipLaunchKernelGGL(k_fr_l1bwd<WP>, dim3((unsigned)(nl[1] / 2), groups, 2), dim3(64), 0,
+                           s, ops, f->recw, Z, P, XT, bars, H, m, 0);
+        KCHK();
       }
     }
     hipLaunchKernelGGL(k_fr_out<WP>, dim3(nblk(H), m), dim3(256), 0, s, Xc, ldx, Yc, ldy, m,
@@ -714,6 +839,8 @@ int hm_frontal_create(int64_t height, int32_t width, const double* ch, const dou
     F->fac = DevBuf((size_t)(2 * H * 3 * F->wp * F->wp) * sizeof(double));
     F->bars = DevBuf((size_t)(3 * H) * sizeof(double));
     F->edge = DevBuf((size_t)(2 * H * (2 * F->wp + 2)) * sizeof(double));
+    F->recw = 7 * F->wp + 12;
+    F->ops = DevBuf((size_t)(2 * ((H + 1) / 2) * F->recw) * sizeof(double));
     DevBuf Dw((size_t)(2 * H * per) * sizeof(double)), Cw((size_t)(2 * H * per) * sizeof(double));
     DevBuf bad(256);
     HIPCHK(hipMemsetAsync(bad.p, 0, 16, s));
@@ -738,6 +865,12 @@ int hm_frontal_create(int64_t height, int32_t width, const double* ch, const dou
                        Cw.as<double>(), F->fac.as<double>(), F->edge.as<double>(), H, w, F->wp,
                        (int64_t)1 << L, 1, 1, bad.as<int32_t>());
     KCHK();
+    if (L >= 1) {
+      hipLaunchKernelGGL(k_fr_lvl1_ops, dim3((unsigned)((H + 1) / 2), 1, 2), dim3(256), 0, s,
+                         F->fac.as<double>(), F->edge.as<double>(), F->ops.as<double>(), H, w,
+                         F->wp, F->recw);
+      KCHK();
+    }
     int hb[4] = {0, 0, 0, 0};
     HIPCHK(hipMemcpyAsync(hb, bad.p, 16, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
