@@ -443,15 +443,18 @@ def frontal_apply_bytes(H, w, m):
     columns: block cyclic reduction over H grid rows on each side, every array
     a kernel touches counted once per kernel.  x read twice (transposed copy,
     output) and its transposed copy written and read once, y written once.
-    Per side: the level-1 reduction reads its rows' level-1 operators (7 wp
-    FP64 each, wp = w rounded up to 4) and writes the level-2 right-hand
-    sides (wp entries per column); each coarser level reads its active rows'
-    right-hand sides once and two w x w matrices per kept row, writes the
-    kept rows; the root and each back substitution of level >= 2 read their
-    rows' Dinv, gam, del and right-hand sides and the neighbours' solutions
-    once, write x and the 4-entry projection P; the level-1 back substitution
-    reads its operators (6 wp + 9) and the level-2 rows' solutions, writes P;
-    the output kernel reads P, writes y."""
+    Per side (wp = w rounded up to 4, right-hand sides wp entries per column):
+    levels 1 and 2 run through operators built with the factor -- the
+    level-3 right-hand sides come from fifteen x values per row (15 wp FP64
+    of operator per row, written once), the level-2 back substitution reads
+    its 7 wp operator, gam and del and the level-3 rows' solutions, writes x
+    and the 4-entry projection P, the level-1 back substitution reads its
+    6 wp + 9 operator and the level-2 rows' solutions, writes P; each level
+    >= 3 reads its active rows' right-hand sides once and two w x w matrices
+    per kept row, writes the kept rows; the root and each back substitution
+    there read Dinv, gam, del, the right-hand sides and the neighbours'
+    solutions once, write x and P; the output kernel reads P, writes y.  (Two
+    levels only: the level-2 right-hand sides from seven x values each.)"""
     wp = (w + 3) // 4 * 4
     R, Mb, Pb = 8 * wp * m, 8 * w * w, 32 * m
     nl = [H]
@@ -464,16 +467,23 @@ def frontal_apply_bytes(H, w, m):
         side += 8 * (6 * wp + 9) + Pb
     elif L >= 2:
         n1 = nl[1]
-        kept1, odd1 = (n1 + 1) // 2, n1 // 2
-        side += kept1 * (8 * 7 * wp + R)
-        for l in range(2, L):
-            kept = (nl[l] + 1) // 2
-            side += nl[l] * R + 2 * Mb * kept + kept * R
-        side += R + Mb + R + Pb
-        for l in range(2, L):
-            odd = nl[l] // 2
-            side += nl[l] * R + 3 * Mb * odd + odd * (R + Pb)
-        side += kept1 * R + odd1 * (8 * (6 * wp + 9) + Pb)
+        odd1 = n1 // 2
+        l1bwd = ((n1 + 1) // 2) * R + odd1 * (8 * (6 * wp + 9) + Pb)
+        if L == 2:
+            side += ((n1 + 1) // 2) * (8 * 7 * wp + R) + (R + Mb + R + Pb) + l1bwd
+        else:
+            n2 = nl[2]
+            kept2, odd2 = (n2 + 1) // 2, n2 // 2
+            side += kept2 * (8 * 15 * wp + R)
+            for l in range(3, L):
+                kept = (nl[l] + 1) // 2
+                side += nl[l] * R + 2 * Mb * kept + kept * R
+            side += R + Mb + R + Pb
+            for l in range(3, L):
+                odd = nl[l] // 2
+                side += nl[l] * R + 3 * Mb * odd + odd * (R + Pb)
+            side += kept2 * R + odd2 * (8 * 7 * wp + 2 * Mb + R + Pb)
+            side += l1bwd
     total += 2 * side + 2 * ((H + 1) // 2) * Pb   # both sides; P read by the output
     return float(total)
 

@@ -46,6 +46,8 @@ struct hm_frontal_s {
   hm::DevBuf edge;       // [side][row][gam(w-1, :) | del(w-1, :) | Dinv(w-1, w-1), 0]
   hm::DevBuf ops;        // level-1 operators: [side][level-1 position][recw]
   int recw = 0;
+  hm::DevBuf ops2;       // level-2 operators (levels >= 3): [side][level-2 position][recw2]
+  int recw2 = 0;
   hm::DevBuf bars;       // [row][cL, cR, cv_mid]: the middle column's bars
 };
 
@@ -343,6 +345,64 @@ __global__ __launch_bounds__(256) void k_fr_lvl1_ops(const double* fac, const do
   }
 }
 
+// Level-2 operators (when the reduction has three or more levels), from the
+// level-1 ones: the level-2 right-hand side of a row j = 0 mod 4 is
+// b2_j = sum_{d=0..6} g_{j+d-3} W_{j,d}, so
+//  * reduction at row i (level-2 position q = i / 4 even):
+//      b3_i = sum_{e=0..14} g_{i+e-7} V_e,  V_e = W_{i,e-4} - del_{i-4}^T W_{i-4,e}
+//             - gam_{i+4}^T W_{i+4,e-8}  (terms whose index is out of 0..6 or
+//             whose row is absent: 0);
+//  * back substitution at row i (q odd): x_i = sum_d g_{i+d-3} DW_d - gam_i x_{i-4}
+//    - del_i x_{i+4}, DW_d = Dinv_i W_{i,d}.
+// Record of (side, q): V_0..V_14 or DW_0..DW_6 (wp each).
+__global__ __launch_bounds__(256) void k_fr_lvl2_ops(const double* fac, const double* ops1,
+                                                     int recw1, double* ops2, int64_t H, int w,
+                                                     int wp, int recw2) {
+  constexpr int WM = FR_WMAX;
+  __shared__ double M1[WM * WM], M2[WM * WM];   // ld wp
+  __shared__ double Wc[7 * WM], Wm[7 * WM], Wp[7 * WM];
+  const int side = blockIdx.z, tid = threadIdx.x;
+  const int64_t q = blockIdx.x, i = 4 * q;
+  const int pp = wp * wp;
+  const int64_t n1 = (H + 1) / 2, n2 = (n1 + 1) / 2;
+  auto rec1 = [&](int64_t row) { return ops1 + ((int64_t)side * n1 + row / 2) * recw1; };
+  double* R = ops2 + ((int64_t)side * n2 + q) * recw2;
+  for (int e = tid; e < 7 * wp; e += 256) Wc[e] = rec1(i)[e];
+  if (!(q & 1)) {
+    const bool prv = q >= 1, nxt = i + 4 < H;
+    for (int e = tid; e < pp; e += 256) {
+      M1[e] = prv ? fac[fr_fac(side, H, i - 4, wp) + 2 * pp + e] : 0.0;   // del_{i-4}
+      M2[e] = nxt ? fac[fr_fac(side, H, i + 4, wp) + pp + e] : 0.0;       // gam_{i+4}
+    }
+    for (int e = tid; e < 7 * wp; e += 256) {
+      Wm[e] = prv ? rec1(i - 4)[e] : 0.0;
+      Wp[e] = nxt ? rec1(i + 4)[e] : 0.0;
+    }
+    __syncthreads();
+    for (int e = tid; e < 15 * wp; e += 256) {
+      const int ee = e / wp, r = e % wp;
+      double v = (ee >= 4 && ee <= 10) ? Wc[(ee - 4) * wp + r] : 0.0;
+      if (r < w) {
+        if (ee <= 6)
+          for (int k = 0; k < w; ++k) v = fma(-M1[k + r * wp], Wm[ee * wp + k], v);
+        if (ee >= 8)
+          for (int k = 0; k < w; ++k) v = fma(-M2[k + r * wp], Wp[(ee - 8) * wp + k], v);
+      }
+      R[e] = v;
+    }
+    return;
+  }
+  for (int e = tid; e < pp; e += 256) M1[e] = fac[fr_fac(side, H, i, wp) + e];   // Dinv_i
+  __syncthreads();
+  for (int e = tid; e < 7 * wp; e += 256) {
+    const int d = e / wp, r = e % wp;
+    double v = 0.0;
+    if (r < w)
+      for (int k = 0; k < w; ++k) v = fma(M1[r + k * wp], Wc[d * wp + k], v);
+    R[e] = v;
+  }
+}
+
 // ---- solve ----------------------------------------------------------------------
 // Right-hand sides Z[side][row][column][j]: WP entries per column (w rounded
 // up to a multiple of 4, the entries past w zero), contiguous per row, so a
@@ -370,29 +430,33 @@ __device__ inline void fr_store(double* dst, const double (&v)[WP]) {
   for (int j = 0; j < WP; j += 2) *reinterpret_cast<double2*>(dst + j) = make_double2(v[j], v[j + 1]);
 }
 
-// Level-1 reduction from the level-1 operators (k_fr_lvl1_ops): the level-2
-// right-hand side of row i = 4 x, b2_i = sum_d g_{i+d-3} W_d, one column per
-// lane (x transposed: XT[j m + c] = x_j(c), contiguous over the lanes), W in
-// LDS read as broadcasts; 64 columns per workgroup.
-template <int WP>
-__global__ __launch_bounds__(64) void k_fr_l1fwd(const double* __restrict__ ops, int recw,
-                                                 double* __restrict__ Z, const double* XT,
-                                                 const double* bars, int64_t H, int m) {
-  __shared__ __attribute__((aligned(16))) double sW[7 * WP];
+// Reduction from the level-1 (NV = 7) or level-2 (NV = 15) operators: the
+// next level's right-hand side of row i = spacing x, sum_e g_{i+e-(NV-1)/2} V_e,
+// one column per lane (x transposed: XT[j m + c] = x_j(c), contiguous over
+// the lanes), V in LDS read as broadcasts, the result through LDS for
+// contiguous stores; 64 columns per workgroup.  Records are indexed by the
+// row's position at their level, i / (spacing / 2).
+template <int WP, int NV>
+__global__ __launch_bounds__(64) void k_fr_gfwd(const double* __restrict__ ops, int recw,
+                                                int64_t nrec, int64_t spacing,
+                                                double* __restrict__ Z, const double* XT,
+                                                const double* bars, int64_t H, int m) {
+  __shared__ __attribute__((aligned(16))) double sW[NV * WP];
   __shared__ __attribute__((aligned(16))) double sB[64 * WP];   // the result, for contiguous stores
+  constexpr int HALF = (NV - 1) / 2;
   const int side = blockIdx.z, lane = threadIdx.x;
   const int64_t T = gridDim.x;
   int64_t x = blockIdx.x;
   if ((T & 7) == 0) x = (x & 7) * (T >> 3) + (x >> 3);
-  const int64_t p = 2 * x, i = 2 * p;
-  const int64_t n1 = (H + 1) / 2;
-  const double* R = ops + ((int64_t)side * n1 + p) * recw;
-  for (int e = lane; e < 7 * WP; e += 64) sW[e] = R[e];
+  const int64_t i = spacing * x;
+  // records are indexed by position at their level: i / (spacing / 2)
+  const double* R = ops + ((int64_t)side * nrec + i / (spacing / 2)) * recw;
+  for (int e = lane; e < NV * WP; e += 64) sW[e] = R[e];
   const int c = blockIdx.y * 64 + lane;
-  double gv[7];
+  double gv[NV];
 #pragma unroll
-  for (int d = 0; d < 7; ++d) {
-    const int64_t j = i + d - 3;
+  for (int d = 0; d < NV; ++d) {
+    const int64_t j = i + d - HALF;
     gv[d] = (c < m && j >= 0 && j < H) ? bars[3 * j + side] * XT[j * m + c] : 0.0;
   }
   __syncthreads();
@@ -400,7 +464,7 @@ __global__ __launch_bounds__(64) void k_fr_l1fwd(const double* __restrict__ ops,
   for (int r = 0; r < WP; r += 2) {
     double b0 = 0.0, b1 = 0.0;
 #pragma unroll
-    for (int d = 0; d < 7; ++d) {
+    for (int d = 0; d < NV; ++d) {
       const double2 wv = *reinterpret_cast<const double2*>(sW + d * WP + r);
       b0 = fma(wv.x, gv[d], b0);
       b1 = fma(wv.y, gv[d], b1);
@@ -474,7 +538,9 @@ __global__ __launch_bounds__(64) void k_fr_l1bwd(const double* __restrict__ ops,
 // group of columns, blockIdx.z: the side).  mode 0 reduction (even p):
 // b_p -= del_{p-1}^T b_{p-1} + gam_{p+1}^T b_{p+1}; mode 1 back substitution
 // (odd p): x_p = Dinv_p b_p - gam_p x_{p-1} - del_p x_{p+1}; mode 2 root:
-// x_0 = Dinv_0 b_0.  A back substitution or root writes x to Z and the
+// x_0 = Dinv_0 b_0; mode 3, the level-2 back substitution from the level-2
+// operators: x_p = sum_d g_{i+d-3} DW_d - gam_p x_{p-1} - del_p x_{p+1}.  A back
+// substitution or root writes x to Z and the
 // 4-entry projection P_i = (x_i(w-1), Ed_{i-1}^T x_i, Eg_{i+1}^T x_i, 0) the
 // output kernel reads.
 //
@@ -493,6 +559,11 @@ struct FrStep {
   int mode;
   const double* edge;
   double* P;
+  // mode 3 (level-2 back substitution from the level-2 operators)
+  const double* XT;
+  const double* bars;
+  const double* ops2;
+  int recw2;
 };
 
 template <int WP>
@@ -501,13 +572,14 @@ __global__ __launch_bounds__(128) void k_fr_step(const double* __restrict__ fac,
   constexpr int PP = WP * WP, RB = WP / 4, EW = 2 * WP + 2;
   __shared__ __attribute__((aligned(16))) double sL[3 * PP];   // L_t(r, k) at t PP + r WP + k
   __shared__ double sP[3][4][64];                                  // P partial sums per group
+  __shared__ double sD[7 * WP];                                    // mode 3: DW_0..DW_6
   const int side = blockIdx.z;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int g = lane >> 4, q = lane & 15;
   const int64_t T = gridDim.x;
   int64_t x = blockIdx.x;
   if ((T & 7) == 0) x = (x & 7) * (T >> 3) + (x >> 3);
-  const int64_t p = a.mode == 2 ? 0 : 2 * x + (a.mode == 1 ? 1 : 0);
+  const int64_t p = a.mode == 2 ? 0 : 2 * x + (a.mode == 0 ? 0 : 1);
   const int64_t i = p * a.s;
   const int w = a.w;
   const bool has_prev = a.mode != 2 && p >= 1, has_next = a.mode != 2 && p + 1 < a.n;
@@ -520,9 +592,15 @@ __global__ __launch_bounds__(128) void k_fr_step(const double* __restrict__ fac,
     src[1] = has_prev ? fac + fr_fac(side, a.H, i - a.s, WP) + 2 * PP : nullptr;
     src[2] = has_next ? fac + fr_fac(side, a.H, i + a.s, WP) + PP : nullptr;
   } else {
-    src[0] = fac + fr_fac(side, a.H, i, WP);
-    src[1] = has_prev ? src[0] + PP : nullptr;
-    src[2] = has_next ? src[0] + 2 * PP : nullptr;
+    const double* base = fac + fr_fac(side, a.H, i, WP);
+    src[0] = a.mode == 3 ? nullptr : base;
+    src[1] = has_prev ? base + PP : nullptr;
+    src[2] = has_next ? base + 2 * PP : nullptr;
+  }
+  if (a.mode == 3) {
+    const int64_t n2 = (((a.H + 1) / 2) + 1) / 2;
+    const double* R = a.ops2 + ((int64_t)side * n2 + i / 4) * a.recw2;
+    for (int e = tid; e < 7 * WP; e += 128) sD[e] = R[e];
   }
   constexpr int NM = (3 * PP / 2 + 127) / 128;
   double2 mv[NM];
@@ -611,9 +689,31 @@ __global__ __launch_bounds__(128) void k_fr_step(const double* __restrict__ fac,
     if (has_prev) product(1, i - a.s, -1.0);
     if (has_next) product(2, i + a.s, -1.0);
   } else {
+    if (a.mode == 3) {
+      // acc = sum_d g_{i+d-3} DW_d on the lane's rows
+      double gv[7][2];
 #pragma unroll
-    for (int rr = 0; rr < RB; ++rr) acc[rr][0] = acc[rr][1] = 0.0;
-    product(0, i, 1.0);
+      for (int d = 0; d < 7; ++d)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int64_t j = i + d - 3;
+          gv[d][u] = (cok[u] && j >= 0 && j < a.H) ? a.bars[3 * j + side] * a.XT[j * a.m + col[u]]
+                                                   : 0.0;
+        }
+#pragma unroll
+      for (int rr = 0; rr < RB; ++rr)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          double t = 0.0;
+#pragma unroll
+          for (int d = 0; d < 7; ++d) t = fma(sD[d * WP + g * RB + rr], gv[d][u], t);
+          acc[rr][u] = t;
+        }
+    } else {
+#pragma unroll
+      for (int rr = 0; rr < RB; ++rr) acc[rr][0] = acc[rr][1] = 0.0;
+      product(0, i, 1.0);
+    }
     if (has_prev) product(1, i - a.s, -1.0);
     if (has_next) product(2, i + a.s, -1.0);
   }
@@ -750,7 +850,7 @@ static void frontal_apply_wp(const hm_frontal_s* f, int64_t ncols, const double*
       const double* ops = f->ops.as<double>();
       auto step = [&](int mode, int64_t stride, int64_t n, int64_t rows) {
         if (rows <= 0) return;
-        FrStep a{H, stride, n, w, m, mode, edge, P};
+        FrStep a{H, stride, n, w, m, mode, edge, P, XT, bars, f->ops2.as<double>(), f->recw2};
         hipLaunchKernelGGL(k_fr_step<WP>, dim3((unsigned)rows, groups, 2), dim3(128), 0, s, fac,
                            Z, a);
         KCHK();
@@ -760,19 +860,32 @@ static void frontal_apply_wp(const hm_frontal_s* f, int64_t ncols, const double*
       std::vector<int64_t> nl(L + 1);
       nl[0] = H;
       for (int l = 1; l <= L; ++l) nl[l] = (nl[l - 1] + 1) / 2;
+      const int64_t n1 = nl[1];
       if (L == 1) {
         hipLaunchKernelGGL(k_fr_l1bwd<WP>, dim3(1, groups, 2), dim3(64), 0, s, ops, f->recw, Z,
                            P, XT, bars, H, m, 1);
         KCHK();
-      } else {
-        hipLaunchKernelGGL(k_fr_l1fwd<WP>, dim3((unsigned)((nl[1] + 1) / 2), groups, 2), dim3(64),
-                           0, s, ops, f->recw, Z, XT, bars, H, m);
+      } else if (L == 2) {
+        hipLaunchKernelGGL((k_fr_gfwd<WP, 7>), dim3((unsigned)((n1 + 1) / 2), groups, 2), dim3(64),
+                           0, s, ops, f->recw, n1, (int64_t)4, Z, XT, bars, H, m);
         KCHK();
-        for (int l = 2; l < L; ++l) step(0, (int64_t)1 << l, nl[l], (nl[l] + 1) / 2);
         step(2, (int64_t)1 << L, 1, 1);
-        for (int l = L - 1; l >= 2; --l) step(1, (int64_t)1 << l, nl[l], nl[l] / 2);
-        hipLaunchKernelGGL(k_fr_l1bwd<WP>, dim3((unsigned)(nl[1] / 2), groups, 2), dim3(64), 0,
-                           s, ops, f->recw, Z, P, XT, bars, H, m, 0);
+        hipLaunchKernelGGL(k_fr_l1bwd<WP>, dim3((unsigned)(n1 / 2), groups, 2), dim3(64), 0, s,
+                           ops, f->recw, Z, P, XT, bars, H, m, 0);
+        KCHK();
+      } else {
+        // levels 1 and 2 through their operators, 3 .. L - 1 and the root dense
+        const int64_t n2 = nl[2];
+        hipLaunchKernelGGL((k_fr_gfwd<WP, 15>), dim3((unsigned)((n2 + 1) / 2), groups, 2),
+                           dim3(64), 0, s, f->ops2.as<double>(), f->recw2, n2, (int64_t)8, Z, XT,
+                           bars, H, m);
+        KCHK();
+        for (int l = 3; l < L; ++l) step(0, (int64_t)1 << l, nl[l], (nl[l] + 1) / 2);
+        step(2, (int64_t)1 << L, 1, 1);
+        for (int l = L - 1; l >= 3; --l) step(1, (int64_t)1 << l, nl[l], nl[l] / 2);
+        step(3, (int64_t)4, n2, n2 / 2);
+        hipLaunchKernelGGL(k_fr_l1bwd<WP>, dim3((unsigned)(n1 / 2), groups, 2), dim3(64), 0, s,
+                           ops, f->recw, Z, P, XT, bars, H, m, 0);
         KCHK();
       }
     }
@@ -841,6 +954,9 @@ int hm_frontal_create(int64_t height, int32_t width, const double* ch, const dou
     F->edge = DevBuf((size_t)(2 * H * (2 * F->wp + 2)) * sizeof(double));
     F->recw = 7 * F->wp + 12;
     F->ops = DevBuf((size_t)(2 * ((H + 1) / 2) * F->recw) * sizeof(double));
+    const int64_t n2 = ((H + 1) / 2 + 1) / 2;
+    F->recw2 = 15 * F->wp;
+    if (L >= 3) F->ops2 = DevBuf((size_t)(2 * n2 * F->recw2) * sizeof(double));
     DevBuf Dw((size_t)(2 * H * per) * sizeof(double)), Cw((size_t)(2 * H * per) * sizeof(double));
     DevBuf bad(256);
     HIPCHK(hipMemsetAsync(bad.p, 0, 16, s));
@@ -869,6 +985,12 @@ int hm_frontal_create(int64_t height, int32_t width, const double* ch, const dou
       hipLaunchKernelGGL(k_fr_lvl1_ops, dim3((unsigned)((H + 1) / 2), 1, 2), dim3(256), 0, s,
                          F->fac.as<double>(), F->edge.as<double>(), F->ops.as<double>(), H, w,
                          F->wp, F->recw);
+      KCHK();
+    }
+    if (L >= 3) {
+      hipLaunchKernelGGL(k_fr_lvl2_ops, dim3((unsigned)n2, 1, 2), dim3(256), 0, s,
+                         F->fac.as<double>(), F->ops.as<double>(), F->recw, F->ops2.as<double>(),
+                         H, w, F->wp, F->recw2);
       KCHK();
     }
     int hb[4] = {0, 0, 0, 0};
