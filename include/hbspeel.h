@@ -357,9 +357,11 @@ void hm_hbs_factor_free(hm_hbs_factor* f);
  * j] joins (i, j) and (i+1, j) (may be NULL when height == 1).  Both are read
  * during the call only.  Conductivities must be positive and finite; a
  * non-positive pivot gives HM_ERR_SINGULAR.  width > 65 gives
- * HM_ERR_UNSUPPORTED, other bad sizes HM_ERR_ARG.  With w = (width - 1) / 2,
- * the handle holds 8 (6 w^2 + 3) height bytes of device memory (2 GB per 100k
- * rows at width 41) and the call uses 32 w^2 height bytes more as work.
+ * HM_ERR_UNSUPPORTED, other bad sizes HM_ERR_ARG.  With w = (width - 1) / 2
+ * and wp = w rounded up to a multiple of 4, the handle holds about
+ * 8 (6 wp^2 + 19 wp + 19) height bytes of device memory (2.3 GB per 100k rows
+ * at width 41: the factor and the small operators of its first two levels)
+ * and the call uses 32 w^2 height bytes more as work.
  * hm_frontal_apply: Y = A X for X, Y device, column-major, height x ncols,
  * leading dims >= height (HM_ERR_ARG otherwise); FP64; enqueued on `stream`,
  * in passes of at most 128 columns with a work block of about
