@@ -146,3 +146,30 @@ def test_frontal_compression_matches_oracle(kind):
     # threshold may differ by rounding)
     assert rel(Y, AX) < 20 * tol and rel(Yo, AX) < 20 * tol
     assert rel(Y, Yo) < 20 * tol
+
+
+def test_frontal_rejects_a_grid_without_conductance():
+    # every bar at zero: D = 0, the first pivot is not positive -> HM_ERR_SINGULAR,
+    # reported by the factor's own pivot check (no fault, no handle)
+    import ctypes as C
+    H, W = 16, 41
+    ch = torch.zeros((H, W - 1), dtype=torch.float64, device="cuda")
+    cv = torch.zeros((H - 1, W), dtype=torch.float64, device="cuda")
+    f = C.c_void_p()
+    rc = hm.lib.hm_frontal_create(H, W, ch.data_ptr(), cv.data_ptr(), None, C.byref(f))
+    assert rc == -7 and f.value is None
+    assert b"pivot" in hm.lib.hm_last_error()
+
+
+def test_frontal_handle_outlives_its_inputs():
+    # the conductivities are read during create only; the handle keeps what it needs
+    H = 300
+    ch, cv = wl.grid_conductivities(H, 41, seed=13)
+    chd, cvd = torch.from_numpy(ch).cuda(), torch.from_numpy(cv).cuda()
+    f = hm.frontal_create(chd, cvd)
+    chd.fill_(float("nan"))
+    cvd.fill_(float("nan"))
+    del chd, cvd
+    torch.cuda.synchronize()
+    X = wl.gaussian((H, 5), seed=2)
+    assert rel(_apply(f, X), ofr.FrontalOp(ch, cv).apply(X)) < TOL
