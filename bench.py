@@ -447,16 +447,18 @@ def frontal_apply_bytes(H, w, m):
     levels 1 and 2 run through operators built with the factor -- the
     level-3 right-hand sides come from fifteen x values per row (15 wp FP64
     of operator per row, written once), the level-2 back substitution reads
-    its 7 wp operator, gam and del and the level-3 rows' solutions, writes x
-    and the 4-entry projection P, the level-1 back substitution reads its
-    6 wp + 9 operator and the level-2 rows' solutions, writes P; each level
-    >= 3 reads its active rows' right-hand sides once and two w x w matrices
-    per kept row, writes the kept rows; the root and each back substitution
-    there read Dinv, gam, del, the right-hand sides and the neighbours'
-    solutions once, write x and P; the output kernel reads P, writes y.  (Two
-    levels only: the level-2 right-hand sides from seven x values each.)"""
+    its 7 wp operator, gam and del and the level-3 rows' solutions, writes
+    the 4-entry projection P and the six projections NP its level-1
+    neighbours need (no x: nothing finer reads it); the level-1 back
+    substitution reads 9 operator values and its neighbours' NP halves,
+    writes P; each level >= 3 reads its active rows' right-hand sides once
+    and two w x w matrices per kept row, writes the kept rows; the root and
+    each back substitution there read Dinv, gam, del, the right-hand sides,
+    the neighbours' solutions and 6 wp of level-1 operator once, write x, P
+    and NP; the output kernel reads P, writes y.  (Two levels only: the
+    level-2 right-hand sides from seven x values each.)"""
     wp = (w + 3) // 4 * 4
-    R, Mb, Pb = 8 * wp * m, 8 * w * w, 32 * m
+    R, Mb, Pb, NPb, Qb = 8 * wp * m, 8 * w * w, 32 * m, 48 * m, 8 * 6 * wp
     nl = [H]
     while nl[-1] > 1:
         nl.append((nl[-1] + 1) // 2)
@@ -468,9 +470,9 @@ def frontal_apply_bytes(H, w, m):
     elif L >= 2:
         n1 = nl[1]
         odd1 = n1 // 2
-        l1bwd = ((n1 + 1) // 2) * R + odd1 * (8 * (6 * wp + 9) + Pb)
+        l1bwd = ((n1 + 1) // 2) * NPb + odd1 * (8 * 9 + Pb)
         if L == 2:
-            side += ((n1 + 1) // 2) * (8 * 7 * wp + R) + (R + Mb + R + Pb) + l1bwd
+            side += ((n1 + 1) // 2) * (8 * 7 * wp + R) + (R + Mb + Qb + R + Pb + NPb) + l1bwd
         else:
             n2 = nl[2]
             kept2, odd2 = (n2 + 1) // 2, n2 // 2
@@ -478,11 +480,11 @@ def frontal_apply_bytes(H, w, m):
             for l in range(3, L):
                 kept = (nl[l] + 1) // 2
                 side += nl[l] * R + 2 * Mb * kept + kept * R
-            side += R + Mb + R + Pb
+            side += R + Mb + Qb + R + Pb + NPb
             for l in range(3, L):
                 odd = nl[l] // 2
-                side += nl[l] * R + 3 * Mb * odd + odd * (R + Pb)
-            side += kept2 * R + odd2 * (8 * 7 * wp + 2 * Mb + R + Pb)
+                side += nl[l] * R + odd * (3 * Mb + Qb) + odd * (R + Pb + NPb)
+            side += kept2 * R + odd2 * (8 * 7 * wp + 2 * Mb + Qb + Pb + NPb)
             side += l1bwd
     total += 2 * side + 2 * ((H + 1) // 2) * Pb   # both sides; P read by the output
     return float(total)

@@ -481,21 +481,22 @@ __global__ __launch_bounds__(64) void k_fr_gfwd(const double* __restrict__ ops, 
 
 // Level-1 back substitution from the level-1 operators: P_i = sum_d S_d
 // g_{i+d-1} - A x_{i-2} - B x_{i+2} for row i = 2 p (p odd; p = 0 when level 1
-// is the root), one column per lane.
+// is the root), one column per lane.  A x_{i-2} and B x_{i+2} come ready from
+// the kernels that produced those solutions (NP).
 template <int WP>
 __global__ __launch_bounds__(64) void k_fr_l1bwd(const double* __restrict__ ops, int recw,
-                                                 const double* __restrict__ Z, double* P,
+                                                 const double* __restrict__ NP, double* P,
                                                  const double* XT, const double* bars, int64_t H,
                                                  int m, int root) {
-  __shared__ __attribute__((aligned(16))) double sA[6 * WP + 9];
+  __shared__ double sS[9];
   const int side = blockIdx.z, lane = threadIdx.x;
   const int64_t T = gridDim.x;
   int64_t x = blockIdx.x;
   if ((T & 7) == 0) x = (x & 7) * (T >> 3) + (x >> 3);
   const int64_t p = root ? 0 : 2 * x + 1, i = 2 * p;
-  const int64_t n1 = (H + 1) / 2;
+  const int64_t n1 = (H + 1) / 2, Hq = (H + 3) / 4;
   const double* R = ops + ((int64_t)side * n1 + p) * recw;
-  for (int e = lane; e < 6 * WP + 9; e += 64) sA[e] = R[e];
+  if (lane < 9) sS[lane] = R[6 * WP + lane];
   const int c = blockIdx.y * 64 + lane;
   const bool act = c < m;
   const bool prv = !root, nxt = !root && i + 2 < H;
@@ -505,28 +506,25 @@ __global__ __launch_bounds__(64) void k_fr_l1bwd(const double* __restrict__ ops,
     const int64_t j = i + d - 1;
     gv[d] = (act && j >= 0 && j < H) ? bars[3 * j + side] * XT[j * m + c] : 0.0;
   }
-  double xm[WP], xp[WP];
+  double nm[3] = {0.0, 0.0, 0.0}, npx[3] = {0.0, 0.0, 0.0};
+  if (act && prv) {
+    const double* src = NP + (((int64_t)side * Hq + (i - 2) / 4) * m + c) * 6;
 #pragma unroll
-  for (int k = 0; k < WP; ++k) xm[k] = xp[k] = 0.0;
-  if (act && prv) fr_load<WP>(xm, Z + fr_rhs(side, H, i - 2, m, WP) + (int64_t)c * WP);
-  if (act && nxt) fr_load<WP>(xp, Z + fr_rhs(side, H, i + 2, m, WP) + (int64_t)c * WP);
+    for (int q = 0; q < 3; ++q) nm[q] = src[q];
+  }
+  if (act && nxt) {
+    const double* src = NP + (((int64_t)side * Hq + (i + 2) / 4) * m + c) * 6;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) npx[q] = src[3 + q];
+  }
   __syncthreads();
   if (!act) return;
   double pv[3];
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    double t = 0.0;
+    double t = -nm[q] - npx[q];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) t = fma(sA[6 * WP + 3 * q + d], gv[d], t);
-#pragma unroll
-    for (int k = 0; k < WP; k += 2) {
-      const double2 a2 = *reinterpret_cast<const double2*>(sA + q * WP + k);
-      const double2 b2 = *reinterpret_cast<const double2*>(sA + 3 * WP + q * WP + k);
-      t = fma(-a2.x, xm[k], t);
-      t = fma(-a2.y, xm[k + 1], t);
-      t = fma(-b2.x, xp[k], t);
-      t = fma(-b2.y, xp[k + 1], t);
-    }
+    for (int d = 0; d < 3; ++d) t = fma(sS[3 * q + d], gv[d], t);
     pv[q] = t;
   }
   double* dst = P + (((int64_t)side * m + c) * ((H + 1) / 2) + i / 2) * 4;
@@ -564,6 +562,13 @@ struct FrStep {
   const double* bars;
   const double* ops2;
   int recw2;
+  // the level-1 operators: a back substitution or root also writes NP, the
+  // six projections of its x that the level-1 back substitutions of its
+  // neighbours i -+ 2 read (A_{i+2} x_i, B_{i-2} x_i), at NP[side][i / 4][c][6]
+  const double* ops1;
+  int recw1;
+  double* NP;
+  int write_x;     // 0: only P and NP (no finer dense level reads this x)
 };
 
 template <int WP>
@@ -571,8 +576,8 @@ __global__ __launch_bounds__(128) void k_fr_step(const double* __restrict__ fac,
                                                  double* __restrict__ Z, FrStep a) {
   constexpr int PP = WP * WP, RB = WP / 4, EW = 2 * WP + 2;
   __shared__ __attribute__((aligned(16))) double sL[3 * PP];   // L_t(r, k) at t PP + r WP + k
-  __shared__ double sP[3][4][64];                                  // P partial sums per group
-  __shared__ double sD[7 * WP];                                    // mode 3: DW_0..DW_6
+  __shared__ double sQ[6 * WP];   // A_{i+2} (3 rows), B_{i-2} (3 rows), wp each (0 if absent)
+  __shared__ double sD[7 * WP];   // mode 3: DW_0..DW_6
   const int side = blockIdx.z;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int g = lane >> 4, q = lane & 15;
@@ -601,6 +606,16 @@ __global__ __launch_bounds__(128) void k_fr_step(const double* __restrict__ fac,
     const int64_t n2 = (((a.H + 1) / 2) + 1) / 2;
     const double* R = a.ops2 + ((int64_t)side * n2 + i / 4) * a.recw2;
     for (int e = tid; e < 7 * WP; e += 128) sD[e] = R[e];
+  }
+  if (a.mode != 0 && a.NP) {
+    const int64_t n1 = (a.H + 1) / 2;
+    for (int e = tid; e < 6 * WP; e += 128) {
+      const int h = e / (3 * WP), k = e % (3 * WP);
+      const int64_t nb = h == 0 ? i + 2 : i - 2;   // A from row i + 2, B from row i - 2
+      sQ[e] = (nb >= 0 && nb < a.H)
+                  ? a.ops1[((int64_t)side * n1 + nb / 2) * a.recw1 + (h == 0 ? 0 : 3 * WP) + k]
+                  : 0.0;
+    }
   }
   constexpr int NM = (3 * PP / 2 + 127) / 128;
   double2 mv[NM];
@@ -720,42 +735,52 @@ __global__ __launch_bounds__(128) void k_fr_step(const double* __restrict__ fac,
   // results: x (or the reduced b) of the lane's rows to Z
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
-    if (!cok[u]) continue;
+    if (!cok[u] || (a.mode != 0 && !a.write_x)) continue;
     double* dp = rhs(i, col[u]) + g * RB;
 #pragma unroll
     for (int rr = 0; rr < RB; ++rr) dp[rr] = acc[rr][u];
   }
   if (a.mode == 0) return;
-  // P of row i, summed over the four row groups through LDS
+  // P of row i and, with the level-1 operators, NP: partial sums over the
+  // lane's rows, summed over the four row groups (lanes q, q + 16, q + 32,
+  // q + 48 of the wave) with cross-lane exchanges
   const double* Ed = i >= 1 ? a.edge + EW * ((int64_t)side * a.H + i - 1) + WP : nullptr;
   const double* Eg = i + 1 < a.H ? a.edge + EW * ((int64_t)side * a.H + i + 1) : nullptr;
+  const bool np = a.NP != nullptr;
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
-    double p0 = 0.0, p1 = 0.0, p2 = 0.0;
+    double pv[9];
+#pragma unroll
+    for (int h = 0; h < 9; ++h) pv[h] = 0.0;
 #pragma unroll
     for (int rr = 0; rr < RB; ++rr) {
       const int r = g * RB + rr;
-      if (r == w - 1) p0 = acc[rr][u];
-      if (Ed) p1 = fma(Ed[r], acc[rr][u], p1);
-      if (Eg) p2 = fma(Eg[r], acc[rr][u], p2);
-    }
-    const int cl = wv * 32 + q + 16 * u;   // column within the workgroup
-    sP[0][g][cl] = p0;
-    sP[1][g][cl] = p1;
-    sP[2][g][cl] = p2;
-  }
-  __syncthreads();
-  if (tid < 64) {
-    const int c = blockIdx.y * 64 + tid;
-    if (c < a.m) {
-      double pv[3];
+      const double xv = acc[rr][u];
+      if (r == w - 1) pv[0] = xv;
+      if (Ed) pv[1] = fma(Ed[r], xv, pv[1]);
+      if (Eg) pv[2] = fma(Eg[r], xv, pv[2]);
+      if (np)
 #pragma unroll
-      for (int h = 0; h < 3; ++h)
-        pv[h] = sP[h][0][tid] + sP[h][1][tid] + sP[h][2][tid] + sP[h][3][tid];
+        for (int h = 0; h < 6; ++h) pv[3 + h] = fma(sQ[h * WP + r], xv, pv[3 + h]);
+    }
+#pragma unroll
+    for (int h = 0; h < 9; ++h) {
+      pv[h] += __shfl_xor(pv[h], 16);
+      pv[h] += __shfl_xor(pv[h], 32);
+    }
+    const int c = blockIdx.y * 64 + wv * 32 + q + 16 * u;
+    if (g == 0 && c < a.m) {
       const int64_t Hh = (a.H + 1) / 2;
       double* dst = a.P + (((int64_t)side * a.m + c) * Hh + i / 2) * 4;
       *reinterpret_cast<double2*>(dst) = make_double2(pv[0], pv[1]);
       *reinterpret_cast<double2*>(dst + 2) = make_double2(pv[2], 0.0);
+      if (np) {
+        const int64_t Hq = (a.H + 3) / 4;
+        double* dn = a.NP + ((((int64_t)side * Hq + i / 4) * a.m) + c) * 6;
+        *reinterpret_cast<double2*>(dn) = make_double2(pv[3], pv[4]);
+        *reinterpret_cast<double2*>(dn + 2) = make_double2(pv[5], pv[6]);
+        *reinterpret_cast<double2*>(dn + 4) = make_double2(pv[7], pv[8]);
+      }
     }
   }
 }
@@ -812,6 +837,14 @@ static size_t fr_p_bytes(const hm_frontal_s* f, int m) {
   return ((size_t)(2 * ((f->H + 1) / 2) * m * 4) * sizeof(double) + 255) / 256 * 256;
 }
 
+static size_t fr_xt_bytes(const hm_frontal_s* f, int m) {
+  return ((size_t)(f->H * m) * sizeof(double) + 255) / 256 * 256;
+}
+
+static size_t fr_np_bytes(const hm_frontal_s* f, int m) {
+  return (size_t)(2 * ((f->H + 3) / 4) * m * 6) * sizeof(double);
+}
+
 // XT[j m + c] = X(j, c): 64 x 64 tiles through LDS, both sides contiguous.
 __global__ __launch_bounds__(256) void k_fr_transpose(const double* X, int64_t ldx, int64_t H,
                                                       int m, double* XT) {
@@ -840,6 +873,8 @@ static void frontal_apply_wp(const hm_frontal_s* f, int64_t ncols, const double*
     double* P = reinterpret_cast<double*>(static_cast<char*>(work) + fr_z_bytes(f, m));
     double* XT =
         reinterpret_cast<double*>(static_cast<char*>(work) + fr_z_bytes(f, m) + fr_p_bytes(f, m));
+    double* NPw = reinterpret_cast<double*>(static_cast<char*>(work) + fr_z_bytes(f, m) +
+                                            fr_p_bytes(f, m) + fr_xt_bytes(f, m));
     const double* Xc = X + c0 * ldx;
     double* Yc = Y + c0 * ldy;
     if (f->levels >= 1) {
@@ -848,9 +883,11 @@ static void frontal_apply_wp(const hm_frontal_s* f, int64_t ncols, const double*
       KCHK();
       const unsigned groups = (unsigned)((m + 63) / 64);
       const double* ops = f->ops.as<double>();
-      auto step = [&](int mode, int64_t stride, int64_t n, int64_t rows) {
+      auto step = [&](int mode, int64_t stride, int64_t n, int64_t rows, int write_x = 1) {
         if (rows <= 0) return;
-        FrStep a{H, stride, n, w, m, mode, edge, P, XT, bars, f->ops2.as<double>(), f->recw2};
+        FrStep a{H,   stride, n,    w,         m,       mode,   edge,   P,
+                 XT,  bars,   f->ops2.as<double>(), f->recw2, f->ops.as<double>(), f->recw,
+                 f->levels >= 2 ? NPw : nullptr, write_x};
         hipLaunchKernelGGL(k_fr_step<WP>, dim3((unsigned)rows, groups, 2), dim3(128), 0, s, fac,
                            Z, a);
         KCHK();
@@ -862,7 +899,7 @@ static void frontal_apply_wp(const hm_frontal_s* f, int64_t ncols, const double*
       for (int l = 1; l <= L; ++l) nl[l] = (nl[l - 1] + 1) / 2;
       const int64_t n1 = nl[1];
       if (L == 1) {
-        hipLaunchKernelGGL(k_fr_l1bwd<WP>, dim3(1, groups, 2), dim3(64), 0, s, ops, f->recw, Z,
+        hipLaunchKernelGGL(k_fr_l1bwd<WP>, dim3(1, groups, 2), dim3(64), 0, s, ops, f->recw, NPw,
                            P, XT, bars, H, m, 1);
         KCHK();
       } else if (L == 2) {
@@ -871,7 +908,7 @@ static void frontal_apply_wp(const hm_frontal_s* f, int64_t ncols, const double*
         KCHK();
         step(2, (int64_t)1 << L, 1, 1);
         hipLaunchKernelGGL(k_fr_l1bwd<WP>, dim3((unsigned)(n1 / 2), groups, 2), dim3(64), 0, s,
-                           ops, f->recw, Z, P, XT, bars, H, m, 0);
+                           ops, f->recw, NPw, P, XT, bars, H, m, 0);
         KCHK();
       } else {
         // levels 1 and 2 through their operators, 3 .. L - 1 and the root dense
@@ -883,9 +920,9 @@ static void frontal_apply_wp(const hm_frontal_s* f, int64_t ncols, const double*
         for (int l = 3; l < L; ++l) step(0, (int64_t)1 << l, nl[l], (nl[l] + 1) / 2);
         step(2, (int64_t)1 << L, 1, 1);
         for (int l = L - 1; l >= 3; --l) step(1, (int64_t)1 << l, nl[l], nl[l] / 2);
-        step(3, (int64_t)4, n2, n2 / 2);
+        step(3, (int64_t)4, n2, n2 / 2, 0);
         hipLaunchKernelGGL(k_fr_l1bwd<WP>, dim3((unsigned)(n1 / 2), groups, 2), dim3(64), 0, s,
-                           ops, f->recw, Z, P, XT, bars, H, m, 0);
+                           ops, f->recw, NPw, P, XT, bars, H, m, 0);
         KCHK();
       }
     }
@@ -912,7 +949,7 @@ void frontal_apply(const hm_frontal_s* f, int64_t ncols, const double* X, int64_
 
 size_t frontal_work_bytes(const hm_frontal_s* f, int64_t ncols) {
   const int m = (int)std::min<int64_t>(FR_COLS, std::max<int64_t>(ncols, 1));
-  return fr_z_bytes(f, m) + fr_p_bytes(f, m) + (size_t)(f->H * m) * sizeof(double);
+  return fr_z_bytes(f, m) + fr_p_bytes(f, m) + fr_xt_bytes(f, m) + fr_np_bytes(f, m);
 }
 
 int64_t frontal_n(const hm_frontal_s* f) { return f->H; }
