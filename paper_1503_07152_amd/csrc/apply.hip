@@ -457,7 +457,7 @@ __global__ __launch_bounds__(256) void k_leaf_down(const Node* nodes, const int3
     else
       mf_tile<T>(M, N, nt, D + nd.lo + (i0 - nd.lo) * ldd, ldd, 1, xb, 1, ldx, acc, smem);
   }
-  mf_store<T>(M, N, Y + i0 + (int64_t)j0 * ldy, ldy, acc, alpha, beta);
+  mf_store_lds<T>(M, N, Y + i0 + (int64_t)j0 * ldy, ldy, acc, alpha, beta, smem);
 }
 
 // ---- forward leaf product, one workgroup per (frontier node, column tile) ---

@@ -37,18 +37,18 @@ __global__ __launch_bounds__(256) void k_grad_leaf(const Node* nodes, const int3
     if (!gU || nd.level == 0) return;
     // gU(rows) = GY(rows, :) UH_g^T  (UH_g is R x c, ld R)
     mf_tile<T>(M, R, c, GY + i0, 1, ldgy, UH + (int64_t)g * R * c, R, 1, acc, smem);
-    mf_store<T>(M, R, gU + i0, ld, acc, T(1), T(0));
+    mf_store_lds<T>(M, R, gU + i0, ld, acc, T(1), T(0), smem);
   } else if (part == 1) {
     if (!gV || nd.level == 0) return;
     mf_tile<T>(M, R, c, X + i0, 1, ldx, GQ + (int64_t)g * R * c, R, 1, acc, smem);
-    mf_store<T>(M, R, gV + i0, ld, acc, T(1), T(0));
+    mf_store_lds<T>(M, R, gV + i0, ld, acc, T(1), T(0), smem);
   } else {
     if (!gD) return;
     const int j0 = (part - 2) * GN;
     if (j0 >= nt) return;
     // gD(rows, j) = sum_c GY(row, c) X(lo + j, c)
     mf_tile<T>(M, nt - j0, c, GY + i0, 1, ldgy, X + nd.lo + j0, ldx, 1, acc, smem);
-    mf_store<T>(M, min(GN, nt - j0), gD + i0 + (int64_t)j0 * ldd, ldd, acc, T(1), T(0));
+    mf_store_lds<T>(M, min(GN, nt - j0), gD + i0 + (int64_t)j0 * ldd, ldd, acc, T(1), T(0), smem);
   }
 }
 

@@ -157,4 +157,34 @@ __device__ __forceinline__ void mf_store(int M, int N, T* C, int64_t ldc, const 
     }
 }
 
+// As mf_store, through LDS: the accumulators go to a 64 x 64 tile in smem
+// (at least mf_smem_elems<T>() elements; callers pass the smem of their
+// mf_tile, which ends with a barrier), then each column is written by
+// consecutive threads (contiguous, coalesced), instead of each lane's 16
+// scattered elements.  All threads of the block must call it.
+template <class T>
+__device__ __forceinline__ void mf_store_lds(int M, int N, T* C, int64_t ldc, const MfAcc<T>& acc,
+                                             T alpha, T beta, T* smem) {
+  typedef MfTraits<T> Tr;
+  constexpr int LD = MF_T + 1;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 16 * w + Tr::row(lane, v), j = 16 * t + (lane & 15);
+      smem[i + j * LD] = acc.v[t][v];
+    }
+  __syncthreads();
+  for (int e = threadIdx.x; e < MF_T * MF_T; e += 256) {
+    const int i = e % MF_T, j = e / MF_T;
+    if (i < M && j < N) {
+      T* c = C + i + (int64_t)j * ldc;
+      const T a = smem[i + j * LD];
+      *c = beta == T(0) ? alpha * a : alpha * a + beta * *c;
+    }
+  }
+  __syncthreads();
+}
+
 }  // namespace hm
