@@ -181,6 +181,14 @@ void release_cached_memory();
 // Staging chunks are kept for the process and reused once the copy out of
 // them has completed.
 void stage_h2d(void* dst, const void* src, size_t bytes, hipStream_t s);
+// device -> host reads gathered in one pinned staging chunk; returns after
+// the stream has drained (the reads are the stream's last work)
+struct D2HRead {
+  void* dst;
+  const void* src;
+  size_t bytes;
+};
+void read_d2h(const std::vector<D2HRead>& items, hipStream_t s);
 
 // Upload a host vector into a fresh device buffer (enqueued on s; the host
 // vector may be freed on return).

@@ -985,18 +985,18 @@ static hm_hbs_s* compress_attempt(Forest f, std::vector<OpRunner*>& ops, int32_t
   h->f = f;
   // ---- status, ranks, statistics ------------------------------------------------
   int hflag[5] = {0, 0, 0, 0, 0};
-  HIPCHK(hipMemcpyAsync(hflag, flag.p, 20, hipMemcpyDeviceToHost, s));
   h->rank_u.assign(nn, 0);
   h->rank_v.assign(nn, 0);
   h->skel_in.assign((size_t)nn * R, -1);
   h->skel_out.assign((size_t)nn * R, -1);
+  std::vector<D2HRead> reads{{hflag, flag.p, 20}};
   if (to_id) {
-    HIPCHK(hipMemcpyAsync(h->rank_u.data(), rk_u.p, nn * 4, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(h->rank_v.data(), rk_v.p, nn * 4, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(h->skel_in.data(), sk_in.p, (size_t)nn * R * 4, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(h->skel_out.data(), sk_out.p, (size_t)nn * R * 4, hipMemcpyDeviceToHost, s));
+    reads.push_back({h->rank_u.data(), rk_u.p, (size_t)nn * 4});
+    reads.push_back({h->rank_v.data(), rk_v.p, (size_t)nn * 4});
+    reads.push_back({h->skel_in.data(), sk_in.p, (size_t)nn * R * 4});
+    reads.push_back({h->skel_out.data(), sk_out.p, (size_t)nn * R * 4});
   }
-  HIPCHK(hipStreamSynchronize(s));
+  read_d2h(reads, s);
   if (hflag[0]) HM_THROW(HM_ERR_NONFINITE, "operator samples contain NaN or Inf");
   if (hflag[4]) HM_THROW(HM_ERR_HIP, "HBS-ID sweep: a dependency wait ran past its limit");
   if (hflag[3] && !(flags & HM_FLAG_INTERNAL_NO_FALLBACK)) {

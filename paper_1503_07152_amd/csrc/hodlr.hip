@@ -121,9 +121,7 @@ hm_hodlr_s* hodlr_compress_forest(Forest f, OpRunner& op, hipStream_t s, int* st
   build_apply_lists(f, full, h->full, s);
   int hflag[4] = {0, 0, 0, 0};
   h->rank.assign(nn, 0);
-  HIPCHK(hipMemcpyAsync(hflag, flag.p, 16, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(h->rank.data(), rk.p, nn * 4, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+  read_d2h({{hflag, flag.p, 16}, {h->rank.data(), rk.p, (size_t)nn * 4}}, s);
   if (hflag[0]) HM_THROW(HM_ERR_NONFINITE, "operator samples contain NaN or Inf");
   hm_info& inf = h->info;
   inf.n = N;

@@ -244,6 +244,65 @@ void stage_h2d(void* dst, const void* src, size_t bytes, hipStream_t s) {
   HIPCHK(hipEventRecord(c.ev, s));
 }
 
+// Several device -> host reads through one pinned chunk of the staging pool,
+// then a wait for the stream: copies into pageable memory are staged by the
+// runtime one at a time, each with its own host round trip.
+void read_d2h(const std::vector<D2HRead>& items, hipStream_t s) {
+  size_t total = 0;
+  for (const D2HRead& it : items) total += (it.bytes + 255) / 256 * 256;
+  if (total == 0) {
+    HIPCHK(hipStreamSynchronize(s));
+    return;
+  }
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  PinChunk c;
+  {
+    std::lock_guard<std::mutex> lock(g_pin_mu);
+    for (size_t i = 0; i < g_pin_free.size(); ++i)
+      if (g_pin_free[i].cap >= total && g_pin_free[i].dev == dev) {
+        c = g_pin_free[i];
+        g_pin_free[i] = g_pin_free.back();
+        g_pin_free.pop_back();
+        break;
+      }
+  }
+  if (!c.p) {
+    c.cap = std::max(kPinChunk, (total + kPinChunk - 1) / kPinChunk * kPinChunk);
+    c.dev = dev;
+    HIPCHK(hipHostMalloc((void**)&c.p, c.cap, hipHostMallocDefault));
+    const hipError_t e = hipEventCreateWithFlags(&c.ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      (void)hipHostFree(c.p);
+      HM_THROW(HM_ERR_HIP, "hipEventCreate failed: %s", hipGetErrorString(e));
+    }
+  }
+  // the chunk goes back to the pool whatever happens below, once the stream
+  // is idle
+  struct Return {
+    PinChunk& c;
+    hipStream_t s;
+    ~Return() {
+      (void)hipStreamSynchronize(s);   // no copy into the chunk is still in flight
+      (void)hipGetLastError();
+      std::lock_guard<std::mutex> lock(g_pin_mu);
+      g_pin_free.push_back(c);
+    }
+  } ret{c, s};
+  size_t off = 0;
+  for (const D2HRead& it : items) {
+    if (it.bytes)
+      HIPCHK(hipMemcpyAsync(c.p + off, it.src, it.bytes, hipMemcpyDeviceToHost, s));
+    off += (it.bytes + 255) / 256 * 256;
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  off = 0;
+  for (const D2HRead& it : items) {
+    if (it.bytes) std::memcpy(it.dst, c.p + off, it.bytes);
+    off += (it.bytes + 255) / 256 * 256;
+  }
+}
+
 // ------------------------------------------------------------------ forest
 void forest_add_tree(Forest& f, int64_t n, int64_t leaf, int32_t r, int32_t k, int32_t p,
                      double tol, uint64_t seed) {
