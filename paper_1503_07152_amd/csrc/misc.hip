@@ -198,16 +198,48 @@ TuneScope::~TuneScope() { g_tune_cur = prev; }
 
 // ------------------------------------------------------------ staging ------
 namespace {
+constexpr size_t kPinChunk = (size_t)64 << 10;
 struct PinChunk {
   char* p = nullptr;
+  void* dp = nullptr;   // the chunk as the device addresses it (null: copy engine only)
   size_t cap = 0;
   hipEvent_t ev = nullptr;
   int dev = -1;
 };
+
+// A new pinned chunk of at least `bytes` on device `dev`.
+PinChunk new_pin_chunk(size_t bytes, int dev) {
+  PinChunk c;
+  c.cap = std::max(kPinChunk, (bytes + kPinChunk - 1) / kPinChunk * kPinChunk);
+  c.dev = dev;
+  HIPCHK(hipHostMalloc((void**)&c.p, c.cap, hipHostMallocDefault));
+  const hipError_t e = hipEventCreateWithFlags(&c.ev, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    (void)hipHostFree(c.p);
+    HM_THROW(HM_ERR_HIP, "hipEventCreate failed: %s", hipGetErrorString(e));
+  }
+  if (hipHostGetDevicePointer(&c.dp, c.p, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    c.dp = nullptr;
+  }
+  return c;
+}
+
+// Host -> device copy by a kernel reading the pinned chunk: it runs in the
+// stream's own queue, so the kernels around it do not wait for a copy
+// engine to take over and hand back (~20 us per copy at the fine levels).
+__global__ void k_stage_copy(char* __restrict__ dst, const char* __restrict__ src,
+                             int64_t bytes) {
+  const int64_t n16 = ((uintptr_t)dst % 16 == 0 && (uintptr_t)src % 16 == 0) ? bytes / 16 : 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  for (int64_t i = t0; i < n16; i += stride)
+    reinterpret_cast<uint4*>(dst)[i] = reinterpret_cast<const uint4*>(src)[i];
+  for (int64_t i = n16 * 16 + t0; i < bytes; i += stride) dst[i] = src[i];
+}
 std::mutex g_pin_mu;
 std::deque<PinChunk> g_pin_busy;   // copies in flight, in order of use
 std::vector<PinChunk> g_pin_free;
-constexpr size_t kPinChunk = (size_t)64 << 10;
 }  // namespace
 
 void stage_h2d(void* dst, const void* src, size_t bytes, hipStream_t s) {
@@ -228,19 +260,18 @@ void stage_h2d(void* dst, const void* src, size_t bytes, hipStream_t s) {
       g_pin_free.pop_back();
       break;
     }
-  if (!c.p) {
-    c.cap = std::max(kPinChunk, (bytes + kPinChunk - 1) / kPinChunk * kPinChunk);
-    c.dev = dev;
-    HIPCHK(hipHostMalloc((void**)&c.p, c.cap, hipHostMallocDefault));
-    const hipError_t e = hipEventCreateWithFlags(&c.ev, hipEventDisableTiming);
-    if (e != hipSuccess) {
-      (void)hipHostFree(c.p);
-      HM_THROW(HM_ERR_HIP, "hipEventCreate failed: %s", hipGetErrorString(e));
-    }
-  }
+  if (!c.p) c = new_pin_chunk(bytes, dev);
   std::memcpy(c.p, src, bytes);
   g_pin_busy.push_back(c);   // from here the chunk is owned by the queue
-  HIPCHK(hipMemcpyAsync(dst, c.p, bytes, hipMemcpyHostToDevice, s));
+  if (c.dp) {
+    const int64_t n16 = (int64_t)(bytes + 15) / 16;
+    const int blocks = (int)std::min<int64_t>((n16 + 255) / 256, 64);
+    hipLaunchKernelGGL(k_stage_copy, dim3(blocks), dim3(256), 0, s, static_cast<char*>(dst),
+                       static_cast<const char*>(c.dp), (int64_t)bytes);
+    HIPCHK(hipGetLastError());
+  } else {
+    HIPCHK(hipMemcpyAsync(dst, c.p, bytes, hipMemcpyHostToDevice, s));
+  }
   HIPCHK(hipEventRecord(c.ev, s));
 }
 
@@ -267,16 +298,7 @@ void read_d2h(const std::vector<D2HRead>& items, hipStream_t s) {
         break;
       }
   }
-  if (!c.p) {
-    c.cap = std::max(kPinChunk, (total + kPinChunk - 1) / kPinChunk * kPinChunk);
-    c.dev = dev;
-    HIPCHK(hipHostMalloc((void**)&c.p, c.cap, hipHostMallocDefault));
-    const hipError_t e = hipEventCreateWithFlags(&c.ev, hipEventDisableTiming);
-    if (e != hipSuccess) {
-      (void)hipHostFree(c.p);
-      HM_THROW(HM_ERR_HIP, "hipEventCreate failed: %s", hipGetErrorString(e));
-    }
-  }
+  if (!c.p) c = new_pin_chunk(total, dev);
   // the chunk goes back to the pool whatever happens below, once the stream
   // is idle
   struct Return {
