@@ -102,5 +102,12 @@ void seg_tn(const Node* d_nodes, const int32_t* list, int nlist, int64_t max_row
             int to_parent = 0);
 template <class T>
 size_t seg_tn_work_bytes(int nlist, int64_t max_rows, int rows, int cols);
+// The same for A = B (Gram matrices of node blocks, FP64, c <= 96 columns):
+// OUT_v = A(I_v, 0:c)^T A(I_v, 0:c), only the 16 x 16 tiles on and above the
+// diagonal multiplied (each written with its mirror); work as
+// seg_tn_work_bytes(nlist, max_rows, c, c).
+void seg_gram(const Node* d_nodes, const int32_t* list, int nlist, int64_t max_rows, int c,
+              const double* A, int64_t lda, double* out, int64_t out_stride, void* work,
+              hipStream_t s);
 
 }  // namespace hm

@@ -790,6 +790,104 @@ __global__ void k_seg_reduce(const Node* nodes, const int32_t* list, int chunks,
   }
 }
 
+// Gram partials of one APPLY_CHUNK-row chunk of one node: the chunk goes
+// through LDS in SG_K-row slices, column-major with pitch SG_P (the MFMA
+// operand reads, 16 columns x 4 rows per instruction, then touch every bank
+// at most twice; the staging writes run down a column), the next slice in
+// registers while the current one feeds the MFMAs.  The SG_NT (SG_NT + 1) / 2
+// tiles on and above the diagonal go to the four waves round-robin.
+constexpr int SG_K = 32, SG_P = SG_K + 4, SG_C = 96, SG_NT = SG_C / 16;
+constexpr int SG_TW = (SG_NT * (SG_NT + 1) / 2 + 3) / 4;   // tiles per wave
+__global__ __launch_bounds__(256) void k_seg_gram(const Node* nodes, const int32_t* list,
+                                                  int chunks, int c, const double* A,
+                                                  int64_t lda, double* P) {
+  typedef MfTraits<double> Tr;
+  __shared__ double sM[2][SG_C * SG_P];
+  const int ch = blockIdx.x, li = blockIdx.y;
+  const Node nd = nodes[list[li]];
+  const int64_t r0 = nd.lo + (int64_t)ch * APPLY_CHUNK;
+  const int K = (int)max<int64_t>(0, min<int64_t>(APPLY_CHUNK, nd.hi - r0));
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nt = (c + 15) / 16;
+  Tr::acc_t acc[SG_TW];
+#pragma unroll
+  for (int q = 0; q < SG_TW; ++q) acc[q] = Tr::acc_t{0, 0, 0, 0};
+  // staging: thread t moves row t % SG_K of columns t / SG_K + 8 u
+  constexpr int SU = SG_C * SG_K / 256;
+  const int sk = tid % SG_K, sc = tid / SG_K;
+  double pre[SU];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      const int col = sc + 8 * u;
+      pre[u] = (col < c && k0 + sk < K) ? A[r0 + k0 + sk + (int64_t)col * lda] : 0.0;
+    }
+  };
+  auto stash = [&](int b) {
+#pragma unroll
+    for (int u = 0; u < SU; ++u) sM[b][(sc + 8 * u) * SG_P + sk] = pre[u];
+  };
+  const int ns = (K + SG_K - 1) / SG_K;
+  if (ns > 0) {
+    fetch(0);
+    stash(0);
+  }
+  __syncthreads();
+  const int li16 = lane & 15, lk = lane >> 4;
+  for (int sl = 0; sl < ns; ++sl) {
+    const int b = sl & 1;
+    if (sl + 1 < ns) fetch((sl + 1) * SG_K);
+    const double* m = sM[b];
+    int t = 0;
+#pragma unroll
+    for (int ti = 0; ti < SG_NT; ++ti)
+#pragma unroll
+      for (int tj = ti; tj < SG_NT; ++tj, ++t) {
+        if ((t & 3) != wave || tj >= nt) continue;
+        const double* pa = m + (16 * ti + li16) * SG_P + lk;
+        const double* pb = m + (16 * tj + li16) * SG_P + lk;
+#pragma unroll
+        for (int kk = 0; kk < SG_K / 4; ++kk)
+          acc[t >> 2] = Tr::step(pa[4 * kk], pb[4 * kk], acc[t >> 2]);
+      }
+    if (sl + 1 < ns) stash(b ^ 1);
+    __syncthreads();
+  }
+  double* out = P + ((int64_t)li * chunks + ch) * c * c;
+  int t = 0;
+#pragma unroll
+  for (int ti = 0; ti < SG_NT; ++ti)
+#pragma unroll
+    for (int tj = ti; tj < SG_NT; ++tj, ++t) {
+      if ((t & 3) != wave || tj >= nt) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * ti + Tr::row(lane, v), j = 16 * tj + li16;
+        if (i < c && j < c) {
+          out[i + (int64_t)j * c] = acc[t >> 2][v];
+          out[j + (int64_t)i * c] = acc[t >> 2][v];
+        }
+      }
+    }
+}
+
+void seg_gram(const Node* d_nodes, const int32_t* list, int nlist, int64_t max_rows, int c,
+              const double* A, int64_t lda, double* out, int64_t out_stride, void* work,
+              hipStream_t s) {
+  if (nlist == 0 || c == 0) return;
+  if (c > SG_C) HM_THROW(HM_ERR_ARG, "seg_gram: %d columns > %d", c, SG_C);
+  const int chunks = (int)std::max<int64_t>(1, (max_rows + APPLY_CHUNK - 1) / APPLY_CHUNK);
+  double* P = static_cast<double*>(work);
+  hipLaunchKernelGGL(k_seg_gram, dim3(chunks, nlist), dim3(256), 0, s, d_nodes, list, chunks, c,
+                     A, lda, P);
+  KCHK();
+  const int64_t n = (int64_t)c * c;
+  hipLaunchKernelGGL(k_seg_reduce<double>,
+                     dim3((unsigned)std::min<int64_t>((n + 255) / 256, 64), nlist), dim3(256), 0, s,
+                     d_nodes, list, chunks, c, c, P, out, out_stride, (int64_t)c, 1.0, 0.0, 0);
+  KCHK();
+}
+
 template <class T>
 size_t seg_tn_work_bytes(int nlist, int64_t max_rows, int rows, int cols) {
   const int64_t chunks = std::max<int64_t>(1, (max_rows + APPLY_CHUNK - 1) / APPLY_CHUNK);

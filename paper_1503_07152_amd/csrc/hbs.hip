@@ -373,8 +373,7 @@ void node_svd_gram(const std::vector<SvdJob>& jobs, const Node* dn, const int32_
   double* L = reinterpret_cast<double*>(base + l_off);
   int32_t* PM = reinterpret_cast<int32_t*>(base + p_off);
   ws_seg.ensure(seg_tn_work_bytes<double>(nj, max_rows, c, c), s);
-  seg_tn<double>(dn, dk, nj, max_rows, c, c, M, ldm, M, ldm, G, (int64_t)c * c, c, 1.0, 0.0,
-                 ws_seg.base(), s);
+  seg_gram(dn, dk, nj, max_rows, c, M, ldm, G, (int64_t)c * c, ws_seg.base(), s);
   std::vector<PcholDesc> pd(nj);
   std::vector<SvdDesc> sd(nj);
   for (int q = 0; q < nj; ++q) {
