@@ -4,6 +4,7 @@
 
 #include "factor.h"
 #include "tile.h"
+#include "tile_mfma.h"
 
 namespace hm {
 
@@ -1463,11 +1464,14 @@ void launch_bskel(const Node* nodes, const int32_t* list, int nlist, int R, cons
   KCHK();
 }
 
+// 64 x 64 output tiles on the FP64 matrix cores, stored through LDS
+// (column-contiguous writes)
 __global__ __launch_bounds__(256) void k_node_nn(const Node* nodes, const int32_t* list, int K,
                                                  int N, const double* A, int64_t lda,
                                                  const double* Bn, int64_t bstride, int64_t ldb,
                                                  double* out, int64_t ldo, int from_sibling) {
-  __shared__ double smem[tile_smem_elems<STM, STN>()];
+  static_assert(STM == MF_T && STN == MF_T, "node products in the MFMA tile shape");
+  __shared__ double smem[mf_smem_elems<double>()];
   const int g = list[blockIdx.y];
   const int gb = from_sibling ? nodes[g].sib : g;
   const Node nd = nodes[g];
@@ -1475,11 +1479,11 @@ __global__ __launch_bounds__(256) void k_node_nn(const Node* nodes, const int32_
   if (i0 >= nd.hi) return;
   const int M = (int)min<int64_t>(STM, nd.hi - i0);
   const int j0 = blockIdx.z * STN;
-  TileAcc<double, STM, STN> acc;
+  MfAcc<double> acc;
   acc.zero();
-  mm_tile<double, STM, STN>(M, N - j0, K, A + i0, 1, lda, Bn + (int64_t)gb * bstride + j0 * ldb,
-                            1, ldb, acc, smem);
-  store_tile<double, STM, STN>(M, N - j0, out + i0 + (int64_t)j0 * ldo, ldo, acc, 1.0, 0.0);
+  mf_tile<double>(M, N - j0, K, A + i0, 1, lda, Bn + (int64_t)gb * bstride + j0 * ldb, 1, ldb, acc,
+                  smem);
+  mf_store_lds<double>(M, N - j0, out + i0 + (int64_t)j0 * ldo, ldo, acc, 1.0, 0.0, smem);
 }
 
 void launch_node_nn(const Node* nodes, const int32_t* list, int nlist, int64_t max_rows, int K,
