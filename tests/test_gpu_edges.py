@@ -138,6 +138,21 @@ def test_nonfinite_samples_report_error():
     assert e.value.code == -5
 
 
+def test_nonfinite_kernel_points_report_error():
+    # the near-singular kernel's samples are finite whenever its points are,
+    # so the compression checks the points instead of every sample block: a
+    # non-finite point must still end it with HM_ERR_NONFINITE (-5)
+    n = 1024
+    P = W.ellipse_points(n)
+    P[300, 1] = np.inf
+    pts = torch.from_numpy(P).cuda()
+    for dt in (hm.HM_BF16, hm.HM_F64):
+        op = hm.KernelOperator(pts, "near", 1e-3, dt)
+        with pytest.raises(hm.HMError) as e:
+            hm.hbs_compress(hm.Options(n, 64, 8, 4, seed=1), op)
+        assert e.value.code == -5
+
+
 def test_rank_saturation_warning():
     # a dense Gaussian matrix has full-rank off-diagonal blocks: at tol 1e-12
     # every block's revealed rank reaches the cap r - p
