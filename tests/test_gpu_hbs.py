@@ -252,6 +252,24 @@ def test_mixed_precision_sampling_errors(mode, tol, n):
     assert inf["sample_columns"] == 4 * (k + p) * L + ho.tree.nmax()
 
 
+@pytest.mark.parametrize("n,leaf,k,p", [(3001, 100, 20, 8), (1537, 96, 30, 10)])
+def test_bf16_gram_route_ragged_blocks(n, leaf, k, p):
+    """BF16 kernel sampling takes the Gram route of the node SVD (node Gram
+    matrices, pivoted Cholesky, Jacobi); sizes with node blocks of rows not a
+    multiple of 32 and 2r = 56 or 80 columns (partial 16-column tiles of the
+    Gram kernel) must reach the same BF16 accuracy against the oracle."""
+    seed = 5
+    say(f"bf16 gram route n={n} leaf={leaf} k={k} p={p}")
+    P = W.fourier_curve_points(n, seed=7)
+    K = oops.KernelOp(P, "near")
+    h = hm.hbs_compress(hm.Options(n, leaf, k, p, seed=seed, orthonormal=True),
+                        hm.KernelOperator(P, "near", 1e-3, hm.HM_BF16))
+    ho, _, _ = ohbs.compress(K, n, leaf, k + p, seed, rank=k, to_id=False)
+    r = _compare_compress(h, ho, n, K.apply)
+    say(f"  {r}")
+    assert r["vs_oracle"] < 5e-3
+
+
 @pytest.mark.parametrize("n,leaf,k,p", [(1024, 64, 10, 10), (2000, 64, 12, 8)])
 def test_orthonormal_bases_with_rank_deficient_blocks(n, leaf, k, p):
     """Node blocks of an operator with off-diagonal rank exactly k < r have
