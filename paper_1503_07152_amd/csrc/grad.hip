@@ -56,51 +56,106 @@ __global__ __launch_bounds__(256) void k_grad_leaf(const Node* nodes, const int3
 // Output blocks are heap-indexed in the flat layout: node g -> block g + 1 of
 // its tree (single-tree handles).  The blocks no node owns (gB of the root,
 // gUt / gVt of the root and of the leaves, and block 0) are written as zeros.
-template <class T>
-__global__ __launch_bounds__(256) void k_grad_node(const Node* nodes, const int32_t* list, int R,
-                                                   int c, const T* QH, const T* UH,
-                                                   const T* GU, const T* GQ, T* gB, T* gUt,
-                                                   T* gVt) {
-  __shared__ T smem[mf_smem_elems<T>()];
-  const int v = list[blockIdx.x];
+// One wave per (node, part) product out = a b^T (a, b: R x c, column-major,
+// ld R), with no LDS and no barrier: NT x NT tiles of 16 x 16 held in
+// registers, the operands of each 4-deep K-step read straight from global
+// memory (16 consecutive entries per lane group).
+template <class T, int NT>
+__global__ __launch_bounds__(256) void k_grad_node(const Node* nodes, const int32_t* list,
+                                                   int nlist, int R, int c, const T* QH,
+                                                   const T* UH, const T* GU, const T* GQ, T* gB,
+                                                   T* gUt, T* gVt) {
+  typedef MfTraits<T> Tr;
+  const int lane = threadIdx.x & 63;
+  const int64_t prod = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (prod >= (int64_t)nlist * 5) return;
+  const int v = list[prod / 5];
+  const int part = (int)(prod % 5);
   const Node nd = nodes[v];
-  const int part = blockIdx.y;
   const int64_t blk = (int64_t)v + 1;
-  MfAcc<T> acc;
-  acc.zero();
-  const T* qh = QH + (int64_t)v * R * c;
+  T* out = nullptr;    // the product's block
+  T* out0 = nullptr;   // the root's block 0 (zeros)
+  int64_t ld = R;
+  const T* a = nullptr;   // null: a zero block
+  const T* b = nullptr;
   if (part == 0) {
     if (!gB) return;
-    if (nd.parent < 0) {
-      mf_store<T>(R, R, gB + blk * R * R, R, acc, T(1), T(0));
-      mf_store<T>(R, R, gB, R, acc, T(1), T(0));
-      return;
-    }
     // gB[v] = g(uh)_sib qh_v^T
-    mf_tile<T>(R, R, c, GU + (int64_t)nd.sib * R * c, 1, R, qh, R, 1, acc, smem);
-    mf_store<T>(R, R, gB + blk * R * R, R, acc, T(1), T(0));
+    out = gB + blk * R * R;
+    if (nd.parent < 0) {
+      out0 = gB;
+    } else {
+      a = GU + (int64_t)nd.sib * R * c;
+      b = QH + (int64_t)v * R * c;
+    }
   } else {
-    // part 1: gUt half of child (side 0/1), part 3/4: gVt half
+    // parts 1 / 2: gUt half of child (side 0 / 1), parts 3 / 4: gVt half
     const bool want_u = part <= 2;
     const int side = (part - 1) % 2;
-    if (want_u ? !gUt : !gVt) return;
-    if (nd.left < 0 || nd.parent < 0) {
-      T* gt = want_u ? gUt : gVt;
-      mf_store<T>(R, R, gt + blk * 2 * R * R + side * R, 2 * R, acc, T(1), T(0));
-      if (nd.parent < 0) mf_store<T>(R, R, gt + side * R, 2 * R, acc, T(1), T(0));
-      return;
-    }
-    const int a = side == 0 ? nd.left : nd.right;
-    if (want_u) {
-      mf_tile<T>(R, R, c, GU + (int64_t)a * R * c, 1, R, UH + (int64_t)v * R * c, R, 1,
-                         acc, smem);
-      mf_store<T>(R, R, gUt + blk * 2 * R * R + side * R, 2 * R, acc, T(1), T(0));
-    } else {
-      mf_tile<T>(R, R, c, QH + (int64_t)a * R * c, 1, R, GQ + (int64_t)v * R * c, R, 1,
-                         acc, smem);
-      mf_store<T>(R, R, gVt + blk * 2 * R * R + side * R, 2 * R, acc, T(1), T(0));
+    T* gt = want_u ? gUt : gVt;
+    if (!gt) return;
+    out = gt + blk * 2 * R * R + side * R;
+    ld = 2 * R;
+    if (nd.parent < 0) out0 = gt + side * R;
+    if (nd.left >= 0 && nd.parent >= 0) {
+      const int ch = side == 0 ? nd.left : nd.right;
+      a = (want_u ? GU : QH) + (int64_t)ch * R * c;
+      b = (want_u ? UH : GQ) + (int64_t)v * R * c;
     }
   }
+  typename Tr::acc_t acc[NT][NT];
+#pragma unroll
+  for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj) acc[ti][tj] = typename Tr::acc_t{0, 0, 0, 0};
+  const int li = lane & 15, lk = lane >> 4;
+  if (a) {
+    // four K-steps per round: every load of the round (at clamped, always
+    // valid indices; entries outside R x c zeroed after the load) is issued
+    // before its MFMAs, so that they are in flight together
+    constexpr int KS = 4;
+    for (int k0 = 0; k0 < c; k0 += 4 * KS) {
+      T av[KS][NT], bv[KS][NT];
+#pragma unroll
+      for (int s4 = 0; s4 < KS; ++s4) {
+        const int k = k0 + 4 * s4 + lk;
+        const int kc = min(k, c - 1);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const int ic = min(16 * t + li, R - 1);
+          av[s4][t] = a[ic + (int64_t)kc * R];
+          bv[s4][t] = b[ic + (int64_t)kc * R];
+        }
+      }
+#pragma unroll
+      for (int s4 = 0; s4 < KS; ++s4) {
+        const int k = k0 + 4 * s4 + lk;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const bool ok = 16 * t + li < R && k < c;
+          av[s4][t] = ok ? av[s4][t] : T(0);
+          bv[s4][t] = ok ? bv[s4][t] : T(0);
+        }
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+          for (int tj = 0; tj < NT; ++tj)
+            acc[ti][tj] = Tr::step(av[s4][ti], bv[s4][tj], acc[ti][tj]);
+      }
+    }
+  }
+#pragma unroll
+  for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = 16 * ti + Tr::row(lane, q), j = 16 * tj + li;
+        if (i < R && j < R) {
+          out[i + (int64_t)j * ld] = acc[ti][tj][q];
+          if (out0) out0[i + (int64_t)j * ld] = T(0);
+        }
+      }
 }
 
 template <class T>
@@ -117,9 +172,16 @@ void launch_grad(const Node* d_nodes, const int32_t* leaves, int nleaves, int64_
     KCHK();
   }
   if (nlist > 0 && R > 0) {
-    hipLaunchKernelGGL(k_grad_node<T>, dim3(nlist, 5), dim3(256), 0, s, d_nodes, nodes_list, R, c,
-                       QH, UH, GU, GQ, gB, gUt, gVt);
-    KCHK();
+    const dim3 grid((unsigned)(((int64_t)nlist * 5 + 3) / 4));
+    auto go = [&](auto kern) {
+      hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, d_nodes, nodes_list, nlist, R, c, QH, UH,
+                         GU, GQ, gB, gUt, gVt);
+      KCHK();
+    };
+    if (R <= 16) go(k_grad_node<T, 1>);
+    else if (R <= 32) go(k_grad_node<T, 2>);
+    else if (R <= 48) go(k_grad_node<T, 3>);
+    else HM_THROW(HM_ERR_UNSUPPORTED, "backward: padded rank %d > 48", R);
   }
 }
 
