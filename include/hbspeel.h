@@ -128,6 +128,13 @@ typedef struct hm_operator {
                                   done) instead of the default level by level (two
                                   launches per level and side, the two sides on two
                                   streams); same result */
+#define HM_FLAG_LOW_MEMORY_PLAN 4 /* with the built-in kernel operator sampled in BF16:
+                                  one operator call per product instead of first
+                                  products riding in shared calls of up to 288
+                                  columns, so that one window of sample columns is
+                                  held instead of several (more calls, more time);
+                                  the plan the compression falls back to by itself
+                                  when the shared windows would exceed 4 GiB */
 
 typedef struct hm_options {
   int64_t n;            /* matrix size N >= 1                                    */

@@ -33,7 +33,7 @@ HM_F64, HM_F32, HM_BF16 = 0, 1, 2
 HM_OP_CALLBACK, HM_OP_KERNEL, HM_OP_DENSE, HM_OP_HBS, HM_OP_HBS_PRODUCT = 0, 1, 2, 3, 4
 HM_OP_FRONTAL = 5
 HM_KERNEL_LOG, HM_KERNEL_NEAR = 0, 1
-HM_FLAG_ORTHONORMAL, HM_FLAG_PERSISTENT_ID = 1, 2
+HM_FLAG_ORTHONORMAL, HM_FLAG_PERSISTENT_ID, HM_FLAG_LOW_MEMORY_PLAN = 1, 2, 4
 HM_MAX_SAMPLES = 48
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -190,9 +190,10 @@ def _ld(t):
 
 class Options:
     def __init__(self, n, leaf_size, rank, oversample=10, tol=0.0, seed=0, orthonormal=False,
-                 store_dtype=HM_F64, persistent_id=False):
+                 store_dtype=HM_F64, persistent_id=False, low_memory_plan=False):
         flags = (HM_FLAG_ORTHONORMAL if orthonormal else 0) | \
-            (HM_FLAG_PERSISTENT_ID if persistent_id else 0)
+            (HM_FLAG_PERSISTENT_ID if persistent_id else 0) | \
+            (HM_FLAG_LOW_MEMORY_PLAN if low_memory_plan else 0)
         self.c = _Options(n, leaf_size, rank, oversample, tol, seed, flags, store_dtype)
 
 

@@ -654,7 +654,8 @@ static hm_hbs_s* compress_attempt(Forest f, std::vector<OpRunner*>& ops, int32_t
     p.nwin = std::max<int>(1, (int)busy.size());
     return p;
   };
-  const size_t cap = (size_t)4 << 30;   // bytes of the windows (Omega plus Y)
+  // bytes of the windows (Omega plus Y); none with HM_FLAG_LOW_MEMORY_PLAN
+  const size_t cap = (flags & HM_FLAG_LOW_MEMORY_PLAN) ? 0 : (size_t)4 << 30;
   auto plan_bytes = [&](const Plan& p) { return (size_t)p.nwin * N * p.width * 16; };
   // block-identity columns per second call: all of them on the last level,
   // or spread over the narrow calls' spare columns (first fit, in level order)

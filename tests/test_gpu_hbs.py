@@ -252,6 +252,32 @@ def test_mixed_precision_sampling_errors(mode, tol, n):
     assert inf["sample_columns"] == 4 * (k + p) * L + ho.tree.nmax()
 
 
+def test_low_memory_plan_matches_shared_calls():
+    """HM_FLAG_LOW_MEMORY_PLAN takes the plan the compression falls back to
+    when the shared sample windows would exceed 4 GiB: one operator call per
+    product instead of first products riding in shared 288-column calls.  The
+    test blocks are the same, so both reach the oracle's compression to the
+    BF16 accuracy, with more operator calls."""
+    n, leaf, k, p, seed = 4096, 128, 32, 16, 3
+    say(f"low-memory plan n={n}")
+    P = W.fourier_curve_points(n, seed=3)
+    K = oops.KernelOp(P, "near")
+    op = hm.KernelOperator(P, "near", 1e-3, hm.HM_BF16)
+    h1 = hm.hbs_compress(hm.Options(n, leaf, k, p, seed=seed, orthonormal=True), op)
+    h2 = hm.hbs_compress(hm.Options(n, leaf, k, p, seed=seed, orthonormal=True,
+                                    low_memory_plan=True), op)
+    ho, _, _ = ohbs.compress(K, n, leaf, k + p, seed, rank=k, to_id=False)
+    L = ho.tree.L
+    c1, c2 = h1.info()["operator_calls"], h2.info()["operator_calls"]
+    say(f"  operator calls: shared {c1}, low-memory {c2}")
+    assert c1 < c2 <= 2 * L + 1
+    assert h2.info()["sample_columns"] == h1.info()["sample_columns"]
+    for h in (h1, h2):
+        r = _compare_compress(h, ho, n, K.apply)
+        say(f"  {r}")
+        assert r["vs_oracle"] < 5e-3
+
+
 @pytest.mark.parametrize("n,leaf,k,p", [(3001, 100, 20, 8), (1537, 96, 30, 10)])
 def test_bf16_gram_route_ragged_blocks(n, leaf, k, p):
     """BF16 kernel sampling takes the Gram route of the node SVD (node Gram
